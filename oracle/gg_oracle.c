@@ -1,0 +1,839 @@
+/*
+ * FP64 CPU oracle of the local level-set grain-growth timestep
+ * (Miessen et al., arXiv:1701.06658, section 2.1 "Simulation model").
+ *
+ * TEST INFRASTRUCTURE ONLY -- see gg_oracle.h.  Plain, grain-major and slow on
+ * purpose: every step below follows the method's definition directly, with no
+ * tiling, fusion or reordering, so that it can be checked against the paper by
+ * eye.  Built with -ffp-contract=off so that each product and sum is rounded
+ * separately, in the order written.
+ *
+ * The step (Algorithm 1 of the paper: predictor, corrector, re-initialization):
+ *   1. predictor  (sec. 2.1.4, Eqs. Heatequation/Gaussian/solution):
+ *        psi_k = G_sigma * phi_k, separable, x then y then z, taps
+ *        g_i = exp(-i^2 / (2 sigma^2)) / sum_j exp(-j^2 / (2 sigma^2)), |i| <= R,
+ *        R = ceil(4 sigma), sigma = sqrt(2 dt) * n voxels (heat kernel variance
+ *        2t per axis); samples outside the box read -W;
+ *      optional correction (Eq. eq:velocorrect):
+ *        d^p = phi + w (psi - phi) + mob (E_iota - E_k) sigma^2 h / (2 gamma_max),
+ *        clamped to [-W, W], with (w, mob) from the misorientation of the pair
+ *        (k, iota_k(x)), iota the ID-field of the previous corrector;
+ *   2. corrector (sec. 2.1.5): phi^c_k = (psi_k - max_{j != k} psi_j) / 2, the
+ *      max over the other alive grains whose box covers the voxel (-W if none);
+ *      the ID-field iota_k = that argmax (ties to the lowest id, -1 if none);
+ *   3. extinction: grain k dies when no voxel has phi^c_k > 0;
+ *   4. box update (sec. 3.1, size-adaptive boxes): new box = bounding box of
+ *      {phi^c_k > 0} padded by P = ceil(W) and capped at the grid; phi^c and
+ *      iota are carried over through the sampling rule (new cells read -W / -1);
+ *   5. re-initialization (sec. 2.1.6, the fast "taxicab" scheme): reference
+ *      values at voxels next to a sign change, theta = phi(x)/(phi(x)-phi(n))
+ *      over face neighbours n of opposite sign, ref = min theta (the exact L1
+ *      distance to a locally planar interface); then the L1 distance
+ *      min_p ref(p) + |x - p|_1 by three 1D min-plus passes (x, y, z), and
+ *      phi = +-min(dist, W) with the sign of phi^c > 0;
+ *   6. volume V_k = sum over the box of clamp(phi + 1/2, 0, 1).
+ *
+ * Sampling rule (periodic grid): global voxel g is covered by box k iff
+ * l = (g - lo_k) mod n satisfies l_a < ext_a on every axis; then the value is
+ * the stored one at l, otherwise the fill value (-W for level-set values).
+ */
+#include "gg_oracle.h"
+
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+struct orc_sim {
+    int dim;
+    int n[3];
+    double W;
+    int P;
+    int G;
+    int *alive;
+    int *lo;  /* 3*G */
+    int *ext; /* 3*G */
+    double **phi;
+    int **iota;
+    double *vol;
+    /* predictor correction */
+    int mode;
+    double *quat;
+    double theta_c;
+    double *energy;
+    double h_phys;
+    double gamma_max;
+    /* intermediates of the last step */
+    int keep;
+    int *plo, *pext, *palive;
+    double **psi;
+    double **phic;
+};
+
+/* ------------------------------------------------------------------ helpers */
+
+static int wrapi(long v, int N) {
+    long r = v % N;
+    if (r < 0) r += N;
+    return (int)r;
+}
+
+static long nvox(const int *e) { return (long)e[0] * e[1] * e[2]; }
+
+static long lidx(const int *e, int x, int y, int z) {
+    return x + (long)e[0] * (y + (long)e[1] * z);
+}
+
+/* Value of a box field at local coordinates that may lie outside the box:
+ * wrap modulo the grid, then test against the extent. */
+static double sample(const double *f, const int *e, const int *n, long x, long y, long z,
+                     double fill) {
+    int lx = wrapi(x, n[0]), ly = wrapi(y, n[1]), lz = wrapi(z, n[2]);
+    if (lx >= e[0] || ly >= e[1] || lz >= e[2]) return fill;
+    return f[lidx(e, lx, ly, lz)];
+}
+
+static int kernel_radius(double sigma) {
+    int R = (int)ceil(4.0 * sigma - 1e-9);
+    return R < 1 ? 1 : R;
+}
+
+static double *gaussian_taps(double sigma, int R) {
+    double *t = (double *)malloc(sizeof(double) * (2 * R + 1));
+    double s2 = 2.0 * sigma * sigma, sum = 0.0;
+    for (int i = -R; i <= R; i++) {
+        t[i + R] = exp(-(double)(i * i) / s2);
+        sum = sum + t[i + R];
+    }
+    for (int i = 0; i < 2 * R + 1; i++) t[i] = t[i] / sum;
+    return t;
+}
+
+/* One 1D convolution pass along axis a over a box. */
+static void conv_axis(const double *in, double *out, const int *e, const int *n, int a,
+                      const double *taps, int R, double W) {
+    for (int z = 0; z < e[2]; z++)
+        for (int y = 0; y < e[1]; y++)
+            for (int x = 0; x < e[0]; x++) {
+                double acc = 0.0;
+                for (int i = -R; i <= R; i++) {
+                    long c[3] = {x, y, z};
+                    c[a] += i;
+                    acc = acc + taps[i + R] * sample(in, e, n, c[0], c[1], c[2], -W);
+                }
+                out[lidx(e, x, y, z)] = acc;
+            }
+}
+
+/* Gaussian predictor on one box: x, then y, then z (3D). */
+static void predictor_box(int dim, const int *n, double W, const int *e, const double *f,
+                          double *out, const double *taps, int R) {
+    long m = nvox(e);
+    double *t1 = (double *)malloc(sizeof(double) * m);
+    conv_axis(f, t1, e, n, 0, taps, R, W);
+    if (dim == 2) {
+        conv_axis(t1, out, e, n, 1, taps, R, W);
+    } else {
+        double *t2 = (double *)malloc(sizeof(double) * m);
+        conv_axis(t1, t2, e, n, 1, taps, R, W);
+        conv_axis(t2, out, e, n, 2, taps, R, W);
+        free(t2);
+    }
+    free(t1);
+}
+
+/* Re-initialization on one box: exact L1 reference values next to the sign
+ * change, spread by three 1D min-plus passes (x, y, z). */
+static void redistance_box(int dim, const int *n, double W, const int *e, const double *f,
+                           double *out) {
+    long m = nvox(e);
+    int K = (int)ceil(W);
+    double *ref = (double *)malloc(sizeof(double) * m);
+    double *tmp = (double *)malloc(sizeof(double) * m);
+    for (int z = 0; z < e[2]; z++)
+        for (int y = 0; y < e[1]; y++)
+            for (int x = 0; x < e[0]; x++) {
+                double fx = f[lidx(e, x, y, z)];
+                int in = fx > 0.0;
+                double r = INFINITY;
+                for (int a = 0; a < dim; a++)
+                    for (int s = -1; s <= 1; s += 2) {
+                        long c[3] = {x, y, z};
+                        c[a] += s;
+                        double fn = sample(f, e, n, c[0], c[1], c[2], -W);
+                        if ((fn > 0.0) != in) {
+                            double th = fx / (fx - fn);
+                            if (th < r) r = th;
+                        }
+                    }
+                ref[lidx(e, x, y, z)] = r;
+            }
+    double *src = ref, *dst = tmp;
+    for (int a = 0; a < dim; a++) {
+        for (int z = 0; z < e[2]; z++)
+            for (int y = 0; y < e[1]; y++)
+                for (int x = 0; x < e[0]; x++) {
+                    double best = INFINITY;
+                    for (int i = -K; i <= K; i++) {
+                        long c[3] = {x, y, z};
+                        c[a] += i;
+                        double t = sample(src, e, n, c[0], c[1], c[2], INFINITY) + (double)abs(i);
+                        if (t < best) best = t;
+                    }
+                    dst[lidx(e, x, y, z)] = best;
+                }
+        double *sw = src;
+        src = dst;
+        dst = sw;
+    }
+    for (long v = 0; v < m; v++) {
+        double d = fmin(src[v], W);
+        out[v] = f[v] > 0.0 ? d : -d;
+    }
+    free(ref);
+    free(tmp);
+}
+
+static double volume_box(const double *phi, long m) {
+    double v = 0.0;
+    for (long i = 0; i < m; i++) {
+        double c = phi[i] + 0.5;
+        if (c < 0.0) c = 0.0;
+        if (c > 1.0) c = 1.0;
+        v = v + c;
+    }
+    return v;
+}
+
+/* Covered cyclic interval of an occupancy row: the complement of the largest
+ * cyclic run of empty cells (ties to the run with the smallest start).
+ * Returns 0 if nothing is occupied; len == N when nothing is empty. */
+static int cyclic_cover(const unsigned char *occ, int N, int *start, int *len) {
+    int any = 0, full = 1;
+    for (int i = 0; i < N; i++) {
+        if (occ[i]) any = 1;
+        else full = 0;
+    }
+    if (!any) return 0;
+    if (full) {
+        *start = 0;
+        *len = N;
+        return 1;
+    }
+    int best_s = -1, best_l = -1;
+    for (int s = 0; s < N; s++) {
+        if (occ[s] || !occ[wrapi(s - 1, N)]) continue; /* a run of empties starts at s */
+        int l = 0;
+        while (l < N && !occ[wrapi(s + l, N)]) l++;
+        if (l > best_l) {
+            best_l = l;
+            best_s = s;
+        }
+    }
+    *start = wrapi(best_s + best_l, N);
+    *len = N - best_l;
+    return 1;
+}
+
+/* New (lo, ext) along one axis from a covered interval (start, len). */
+static void pad_interval(int start, int len, int P, int N, int *lo, int *ext) {
+    long e = (long)len + 2L * P;
+    if (e >= N) {
+        *ext = N;
+        *lo = 0;
+    } else {
+        *ext = (int)e;
+        *lo = wrapi((long)start - P, N);
+    }
+}
+
+static int boxes_overlap(const int *loa, const int *ea, const int *lob, const int *eb,
+                         const int *n) {
+    for (int a = 0; a < 3; a++) {
+        if (!(wrapi((long)lob[a] - loa[a], n[a]) < ea[a] || wrapi((long)loa[a] - lob[a], n[a]) < eb[a]))
+            return 0;
+    }
+    return 1;
+}
+
+/* ------------------------------------------------------------- physics (a2) */
+
+double orc_misorientation_deg(const double qa[4], const double qb[4]) {
+    /* dq = conj(qa) * qb */
+    double aw = qa[0], ax = -qa[1], ay = -qa[2], az = -qa[3];
+    double bw = qb[0], bx = qb[1], by = qb[2], bz = qb[3];
+    double dw = aw * bw - ax * bx - ay * by - az * bz;
+    double dx = aw * bx + ax * bw + ay * bz - az * by;
+    double dy = aw * by - ax * bz + ay * bw + az * bx;
+    double dz = aw * bz + ax * by - ay * bx + az * bw;
+    double best = 4.0;
+    /* proper rotations of the hexagonal 622 group: 6-fold about c (z) and six
+     * 2-fold axes in the basal plane */
+    for (int k = 0; k < 6; k++) {
+        double h = 0.5 * (M_PI / 3.0) * k;
+        double sw[2] = {cos(h), 0.0}, sx[2] = {0.0, cos(h)}, sy[2] = {0.0, sin(h)},
+               sz[2] = {sin(h), 0.0};
+        for (int t = 0; t < 2; t++) {
+            double w = dw * sw[t] - dx * sx[t] - dy * sy[t] - dz * sz[t];
+            double c = fabs(w);
+            if (c > 1.0) c = 1.0;
+            double ang = 2.0 * acos(c);
+            if (ang < best) best = ang;
+        }
+    }
+    return best * 180.0 / M_PI;
+}
+
+double orc_pair_weight(double theta_deg, double theta_c_deg, double *mobility) {
+    double g;
+    if (theta_deg >= theta_c_deg) g = 1.0;
+    else if (theta_deg <= 0.0) g = 0.0;
+    else {
+        double r = theta_deg / theta_c_deg;
+        g = r * (1.0 - log(r));
+    }
+    double mu = 1.0 - 0.99 * exp(-5.0 * pow(theta_deg / 15.0, 9.0));
+    if (mobility) *mobility = mu;
+    return mu * g;
+}
+
+/* --------------------------------------------------------------- lifecycle */
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_keep_intermediates(orc_sim *s, int on) {
+    if (s) s->keep = on;
+}
+
+static void free_intermediates(orc_sim *s) {
+    if (s->psi)
+        for (int k = 0; k < s->G; k++) {
+            free(s->psi[k]);
+            s->psi[k] = NULL;
+        }
+    if (s->phic)
+        for (int k = 0; k < s->G; k++) {
+            free(s->phic[k]);
+            s->phic[k] = NULL;
+        }
+}
+
+void orc_destroy(orc_sim *s) {
+    if (!s) return;
+    for (int k = 0; k < s->G; k++) {
+        free(s->phi[k]);
+        free(s->iota[k]);
+    }
+    free_intermediates(s);
+    free(s->psi);
+    free(s->phic);
+    free(s->phi);
+    free(s->iota);
+    free(s->alive);
+    free(s->lo);
+    free(s->ext);
+    free(s->vol);
+    free(s->quat);
+    free(s->energy);
+    free(s->plo);
+    free(s->pext);
+    free(s->palive);
+    free(s);
+}
+
+static int valid_grid(int dim, const int32_t n[3]) {
+    if (dim != 2 && dim != 3) return 0;
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) return 0;
+    if (dim == 2 && n[2] != 1) return 0;
+    return 1;
+}
+
+/* Corrector argmax on the current phi (no halving): the initial ID-field. */
+static void initial_iota(orc_sim *s);
+
+orc_sim *orc_create(int dim, const int32_t n[3], double band, const int32_t *labels, int32_t G) {
+    if (!valid_grid(dim, n) || !labels || G < 1 || !(band >= 1.0) || !isfinite(band)) return NULL;
+    long nt = (long)n[0] * n[1] * n[2];
+    for (long i = 0; i < nt; i++)
+        if (labels[i] < 0 || labels[i] >= G) return NULL;
+    orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
+    s->dim = dim;
+    memcpy(s->n, n, sizeof(int) * 3);
+    s->W = band;
+    s->P = (int)ceil(band);
+    s->G = G;
+    s->alive = (int *)calloc(G, sizeof(int));
+    s->lo = (int *)calloc(3L * G, sizeof(int));
+    s->ext = (int *)calloc(3L * G, sizeof(int));
+    s->phi = (double **)calloc(G, sizeof(double *));
+    s->iota = (int **)calloc(G, sizeof(int *));
+    s->vol = (double *)calloc(G, sizeof(double));
+    s->psi = (double **)calloc(G, sizeof(double *));
+    s->phic = (double **)calloc(G, sizeof(double *));
+    s->plo = (int *)calloc(3L * G, sizeof(int));
+    s->pext = (int *)calloc(3L * G, sizeof(int));
+    s->palive = (int *)calloc(G, sizeof(int));
+
+    /* initial boxes: per axis, the covered cyclic interval of the grain's
+     * projection, padded by P */
+    long ntot_axis = (long)n[0] + n[1] + n[2];
+    unsigned char *occ = (unsigned char *)calloc((size_t)G * ntot_axis, 1);
+    for (int z = 0; z < n[2]; z++)
+        for (int y = 0; y < n[1]; y++)
+            for (int x = 0; x < n[0]; x++) {
+                int k = labels[x + (long)n[0] * (y + (long)n[1] * z)];
+                unsigned char *o = occ + (size_t)k * ntot_axis;
+                o[x] = 1;
+                o[n[0] + y] = 1;
+                o[n[0] + n[1] + z] = 1;
+            }
+    for (int k = 0; k < G; k++) {
+        unsigned char *o = occ + (size_t)k * ntot_axis;
+        int ok = 1, off = 0;
+        for (int a = 0; a < 3; a++) {
+            int st, ln;
+            if (!cyclic_cover(o + off, n[a], &st, &ln)) {
+                ok = 0;
+                break;
+            }
+            pad_interval(st, ln, s->P, n[a], &s->lo[3 * k + a], &s->ext[3 * k + a]);
+            off += n[a];
+        }
+        s->alive[k] = ok;
+    }
+    free(occ);
+
+    /* initial phi: +1/2 on the grain's voxels, -1/2 elsewhere, redistanced */
+#pragma omp parallel for schedule(dynamic)
+    for (int k = 0; k < G; k++) {
+        if (!s->alive[k]) continue;
+        const int *lo = &s->lo[3 * k], *e = &s->ext[3 * k];
+        long m = nvox(e);
+        double *f0 = (double *)malloc(sizeof(double) * m);
+        for (int z = 0; z < e[2]; z++)
+            for (int y = 0; y < e[1]; y++)
+                for (int x = 0; x < e[0]; x++) {
+                    int gx = wrapi((long)lo[0] + x, n[0]), gy = wrapi((long)lo[1] + y, n[1]),
+                        gz = wrapi((long)lo[2] + z, n[2]);
+                    int lab = labels[gx + (long)n[0] * (gy + (long)n[1] * gz)];
+                    f0[lidx(e, x, y, z)] = lab == k ? 0.5 : -0.5;
+                }
+        s->phi[k] = (double *)malloc(sizeof(double) * m);
+        redistance_box(dim, s->n, s->W, e, f0, s->phi[k]);
+        free(f0);
+        s->iota[k] = (int *)malloc(sizeof(int) * m);
+        for (long v = 0; v < m; v++) s->iota[k][v] = -1;
+        s->vol[k] = volume_box(s->phi[k], m);
+    }
+    return s;
+}
+
+/* ----------------------------------------------------------------- corrector */
+
+/* For each alive grain, the alive grains whose boxes overlap its box. */
+static int **candidate_lists(const orc_sim *s, int *counts) {
+    int G = s->G;
+    int **lists = (int **)calloc(G, sizeof(int *));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int k = 0; k < G; k++) {
+        counts[k] = 0;
+        if (!s->alive[k]) continue;
+        int cap = 16, c = 0;
+        int *l = (int *)malloc(sizeof(int) * cap);
+        for (int j = 0; j < G; j++) {
+            if (j == k || !s->alive[j]) continue;
+            if (!boxes_overlap(&s->lo[3 * k], &s->ext[3 * k], &s->lo[3 * j], &s->ext[3 * j], s->n))
+                continue;
+            if (c == cap) {
+                cap *= 2;
+                l = (int *)realloc(l, sizeof(int) * cap);
+            }
+            l[c++] = j; /* ascending id order */
+        }
+        lists[k] = l;
+        counts[k] = c;
+    }
+    return lists;
+}
+
+/* max over the other covering grains of field[j] at global voxel g, with its
+ * argmax (ties to the lowest id); returns 0 (and leaves m, id) if none covers */
+static int max_other(const orc_sim *s, double *const *field, const int *cand, int nc,
+                     const int g[3], double *m, int *id) {
+    int have = 0;
+    for (int c = 0; c < nc; c++) {
+        int j = cand[c];
+        const int *lo = &s->lo[3 * j], *e = &s->ext[3 * j];
+        int lx = wrapi((long)g[0] - lo[0], s->n[0]);
+        int ly = wrapi((long)g[1] - lo[1], s->n[1]);
+        int lz = wrapi((long)g[2] - lo[2], s->n[2]);
+        if (lx >= e[0] || ly >= e[1] || lz >= e[2]) continue;
+        double v = field[j][lidx(e, lx, ly, lz)];
+        if (!have || v > *m) {
+            *m = v;
+            *id = j;
+            have = 1;
+        }
+    }
+    return have;
+}
+
+static void initial_iota(orc_sim *s) {
+    int *counts = (int *)calloc(s->G, sizeof(int));
+    int **cand = candidate_lists(s, counts);
+#pragma omp parallel for schedule(dynamic)
+    for (int k = 0; k < s->G; k++) {
+        if (!s->alive[k]) continue;
+        const int *lo = &s->lo[3 * k], *e = &s->ext[3 * k];
+        for (int z = 0; z < e[2]; z++)
+            for (int y = 0; y < e[1]; y++)
+                for (int x = 0; x < e[0]; x++) {
+                    int g[3] = {wrapi((long)lo[0] + x, s->n[0]), wrapi((long)lo[1] + y, s->n[1]),
+                                wrapi((long)lo[2] + z, s->n[2])};
+                    double m = 0.0;
+                    int id = -1;
+                    max_other(s, s->phi, cand[k], counts[k], g, &m, &id);
+                    s->iota[k][lidx(e, x, y, z)] = id;
+                }
+    }
+    for (int k = 0; k < s->G; k++) free(cand[k]);
+    free(cand);
+    free(counts);
+}
+
+int orc_set_physics(orc_sim *s, int mode, const double *quat, double theta_c_deg,
+                    const double *energy, double h_phys, double gamma_max) {
+    if (!s || mode < 0 || mode > 3) return -1;
+    if ((mode & 1) && (!quat || !(theta_c_deg > 0.0))) return -1;
+    if ((mode & 2) && (!energy || !(h_phys > 0.0) || !(gamma_max > 0.0))) return -1;
+    s->mode = mode;
+    free(s->quat);
+    free(s->energy);
+    s->quat = NULL;
+    s->energy = NULL;
+    if (mode & 1) {
+        s->quat = (double *)malloc(sizeof(double) * 4 * s->G);
+        memcpy(s->quat, quat, sizeof(double) * 4 * s->G);
+        s->theta_c = theta_c_deg;
+    }
+    if (mode & 2) {
+        s->energy = (double *)malloc(sizeof(double) * s->G);
+        memcpy(s->energy, energy, sizeof(double) * s->G);
+        s->h_phys = h_phys;
+        s->gamma_max = gamma_max;
+    }
+    if (mode) initial_iota(s);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- step */
+
+int orc_step(orc_sim *s, double dt) {
+    if (!s || !(dt > 0.0) || !isfinite(dt)) return -1;
+    const int G = s->G, dim = s->dim;
+    const int *n = s->n;
+    const double W = s->W;
+    double sigma = sqrt(2.0 * dt) * (double)n[0];
+    int R = kernel_radius(sigma);
+    double *taps = gaussian_taps(sigma, R);
+    double bulk_scale = (s->mode & 2) ? sigma * sigma * s->h_phys / (2.0 * s->gamma_max) : 0.0;
+    free_intermediates(s);
+    double **psi = s->psi, **phic = s->phic;
+    int **niota = (int **)calloc(G, sizeof(int *));
+
+    /* 1. predictor (+ correction) */
+#pragma omp parallel for schedule(dynamic)
+    for (int k = 0; k < G; k++) {
+        if (!s->alive[k]) continue;
+        const int *e = &s->ext[3 * k];
+        long m = nvox(e);
+        psi[k] = (double *)malloc(sizeof(double) * m);
+        predictor_box(dim, n, W, e, s->phi[k], psi[k], taps, R);
+        if (s->mode) {
+            for (long v = 0; v < m; v++) {
+                int j = s->iota[k][v];
+                double w = 1.0, mob = 1.0, b = 0.0;
+                if (j >= 0) {
+                    if (s->mode & 1) {
+                        double th = orc_misorientation_deg(&s->quat[4 * k], &s->quat[4 * j]);
+                        w = orc_pair_weight(th, s->theta_c, &mob);
+                    }
+                    if (s->mode & 2) b = mob * (s->energy[j] - s->energy[k]) * bulk_scale;
+                }
+                double p = s->phi[k][v];
+                double d = p + w * (psi[k][v] - p) + b;
+                if (d > W) d = W;
+                if (d < -W) d = -W;
+                psi[k][v] = d;
+            }
+        }
+    }
+
+    /* 2. corrector */
+    int *counts = (int *)calloc(G, sizeof(int));
+    int **cand = candidate_lists(s, counts);
+#pragma omp parallel for schedule(dynamic)
+    for (int k = 0; k < G; k++) {
+        if (!s->alive[k]) continue;
+        const int *lo = &s->lo[3 * k], *e = &s->ext[3 * k];
+        long m = nvox(e);
+        phic[k] = (double *)malloc(sizeof(double) * m);
+        niota[k] = (int *)malloc(sizeof(int) * m);
+        for (int z = 0; z < e[2]; z++)
+            for (int y = 0; y < e[1]; y++)
+                for (int x = 0; x < e[0]; x++) {
+                    int g[3] = {wrapi((long)lo[0] + x, n[0]), wrapi((long)lo[1] + y, n[1]),
+                                wrapi((long)lo[2] + z, n[2])};
+                    double mx = 0.0;
+                    int id = -1;
+                    if (!max_other(s, psi, cand[k], counts[k], g, &mx, &id)) mx = -W;
+                    long v = lidx(e, x, y, z);
+                    phic[k][v] = 0.5 * (psi[k][v] - mx);
+                    niota[k][v] = id;
+                }
+    }
+    for (int k = 0; k < G; k++) free(cand[k]);
+    free(cand);
+    free(counts);
+
+    memcpy(s->plo, s->lo, sizeof(int) * 3 * G);
+    memcpy(s->pext, s->ext, sizeof(int) * 3 * G);
+    memcpy(s->palive, s->alive, sizeof(int) * G);
+
+    /* 3.-6. extinction, box update, re-initialization, volume */
+#pragma omp parallel for schedule(dynamic)
+    for (int k = 0; k < G; k++) {
+        if (!s->alive[k]) continue;
+        int *lo = &s->lo[3 * k], *e = &s->ext[3 * k];
+        int olo[3] = {lo[0], lo[1], lo[2]}, oe[3] = {e[0], e[1], e[2]};
+        /* bounding box of the positive set (cyclic rule on full-grid axes) */
+        int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-1, -1, -1};
+        unsigned char *occ[3] = {NULL, NULL, NULL};
+        for (int a = 0; a < 3; a++)
+            if (oe[a] == n[a]) occ[a] = (unsigned char *)calloc(n[a], 1);
+        int any = 0;
+        for (int z = 0; z < oe[2]; z++)
+            for (int y = 0; y < oe[1]; y++)
+                for (int x = 0; x < oe[0]; x++) {
+                    if (!(phic[k][lidx(oe, x, y, z)] > 0.0)) continue;
+                    int c[3] = {x, y, z};
+                    any = 1;
+                    for (int a = 0; a < 3; a++) {
+                        if (c[a] < mn[a]) mn[a] = c[a];
+                        if (c[a] > mx[a]) mx[a] = c[a];
+                        if (occ[a]) occ[a][c[a]] = 1;
+                    }
+                }
+        if (!any) {
+            s->alive[k] = 0;
+            s->vol[k] = 0.0;
+            free(s->phi[k]);
+            free(s->iota[k]);
+            s->phi[k] = NULL;
+            s->iota[k] = NULL;
+            for (int a = 0; a < 3; a++) free(occ[a]);
+            continue;
+        }
+        int nlo[3], ne[3];
+        for (int a = 0; a < 3; a++) {
+            int st, ln;
+            if (occ[a]) {
+                cyclic_cover(occ[a], n[a], &st, &ln);
+                st = wrapi((long)olo[a] + st, n[a]);
+                free(occ[a]);
+            } else {
+                st = wrapi((long)olo[a] + mn[a], n[a]);
+                ln = mx[a] - mn[a] + 1;
+            }
+            pad_interval(st, ln, s->P, n[a], &nlo[a], &ne[a]);
+        }
+        /* carry phi^c and iota over to the new box through the sampling rule */
+        long m = nvox(ne);
+        double *f = (double *)malloc(sizeof(double) * m);
+        int *io = (int *)malloc(sizeof(int) * m);
+        for (int z = 0; z < ne[2]; z++)
+            for (int y = 0; y < ne[1]; y++)
+                for (int x = 0; x < ne[0]; x++) {
+                    long g0 = (long)nlo[0] + x, g1 = (long)nlo[1] + y, g2 = (long)nlo[2] + z;
+                    int ox = wrapi(g0 - olo[0], n[0]), oy = wrapi(g1 - olo[1], n[1]),
+                        oz = wrapi(g2 - olo[2], n[2]);
+                    long v = lidx(ne, x, y, z);
+                    if (ox < oe[0] && oy < oe[1] && oz < oe[2]) {
+                        f[v] = phic[k][lidx(oe, ox, oy, oz)];
+                        io[v] = niota[k][lidx(oe, ox, oy, oz)];
+                    } else {
+                        f[v] = -W;
+                        io[v] = -1;
+                    }
+                }
+        free(s->phi[k]);
+        free(s->iota[k]);
+        s->phi[k] = (double *)malloc(sizeof(double) * m);
+        redistance_box(dim, n, W, ne, f, s->phi[k]);
+        s->iota[k] = io;
+        memcpy(lo, nlo, sizeof(nlo));
+        memcpy(e, ne, sizeof(ne));
+        s->vol[k] = volume_box(s->phi[k], m);
+        free(f);
+    }
+    for (int k = 0; k < G; k++) free(niota[k]);
+    free(niota);
+    if (!s->keep) free_intermediates(s);
+    free(taps);
+    return 0;
+}
+
+/* ------------------------------------------------------------------- queries */
+
+int orc_grain_count(const orc_sim *s) { return s ? s->G : -1; }
+
+int orc_alive_count(const orc_sim *s) {
+    if (!s) return -1;
+    int c = 0;
+    for (int k = 0; k < s->G; k++) c += s->alive[k] != 0;
+    return c;
+}
+
+int orc_get_box(const orc_sim *s, int k, int32_t lo[3], int32_t ext[3]) {
+    if (!s || k < 0 || k >= s->G) return -1;
+    for (int a = 0; a < 3; a++) {
+        lo[a] = s->lo[3 * k + a];
+        ext[a] = s->ext[3 * k + a];
+    }
+    return s->alive[k] ? 1 : 0;
+}
+
+int orc_get_prev_box(const orc_sim *s, int k, int32_t lo[3], int32_t ext[3]) {
+    if (!s || k < 0 || k >= s->G) return -1;
+    for (int a = 0; a < 3; a++) {
+        lo[a] = s->plo[3 * k + a];
+        ext[a] = s->pext[3 * k + a];
+    }
+    return s->palive[k] ? 1 : 0;
+}
+
+static int copy_field(const double *src, const int *e, double *out, int64_t cap) {
+    if (!src) return -1;
+    long m = nvox(e);
+    if (cap < m) return -1;
+    memcpy(out, src, sizeof(double) * m);
+    return 0;
+}
+
+int orc_get_phi(const orc_sim *s, int k, double *out, int64_t cap) {
+    if (!s || k < 0 || k >= s->G || !s->alive[k]) return -1;
+    return copy_field(s->phi[k], &s->ext[3 * k], out, cap);
+}
+
+int orc_get_iota(const orc_sim *s, int k, int32_t *out, int64_t cap) {
+    if (!s || k < 0 || k >= s->G || !s->alive[k]) return -1;
+    long m = nvox(&s->ext[3 * k]);
+    if (cap < m) return -1;
+    memcpy(out, s->iota[k], sizeof(int) * m);
+    return 0;
+}
+
+int orc_get_psi(const orc_sim *s, int k, double *out, int64_t cap) {
+    if (!s || k < 0 || k >= s->G || !s->palive[k]) return -1;
+    return copy_field(s->psi[k], &s->pext[3 * k], out, cap);
+}
+
+int orc_get_phic(const orc_sim *s, int k, double *out, int64_t cap) {
+    if (!s || k < 0 || k >= s->G || !s->palive[k]) return -1;
+    return copy_field(s->phic[k], &s->pext[3 * k], out, cap);
+}
+
+int orc_set_grain(orc_sim *s, int k, int alive, const int32_t lo[3], const int32_t ext[3],
+                  const double *phi, const int32_t *iota) {
+    if (!s || k < 0 || k >= s->G) return -1;
+    free(s->phi[k]);
+    free(s->iota[k]);
+    s->phi[k] = NULL;
+    s->iota[k] = NULL;
+    s->alive[k] = 0;
+    s->vol[k] = 0.0;
+    if (!alive) return 0;
+    for (int a = 0; a < 3; a++) {
+        if (ext[a] < 1 || ext[a] > s->n[a] || lo[a] < 0 || lo[a] >= s->n[a]) return -1;
+    }
+    if (!phi) return -1;
+    for (int a = 0; a < 3; a++) {
+        s->lo[3 * k + a] = lo[a];
+        s->ext[3 * k + a] = ext[a];
+    }
+    long m = nvox(&s->ext[3 * k]);
+    s->phi[k] = (double *)malloc(sizeof(double) * m);
+    memcpy(s->phi[k], phi, sizeof(double) * m);
+    s->iota[k] = (int *)malloc(sizeof(int) * m);
+    for (long v = 0; v < m; v++) s->iota[k][v] = iota ? iota[v] : -1;
+    s->alive[k] = 1;
+    s->vol[k] = volume_box(s->phi[k], m);
+    return 0;
+}
+
+int orc_volumes(const orc_sim *s, double *out) {
+    if (!s || !out) return -1;
+    for (int k = 0; k < s->G; k++) out[k] = s->alive[k] ? s->vol[k] : 0.0;
+    return 0;
+}
+
+int orc_labels(const orc_sim *s, int32_t *out) {
+    if (!s || !out) return -1;
+    const int *n = s->n;
+    long nt = (long)n[0] * n[1] * n[2];
+    double *best = (double *)malloc(sizeof(double) * nt);
+    for (long i = 0; i < nt; i++) {
+        best[i] = -INFINITY;
+        out[i] = -1;
+    }
+    for (int k = 0; k < s->G; k++) { /* ascending id, strict '>' : ties -> lowest id */
+        if (!s->alive[k]) continue;
+        const int *lo = &s->lo[3 * k], *e = &s->ext[3 * k];
+        for (int z = 0; z < e[2]; z++)
+            for (int y = 0; y < e[1]; y++)
+                for (int x = 0; x < e[0]; x++) {
+                    long g = wrapi((long)lo[0] + x, n[0]) +
+                             (long)n[0] * (wrapi((long)lo[1] + y, n[1]) +
+                                           (long)n[1] * wrapi((long)lo[2] + z, n[2]));
+                    double v = s->phi[k][lidx(e, x, y, z)];
+                    if (v > best[g]) {
+                        best[g] = v;
+                        out[g] = k;
+                    }
+                }
+    }
+    free(best);
+    return 0;
+}
+
+/* ------------------------------------------------------- stand-alone pieces */
+
+int orc_convolve_box(int dim, const int32_t n[3], double band, double sigma,
+                     const int32_t lo[3], const int32_t ext[3], const double *f, double *out) {
+    (void)lo;
+    if (!valid_grid(dim, n) || !(sigma > 0.0) || !f || !out) return -1;
+    int e[3] = {ext[0], ext[1], ext[2]}, nn[3] = {n[0], n[1], n[2]};
+    int R = kernel_radius(sigma);
+    double *taps = gaussian_taps(sigma, R);
+    predictor_box(dim, nn, band, e, f, out, taps, R);
+    free(taps);
+    return R;
+}
+
+int orc_redistance_box(int dim, const int32_t n[3], double band,
+                       const int32_t lo[3], const int32_t ext[3], const double *f, double *out) {
+    (void)lo;
+    if (!valid_grid(dim, n) || !f || !out) return -1;
+    int e[3] = {ext[0], ext[1], ext[2]}, nn[3] = {n[0], n[1], n[2]};
+    redistance_box(dim, nn, band, e, f, out);
+    return 0;
+}

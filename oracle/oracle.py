@@ -1,0 +1,249 @@
+"""ctypes wrapper of the C oracle in ``gg_oracle.c`` (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gg_oracle.c")
+_LIB = os.path.join(_HERE, "libgg_oracle.so")
+_lib = None
+
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+
+def build_oracle(force=True):
+    """Compile the oracle with gcc (FP64, no FMA contraction, OpenMP)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + f".tmp{os.getpid()}"
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", "-Wall", "-Wno-unknown-pragmas", _SRC, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def load_library():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build_oracle()
+    lib = C.CDLL(_LIB)
+    i32_3 = C.POINTER(C.c_int32)
+    lib.orc_create.restype = C.c_void_p
+    lib.orc_create.argtypes = [C.c_int, _i32p, C.c_double, _i32p, C.c_int32]
+    lib.orc_destroy.argtypes = [C.c_void_p]
+    lib.orc_set_physics.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_void_p,
+                                    C.c_double, C.c_double]
+    lib.orc_step.argtypes = [C.c_void_p, C.c_double]
+    lib.orc_keep_intermediates.argtypes = [C.c_void_p, C.c_int]
+    lib.orc_grain_count.argtypes = [C.c_void_p]
+    lib.orc_alive_count.argtypes = [C.c_void_p]
+    for f in (lib.orc_get_box, lib.orc_get_prev_box):
+        f.argtypes = [C.c_void_p, C.c_int, _i32p, _i32p]
+    for f in (lib.orc_get_phi, lib.orc_get_psi, lib.orc_get_phic):
+        f.argtypes = [C.c_void_p, C.c_int, _f64p, C.c_int64]
+    lib.orc_get_iota.argtypes = [C.c_void_p, C.c_int, _i32p, C.c_int64]
+    lib.orc_set_grain.argtypes = [C.c_void_p, C.c_int, C.c_int, _i32p, _i32p, C.c_void_p,
+                                  C.c_void_p]
+    lib.orc_volumes.argtypes = [C.c_void_p, _f64p]
+    lib.orc_labels.argtypes = [C.c_void_p, _i32p]
+    lib.orc_convolve_box.argtypes = [C.c_int, _i32p, C.c_double, C.c_double, _i32p, _i32p,
+                                     _f64p, _f64p]
+    lib.orc_redistance_box.argtypes = [C.c_int, _i32p, C.c_double, _i32p, _i32p, _f64p, _f64p]
+    lib.orc_misorientation_deg.restype = C.c_double
+    lib.orc_misorientation_deg.argtypes = [_f64p, _f64p]
+    lib.orc_pair_weight.restype = C.c_double
+    lib.orc_pair_weight.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_double)]
+    lib.orc_num_threads.restype = C.c_int
+    del i32_3
+    _lib = lib
+    return lib
+
+
+def _grid(n):
+    n = [int(v) for v in n]
+    if len(n) == 2:
+        n.append(1)
+    return np.array(n, dtype=np.int32)
+
+
+def _shape(ext):
+    return (int(ext[2]), int(ext[1]), int(ext[0]))
+
+
+class Oracle:
+    """One oracle simulation built from a label field of shape (nz, ny, nx)."""
+
+    def __init__(self, labels, band, G=None, dim=None):
+        lib = load_library()
+        labels = np.ascontiguousarray(labels, dtype=np.int32)
+        if labels.ndim == 2:
+            labels = labels[None]
+        nz, ny, nx = labels.shape
+        self.dim = int(dim or (2 if nz == 1 else 3))
+        self.n = _grid((nx, ny, nz))
+        self.G = int(G if G is not None else labels.max() + 1)
+        self.band = float(band)
+        self._lib = lib
+        self._p = lib.orc_create(self.dim, self.n, self.band, labels.ravel(), self.G)
+        if not self._p:
+            raise ValueError("oracle rejected the inputs")
+
+    def close(self):
+        if getattr(self, "_p", None):
+            self._lib.orc_destroy(self._p)
+            self._p = None
+
+    __del__ = close
+
+    def set_physics(self, mode, quat=None, theta_c_deg=15.0, energy=None, h_phys=0.0,
+                    gamma_max=0.0):
+        q = None if quat is None else np.ascontiguousarray(quat, dtype=np.float64)
+        e = None if energy is None else np.ascontiguousarray(energy, dtype=np.float64)
+        rc = self._lib.orc_set_physics(self._p, int(mode),
+                                       None if q is None else q.ctypes.data_as(C.c_void_p),
+                                       float(theta_c_deg),
+                                       None if e is None else e.ctypes.data_as(C.c_void_p),
+                                       float(h_phys), float(gamma_max))
+        if rc != 0:
+            raise ValueError("oracle rejected the physics inputs")
+        self._keep_q, self._keep_e = q, e
+
+    def keep_intermediates(self, on=True):
+        self._lib.orc_keep_intermediates(self._p, int(bool(on)))
+
+    def step(self, dt, n=1):
+        for _ in range(int(n)):
+            if self._lib.orc_step(self._p, float(dt)) != 0:
+                raise ValueError("oracle step failed")
+
+    def alive_count(self):
+        return self._lib.orc_alive_count(self._p)
+
+    def box(self, k, prev=False):
+        lo = np.zeros(3, np.int32)
+        ext = np.zeros(3, np.int32)
+        f = self._lib.orc_get_prev_box if prev else self._lib.orc_get_box
+        alive = f(self._p, int(k), lo, ext)
+        if alive < 0:
+            raise IndexError(k)
+        return bool(alive), lo, ext
+
+    def _field(self, getter, k, prev=False):
+        alive, lo, ext = self.box(k, prev)
+        if not alive:
+            return None
+        out = np.empty(int(np.prod(ext)), np.float64)
+        if getter(self._p, int(k), out, out.size) != 0:
+            return None
+        return out.reshape(_shape(ext))
+
+    def phi(self, k):
+        return self._field(self._lib.orc_get_phi, k)
+
+    def psi(self, k):
+        return self._field(self._lib.orc_get_psi, k, prev=True)
+
+    def phic(self, k):
+        return self._field(self._lib.orc_get_phic, k, prev=True)
+
+    def iota(self, k):
+        alive, lo, ext = self.box(k)
+        if not alive:
+            return None
+        out = np.empty(int(np.prod(ext)), np.int32)
+        if self._lib.orc_get_iota(self._p, int(k), out, out.size) != 0:
+            return None
+        return out.reshape(_shape(ext))
+
+    def set_grain(self, k, alive, lo=None, ext=None, phi=None, iota=None):
+        lo = np.ascontiguousarray(lo if lo is not None else [0, 0, 0], dtype=np.int32)
+        ext = np.ascontiguousarray(ext if ext is not None else [1, 1, 1], dtype=np.int32)
+        ph = None if phi is None else np.ascontiguousarray(phi, dtype=np.float64)
+        io = None if iota is None else np.ascontiguousarray(iota, dtype=np.int32)
+        rc = self._lib.orc_set_grain(self._p, int(k), int(bool(alive)), lo, ext,
+                                     None if ph is None else ph.ctypes.data_as(C.c_void_p),
+                                     None if io is None else io.ctypes.data_as(C.c_void_p))
+        if rc != 0:
+            raise ValueError("oracle rejected the grain state")
+
+    def volumes(self):
+        out = np.zeros(self.G, np.float64)
+        self._lib.orc_volumes(self._p, out)
+        return out
+
+    def labels(self):
+        out = np.empty(int(np.prod(self.n)), np.int32)
+        self._lib.orc_labels(self._p, out)
+        return out.reshape(int(self.n[2]), int(self.n[1]), int(self.n[0]))
+
+    def state(self):
+        """All grains: dict with alive (G,), lo (G,3), ext (G,3), phi (list of arrays or None)."""
+        alive = np.zeros(self.G, bool)
+        lo = np.zeros((self.G, 3), np.int32)
+        ext = np.zeros((self.G, 3), np.int32)
+        phis = []
+        for k in range(self.G):
+            a, l, e = self.box(k)
+            alive[k] = a
+            lo[k] = l
+            ext[k] = e
+            phis.append(self.phi(k) if a else None)
+        return dict(alive=alive, lo=lo, ext=ext, phi=phis)
+
+
+def convolve_box(f, band, sigma, n, dim=None):
+    """Predictor convolution of one box field f (shape (ez, ey, ex)) on grid n."""
+    lib = load_library()
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    if f.ndim == 2:
+        f = f[None]
+    nn = _grid(n)
+    dim = dim or (2 if nn[2] == 1 else 3)
+    ext = np.array([f.shape[2], f.shape[1], f.shape[0]], np.int32)
+    out = np.empty_like(f)
+    R = lib.orc_convolve_box(dim, nn, float(band), float(sigma), np.zeros(3, np.int32), ext,
+                             f.ravel(), out.ravel())
+    if R < 0:
+        raise ValueError("bad arguments")
+    return out
+
+
+def redistance_box(f, band, n, dim=None):
+    """Re-initialization of one box field f (shape (ez, ey, ex)) on grid n."""
+    lib = load_library()
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    if f.ndim == 2:
+        f = f[None]
+    nn = _grid(n)
+    dim = dim or (2 if nn[2] == 1 else 3)
+    ext = np.array([f.shape[2], f.shape[1], f.shape[0]], np.int32)
+    out = np.empty_like(f)
+    if lib.orc_redistance_box(dim, nn, float(band), np.zeros(3, np.int32), ext, f.ravel(),
+                              out.ravel()) != 0:
+        raise ValueError("bad arguments")
+    return out
+
+
+def misorientation_deg(qa, qb):
+    lib = load_library()
+    return lib.orc_misorientation_deg(np.ascontiguousarray(qa, np.float64),
+                                      np.ascontiguousarray(qb, np.float64))
+
+
+def pair_weight(theta_deg, theta_c_deg=15.0):
+    lib = load_library()
+    mob = C.c_double(0.0)
+    w = lib.orc_pair_weight(float(theta_deg), float(theta_c_deg), C.byref(mob))
+    return w, mob.value
+
+
+def num_threads():
+    return load_library().orc_num_threads()
