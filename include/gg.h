@@ -1,0 +1,168 @@
+/*
+ * gg.h -- C ABI of the MI355X (gfx950) level-set grain-growth library.
+ *
+ * One timestep of the local level-set method of Miessen, Velinov, Gottstein and
+ * Barrales-Mora (arXiv:1701.06658, sec. 2.1, Algorithm 1): every grain carries a
+ * signed-distance function on its own padded bounding box; a step is the
+ * Gaussian predictor (sec. 2.1.4), the comparison corrector (sec. 2.1.5), the
+ * taxicab re-initialization in the narrow band (sec. 2.1.6) and the box /
+ * neighbour update (sec. 3.1).
+ *
+ * Conventions
+ *  - Lengths are in voxels.  The grid is periodic with n[0] x n[1] x n[2] voxels
+ *    (n[2] == 1 in 2D); field arrays are x fastest: index x + n0*(y + n1*z).
+ *  - Grain ids are the label values 0 .. n_grains-1 given to gg_create; they
+ *    never change.  Extinct grains keep their id and report volume 0.
+ *  - A grain's box is (lo[3], ext[3]); global voxel g lies in it iff
+ *    (g - lo) mod n < ext on every axis.  Box values are stored x fastest.
+ *  - Every call returns gg_status; nothing throws across the boundary.  After
+ *    an error the text is available from gg_last_error.  A HIP runtime error
+ *    poisons the simulation: later calls return GG_E_POISONED (gg_destroy
+ *    still works).  Argument errors leave the simulation unchanged.
+ *  - Host pointers are read or written only during the call; the library
+ *    copies inputs and owns all device memory it allocates.
+ *  - Work is issued on the HIP stream given to gg_create (NULL: the library
+ *    creates its own).  gg_step returns when the steps have been issued and
+ *    the layout bookkeeping of the last step has been read back; query calls
+ *    synchronise the stream.
+ */
+#ifndef GG_H
+#define GG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gg_sim gg_sim;
+
+typedef enum {
+    GG_OK = 0,
+    GG_E_ARG = 1,         /* invalid argument; nothing changed                     */
+    GG_E_NOMEM = 2,       /* host or device allocation failed                     */
+    GG_E_HIP = 3,         /* HIP runtime error; the simulation is now poisoned     */
+    GG_E_CAPACITY = 4,    /* a size limit of the library was exceeded             */
+    GG_E_SMALLBUF = 5,    /* caller's output buffer is too small                  */
+    GG_E_NUMERIC = 6,     /* non-finite value detected                            */
+    GG_E_POISONED = 7,    /* an earlier HIP error poisoned this simulation         */
+    GG_E_UNSUPPORTED = 8, /* valid request this build does not implement          */
+    GG_E_NODEVICE = 9     /* no usable gfx950 device                              */
+} gg_status;
+
+typedef enum {
+    GG_FP64 = 0, /* plain path: FP64 storage and arithmetic                      */
+    GG_FP32 = 1  /* mixed path: FP32 storage/arithmetic, FP64 volume reductions  */
+} gg_precision;
+
+/* Predictor-correction terms (sec. 2.1.4, Eq. eq:velocorrect). */
+enum {
+    GG_PHYS_NONE = 0,
+    GG_PHYS_MISORIENTATION = 1, /* per-pair weight w = mobility * energy from the
+                                   misorientation of the two grains (hexagonal 622
+                                   symmetry; Read-Shockley energy below theta_c,
+                                   mobility law Eq. eq:GB_mob); needs quat       */
+    GG_PHYS_BULK = 2            /* per-grain bulk energy density driving force
+                                   (Eqs. magneticE/magneticF, normalised with
+                                   Eq. bulk normalization); needs energy_density */
+};
+
+typedef struct {
+    int32_t dim;            /* 2 or 3                                               */
+    int32_t n[3];           /* periodic grid size; n[2] == 1 when dim == 2           */
+    double band;            /* narrow-band half width W in voxels (1 <= W <= 16);
+                               the box pad is P = ceil(W) (Fig. 1a: >= 7 points)   */
+    int32_t precision;      /* gg_precision                                         */
+    int32_t physics;        /* GG_PHYS_* bits                                       */
+    double theta_c_deg;     /* Read-Shockley cutoff angle (GG_PHYS_MISORIENTATION)   */
+    double voxel_m;         /* voxel edge h in metres (GG_PHYS_BULK)                 */
+    double gamma_max;       /* maximal boundary energy, J/m^2 (GG_PHYS_BULK)         */
+    double capacity_headroom; /* device arena slack factor (0: default 1.25)       */
+} gg_config;
+
+typedef struct {
+    int64_t steps;          /* steps taken since gg_create                          */
+    int32_t alive;          /* alive grains                                         */
+    int32_t kernel_radius;  /* R of the last step                                   */
+    int64_t grain_voxels;   /* sum of box volumes at the start of the last step    */
+    int64_t capacity;       /* device arena capacity in values                      */
+    double superposition;   /* grain_voxels / prod(n)                               */
+    double last_step_ms;    /* device time of the last gg_step call / its n_steps   */
+} gg_step_stats;
+
+/* Create a simulation from a label field (host, prod(n) int32, x fastest, values
+ * in [0, n_grains)); sec. 3.1: one grain object per cell of the input tessellation.
+ * Each grain's box is the covered cyclic interval of its projection on every
+ * axis, padded by P; its function is the re-initialised +-1/2 indicator.
+ * quat: 4*n_grains doubles (w,x,y,z) or NULL; energy_density: n_grains doubles
+ * in J/m^3 or NULL (required by the matching physics bits).
+ * hip_stream: a hipStream_t or NULL.  On success *out owns the simulation.
+ * Errors: GG_E_ARG (bad config/labels), GG_E_NODEVICE, GG_E_NOMEM, GG_E_HIP. */
+gg_status gg_create(const gg_config *cfg, const int32_t *labels, int32_t n_grains,
+                    const double *quat, const double *energy_density, void *hip_stream,
+                    gg_sim **out);
+
+/* Advance n_steps timesteps of normalised length dt (Algorithm 1): Gaussian
+ * width sigma = sqrt(2 dt) * n[0] voxels (heat kernel of Eq. Heatequation),
+ * kernel radius R = ceil(4 sigma).  Requires R <= 2*ceil(W) and R <= 24.
+ * Errors: GG_E_ARG (dt not finite/positive, n_steps < 0, R too large),
+ * GG_E_CAPACITY, GG_E_HIP, GG_E_POISONED. */
+gg_status gg_step(gg_sim *sim, double dt, int32_t n_steps);
+
+/* Wait for all issued work. */
+gg_status gg_sync(gg_sim *sim);
+
+/* Number of alive grains. */
+gg_status gg_grain_count(gg_sim *sim, int32_t *alive);
+
+/* Grain volumes V_k = sum over the box of clamp(phi + 1/2, 0, 1), FP64, indexed
+ * by grain id (0 for extinct grains); out: host, cap >= n_grains. */
+gg_status gg_grain_volumes(gg_sim *sim, double *out, int64_t cap);
+
+/* Voxel labels: argmax over the grains whose box covers the voxel of their
+ * function (ties to the lowest id); out: prod(n) int32, x fastest, host memory,
+ * or device memory on the simulation's device when out_is_device != 0 (then
+ * the write is ordered on the simulation's stream and the call does not wait). */
+gg_status gg_labels(gg_sim *sim, int32_t *out, int64_t cap, int32_t out_is_device);
+
+/* Step statistics. */
+gg_status gg_stats(gg_sim *sim, gg_step_stats *out);
+
+/* State access (host memory).  gg_get_boxes fills cap >= n_grains entries:
+ * lo/ext 3 per grain, alive 1 per grain, offset 1 per grain (start of the
+ * grain's values in the packed order used by gg_get_values, -1 if extinct).
+ * gg_get_values writes all alive grains' values as doubles in that packed
+ * order (cap >= sum of box volumes); gg_get_iota does the same for the
+ * ID-field (argmax neighbour of the last corrector, -1 where none). */
+gg_status gg_get_boxes(gg_sim *sim, int32_t *lo, int32_t *ext, int32_t *alive, int64_t *offset,
+                       int64_t cap);
+gg_status gg_get_values(gg_sim *sim, double *out, int64_t cap);
+gg_status gg_get_iota(gg_sim *sim, int32_t *out, int64_t cap);
+
+/* Replace the whole state (host memory): boxes and liveness for every grain,
+ * values packed grain after grain in id order over the alive grains, and an
+ * optional ID-field in the same order (NULL: all -1).  Boxes must satisfy the
+ * library's box rule: 1 <= ext[a] <= n[a] - 2P or ext[a] == n[a], 0 <= lo < n.
+ * Errors: GG_E_ARG, GG_E_NOMEM, GG_E_HIP. */
+gg_status gg_load_state(gg_sim *sim, const int32_t *lo, const int32_t *ext, const uint8_t *alive,
+                        const double *values, const int32_t *iota);
+
+/* Test hook: when on, each step keeps its predictor output (which = 0) and its
+ * corrector output (which = 1) on the box layout the step started from; read
+ * them with gg_get_intermediate (same packing as gg_get_values, with the boxes
+ * of that layout written to lo/ext/alive/offset when not NULL). */
+gg_status gg_keep_intermediates(gg_sim *sim, int32_t on);
+gg_status gg_get_intermediate(gg_sim *sim, int32_t which, double *out, int64_t cap, int32_t *lo,
+                              int32_t *ext, int32_t *alive, int64_t *offset, int64_t cap_grains);
+
+const char *gg_status_str(gg_status st);
+const char *gg_last_error(const gg_sim *sim);
+void gg_destroy(gg_sim *sim);
+
+/* Library version string. */
+const char *gg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GG_H */

@@ -23,8 +23,9 @@
  *      the ID-field iota_k = that argmax (ties to the lowest id, -1 if none);
  *   3. extinction: grain k dies when no voxel has phi^c_k > 0;
  *   4. box update (sec. 3.1, size-adaptive boxes): new box = bounding box of
- *      {phi^c_k > 0} padded by P = ceil(W) and capped at the grid; phi^c and
- *      iota are carried over through the sampling rule (new cells read -W / -1);
+ *      {phi^c_k > 0} padded by P = ceil(W); a box longer than n - 2P on an axis
+ *      takes the whole periodic axis; phi^c and iota are carried over through
+ *      the sampling rule (new cells read -W / -1);
  *   5. re-initialization (sec. 2.1.6, the fast "taxicab" scheme): reference
  *      values at voxels next to a sign change, theta = phi(x)/(phi(x)-phi(n))
  *      over face neighbours n of opposite sign, ref = min theta (the exact L1
@@ -238,10 +239,13 @@ static int cyclic_cover(const unsigned char *occ, int N, int *start, int *len) {
     return 1;
 }
 
-/* New (lo, ext) along one axis from a covered interval (start, len). */
+/* New (lo, ext) along one axis from a covered interval (start, len): pad by P
+ * on both sides; a box that would come within 2P of the whole axis takes the
+ * whole (periodic) axis instead, so that no stencil of reach <= 2P ever wraps
+ * around a partial box. */
 static void pad_interval(int start, int len, int P, int N, int *lo, int *ext) {
     long e = (long)len + 2L * P;
-    if (e >= N) {
+    if (e > (long)N - 2L * P) {
         *ext = N;
         *lo = 0;
     } else {

@@ -1,0 +1,992 @@
+// Host side of the MI355X level-set grain-growth library: the C ABI declared
+// in include/gg.h, device memory ownership, and the per-step launch sequence
+//   predictor (xy, z) -> corrector (global tiles) -> box plan + item/coverage
+//   bookkeeping -> re-initialization (xy, z) into the new box layout -> volumes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/gg.h"
+#include "gg_kernels.hpp"
+
+namespace {
+
+using gg::Boxes;
+using gg::Items;
+using gg::Totals;
+
+struct HipError {
+    hipError_t err;
+    std::string where;
+};
+
+#define HIPCHECK(x)                                                    \
+    do {                                                               \
+        hipError_t e_ = (x);                                           \
+        if (e_ != hipSuccess) throw HipError{e_, std::string(#x)};     \
+    } while (0)
+
+struct ArgError {
+    std::string msg;
+};
+struct CapError {
+    std::string msg;
+};
+struct MemError {
+    std::string msg;
+};
+
+// A device buffer with a capacity in bytes.
+struct DBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    void ensure(size_t bytes) {
+        if (bytes <= cap && p) return;
+        if (p) (void)hipDeviceSynchronize();  // no pending work may still use the old buffer
+        release();
+        size_t b = std::max<size_t>(bytes, 256);
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            p = nullptr;
+            cap = 0;
+            (void)hipGetLastError();
+            throw MemError{"device allocation of " + std::to_string(b) + " bytes failed"};
+        }
+        cap = b;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    template <typename U> U *as() const { return reinterpret_cast<U *>(p); }
+};
+
+int pow2_divisor(int N, int target) {
+    int t = target;
+    while (t > 1 && N % t) t >>= 1;
+    return t;
+}
+
+struct SimBase {
+    virtual ~SimBase() = default;
+    virtual void step(double dt, int n) = 0;
+    virtual void volumes(double *out) = 0;
+    virtual void labels(int32_t *out, bool device) = 0;
+    virtual void boxes(int32_t *lo, int32_t *ext, int32_t *alive, int64_t *off, bool prev) = 0;
+    virtual long long values(double *out, long long cap, int which) = 0;
+    virtual long long iota(int32_t *out, long long cap) = 0;
+    virtual void load_state(const int32_t *lo, const int32_t *ext, const uint8_t *alive, const double *vals,
+                            const int32_t *iota) = 0;
+    virtual void sync() = 0;
+    virtual int alive_count() const = 0;
+    virtual gg_step_stats stats() const = 0;
+    virtual long long arena_total(bool prev) const = 0;
+    bool keep = false;
+};
+
+template <typename T> struct Sim final : SimBase {
+    // configuration
+    int dim, G, n[3], P, K;
+    T W;
+    int physics;
+    double theta_c, voxel_m, gamma_max, headroom;
+    int tdim[3], nt[3], ntiles, occ_words;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+
+    // layouts 0/1: box tables and work items
+    DBuf lo[2], ext[2], alive[2], off[2];
+    DBuf ipref[2][gg::kKinds], iowner[2][gg::kKinds];
+    int items_R[2] = {-1, -1};
+    Totals tot[2];
+    int cur = 0;
+
+    // per step accumulators and scratch
+    DBuf bmin, bmax, occ, sizes, cnt[gg::kKinds], ldsmax, vol, vol_part;
+    DBuf cov_cnt, cov_off, cov_cur, cov_list;
+    DBuf taps_d, quat_d, energy_d, totals_d;
+    Totals *totals_h = nullptr;
+    // value arenas (3) and ID-fields (old layout, current layout)
+    DBuf arena[3], iota_a[2];
+    int is = 0;       // arena holding the state
+    int iota_cur = 0; // ID-field of the current layout
+    // kept intermediates (test hook)
+    DBuf keep_psi, keep_phic, keep_lo, keep_ext, keep_alive, keep_off;
+    Totals keep_tot{};
+    bool have_keep = false;
+
+    // current Gaussian
+    double sigma = -1.0;
+    int R = 0;
+    std::vector<T> taps_h;
+
+    long long steps_done = 0;
+    double last_ms = 0.0;
+    long long last_gv = 0;
+
+    Boxes boxes_of(int l) {
+        return Boxes{lo[l].as<int>(), ext[l].as<int>(), alive[l].as<int>(), off[l].as<long long>()};
+    }
+    gg::TileArgs tile_args() const {
+        gg::TileArgs t;
+        for (int a = 0; a < 3; ++a) {
+            t.n[a] = n[a];
+            t.t[a] = tdim[a];
+            t.nt[a] = nt[a];
+        }
+        t.occ_words = occ_words;
+        return t;
+    }
+    gg::GridArgs grid_args() const {
+        gg::GridArgs g;
+        for (int a = 0; a < 3; ++a) g.n[a] = n[a];
+        g.dim = dim;
+        return g;
+    }
+
+    Sim(const gg_config &c, int G_, hipStream_t s) {
+        dim = c.dim;
+        G = G_;
+        for (int a = 0; a < 3; ++a) n[a] = c.n[a];
+        W = (T)c.band;
+        P = (int)std::ceil(c.band);
+        K = P;
+        physics = c.physics;
+        theta_c = c.theta_c_deg;
+        voxel_m = c.voxel_m;
+        gamma_max = c.gamma_max;
+        headroom = c.capacity_headroom > 1.0 ? c.capacity_headroom : 1.25;
+        if (dim == 3) {
+            tdim[0] = pow2_divisor(n[0], 16);
+            tdim[1] = pow2_divisor(n[1], 8);
+            tdim[2] = pow2_divisor(n[2], 4);
+        } else {
+            tdim[0] = pow2_divisor(n[0], 32);
+            tdim[1] = pow2_divisor(n[1], 16);
+            tdim[2] = 1;
+        }
+        ntiles = 1;
+        for (int a = 0; a < 3; ++a) {
+            nt[a] = n[a] / tdim[a];
+            ntiles *= nt[a];
+        }
+        occ_words = (std::max(n[0], std::max(n[1], n[2])) + 31) / 32;
+        if (s) {
+            stream = s;
+        } else {
+            HIPCHECK(hipStreamCreate(&stream));
+            own_stream = true;
+        }
+        HIPCHECK(hipHostMalloc((void **)&totals_h, sizeof(Totals), hipHostMallocDefault));
+        std::memset(totals_h, 0, sizeof(Totals));
+        for (int l = 0; l < 2; ++l) {
+            lo[l].ensure(sizeof(int) * 3 * G);
+            ext[l].ensure(sizeof(int) * 3 * G);
+            alive[l].ensure(sizeof(int) * G);
+            off[l].ensure(sizeof(long long) * (G + 1));
+            for (int q = 0; q < gg::kKinds; ++q) ipref[l][q].ensure(sizeof(long long) * (G + 1));
+        }
+        bmin.ensure(sizeof(int) * 3 * G);
+        bmax.ensure(sizeof(int) * 3 * G);
+        occ.ensure(sizeof(unsigned) * 3 * (size_t)G * occ_words);
+        HIPCHECK(hipMemsetAsync(occ.p, 0, occ.cap, stream));
+        std::vector<int> init_min(3 * G, 0x7fffffff), init_max(3 * G, -1);
+        HIPCHECK(hipMemcpyAsync(bmin.p, init_min.data(), sizeof(int) * 3 * G, hipMemcpyHostToDevice, stream));
+        HIPCHECK(hipMemcpyAsync(bmax.p, init_max.data(), sizeof(int) * 3 * G, hipMemcpyHostToDevice, stream));
+        sizes.ensure(sizeof(long long) * G);
+        for (int q = 0; q < gg::kKinds; ++q) cnt[q].ensure(sizeof(long long) * G);
+        ldsmax.ensure(sizeof(unsigned long long) * gg::kKinds);
+        vol.ensure(sizeof(double) * G);
+        cov_cnt.ensure(sizeof(int) * ntiles);
+        cov_off.ensure(sizeof(int) * (ntiles + 1));
+        cov_cur.ensure(sizeof(int) * (ntiles + 1));
+        taps_d.ensure(sizeof(T) * (2 * gg::kMaxRadius + 1));
+        totals_d.ensure(sizeof(Totals));
+        HIPCHECK(hipStreamSynchronize(stream));
+    }
+
+    ~Sim() override {
+        if (stream) (void)hipStreamSynchronize(stream);
+        DBuf *all[] = {&bmin, &bmax, &occ, &sizes, &ldsmax, &vol, &vol_part, &cov_cnt, &cov_off, &cov_cur,
+                       &cov_list, &taps_d, &quat_d, &energy_d, &totals_d, &keep_psi, &keep_phic, &keep_lo,
+                       &keep_ext, &keep_alive, &keep_off};
+        for (DBuf *b : all) b->release();
+        for (int q = 0; q < gg::kKinds; ++q) cnt[q].release();
+        for (int l = 0; l < 2; ++l) {
+            lo[l].release();
+            ext[l].release();
+            alive[l].release();
+            off[l].release();
+            iota_a[l].release();
+            for (int q = 0; q < gg::kKinds; ++q) {
+                ipref[l][q].release();
+                iowner[l][q].release();
+            }
+        }
+        for (int a = 0; a < 3; ++a) arena[a].release();
+        if (totals_h) (void)hipHostFree(totals_h);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+
+    void sync() override { HIPCHECK(hipStreamSynchronize(stream)); }
+
+    // Arena capacity for a layout of `need` values (with headroom).
+    size_t grow_to(long long need) const { return (size_t)((double)need * headroom) + 1024; }
+
+    void ensure_arena(int a, long long need) {
+        if ((size_t)need * sizeof(T) <= arena[a].cap && arena[a].p) return;
+        arena[a].ensure(grow_to(need) * sizeof(T));
+    }
+    void ensure_iota(int a, long long need) {
+        if ((size_t)need * sizeof(int) <= iota_a[a].cap && iota_a[a].p) return;
+        iota_a[a].ensure(grow_to(need) * sizeof(int));
+    }
+
+    // Offsets, work items and coverage counts of layout l; fills tot[l] (syncs).
+    // Then the item maps and the coverage lists.
+    void layout_meta_count(int l, bool coverage) {
+        Boxes L = boxes_of(l);
+        HIPCHECK(hipMemsetAsync(ldsmax.p, 0, sizeof(unsigned long long) * gg::kKinds, stream));
+        const int tb = 256, gb = (G + tb - 1) / tb;
+        hipLaunchKernelGGL(gg::k_item_counts, dim3(gb), dim3(tb), 0, stream, L, cnt[0].as<long long>(),
+                           cnt[1].as<long long>(), cnt[2].as<long long>(), cnt[3].as<long long>(),
+                           ldsmax.as<unsigned long long>(), R, K, G, gg::lds_budget<T>());
+        for (int q = 0; q < gg::kKinds; ++q)
+            hipLaunchKernelGGL(gg::k_scan, dim3(1), dim3(1024), 0, stream, cnt[q].as<long long>(),
+                               ipref[l][q].as<long long>(), G);
+        if (coverage) {
+            HIPCHECK(hipMemsetAsync(cov_cnt.p, 0, sizeof(int) * ntiles, stream));
+            hipLaunchKernelGGL(gg::k_coverage, dim3(G), dim3(64), 0, stream, L, cov_cnt.as<int>(), (int *)nullptr,
+                               tile_args(), G, 0);
+            hipLaunchKernelGGL(gg::k_scan_int, dim3(1), dim3(1024), 0, stream, cov_cnt.as<int>(), cov_off.as<int>(),
+                               ntiles);
+        }
+        hipLaunchKernelGGL(gg::k_totals, dim3(1), dim3(256), 0, stream, L.off, ipref[l][0].as<long long>(),
+                           ipref[l][1].as<long long>(), ipref[l][2].as<long long>(), ipref[l][3].as<long long>(),
+                           coverage ? cov_off.as<int>() : (const int *)nullptr, ntiles, L.alive, G,
+                           ldsmax.as<unsigned long long>(), totals_d.as<Totals>());
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipMemcpyAsync(totals_h, totals_d.p, sizeof(Totals), hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+        tot[l] = *totals_h;
+        for (int q = 0; q < gg::kKinds; ++q)
+            if (tot[l].lds[q] < 0 || tot[l].lds[q] > gg::lds_budget<T>())
+                throw CapError{"a box is too large for the stencil tiling"};
+        items_R[l] = R;
+    }
+
+    void layout_meta_fill(int l, bool coverage) {
+        for (int q = 0; q < gg::kKinds; ++q) {
+            iowner[l][q].ensure(sizeof(int) * (size_t)std::max<long long>(tot[l].items[q], 1) * 5 / 4);
+            hipLaunchKernelGGL(gg::k_fill_owner, dim3(G), dim3(64), 0, stream, ipref[l][q].as<long long>(),
+                               iowner[l][q].as<int>(), G);
+        }
+        if (coverage) {
+            if (tot[l].cov > 0x7fffffffLL) throw CapError{"coverage list exceeds 2^31 entries"};
+            cov_list.ensure(sizeof(int) * (size_t)std::max<long long>(tot[l].cov, 1) * 5 / 4);
+            HIPCHECK(hipMemcpyAsync(cov_cur.p, cov_off.p, sizeof(int) * (ntiles + 1), hipMemcpyDeviceToDevice,
+                                    stream));
+            hipLaunchKernelGGL(gg::k_coverage, dim3(G), dim3(64), 0, stream, boxes_of(l), cov_cur.as<int>(),
+                               cov_list.as<int>(), tile_args(), G, 1);
+        }
+        HIPCHECK(hipGetLastError());
+    }
+
+    void set_gaussian(double dt) {
+        double s = std::sqrt(2.0 * dt) * (double)n[0];
+        if (s == sigma) return;
+        int r = (int)std::ceil(4.0 * s - 1e-9);
+        if (r < 1) r = 1;
+        if (r > gg::kMaxRadius || r > 2 * P) throw ArgError{"kernel radius R = ceil(4 sigma) exceeds min(24, 2P)"};
+        std::vector<double> t(2 * r + 1);
+        double s2 = 2.0 * s * s, sum = 0.0;
+        for (int i = -r; i <= r; ++i) {
+            t[i + r] = std::exp(-(double)(i * i) / s2);
+            sum = sum + t[i + r];
+        }
+        taps_h.assign(2 * r + 1, T(0));
+        for (int i = 0; i < 2 * r + 1; ++i) taps_h[i] = (T)(t[i] / sum);
+        HIPCHECK(hipMemcpyAsync(taps_d.p, taps_h.data(), sizeof(T) * taps_h.size(), hipMemcpyHostToDevice, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+        sigma = s;
+        R = r;
+    }
+
+    gg::Physics<T> physics_args(const T *phi, const int *iota_p) const {
+        gg::Physics<T> ph;
+        ph.mode = physics;
+        ph.quat = quat_d.as<T>();
+        ph.energy = energy_d.as<T>();
+        ph.theta_c_deg = (T)theta_c;
+        ph.bulk_scale = (physics & 2) ? (T)(sigma * sigma * voxel_m / (2.0 * gamma_max)) : T(0);
+        ph.phi = phi;
+        ph.iota = iota_p;
+        return ph;
+    }
+
+    static unsigned grid_of(long long items) { return (unsigned)items; }
+
+    // Re-initialization from `src` (layout lo_l) into layout ln_l, written to arena `dst_a`
+    // (3D: through the partial-distance arena `tmp_a`).
+    void reinit(int lo_l, int ln_l, const T *src, int tmp_a, int dst_a, const int *iota_old, int *iota_new) {
+        const Totals &t = tot[ln_l];
+        gg::GridArgs g = grid_args();
+        vol_part.ensure(sizeof(double) * (size_t)std::max<long long>(t.items[dim == 3 ? 3 : 2], 1) * 5 / 4);
+        if (t.items[2] > 0) {
+            T *out = dim == 3 ? arena[tmp_a].as<T>() : arena[dst_a].as<T>();
+            hipLaunchKernelGGL(gg::k_reinit_xy<T>, dim3(grid_of(t.items[2])), dim3(gg::kBlock),
+                               sizeof(T) * t.lds[2], stream, boxes_of(lo_l), boxes_of(ln_l),
+                               iowner[ln_l][2].as<int>(), ipref[ln_l][2].as<long long>(), src, out, iota_old,
+                               iota_new, vol_part.as<double>(), K, W, g);
+        }
+        if (dim == 3 && t.items[3] > 0)
+            hipLaunchKernelGGL(gg::k_reinit_z<T>, dim3(grid_of(t.items[3])), dim3(gg::kBlock),
+                               sizeof(T) * t.lds[3], stream, boxes_of(ln_l), iowner[ln_l][3].as<int>(),
+                               ipref[ln_l][3].as<long long>(), arena[tmp_a].as<T>(), arena[dst_a].as<T>(),
+                               vol_part.as<double>(), K, W, g);
+        const int tb = 256, gb = (G + tb - 1) / tb;
+        hipLaunchKernelGGL(gg::k_volumes, dim3(gb), dim3(tb), 0, stream, boxes_of(ln_l),
+                           ipref[ln_l][dim == 3 ? 3 : 2].as<long long>(), vol_part.as<double>(), vol.as<double>(),
+                           G);
+        HIPCHECK(hipGetLastError());
+    }
+
+    // ---------------------------------------------------------------- create
+    void create(const int32_t *labels, const double *quat, const double *energy) {
+        // initial boxes on the host: per axis the covered cyclic interval of the
+        // grain's projection, padded by P (a box within 2P of the axis takes it all)
+        const long long nt3 = (long long)n[0] * n[1] * n[2];
+        const int nsum = n[0] + n[1] + n[2];
+        std::vector<unsigned char> occh((size_t)G * nsum, 0);
+        for (long long i = 0; i < nt3; ++i) {
+            const int x = (int)(i % n[0]), y = (int)((i / n[0]) % n[1]), z = (int)(i / ((long long)n[0] * n[1]));
+            unsigned char *o = &occh[(size_t)labels[i] * nsum];
+            o[x] = 1;
+            o[n[0] + y] = 1;
+            o[n[0] + n[1] + z] = 1;
+        }
+        std::vector<int> hlo(3 * G, 0), hext(3 * G, 0), hal(G, 0);
+        std::vector<long long> hoff(G + 1, 0);
+        for (int k = 0; k < G; ++k) {
+            const unsigned char *o = &occh[(size_t)k * nsum];
+            bool ok = true;
+            int base = 0;
+            for (int a = 0; a < 3 && ok; ++a) {
+                const int N = n[a];
+                int first = -1, ones = 0;
+                for (int i = 0; i < N; ++i)
+                    if (o[base + i]) {
+                        if (first < 0) first = i;
+                        ++ones;
+                    }
+                if (first < 0) {
+                    ok = false;
+                    break;
+                }
+                int st = 0, ln = N;
+                if (ones < N) {
+                    int best_s = -1, best_l = -1, run_s = -1, run_l = 0;
+                    for (int t = 1; t <= N; ++t) {
+                        const int i = (first + t) % N;
+                        if (!o[base + i]) {
+                            if (run_l == 0) run_s = i;
+                            ++run_l;
+                        } else if (run_l > 0) {
+                            if (run_l > best_l || (run_l == best_l && run_s < best_s)) {
+                                best_l = run_l;
+                                best_s = run_s;
+                            }
+                            run_l = 0;
+                        }
+                    }
+                    st = (best_s + best_l) % N;
+                    ln = N - best_l;
+                }
+                const long long e = (long long)ln + 2LL * P;
+                if (e > (long long)N - 2LL * P) {
+                    hlo[3 * k + a] = 0;
+                    hext[3 * k + a] = N;
+                } else {
+                    hlo[3 * k + a] = gg::imod((long long)st - P, N);
+                    hext[3 * k + a] = (int)e;
+                }
+                base += N;
+            }
+            hal[k] = ok ? 1 : 0;
+            if (!ok)
+                for (int a = 0; a < 3; ++a) hlo[3 * k + a] = hext[3 * k + a] = 0;
+        }
+        for (int k = 0; k < G; ++k)
+            hoff[k + 1] = hoff[k] + (hal[k] ? (long long)hext[3 * k] * hext[3 * k + 1] * hext[3 * k + 2] : 0);
+        upload_table(0, hlo.data(), hext.data(), hal.data(), hoff.data());
+        cur = 0;
+        if (physics & 1) {
+            std::vector<T> q(4 * (size_t)G);
+            for (size_t i = 0; i < q.size(); ++i) q[i] = (T)quat[i];
+            quat_d.ensure(sizeof(T) * q.size());
+            HIPCHECK(hipMemcpyAsync(quat_d.p, q.data(), sizeof(T) * q.size(), hipMemcpyHostToDevice, stream));
+            HIPCHECK(hipStreamSynchronize(stream));
+        }
+        if (physics & 2) {
+            std::vector<T> e(G);
+            for (int k = 0; k < G; ++k) e[k] = (T)energy[k];
+            energy_d.ensure(sizeof(T) * G);
+            HIPCHECK(hipMemcpyAsync(energy_d.p, e.data(), sizeof(T) * G, hipMemcpyHostToDevice, stream));
+            HIPCHECK(hipStreamSynchronize(stream));
+        }
+        // initial function: re-initialised +-1/2 indicator, on the same boxes
+        R = 1;  // any valid radius for the item bookkeeping; set per step
+        layout_meta_count(0, true);
+        layout_meta_fill(0, true);
+        const long long need = tot[0].arena;
+        for (int a = 0; a < 3; ++a) ensure_arena(a, need);
+        DBuf lab;
+        lab.ensure(sizeof(int32_t) * nt3);
+        HIPCHECK(hipMemcpyAsync(lab.p, labels, sizeof(int32_t) * nt3, hipMemcpyHostToDevice, stream));
+        hipLaunchKernelGGL(gg::k_init_indicator<T>, dim3(G), dim3(gg::kBlock), 0, stream, boxes_of(0),
+                           lab.as<int>(), arena[1].as<T>(), grid_args());
+        HIPCHECK(hipGetLastError());
+        reinit(0, 0, arena[1].as<T>(), 2, 0, nullptr, nullptr);
+        is = 0;
+        HIPCHECK(hipStreamSynchronize(stream));
+        lab.release();
+        if (physics) {
+            ensure_iota(0, need);
+            ensure_iota(1, need);
+            iota_cur = 0;
+            hipLaunchKernelGGL(gg::k_compare<T>, dim3(ntiles), dim3(gg::kBlock), 0, stream, boxes_of(0),
+                               cov_off.as<int>(), cov_list.as<int>(), arena[is].as<T>(), (T *)nullptr,
+                               iota_a[0].as<int>(), bmin.as<int>(), bmax.as<int>(), occ.as<unsigned>(),
+                               tile_args(), W, 1);
+            HIPCHECK(hipGetLastError());
+            HIPCHECK(hipStreamSynchronize(stream));
+        }
+    }
+
+    void upload_table(int l, const int *hlo, const int *hext, const int *hal, const long long *hoff) {
+        HIPCHECK(hipMemcpyAsync(lo[l].p, hlo, sizeof(int) * 3 * G, hipMemcpyHostToDevice, stream));
+        HIPCHECK(hipMemcpyAsync(ext[l].p, hext, sizeof(int) * 3 * G, hipMemcpyHostToDevice, stream));
+        HIPCHECK(hipMemcpyAsync(alive[l].p, hal, sizeof(int) * G, hipMemcpyHostToDevice, stream));
+        HIPCHECK(hipMemcpyAsync(off[l].p, hoff, sizeof(long long) * (G + 1), hipMemcpyHostToDevice, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+    }
+
+    // ------------------------------------------------------------------ step
+    void step(double dt, int nsteps) override {
+        set_gaussian(dt);
+        hipEvent_t e0, e1;
+        HIPCHECK(hipEventCreate(&e0));
+        HIPCHECK(hipEventCreate(&e1));
+        HIPCHECK(hipEventRecord(e0, stream));
+        for (int s = 0; s < nsteps; ++s) step_once();
+        HIPCHECK(hipEventRecord(e1, stream));
+        HIPCHECK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (nsteps > 0) last_ms = ms / nsteps;
+    }
+
+    void step_once() {
+        const int L = cur, Ln = 1 - cur;
+        if (items_R[L] != R) {
+            layout_meta_count(L, false);
+            layout_meta_fill(L, false);
+        }
+        const Totals &t = tot[L];
+        last_gv = t.arena;
+        const int a_s = is, a_t1 = (is + 1) % 3, a_psi = (is + 2) % 3;
+        gg::GridArgs g = grid_args();
+        const int *iota_in = physics ? iota_a[iota_cur].as<int>() : nullptr;
+        gg::Physics<T> ph = physics_args(arena[a_s].as<T>(), iota_in);
+        gg::Physics<T> noph = ph;
+        noph.mode = 0;
+        // 1. predictor
+        T *psi = arena[a_psi].as<T>();
+        if (dim == 3) {
+            if (t.items[0] > 0)
+                hipLaunchKernelGGL(gg::k_conv_xy<T>, dim3(grid_of(t.items[0])), dim3(gg::kBlock), sizeof(T) * t.lds[0],
+                                   stream, boxes_of(L), iowner[L][0].as<int>(), ipref[L][0].as<long long>(),
+                                   arena[a_s].as<T>(), arena[a_t1].as<T>(), taps_d.as<T>(), R, W, g, noph);
+            if (t.items[1] > 0)
+                hipLaunchKernelGGL(gg::k_conv_z<T>, dim3(grid_of(t.items[1])), dim3(gg::kBlock), sizeof(T) * t.lds[1],
+                                   stream, boxes_of(L), iowner[L][1].as<int>(), ipref[L][1].as<long long>(),
+                                   arena[a_t1].as<T>(), psi, taps_d.as<T>(), R, W, g, ph);
+        } else if (t.items[0] > 0) {
+            hipLaunchKernelGGL(gg::k_conv_xy<T>, dim3(grid_of(t.items[0])), dim3(gg::kBlock), sizeof(T) * t.lds[0],
+                               stream, boxes_of(L), iowner[L][0].as<int>(), ipref[L][0].as<long long>(),
+                               arena[a_s].as<T>(), psi, taps_d.as<T>(), R, W, g, ph);
+        }
+        // 2. corrector into the t1 arena (dead after the predictor)
+        T *phic = arena[a_t1].as<T>();
+        const int iota_old = 1 - iota_cur;
+        if (physics) ensure_iota(iota_old, t.arena);
+        hipLaunchKernelGGL(gg::k_compare<T>, dim3(ntiles), dim3(gg::kBlock), 0, stream, boxes_of(L), cov_off.as<int>(),
+                           cov_list.as<int>(), psi, phic, physics ? iota_a[iota_old].as<int>() : (int *)nullptr,
+                           bmin.as<int>(), bmax.as<int>(), occ.as<unsigned>(), tile_args(), W, 0);
+        HIPCHECK(hipGetLastError());
+        if (keep) keep_copy(L, psi, phic);
+        // 3. new boxes, offsets, items and coverage of the new layout
+        gg::PlanArgs pa;
+        for (int a = 0; a < 3; ++a) pa.n[a] = n[a];
+        pa.P = P;
+        pa.occ_words = occ_words;
+        pa.G = G;
+        const int tb = 256, gb = (G + tb - 1) / tb;
+        hipLaunchKernelGGL(gg::k_plan, dim3(gb), dim3(tb), 0, stream, boxes_of(L), boxes_of(Ln), bmin.as<int>(),
+                           bmax.as<int>(), occ.as<unsigned>(), sizes.as<long long>(), pa);
+        hipLaunchKernelGGL(gg::k_scan, dim3(1), dim3(1024), 0, stream, sizes.as<long long>(), off[Ln].as<long long>(), G);
+        HIPCHECK(hipGetLastError());
+        layout_meta_count(Ln, true);
+        const long long need = tot[Ln].arena;
+        // the destinations of the re-initialization are dead now: grow them if needed
+        ensure_arena(a_s, need);
+        ensure_arena(a_psi, need);
+        if (physics) ensure_iota(iota_cur, need);
+        layout_meta_fill(Ln, true);
+        // 4. re-initialization into the new layout: 3D partial distances in the
+        // state arena (dead), final function in the psi arena (dead)
+        const int dst = dim == 3 ? a_psi : a_s;
+        reinit(L, Ln, phic, a_s, dst, physics ? iota_a[iota_old].as<int>() : nullptr,
+               physics ? iota_a[iota_cur].as<int>() : nullptr);
+        is = dst;
+        cur = Ln;
+        ++steps_done;
+        // arenas left below the new layout's size are grown while dead
+        for (int a = 0; a < 3; ++a)
+            if (a != is) ensure_arena(a, need);
+    }
+
+    void keep_copy(int L, const T *psi, const T *phic) {
+        const long long m = tot[L].arena;
+        keep_psi.ensure(sizeof(T) * std::max<long long>(m, 1));
+        keep_phic.ensure(sizeof(T) * std::max<long long>(m, 1));
+        keep_lo.ensure(sizeof(int) * 3 * G);
+        keep_ext.ensure(sizeof(int) * 3 * G);
+        keep_alive.ensure(sizeof(int) * G);
+        keep_off.ensure(sizeof(long long) * (G + 1));
+        HIPCHECK(hipMemcpyAsync(keep_psi.p, psi, sizeof(T) * m, hipMemcpyDeviceToDevice, stream));
+        HIPCHECK(hipMemcpyAsync(keep_phic.p, phic, sizeof(T) * m, hipMemcpyDeviceToDevice, stream));
+        HIPCHECK(hipMemcpyAsync(keep_lo.p, lo[L].p, sizeof(int) * 3 * G, hipMemcpyDeviceToDevice, stream));
+        HIPCHECK(hipMemcpyAsync(keep_ext.p, ext[L].p, sizeof(int) * 3 * G, hipMemcpyDeviceToDevice, stream));
+        HIPCHECK(hipMemcpyAsync(keep_alive.p, alive[L].p, sizeof(int) * G, hipMemcpyDeviceToDevice, stream));
+        HIPCHECK(hipMemcpyAsync(keep_off.p, off[L].p, sizeof(long long) * (G + 1), hipMemcpyDeviceToDevice, stream));
+        keep_tot = tot[L];
+        have_keep = true;
+    }
+
+    // ---------------------------------------------------------------- queries
+    void volumes(double *out) override {
+        HIPCHECK(hipMemcpyAsync(out, vol.p, sizeof(double) * G, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+    }
+
+    void labels(int32_t *out, bool device) override {
+        const long long nt3 = (long long)n[0] * n[1] * n[2];
+        DBuf tmp;
+        int32_t *dst = out;
+        if (!device) {
+            tmp.ensure(sizeof(int32_t) * nt3);
+            dst = tmp.as<int32_t>();
+        }
+        hipLaunchKernelGGL(gg::k_labels<T>, dim3(ntiles), dim3(gg::kBlock), 0, stream, boxes_of(cur), cov_off.as<int>(),
+                           cov_list.as<int>(), arena[is].as<T>(), dst, tile_args());
+        HIPCHECK(hipGetLastError());
+        if (!device) {
+            HIPCHECK(hipMemcpyAsync(out, dst, sizeof(int32_t) * nt3, hipMemcpyDeviceToHost, stream));
+            HIPCHECK(hipStreamSynchronize(stream));
+        }
+    }
+
+    void boxes(int32_t *hlo, int32_t *hext, int32_t *hal, int64_t *hoff, bool prev) override {
+        std::vector<int> a(G);
+        std::vector<long long> o(G + 1);
+        const void *plo = prev ? keep_lo.p : lo[cur].p, *pext = prev ? keep_ext.p : ext[cur].p;
+        const void *pal = prev ? keep_alive.p : alive[cur].p, *poff = prev ? keep_off.p : off[cur].p;
+        if (hlo) HIPCHECK(hipMemcpyAsync(hlo, plo, sizeof(int) * 3 * G, hipMemcpyDeviceToHost, stream));
+        if (hext) HIPCHECK(hipMemcpyAsync(hext, pext, sizeof(int) * 3 * G, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipMemcpyAsync(a.data(), pal, sizeof(int) * G, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipMemcpyAsync(o.data(), poff, sizeof(long long) * (G + 1), hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+        for (int k = 0; k < G; ++k) {
+            if (hal) hal[k] = a[k];
+            if (hoff) hoff[k] = a[k] ? o[k] : -1;
+        }
+    }
+
+    long long arena_total(bool prev) const override { return prev ? keep_tot.arena : tot[cur].arena; }
+
+    long long values(double *out, long long cap, int which) override {
+        const T *src;
+        long long m;
+        if (which < 0) {
+            src = arena[is].as<T>();
+            m = tot[cur].arena;
+        } else {
+            if (!have_keep) throw ArgError{"no intermediates kept"};
+            src = which == 0 ? keep_psi.as<T>() : keep_phic.as<T>();
+            m = keep_tot.arena;
+        }
+        if (cap < m) return -m;
+        DBuf tmp;
+        tmp.ensure(sizeof(double) * std::max<long long>(m, 1));
+        if (m > 0) {
+            hipLaunchKernelGGL((gg::k_convert<T, double>), dim3(1024), dim3(256), 0, stream, src, tmp.as<double>(), m);
+            HIPCHECK(hipGetLastError());
+            HIPCHECK(hipMemcpyAsync(out, tmp.p, sizeof(double) * m, hipMemcpyDeviceToHost, stream));
+        }
+        HIPCHECK(hipStreamSynchronize(stream));
+        return m;
+    }
+
+    long long iota(int32_t *out, long long cap) override {
+        const long long m = tot[cur].arena;
+        if (cap < m) return -m;
+        if (!physics) {
+            for (long long i = 0; i < m; ++i) out[i] = -1;
+            return m;
+        }
+        HIPCHECK(hipMemcpyAsync(out, iota_a[iota_cur].p, sizeof(int) * m, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+        return m;
+    }
+
+    void load_state(const int32_t *hlo, const int32_t *hext, const uint8_t *hal, const double *vals,
+                    const int32_t *hiota) override {
+        std::vector<int> l(3 * G), e(3 * G), a(G);
+        std::vector<long long> o(G + 1, 0);
+        std::vector<double> vh(G, 0.0);
+        for (int k = 0; k < G; ++k) {
+            a[k] = hal[k] ? 1 : 0;
+            for (int q = 0; q < 3; ++q) {
+                l[3 * k + q] = a[k] ? hlo[3 * k + q] : 0;
+                e[3 * k + q] = a[k] ? hext[3 * k + q] : 0;
+            }
+            if (a[k])
+                for (int q = 0; q < 3; ++q) {
+                    const int N = n[q], ex = e[3 * k + q];
+                    if (l[3 * k + q] < 0 || l[3 * k + q] >= N || ex < 1 || ex > N ||
+                        (ex != N && ex > N - 2 * P))
+                        throw ArgError{"box of grain " + std::to_string(k) + " violates the box rule"};
+                }
+            o[k + 1] = o[k] + (a[k] ? (long long)e[3 * k] * e[3 * k + 1] * e[3 * k + 2] : 0);
+        }
+        const long long m = o[G];
+        for (long long i = 0; i < m; ++i)
+            if (!std::isfinite(vals[i])) throw ArgError{"non-finite value in the state"};
+        for (int k = 0; k < G; ++k)
+            if (a[k]) {
+                double s = 0.0;
+                for (long long i = o[k]; i < o[k + 1]; ++i) {
+                    double c = vals[i] + 0.5;
+                    c = c < 0.0 ? 0.0 : (c > 1.0 ? 1.0 : c);
+                    s += c;
+                }
+                vh[k] = s;
+            }
+        HIPCHECK(hipStreamSynchronize(stream));
+        cur = 0;
+        upload_table(0, l.data(), e.data(), a.data(), o.data());
+        for (int q = 0; q < 3; ++q) ensure_arena(q, m);
+        std::vector<T> tv(std::max<long long>(m, 1));
+        for (long long i = 0; i < m; ++i) tv[i] = (T)vals[i];
+        is = 0;
+        HIPCHECK(hipMemcpyAsync(arena[0].p, tv.data(), sizeof(T) * m, hipMemcpyHostToDevice, stream));
+        HIPCHECK(hipMemcpyAsync(vol.p, vh.data(), sizeof(double) * G, hipMemcpyHostToDevice, stream));
+        if (physics) {
+            ensure_iota(0, m);
+            ensure_iota(1, m);
+            iota_cur = 0;
+            std::vector<int> io(std::max<long long>(m, 1), -1);
+            if (hiota)
+                for (long long i = 0; i < m; ++i) io[i] = hiota[i];
+            HIPCHECK(hipMemcpyAsync(iota_a[0].p, io.data(), sizeof(int) * m, hipMemcpyHostToDevice, stream));
+        }
+        HIPCHECK(hipStreamSynchronize(stream));
+        items_R[0] = items_R[1] = -1;
+        const int keepR = R;
+        R = R > 0 ? R : 1;
+        layout_meta_count(0, true);
+        layout_meta_fill(0, true);
+        R = keepR;
+        if (R <= 0) items_R[0] = -1;
+        HIPCHECK(hipStreamSynchronize(stream));
+    }
+
+    int alive_count() const override { return (int)tot[cur].alive; }
+
+    gg_step_stats stats() const override {
+        gg_step_stats s;
+        s.steps = steps_done;
+        s.alive = (int)tot[cur].alive;
+        s.kernel_radius = R;
+        s.grain_voxels = last_gv;
+        s.capacity = (int64_t)(arena[is].cap / sizeof(T));
+        s.superposition = (double)last_gv / ((double)n[0] * n[1] * n[2]);
+        s.last_step_ms = last_ms;
+        return s;
+    }
+};
+
+}  // namespace
+
+struct gg_sim {
+    std::unique_ptr<SimBase> impl;
+    std::string err;
+    bool poisoned = false;
+    int G = 0;
+    int n[3] = {0, 0, 0};
+    int device = 0;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+gg_status fail(gg_sim *s, gg_status st, const std::string &msg) {
+    if (s) {
+        s->err = msg;
+        if (st == GG_E_HIP) s->poisoned = true;
+    } else {
+        g_create_error = msg;
+    }
+    return st;
+}
+
+template <typename F> gg_status guarded(gg_sim *s, F &&f) {
+    if (!s) return GG_E_ARG;
+    if (s->poisoned) return fail(s, GG_E_POISONED, "simulation poisoned by an earlier HIP error: " + s->err);
+    try {
+        HIPCHECK(hipSetDevice(s->device));
+        return f();
+    } catch (const ArgError &e) {
+        return fail(s, GG_E_ARG, e.msg);
+    } catch (const CapError &e) {
+        return fail(s, GG_E_CAPACITY, e.msg);
+    } catch (const MemError &e) {
+        return fail(s, GG_E_NOMEM, e.msg);
+    } catch (const HipError &e) {
+        return fail(s, GG_E_HIP, std::string(hipGetErrorString(e.err)) + " in " + e.where);
+    } catch (const std::bad_alloc &) {
+        return fail(s, GG_E_NOMEM, "host allocation failed");
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gg_version(void) { return "gg-mi355x 0.1 (gfx950)"; }
+
+const char *gg_status_str(gg_status st) {
+    switch (st) {
+    case GG_OK: return "ok";
+    case GG_E_ARG: return "invalid argument";
+    case GG_E_NOMEM: return "out of memory";
+    case GG_E_HIP: return "HIP runtime error";
+    case GG_E_CAPACITY: return "capacity exceeded";
+    case GG_E_SMALLBUF: return "output buffer too small";
+    case GG_E_NUMERIC: return "non-finite value";
+    case GG_E_POISONED: return "simulation poisoned";
+    case GG_E_UNSUPPORTED: return "unsupported";
+    case GG_E_NODEVICE: return "no usable device";
+    }
+    return "unknown status";
+}
+
+const char *gg_last_error(const gg_sim *sim) { return sim ? sim->err.c_str() : g_create_error.c_str(); }
+
+gg_status gg_create(const gg_config *cfg, const int32_t *labels, int32_t n_grains, const double *quat,
+                    const double *energy_density, void *hip_stream, gg_sim **out) {
+    g_create_error.clear();
+    if (!out) return fail(nullptr, GG_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!cfg || !labels) return fail(nullptr, GG_E_ARG, "cfg or labels is NULL");
+    if (cfg->dim != 2 && cfg->dim != 3) return fail(nullptr, GG_E_ARG, "dim must be 2 or 3");
+    for (int a = 0; a < 3; ++a)
+        if (cfg->n[a] < 1 || cfg->n[a] > 4096) return fail(nullptr, GG_E_ARG, "grid size out of range [1, 4096]");
+    if (cfg->dim == 2 && cfg->n[2] != 1) return fail(nullptr, GG_E_ARG, "2D requires n[2] == 1");
+    if (!(cfg->band >= 1.0 && cfg->band <= gg::kMaxBand)) return fail(nullptr, GG_E_ARG, "band must be in [1, 16]");
+    const int P = (int)std::ceil(cfg->band);
+    for (int a = 0; a < cfg->dim; ++a)
+        if (cfg->n[a] < 4 * P + 2) return fail(nullptr, GG_E_ARG, "grid must have at least 4P + 2 voxels per axis");
+    if (cfg->precision != GG_FP64 && cfg->precision != GG_FP32)
+        return fail(nullptr, GG_E_UNSUPPORTED, "precision must be GG_FP64 or GG_FP32");
+    if (cfg->physics < 0 || cfg->physics > 3) return fail(nullptr, GG_E_ARG, "unknown physics bits");
+    if ((cfg->physics & GG_PHYS_MISORIENTATION) && (!quat || !(cfg->theta_c_deg > 0.0)))
+        return fail(nullptr, GG_E_ARG, "misorientation weights need quat and theta_c_deg > 0");
+    if ((cfg->physics & GG_PHYS_BULK) && (!energy_density || !(cfg->voxel_m > 0.0) || !(cfg->gamma_max > 0.0)))
+        return fail(nullptr, GG_E_ARG, "bulk energy needs energy_density, voxel_m > 0 and gamma_max > 0");
+    if (n_grains < 1) return fail(nullptr, GG_E_ARG, "n_grains must be >= 1");
+    const long long nt3 = (long long)cfg->n[0] * cfg->n[1] * cfg->n[2];
+    for (long long i = 0; i < nt3; ++i)
+        if (labels[i] < 0 || labels[i] >= n_grains) return fail(nullptr, GG_E_ARG, "label out of [0, n_grains)");
+    if (quat && (cfg->physics & GG_PHYS_MISORIENTATION))
+        for (long long i = 0; i < 4LL * n_grains; ++i)
+            if (!std::isfinite(quat[i])) return fail(nullptr, GG_E_ARG, "non-finite quaternion");
+    if (energy_density && (cfg->physics & GG_PHYS_BULK))
+        for (int k = 0; k < n_grains; ++k)
+            if (!std::isfinite(energy_density[k])) return fail(nullptr, GG_E_ARG, "non-finite energy density");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return fail(nullptr, GG_E_NODEVICE, "no HIP device");
+    }
+    std::unique_ptr<gg_sim> s(new (std::nothrow) gg_sim());
+    if (!s) return fail(nullptr, GG_E_NOMEM, "host allocation failed");
+    s->G = n_grains;
+    for (int a = 0; a < 3; ++a) s->n[a] = cfg->n[a];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    s->device = dev;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(nullptr, GG_E_NODEVICE, "device query failed");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(nullptr, GG_E_NODEVICE, std::string("device is ") + prop.gcnArchName + ", not gfx950");
+    try {
+        if (cfg->precision == GG_FP64) {
+            auto *p = new Sim<double>(*cfg, n_grains, (hipStream_t)hip_stream);
+            s->impl.reset(p);
+            p->create(labels, quat, energy_density);
+        } else {
+            auto *p = new Sim<float>(*cfg, n_grains, (hipStream_t)hip_stream);
+            s->impl.reset(p);
+            p->create(labels, quat, energy_density);
+        }
+    } catch (const ArgError &e) {
+        return fail(nullptr, GG_E_ARG, e.msg);
+    } catch (const CapError &e) {
+        return fail(nullptr, GG_E_CAPACITY, e.msg);
+    } catch (const MemError &e) {
+        return fail(nullptr, GG_E_NOMEM, e.msg);
+    } catch (const HipError &e) {
+        return fail(nullptr, GG_E_HIP, std::string(hipGetErrorString(e.err)) + " in " + e.where);
+    } catch (const std::bad_alloc &) {
+        return fail(nullptr, GG_E_NOMEM, "host allocation failed");
+    }
+    *out = s.release();
+    return GG_OK;
+}
+
+gg_status gg_step(gg_sim *sim, double dt, int32_t n_steps) {
+    if (!sim) return GG_E_ARG;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(sim, GG_E_ARG, "dt must be finite and positive");
+    if (n_steps < 0) return fail(sim, GG_E_ARG, "n_steps must be >= 0");
+    return guarded(sim, [&]() {
+        sim->impl->step(dt, n_steps);
+        return GG_OK;
+    });
+}
+
+gg_status gg_sync(gg_sim *sim) {
+    return guarded(sim, [&]() {
+        sim->impl->sync();
+        return GG_OK;
+    });
+}
+
+gg_status gg_grain_count(gg_sim *sim, int32_t *alive) {
+    if (!alive) return fail(sim, GG_E_ARG, "alive is NULL");
+    return guarded(sim, [&]() {
+        *alive = sim->impl->alive_count();
+        return GG_OK;
+    });
+}
+
+gg_status gg_grain_volumes(gg_sim *sim, double *out, int64_t cap) {
+    if (!sim || !out) return fail(sim, GG_E_ARG, "NULL argument");
+    if (cap < sim->G) return fail(sim, GG_E_SMALLBUF, "cap < n_grains");
+    return guarded(sim, [&]() {
+        sim->impl->volumes(out);
+        return GG_OK;
+    });
+}
+
+gg_status gg_labels(gg_sim *sim, int32_t *out, int64_t cap, int32_t out_is_device) {
+    if (!sim || !out) return fail(sim, GG_E_ARG, "NULL argument");
+    if (cap < (int64_t)sim->n[0] * sim->n[1] * sim->n[2]) return fail(sim, GG_E_SMALLBUF, "cap < prod(n)");
+    return guarded(sim, [&]() {
+        sim->impl->labels(out, out_is_device != 0);
+        return GG_OK;
+    });
+}
+
+gg_status gg_stats(gg_sim *sim, gg_step_stats *out) {
+    if (!sim || !out) return fail(sim, GG_E_ARG, "NULL argument");
+    return guarded(sim, [&]() {
+        *out = sim->impl->stats();
+        return GG_OK;
+    });
+}
+
+gg_status gg_get_boxes(gg_sim *sim, int32_t *lo, int32_t *ext, int32_t *alive, int64_t *offset, int64_t cap) {
+    if (!sim) return GG_E_ARG;
+    if (cap < sim->G) return fail(sim, GG_E_SMALLBUF, "cap < n_grains");
+    return guarded(sim, [&]() {
+        sim->impl->boxes(lo, ext, alive, offset, false);
+        return GG_OK;
+    });
+}
+
+gg_status gg_get_values(gg_sim *sim, double *out, int64_t cap) {
+    if (!sim || !out) return fail(sim, GG_E_ARG, "NULL argument");
+    return guarded(sim, [&]() {
+        long long m = sim->impl->values(out, cap, -1);
+        if (m < 0) return fail(sim, GG_E_SMALLBUF, "cap < sum of box volumes (" + std::to_string(-m) + ")");
+        return GG_OK;
+    });
+}
+
+gg_status gg_get_iota(gg_sim *sim, int32_t *out, int64_t cap) {
+    if (!sim || !out) return fail(sim, GG_E_ARG, "NULL argument");
+    return guarded(sim, [&]() {
+        long long m = sim->impl->iota(out, cap);
+        if (m < 0) return fail(sim, GG_E_SMALLBUF, "cap < sum of box volumes");
+        return GG_OK;
+    });
+}
+
+gg_status gg_load_state(gg_sim *sim, const int32_t *lo, const int32_t *ext, const uint8_t *alive,
+                        const double *values, const int32_t *iota) {
+    if (!sim || !lo || !ext || !alive || !values) return fail(sim, GG_E_ARG, "NULL argument");
+    return guarded(sim, [&]() {
+        sim->impl->load_state(lo, ext, alive, values, iota);
+        return GG_OK;
+    });
+}
+
+gg_status gg_keep_intermediates(gg_sim *sim, int32_t on) {
+    return guarded(sim, [&]() {
+        sim->impl->keep = on != 0;
+        return GG_OK;
+    });
+}
+
+gg_status gg_get_intermediate(gg_sim *sim, int32_t which, double *out, int64_t cap, int32_t *lo, int32_t *ext,
+                              int32_t *alive, int64_t *offset, int64_t cap_grains) {
+    if (!sim || !out || (which != 0 && which != 1)) return fail(sim, GG_E_ARG, "bad argument");
+    if ((lo || ext || alive || offset) && cap_grains < sim->G) return fail(sim, GG_E_SMALLBUF, "cap_grains < n_grains");
+    return guarded(sim, [&]() {
+        long long m = sim->impl->values(out, cap, which);
+        if (m < 0) return fail(sim, GG_E_SMALLBUF, "cap too small (" + std::to_string(-m) + ")");
+        if (lo || ext || alive || offset) sim->impl->boxes(lo, ext, alive, offset, true);
+        return GG_OK;
+    });
+}
+
+void gg_destroy(gg_sim *sim) {
+    if (!sim) return;
+    (void)hipSetDevice(sim->device);
+    delete sim;
+}
+
+}  // extern "C"

@@ -1,0 +1,257 @@
+"""ctypes binding of the C ABI in include/gg.h (argument marshalling only).
+
+Every step of the method runs in the HIP library ``libgg.so``; this module only
+converts arguments.  It raises if the library has not been built: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgg.so")
+
+GG_FP64, GG_FP32 = 0, 1
+PHYS_NONE, PHYS_MISORIENTATION, PHYS_BULK = 0, 1, 2
+
+STATUS = {0: "GG_OK", 1: "GG_E_ARG", 2: "GG_E_NOMEM", 3: "GG_E_HIP", 4: "GG_E_CAPACITY",
+          5: "GG_E_SMALLBUF", 6: "GG_E_NUMERIC", 7: "GG_E_POISONED", 8: "GG_E_UNSUPPORTED",
+          9: "GG_E_NODEVICE"}
+
+EXPORTS = ["gg_create", "gg_step", "gg_sync", "gg_grain_count", "gg_grain_volumes", "gg_labels",
+           "gg_stats", "gg_get_boxes", "gg_get_values", "gg_get_iota", "gg_load_state",
+           "gg_keep_intermediates", "gg_get_intermediate", "gg_status_str", "gg_last_error",
+           "gg_destroy", "gg_version"]
+
+
+class GGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Config(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("band", C.c_double),
+                ("precision", C.c_int32), ("physics", C.c_int32), ("theta_c_deg", C.c_double),
+                ("voxel_m", C.c_double), ("gamma_max", C.c_double),
+                ("capacity_headroom", C.c_double)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("alive", C.c_int32), ("kernel_radius", C.c_int32),
+                ("grain_voxels", C.c_int64), ("capacity", C.c_int64),
+                ("superposition", C.c_double), ("last_step_ms", C.c_double)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libgg.so; raises ImportError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1701_06658_amd.build`")
+    lib = C.CDLL(path)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "gg_create": (i32, [C.POINTER(Config), vp, i32, vp, vp, vp, C.POINTER(vp)]),
+        "gg_step": (i32, [vp, dbl, i32]),
+        "gg_sync": (i32, [vp]),
+        "gg_grain_count": (i32, [vp, C.POINTER(i32)]),
+        "gg_grain_volumes": (i32, [vp, vp, i64]),
+        "gg_labels": (i32, [vp, vp, i64, i32]),
+        "gg_stats": (i32, [vp, C.POINTER(StepStats)]),
+        "gg_get_boxes": (i32, [vp, vp, vp, vp, vp, i64]),
+        "gg_get_values": (i32, [vp, vp, i64]),
+        "gg_get_iota": (i32, [vp, vp, i64]),
+        "gg_load_state": (i32, [vp, vp, vp, vp, vp, vp]),
+        "gg_keep_intermediates": (i32, [vp, i32]),
+        "gg_get_intermediate": (i32, [vp, i32, vp, i64, vp, vp, vp, vp, i64]),
+        "gg_status_str": (C.c_char_p, [i32]),
+        "gg_last_error": (C.c_char_p, [vp]),
+        "gg_destroy": (None, [vp]),
+        "gg_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+class Simulation:
+    """One grain-growth simulation on the GPU, created from a label field.
+
+    labels: int array (nz, ny, nx) (nz == 1 in 2D), values in [0, G).
+    precision: "fp64" (plain) or "fp32" (mixed).
+    stream: optional hipStream_t handle (int), e.g. torch.cuda.current_stream().cuda_stream.
+    """
+
+    def __init__(self, labels, band, G=None, precision="fp64", physics=0, quat=None,
+                 theta_c_deg=15.0, energy=None, voxel_m=0.0, gamma_max=0.0, stream=None,
+                 headroom=0.0):
+        lib = load_library()
+        labels = np.ascontiguousarray(labels, dtype=np.int32)
+        if labels.ndim == 2:
+            labels = labels[None]
+        nz, ny, nx = labels.shape
+        self.dim = 2 if nz == 1 else 3
+        self.n = (nx, ny, nz)
+        self.G = int(G if G is not None else labels.max() + 1)
+        cfg = Config()
+        cfg.dim = self.dim
+        cfg.n[0], cfg.n[1], cfg.n[2] = nx, ny, nz
+        cfg.band = float(band)
+        cfg.precision = {"fp64": GG_FP64, "fp32": GG_FP32}[precision]
+        cfg.physics = int(physics)
+        cfg.theta_c_deg = float(theta_c_deg)
+        cfg.voxel_m = float(voxel_m)
+        cfg.gamma_max = float(gamma_max)
+        cfg.capacity_headroom = float(headroom)
+        q = None if quat is None else np.ascontiguousarray(quat, dtype=np.float64)
+        e = None if energy is None else np.ascontiguousarray(energy, dtype=np.float64)
+        h = C.c_void_p()
+        st = lib.gg_create(C.byref(cfg), _ptr(labels), self.G, _ptr(q), _ptr(e),
+                           C.c_void_p(int(stream)) if stream else None, C.byref(h))
+        if st != 0:
+            raise GGError(st, lib.gg_last_error(None).decode())
+        self._lib = lib
+        self._h = h
+        self.precision = precision
+        self.band = float(band)
+
+    def _check(self, st):
+        if st != 0:
+            raise GGError(st, self._lib.gg_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.gg_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def step(self, dt, n=1):
+        self._check(self._lib.gg_step(self._h, float(dt), int(n)))
+
+    def sync(self):
+        self._check(self._lib.gg_sync(self._h))
+
+    def alive_count(self):
+        v = C.c_int32()
+        self._check(self._lib.gg_grain_count(self._h, C.byref(v)))
+        return v.value
+
+    def volumes(self):
+        out = np.zeros(self.G, np.float64)
+        self._check(self._lib.gg_grain_volumes(self._h, _ptr(out), out.size))
+        return out
+
+    def labels(self, device_out=None):
+        """Voxel labels as a numpy array, or written into a device buffer (torch tensor)."""
+        if device_out is not None:
+            self._check(self._lib.gg_labels(self._h, C.c_void_p(device_out.data_ptr()),
+                                            device_out.numel(), 1))
+            return device_out
+        out = np.empty(int(np.prod(self.n)), np.int32)
+        self._check(self._lib.gg_labels(self._h, _ptr(out), out.size, 0))
+        return out.reshape(self.n[2], self.n[1], self.n[0])
+
+    def stats(self):
+        s = StepStats()
+        self._check(self._lib.gg_stats(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in StepStats._fields_}
+
+    def boxes(self):
+        lo = np.zeros((self.G, 3), np.int32)
+        ext = np.zeros((self.G, 3), np.int32)
+        alive = np.zeros(self.G, np.int32)
+        off = np.zeros(self.G, np.int64)
+        self._check(self._lib.gg_get_boxes(self._h, _ptr(lo), _ptr(ext), _ptr(alive), _ptr(off),
+                                           self.G))
+        return dict(lo=lo, ext=ext, alive=alive.astype(bool), offset=off)
+
+    def values(self):
+        b = self.boxes()
+        m = int(sum(int(np.prod(e)) for e, a in zip(b["ext"], b["alive"]) if a))
+        out = np.empty(max(m, 1), np.float64)
+        self._check(self._lib.gg_get_values(self._h, _ptr(out), out.size))
+        return b, out[:m]
+
+    def iota(self):
+        b = self.boxes()
+        m = int(sum(int(np.prod(e)) for e, a in zip(b["ext"], b["alive"]) if a))
+        out = np.empty(max(m, 1), np.int32)
+        self._check(self._lib.gg_get_iota(self._h, _ptr(out), out.size))
+        return b, out[:m]
+
+    def state(self):
+        """Per-grain dict like the oracle's: alive, lo, ext, phi (list of (ez, ey, ex) arrays)."""
+        b, v = self.values()
+        return _unpack(b, v)
+
+    def load_state(self, alive, lo, ext, phis, iotas=None):
+        """Replace the state; phis/iotas: lists of (ez, ey, ex) arrays (None for extinct)."""
+        alive = np.ascontiguousarray(alive, dtype=np.uint8)
+        lo = np.ascontiguousarray(lo, dtype=np.int32)
+        ext = np.ascontiguousarray(ext, dtype=np.int32)
+        vals = [np.asarray(p, np.float64).ravel() for p, a in zip(phis, alive) if a]
+        flat = np.ascontiguousarray(np.concatenate(vals) if vals else np.zeros(1))
+        io = None
+        if iotas is not None:
+            iv = [np.asarray(p, np.int32).ravel() for p, a in zip(iotas, alive) if a]
+            io = np.ascontiguousarray(np.concatenate(iv) if iv else np.zeros(1, np.int32))
+        self._check(self._lib.gg_load_state(self._h, _ptr(lo), _ptr(ext), _ptr(alive),
+                                            _ptr(flat), _ptr(io)))
+
+    def keep_intermediates(self, on=True):
+        self._check(self._lib.gg_keep_intermediates(self._h, int(bool(on))))
+
+    def intermediate(self, which):
+        """which 0: predictor output, 1: corrector output, on the step's starting boxes."""
+        lo = np.zeros((self.G, 3), np.int32)
+        ext = np.zeros((self.G, 3), np.int32)
+        alive = np.zeros(self.G, np.int32)
+        off = np.zeros(self.G, np.int64)
+        cap = 1
+        while True:
+            out = np.empty(cap, np.float64)
+            st = self._lib.gg_get_intermediate(self._h, int(which), _ptr(out), cap, _ptr(lo),
+                                               _ptr(ext), _ptr(alive), _ptr(off), self.G)
+            if st == 5 and cap == 1:
+                m = int(sum(int(np.prod(e)) for e, a in zip(ext, alive) if a))
+                msg = self._lib.gg_last_error(self._h).decode()
+                cap = int(msg.split("(")[-1].rstrip(")")) if "(" in msg else max(m, 1)
+                continue
+            self._check(st)
+            break
+        b = dict(lo=lo, ext=ext, alive=alive.astype(bool), offset=off)
+        m = int(sum(int(np.prod(e)) for e, a in zip(ext, alive) if a))
+        return _unpack(b, out[:m])
+
+
+def _unpack(b, v):
+    phis = []
+    for k in range(len(b["alive"])):
+        if not b["alive"][k]:
+            phis.append(None)
+            continue
+        e = b["ext"][k]
+        m = int(np.prod(e))
+        o = int(b["offset"][k])
+        phis.append(v[o:o + m].reshape(int(e[2]), int(e[1]), int(e[0])))
+    return dict(alive=np.asarray(b["alive"], bool), lo=b["lo"], ext=b["ext"], phi=phis)
+
+
+def version():
+    return load_library().gg_version().decode()

@@ -1,0 +1,84 @@
+"""Host-side checks of the C-ABI library (no GPU needed): exports and argument errors."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gg.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1701_06658_amd import build, gg
+    if not os.path.exists(gg.LIB_PATH):
+        build.build_library()
+    return gg.load_library()
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gg_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    from paper_1701_06658_amd import gg
+    assert sorted(gg.EXPORTS) == names
+
+
+def test_status_strings(lib):
+    assert lib.gg_status_str(0) == b"ok"
+    assert lib.gg_status_str(1) == b"invalid argument"
+    assert lib.gg_version().startswith(b"gg-mi355x")
+
+
+def _create(lib, **kw):
+    from paper_1701_06658_amd import gg
+    cfg = gg.Config()
+    cfg.dim = kw.get("dim", 2)
+    n = kw.get("n", (32, 32, 1))
+    cfg.n[0], cfg.n[1], cfg.n[2] = n
+    cfg.band = kw.get("band", 4.0)
+    cfg.precision = kw.get("precision", 0)
+    cfg.physics = kw.get("physics", 0)
+    cfg.theta_c_deg = 15.0
+    labels = kw.get("labels", np.zeros(int(np.prod(n)), np.int32))
+    h = C.c_void_p()
+    st = lib.gg_create(C.byref(cfg), labels.ctypes.data_as(C.c_void_p), kw.get("G", 1), None,
+                       None, None, C.byref(h))
+    return st, lib.gg_last_error(None)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(dim=4),
+    dict(band=0.5),
+    dict(band=40.0),
+    dict(n=(32, 32, 2)),                       # 2D needs n[2] == 1
+    dict(n=(12, 32, 1)),                       # fewer than 4P + 2 voxels on an axis
+    dict(labels=np.full(32 * 32, 3, np.int32), G=2),   # label out of range
+    dict(G=0),
+    dict(physics=1),                           # misorientation weights without quaternions
+    dict(physics=2),                           # bulk energy without energy densities
+])
+def test_argument_errors_are_reported_before_any_device_use(lib, kw):
+    st, msg = _create(lib, **kw)
+    assert st == 1, (st, msg)
+    assert msg
+
+
+def test_unsupported_precision(lib):
+    st, _ = _create(lib, precision=7)
+    assert st == 8
+
+
+def test_null_handles(lib):
+    assert lib.gg_step(None, 1e-3, 1) == 1
+    assert lib.gg_sync(None) == 1
+    lib.gg_destroy(None)

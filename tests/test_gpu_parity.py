@@ -1,0 +1,165 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+FP64 plain path: |dphi| <= 1e-10 voxel at every box voxel, after every step.
+FP32 mixed path: one step from an identical state, |dphi| <= 2e-3 voxel at band
+voxels, ownership identical except where the top-2 gap is below 4e-3, grain
+volumes within 0.5% (1 voxel for grains below 50 voxels).
+"""
+import numpy as np
+import pytest
+
+from _compare import compare_states, top2_gap
+from oracle import Oracle
+from synth import ball_labels, config_dt, make_config, power_labels, uniform_voronoi
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-10
+TOL_MIXED = 2e-3
+
+
+def _gpu():
+    import paper_1701_06658_amd as gg
+    return gg
+
+
+def _pair(labels, W, G, precision="fp64", **phys):
+    gg = _gpu()
+    o = Oracle(labels, W, G=G)
+    s = gg.Simulation(labels, W, G=G, precision=precision, **phys)
+    return o, s
+
+
+def _check_fp64(o, s, W, tag):
+    a, b = o.state(), s.state()
+    r = compare_states(a, b, o.n, W)
+    print(f"[{tag}] max|dphi|={r['max_abs']:.3e} alive_mismatch={r['alive_mismatch']} "
+          f"box_mismatch={r['box_mismatch']}", flush=True)
+    assert r["alive_mismatch"] == 0, tag
+    assert r["max_abs"] <= TOL_FP64, (tag, r)
+    vo, vg = o.volumes(), s.volumes()
+    assert np.allclose(vo, vg, rtol=1e-10, atol=1e-9), tag
+    return r
+
+
+def test_create_matches_oracle_2d():
+    c = make_config(1)
+    o, s = _pair(c["labels"], c["W"], c["G"])
+    _check_fp64(o, s, c["W"], "cfg1 create")
+    assert s.alive_count() == o.alive_count()
+
+
+def test_fp64_trajectory_config1():
+    c = make_config(1)
+    o, s = _pair(c["labels"], c["W"], c["G"])
+    for step in range(1, c["steps"] + 1):
+        o.step(c["dt"])
+        s.step(c["dt"])
+        _check_fp64(o, s, c["W"], f"cfg1 step {step}")
+        assert np.array_equal(o.labels(), s.labels())
+
+
+def test_fp64_intermediates_config1():
+    c = make_config(1)
+    o, s = _pair(c["labels"], c["W"], c["G"])
+    o.keep_intermediates(True)
+    s.keep_intermediates(True)
+    for step in range(3):
+        o.step(c["dt"])
+        s.step(c["dt"])
+        for which, getter in ((0, o.psi), (1, o.phic)):
+            st = s.intermediate(which)
+            ref = dict(alive=np.zeros(o.G, bool), lo=np.zeros((o.G, 3), np.int32),
+                       ext=np.zeros((o.G, 3), np.int32), phi=[])
+            for k in range(o.G):
+                alive, lo, ext = o.box(k, prev=True)
+                ref["alive"][k] = alive
+                ref["lo"][k] = lo
+                ref["ext"][k] = ext
+                ref["phi"].append(getter(k) if alive else None)
+            r = compare_states(ref, st, o.n, c["W"])
+            print(f"[cfg1 step {step} pass {which}] {r}", flush=True)
+            assert r["box_mismatch"] == 0 and r["max_abs"] <= TOL_FP64
+
+
+def test_fp64_config2_first_steps():
+    c = make_config(2)
+    o, s = _pair(c["labels"], c["W"], c["G"])
+    _check_fp64(o, s, c["W"], "cfg2 create")
+    for step in range(1, 3):
+        o.step(c["dt"])
+        s.step(c["dt"])
+        _check_fp64(o, s, c["W"], f"cfg2 step {step}")
+
+
+@pytest.mark.parametrize("dim,N,R0", [(2, 96, 20.0), (3, 48, 12.0)])
+def test_fp64_ball_with_full_periodic_matrix(dim, N, R0):
+    # grain 0 spans the whole periodic grid (its box wraps on every axis)
+    n = (N, N) if dim == 2 else (N, N, N)
+    labels = ball_labels(n, R0)
+    W, sigma = (6.0, 1.5) if dim == 2 else (8.0, 2.0)
+    o, s = _pair(labels, W, 2)
+    dt = config_dt(sigma, N)
+    steps = 12 if dim == 2 else 5
+    for step in range(steps):
+        o.step(dt)
+        s.step(dt)
+    _check_fp64(o, s, W, f"ball dim={dim}")
+
+
+def test_fp64_extinction_and_unused_ids():
+    # ids 1 and 4 never appear in the labels; the small disc vanishes
+    N = 48
+    labels = ball_labels((N, N), 5.0) * 3       # ids {0, 3}
+    labels[:, :, :14] = np.where(labels[:, :, :14] == 0, 2, labels[:, :, :14])
+    o, s = _pair(labels, 6.0, 5)
+    assert s.alive_count() == o.alive_count() == 3
+    dt = config_dt(1.5, N)
+    for step in range(40):
+        o.step(dt)
+        s.step(dt)
+        if o.alive_count() < 3:
+            break
+    assert o.alive_count() == 2 and s.alive_count() == 2
+    _check_fp64(o, s, 6.0, "extinction")
+    assert s.volumes()[3] == 0.0
+
+
+def _mixed_one_step(o, c_dt, W, G, tag, **phys):
+    gg = _gpu()
+    st = o.state()
+    labels = o.labels()
+    s = gg.Simulation(labels, W, G=G, precision="fp32", **phys)
+    io = None
+    if phys.get("physics"):
+        io = [o.iota(k) if st["alive"][k] else None for k in range(G)]
+    s.load_state(st["alive"], st["lo"], st["ext"], st["phi"], io)
+    o.step(c_dt)
+    s.step(c_dt)
+    a, b = o.state(), s.state()
+    r = compare_states(a, b, o.n, W, band_only=True)
+    print(f"[{tag}] mixed one-step max|dphi| (band) = {r['max_abs']:.3e} "
+          f"alive_mismatch={r['alive_mismatch']}", flush=True)
+    assert r["max_abs"] <= TOL_MIXED, (tag, r)
+    lo_, lg = o.labels(), s.labels()
+    gap = top2_gap(a, o.n, W)
+    bad = (lo_ != lg) & (gap >= 4e-3)
+    assert not bad.any(), (tag, int(bad.sum()))
+    vo, vg = o.volumes(), s.volumes()
+    big = vo >= 50
+    assert np.all(np.abs(vg[big] - vo[big]) <= 5e-3 * vo[big]), tag
+    assert np.all(np.abs(vg[~big] - vo[~big]) <= 1.0), tag
+
+
+def test_mixed_one_step_config1():
+    c = make_config(1)
+    o = Oracle(c["labels"], c["W"], G=c["G"])
+    for start in (0, 5, 10):
+        _mixed_one_step(o, c["dt"], c["W"], c["G"], f"cfg1 from step {start}")
+        o.step(c["dt"], 4)
+
+
+def test_mixed_one_step_config2():
+    c = make_config(2)
+    o = Oracle(c["labels"], c["W"], G=c["G"])
+    _mixed_one_step(o, c["dt"], c["W"], c["G"], "cfg2 from step 0")
