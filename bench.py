@@ -1,0 +1,188 @@
+"""Throughput of the level-set grain-growth step on one MI355X.
+
+Prints ONE JSON line: grain-voxel updates per second of the batched mixed
+(FP32) step on the 3D 256^3 / 8000-grain lognormal workload, the plain FP64
+path on the same inputs, the roofline of the dominant kernel (HIP events on
+the library's stream, algorithmic bytes), and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 3]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+# Algorithmic bytes per grain voxel of one launch, by kernel class, in units of
+# the stored value size s (plus fixed extra bytes): every stencil kernel reads
+# its input box values once and writes its output box values once.
+ALG_BYTES = {
+    "conv_xy": (2, 0), "conv_z": (2, 0), "compare": (2, 0),
+    "reinit_xy": (2, 0), "reinit_z": (2, 0),
+}
+# with the predictor correction the z pass also reads phi and the ID-field, the
+# corrector writes the ID-field and the re-initialization carries it over
+ALG_BYTES_PHYS = {
+    "conv_xy": (2, 0), "conv_z": (3, 4), "compare": (2, 4),
+    "reinit_xy": (2, 8), "reinit_z": (2, 0),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_gpu(cfg, precision, steps, warmup):
+    import paper_1701_06658_amd as gg
+    phys = {}
+    if cfg.get("physics") == "anisotropic":
+        phys = dict(physics=gg.PHYS_MISORIENTATION, quat=cfg["quat"], theta_c_deg=cfg["theta_c_deg"])
+    elif cfg.get("physics") == "magnetic":
+        phys = dict(physics=gg.PHYS_BULK, energy=cfg["energy"], voxel_m=cfg["h_phys"],
+                    gamma_max=cfg["gamma_max"])
+    t0 = time.perf_counter()
+    sim = gg.Simulation(cfg["labels"], cfg["W"], G=cfg["G"], precision=precision, **phys)
+    sim.sync()
+    log(f"[bench] {precision}: created in {time.perf_counter() - t0:.2f} s")
+    if warmup:
+        sim.step(cfg["dt"], warmup)
+    sim.sync()
+    gv0 = sim.stats()["total_grain_voxels"]
+    sim.profile(True)
+    sim.sync()
+    t0 = time.perf_counter()
+    sim.step(cfg["dt"], steps)
+    sim.sync()
+    dt = time.perf_counter() - t0
+    st = sim.stats()
+    kt = sim.kernel_times()
+    sim.profile(False)
+    gv = st["total_grain_voxels"] - gv0
+    out = dict(value=gv / dt, ms_per_step=1e3 * dt / steps, grain_voxels=gv, alive=st["alive"],
+               superposition=st["superposition"], kernels=kt, physics=bool(phys))
+    log(f"[bench] {precision}: {steps} steps in {dt:.3f} s, {out['value']:.3e} gv/s, "
+        f"alive {st['alive']}")
+    sim.close()
+    return out
+
+
+def roofline(res, s_bytes):
+    table = ALG_BYTES_PHYS if res["physics"] else ALG_BYTES
+    best = None
+    per = {}
+    for name, (mult, extra) in table.items():
+        k = res["kernels"][name]
+        if not k["launches"] or k["ms"] <= 0:
+            continue
+        bytes_alg = (mult * s_bytes + extra) * k["voxels"]
+        avg_ms = k["ms"] / k["launches"]
+        gbs = bytes_alg / (k["ms"] * 1e-3) / 1e9
+        per[name] = dict(avg_ms=avg_ms, gbs=gbs, bytes_per_launch=bytes_alg / k["launches"])
+        if best is None or k["ms"] > res["kernels"][best]["ms"]:
+            best = name
+    r = per[best]
+    return dict(bound="hbm", kernel=best, achieved=r["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=r["gbs"] / HBM_PEAK_GBS, traffic=None,
+                avg_launch_ms=r["avg_ms"], alg_bytes_per_launch=r["bytes_per_launch"],
+                per_kernel={k: round(v["gbs"], 1) for k, v in per.items()})
+
+
+def cpu_baseline(index):
+    """FP64 oracle on a bounded sample: one step of a density-matched 128^3 cut."""
+    from oracle import Oracle, num_threads
+    from synth import make_config
+    G = {1: None, 2: 1000, 3: 1000, 4: 781, 5: 781}[index]
+    N = None if index == 1 else 128
+    c = make_config(index, N=N, G=G)
+    o = Oracle(c["labels"], c["W"], G=c["G"])
+    gv = 0
+    for k in range(c["G"]):
+        alive, lo, ext = o.box(k)
+        if alive:
+            gv += int(ext[0]) * int(ext[1]) * int(ext[2])
+    t0 = time.perf_counter()
+    o.step(c["dt"])
+    dt = time.perf_counter() - t0
+    o.close()
+    return dict(value=gv / dt, unit="grain-voxel updates/s", cores=num_threads(), kind="oracle",
+                sample=f"1 FP64 oracle step of a density-matched {c['N']}^{c['dim']} cut with "
+                       f"{c['G']} grains of workload {index} ({gv} grain voxels, {dt:.2f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--precision", default=None, help="fp32 (mixed) or fp64 (plain)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also time a 1 GiB device copy (HBM reference for profiler counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    from synth import make_config
+    t0 = time.perf_counter()
+    cfg = make_config(args.config)
+    log(f"[bench] inputs {cfg['name']}: {cfg['G']} grains in {time.perf_counter() - t0:.1f} s")
+    precision = args.precision or cfg["precision"]
+    main_res = run_gpu(cfg, precision, args.steps, args.warmup)
+    s_bytes = 4 if precision == "fp32" else 8
+    line = {
+        "metric": "grain-voxel updates/s per step (mixed batched vs FP64 plain) + %HBM roofline",
+        "value": main_res["value"],
+        "unit": "grain-voxel updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "grid": list(cfg["n"]), "grains": cfg["G"],
+                   "sigma_voxels": cfg["sigma"], "band_voxels": cfg["W"],
+                   "precision": precision, "alive_after": main_res["alive"],
+                   "superposition": round(main_res["superposition"], 3)},
+        "roofline": roofline(main_res, s_bytes),
+    }
+    if not args.no_plain and precision != "fp64":
+        plain = run_gpu(cfg, "fp64", args.steps, args.warmup)
+        line["plain_fp64"] = dict(value=plain["value"], ms_per_step=plain["ms_per_step"],
+                                  roofline=roofline(plain, 8), mixed_speedup=main_res["value"] / plain["value"])
+    if args.copy_probe:
+        import torch
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        reps = 10
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        line["copy_probe"] = dict(bytes=2 * a.numel() * 4, ms=ms, gbs=2 * a.numel() * 4 / ms / 1e6)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(args.config)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

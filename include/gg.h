@@ -82,6 +82,7 @@ typedef struct {
 
 typedef struct {
     int64_t steps;          /* steps taken since gg_create                          */
+    int64_t total_grain_voxels; /* sum over all steps taken of the grain voxels    */
     int32_t alive;          /* alive grains                                         */
     int32_t kernel_radius;  /* R of the last step                                   */
     int64_t grain_voxels;   /* sum of box volumes at the start of the last step    */
@@ -127,6 +128,28 @@ gg_status gg_labels(gg_sim *sim, int32_t *out, int64_t cap, int32_t out_is_devic
 
 /* Step statistics. */
 gg_status gg_stats(gg_sim *sim, gg_step_stats *out);
+
+/* Per-kernel device time, for roofline accounting.  Kernel classes: */
+enum {
+    GG_K_CONV_XY = 0,   /* predictor x and y passes (2D: whole predictor)          */
+    GG_K_CONV_Z = 1,    /* predictor z pass (+ correction epilogue)                 */
+    GG_K_COMPARE = 2,   /* corrector over global tiles                              */
+    GG_K_REINIT_XY = 3, /* reference values, x and y min-plus passes (2D: all)      */
+    GG_K_REINIT_Z = 4,  /* z min-plus pass, clamp, volume partial sums              */
+    GG_K_PLAN = 5,      /* box plan, scans, work items, coverage lists              */
+    GG_K_VOLUME = 6,    /* per-grain volume reduction                               */
+    GG_K_CLASSES = 8
+};
+typedef struct {
+    double ms[GG_K_CLASSES];          /* summed device time (HIP events)            */
+    int64_t launches[GG_K_CLASSES];   /* timed launches                             */
+    int64_t voxels[GG_K_CLASSES];     /* grain voxels those launches covered        */
+} gg_kernel_times;
+
+/* Turn per-kernel timing on (resets the sums) or off.  While on, every launch
+ * of the step is bracketed by HIP events on the simulation's stream. */
+gg_status gg_profile(gg_sim *sim, int32_t on);
+gg_status gg_get_kernel_times(gg_sim *sim, gg_kernel_times *out);
 
 /* State access (host memory).  gg_get_boxes fills cap >= n_grains entries:
  * lo/ext 3 per grain, alive 1 per grain, offset 1 per grain (start of the

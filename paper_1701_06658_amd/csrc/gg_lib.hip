@@ -89,6 +89,8 @@ struct SimBase {
     virtual int alive_count() const = 0;
     virtual gg_step_stats stats() const = 0;
     virtual long long arena_total(bool prev) const = 0;
+    virtual void profile(bool on) = 0;
+    virtual gg_kernel_times kernel_times() const = 0;
     bool keep = false;
 };
 
@@ -131,6 +133,58 @@ template <typename T> struct Sim final : SimBase {
     long long steps_done = 0;
     double last_ms = 0.0;
     long long last_gv = 0;
+    long long total_gv = 0;
+
+    // per-kernel timing: HIP event pairs on the simulation's stream
+    struct Span {
+        hipEvent_t a, b;
+        int cls;
+        long long vox;
+    };
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<Span> spans;
+    gg_kernel_times ktimes{};
+
+    hipEvent_t next_event() {
+        if (ev_used == ev_pool.size()) {
+            hipEvent_t e;
+            HIPCHECK(hipEventCreate(&e));
+            ev_pool.push_back(e);
+        }
+        return ev_pool[ev_used++];
+    }
+    void tbegin(int cls, long long vox) {
+        if (!prof) return;
+        Span sp{next_event(), nullptr, cls, vox};
+        HIPCHECK(hipEventRecord(sp.a, stream));
+        spans.push_back(sp);
+    }
+    void tend() {
+        if (!prof) return;
+        spans.back().b = next_event();
+        HIPCHECK(hipEventRecord(spans.back().b, stream));
+    }
+    void resolve_spans() {
+        if (spans.empty()) return;
+        HIPCHECK(hipStreamSynchronize(stream));
+        for (const Span &sp : spans) {
+            float ms = 0.f;
+            HIPCHECK(hipEventElapsedTime(&ms, sp.a, sp.b));
+            ktimes.ms[sp.cls] += ms;
+            ktimes.launches[sp.cls] += 1;
+            ktimes.voxels[sp.cls] += sp.vox;
+        }
+        spans.clear();
+        ev_used = 0;
+    }
+    void profile(bool on) override {
+        resolve_spans();
+        prof = on;
+        std::memset(&ktimes, 0, sizeof(ktimes));
+    }
+    gg_kernel_times kernel_times() const override { return ktimes; }
 
     Boxes boxes_of(int l) {
         return Boxes{lo[l].as<int>(), ext[l].as<int>(), alive[l].as<int>(), off[l].as<long long>()};
@@ -232,6 +286,7 @@ template <typename T> struct Sim final : SimBase {
             }
         }
         for (int a = 0; a < 3; ++a) arena[a].release();
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         if (totals_h) (void)hipHostFree(totals_h);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
@@ -254,6 +309,7 @@ template <typename T> struct Sim final : SimBase {
     // Then the item maps and the coverage lists.
     void layout_meta_count(int l, bool coverage) {
         Boxes L = boxes_of(l);
+        tbegin(GG_K_PLAN, 0);
         HIPCHECK(hipMemsetAsync(ldsmax.p, 0, sizeof(unsigned long long) * gg::kKinds, stream));
         const int tb = 256, gb = (G + tb - 1) / tb;
         hipLaunchKernelGGL(gg::k_item_counts, dim3(gb), dim3(tb), 0, stream, L, cnt[0].as<long long>(),
@@ -274,6 +330,7 @@ template <typename T> struct Sim final : SimBase {
                            coverage ? cov_off.as<int>() : (const int *)nullptr, ntiles, L.alive, G,
                            ldsmax.as<unsigned long long>(), totals_d.as<Totals>());
         HIPCHECK(hipGetLastError());
+        tend();
         HIPCHECK(hipMemcpyAsync(totals_h, totals_d.p, sizeof(Totals), hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipStreamSynchronize(stream));
         tot[l] = *totals_h;
@@ -284,20 +341,25 @@ template <typename T> struct Sim final : SimBase {
     }
 
     void layout_meta_fill(int l, bool coverage) {
-        for (int q = 0; q < gg::kKinds; ++q) {
+        for (int q = 0; q < gg::kKinds; ++q)
             iowner[l][q].ensure(sizeof(int) * (size_t)std::max<long long>(tot[l].items[q], 1) * 5 / 4);
+        if (coverage) {
+            if (tot[l].cov > 0x7fffffffLL) throw CapError{"coverage list exceeds 2^31 entries"};
+            cov_list.ensure(sizeof(int) * (size_t)std::max<long long>(tot[l].cov, 1) * 5 / 4);
+        }
+        tbegin(GG_K_PLAN, 0);
+        for (int q = 0; q < gg::kKinds; ++q) {
             hipLaunchKernelGGL(gg::k_fill_owner, dim3(G), dim3(64), 0, stream, ipref[l][q].as<long long>(),
                                iowner[l][q].as<int>(), G);
         }
         if (coverage) {
-            if (tot[l].cov > 0x7fffffffLL) throw CapError{"coverage list exceeds 2^31 entries"};
-            cov_list.ensure(sizeof(int) * (size_t)std::max<long long>(tot[l].cov, 1) * 5 / 4);
             HIPCHECK(hipMemcpyAsync(cov_cur.p, cov_off.p, sizeof(int) * (ntiles + 1), hipMemcpyDeviceToDevice,
                                     stream));
             hipLaunchKernelGGL(gg::k_coverage, dim3(G), dim3(64), 0, stream, boxes_of(l), cov_cur.as<int>(),
                                cov_list.as<int>(), tile_args(), G, 1);
         }
         HIPCHECK(hipGetLastError());
+        tend();
     }
 
     void set_gaussian(double dt) {
@@ -342,20 +404,27 @@ template <typename T> struct Sim final : SimBase {
         vol_part.ensure(sizeof(double) * (size_t)std::max<long long>(t.items[dim == 3 ? 3 : 2], 1) * 5 / 4);
         if (t.items[2] > 0) {
             T *out = dim == 3 ? arena[tmp_a].as<T>() : arena[dst_a].as<T>();
+            tbegin(GG_K_REINIT_XY, t.arena);
             hipLaunchKernelGGL(gg::k_reinit_xy<T>, dim3(grid_of(t.items[2])), dim3(gg::kBlock),
                                sizeof(T) * t.lds[2], stream, boxes_of(lo_l), boxes_of(ln_l),
                                iowner[ln_l][2].as<int>(), ipref[ln_l][2].as<long long>(), src, out, iota_old,
                                iota_new, vol_part.as<double>(), K, W, g);
+            tend();
         }
-        if (dim == 3 && t.items[3] > 0)
+        if (dim == 3 && t.items[3] > 0) {
+            tbegin(GG_K_REINIT_Z, t.arena);
             hipLaunchKernelGGL(gg::k_reinit_z<T>, dim3(grid_of(t.items[3])), dim3(gg::kBlock),
                                sizeof(T) * t.lds[3], stream, boxes_of(ln_l), iowner[ln_l][3].as<int>(),
                                ipref[ln_l][3].as<long long>(), arena[tmp_a].as<T>(), arena[dst_a].as<T>(),
                                vol_part.as<double>(), K, W, g);
+            tend();
+        }
         const int tb = 256, gb = (G + tb - 1) / tb;
+        tbegin(GG_K_VOLUME, t.arena);
         hipLaunchKernelGGL(gg::k_volumes, dim3(gb), dim3(tb), 0, stream, boxes_of(ln_l),
                            ipref[ln_l][dim == 3 ? 3 : 2].as<long long>(), vol_part.as<double>(), vol.as<double>(),
                            G);
+        tend();
         HIPCHECK(hipGetLastError());
     }
 
@@ -489,6 +558,7 @@ template <typename T> struct Sim final : SimBase {
         for (int s = 0; s < nsteps; ++s) step_once();
         HIPCHECK(hipEventRecord(e1, stream));
         HIPCHECK(hipEventSynchronize(e1));
+        resolve_spans();
         float ms = 0.f;
         HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
         (void)hipEventDestroy(e0);
@@ -504,6 +574,7 @@ template <typename T> struct Sim final : SimBase {
         }
         const Totals &t = tot[L];
         last_gv = t.arena;
+        total_gv += t.arena;
         const int a_s = is, a_t1 = (is + 1) % 3, a_psi = (is + 2) % 3;
         gg::GridArgs g = grid_args();
         const int *iota_in = physics ? iota_a[iota_cur].as<int>() : nullptr;
@@ -513,26 +584,36 @@ template <typename T> struct Sim final : SimBase {
         // 1. predictor
         T *psi = arena[a_psi].as<T>();
         if (dim == 3) {
-            if (t.items[0] > 0)
+            if (t.items[0] > 0) {
+                tbegin(GG_K_CONV_XY, t.arena);
                 hipLaunchKernelGGL(gg::k_conv_xy<T>, dim3(grid_of(t.items[0])), dim3(gg::kBlock), sizeof(T) * t.lds[0],
                                    stream, boxes_of(L), iowner[L][0].as<int>(), ipref[L][0].as<long long>(),
                                    arena[a_s].as<T>(), arena[a_t1].as<T>(), taps_d.as<T>(), R, W, g, noph);
-            if (t.items[1] > 0)
+                tend();
+            }
+            if (t.items[1] > 0) {
+                tbegin(GG_K_CONV_Z, t.arena);
                 hipLaunchKernelGGL(gg::k_conv_z<T>, dim3(grid_of(t.items[1])), dim3(gg::kBlock), sizeof(T) * t.lds[1],
                                    stream, boxes_of(L), iowner[L][1].as<int>(), ipref[L][1].as<long long>(),
                                    arena[a_t1].as<T>(), psi, taps_d.as<T>(), R, W, g, ph);
+                tend();
+            }
         } else if (t.items[0] > 0) {
+            tbegin(GG_K_CONV_XY, t.arena);
             hipLaunchKernelGGL(gg::k_conv_xy<T>, dim3(grid_of(t.items[0])), dim3(gg::kBlock), sizeof(T) * t.lds[0],
                                stream, boxes_of(L), iowner[L][0].as<int>(), ipref[L][0].as<long long>(),
                                arena[a_s].as<T>(), psi, taps_d.as<T>(), R, W, g, ph);
+            tend();
         }
         // 2. corrector into the t1 arena (dead after the predictor)
         T *phic = arena[a_t1].as<T>();
         const int iota_old = 1 - iota_cur;
         if (physics) ensure_iota(iota_old, t.arena);
+        tbegin(GG_K_COMPARE, t.arena);
         hipLaunchKernelGGL(gg::k_compare<T>, dim3(ntiles), dim3(gg::kBlock), 0, stream, boxes_of(L), cov_off.as<int>(),
                            cov_list.as<int>(), psi, phic, physics ? iota_a[iota_old].as<int>() : (int *)nullptr,
                            bmin.as<int>(), bmax.as<int>(), occ.as<unsigned>(), tile_args(), W, 0);
+        tend();
         HIPCHECK(hipGetLastError());
         if (keep) keep_copy(L, psi, phic);
         // 3. new boxes, offsets, items and coverage of the new layout
@@ -542,9 +623,11 @@ template <typename T> struct Sim final : SimBase {
         pa.occ_words = occ_words;
         pa.G = G;
         const int tb = 256, gb = (G + tb - 1) / tb;
+        tbegin(GG_K_PLAN, 0);
         hipLaunchKernelGGL(gg::k_plan, dim3(gb), dim3(tb), 0, stream, boxes_of(L), boxes_of(Ln), bmin.as<int>(),
                            bmax.as<int>(), occ.as<unsigned>(), sizes.as<long long>(), pa);
         hipLaunchKernelGGL(gg::k_scan, dim3(1), dim3(1024), 0, stream, sizes.as<long long>(), off[Ln].as<long long>(), G);
+        tend();
         HIPCHECK(hipGetLastError());
         layout_meta_count(Ln, true);
         const long long need = tot[Ln].arena;
@@ -727,6 +810,7 @@ template <typename T> struct Sim final : SimBase {
     gg_step_stats stats() const override {
         gg_step_stats s;
         s.steps = steps_done;
+        s.total_grain_voxels = total_gv;
         s.alive = (int)tot[cur].alive;
         s.kernel_radius = R;
         s.grain_voxels = last_gv;
@@ -979,6 +1063,21 @@ gg_status gg_get_intermediate(gg_sim *sim, int32_t which, double *out, int64_t c
         long long m = sim->impl->values(out, cap, which);
         if (m < 0) return fail(sim, GG_E_SMALLBUF, "cap too small (" + std::to_string(-m) + ")");
         if (lo || ext || alive || offset) sim->impl->boxes(lo, ext, alive, offset, true);
+        return GG_OK;
+    });
+}
+
+gg_status gg_profile(gg_sim *sim, int32_t on) {
+    return guarded(sim, [&]() {
+        sim->impl->profile(on != 0);
+        return GG_OK;
+    });
+}
+
+gg_status gg_get_kernel_times(gg_sim *sim, gg_kernel_times *out) {
+    if (!sim || !out) return fail(sim, GG_E_ARG, "NULL argument");
+    return guarded(sim, [&]() {
+        *out = sim->impl->kernel_times();
         return GG_OK;
     });
 }

@@ -24,7 +24,9 @@ STATUS = {0: "GG_OK", 1: "GG_E_ARG", 2: "GG_E_NOMEM", 3: "GG_E_HIP", 4: "GG_E_CA
 EXPORTS = ["gg_create", "gg_step", "gg_sync", "gg_grain_count", "gg_grain_volumes", "gg_labels",
            "gg_stats", "gg_get_boxes", "gg_get_values", "gg_get_iota", "gg_load_state",
            "gg_keep_intermediates", "gg_get_intermediate", "gg_status_str", "gg_last_error",
-           "gg_destroy", "gg_version"]
+           "gg_destroy", "gg_version", "gg_profile", "gg_get_kernel_times"]
+
+KERNEL_CLASSES = ["conv_xy", "conv_z", "compare", "reinit_xy", "reinit_z", "plan", "volume", "unused"]
 
 
 class GGError(RuntimeError):
@@ -40,8 +42,13 @@ class Config(C.Structure):
                 ("capacity_headroom", C.c_double)]
 
 
+class KernelTimes(C.Structure):
+    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8), ("voxels", C.c_int64 * 8)]
+
+
 class StepStats(C.Structure):
-    _fields_ = [("steps", C.c_int64), ("alive", C.c_int32), ("kernel_radius", C.c_int32),
+    _fields_ = [("steps", C.c_int64), ("total_grain_voxels", C.c_int64), ("alive", C.c_int32),
+                ("kernel_radius", C.c_int32),
                 ("grain_voxels", C.c_int64), ("capacity", C.c_int64),
                 ("superposition", C.c_double), ("last_step_ms", C.c_double)]
 
@@ -76,6 +83,8 @@ def load_library(path=LIB_PATH):
         "gg_last_error": (C.c_char_p, [vp]),
         "gg_destroy": (None, [vp]),
         "gg_version": (C.c_char_p, []),
+        "gg_profile": (i32, [vp, i32]),
+        "gg_get_kernel_times": (i32, [vp, C.POINTER(KernelTimes)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -171,6 +180,16 @@ class Simulation:
         s = StepStats()
         self._check(self._lib.gg_stats(self._h, C.byref(s)))
         return {f: getattr(s, f) for f, _ in StepStats._fields_}
+
+    def profile(self, on=True):
+        """Per-kernel HIP-event timing on the simulation's stream (resets the sums)."""
+        self._check(self._lib.gg_profile(self._h, int(bool(on))))
+
+    def kernel_times(self):
+        t = KernelTimes()
+        self._check(self._lib.gg_get_kernel_times(self._h, C.byref(t)))
+        return {name: dict(ms=t.ms[i], launches=t.launches[i], voxels=t.voxels[i])
+                for i, name in enumerate(KERNEL_CLASSES) if name != "unused"}
 
     def boxes(self):
         lo = np.zeros((self.G, 3), np.int32)
