@@ -10,7 +10,7 @@
  *
  * The step (Algorithm 1 of the paper: predictor, corrector, re-initialization):
  *   1. predictor  (sec. 2.1.4, Eqs. Heatequation/Gaussian/solution):
- *        psi_k = G_sigma * phi_k, separable, x then y then z, taps
+ *        psi_k = G_sigma * phi_k, separable (passes z, x, y in 3D; x, y in 2D), taps
  *        g_i = exp(-i^2 / (2 sigma^2)) / sum_j exp(-j^2 / (2 sigma^2)), |i| <= R,
  *        R = ceil(4 sigma), sigma = sqrt(2 dt) * n voxels (heat kernel variance
  *        2t per axis); samples outside the box read -W;
@@ -129,18 +129,20 @@ static void conv_axis(const double *in, double *out, const int *e, const int *n,
             }
 }
 
-/* Gaussian predictor on one box: x, then y, then z (3D). */
+/* Gaussian predictor on one box.  The kernel is a product of 1D kernels, so
+ * the passes commute; they are applied z (3D), then x, then y. */
 static void predictor_box(int dim, const int *n, double W, const int *e, const double *f,
                           double *out, const double *taps, int R) {
     long m = nvox(e);
     double *t1 = (double *)malloc(sizeof(double) * m);
-    conv_axis(f, t1, e, n, 0, taps, R, W);
     if (dim == 2) {
+        conv_axis(f, t1, e, n, 0, taps, R, W);
         conv_axis(t1, out, e, n, 1, taps, R, W);
     } else {
         double *t2 = (double *)malloc(sizeof(double) * m);
-        conv_axis(t1, t2, e, n, 1, taps, R, W);
-        conv_axis(t2, out, e, n, 2, taps, R, W);
+        conv_axis(f, t1, e, n, 2, taps, R, W);
+        conv_axis(t1, t2, e, n, 0, taps, R, W);
+        conv_axis(t2, out, e, n, 1, taps, R, W);
         free(t2);
     }
     free(t1);
