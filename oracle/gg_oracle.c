@@ -29,9 +29,10 @@
  *   5. re-initialization (sec. 2.1.6, the fast "taxicab" scheme): reference
  *      values at voxels next to a sign change, theta = phi(x)/(phi(x)-phi(n))
  *      over face neighbours n of opposite sign, ref = min theta (the exact L1
- *      distance to a locally planar interface); then the L1 distance
- *      min_p ref(p) + |x - p|_1 by three 1D min-plus passes (x, y, z), and
- *      phi = +-min(dist, W) with the sign of phi^c > 0;
+ *      distance to a locally planar interface); then the values are spread
+ *      through the box one voxel at a time (+1 per voxel, forward and backward
+ *      sweeps along x, y, z), which gives the L1 distance min_p ref(p) + |x - p|_1,
+ *      and phi = +-min(dist, W) with the sign of phi^c > 0;
  *   6. volume V_k = sum over the box of clamp(phi + 1/2, 0, 1).
  *
  * Sampling rule (periodic grid): global voxel g is covered by box k iff
@@ -148,14 +149,51 @@ static void predictor_box(int dim, const int *n, double W, const int *e, const d
     free(t1);
 }
 
-/* Re-initialization on one box: exact L1 reference values next to the sign
- * change, spread by three 1D min-plus passes (x, y, z). */
+/* One axis of the L1 spreading on a box: along every line the distance grows
+ * by one per voxel travelled, carried forward then backward.  A line that spans
+ * a whole periodic axis is a ring: each direction goes around it twice, so that
+ * paths across the periodic seam are included. */
+static void sweep_axis(double *d, const int *e, const int *n, int a) {
+    const int len = e[a];
+    const long stride = a == 0 ? 1 : (a == 1 ? (long)e[0] : (long)e[0] * e[1]);
+    const int o1 = a == 0 ? 1 : 0, o2 = a == 2 ? 1 : 2; /* the two other axes */
+    for (int v = 0; v < e[o2]; v++)
+        for (int u = 0; u < e[o1]; u++) {
+            int c[3] = {0, 0, 0};
+            c[o1] = u;
+            c[o2] = v;
+            double *line = d + lidx(e, c[0], c[1], c[2]);
+            if (len == n[a]) {
+                for (int t = 1; t < 2 * len; t++) {
+                    const int i = t % len, p = (t - 1) % len;
+                    const double w = line[p * stride] + 1.0;
+                    if (w < line[i * stride]) line[i * stride] = w;
+                }
+                for (int t = 1; t < 2 * len; t++) {
+                    const int i = wrapi((long)len - 1 - t, len), p = (i + 1) % len;
+                    const double w = line[p * stride] + 1.0;
+                    if (w < line[i * stride]) line[i * stride] = w;
+                }
+            } else {
+                for (int i = 1; i < len; i++) {
+                    const double w = line[(i - 1) * stride] + 1.0;
+                    if (w < line[i * stride]) line[i * stride] = w;
+                }
+                for (int i = len - 2; i >= 0; i--) {
+                    const double w = line[(i + 1) * stride] + 1.0;
+                    if (w < line[i * stride]) line[i * stride] = w;
+                }
+            }
+        }
+}
+
+/* Re-initialization on one box (sec. 2.1.6): exact distances at the voxels
+ * next to the sign change, then spread along x, y (and z), one voxel per step;
+ * the result is min over reference voxels p of ref(p) + |x - p|_1. */
 static void redistance_box(int dim, const int *n, double W, const int *e, const double *f,
                            double *out) {
     long m = nvox(e);
-    int K = (int)ceil(W);
     double *ref = (double *)malloc(sizeof(double) * m);
-    double *tmp = (double *)malloc(sizeof(double) * m);
     for (int z = 0; z < e[2]; z++)
         for (int y = 0; y < e[1]; y++)
             for (int x = 0; x < e[0]; x++) {
@@ -174,30 +212,12 @@ static void redistance_box(int dim, const int *n, double W, const int *e, const 
                     }
                 ref[lidx(e, x, y, z)] = r;
             }
-    double *src = ref, *dst = tmp;
-    for (int a = 0; a < dim; a++) {
-        for (int z = 0; z < e[2]; z++)
-            for (int y = 0; y < e[1]; y++)
-                for (int x = 0; x < e[0]; x++) {
-                    double best = INFINITY;
-                    for (int i = -K; i <= K; i++) {
-                        long c[3] = {x, y, z};
-                        c[a] += i;
-                        double t = sample(src, e, n, c[0], c[1], c[2], INFINITY) + (double)abs(i);
-                        if (t < best) best = t;
-                    }
-                    dst[lidx(e, x, y, z)] = best;
-                }
-        double *sw = src;
-        src = dst;
-        dst = sw;
-    }
+    for (int a = 0; a < dim; a++) sweep_axis(ref, e, n, a);
     for (long v = 0; v < m; v++) {
-        double d = fmin(src[v], W);
+        double d = fmin(ref[v], W);
         out[v] = f[v] > 0.0 ? d : -d;
     }
     free(ref);
-    free(tmp);
 }
 
 static double volume_box(const double *phi, long m) {

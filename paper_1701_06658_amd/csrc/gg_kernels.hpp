@@ -2,15 +2,24 @@
 //
 // Data layout in HBM: every alive grain's box is stored contiguously, x
 // fastest, in grain-id order ("packed arena"); a box table (lo, ext, alive,
-// offset) per layout describes it.  All per-voxel work is expressed as work
-// items over boxes (predictor, re-initialization) or over fixed tiles of the
-// global grid (corrector, labels); per-item grain lookups are O(1) maps.
+// offset) per layout describes it.  Per-voxel work is expressed as work items
+// over boxes (predictor, re-initialization) or over fixed tiles of the global
+// grid (corrector, labels); per-item grain lookups are O(1) maps.
 //
-// Stencil kernels stage one output tile plus its halo in LDS, so every HBM
-// value of a box plane is read once per pass and written once.  Along an axis
-// a box is either the whole periodic axis (indices wrap) or at most n - 2P long
-// (indices outside the box read the fill value): a stencil of reach <= 2P then
-// never wraps into a partial box.
+// One step is four sweeps over the packed boxes:
+//   k_compare    psi            -> phi^c   (global tiles, top-2 of the covering grains)
+//   k_reinit_xy  phi^c (old box) -> d      (reference values, x and y min-plus, new box)
+//   k_zfused     d              -> t, phi  (z min-plus, band clamp, volume, predictor z pass)
+//   k_conv_xy    t              -> psi     (predictor x and y passes, correction epilogue)
+// The separable Gaussian is applied z, x, y so that its z pass can share the
+// z-line sweep of the re-initialization.
+//
+// Stencil kernels stage one output tile plus its halo in LDS and read every HBM
+// value of their tile once; each thread produces KB consecutive outputs along
+// the stencil axis from a register window.  Along an axis a box is either the
+// whole periodic axis (indices wrap) or at most n - 2P long (indices outside
+// the box read the fill value): a stencil of reach <= 2P never wraps into a
+// partial box.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,11 +28,12 @@
 namespace gg {
 
 constexpr int kBlock = 256;       // threads per work group of the stencil/tile kernels
-constexpr int kLdsBytes = 61440;  // dynamic LDS budget per work group (stays below 64 KB)
+constexpr int kLdsBytes = 32768;  // dynamic LDS budget per work group
+constexpr int kKB = 4;            // outputs per thread along a stencil axis
 constexpr int kMaxRadius = 24;    // largest Gaussian radius R
 constexpr int kMaxBand = 16;      // largest band half width W
-constexpr int kKinds = 4;         // item kinds: predictor xy, predictor z, reinit xy, reinit z
-enum { KIND_CXY = 0, KIND_CZ = 1, KIND_RXY = 2, KIND_RZ = 3 };
+constexpr int kKinds = 4;         // item kinds: predictor xy, predictor z, reinit xy, fused z
+enum { KIND_CXY = 0, KIND_CZ = 1, KIND_RXY = 2, KIND_ZF = 3 };
 
 // Box table of one layout.
 struct Boxes {
@@ -33,18 +43,11 @@ struct Boxes {
     long long *off;  // G + 1: exclusive prefix of box volumes
 };
 
-// Work items of one layout: per kind, prefix counts over grains (G + 1) and the
-// item -> grain map.
-struct Items {
-    long long *pref[kKinds];
-    int *owner[kKinds];
-};
-
 struct Totals {
-    long long arena;      // sum of box volumes
+    long long arena;        // sum of box volumes
     long long items[kKinds];
-    long long cov;        // coverage list entries
-    long long alive;      // alive grains
+    long long cov;          // coverage list entries
+    long long alive;        // alive grains
     long long lds[kKinds];  // largest LDS need of any item, in values
 };
 
@@ -55,37 +58,44 @@ __host__ __device__ inline int imod(long long v, int N) {
     return (int)(r < 0 ? r + N : r);
 }
 
-// Local index along an axis for a stencil read at local coordinate c: a whole
-// axis wraps, a partial box clips (-1 = outside).
-__device__ inline int axis_map(int c, int e, int N) {
-    if (e == N) {
-        int r = c % N;
-        return r < 0 ? r + N : r;
-    }
+// Local index along an axis for a stencil read at local coordinate c, with
+// -N < c < 2N: a whole axis wraps, a partial box clips (-1 = outside).
+__device__ __forceinline__ int axis_map(int c, int e, int N) {
+    if (e == N) return c < 0 ? c + N : (c >= N ? c - N : c);
     return (c >= 0 && c < e) ? c : -1;
+}
+
+// (a - b) mod N for a, b in [0, N).
+__device__ __forceinline__ int wrap_diff(int a, int b, int N) {
+    const int d = a - b;
+    return d < 0 ? d + N : d;
 }
 
 template <typename T> constexpr int lds_budget() { return kLdsBytes / (int)sizeof(T); }
 
-template <typename T> __device__ inline T mac(T acc, T a, T b);
-template <> __device__ inline double mac<double>(double acc, double a, double b) {
+template <typename T> __device__ __forceinline__ T mac(T acc, T a, T b);
+template <> __device__ __forceinline__ double mac<double>(double acc, double a, double b) {
     return acc + a * b;  // built without contraction: product and sum rounded separately
 }
-template <> __device__ inline float mac<float>(float acc, float a, float b) {
+template <> __device__ __forceinline__ float mac<float>(float acc, float a, float b) {
     return __builtin_fmaf(a, b, acc);
 }
 
-template <typename T> __device__ inline T tinf();
-template <> __device__ inline double tinf<double>() { return __builtin_inf(); }
-template <> __device__ inline float tinf<float>() { return __builtin_inff(); }
+template <typename T> __device__ __forceinline__ T tinf();
+template <> __device__ __forceinline__ double tinf<double>() { return __builtin_inf(); }
+template <> __device__ __forceinline__ float tinf<float>() { return __builtin_inff(); }
 
-// LDS values needed by an output tile tx * ty with halo h.
-__host__ __device__ inline long long lds_need(int kind, int tx, int ty, int h) {
-    if (kind == KIND_CXY) return (long long)(tx + 2 * h) * (ty + 2 * h) + (long long)tx * (ty + 2 * h);
+// LDS values needed by an output tile tx * ty; h is the halo along both tile
+// axes (fused z kind: h = K, h2 = R along z).
+__host__ __device__ inline long long lds_need(int kind, int tx, int ty, int h, int h2) {
+    if (kind == KIND_CXY)
+        return (long long)((tx + 2 * h) | 1) * (ty + 2 * h) + kKB + (long long)tx * (ty + 2 * h + kKB);
     if (kind == KIND_RXY)
-        return (long long)(tx + 2 * h + 2) * (ty + 2 * h + 2) + (long long)(tx + 2 * h) * (ty + 2 * h) +
-               (long long)tx * (ty + 2 * h);
-    return (long long)tx * (ty + 2 * h);  // z passes: tx lines of ty + 2h planes
+        return (long long)((tx + 2 * h + 2) | 1) * (ty + 2 * h + 2) + (long long)((tx + 2 * h) | 1) * (ty + 2 * h) +
+               kKB + (long long)tx * (ty + 2 * h + kKB);
+    if (kind == KIND_ZF)
+        return (long long)tx * (ty + 2 * (h + h2) + kKB) + (long long)tx * (ty + 2 * h2 + kKB);
+    return (long long)tx * (ty + 2 * h);  // prologue z pass
 }
 
 struct Tiling {
@@ -94,25 +104,15 @@ struct Tiling {
 
 // Split a box cross-section ex * ey (second axis y for xy kernels, z for z
 // kernels) into the fewest near-equal tiles whose LDS need fits the budget.
-__host__ __device__ inline Tiling choose_tiling(int kind, int ex, int ey, int h, int budget) {
+__host__ __device__ inline Tiling choose_tiling(int kind, int ex, int ey, int h, int h2, int budget) {
     Tiling t = {0, 0, 0, 0};
     for (int nxs = (ex + 127) / 128; nxs <= ex; ++nxs) {
-        int tx = (ex + nxs - 1) / nxs;
-        long long a, b;  // lds_need = a * ty + b
-        if (kind == KIND_CXY) {
-            a = 2LL * tx + 2 * h;
-            b = a * 2 * h;
-        } else if (kind == KIND_RXY) {
-            long long p = tx + 2 * h + 2, q = tx + 2 * h, r = tx;
-            a = p + q + r;
-            b = p * (2 * h + 2) + (q + r) * 2 * h;
-        } else {
-            a = tx;
-            b = (long long)tx * 2 * h;
-        }
-        long long tymax = (budget - b) / a;
-        if (tymax < 1) continue;
-        int nys = (int)((ey + tymax - 1) / tymax);
+        const int tx = (ex + nxs - 1) / nxs;
+        const int b = (int)lds_need(kind, tx, 0, h, h2);  // the need is affine in ty
+        const int a = (int)lds_need(kind, tx, 1, h, h2) - b;
+        if (budget - b < a) continue;
+        const int tymax = (budget - b) / a;
+        const int nys = (ey + tymax - 1) / tymax;
         t.nxs = nxs;
         t.nys = nys;
         t.tx = tx;
@@ -122,14 +122,64 @@ __host__ __device__ inline Tiling choose_tiling(int kind, int ex, int ey, int h,
     return t;  // infeasible: nxs == 0
 }
 
+__host__ __device__ inline void kind_halos(int kind, int R, int K, int *h, int *h2) {
+    *h = (kind == KIND_CXY || kind == KIND_CZ) ? R : K;
+    *h2 = kind == KIND_ZF ? R : 0;
+}
+
+__host__ __device__ inline Tiling kind_tiling(int kind, const int *e, int R, int K, int budget) {
+    int h, h2;
+    kind_halos(kind, R, K, &h, &h2);
+    const int ey = (kind == KIND_CXY || kind == KIND_RXY) ? e[1] : e[2];
+    return choose_tiling(kind, e[0], ey, h, h2, budget);
+}
+
 // Number of work items of one kind for a box.
-__host__ __device__ inline long long kind_items(int kind, const int *e, int h, int budget) {
-    if (kind == KIND_CXY || kind == KIND_RXY) {
-        Tiling t = choose_tiling(kind, e[0], e[1], h, budget);
-        return (long long)e[2] * t.nxs * t.nys;
-    }
-    Tiling t = choose_tiling(kind, e[0], e[2], h, budget);
-    return (long long)e[1] * t.nxs * t.nys;
+__host__ __device__ inline long long kind_items(int kind, const int *e, int R, int K, int budget) {
+    const Tiling t = kind_tiling(kind, e, R, K, budget);
+    const int planes = (kind == KIND_CXY || kind == KIND_RXY) ? e[2] : e[1];
+    return (long long)planes * t.nxs * t.nys;
+}
+
+// Work groups are dealt round-robin to the 8 XCDs of the chip (each with its
+// own L2).  Launches use a grid of 8 * ceil(n / 8) groups and give every XCD a
+// contiguous run of items, so that neighbouring planes of a box, or
+// neighbouring tiles of the grid, are processed by the same L2.
+constexpr int kXcds = 8;
+__host__ __device__ inline long long xcd_grid(long long n) { return kXcds * ((n + kXcds - 1) / kXcds); }
+__device__ __forceinline__ long long xcd_item(long long n) {
+    const long long chunk = (n + kXcds - 1) / kXcds;
+    const long long b = blockIdx.x;
+    return (b % kXcds) * chunk + b / kXcds;
+}
+
+// Work item -> (grain, plane, tile origin, tile size).
+struct ItemTile {
+    long long item;
+    int k, plane, x0, y0, wx, wy;
+};
+
+// The tiling of every grain and kind is computed once per layout (k_item_counts)
+// and stored as int4 (nxs, nys, tx, ty).
+__device__ __forceinline__ ItemTile decode_item(long long item, int kind, const Boxes &L, const int *owner,
+                                                const long long *pref, const int4 *tilings) {
+    ItemTile it;
+    it.item = item;
+    it.k = owner[item];
+    const int sub = (int)(item - pref[it.k]);
+    const int e[3] = {L.ext[3 * it.k], L.ext[3 * it.k + 1], L.ext[3 * it.k + 2]};
+    const int4 t4 = tilings[it.k];
+    const Tiling tl = {t4.x, t4.y, t4.z, t4.w};
+    const int per = tl.nxs * tl.nys;
+    it.plane = sub / per;
+    const int rem = sub - it.plane * per;
+    const int ys = rem / tl.nxs, xs = rem - ys * tl.nxs;
+    it.x0 = xs * tl.tx;
+    it.y0 = ys * tl.ty;
+    const int ey = (kind == KIND_CXY || kind == KIND_RXY) ? e[1] : e[2];
+    it.wx = min(tl.tx, e[0] - it.x0);
+    it.wy = min(tl.ty, ey - it.y0);
+    return it;
 }
 
 __device__ inline double block_sum(double v, double *scratch) {
@@ -151,6 +201,100 @@ __device__ inline int wave_min(int v) {
 __device__ inline int wave_max(int v) {
     for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
     return v;
+}
+
+// 1D Gaussian pass over KB consecutive outputs: acc[q] = sum_t g_t v[q + t],
+// summed in increasing t from 0.  Static radius: register window; RS == 0:
+// runtime radius read from `taps`.
+template <typename T, int RS>
+__device__ __forceinline__ void gauss_run(const T *src, int stride, const T *tp, const T *taps, int R, T acc[kKB]) {
+#pragma unroll
+    for (int q = 0; q < kKB; ++q) acc[q] = T(0);
+    if constexpr (RS > 0) {
+#pragma unroll
+        for (int i = 0; i < 2 * RS + kKB; ++i) {
+            const T v = src[i * stride];
+#pragma unroll
+            for (int q = 0; q < kKB; ++q) {
+                const int t = i - q;
+                if (t >= 0 && t <= 2 * RS) acc[q] = mac<T>(acc[q], tp[t], v);
+            }
+        }
+    } else {
+        for (int t = 0; t <= 2 * R; ++t) {
+            const T g = taps[t];
+#pragma unroll
+            for (int q = 0; q < kKB; ++q) acc[q] = mac<T>(acc[q], g, src[(q + t) * stride]);
+        }
+    }
+}
+
+// 1D min-plus pass over KB consecutive outputs: best[q] = min_t |v[q + t]| + |t - K|.
+template <typename T, int KS>
+__device__ __forceinline__ void minplus_run(const T *src, int stride, int K, T best[kKB], bool magnitude) {
+#pragma unroll
+    for (int q = 0; q < kKB; ++q) best[q] = tinf<T>();
+    if constexpr (KS > 0) {
+#pragma unroll
+        for (int i = 0; i < 2 * KS + kKB; ++i) {
+            T v = src[i * stride];
+            if (magnitude) v = fabs(v);
+#pragma unroll
+            for (int q = 0; q < kKB; ++q) {
+                const int t = i - q;
+                if (t >= 0 && t <= 2 * KS) {
+                    const T c = v + T(t < KS ? KS - t : t - KS);
+                    if (c < best[q]) best[q] = c;
+                }
+            }
+        }
+    } else {
+        for (int t = 0; t <= 2 * K; ++t) {
+            const T d = T(t < K ? K - t : t - K);
+#pragma unroll
+            for (int q = 0; q < kKB; ++q) {
+                T v = src[(q + t) * stride];
+                if (magnitude) v = fabs(v);
+                const T c = v + d;
+                if (c < best[q]) best[q] = c;
+            }
+        }
+    }
+}
+
+// Stage a W x H tile into LDS (row pitch `pitch`).  Element (rr, cc) is
+// src[rowbase(rr) + colidx(cc)], or `fill` when either is negative.  Waves own
+// rows (the row mapping is wave-uniform), lanes own columns (the column mapping
+// is computed once per lane), and each lane issues kLoadBatch independent loads
+// before it stores any of them, so that enough bytes are in flight to cover
+// HBM latency.
+constexpr int kLoadBatch = 8;
+constexpr int kWaves = kBlock / 64;
+
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+template <typename T, typename RowF, typename ColF>
+__device__ __forceinline__ void stage_rows(T *lds, int pitch, int W, int H, const T *__restrict__ src, RowF rowbase,
+                                           ColF colidx, T fill) {
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    for (int c0 = 0; c0 < W; c0 += 64) {
+        const int cc = c0 + lane;
+        const int ci = cc < W ? colidx(cc) : -1;
+        for (int r0 = wave; r0 < H; r0 += kWaves * kLoadBatch) {
+            T v[kLoadBatch];
+#pragma unroll
+            for (int j = 0; j < kLoadBatch; ++j) {
+                const int rr = r0 + kWaves * j;
+                const long long rb = rr < H ? rowbase(rr) : -1;
+                v[j] = (rb >= 0 && ci >= 0) ? src[rb + ci] : fill;
+            }
+#pragma unroll
+            for (int j = 0; j < kLoadBatch; ++j) {
+                const int rr = r0 + kWaves * j;
+                if (rr < H && cc < W) lds[rr * pitch + cc] = v[j];
+            }
+        }
+    }
 }
 
 // ------------------------------------------------ predictor correction terms
@@ -189,12 +333,13 @@ template <typename T> __device__ inline T misorientation_deg(const T *qa, const 
     const T c6[6] = {T(1), T(0.86602540378443864676), T(0.5), T(0), T(-0.5), T(-0.86602540378443864676)};
     const T s6[6] = {T(0), T(0.5), T(0.86602540378443864676), T(1), T(0.86602540378443864676), T(0.5)};
     T best = 0;
+#pragma unroll
     for (int k = 0; k < 6; ++k) {
-        T w1 = dw * c6[k] - dz * s6[k];       // rotation about c by 60k degrees
-        T w2 = -dx * c6[k] - dy * s6[k];      // 2-fold axis in the basal plane at 30k degrees
-        T m = w1 < 0 ? -w1 : w1;
-        T m2 = w2 < 0 ? -w2 : w2;
-        best = m > best ? m : best;
+        const T w1 = dw * c6[k] - dz * s6[k];   // rotation about c by 60k degrees
+        const T w2 = -dx * c6[k] - dy * s6[k];  // 2-fold axis in the basal plane at 30k degrees
+        const T m1 = w1 < 0 ? -w1 : w1;
+        const T m2 = w2 < 0 ? -w2 : w2;
+        best = m1 > best ? m1 : best;
         best = m2 > best ? m2 : best;
     }
     if (best > T(1)) best = T(1);
@@ -207,12 +352,12 @@ template <typename T> __device__ inline T pair_weight(T theta, T theta_c, T *mob
     if (theta >= theta_c) g = T(1);
     else if (theta <= T(0)) g = T(0);
     else {
-        T r = theta / theta_c;
+        const T r = theta / theta_c;
         g = r * (T(1) - dev_log(r));
     }
-    T u = theta / T(15);
-    T u3 = u * u * u;
-    T mu = T(1) - T(0.99) * dev_exp(T(-5) * (u3 * u3 * u3));
+    const T u = theta / T(15);
+    const T u3 = u * u * u;
+    const T mu = T(1) - T(0.99) * dev_exp(T(-5) * (u3 * u3 * u3));
     *mob = mu;
     return mu * g;
 }
@@ -224,8 +369,7 @@ template <typename T> struct PairCache {
 
 // d^p = phi + w (psi - phi) + mob (E_j - E_k) * bulk_scale, clamped to [-W, W].
 template <typename T>
-__device__ inline T correct_prediction(const Physics<T> &ph, int k, long long idx, T psi, T W,
-                                       PairCache<T> &pc) {
+__device__ inline T correct_prediction(const Physics<T> &ph, int k, long long idx, T psi, T W, PairCache<T> &pc) {
     const int j = ph.iota[idx];
     if (j != pc.j) {
         pc.j = j;
@@ -234,7 +378,7 @@ __device__ inline T correct_prediction(const Physics<T> &ph, int k, long long id
         if (j >= 0) {
             T mob = 1;
             if (ph.mode & 1) {
-                T th = misorientation_deg<T>(ph.quat + 4LL * k, ph.quat + 4LL * j);
+                const T th = misorientation_deg<T>(ph.quat + 4LL * k, ph.quat + 4LL * j);
                 pc.w = pair_weight<T>(th, ph.theta_c_deg, &mob);
             }
             if (ph.mode & 2) pc.b = mob * (ph.energy[j] - ph.energy[k]) * ph.bulk_scale;
@@ -254,97 +398,100 @@ struct GridArgs {
     int dim;
 };
 
-// x and y passes of the Gaussian on one tile of one z plane (2D: the whole
-// predictor, with the optional correction epilogue).
-template <typename T>
+// x and y passes of the Gaussian on one tile of one z plane, then the optional
+// correction epilogue; the output is the predicted function psi.
+template <typename T, int RS, bool PH>
 __global__ void __launch_bounds__(kBlock)
     k_conv_xy(Boxes L, const int *__restrict__ owner, const long long *__restrict__ pref,
-              const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ taps, int R, T W,
-              GridArgs g, Physics<T> ph) {
+              const int4 *__restrict__ tilings, long long nitems,
+              const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ taps, int R_, T W, GridArgs g,
+              Physics<T> ph) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
-    const long long item = blockIdx.x;
-    const int k = owner[item];
-    const int sub = (int)(item - pref[k]);
+    const int R = RS ? RS : R_;
+    const long long item = xcd_item(nitems);
+    if (item >= nitems) return;
+    const ItemTile it = decode_item(item, KIND_CXY, L, owner, pref, tilings);
+    const int k = it.k, z = it.plane, x0 = it.x0, y0 = it.y0, wx = it.wx, wy = it.wy;
     const int ex = L.ext[3 * k], ey = L.ext[3 * k + 1];
-    const Tiling tl = choose_tiling(KIND_CXY, ex, ey, R, lds_budget<T>());
-    const int per_z = tl.nxs * tl.nys;
-    const int z = sub / per_z, rem = sub - z * per_z, ys = rem / tl.nxs, xs = rem - ys * tl.nxs;
-    const int x0 = xs * tl.tx, y0 = ys * tl.ty;
-    const int wx = min(tl.tx, ex - x0), wy = min(tl.ty, ey - y0);
-    const int RW = wx + 2 * R, RH = wy + 2 * R;
+    const int RW = wx + 2 * R, RP = RW | 1, RH = wy + 2 * R;
     const long long base = L.off[k] + (long long)z * ex * ey;
-    const T *src = in + base;
-    T *raw = sm, *xp = sm + RW * RH;
-    for (int e = threadIdx.x; e < RW * RH; e += kBlock) {
-        const int rr = e / RW, cc = e - rr * RW;
-        const int yy = axis_map(y0 - R + rr, ey, g.n[1]);
-        const int xx = axis_map(x0 - R + cc, ex, g.n[0]);
-        raw[e] = (yy >= 0 && xx >= 0) ? src[(long long)yy * ex + xx] : -W;
+    T *raw = sm, *xp = sm + RH * RP + kKB;
+    T tp[RS > 0 ? 2 * RS + 1 : 1];
+    if constexpr (RS > 0) {
+#pragma unroll
+        for (int t = 0; t <= 2 * RS; ++t) tp[t] = taps[t];
     }
+    stage_rows<T>(
+        raw, RP, RW, RH, in,
+        [&](int rr) -> long long {
+            const int yy = axis_map(y0 - R + rr, ey, g.n[1]);
+            return yy >= 0 ? base + (long long)yy * ex : -1;
+        },
+        [&](int cc) { return axis_map(x0 - R + cc, ex, g.n[0]); }, -W);
     __syncthreads();
-    for (int e = threadIdx.x; e < wx * RH; e += kBlock) {
-        const int rr = e / wx, c = e - rr * wx;
-        T acc;
+    const int ngx = (wx + kKB - 1) / kKB;
+    for (int e = threadIdx.x; e < ngx * RH; e += kBlock) {
+        const int rr = e % RH, c0 = (e / RH) * kKB;
+        T acc[kKB];
         if (axis_map(y0 - R + rr, ey, g.n[1]) < 0) {
-            acc = -W;  // rows outside the box read the fill value in the y pass
+#pragma unroll
+            for (int q = 0; q < kKB; ++q) acc[q] = -W;  // rows outside the box read the fill value
         } else {
-            acc = 0;
-            const T *rp = raw + rr * RW + c;
-            for (int i = 0; i <= 2 * R; ++i) acc = mac<T>(acc, taps[i], rp[i]);
+            gauss_run<T, RS>(raw + rr * RP + c0, 1, tp, taps, R, acc);
         }
-        xp[e] = acc;
+#pragma unroll
+        for (int q = 0; q < kKB; ++q)
+            if (c0 + q < wx) xp[rr * wx + c0 + q] = acc[q];
     }
     __syncthreads();
-    T *dst = out + base;
+    const int ngy = (wy + kKB - 1) / kKB;
     PairCache<T> pc;
-    for (int e = threadIdx.x; e < wx * wy; e += kBlock) {
-        const int r = e / wx, c = e - r * wx;
-        T acc = 0;
-        const T *cp = xp + r * wx + c;
-        for (int j = 0; j <= 2 * R; ++j) acc = mac<T>(acc, taps[j], cp[j * wx]);
-        const long long idx = (long long)(y0 + r) * ex + x0 + c;
-        if (g.dim == 2 && ph.mode) acc = correct_prediction<T>(ph, k, base + idx, acc, W, pc);
-        dst[idx] = acc;
+    for (int e = threadIdx.x; e < ngy * wx; e += kBlock) {
+        const int c = e % wx, r0 = (e / wx) * kKB;
+        T acc[kKB];
+        gauss_run<T, RS>(xp + r0 * wx + c, wx, tp, taps, R, acc);
+#pragma unroll
+        for (int q = 0; q < kKB; ++q) {
+            if (r0 + q >= wy) break;
+            const long long idx = base + (long long)(y0 + r0 + q) * ex + x0 + c;
+            T v = acc[q];
+            if constexpr (PH) v = correct_prediction<T>(ph, k, idx, v, W, pc);
+            out[idx] = v;
+        }
     }
 }
 
-// z pass of the Gaussian on one tile (x chunk * z range) of one y row, with the
-// optional correction epilogue.
+// Predictor z pass on its own (first step after create / load / a new dt).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_conv_z(Boxes L, const int *__restrict__ owner, const long long *__restrict__ pref,
-             const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ taps, int R, T W,
-             GridArgs g, Physics<T> ph) {
+             const int4 *__restrict__ tilings, long long nitems,
+             const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ taps, int R, T W, GridArgs g) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *col = reinterpret_cast<T *>(smem_raw);
-    const long long item = blockIdx.x;
-    const int k = owner[item];
-    const int sub = (int)(item - pref[k]);
+    const long long item = xcd_item(nitems);
+    if (item >= nitems) return;
+    const ItemTile it = decode_item(item, KIND_CZ, L, owner, pref, tilings);
+    const int k = it.k, y = it.plane, x0 = it.x0, z0 = it.y0, wx = it.wx, wz = it.wy;
     const int ex = L.ext[3 * k], ey = L.ext[3 * k + 1], ez = L.ext[3 * k + 2];
-    const Tiling tl = choose_tiling(KIND_CZ, ex, ez, R, lds_budget<T>());
-    const int per_y = tl.nxs * tl.nys;
-    const int y = sub / per_y, rem = sub - y * per_y, zs = rem / tl.nxs, xs = rem - zs * tl.nxs;
-    const int x0 = xs * tl.tx, z0 = zs * tl.ty;
-    const int wx = min(tl.tx, ex - x0), wz = min(tl.ty, ez - z0);
     const int CH = wz + 2 * R;
     const long long plane = (long long)ex * ey;
     const long long rowbase = L.off[k] + (long long)y * ex + x0;
-    for (int e = threadIdx.x; e < wx * CH; e += kBlock) {
-        const int rr = e / wx, c = e - rr * wx;
-        const int zz = axis_map(z0 - R + rr, ez, g.n[2]);
-        col[e] = zz >= 0 ? in[rowbase + zz * plane + c] : -W;
-    }
+    stage_rows<T>(
+        col, wx, wx, CH, in,
+        [&](int rr) -> long long {
+            const int zz = axis_map(z0 - R + rr, ez, g.n[2]);
+            return zz >= 0 ? rowbase + zz * plane : -1;
+        },
+        [&](int c) { return c; }, -W);
     __syncthreads();
-    PairCache<T> pc;
     for (int e = threadIdx.x; e < wx * wz; e += kBlock) {
         const int r = e / wx, c = e - r * wx;
         T acc = 0;
         const T *cp = col + r * wx + c;
         for (int j = 0; j <= 2 * R; ++j) acc = mac<T>(acc, taps[j], cp[j * wx]);
-        const long long idx = rowbase + (long long)(z0 + r) * plane + c;
-        if (ph.mode) acc = correct_prediction<T>(ph, k, idx, acc, W, pc);
-        out[idx] = acc;
+        out[rowbase + (long long)(z0 + r) * plane + c] = acc;
     }
 }
 
@@ -388,10 +535,12 @@ constexpr int kVpt = kTileVox / kBlock;
 // mode 0: corrector; mode 1: ID-field only (argmax of the others' values).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-    k_compare(Boxes L, const int *__restrict__ cov_off, const int *__restrict__ cov_list,
-              const T *__restrict__ psi, T *__restrict__ phic, int *__restrict__ iota_out, int *bmin,
-              int *bmax, unsigned *occ, TileArgs ta, T W, int mode) {
-    const int tile = blockIdx.x;
+    k_compare(Boxes L, const int *__restrict__ cov_off, const int *__restrict__ cov_list, const T *__restrict__ psi,
+              T *__restrict__ phic, int *__restrict__ iota_out, int *bmin, int *bmax, unsigned *occ, TileArgs ta,
+              T W, int mode) {
+    const int ntiles = ta.nt[0] * ta.nt[1] * ta.nt[2];
+    const int tile = (int)xcd_item(ntiles);
+    if (tile >= ntiles) return;
     const int tx = tile % ta.nt[0], ty = (tile / ta.nt[0]) % ta.nt[1], tz = tile / (ta.nt[0] * ta.nt[1]);
     const int tvol = ta.t[0] * ta.t[1] * ta.t[2];
     int gx[kVpt], gy[kVpt], gz[kVpt];
@@ -409,18 +558,35 @@ __global__ void __launch_bounds__(kBlock)
     Top2<T> top[kVpt];
 #pragma unroll
     for (int i = 0; i < kVpt; ++i) top[i].init();
-    for (int c = b; c < e; ++c) {
-        const int j = cov_list[c];
-        const int lx0 = L.lo[3 * j], ly0 = L.lo[3 * j + 1], lz0 = L.lo[3 * j + 2];
-        const int ex = L.ext[3 * j], ey = L.ext[3 * j + 1], ez = L.ext[3 * j + 2];
-        const long long off = L.off[j];
+    constexpr int U = 4;  // grains per batch: their loads are issued together
+    for (int c0 = b; c0 < e; c0 += U) {
+        T v[U][kVpt];
+        int jj[U];
+        bool hit[U][kVpt];
 #pragma unroll
-        for (int i = 0; i < kVpt; ++i) {
-            const int lx = imod(gx[i] - lx0, ta.n[0]), ly = imod(gy[i] - ly0, ta.n[1]),
-                      lz = imod(gz[i] - lz0, ta.n[2]);
-            if (valid[i] && lx < ex && ly < ey && lz < ez)
-                top[i].push(psi[off + lx + (long long)ex * (ly + (long long)ey * lz)], j);
+        for (int u = 0; u < U; ++u) {
+            const int c = c0 + u;
+            jj[u] = c < e ? cov_list[c] : -1;
+#pragma unroll
+            for (int i = 0; i < kVpt; ++i) hit[u][i] = false;
+            if (jj[u] < 0) continue;
+            const int j = jj[u];
+            const int lx0 = L.lo[3 * j], ly0 = L.lo[3 * j + 1], lz0 = L.lo[3 * j + 2];
+            const int ex = L.ext[3 * j], ey = L.ext[3 * j + 1], ez = L.ext[3 * j + 2];
+            const long long off = L.off[j];
+#pragma unroll
+            for (int i = 0; i < kVpt; ++i) {
+                const int lx = wrap_diff(gx[i], lx0, ta.n[0]), ly = wrap_diff(gy[i], ly0, ta.n[1]),
+                          lz = wrap_diff(gz[i], lz0, ta.n[2]);
+                hit[u][i] = valid[i] && lx < ex && ly < ey && lz < ez;
+                if (hit[u][i]) v[u][i] = psi[off + lx + (long long)ex * (ly + (long long)ey * lz)];
+            }
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int i = 0; i < kVpt; ++i)
+                if (hit[u][i]) top[i].push(v[u][i], jj[u]);
     }
     for (int c = b; c < e; ++c) {
         const int j = cov_list[c];
@@ -430,8 +596,8 @@ __global__ void __launch_bounds__(kBlock)
         int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-1, -1, -1};
 #pragma unroll
         for (int i = 0; i < kVpt; ++i) {
-            const int lx = imod(gx[i] - lx0, ta.n[0]), ly = imod(gy[i] - ly0, ta.n[1]),
-                      lz = imod(gz[i] - lz0, ta.n[2]);
+            const int lx = wrap_diff(gx[i], lx0, ta.n[0]), ly = wrap_diff(gy[i], ly0, ta.n[1]),
+                      lz = wrap_diff(gz[i], lz0, ta.n[2]);
             if (!(valid[i] && lx < ex && ly < ey && lz < ez)) continue;
             const long long idx = off + lx + (long long)ex * (ly + (long long)ey * lz);
             const bool first = top[i].i1 == j;
@@ -452,8 +618,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
                     if (e3[a] == ta.n[a])
-                        atomicOr(&occ[((long long)j * 3 + a) * ta.occ_words + (l3[a] >> 5)],
-                                 1u << (l3[a] & 31));
+                        atomicOr(&occ[((long long)j * 3 + a) * ta.occ_words + (l3[a] >> 5)], 1u << (l3[a] & 31));
             }
         }
         if (mode != 0) continue;
@@ -476,8 +641,8 @@ __global__ void __launch_bounds__(kBlock)
 // Voxel labels: argmax over the covering grains (ties to the lowest id).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-    k_labels(Boxes L, const int *__restrict__ cov_off, const int *__restrict__ cov_list,
-             const T *__restrict__ phi, int *__restrict__ labels, TileArgs ta) {
+    k_labels(Boxes L, const int *__restrict__ cov_off, const int *__restrict__ cov_list, const T *__restrict__ phi,
+             int *__restrict__ labels, TileArgs ta) {
     const int tile = blockIdx.x;
     const int tx = tile % ta.nt[0], ty = (tile / ta.nt[0]) % ta.nt[1], tz = tile / (ta.nt[0] * ta.nt[1]);
     const int tvol = ta.t[0] * ta.t[1] * ta.t[2];
@@ -489,8 +654,8 @@ __global__ void __launch_bounds__(kBlock)
         int id = -1;
         for (int c = b; c < e; ++c) {
             const int j = cov_list[c];
-            const int lx = imod(gx - L.lo[3 * j], ta.n[0]), ly = imod(gy - L.lo[3 * j + 1], ta.n[1]),
-                      lz = imod(gz - L.lo[3 * j + 2], ta.n[2]);
+            const int lx = wrap_diff(gx, L.lo[3 * j], ta.n[0]), ly = wrap_diff(gy, L.lo[3 * j + 1], ta.n[1]),
+                      lz = wrap_diff(gz, L.lo[3 * j + 2], ta.n[2]);
             const int ex = L.ext[3 * j], ey = L.ext[3 * j + 1], ez = L.ext[3 * j + 2];
             if (lx < ex && ly < ey && lz < ez) {
                 const T v2 = phi[L.off[j] + lx + (long long)ex * (ly + (long long)ey * lz)];
@@ -510,134 +675,178 @@ __global__ void __launch_bounds__(kBlock)
 // outside the new box or outside the old box the value is -W.
 template <typename T> struct Carry {
     const T *src;
-    int nlo[3], nex[3], olo[3], oex[3];
+    int nex[3], oex[3], d[3], n[3];  // d = (new lo - old lo) mod n
     long long ooff;
-    int n[3];
     T W;
-    __device__ inline long long old_index(int x, int y, int z) const {
-        const int xm = axis_map(x, nex[0], n[0]), ym = axis_map(y, nex[1], n[1]),
-                  zm = axis_map(z, nex[2], n[2]);
+    __device__ __forceinline__ long long old_index(int x, int y, int z) const {
+        const int xm = axis_map(x, nex[0], n[0]), ym = axis_map(y, nex[1], n[1]), zm = axis_map(z, nex[2], n[2]);
         if (xm < 0 || ym < 0 || zm < 0) return -1;
-        const int ox = imod((long long)nlo[0] + xm - olo[0], n[0]);
-        const int oy = imod((long long)nlo[1] + ym - olo[1], n[1]);
-        const int oz = imod((long long)nlo[2] + zm - olo[2], n[2]);
+        int ox = xm + d[0], oy = ym + d[1], oz = zm + d[2];
+        ox -= ox >= n[0] ? n[0] : 0;
+        oy -= oy >= n[1] ? n[1] : 0;
+        oz -= oz >= n[2] ? n[2] : 0;
         if (ox >= oex[0] || oy >= oex[1] || oz >= oex[2]) return -1;
         return ooff + ox + (long long)oex[0] * (oy + (long long)oex[1] * oz);
     }
-    __device__ inline T value(int x, int y, int z) const {
+    __device__ __forceinline__ T value(int x, int y, int z) const {
         const long long i = old_index(x, y, z);
         return i >= 0 ? src[i] : -W;
+    }
+    // Separable form of old_index: old_row(y, z) + old_col(x), each -1 outside.
+    __device__ __forceinline__ long long old_row(int y, int z) const {
+        const int ym = axis_map(y, nex[1], n[1]), zm = axis_map(z, nex[2], n[2]);
+        if (ym < 0 || zm < 0) return -1;
+        int oy = ym + d[1], oz = zm + d[2];
+        oy -= oy >= n[1] ? n[1] : 0;
+        oz -= oz >= n[2] ? n[2] : 0;
+        if (oy >= oex[1] || oz >= oex[2]) return -1;
+        return ooff + (long long)oex[0] * (oy + (long long)oex[1] * oz);
+    }
+    __device__ __forceinline__ int old_col(int x) const {
+        const int xm = axis_map(x, nex[0], n[0]);
+        if (xm < 0) return -1;
+        int ox = xm + d[0];
+        ox -= ox >= n[0] ? n[0] : 0;
+        return ox < oex[0] ? ox : -1;
     }
 };
 
 // Reference values next to the sign change and the x and y min-plus passes on
-// one tile of one z plane of the new box.  3D: writes the partial distance
-// with the inside flag as its sign bit; 2D: writes the final function and the
-// tile's volume.  Also carries the ID-field over to the new layout.
-template <typename T>
+// one tile of one z plane of the new box.  3D: writes the partial distance with
+// the inside flag as its sign bit; 2D: writes the final function and the tile's
+// volume.  Also carries the ID-field over to the new layout.
+template <typename T, int KS>
 __global__ void __launch_bounds__(kBlock)
     k_reinit_xy(Boxes Lo, Boxes Ln, const int *__restrict__ owner, const long long *__restrict__ pref,
-                const T *__restrict__ phic, T *__restrict__ out, const int *__restrict__ iota_old,
-                int *__restrict__ iota_new, double *__restrict__ vol_part, int K, T W, GridArgs g) {
+                const int4 *__restrict__ tilings, long long nitems, const T *__restrict__ phic, T *__restrict__ out, const int *__restrict__ iota_old,
+                int *__restrict__ iota_new, double *__restrict__ vol_part, int K_, T W, GridArgs g) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
     __shared__ double red[kBlock / 64];
-    const long long item = blockIdx.x;
-    const int k = owner[item];
-    const int sub = (int)(item - pref[k]);
+    const int K = KS ? KS : K_;
+    const long long item = xcd_item(nitems);
+    if (item >= nitems) return;
+    const ItemTile it = decode_item(item, KIND_RXY, Ln, owner, pref, tilings);
+    const int k = it.k, z = it.plane, x0 = it.x0, y0 = it.y0, wx = it.wx, wy = it.wy;
     Carry<T> cr;
     cr.src = phic;
     cr.W = W;
     cr.ooff = Lo.off[k];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        cr.nlo[a] = Ln.lo[3 * k + a];
         cr.nex[a] = Ln.ext[3 * k + a];
-        cr.olo[a] = Lo.lo[3 * k + a];
         cr.oex[a] = Lo.ext[3 * k + a];
         cr.n[a] = g.n[a];
+        const int dd = Ln.lo[3 * k + a] - Lo.lo[3 * k + a];  // both in [0, n)
+        cr.d[a] = dd < 0 ? dd + g.n[a] : dd;
     }
     const int ex = cr.nex[0], ey = cr.nex[1];
-    const Tiling tl = choose_tiling(KIND_RXY, ex, ey, K, lds_budget<T>());
-    const int per_z = tl.nxs * tl.nys;
-    const int z = sub / per_z, rem = sub - z * per_z, ys = rem / tl.nxs, xs = rem - ys * tl.nxs;
-    const int x0 = xs * tl.tx, y0 = ys * tl.ty;
-    const int wx = min(tl.tx, ex - x0), wy = min(tl.ty, ey - y0);
-    const int FW = wx + 2 * K + 2, FH = wy + 2 * K + 2, RW = wx + 2 * K, RH = wy + 2 * K;
-    T *f = sm, *ref = sm + FW * FH, *d1 = ref + RW * RH;
+    const int FW = wx + 2 * K + 2, FP = FW | 1, FH = wy + 2 * K + 2;
+    const int RW = wx + 2 * K, RP = RW | 1, RH = wy + 2 * K;
+    T *f = sm, *ref = sm + FP * FH, *d1 = ref + RP * RH + kKB;
     const T inf = tinf<T>();
-    for (int e = threadIdx.x; e < FW * FH; e += kBlock) {
-        const int rr = e / FW, cc = e - rr * FW;
-        f[e] = cr.value(x0 - K - 1 + cc, y0 - K - 1 + rr, z);
-    }
+    stage_rows<T>(
+        f, FP, FW, FH, phic, [&](int rr) { return cr.old_row(y0 - K - 1 + rr, z); },
+        [&](int cc) { return cr.old_col(x0 - K - 1 + cc); }, -W);
     __syncthreads();
-    for (int e = threadIdx.x; e < RW * RH; e += kBlock) {
-        const int rr = e / RW, cc = e - rr * RW;
-        const int x = x0 - K + cc, y = y0 - K + rr;
-        T r = inf;
-        if (axis_map(x, ex, g.n[0]) >= 0 && axis_map(y, ey, g.n[1]) >= 0) {
-            const T fc = f[(rr + 1) * FW + cc + 1];
-            const bool in = fc > T(0);
-            T nb[6];
-            nb[0] = f[(rr + 1) * FW + cc];
-            nb[1] = f[(rr + 1) * FW + cc + 2];
-            nb[2] = f[rr * FW + cc + 1];
-            nb[3] = f[(rr + 2) * FW + cc + 1];
-            int nn = 4;
-            if (g.dim == 3) {
-                nb[4] = cr.value(x, y, z - 1);
-                nb[5] = cr.value(x, y, z + 1);
-                nn = 6;
-            }
-            for (int q = 0; q < nn; ++q) {
-                const T fn = nb[q];
-                if ((fn > T(0)) != in) {
-                    const T th = fc / (fc - fn);
-                    if (th < r) r = th;
+    // reference values: waves own rows, lanes own columns; the z neighbours of
+    // kLoadBatch rows are gathered before any is used
+    {
+        const int lane = threadIdx.x & 63, wave = wave_id();
+        const int nn = g.dim == 3 ? 6 : 4;
+        for (int c0 = 0; c0 < RW; c0 += 64) {
+            const int cc = c0 + lane;
+            const int x = x0 - K + cc;
+            const bool xin = cc < RW && axis_map(x, ex, g.n[0]) >= 0;
+            const int oc = xin ? cr.old_col(x) : -1;
+            for (int r0 = wave; r0 < RH; r0 += kWaves * kLoadBatch) {
+                T zm[kLoadBatch], zp[kLoadBatch];
+#pragma unroll
+                for (int j = 0; j < kLoadBatch; ++j) {
+                    const int rr = r0 + kWaves * j;
+                    zm[j] = zp[j] = -W;
+                    if (g.dim == 3 && rr < RH && oc >= 0) {
+                        const int y = y0 - K + rr;
+                        const long long bm = cr.old_row(y, z - 1), bp = cr.old_row(y, z + 1);
+                        if (bm >= 0) zm[j] = phic[bm + oc];
+                        if (bp >= 0) zp[j] = phic[bp + oc];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < kLoadBatch; ++j) {
+                    const int rr = r0 + kWaves * j;
+                    if (rr >= RH || cc >= RW) continue;
+                    T r = inf;
+                    if (xin && axis_map(y0 - K + rr, ey, g.n[1]) >= 0) {
+                        const T *fc_p = f + (rr + 1) * FP + cc + 1;
+                        const T fc = fc_p[0];
+                        const bool in = fc > T(0);
+                        const T nb[6] = {fc_p[-1], fc_p[1], fc_p[-FP], fc_p[FP], zm[j], zp[j]};
+                        // theta = fc / (fc - fn) is monotone in fn (decreasing for an
+                        // inside voxel over fn <= 0, increasing for an outside voxel
+                        // over fn > 0), and so are the rounded operations: the
+                        // smallest theta is the one at the extreme opposite neighbour
+                        T ext = in ? inf : -inf;
+                        bool any = false;
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) {
+                            if (q >= nn) break;
+                            const T fn = nb[q];
+                            if ((fn > T(0)) != in) {
+                                any = true;
+                                ext = in ? (fn < ext ? fn : ext) : (fn > ext ? fn : ext);
+                            }
+                        }
+                        if (any) r = fc / (fc - ext);
+                    }
+                    ref[rr * RP + cc] = r;
                 }
             }
         }
-        ref[e] = r;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < wx * RH; e += kBlock) {
-        const int rr = e / wx, c = e - rr * wx;
-        T best = inf;
-        if (axis_map(y0 - K + rr, ey, g.n[1]) >= 0) {
-            const T *rp = ref + rr * RW + c;
-            for (int i = 0; i <= 2 * K; ++i) {
-                const T t = rp[i] + T(i < K ? K - i : i - K);
-                if (t < best) best = t;
-            }
+    const int ngx = (wx + kKB - 1) / kKB;
+    for (int e = threadIdx.x; e < ngx * RH; e += kBlock) {
+        const int rr = e % RH, c0 = (e / RH) * kKB;
+        T best[kKB];
+        if (axis_map(y0 - K + rr, ey, g.n[1]) < 0) {
+#pragma unroll
+            for (int q = 0; q < kKB; ++q) best[q] = inf;
+        } else {
+            minplus_run<T, KS>(ref + rr * RP + c0, 1, K, best, false);
         }
-        d1[e] = best;
+#pragma unroll
+        for (int q = 0; q < kKB; ++q)
+            if (c0 + q < wx) d1[rr * wx + c0 + q] = best[q];
     }
     __syncthreads();
     const long long base = Ln.off[k] + (long long)z * ex * ey;
     double vsum = 0.0;
-    for (int e = threadIdx.x; e < wx * wy; e += kBlock) {
-        const int r = e / wx, c = e - r * wx;
-        T best = inf;
-        const T *cp = d1 + r * wx + c;
-        for (int j = 0; j <= 2 * K; ++j) {
-            const T t = cp[j * wx] + T(j < K ? K - j : j - K);
-            if (t < best) best = t;
-        }
-        const bool in = f[(r + K + 1) * FW + c + K + 1] > T(0);
-        const long long idx = base + (long long)(y0 + r) * ex + x0 + c;
-        if (g.dim == 2) {
-            const T d = best < W ? best : W;
-            const T p = in ? d : -d;
-            out[idx] = p;
-            double cl = (double)p + 0.5;
-            cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
-            vsum += cl;
-        } else {
-            out[idx] = in ? best : -best;
-        }
-        if (iota_new) {
-            const long long oi = cr.old_index(x0 + c, y0 + r, z);
-            iota_new[idx] = oi >= 0 ? iota_old[oi] : -1;
+    const int ngy = (wy + kKB - 1) / kKB;
+    for (int e = threadIdx.x; e < ngy * wx; e += kBlock) {
+        const int c = e % wx, r0 = (e / wx) * kKB;
+        T best[kKB];
+        minplus_run<T, KS>(d1 + r0 * wx + c, wx, K, best, false);
+#pragma unroll
+        for (int q = 0; q < kKB; ++q) {
+            const int r = r0 + q;
+            if (r >= wy) break;
+            const bool in = f[(r + K + 1) * FP + c + K + 1] > T(0);
+            const long long idx = base + (long long)(y0 + r) * ex + x0 + c;
+            if (g.dim == 2) {
+                const T d = best[q] < W ? best[q] : W;
+                const T p = in ? d : -d;
+                out[idx] = p;
+                double cl = (double)p + 0.5;
+                cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
+                vsum += cl;
+            } else {
+                out[idx] = in ? best[q] : -best[q];
+            }
+            if (iota_new) {
+                const long long oi = cr.old_index(x0 + c, y0 + r, z);
+                iota_new[idx] = oi >= 0 ? iota_old[oi] : -1;
+            }
         }
     }
     if (g.dim == 2) {
@@ -646,50 +855,82 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
-// z min-plus pass, sign and band clamp, and the tile's volume (3D).
-template <typename T>
+// Fused z sweep (3D) over one tile (x chunk * z range) of one y row of the new
+// box: z min-plus pass, sign and band clamp -> phi (optionally stored) and the
+// tile's volume; then the next predictor's z pass of phi -> t.
+template <typename T, int KS, int RS>
 __global__ void __launch_bounds__(kBlock)
-    k_reinit_z(Boxes Ln, const int *__restrict__ owner, const long long *__restrict__ pref,
-               const T *__restrict__ d2, T *__restrict__ out, double *__restrict__ vol_part, int K,
-               T W, GridArgs g) {
+    k_zfused(Boxes Ln, const int *__restrict__ owner, const long long *__restrict__ pref,
+             const int4 *__restrict__ tilings, long long nitems,
+             const T *__restrict__ d2,
+             T *__restrict__ phi_out, T *__restrict__ t_out, double *__restrict__ vol_part, const T *__restrict__ taps,
+             int K_, int R_, T W, GridArgs g) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *col = reinterpret_cast<T *>(smem_raw);
+    T *sm = reinterpret_cast<T *>(smem_raw);
     __shared__ double red[kBlock / 64];
-    const long long item = blockIdx.x;
-    const int k = owner[item];
-    const int sub = (int)(item - pref[k]);
+    const int K = KS ? KS : K_, R = RS ? RS : R_;
+    const long long item = xcd_item(nitems);
+    if (item >= nitems) return;
+    const ItemTile it = decode_item(item, KIND_ZF, Ln, owner, pref, tilings);
+    const int k = it.k, y = it.plane, x0 = it.x0, z0 = it.y0, wx = it.wx, wz = it.wy;
     const int ex = Ln.ext[3 * k], ey = Ln.ext[3 * k + 1], ez = Ln.ext[3 * k + 2];
-    const Tiling tl = choose_tiling(KIND_RZ, ex, ez, K, lds_budget<T>());
-    const int per_y = tl.nxs * tl.nys;
-    const int y = sub / per_y, rem = sub - y * per_y, zs = rem / tl.nxs, xs = rem - zs * tl.nxs;
-    const int x0 = xs * tl.tx, z0 = zs * tl.ty;
-    const int wx = min(tl.tx, ex - x0), wz = min(tl.ty, ez - z0);
-    const int CH = wz + 2 * K;
+    const int DH = wz + 2 * (K + R), PH = wz + 2 * R;
+    T *dc = sm, *pc = sm + wx * (DH + kKB);
     const long long plane = (long long)ex * ey;
     const long long rowbase = Ln.off[k] + (long long)y * ex + x0;
+    T tp[RS > 0 ? 2 * RS + 1 : 1];
+    if constexpr (RS > 0) {
+#pragma unroll
+        for (int t = 0; t <= 2 * RS; ++t) tp[t] = taps[t];
+    }
     const T inf = tinf<T>();
-    for (int e = threadIdx.x; e < wx * CH; e += kBlock) {
-        const int rr = e / wx, c = e - rr * wx;
-        const int zz = axis_map(z0 - K + rr, ez, g.n[2]);
-        col[e] = zz >= 0 ? d2[rowbase + zz * plane + c] : inf;
+    stage_rows<T>(
+        dc, wx, wx, DH, d2,
+        [&](int rr) -> long long {
+            const int zz = axis_map(z0 - K - R + rr, ez, g.n[2]);
+            return zz >= 0 ? rowbase + (long long)zz * plane : -1;
+        },
+        [&](int c) { return c; }, inf);
+    __syncthreads();
+    const int ngp = (PH + kKB - 1) / kKB;
+    for (int e = threadIdx.x; e < ngp * wx; e += kBlock) {
+        const int c = e % wx, r0 = (e / wx) * kKB;
+        T best[kKB];
+        minplus_run<T, KS>(dc + r0 * wx + c, wx, K, best, true);
+#pragma unroll
+        for (int q = 0; q < kKB; ++q) {
+            const int r = r0 + q;
+            if (r >= PH) break;
+            T p;
+            if (axis_map(z0 - R + r, ez, g.n[2]) < 0) {
+                p = -W;  // outside the box the predictor reads the fill value
+            } else {
+                const bool in = !signbit(dc[(r + K) * wx + c]);
+                const T d = best[q] < W ? best[q] : W;
+                p = in ? d : -d;
+            }
+            pc[r * wx + c] = p;
+        }
     }
     __syncthreads();
     double vsum = 0.0;
-    for (int e = threadIdx.x; e < wx * wz; e += kBlock) {
-        const int r = e / wx, c = e - r * wx;
-        T best = inf;
-        const T *cp = col + r * wx + c;
-        for (int j = 0; j <= 2 * K; ++j) {
-            const T t = fabs(cp[j * wx]) + T(j < K ? K - j : j - K);
-            if (t < best) best = t;
+    const int ngz = (wz + kKB - 1) / kKB;
+    for (int e = threadIdx.x; e < ngz * wx; e += kBlock) {
+        const int c = e % wx, r0 = (e / wx) * kKB;
+        T acc[kKB];
+        gauss_run<T, RS>(pc + r0 * wx + c, wx, tp, taps, R, acc);
+#pragma unroll
+        for (int q = 0; q < kKB; ++q) {
+            const int r = r0 + q;
+            if (r >= wz) break;
+            const long long idx = rowbase + (long long)(z0 + r) * plane + c;
+            const T p = pc[(r + R) * wx + c];
+            if (phi_out) phi_out[idx] = p;
+            double cl = (double)p + 0.5;
+            cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
+            vsum += cl;
+            t_out[idx] = acc[q];
         }
-        const bool in = !signbit(cp[K * wx]);
-        const T d = best < W ? best : W;
-        const T p = in ? d : -d;
-        out[rowbase + (long long)(z0 + r) * plane + c] = p;
-        double cl = (double)p + 0.5;
-        cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
-        vsum += cl;
     }
     const double s = block_sum(vsum, red);
     if (threadIdx.x == 0) vol_part[item] = s;
@@ -698,8 +939,8 @@ __global__ void __launch_bounds__(kBlock)
 // Initial function before re-initialization: +1/2 on the grain's labelled
 // voxels, -1/2 elsewhere in its box.
 template <typename T>
-__global__ void __launch_bounds__(kBlock)
-    k_init_indicator(Boxes L, const int *__restrict__ labels, T *__restrict__ out, GridArgs g) {
+__global__ void __launch_bounds__(kBlock) k_init_indicator(Boxes L, const int *__restrict__ labels, T *__restrict__ out,
+                                                           GridArgs g) {
     const int k = blockIdx.x;
     if (!L.alive[k]) return;
     const int ex = L.ext[3 * k], ey = L.ext[3 * k + 1], ez = L.ext[3 * k + 2];
@@ -760,11 +1001,10 @@ struct PlanArgs {
 
 // New boxes from the positive set of phi^c (sec. 3.1: size-adaptive boxes;
 // extinction when the set is empty).  Resets the bounding-box accumulators.
-__global__ void k_plan(Boxes Lo, Boxes Ln, int *bmin, int *bmax, unsigned *occ, long long *sizes,
-                       PlanArgs pa) {
+__global__ void k_plan(Boxes Lo, Boxes Ln, int *bmin, int *bmax, unsigned *occ, long long *sizes, PlanArgs pa) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= pa.G) return;
-    bool alive = Lo.alive[k] && bmax[3 * k] >= 0;
+    const bool alive = Lo.alive[k] && bmax[3 * k] >= 0;
     long long size = 0;
     if (alive) {
         size = 1;
@@ -811,34 +1051,32 @@ __global__ void k_plan(Boxes Lo, Boxes Ln, int *bmin, int *bmax, unsigned *occ, 
     }
 }
 
-// Box volumes of a layout (for layouts set from the host).
-__global__ void k_box_sizes(Boxes L, long long *sizes, int G) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= G) return;
-    sizes[k] = L.alive[k] ? (long long)L.ext[3 * k] * L.ext[3 * k + 1] * L.ext[3 * k + 2] : 0;
-}
-
-// Per-grain work item counts of the four stencil kinds.
-__global__ void k_item_counts(Boxes L, long long *c0, long long *c1, long long *c2, long long *c3,
+// Per-grain work item counts of the four stencil kinds and the largest LDS need.
+__global__ void k_item_counts(Boxes L, long long *c0, long long *c1, long long *c2, long long *c3, int4 *tilings,
                               unsigned long long *lds_max, int R, int K, int G, int budget) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= G) return;
     long long *cs[4] = {c0, c1, c2, c3};
     if (!L.alive[k]) {
-        for (int q = 0; q < 4; ++q) cs[q][k] = 0;
+        for (int q = 0; q < 4; ++q) {
+            cs[q][k] = 0;
+            tilings[(long long)q * G + k] = make_int4(0, 0, 0, 0);
+        }
         return;
     }
     const int *e = L.ext + 3 * k;
-    const int h[4] = {R, R, K, K};
     for (int q = 0; q < 4; ++q) {
-        cs[q][k] = kind_items(q, e, h[q], budget);
-        const int sa = (q == KIND_CXY || q == KIND_RXY) ? e[1] : e[2];
-        const Tiling t = choose_tiling(q, e[0], sa, h[q], budget);
+        const Tiling t = kind_tiling(q, e, R, K, budget);
+        tilings[(long long)q * G + k] = make_int4(t.nxs, t.nys, t.tx, t.ty);
         if (t.nxs == 0) {
+            cs[q][k] = 0;
             atomicMax(&lds_max[q], 0xffffffffffffffffULL);  // infeasible tiling
-        } else {
-            atomicMax(&lds_max[q], (unsigned long long)lds_need(q, t.tx, t.ty, h[q]));
+            continue;
         }
+        cs[q][k] = kind_items(q, e, R, K, budget);
+        int h, h2;
+        kind_halos(q, R, K, &h, &h2);
+        atomicMax(&lds_max[q], (unsigned long long)lds_need(q, t.tx, t.ty, h, h2));
     }
 }
 
@@ -866,7 +1104,7 @@ __global__ void __launch_bounds__(1024) k_scan(const long long *in, long long *o
     if (t == 1023) out[n] = part[1023];
 }
 
-__global__ void k_scan_int(const int *in, int *out, int n) {
+__global__ void __launch_bounds__(1024) k_scan_int(const int *in, int *out, int n) {
     __shared__ long long part[1024];
     const int t = threadIdx.x;
     const int chunk = (n + 1023) / 1024;
@@ -914,7 +1152,8 @@ __global__ void k_coverage(Boxes L, int *cnt_or_cursor, int *list, TileArgs ta, 
     const int k = blockIdx.x;
     if (!L.alive[k]) return;
     int t0[3], c[3];
-    for (int a = 0; a < 3; ++a) axis_tiles(L.lo[3 * k + a], L.ext[3 * k + a], ta.n[a], ta.t[a], ta.nt[a], &t0[a], &c[a]);
+    for (int a = 0; a < 3; ++a)
+        axis_tiles(L.lo[3 * k + a], L.ext[3 * k + a], ta.n[a], ta.t[a], ta.nt[a], &t0[a], &c[a]);
     const int total = c[0] * c[1] * c[2];
     for (int q = threadIdx.x; q < total; q += blockDim.x) {
         const int ix = q % c[0], iy = (q / c[0]) % c[1], iz = q / (c[0] * c[1]);
@@ -939,9 +1178,9 @@ __global__ void k_volumes(const Boxes L, const long long *pref, const double *vo
     vol[k] = s;
 }
 
-__global__ void k_totals(const long long *arena_pref, const long long *p0, const long long *p1,
-                         const long long *p2, const long long *p3, const int *cov_off, int ntiles,
-                         const int *alive, int G, const unsigned long long *lds_max, Totals *t) {
+__global__ void k_totals(const long long *arena_pref, const long long *p0, const long long *p1, const long long *p2,
+                         const long long *p3, const int *cov_off, int ntiles, const int *alive, int G,
+                         const unsigned long long *lds_max, Totals *t) {
     if (threadIdx.x == 0) {
         t->arena = arena_pref[G];
         t->items[0] = p0[G];
@@ -962,10 +1201,8 @@ __global__ void k_totals(const long long *arena_pref, const long long *p0, const
 }
 
 // Copy between value types (state download / upload).
-template <typename A, typename B>
-__global__ void k_convert(const A *in, B *out, long long n) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x)
+template <typename A, typename B> __global__ void k_convert(const A *in, B *out, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         out[i] = (B)in[i];
 }
 

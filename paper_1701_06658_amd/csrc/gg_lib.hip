@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -19,7 +20,6 @@
 namespace {
 
 using gg::Boxes;
-using gg::Items;
 using gg::Totals;
 
 struct HipError {
@@ -106,7 +106,7 @@ template <typename T> struct Sim final : SimBase {
 
     // layouts 0/1: box tables and work items
     DBuf lo[2], ext[2], alive[2], off[2];
-    DBuf ipref[2][gg::kKinds], iowner[2][gg::kKinds];
+    DBuf ipref[2][gg::kKinds], iowner[2][gg::kKinds], itile[2];
     int items_R[2] = {-1, -1};
     Totals tot[2];
     int cur = 0;
@@ -116,10 +116,13 @@ template <typename T> struct Sim final : SimBase {
     DBuf cov_cnt, cov_off, cov_cur, cov_list;
     DBuf taps_d, quat_d, energy_d, totals_d;
     Totals *totals_h = nullptr;
-    // value arenas (3) and ID-fields (old layout, current layout)
-    DBuf arena[3], iota_a[2];
-    int is = 0;       // arena holding the state
-    int iota_cur = 0; // ID-field of the current layout
+    // value arenas and their roles for the current layout (-1: not held)
+    DBuf arena[4], iota_a[2];
+    int a_state = -1;  // phi, materialised
+    int a_T = -1;      // z pass of the predictor applied to phi (3D), radius T_R
+    int a_psi = -1;    // predicted function psi, radius psi_R
+    int T_R = -1, psi_R = -1;
+    int iota_cur = 0;  // ID-field of the current layout
     // kept intermediates (test hook)
     DBuf keep_psi, keep_phic, keep_lo, keep_ext, keep_alive, keep_off;
     Totals keep_tot{};
@@ -186,6 +189,7 @@ template <typename T> struct Sim final : SimBase {
     }
     gg_kernel_times kernel_times() const override { return ktimes; }
 
+    const int4 *tiles_of(int l, int kind) const { return itile[l].as<int4>() + (size_t)kind * G; }
     Boxes boxes_of(int l) {
         return Boxes{lo[l].as<int>(), ext[l].as<int>(), alive[l].as<int>(), off[l].as<long long>()};
     }
@@ -247,6 +251,7 @@ template <typename T> struct Sim final : SimBase {
             alive[l].ensure(sizeof(int) * G);
             off[l].ensure(sizeof(long long) * (G + 1));
             for (int q = 0; q < gg::kKinds; ++q) ipref[l][q].ensure(sizeof(long long) * (G + 1));
+            itile[l].ensure(sizeof(int4) * gg::kKinds * (size_t)G);
         }
         bmin.ensure(sizeof(int) * 3 * G);
         bmax.ensure(sizeof(int) * 3 * G);
@@ -280,12 +285,13 @@ template <typename T> struct Sim final : SimBase {
             alive[l].release();
             off[l].release();
             iota_a[l].release();
+            itile[l].release();
             for (int q = 0; q < gg::kKinds; ++q) {
                 ipref[l][q].release();
                 iowner[l][q].release();
             }
         }
-        for (int a = 0; a < 3; ++a) arena[a].release();
+        for (int a = 0; a < 4; ++a) arena[a].release();
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         if (totals_h) (void)hipHostFree(totals_h);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -300,6 +306,20 @@ template <typename T> struct Sim final : SimBase {
         if ((size_t)need * sizeof(T) <= arena[a].cap && arena[a].p) return;
         arena[a].ensure(grow_to(need) * sizeof(T));
     }
+    // First arena outside `excl` (bit mask of arenas holding live data) with room
+    // for `need` values; grows a dead one when none has room.
+    int pick(unsigned excl, long long need) {
+        for (int a = 0; a < 4; ++a)
+            if (!(excl >> a & 1u) && arena[a].p && (size_t)need * sizeof(T) <= arena[a].cap) return a;
+        for (int a = 0; a < 4; ++a)
+            if (!(excl >> a & 1u)) {
+                ensure_arena(a, need);
+                return a;
+            }
+        throw CapError{"no free value arena"};
+    }
+    static unsigned bit(int a) { return a >= 0 ? 1u << a : 0u; }
+
     void ensure_iota(int a, long long need) {
         if ((size_t)need * sizeof(int) <= iota_a[a].cap && iota_a[a].p) return;
         iota_a[a].ensure(grow_to(need) * sizeof(int));
@@ -313,7 +333,7 @@ template <typename T> struct Sim final : SimBase {
         HIPCHECK(hipMemsetAsync(ldsmax.p, 0, sizeof(unsigned long long) * gg::kKinds, stream));
         const int tb = 256, gb = (G + tb - 1) / tb;
         hipLaunchKernelGGL(gg::k_item_counts, dim3(gb), dim3(tb), 0, stream, L, cnt[0].as<long long>(),
-                           cnt[1].as<long long>(), cnt[2].as<long long>(), cnt[3].as<long long>(),
+                           cnt[1].as<long long>(), cnt[2].as<long long>(), cnt[3].as<long long>(), itile[l].as<int4>(),
                            ldsmax.as<unsigned long long>(), R, K, G, gg::lds_budget<T>());
         for (int q = 0; q < gg::kKinds; ++q)
             hipLaunchKernelGGL(gg::k_scan, dim3(1), dim3(1024), 0, stream, cnt[q].as<long long>(),
@@ -396,34 +416,88 @@ template <typename T> struct Sim final : SimBase {
 
     static unsigned grid_of(long long items) { return (unsigned)items; }
 
-    // Re-initialization from `src` (layout lo_l) into layout ln_l, written to arena `dst_a`
-    // (3D: through the partial-distance arena `tmp_a`).
-    void reinit(int lo_l, int ln_l, const T *src, int tmp_a, int dst_a, const int *iota_old, int *iota_new) {
+    // Predictor x and y passes (+ correction epilogue) on layout l: src -> dst.
+    void launch_conv_xy(int l, const T *src, T *dst, const gg::Physics<T> &ph) {
+        const Totals &t = tot[l];
+        if (t.items[gg::KIND_CXY] <= 0) return;
+        tbegin(GG_K_CONV_XY, t.arena);
+        const dim3 gr(grid_of(gg::xcd_grid(t.items[gg::KIND_CXY]))), bl(gg::kBlock);
+        const size_t lds = sizeof(T) * t.lds[gg::KIND_CXY];
+        auto args = std::make_tuple(boxes_of(l), (const int *)iowner[l][gg::KIND_CXY].as<int>(),
+                                    (const long long *)ipref[l][gg::KIND_CXY].as<long long>(), tiles_of(l, gg::KIND_CXY),
+                                    (long long)t.items[gg::KIND_CXY], src, dst,
+                                    (const T *)taps_d.as<T>(), R, W, grid_args(), ph);
+        auto go = [&](auto kern) {
+            std::apply([&](auto... a) { hipLaunchKernelGGL(kern, gr, bl, lds, stream, a...); }, args);
+        };
+        if (ph.mode) go(gg::k_conv_xy<T, 0, true>);
+        else if (R == 6) go(gg::k_conv_xy<T, 6, false>);
+        else if (R == 8) go(gg::k_conv_xy<T, 8, false>);
+        else go(gg::k_conv_xy<T, 0, false>);
+        tend();
+        HIPCHECK(hipGetLastError());
+    }
+
+    // Predictor z pass alone on layout l (3D): src -> dst.
+    void launch_conv_z(int l, const T *src, T *dst) {
+        const Totals &t = tot[l];
+        if (t.items[gg::KIND_CZ] <= 0) return;
+        tbegin(GG_K_CONV_Z, t.arena);
+        hipLaunchKernelGGL(gg::k_conv_z<T>, dim3(grid_of(gg::xcd_grid(t.items[gg::KIND_CZ]))), dim3(gg::kBlock),
+                           sizeof(T) * t.lds[gg::KIND_CZ], stream, boxes_of(l), iowner[l][gg::KIND_CZ].as<int>(),
+                           ipref[l][gg::KIND_CZ].as<long long>(), tiles_of(l, gg::KIND_CZ),
+                           (long long)t.items[gg::KIND_CZ], src, dst,
+                           taps_d.as<T>(), R, W, grid_args());
+        tend();
+        HIPCHECK(hipGetLastError());
+    }
+
+    // Re-initialization of phi^c (layout lo_l) into layout ln_l.  2D: the final
+    // function goes to `phi`.  3D: partial distances to `d2`, then the fused z
+    // sweep writes phi (when `phi` is not null) and the predictor z pass to `t`.
+    void launch_reinit(int lo_l, int ln_l, const T *phic, T *d2, T *phi, T *tz, const int *iota_old, int *iota_new) {
         const Totals &t = tot[ln_l];
-        gg::GridArgs g = grid_args();
-        vol_part.ensure(sizeof(double) * (size_t)std::max<long long>(t.items[dim == 3 ? 3 : 2], 1) * 5 / 4);
-        if (t.items[2] > 0) {
-            T *out = dim == 3 ? arena[tmp_a].as<T>() : arena[dst_a].as<T>();
+        const gg::GridArgs g = grid_args();
+        const int vk = dim == 3 ? gg::KIND_ZF : gg::KIND_RXY;
+        vol_part.ensure(sizeof(double) * (size_t)std::max<long long>(t.items[vk], 1) * 5 / 4);
+        if (t.items[gg::KIND_RXY] > 0) {
             tbegin(GG_K_REINIT_XY, t.arena);
-            hipLaunchKernelGGL(gg::k_reinit_xy<T>, dim3(grid_of(t.items[2])), dim3(gg::kBlock),
-                               sizeof(T) * t.lds[2], stream, boxes_of(lo_l), boxes_of(ln_l),
-                               iowner[ln_l][2].as<int>(), ipref[ln_l][2].as<long long>(), src, out, iota_old,
-                               iota_new, vol_part.as<double>(), K, W, g);
+            const dim3 gr(grid_of(gg::xcd_grid(t.items[gg::KIND_RXY]))), bl(gg::kBlock);
+            const size_t lds = sizeof(T) * t.lds[gg::KIND_RXY];
+            T *out = dim == 3 ? d2 : phi;
+            auto args = std::make_tuple(boxes_of(lo_l), boxes_of(ln_l),
+                                        (const int *)iowner[ln_l][gg::KIND_RXY].as<int>(),
+                                        (const long long *)ipref[ln_l][gg::KIND_RXY].as<long long>(),
+                                        tiles_of(ln_l, gg::KIND_RXY), (long long)t.items[gg::KIND_RXY], phic, out,
+                                        iota_old, iota_new, vol_part.as<double>(), K, W, g);
+            auto go = [&](auto kern) {
+                std::apply([&](auto... a) { hipLaunchKernelGGL(kern, gr, bl, lds, stream, a...); }, args);
+            };
+            if (K == 6) go(gg::k_reinit_xy<T, 6>);
+            else if (K == 8) go(gg::k_reinit_xy<T, 8>);
+            else go(gg::k_reinit_xy<T, 0>);
             tend();
         }
-        if (dim == 3 && t.items[3] > 0) {
+        if (dim == 3 && t.items[gg::KIND_ZF] > 0) {
             tbegin(GG_K_REINIT_Z, t.arena);
-            hipLaunchKernelGGL(gg::k_reinit_z<T>, dim3(grid_of(t.items[3])), dim3(gg::kBlock),
-                               sizeof(T) * t.lds[3], stream, boxes_of(ln_l), iowner[ln_l][3].as<int>(),
-                               ipref[ln_l][3].as<long long>(), arena[tmp_a].as<T>(), arena[dst_a].as<T>(),
-                               vol_part.as<double>(), K, W, g);
+            const dim3 gr(grid_of(gg::xcd_grid(t.items[gg::KIND_ZF]))), bl(gg::kBlock);
+            const size_t lds = sizeof(T) * t.lds[gg::KIND_ZF];
+            auto args = std::make_tuple(boxes_of(ln_l), (const int *)iowner[ln_l][gg::KIND_ZF].as<int>(),
+                                        (const long long *)ipref[ln_l][gg::KIND_ZF].as<long long>(),
+                                        tiles_of(ln_l, gg::KIND_ZF), (long long)t.items[gg::KIND_ZF], (const T *)d2,
+                                        phi, tz, vol_part.as<double>(), (const T *)taps_d.as<T>(), K, R, W, g);
+            auto go = [&](auto kern) {
+                std::apply([&](auto... a) { hipLaunchKernelGGL(kern, gr, bl, lds, stream, a...); }, args);
+            };
+            if (K == 6 && R == 6) go(gg::k_zfused<T, 6, 6>);
+            else if (K == 8 && R == 8) go(gg::k_zfused<T, 8, 8>);
+            else go(gg::k_zfused<T, 0, 0>);
             tend();
         }
         const int tb = 256, gb = (G + tb - 1) / tb;
         tbegin(GG_K_VOLUME, t.arena);
-        hipLaunchKernelGGL(gg::k_volumes, dim3(gb), dim3(tb), 0, stream, boxes_of(ln_l),
-                           ipref[ln_l][dim == 3 ? 3 : 2].as<long long>(), vol_part.as<double>(), vol.as<double>(),
-                           G);
+        hipLaunchKernelGGL(gg::k_volumes, dim3(gb), dim3(tb), 0, stream, boxes_of(ln_l), ipref[ln_l][vk].as<long long>(),
+                           vol_part.as<double>(), vol.as<double>(), G);
         tend();
         HIPCHECK(hipGetLastError());
     }
@@ -512,32 +586,45 @@ template <typename T> struct Sim final : SimBase {
             HIPCHECK(hipStreamSynchronize(stream));
         }
         // initial function: re-initialised +-1/2 indicator, on the same boxes
-        R = 1;  // any valid radius for the item bookkeeping; set per step
+        // (the item bookkeeping needs a radius: R = 1 with identity taps; the
+        // z-convolved output of this pass is discarded)
+        set_identity_taps();
         layout_meta_count(0, true);
         layout_meta_fill(0, true);
         const long long need = tot[0].arena;
-        for (int a = 0; a < 3; ++a) ensure_arena(a, need);
+        for (int a = 0; a < 4; ++a) ensure_arena(a, need);
         DBuf lab;
         lab.ensure(sizeof(int32_t) * nt3);
         HIPCHECK(hipMemcpyAsync(lab.p, labels, sizeof(int32_t) * nt3, hipMemcpyHostToDevice, stream));
         hipLaunchKernelGGL(gg::k_init_indicator<T>, dim3(G), dim3(gg::kBlock), 0, stream, boxes_of(0),
-                           lab.as<int>(), arena[1].as<T>(), grid_args());
+                           lab.as<int>(), arena[0].as<T>(), grid_args());
         HIPCHECK(hipGetLastError());
-        reinit(0, 0, arena[1].as<T>(), 2, 0, nullptr, nullptr);
-        is = 0;
+        launch_reinit(0, 0, arena[0].as<T>(), arena[1].as<T>(), arena[2].as<T>(), arena[3].as<T>(), nullptr,
+                      nullptr);
+        a_state = 2;
+        a_T = a_psi = -1;
+        T_R = psi_R = -1;
         HIPCHECK(hipStreamSynchronize(stream));
         lab.release();
         if (physics) {
             ensure_iota(0, need);
             ensure_iota(1, need);
             iota_cur = 0;
-            hipLaunchKernelGGL(gg::k_compare<T>, dim3(ntiles), dim3(gg::kBlock), 0, stream, boxes_of(0),
-                               cov_off.as<int>(), cov_list.as<int>(), arena[is].as<T>(), (T *)nullptr,
+            hipLaunchKernelGGL(gg::k_compare<T>, dim3(grid_of(gg::xcd_grid(ntiles))), dim3(gg::kBlock), 0, stream, boxes_of(0),
+                               cov_off.as<int>(), cov_list.as<int>(), arena[a_state].as<T>(), (T *)nullptr,
                                iota_a[0].as<int>(), bmin.as<int>(), bmax.as<int>(), occ.as<unsigned>(),
                                tile_args(), W, 1);
             HIPCHECK(hipGetLastError());
             HIPCHECK(hipStreamSynchronize(stream));
         }
+    }
+
+    void set_identity_taps() {
+        std::vector<T> t = {T(0), T(1), T(0)};
+        HIPCHECK(hipMemcpyAsync(taps_d.p, t.data(), sizeof(T) * 3, hipMemcpyHostToDevice, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+        R = 1;
+        sigma = -1.0;
     }
 
     void upload_table(int l, const int *hlo, const int *hext, const int *hal, const long long *hoff) {
@@ -555,7 +642,7 @@ template <typename T> struct Sim final : SimBase {
         HIPCHECK(hipEventCreate(&e0));
         HIPCHECK(hipEventCreate(&e1));
         HIPCHECK(hipEventRecord(e0, stream));
-        for (int s = 0; s < nsteps; ++s) step_once();
+        for (int s = 0; s < nsteps; ++s) step_once(s == nsteps - 1);
         HIPCHECK(hipEventRecord(e1, stream));
         HIPCHECK(hipEventSynchronize(e1));
         resolve_spans();
@@ -566,7 +653,27 @@ template <typename T> struct Sim final : SimBase {
         if (nsteps > 0) last_ms = ms / nsteps;
     }
 
-    void step_once() {
+    const int *iota_now() { return physics ? iota_a[iota_cur].as<int>() : nullptr; }
+
+    // psi of the current layout from phi (or from the kept z pass of phi).
+    void predict(int l) {
+        const long long m = tot[l].arena;
+        int src = a_state;
+        if (dim == 3) {
+            if (a_T < 0 || T_R != R) {
+                a_T = pick(bit(a_state), m);
+                launch_conv_z(l, arena[a_state].as<T>(), arena[a_T].as<T>());
+                T_R = R;
+            }
+            src = a_T;
+        }
+        a_psi = pick(bit(a_state) | bit(src), m);
+        const T *phi = a_state >= 0 ? arena[a_state].as<T>() : nullptr;
+        launch_conv_xy(l, arena[src].as<T>(), arena[a_psi].as<T>(), physics_args(phi, iota_now()));
+        psi_R = R;
+    }
+
+    void step_once(bool last) {
         const int L = cur, Ln = 1 - cur;
         if (items_R[L] != R) {
             layout_meta_count(L, false);
@@ -575,47 +682,21 @@ template <typename T> struct Sim final : SimBase {
         const Totals &t = tot[L];
         last_gv = t.arena;
         total_gv += t.arena;
-        const int a_s = is, a_t1 = (is + 1) % 3, a_psi = (is + 2) % 3;
-        gg::GridArgs g = grid_args();
-        const int *iota_in = physics ? iota_a[iota_cur].as<int>() : nullptr;
-        gg::Physics<T> ph = physics_args(arena[a_s].as<T>(), iota_in);
-        gg::Physics<T> noph = ph;
-        noph.mode = 0;
-        // 1. predictor
-        T *psi = arena[a_psi].as<T>();
-        if (dim == 3) {
-            if (t.items[0] > 0) {
-                tbegin(GG_K_CONV_XY, t.arena);
-                hipLaunchKernelGGL(gg::k_conv_xy<T>, dim3(grid_of(t.items[0])), dim3(gg::kBlock), sizeof(T) * t.lds[0],
-                                   stream, boxes_of(L), iowner[L][0].as<int>(), ipref[L][0].as<long long>(),
-                                   arena[a_s].as<T>(), arena[a_t1].as<T>(), taps_d.as<T>(), R, W, g, noph);
-                tend();
-            }
-            if (t.items[1] > 0) {
-                tbegin(GG_K_CONV_Z, t.arena);
-                hipLaunchKernelGGL(gg::k_conv_z<T>, dim3(grid_of(t.items[1])), dim3(gg::kBlock), sizeof(T) * t.lds[1],
-                                   stream, boxes_of(L), iowner[L][1].as<int>(), ipref[L][1].as<long long>(),
-                                   arena[a_t1].as<T>(), psi, taps_d.as<T>(), R, W, g, ph);
-                tend();
-            }
-        } else if (t.items[0] > 0) {
-            tbegin(GG_K_CONV_XY, t.arena);
-            hipLaunchKernelGGL(gg::k_conv_xy<T>, dim3(grid_of(t.items[0])), dim3(gg::kBlock), sizeof(T) * t.lds[0],
-                               stream, boxes_of(L), iowner[L][0].as<int>(), ipref[L][0].as<long long>(),
-                               arena[a_s].as<T>(), psi, taps_d.as<T>(), R, W, g, ph);
-            tend();
-        }
-        // 2. corrector into the t1 arena (dead after the predictor)
-        T *phic = arena[a_t1].as<T>();
+        // 1. predictor (already issued at the end of the previous step when possible)
+        if (a_psi < 0 || psi_R != R) predict(L);
+        // 2. corrector: psi -> phi^c (phi, its z pass and psi are dead afterwards)
+        const int a_phic = pick(bit(a_psi), t.arena);
+        T *psi = arena[a_psi].as<T>(), *phic = arena[a_phic].as<T>();
         const int iota_old = 1 - iota_cur;
         if (physics) ensure_iota(iota_old, t.arena);
         tbegin(GG_K_COMPARE, t.arena);
-        hipLaunchKernelGGL(gg::k_compare<T>, dim3(ntiles), dim3(gg::kBlock), 0, stream, boxes_of(L), cov_off.as<int>(),
+        hipLaunchKernelGGL(gg::k_compare<T>, dim3(grid_of(gg::xcd_grid(ntiles))), dim3(gg::kBlock), 0, stream, boxes_of(L), cov_off.as<int>(),
                            cov_list.as<int>(), psi, phic, physics ? iota_a[iota_old].as<int>() : (int *)nullptr,
                            bmin.as<int>(), bmax.as<int>(), occ.as<unsigned>(), tile_args(), W, 0);
         tend();
         HIPCHECK(hipGetLastError());
         if (keep) keep_copy(L, psi, phic);
+        a_state = a_T = a_psi = -1;
         // 3. new boxes, offsets, items and coverage of the new layout
         gg::PlanArgs pa;
         for (int a = 0; a < 3; ++a) pa.n[a] = n[a];
@@ -631,22 +712,32 @@ template <typename T> struct Sim final : SimBase {
         HIPCHECK(hipGetLastError());
         layout_meta_count(Ln, true);
         const long long need = tot[Ln].arena;
-        // the destinations of the re-initialization are dead now: grow them if needed
-        ensure_arena(a_s, need);
-        ensure_arena(a_psi, need);
+        for (int a = 0; a < 4; ++a)
+            if (a != a_phic) ensure_arena(a, need);  // all dead: grow before the writes
         if (physics) ensure_iota(iota_cur, need);
         layout_meta_fill(Ln, true);
-        // 4. re-initialization into the new layout: 3D partial distances in the
-        // state arena (dead), final function in the psi arena (dead)
-        const int dst = dim == 3 ? a_psi : a_s;
-        reinit(L, Ln, phic, a_s, dst, physics ? iota_a[iota_old].as<int>() : nullptr,
-               physics ? iota_a[iota_cur].as<int>() : nullptr);
-        is = dst;
+        // 4. re-initialization into the new layout (+ the next predictor's z pass)
+        const int *io_old = physics ? iota_a[iota_old].as<int>() : nullptr;
+        int *io_new = physics ? iota_a[iota_cur].as<int>() : nullptr;
+        if (dim == 3) {
+            const int a_d2 = pick(bit(a_phic), need);
+            const int a_t = pick(bit(a_phic) | bit(a_d2), need);
+            const bool write_phi = last || physics;
+            const int a_phi = write_phi ? pick(bit(a_phic) | bit(a_d2) | bit(a_t), need) : -1;
+            launch_reinit(L, Ln, phic, arena[a_d2].as<T>(), write_phi ? arena[a_phi].as<T>() : nullptr,
+                          arena[a_t].as<T>(), io_old, io_new);
+            a_T = a_t;
+            T_R = R;
+            a_state = a_phi;
+        } else {
+            const int a_phi = pick(bit(a_phic), need);
+            launch_reinit(L, Ln, phic, nullptr, arena[a_phi].as<T>(), nullptr, io_old, io_new);
+            a_state = a_phi;
+        }
         cur = Ln;
         ++steps_done;
-        // arenas left below the new layout's size are grown while dead
-        for (int a = 0; a < 3; ++a)
-            if (a != is) ensure_arena(a, need);
+        // 5. the next step's predictor
+        if (!last) predict(Ln);
     }
 
     void keep_copy(int L, const T *psi, const T *phic) {
@@ -682,7 +773,7 @@ template <typename T> struct Sim final : SimBase {
             dst = tmp.as<int32_t>();
         }
         hipLaunchKernelGGL(gg::k_labels<T>, dim3(ntiles), dim3(gg::kBlock), 0, stream, boxes_of(cur), cov_off.as<int>(),
-                           cov_list.as<int>(), arena[is].as<T>(), dst, tile_args());
+                           cov_list.as<int>(), arena[a_state].as<T>(), dst, tile_args());
         HIPCHECK(hipGetLastError());
         if (!device) {
             HIPCHECK(hipMemcpyAsync(out, dst, sizeof(int32_t) * nt3, hipMemcpyDeviceToHost, stream));
@@ -712,7 +803,7 @@ template <typename T> struct Sim final : SimBase {
         const T *src;
         long long m;
         if (which < 0) {
-            src = arena[is].as<T>();
+            src = arena[a_state].as<T>();
             m = tot[cur].arena;
         } else {
             if (!have_keep) throw ArgError{"no intermediates kept"};
@@ -779,10 +870,12 @@ template <typename T> struct Sim final : SimBase {
         HIPCHECK(hipStreamSynchronize(stream));
         cur = 0;
         upload_table(0, l.data(), e.data(), a.data(), o.data());
-        for (int q = 0; q < 3; ++q) ensure_arena(q, m);
+        for (int q = 0; q < 4; ++q) ensure_arena(q, m);
         std::vector<T> tv(std::max<long long>(m, 1));
         for (long long i = 0; i < m; ++i) tv[i] = (T)vals[i];
-        is = 0;
+        a_state = 0;
+        a_T = a_psi = -1;
+        T_R = psi_R = -1;
         HIPCHECK(hipMemcpyAsync(arena[0].p, tv.data(), sizeof(T) * m, hipMemcpyHostToDevice, stream));
         HIPCHECK(hipMemcpyAsync(vol.p, vh.data(), sizeof(double) * G, hipMemcpyHostToDevice, stream));
         if (physics) {
@@ -814,7 +907,7 @@ template <typename T> struct Sim final : SimBase {
         s.alive = (int)tot[cur].alive;
         s.kernel_radius = R;
         s.grain_voxels = last_gv;
-        s.capacity = (int64_t)(arena[is].cap / sizeof(T));
+        s.capacity = (int64_t)(arena[a_state >= 0 ? a_state : 0].cap / sizeof(T));
         s.superposition = (double)last_gv / ((double)n[0] * n[1] * n[2]);
         s.last_step_ms = last_ms;
         return s;
