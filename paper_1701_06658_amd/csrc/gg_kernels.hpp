@@ -85,16 +85,21 @@ template <typename T> __device__ __forceinline__ T tinf();
 template <> __device__ __forceinline__ double tinf<double>() { return __builtin_inf(); }
 template <> __device__ __forceinline__ float tinf<float>() { return __builtin_inff(); }
 
-// LDS values needed by an output tile tx * ty; h is the halo along both tile
-// axes (fused z kind: h = K, h2 = R along z).
-__host__ __device__ inline long long lds_need(int kind, int tx, int ty, int h, int h2) {
+// LDS values needed by an output tile tx * ty.  h: stencil halo (R for the
+// predictor kinds, K for the re-initialization kinds), h2: R for the fused z
+// kind.  The re-initialization sweeps whole box lines, so its tiles need a halo
+// only along an axis that is split into several tiles (sx, sy).
+__host__ __device__ inline long long lds_need(int kind, int tx, int ty, int h, int h2, bool sx, bool sy) {
     if (kind == KIND_CXY)
         return (long long)((tx + 2 * h) | 1) * (ty + 2 * h) + kKB + (long long)tx * (ty + 2 * h + kKB);
-    if (kind == KIND_RXY)
-        return (long long)((tx + 2 * h + 2) | 1) * (ty + 2 * h + 2) + (long long)((tx + 2 * h) | 1) * (ty + 2 * h) +
-               kKB + (long long)tx * (ty + 2 * h + kKB);
-    if (kind == KIND_ZF)
-        return (long long)tx * (ty + 2 * (h + h2) + kKB) + (long long)tx * (ty + 2 * h2 + kKB);
+    if (kind == KIND_RXY) {
+        const int hx = sx ? h : 0, hy = sy ? h : 0;
+        return (long long)((tx + 2 * hx + 2) | 1) * (ty + 2 * hy + 2) + (long long)((tx + 2 * hx) | 1) * (ty + 2 * hy);
+    }
+    if (kind == KIND_ZF) {
+        const int hz = sy ? h : 0;
+        return (long long)tx * (ty + 2 * h2 + 2 * hz) + (long long)tx * (ty + 2 * h2 + kKB);
+    }
     return (long long)tx * (ty + 2 * h);  // prologue z pass
 }
 
@@ -108,8 +113,16 @@ __host__ __device__ inline Tiling choose_tiling(int kind, int ex, int ey, int h,
     Tiling t = {0, 0, 0, 0};
     for (int nxs = (ex + 127) / 128; nxs <= ex; ++nxs) {
         const int tx = (ex + nxs - 1) / nxs;
-        const int b = (int)lds_need(kind, tx, 0, h, h2);  // the need is affine in ty
-        const int a = (int)lds_need(kind, tx, 1, h, h2) - b;
+        const bool sx = nxs > 1;
+        if (lds_need(kind, tx, ey, h, h2, sx, false) <= budget) {
+            t.nxs = nxs;
+            t.nys = 1;
+            t.tx = tx;
+            t.ty = ey;
+            return t;
+        }
+        const int b = (int)lds_need(kind, tx, 0, h, h2, sx, true);  // the need is affine in ty
+        const int a = (int)lds_need(kind, tx, 1, h, h2, sx, true) - b;
         if (budget - b < a) continue;
         const int tymax = (budget - b) / a;
         const int nys = (ey + tymax - 1) / tymax;
@@ -156,7 +169,7 @@ __device__ __forceinline__ long long xcd_item(long long n) {
 // Work item -> (grain, plane, tile origin, tile size).
 struct ItemTile {
     long long item;
-    int k, plane, x0, y0, wx, wy;
+    int k, plane, x0, y0, wx, wy, nxs, nys;
 };
 
 // The tiling of every grain and kind is computed once per layout (k_item_counts)
@@ -170,6 +183,8 @@ __device__ __forceinline__ ItemTile decode_item(long long item, int kind, const 
     const int e[3] = {L.ext[3 * it.k], L.ext[3 * it.k + 1], L.ext[3 * it.k + 2]};
     const int4 t4 = tilings[it.k];
     const Tiling tl = {t4.x, t4.y, t4.z, t4.w};
+    it.nxs = tl.nxs;
+    it.nys = tl.nys;
     const int per = tl.nxs * tl.nys;
     it.plane = sub / per;
     const int rem = sub - it.plane * per;
@@ -259,6 +274,82 @@ __device__ __forceinline__ void minplus_run(const T *src, int stride, int K, T b
                 if (c < best[q]) best[q] = c;
             }
         }
+    }
+}
+
+// Spreading along one line of `len` values (stride `stride`): the distance
+// grows by one per voxel, forward then backward.  A ring (a line over a whole
+// periodic axis) is swept twice around in each direction, starting at index 0.
+// Same order of operations as the definition: w = previous + 1; keep w if w < v.
+template <typename T> __device__ __forceinline__ void sweep_line(T *p, int stride, int len, bool ring) {
+    if (len <= 1) return;
+    T cur = p[0];
+    if (!ring) {
+#pragma unroll 4
+        for (int i = 1; i < len; ++i) {
+            const T v = p[i * stride], w = cur + T(1);
+            cur = w < v ? w : v;
+            p[i * stride] = cur;
+        }
+#pragma unroll 4
+        for (int i = len - 2; i >= 0; --i) {
+            const T v = p[i * stride], w = cur + T(1);
+            cur = w < v ? w : v;
+            p[i * stride] = cur;
+        }
+        return;
+    }
+    int i = 0;
+    for (int t = 1; t < 2 * len; ++t) {
+        i = i + 1 == len ? 0 : i + 1;
+        const T v = p[i * stride], w = cur + T(1);
+        cur = w < v ? w : v;
+        p[i * stride] = cur;
+    }
+    i = len - 1;
+    cur = p[i * stride];
+    for (int t = 1; t < 2 * len; ++t) {
+        i = i == 0 ? len - 1 : i - 1;
+        const T v = p[i * stride], w = cur + T(1);
+        cur = w < v ? w : v;
+        p[i * stride] = cur;
+    }
+}
+
+// The same on signed values whose sign bit marks the inside: the magnitude is
+// spread, the sign of every value is kept.
+template <typename T> __device__ __forceinline__ void sweep_line_signed(T *p, int stride, int len, bool ring) {
+    if (len <= 1) return;
+    T cur = fabs(p[0]);
+    if (!ring) {
+#pragma unroll 4
+        for (int i = 1; i < len; ++i) {
+            const T v = p[i * stride], w = cur + T(1), a = fabs(v);
+            cur = w < a ? w : a;
+            p[i * stride] = copysign(cur, v);
+        }
+#pragma unroll 4
+        for (int i = len - 2; i >= 0; --i) {
+            const T v = p[i * stride], w = cur + T(1), a = fabs(v);
+            cur = w < a ? w : a;
+            p[i * stride] = copysign(cur, v);
+        }
+        return;
+    }
+    int i = 0;
+    for (int t = 1; t < 2 * len; ++t) {
+        i = i + 1 == len ? 0 : i + 1;
+        const T v = p[i * stride], w = cur + T(1), a = fabs(v);
+        cur = w < a ? w : a;
+        p[i * stride] = copysign(cur, v);
+    }
+    i = len - 1;
+    cur = fabs(p[i * stride]);
+    for (int t = 1; t < 2 * len; ++t) {
+        i = i == 0 ? len - 1 : i - 1;
+        const T v = p[i * stride], w = cur + T(1), a = fabs(v);
+        cur = w < a ? w : a;
+        p[i * stride] = copysign(cur, v);
     }
 }
 
@@ -711,19 +802,19 @@ template <typename T> struct Carry {
     }
 };
 
-// Reference values next to the sign change and the x and y min-plus passes on
-// one tile of one z plane of the new box.  3D: writes the partial distance with
-// the inside flag as its sign bit; 2D: writes the final function and the tile's
-// volume.  Also carries the ID-field over to the new layout.
-template <typename T, int KS>
+// Reference values next to the sign change, then the x and y spreading sweeps,
+// on one tile of one z plane of the new box.  3D: writes the partial distance
+// with the inside flag as its sign bit; 2D: writes the final function and the
+// tile's volume.  Also carries the ID-field over to the new layout.
+template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_reinit_xy(Boxes Lo, Boxes Ln, const int *__restrict__ owner, const long long *__restrict__ pref,
-                const int4 *__restrict__ tilings, long long nitems, const T *__restrict__ phic, T *__restrict__ out, const int *__restrict__ iota_old,
-                int *__restrict__ iota_new, double *__restrict__ vol_part, int K_, T W, GridArgs g) {
+                const int4 *__restrict__ tilings, long long nitems, const T *__restrict__ phic, T *__restrict__ out,
+                const int *__restrict__ iota_old, int *__restrict__ iota_new, double *__restrict__ vol_part, int K,
+                T W, GridArgs g) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
     __shared__ double red[kBlock / 64];
-    const int K = KS ? KS : K_;
     const long long item = xcd_item(nitems);
     if (item >= nitems) return;
     const ItemTile it = decode_item(item, KIND_RXY, Ln, owner, pref, tilings);
@@ -741,13 +832,14 @@ __global__ void __launch_bounds__(kBlock)
         cr.d[a] = dd < 0 ? dd + g.n[a] : dd;
     }
     const int ex = cr.nex[0], ey = cr.nex[1];
-    const int FW = wx + 2 * K + 2, FP = FW | 1, FH = wy + 2 * K + 2;
-    const int RW = wx + 2 * K, RP = RW | 1, RH = wy + 2 * K;
-    T *f = sm, *ref = sm + FP * FH, *d1 = ref + RP * RH + kKB;
+    const int hx = it.nxs > 1 ? K : 0, hy = it.nys > 1 ? K : 0;
+    const int RW = wx + 2 * hx, RP = RW | 1, RH = wy + 2 * hy;
+    const int FW = RW + 2, FP = FW | 1, FH = RH + 2;
+    T *f = sm, *ref = sm + FP * FH;
     const T inf = tinf<T>();
     stage_rows<T>(
-        f, FP, FW, FH, phic, [&](int rr) { return cr.old_row(y0 - K - 1 + rr, z); },
-        [&](int cc) { return cr.old_col(x0 - K - 1 + cc); }, -W);
+        f, FP, FW, FH, phic, [&](int rr) { return cr.old_row(y0 - hy - 1 + rr, z); },
+        [&](int cc) { return cr.old_col(x0 - hx - 1 + cc); }, -W);
     __syncthreads();
     // reference values: waves own rows, lanes own columns; the z neighbours of
     // kLoadBatch rows are gathered before any is used
@@ -756,7 +848,7 @@ __global__ void __launch_bounds__(kBlock)
         const int nn = g.dim == 3 ? 6 : 4;
         for (int c0 = 0; c0 < RW; c0 += 64) {
             const int cc = c0 + lane;
-            const int x = x0 - K + cc;
+            const int x = x0 - hx + cc;
             const bool xin = cc < RW && axis_map(x, ex, g.n[0]) >= 0;
             const int oc = xin ? cr.old_col(x) : -1;
             for (int r0 = wave; r0 < RH; r0 += kWaves * kLoadBatch) {
@@ -766,7 +858,7 @@ __global__ void __launch_bounds__(kBlock)
                     const int rr = r0 + kWaves * j;
                     zm[j] = zp[j] = -W;
                     if (g.dim == 3 && rr < RH && oc >= 0) {
-                        const int y = y0 - K + rr;
+                        const int y = y0 - hy + rr;
                         const long long bm = cr.old_row(y, z - 1), bp = cr.old_row(y, z + 1);
                         if (bm >= 0) zm[j] = phic[bm + oc];
                         if (bp >= 0) zp[j] = phic[bp + oc];
@@ -777,7 +869,7 @@ __global__ void __launch_bounds__(kBlock)
                     const int rr = r0 + kWaves * j;
                     if (rr >= RH || cc >= RW) continue;
                     T r = inf;
-                    if (xin && axis_map(y0 - K + rr, ey, g.n[1]) >= 0) {
+                    if (xin && axis_map(y0 - hy + rr, ey, g.n[1]) >= 0) {
                         const T *fc_p = f + (rr + 1) * FP + cc + 1;
                         const T fc = fc_p[0];
                         const bool in = fc > T(0);
@@ -805,48 +897,33 @@ __global__ void __launch_bounds__(kBlock)
         }
     }
     __syncthreads();
-    const int ngx = (wx + kKB - 1) / kKB;
-    for (int e = threadIdx.x; e < ngx * RH; e += kBlock) {
-        const int rr = e % RH, c0 = (e / RH) * kKB;
-        T best[kKB];
-        if (axis_map(y0 - K + rr, ey, g.n[1]) < 0) {
-#pragma unroll
-            for (int q = 0; q < kKB; ++q) best[q] = inf;
-        } else {
-            minplus_run<T, KS>(ref + rr * RP + c0, 1, K, best, false);
-        }
-#pragma unroll
-        for (int q = 0; q < kKB; ++q)
-            if (c0 + q < wx) d1[rr * wx + c0 + q] = best[q];
-    }
+    // spreading: x along rows, then y along columns (one lane per line)
+    const bool ringx = it.nxs == 1 && ex == g.n[0];
+    for (int rr = threadIdx.x; rr < RH; rr += kBlock) sweep_line<T>(ref + rr * RP, 1, RW, ringx);
+    __syncthreads();
+    const bool ringy = it.nys == 1 && ey == g.n[1];
+    for (int cc = threadIdx.x; cc < RW; cc += kBlock) sweep_line<T>(ref + cc, RP, RH, ringy);
     __syncthreads();
     const long long base = Ln.off[k] + (long long)z * ex * ey;
     double vsum = 0.0;
-    const int ngy = (wy + kKB - 1) / kKB;
-    for (int e = threadIdx.x; e < ngy * wx; e += kBlock) {
-        const int c = e % wx, r0 = (e / wx) * kKB;
-        T best[kKB];
-        minplus_run<T, KS>(d1 + r0 * wx + c, wx, K, best, false);
-#pragma unroll
-        for (int q = 0; q < kKB; ++q) {
-            const int r = r0 + q;
-            if (r >= wy) break;
-            const bool in = f[(r + K + 1) * FP + c + K + 1] > T(0);
-            const long long idx = base + (long long)(y0 + r) * ex + x0 + c;
-            if (g.dim == 2) {
-                const T d = best[q] < W ? best[q] : W;
-                const T p = in ? d : -d;
-                out[idx] = p;
-                double cl = (double)p + 0.5;
-                cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
-                vsum += cl;
-            } else {
-                out[idx] = in ? best[q] : -best[q];
-            }
-            if (iota_new) {
-                const long long oi = cr.old_index(x0 + c, y0 + r, z);
-                iota_new[idx] = oi >= 0 ? iota_old[oi] : -1;
-            }
+    for (int e = threadIdx.x; e < wx * wy; e += kBlock) {
+        const int r = e / wx, c = e - r * wx;
+        const T d = ref[(r + hy) * RP + c + hx];
+        const bool in = f[(r + hy + 1) * FP + c + hx + 1] > T(0);
+        const long long idx = base + (long long)(y0 + r) * ex + x0 + c;
+        if (g.dim == 2) {
+            const T dc = d < W ? d : W;
+            const T p = in ? dc : -dc;
+            out[idx] = p;
+            double cl = (double)p + 0.5;
+            cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
+            vsum += cl;
+        } else {
+            out[idx] = in ? d : -d;
+        }
+        if (iota_new) {
+            const long long oi = cr.old_index(x0 + c, y0 + r, z);
+            iota_new[idx] = oi >= 0 ? iota_old[oi] : -1;
         }
     }
     if (g.dim == 2) {
@@ -856,26 +933,26 @@ __global__ void __launch_bounds__(kBlock)
 }
 
 // Fused z sweep (3D) over one tile (x chunk * z range) of one y row of the new
-// box: z min-plus pass, sign and band clamp -> phi (optionally stored) and the
+// box: z spreading, sign and band clamp -> phi (optionally stored) and the
 // tile's volume; then the next predictor's z pass of phi -> t.
-template <typename T, int KS, int RS>
+template <typename T, int RS>
 __global__ void __launch_bounds__(kBlock)
     k_zfused(Boxes Ln, const int *__restrict__ owner, const long long *__restrict__ pref,
-             const int4 *__restrict__ tilings, long long nitems,
-             const T *__restrict__ d2,
-             T *__restrict__ phi_out, T *__restrict__ t_out, double *__restrict__ vol_part, const T *__restrict__ taps,
-             int K_, int R_, T W, GridArgs g) {
+             const int4 *__restrict__ tilings, long long nitems, const T *__restrict__ d2, T *__restrict__ phi_out,
+             T *__restrict__ t_out, double *__restrict__ vol_part, const T *__restrict__ taps, int K, int R_, T W,
+             GridArgs g) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
     __shared__ double red[kBlock / 64];
-    const int K = KS ? KS : K_, R = RS ? RS : R_;
+    const int R = RS ? RS : R_;
     const long long item = xcd_item(nitems);
     if (item >= nitems) return;
     const ItemTile it = decode_item(item, KIND_ZF, Ln, owner, pref, tilings);
     const int k = it.k, y = it.plane, x0 = it.x0, z0 = it.y0, wx = it.wx, wz = it.wy;
     const int ex = Ln.ext[3 * k], ey = Ln.ext[3 * k + 1], ez = Ln.ext[3 * k + 2];
-    const int DH = wz + 2 * (K + R), PH = wz + 2 * R;
-    T *dc = sm, *pc = sm + wx * (DH + kKB);
+    const int hz = it.nys > 1 ? K : 0;
+    const int DH = wz + 2 * R + 2 * hz, PH = wz + 2 * R;
+    T *dc = sm, *pc = sm + wx * DH;
     const long long plane = (long long)ex * ey;
     const long long rowbase = Ln.off[k] + (long long)y * ex + x0;
     T tp[RS > 0 ? 2 * RS + 1 : 1];
@@ -887,30 +964,38 @@ __global__ void __launch_bounds__(kBlock)
     stage_rows<T>(
         dc, wx, wx, DH, d2,
         [&](int rr) -> long long {
-            const int zz = axis_map(z0 - K - R + rr, ez, g.n[2]);
+            const int zz = axis_map(z0 - R - hz + rr, ez, g.n[2]);
             return zz >= 0 ? rowbase + (long long)zz * plane : -1;
         },
         [&](int c) { return c; }, inf);
     __syncthreads();
-    const int ngp = (PH + kKB - 1) / kKB;
-    for (int e = threadIdx.x; e < ngp * wx; e += kBlock) {
-        const int c = e % wx, r0 = (e / wx) * kKB;
-        T best[kKB];
-        minplus_run<T, KS>(dc + r0 * wx + c, wx, K, best, true);
-#pragma unroll
-        for (int q = 0; q < kKB; ++q) {
-            const int r = r0 + q;
-            if (r >= PH) break;
-            T p;
-            if (axis_map(z0 - R + r, ez, g.n[2]) < 0) {
-                p = -W;  // outside the box the predictor reads the fill value
-            } else {
-                const bool in = !signbit(dc[(r + K) * wx + c]);
-                const T d = best[q] < W ? best[q] : W;
-                p = in ? d : -d;
+    // z spreading, one lane per column; a whole periodic z axis is a ring whose
+    // copies in the halo rows are refreshed afterwards
+    const bool ring = it.nys == 1 && ez == g.n[2];
+    for (int c = threadIdx.x; c < wx; c += kBlock) {
+        if (ring) {
+            sweep_line_signed<T>(dc + R * wx + c, wx, ez, true);
+            for (int j = 0; j < R; ++j) {
+                dc[j * wx + c] = dc[(ez + j) * wx + c];
+                dc[(R + ez + j) * wx + c] = dc[(R + j) * wx + c];
             }
-            pc[r * wx + c] = p;
+        } else {
+            sweep_line_signed<T>(dc + c, wx, DH, false);
         }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < wx * PH; e += kBlock) {
+        const int r = e / wx, c = e - r * wx;
+        T p;
+        if (axis_map(z0 - R + r, ez, g.n[2]) < 0) {
+            p = -W;  // outside the box the predictor reads the fill value
+        } else {
+            const T v = dc[(r + hz) * wx + c];
+            const T a = fabs(v);
+            const T d = a < W ? a : W;
+            p = signbit(v) ? -d : d;
+        }
+        pc[r * wx + c] = p;
     }
     __syncthreads();
     double vsum = 0.0;
@@ -1076,7 +1161,7 @@ __global__ void k_item_counts(Boxes L, long long *c0, long long *c1, long long *
         cs[q][k] = kind_items(q, e, R, K, budget);
         int h, h2;
         kind_halos(q, R, K, &h, &h2);
-        atomicMax(&lds_max[q], (unsigned long long)lds_need(q, t.tx, t.ty, h, h2));
+        atomicMax(&lds_max[q], (unsigned long long)lds_need(q, t.tx, t.ty, h, h2, t.nxs > 1, t.nys > 1));
     }
 }
 

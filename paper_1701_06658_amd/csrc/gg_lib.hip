@@ -473,9 +473,7 @@ template <typename T> struct Sim final : SimBase {
             auto go = [&](auto kern) {
                 std::apply([&](auto... a) { hipLaunchKernelGGL(kern, gr, bl, lds, stream, a...); }, args);
             };
-            if (K == 6) go(gg::k_reinit_xy<T, 6>);
-            else if (K == 8) go(gg::k_reinit_xy<T, 8>);
-            else go(gg::k_reinit_xy<T, 0>);
+            go(gg::k_reinit_xy<T>);
             tend();
         }
         if (dim == 3 && t.items[gg::KIND_ZF] > 0) {
@@ -489,9 +487,9 @@ template <typename T> struct Sim final : SimBase {
             auto go = [&](auto kern) {
                 std::apply([&](auto... a) { hipLaunchKernelGGL(kern, gr, bl, lds, stream, a...); }, args);
             };
-            if (K == 6 && R == 6) go(gg::k_zfused<T, 6, 6>);
-            else if (K == 8 && R == 8) go(gg::k_zfused<T, 8, 8>);
-            else go(gg::k_zfused<T, 0, 0>);
+            if (R == 6) go(gg::k_zfused<T, 6>);
+            else if (R == 8) go(gg::k_zfused<T, 8>);
+            else go(gg::k_zfused<T, 0>);
             tend();
         }
         const int tb = 256, gb = (G + tb - 1) / tb;
