@@ -163,3 +163,57 @@ def test_mixed_one_step_config2():
     c = make_config(2)
     o = Oracle(c["labels"], c["W"], G=c["G"])
     _mixed_one_step(o, c["dt"], c["W"], c["G"], "cfg2 from step 0")
+
+
+def _physics_inputs(kind, N=64, G=200, seed=7):
+    from synth import (magnetic_energy_density, random_unit_vectors, rsa_power_diagram,
+                       shoemake_quaternions)
+    rng = np.random.default_rng(seed)
+    n = (N, N, N)
+    if kind == "misorientation":
+        labels = power_labels(n, uniform_voronoi(n, G, rng))
+        quat = shoemake_quaternions(G, rng)
+        return labels, dict(physics=1, quat=quat, theta_c_deg=15.0), dict(mode=1, quat=quat,
+                                                                          theta_c_deg=15.0)
+    radii = np.ones(G)
+    radii[: G // 20] = 4.0
+    seeds, w = rsa_power_diagram(n, radii, rng, packing=0.3)
+    labels = power_labels(n, seeds, w)
+    energy = magnetic_energy_density(random_unit_vectors(G, rng, 3), [0, 0, 1], 1.18e-5, 17.0)
+    # a coarse voxel so that the bulk displacement (~0.2 voxel/step) is well above rounding
+    h, gam = 2.0e-5, 0.3
+    gpu = dict(physics=2, energy=energy, voxel_m=h, gamma_max=gam)
+    orc = dict(mode=2, energy=energy, h_phys=h, gamma_max=gam)
+    return labels, gpu, orc
+
+
+@pytest.mark.parametrize("kind", ["misorientation", "bulk"])
+def test_fp64_predictor_correction_trajectory(kind):
+    gg = _gpu()
+    labels, gphys, ophys = _physics_inputs(kind)
+    G = int(labels.max()) + 1
+    W, sigma = 8.0, 2.0
+    o = Oracle(labels, W, G=G)
+    o.set_physics(**ophys)
+    s = gg.Simulation(labels, W, G=G, precision="fp64", **gphys)
+    dt = config_dt(sigma, labels.shape[0])
+    # the initial ID-fields agree (argmax of the other grains' functions)
+    _, io_gpu = s.iota()
+    io_orc = np.concatenate([o.iota(k).ravel() for k in range(G) if o.box(k)[0]])
+    assert np.array_equal(io_gpu, io_orc)
+    for step in range(1, 5):
+        o.step(dt)
+        s.step(dt)
+        _check_fp64(o, s, W, f"{kind} step {step}")
+
+
+@pytest.mark.parametrize("kind", ["misorientation", "bulk"])
+def test_mixed_one_step_predictor_correction(kind):
+    labels, gphys, ophys = _physics_inputs(kind)
+    G = int(labels.max()) + 1
+    W, sigma = 8.0, 2.0
+    o = Oracle(labels, W, G=G)
+    o.set_physics(**ophys)
+    dt = config_dt(sigma, labels.shape[0])
+    o.step(dt, 2)
+    _mixed_one_step(o, dt, W, G, f"{kind} mixed", **gphys)
