@@ -649,8 +649,52 @@ __global__ void __launch_bounds__(kBlock)
     Top2<T> top[kVpt];
 #pragma unroll
     for (int i = 0; i < kVpt; ++i) top[i].init();
-    constexpr int U = 4;  // grains per batch: their loads are issued together
-    for (int c0 = b; c0 < e; c0 += U) {
+    // Local coordinates of the thread's voxels in box j; hit = inside the box.
+    auto locate = [&](int j, long long idx[kVpt], bool hit[kVpt], int l3[kVpt][3]) {
+        const int lx0 = L.lo[3 * j], ly0 = L.lo[3 * j + 1], lz0 = L.lo[3 * j + 2];
+        const int ex = L.ext[3 * j], ey = L.ext[3 * j + 1], ez = L.ext[3 * j + 2];
+        const long long off = L.off[j];
+#pragma unroll
+        for (int i = 0; i < kVpt; ++i) {
+            const int lx = wrap_diff(gx[i], lx0, ta.n[0]), ly = wrap_diff(gy[i], ly0, ta.n[1]),
+                      lz = wrap_diff(gz[i], lz0, ta.n[2]);
+            hit[i] = valid[i] && lx < ex && ly < ey && lz < ez;
+            idx[i] = off + lx + (long long)ex * (ly + (long long)ey * lz);
+            l3[i][0] = lx;
+            l3[i][1] = ly;
+            l3[i][2] = lz;
+        }
+    };
+    // pass 1: top-2.  The first CR grains' values stay in registers for pass 2;
+    // U grains' loads are issued together.
+    constexpr int CR = sizeof(T) == 4 ? 24 : 12;
+    constexpr int U = 4;
+    T cache[CR][kVpt];
+#pragma unroll
+    for (int c0 = 0; c0 < CR; c0 += U) {
+        int jj[U];
+        bool hit[U][kVpt];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int c = b + c0 + u;
+            jj[u] = c < e ? cov_list[c] : -1;
+            long long idx[kVpt];
+            int l3[kVpt][3];
+#pragma unroll
+            for (int i = 0; i < kVpt; ++i) hit[u][i] = false;
+            if (jj[u] < 0) continue;
+            locate(jj[u], idx, hit[u], l3);
+#pragma unroll
+            for (int i = 0; i < kVpt; ++i)
+                if (hit[u][i]) cache[c0 + u][i] = psi[idx[i]];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int i = 0; i < kVpt; ++i)
+                if (hit[u][i]) top[i].push(cache[c0 + u][i], jj[u]);
+    }
+    for (int c0 = b + CR; c0 < e; c0 += U) {
         T v[U][kVpt];
         int jj[U];
         bool hit[U][kVpt];
@@ -658,20 +702,15 @@ __global__ void __launch_bounds__(kBlock)
         for (int u = 0; u < U; ++u) {
             const int c = c0 + u;
             jj[u] = c < e ? cov_list[c] : -1;
+            long long idx[kVpt];
+            int l3[kVpt][3];
 #pragma unroll
             for (int i = 0; i < kVpt; ++i) hit[u][i] = false;
             if (jj[u] < 0) continue;
-            const int j = jj[u];
-            const int lx0 = L.lo[3 * j], ly0 = L.lo[3 * j + 1], lz0 = L.lo[3 * j + 2];
-            const int ex = L.ext[3 * j], ey = L.ext[3 * j + 1], ez = L.ext[3 * j + 2];
-            const long long off = L.off[j];
+            locate(jj[u], idx, hit[u], l3);
 #pragma unroll
-            for (int i = 0; i < kVpt; ++i) {
-                const int lx = wrap_diff(gx[i], lx0, ta.n[0]), ly = wrap_diff(gy[i], ly0, ta.n[1]),
-                          lz = wrap_diff(gz[i], lz0, ta.n[2]);
-                hit[u][i] = valid[i] && lx < ex && ly < ey && lz < ez;
-                if (hit[u][i]) v[u][i] = psi[off + lx + (long long)ex * (ly + (long long)ey * lz)];
-            }
+            for (int i = 0; i < kVpt; ++i)
+                if (hit[u][i]) v[u][i] = psi[idx[i]];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -679,41 +718,33 @@ __global__ void __launch_bounds__(kBlock)
             for (int i = 0; i < kVpt; ++i)
                 if (hit[u][i]) top[i].push(v[u][i], jj[u]);
     }
-    for (int c = b; c < e; ++c) {
-        const int j = cov_list[c];
-        const int lx0 = L.lo[3 * j], ly0 = L.lo[3 * j + 1], lz0 = L.lo[3 * j + 2];
-        const int ex = L.ext[3 * j], ey = L.ext[3 * j + 1], ez = L.ext[3 * j + 2];
-        const long long off = L.off[j];
+    // pass 2: the corrected function of every covering grain
+    auto emit = [&](int j, const T val[kVpt], const bool hit[kVpt], const long long idx[kVpt],
+                    const int l3[kVpt][3]) {
+        const int e3[3] = {L.ext[3 * j], L.ext[3 * j + 1], L.ext[3 * j + 2]};
         int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-1, -1, -1};
 #pragma unroll
         for (int i = 0; i < kVpt; ++i) {
-            const int lx = wrap_diff(gx[i], lx0, ta.n[0]), ly = wrap_diff(gy[i], ly0, ta.n[1]),
-                      lz = wrap_diff(gz[i], lz0, ta.n[2]);
-            if (!(valid[i] && lx < ex && ly < ey && lz < ez)) continue;
-            const long long idx = off + lx + (long long)ex * (ly + (long long)ey * lz);
+            if (!hit[i]) continue;
             const bool first = top[i].i1 == j;
             const int other = first ? top[i].i2 : top[i].i1;
-            if (iota_out) iota_out[idx] = other;
+            if (iota_out) iota_out[idx[i]] = other;
             if (mode != 0) continue;
             const T m = first ? (top[i].i2 < 0 ? -W : top[i].m2) : top[i].m1;
-            const T pc = T(0.5) * (psi[idx] - m);
-            phic[idx] = pc;
+            const T pc = T(0.5) * (val[i] - m);
+            phic[idx[i]] = pc;
             if (pc > T(0)) {
-                const int l3[3] = {lx, ly, lz};
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    mn[a] = min(mn[a], l3[a]);
-                    mx[a] = max(mx[a], l3[a]);
-                }
-                const int e3[3] = {ex, ey, ez};
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
+                    mn[a] = min(mn[a], l3[i][a]);
+                    mx[a] = max(mx[a], l3[i][a]);
                     if (e3[a] == ta.n[a])
-                        atomicOr(&occ[((long long)j * 3 + a) * ta.occ_words + (l3[a] >> 5)], 1u << (l3[a] & 31));
+                        atomicOr(&occ[((long long)j * 3 + a) * ta.occ_words + (l3[i][a] >> 5)], 1u << (l3[i][a] & 31));
+                }
             }
         }
-        if (mode != 0) continue;
-        if (__ballot(mx[0] >= 0) == 0) continue;
+        if (mode != 0) return;
+        if (__ballot(mx[0] >= 0) == 0) return;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             mn[a] = wave_min(mn[a]);
@@ -726,6 +757,29 @@ __global__ void __launch_bounds__(kBlock)
                 atomicMax(&bmax[3 * j + a], mx[a]);
             }
         }
+    };
+#pragma unroll
+    for (int cc = 0; cc < CR; ++cc) {
+        const int c = b + cc;
+        if (c >= e) break;
+        const int j = cov_list[c];
+        long long idx[kVpt];
+        bool hit[kVpt];
+        int l3[kVpt][3];
+        locate(j, idx, hit, l3);
+        emit(j, cache[cc], hit, idx, l3);
+    }
+    for (int c = b + CR; c < e; ++c) {
+        const int j = cov_list[c];
+        long long idx[kVpt];
+        bool hit[kVpt];
+        int l3[kVpt][3];
+        locate(j, idx, hit, l3);
+        T val[kVpt];
+#pragma unroll
+        for (int i = 0; i < kVpt; ++i)
+            if (hit[i]) val[i] = psi[idx[i]];
+        emit(j, val, hit, idx, l3);
     }
 }
 

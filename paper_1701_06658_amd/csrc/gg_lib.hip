@@ -430,8 +430,11 @@ template <typename T> struct Sim final : SimBase {
         auto go = [&](auto kern) {
             std::apply([&](auto... a) { hipLaunchKernelGGL(kern, gr, bl, lds, stream, a...); }, args);
         };
-        if (ph.mode) go(gg::k_conv_xy<T, 0, true>);
-        else if (R == 6) go(gg::k_conv_xy<T, 6, false>);
+        if (ph.mode) {
+            if (R == 6) go(gg::k_conv_xy<T, 6, true>);
+            else if (R == 8) go(gg::k_conv_xy<T, 8, true>);
+            else go(gg::k_conv_xy<T, 0, true>);
+        } else if (R == 6) go(gg::k_conv_xy<T, 6, false>);
         else if (R == 8) go(gg::k_conv_xy<T, 8, false>);
         else go(gg::k_conv_xy<T, 0, false>);
         tend();
