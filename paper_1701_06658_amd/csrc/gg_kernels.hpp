@@ -43,12 +43,17 @@ struct Boxes {
     long long *off;  // G + 1: exclusive prefix of box volumes
 };
 
+// Work items of every kind come in two launch classes by their LDS need, so
+// that the many small boxes are not launched with the LDS of the largest one.
+constexpr int kSmallLdsBytes = 20480;
+constexpr int kClasses = 2;
+
 struct Totals {
-    long long arena;        // sum of box volumes
-    long long items[kKinds];
-    long long cov;          // coverage list entries
-    long long alive;        // alive grains
-    long long lds[kKinds];  // largest LDS need of any item, in values
+    long long arena;                  // sum of box volumes
+    long long items[kKinds][3];       // all, class 0, class 1
+    long long cov;                    // coverage list entries
+    long long alive;                  // alive grains
+    long long lds[kKinds][kClasses];  // largest LDS need per class, in values
 };
 
 // ------------------------------------------------------------------ helpers
@@ -174,12 +179,22 @@ struct ItemTile {
 
 // The tiling of every grain and kind is computed once per layout (k_item_counts)
 // and stored as int4 (nxs, nys, tx, ty).
-__device__ __forceinline__ ItemTile decode_item(long long item, int kind, const Boxes &L, const int *owner,
-                                                const long long *pref, const int4 *tilings) {
+// Items of one class: owner[item] is the grain, pref the class prefix over
+// grains; pref_all (all items of the kind) gives the item's global index.
+struct ItemRefs {
+    const int *owner;
+    const long long *pref;
+    const long long *pref_all;
+    const int4 *tilings;
+    long long n;
+};
+
+__device__ __forceinline__ ItemTile decode_item(long long item, int kind, const Boxes &L, const ItemRefs &ir) {
     ItemTile it;
-    it.item = item;
-    it.k = owner[item];
-    const int sub = (int)(item - pref[it.k]);
+    it.k = ir.owner[item];
+    const int sub = (int)(item - ir.pref[it.k]);
+    it.item = ir.pref_all[it.k] + sub;
+    const int4 *tilings = ir.tilings;
     const int e[3] = {L.ext[3 * it.k], L.ext[3 * it.k + 1], L.ext[3 * it.k + 2]};
     const int4 t4 = tilings[it.k];
     const Tiling tl = {t4.x, t4.y, t4.z, t4.w};
@@ -493,16 +508,14 @@ struct GridArgs {
 // correction epilogue; the output is the predicted function psi.
 template <typename T, int RS, bool PH>
 __global__ void __launch_bounds__(kBlock)
-    k_conv_xy(Boxes L, const int *__restrict__ owner, const long long *__restrict__ pref,
-              const int4 *__restrict__ tilings, long long nitems,
-              const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ taps, int R_, T W, GridArgs g,
-              Physics<T> ph) {
+    k_conv_xy(Boxes L, ItemRefs ir, const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ taps,
+              int R_, T W, GridArgs g, Physics<T> ph) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
     const int R = RS ? RS : R_;
-    const long long item = xcd_item(nitems);
-    if (item >= nitems) return;
-    const ItemTile it = decode_item(item, KIND_CXY, L, owner, pref, tilings);
+    const long long item = xcd_item(ir.n);
+    if (item >= ir.n) return;
+    const ItemTile it = decode_item(item, KIND_CXY, L, ir);
     const int k = it.k, z = it.plane, x0 = it.x0, y0 = it.y0, wx = it.wx, wy = it.wy;
     const int ex = L.ext[3 * k], ey = L.ext[3 * k + 1];
     const int RW = wx + 2 * R, RP = RW | 1, RH = wy + 2 * R;
@@ -556,14 +569,13 @@ __global__ void __launch_bounds__(kBlock)
 // Predictor z pass on its own (first step after create / load / a new dt).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-    k_conv_z(Boxes L, const int *__restrict__ owner, const long long *__restrict__ pref,
-             const int4 *__restrict__ tilings, long long nitems,
-             const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ taps, int R, T W, GridArgs g) {
+    k_conv_z(Boxes L, ItemRefs ir, const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ taps, int R,
+             T W, GridArgs g) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *col = reinterpret_cast<T *>(smem_raw);
-    const long long item = xcd_item(nitems);
-    if (item >= nitems) return;
-    const ItemTile it = decode_item(item, KIND_CZ, L, owner, pref, tilings);
+    const long long item = xcd_item(ir.n);
+    if (item >= ir.n) return;
+    const ItemTile it = decode_item(item, KIND_CZ, L, ir);
     const int k = it.k, y = it.plane, x0 = it.x0, z0 = it.y0, wx = it.wx, wz = it.wy;
     const int ex = L.ext[3 * k], ey = L.ext[3 * k + 1], ez = L.ext[3 * k + 2];
     const int CH = wz + 2 * R;
@@ -862,16 +874,16 @@ template <typename T> struct Carry {
 // tile's volume.  Also carries the ID-field over to the new layout.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-    k_reinit_xy(Boxes Lo, Boxes Ln, const int *__restrict__ owner, const long long *__restrict__ pref,
-                const int4 *__restrict__ tilings, long long nitems, const T *__restrict__ phic, T *__restrict__ out,
+    k_reinit_xy(Boxes Lo, Boxes Ln, ItemRefs ir, const T *__restrict__ phic, T *__restrict__ out,
                 const int *__restrict__ iota_old, int *__restrict__ iota_new, double *__restrict__ vol_part, int K,
                 T W, GridArgs g) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
     __shared__ double red[kBlock / 64];
-    const long long item = xcd_item(nitems);
-    if (item >= nitems) return;
-    const ItemTile it = decode_item(item, KIND_RXY, Ln, owner, pref, tilings);
+    const long long cls_item = xcd_item(ir.n);
+    if (cls_item >= ir.n) return;
+    const ItemTile it = decode_item(cls_item, KIND_RXY, Ln, ir);
+    const long long item = it.item;
     const int k = it.k, z = it.plane, x0 = it.x0, y0 = it.y0, wx = it.wx, wy = it.wy;
     Carry<T> cr;
     cr.src = phic;
@@ -991,17 +1003,17 @@ __global__ void __launch_bounds__(kBlock)
 // tile's volume; then the next predictor's z pass of phi -> t.
 template <typename T, int RS>
 __global__ void __launch_bounds__(kBlock)
-    k_zfused(Boxes Ln, const int *__restrict__ owner, const long long *__restrict__ pref,
-             const int4 *__restrict__ tilings, long long nitems, const T *__restrict__ d2, T *__restrict__ phi_out,
+    k_zfused(Boxes Ln, ItemRefs ir, const T *__restrict__ d2, T *__restrict__ phi_out,
              T *__restrict__ t_out, double *__restrict__ vol_part, const T *__restrict__ taps, int K, int R_, T W,
              GridArgs g) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
     __shared__ double red[kBlock / 64];
     const int R = RS ? RS : R_;
-    const long long item = xcd_item(nitems);
-    if (item >= nitems) return;
-    const ItemTile it = decode_item(item, KIND_ZF, Ln, owner, pref, tilings);
+    const long long cls_item = xcd_item(ir.n);
+    if (cls_item >= ir.n) return;
+    const ItemTile it = decode_item(cls_item, KIND_ZF, Ln, ir);
+    const long long item = it.item;
     const int k = it.k, y = it.plane, x0 = it.x0, z0 = it.y0, wx = it.wx, wz = it.wy;
     const int ex = Ln.ext[3 * k], ey = Ln.ext[3 * k + 1], ez = Ln.ext[3 * k + 2];
     const int hz = it.nys > 1 ? K : 0;
@@ -1190,33 +1202,61 @@ __global__ void k_plan(Boxes Lo, Boxes Ln, int *bmin, int *bmax, unsigned *occ, 
     }
 }
 
-// Per-grain work item counts of the four stencil kinds and the largest LDS need.
-__global__ void k_item_counts(Boxes L, long long *c0, long long *c1, long long *c2, long long *c3, int4 *tilings,
-                              unsigned long long *lds_max, int R, int K, int G, int budget) {
+// Per-grain work item counts of the four stencil kinds, split into the two
+// launch classes, the stored tilings, and the largest LDS need per class.
+// cnt holds 3 arrays of G per kind: all items, class 0, class 1.
+__global__ void k_item_counts(Boxes L, long long *cnt, int4 *tilings, unsigned long long *lds_max, int R, int K, int G,
+                              int budget, int small) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= G) return;
-    long long *cs[4] = {c0, c1, c2, c3};
-    if (!L.alive[k]) {
-        for (int q = 0; q < 4; ++q) {
-            cs[q][k] = 0;
-            tilings[(long long)q * G + k] = make_int4(0, 0, 0, 0);
-        }
-        return;
-    }
-    const int *e = L.ext + 3 * k;
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kKinds; ++q) {
+        long long *c = cnt + (long long)q * 3 * G;
+        c[k] = c[G + k] = c[2LL * G + k] = 0;
+        tilings[(long long)q * G + k] = make_int4(0, 0, 0, 0);
+        if (!L.alive[k]) continue;
+        const int *e = L.ext + 3 * k;
         const Tiling t = kind_tiling(q, e, R, K, budget);
         tilings[(long long)q * G + k] = make_int4(t.nxs, t.nys, t.tx, t.ty);
         if (t.nxs == 0) {
-            cs[q][k] = 0;
-            atomicMax(&lds_max[q], 0xffffffffffffffffULL);  // infeasible tiling
+            atomicMax(&lds_max[q * kClasses + 1], 0xffffffffffffffffULL);  // infeasible tiling
             continue;
         }
-        cs[q][k] = kind_items(q, e, R, K, budget);
+        const long long n = kind_items(q, e, R, K, budget);
         int h, h2;
         kind_halos(q, R, K, &h, &h2);
-        atomicMax(&lds_max[q], (unsigned long long)lds_need(q, t.tx, t.ty, h, h2, t.nxs > 1, t.nys > 1));
+        const long long need = lds_need(q, t.tx, t.ty, h, h2, t.nxs > 1, t.nys > 1);
+        const int cls = need <= small ? 0 : 1;
+        c[k] = n;
+        c[(1LL + cls) * G + k] = n;
+        atomicMax(&lds_max[q * kClasses + cls], (unsigned long long)need);
     }
+}
+
+// Exclusive prefix sums of several arrays of n values (one work group each):
+// array m is in[m * n ..], its prefix out[m * (n + 1) ..].
+__global__ void __launch_bounds__(1024) k_scan_multi(const long long *in, long long *out, int n) {
+    __shared__ long long part[1024];
+    const long long *src = in + (long long)blockIdx.x * n;
+    long long *dst = out + (long long)blockIdx.x * (n + 1);
+    const int t = threadIdx.x;
+    const int chunk = (n + 1023) / 1024;
+    const int b = min(t * chunk, n), e = min(b + chunk, n);
+    long long s = 0;
+    for (int i = b; i < e; ++i) s += src[i];
+    part[t] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const long long v = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    long long base = t ? part[t - 1] : 0;
+    for (int i = b; i < e; ++i) {
+        dst[i] = base;
+        base += src[i];
+    }
+    if (t == 1023) dst[n] = part[1023];
 }
 
 // Exclusive prefix sum of n values (out has n + 1 entries), one work group.
@@ -1266,10 +1306,16 @@ __global__ void __launch_bounds__(1024) k_scan_int(const int *in, int *out, int 
     if (t == 1023) out[n] = (int)part[1023];
 }
 
-// item -> grain maps of one kind.
-__global__ void k_fill_owner(const long long *pref, int *owner, int G) {
-    const int k = blockIdx.x;
-    const long long b = pref[k], e = pref[k + 1];
+// item -> grain maps, one per (kind, class) = blockIdx.y; pref holds the
+// prefixes of one layout (3 per kind: all, class 0, class 1).
+struct OwnerMaps {
+    int *owner[kKinds * kClasses];
+};
+__global__ void k_fill_owner(const long long *pref, OwnerMaps om, int G) {
+    const int k = blockIdx.x, q = blockIdx.y / kClasses, c = blockIdx.y % kClasses;
+    const long long *p = pref + ((long long)q * 3 + 1 + c) * (G + 1);
+    int *owner = om.owner[blockIdx.y];
+    const long long b = p[k], e = p[k + 1];
     for (long long i = b + threadIdx.x; i < e; i += blockDim.x) owner[i] = k;
 }
 
@@ -1317,17 +1363,15 @@ __global__ void k_volumes(const Boxes L, const long long *pref, const double *vo
     vol[k] = s;
 }
 
-__global__ void k_totals(const long long *arena_pref, const long long *p0, const long long *p1, const long long *p2,
-                         const long long *p3, const int *cov_off, int ntiles, const int *alive, int G,
-                         const unsigned long long *lds_max, Totals *t) {
+__global__ void k_totals(const long long *arena_pref, const long long *pref, const int *cov_off, int ntiles,
+                         const int *alive, int G, const unsigned long long *lds_max, Totals *t) {
     if (threadIdx.x == 0) {
         t->arena = arena_pref[G];
-        t->items[0] = p0[G];
-        t->items[1] = p1[G];
-        t->items[2] = p2[G];
-        t->items[3] = p3[G];
+        for (int q = 0; q < kKinds; ++q)
+            for (int j = 0; j < 3; ++j) t->items[q][j] = pref[((long long)q * 3 + j) * (G + 1) + G];
         t->cov = cov_off ? cov_off[ntiles] : 0;
-        for (int q = 0; q < 4; ++q) t->lds[q] = (long long)lds_max[q];
+        for (int q = 0; q < kKinds; ++q)
+            for (int c = 0; c < kClasses; ++c) t->lds[q][c] = (long long)lds_max[q * kClasses + c];
     }
     __shared__ int cnt;
     if (threadIdx.x == 0) cnt = 0;

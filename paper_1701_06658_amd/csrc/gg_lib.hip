@@ -106,13 +106,13 @@ template <typename T> struct Sim final : SimBase {
 
     // layouts 0/1: box tables and work items
     DBuf lo[2], ext[2], alive[2], off[2];
-    DBuf ipref[2][gg::kKinds], iowner[2][gg::kKinds], itile[2];
+    DBuf ipref[2], iowner[2][gg::kKinds * gg::kClasses], itile[2];
     int items_R[2] = {-1, -1};
     Totals tot[2];
     int cur = 0;
 
     // per step accumulators and scratch
-    DBuf bmin, bmax, occ, sizes, cnt[gg::kKinds], ldsmax, vol, vol_part;
+    DBuf bmin, bmax, occ, sizes, cnt, ldsmax, vol, vol_part;
     DBuf cov_cnt, cov_off, cov_cur, cov_list;
     DBuf taps_d, quat_d, energy_d, totals_d;
     Totals *totals_h = nullptr;
@@ -250,7 +250,7 @@ template <typename T> struct Sim final : SimBase {
             ext[l].ensure(sizeof(int) * 3 * G);
             alive[l].ensure(sizeof(int) * G);
             off[l].ensure(sizeof(long long) * (G + 1));
-            for (int q = 0; q < gg::kKinds; ++q) ipref[l][q].ensure(sizeof(long long) * (G + 1));
+            ipref[l].ensure(sizeof(long long) * 3 * gg::kKinds * (size_t)(G + 1));
             itile[l].ensure(sizeof(int4) * gg::kKinds * (size_t)G);
         }
         bmin.ensure(sizeof(int) * 3 * G);
@@ -261,8 +261,8 @@ template <typename T> struct Sim final : SimBase {
         HIPCHECK(hipMemcpyAsync(bmin.p, init_min.data(), sizeof(int) * 3 * G, hipMemcpyHostToDevice, stream));
         HIPCHECK(hipMemcpyAsync(bmax.p, init_max.data(), sizeof(int) * 3 * G, hipMemcpyHostToDevice, stream));
         sizes.ensure(sizeof(long long) * G);
-        for (int q = 0; q < gg::kKinds; ++q) cnt[q].ensure(sizeof(long long) * G);
-        ldsmax.ensure(sizeof(unsigned long long) * gg::kKinds);
+        cnt.ensure(sizeof(long long) * 3 * gg::kKinds * (size_t)G);
+        ldsmax.ensure(sizeof(unsigned long long) * gg::kKinds * gg::kClasses);
         vol.ensure(sizeof(double) * G);
         cov_cnt.ensure(sizeof(int) * ntiles);
         cov_off.ensure(sizeof(int) * (ntiles + 1));
@@ -278,7 +278,7 @@ template <typename T> struct Sim final : SimBase {
                        &cov_list, &taps_d, &quat_d, &energy_d, &totals_d, &keep_psi, &keep_phic, &keep_lo,
                        &keep_ext, &keep_alive, &keep_off};
         for (DBuf *b : all) b->release();
-        for (int q = 0; q < gg::kKinds; ++q) cnt[q].release();
+        cnt.release();
         for (int l = 0; l < 2; ++l) {
             lo[l].release();
             ext[l].release();
@@ -286,10 +286,8 @@ template <typename T> struct Sim final : SimBase {
             off[l].release();
             iota_a[l].release();
             itile[l].release();
-            for (int q = 0; q < gg::kKinds; ++q) {
-                ipref[l][q].release();
-                iowner[l][q].release();
-            }
+            ipref[l].release();
+            for (int q = 0; q < gg::kKinds * gg::kClasses; ++q) iowner[l][q].release();
         }
         for (int a = 0; a < 4; ++a) arena[a].release();
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
@@ -330,14 +328,13 @@ template <typename T> struct Sim final : SimBase {
     void layout_meta_count(int l, bool coverage) {
         Boxes L = boxes_of(l);
         tbegin(GG_K_PLAN, 0);
-        HIPCHECK(hipMemsetAsync(ldsmax.p, 0, sizeof(unsigned long long) * gg::kKinds, stream));
+        HIPCHECK(hipMemsetAsync(ldsmax.p, 0, sizeof(unsigned long long) * gg::kKinds * gg::kClasses, stream));
         const int tb = 256, gb = (G + tb - 1) / tb;
-        hipLaunchKernelGGL(gg::k_item_counts, dim3(gb), dim3(tb), 0, stream, L, cnt[0].as<long long>(),
-                           cnt[1].as<long long>(), cnt[2].as<long long>(), cnt[3].as<long long>(), itile[l].as<int4>(),
-                           ldsmax.as<unsigned long long>(), R, K, G, gg::lds_budget<T>());
-        for (int q = 0; q < gg::kKinds; ++q)
-            hipLaunchKernelGGL(gg::k_scan, dim3(1), dim3(1024), 0, stream, cnt[q].as<long long>(),
-                               ipref[l][q].as<long long>(), G);
+        hipLaunchKernelGGL(gg::k_item_counts, dim3(gb), dim3(tb), 0, stream, L, cnt.as<long long>(), itile[l].as<int4>(),
+                           ldsmax.as<unsigned long long>(), R, K, G, gg::lds_budget<T>(),
+                           gg::kSmallLdsBytes / (int)sizeof(T));
+        hipLaunchKernelGGL(gg::k_scan_multi, dim3(3 * gg::kKinds), dim3(1024), 0, stream, cnt.as<long long>(),
+                           ipref[l].as<long long>(), G);
         if (coverage) {
             HIPCHECK(hipMemsetAsync(cov_cnt.p, 0, sizeof(int) * ntiles, stream));
             hipLaunchKernelGGL(gg::k_coverage, dim3(G), dim3(64), 0, stream, L, cov_cnt.as<int>(), (int *)nullptr,
@@ -345,33 +342,38 @@ template <typename T> struct Sim final : SimBase {
             hipLaunchKernelGGL(gg::k_scan_int, dim3(1), dim3(1024), 0, stream, cov_cnt.as<int>(), cov_off.as<int>(),
                                ntiles);
         }
-        hipLaunchKernelGGL(gg::k_totals, dim3(1), dim3(256), 0, stream, L.off, ipref[l][0].as<long long>(),
-                           ipref[l][1].as<long long>(), ipref[l][2].as<long long>(), ipref[l][3].as<long long>(),
+        hipLaunchKernelGGL(gg::k_totals, dim3(1), dim3(256), 0, stream, L.off, ipref[l].as<long long>(),
                            coverage ? cov_off.as<int>() : (const int *)nullptr, ntiles, L.alive, G,
                            ldsmax.as<unsigned long long>(), totals_d.as<Totals>());
         HIPCHECK(hipGetLastError());
         tend();
         HIPCHECK(hipMemcpyAsync(totals_h, totals_d.p, sizeof(Totals), hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipStreamSynchronize(stream));
+        const long long keep_cov = tot[l].cov;
         tot[l] = *totals_h;
+        if (!coverage) tot[l].cov = keep_cov;
         for (int q = 0; q < gg::kKinds; ++q)
-            if (tot[l].lds[q] < 0 || tot[l].lds[q] > gg::lds_budget<T>())
-                throw CapError{"a box is too large for the stencil tiling"};
+            for (int c = 0; c < gg::kClasses; ++c)
+                if (tot[l].lds[q][c] < 0 || tot[l].lds[q][c] > gg::lds_budget<T>())
+                    throw CapError{"a box is too large for the stencil tiling"};
         items_R[l] = R;
     }
 
     void layout_meta_fill(int l, bool coverage) {
+        gg::OwnerMaps om;
         for (int q = 0; q < gg::kKinds; ++q)
-            iowner[l][q].ensure(sizeof(int) * (size_t)std::max<long long>(tot[l].items[q], 1) * 5 / 4);
+            for (int c = 0; c < gg::kClasses; ++c) {
+                DBuf &b = iowner[l][q * gg::kClasses + c];
+                b.ensure(sizeof(int) * (size_t)std::max<long long>(tot[l].items[q][1 + c], 1) * 5 / 4);
+                om.owner[q * gg::kClasses + c] = b.as<int>();
+            }
         if (coverage) {
             if (tot[l].cov > 0x7fffffffLL) throw CapError{"coverage list exceeds 2^31 entries"};
             cov_list.ensure(sizeof(int) * (size_t)std::max<long long>(tot[l].cov, 1) * 5 / 4);
         }
         tbegin(GG_K_PLAN, 0);
-        for (int q = 0; q < gg::kKinds; ++q) {
-            hipLaunchKernelGGL(gg::k_fill_owner, dim3(G), dim3(64), 0, stream, ipref[l][q].as<long long>(),
-                               iowner[l][q].as<int>(), G);
-        }
+        hipLaunchKernelGGL(gg::k_fill_owner, dim3(G, gg::kKinds * gg::kClasses), dim3(64), 0, stream,
+                           ipref[l].as<long long>(), om, G);
         if (coverage) {
             HIPCHECK(hipMemcpyAsync(cov_cur.p, cov_off.p, sizeof(int) * (ntiles + 1), hipMemcpyDeviceToDevice,
                                     stream));
@@ -380,6 +382,19 @@ template <typename T> struct Sim final : SimBase {
         }
         HIPCHECK(hipGetLastError());
         tend();
+    }
+
+    const long long *pref_of(int l, int kind, int j) const {
+        return ipref[l].as<long long>() + ((size_t)kind * 3 + j) * (size_t)(G + 1);
+    }
+    gg::ItemRefs refs(int l, int kind, int cls) const {
+        gg::ItemRefs r;
+        r.owner = iowner[l][kind * gg::kClasses + cls].as<int>();
+        r.pref = pref_of(l, kind, 1 + cls);
+        r.pref_all = pref_of(l, kind, 0);
+        r.tilings = tiles_of(l, kind);
+        r.n = tot[l].items[kind][1 + cls];
+        return r;
     }
 
     void set_gaussian(double dt) {
@@ -419,24 +434,25 @@ template <typename T> struct Sim final : SimBase {
     // Predictor x and y passes (+ correction epilogue) on layout l: src -> dst.
     void launch_conv_xy(int l, const T *src, T *dst, const gg::Physics<T> &ph) {
         const Totals &t = tot[l];
-        if (t.items[gg::KIND_CXY] <= 0) return;
+        if (t.items[gg::KIND_CXY][0] <= 0) return;
         tbegin(GG_K_CONV_XY, t.arena);
-        const dim3 gr(grid_of(gg::xcd_grid(t.items[gg::KIND_CXY]))), bl(gg::kBlock);
-        const size_t lds = sizeof(T) * t.lds[gg::KIND_CXY];
-        auto args = std::make_tuple(boxes_of(l), (const int *)iowner[l][gg::KIND_CXY].as<int>(),
-                                    (const long long *)ipref[l][gg::KIND_CXY].as<long long>(), tiles_of(l, gg::KIND_CXY),
-                                    (long long)t.items[gg::KIND_CXY], src, dst,
-                                    (const T *)taps_d.as<T>(), R, W, grid_args(), ph);
-        auto go = [&](auto kern) {
-            std::apply([&](auto... a) { hipLaunchKernelGGL(kern, gr, bl, lds, stream, a...); }, args);
-        };
-        if (ph.mode) {
-            if (R == 6) go(gg::k_conv_xy<T, 6, true>);
-            else if (R == 8) go(gg::k_conv_xy<T, 8, true>);
-            else go(gg::k_conv_xy<T, 0, true>);
-        } else if (R == 6) go(gg::k_conv_xy<T, 6, false>);
-        else if (R == 8) go(gg::k_conv_xy<T, 8, false>);
-        else go(gg::k_conv_xy<T, 0, false>);
+        for (int c = 0; c < gg::kClasses; ++c) {
+            const gg::ItemRefs ir = refs(l, gg::KIND_CXY, c);
+            if (ir.n <= 0) continue;
+            const dim3 gr(grid_of(gg::xcd_grid(ir.n))), bl(gg::kBlock);
+            const size_t lds = sizeof(T) * t.lds[gg::KIND_CXY][c];
+            auto args = std::make_tuple(boxes_of(l), ir, src, dst, (const T *)taps_d.as<T>(), R, W, grid_args(), ph);
+            auto go = [&](auto kern) {
+                std::apply([&](auto... a) { hipLaunchKernelGGL(kern, gr, bl, lds, stream, a...); }, args);
+            };
+            if (ph.mode) {
+                if (R == 6) go(gg::k_conv_xy<T, 6, true>);
+                else if (R == 8) go(gg::k_conv_xy<T, 8, true>);
+                else go(gg::k_conv_xy<T, 0, true>);
+            } else if (R == 6) go(gg::k_conv_xy<T, 6, false>);
+            else if (R == 8) go(gg::k_conv_xy<T, 8, false>);
+            else go(gg::k_conv_xy<T, 0, false>);
+        }
         tend();
         HIPCHECK(hipGetLastError());
     }
@@ -444,13 +460,15 @@ template <typename T> struct Sim final : SimBase {
     // Predictor z pass alone on layout l (3D): src -> dst.
     void launch_conv_z(int l, const T *src, T *dst) {
         const Totals &t = tot[l];
-        if (t.items[gg::KIND_CZ] <= 0) return;
+        if (t.items[gg::KIND_CZ][0] <= 0) return;
         tbegin(GG_K_CONV_Z, t.arena);
-        hipLaunchKernelGGL(gg::k_conv_z<T>, dim3(grid_of(gg::xcd_grid(t.items[gg::KIND_CZ]))), dim3(gg::kBlock),
-                           sizeof(T) * t.lds[gg::KIND_CZ], stream, boxes_of(l), iowner[l][gg::KIND_CZ].as<int>(),
-                           ipref[l][gg::KIND_CZ].as<long long>(), tiles_of(l, gg::KIND_CZ),
-                           (long long)t.items[gg::KIND_CZ], src, dst,
-                           taps_d.as<T>(), R, W, grid_args());
+        for (int c = 0; c < gg::kClasses; ++c) {
+            const gg::ItemRefs ir = refs(l, gg::KIND_CZ, c);
+            if (ir.n <= 0) continue;
+            hipLaunchKernelGGL(gg::k_conv_z<T>, dim3(grid_of(gg::xcd_grid(ir.n))), dim3(gg::kBlock),
+                               sizeof(T) * t.lds[gg::KIND_CZ][c], stream, boxes_of(l), ir, src, dst, taps_d.as<T>(), R,
+                               W, grid_args());
+        }
         tend();
         HIPCHECK(hipGetLastError());
     }
@@ -462,42 +480,40 @@ template <typename T> struct Sim final : SimBase {
         const Totals &t = tot[ln_l];
         const gg::GridArgs g = grid_args();
         const int vk = dim == 3 ? gg::KIND_ZF : gg::KIND_RXY;
-        vol_part.ensure(sizeof(double) * (size_t)std::max<long long>(t.items[vk], 1) * 5 / 4);
-        if (t.items[gg::KIND_RXY] > 0) {
+        vol_part.ensure(sizeof(double) * (size_t)std::max<long long>(t.items[vk][0], 1) * 5 / 4);
+        if (t.items[gg::KIND_RXY][0] > 0) {
             tbegin(GG_K_REINIT_XY, t.arena);
-            const dim3 gr(grid_of(gg::xcd_grid(t.items[gg::KIND_RXY]))), bl(gg::kBlock);
-            const size_t lds = sizeof(T) * t.lds[gg::KIND_RXY];
             T *out = dim == 3 ? d2 : phi;
-            auto args = std::make_tuple(boxes_of(lo_l), boxes_of(ln_l),
-                                        (const int *)iowner[ln_l][gg::KIND_RXY].as<int>(),
-                                        (const long long *)ipref[ln_l][gg::KIND_RXY].as<long long>(),
-                                        tiles_of(ln_l, gg::KIND_RXY), (long long)t.items[gg::KIND_RXY], phic, out,
-                                        iota_old, iota_new, vol_part.as<double>(), K, W, g);
-            auto go = [&](auto kern) {
-                std::apply([&](auto... a) { hipLaunchKernelGGL(kern, gr, bl, lds, stream, a...); }, args);
-            };
-            go(gg::k_reinit_xy<T>);
+            for (int c = 0; c < gg::kClasses; ++c) {
+                const gg::ItemRefs ir = refs(ln_l, gg::KIND_RXY, c);
+                if (ir.n <= 0) continue;
+                hipLaunchKernelGGL(gg::k_reinit_xy<T>, dim3(grid_of(gg::xcd_grid(ir.n))), dim3(gg::kBlock),
+                                   sizeof(T) * t.lds[gg::KIND_RXY][c], stream, boxes_of(lo_l), boxes_of(ln_l), ir,
+                                   phic, out, iota_old, iota_new, vol_part.as<double>(), K, W, g);
+            }
             tend();
         }
-        if (dim == 3 && t.items[gg::KIND_ZF] > 0) {
+        if (dim == 3 && t.items[gg::KIND_ZF][0] > 0) {
             tbegin(GG_K_REINIT_Z, t.arena);
-            const dim3 gr(grid_of(gg::xcd_grid(t.items[gg::KIND_ZF]))), bl(gg::kBlock);
-            const size_t lds = sizeof(T) * t.lds[gg::KIND_ZF];
-            auto args = std::make_tuple(boxes_of(ln_l), (const int *)iowner[ln_l][gg::KIND_ZF].as<int>(),
-                                        (const long long *)ipref[ln_l][gg::KIND_ZF].as<long long>(),
-                                        tiles_of(ln_l, gg::KIND_ZF), (long long)t.items[gg::KIND_ZF], (const T *)d2,
-                                        phi, tz, vol_part.as<double>(), (const T *)taps_d.as<T>(), K, R, W, g);
-            auto go = [&](auto kern) {
-                std::apply([&](auto... a) { hipLaunchKernelGGL(kern, gr, bl, lds, stream, a...); }, args);
-            };
-            if (R == 6) go(gg::k_zfused<T, 6>);
-            else if (R == 8) go(gg::k_zfused<T, 8>);
-            else go(gg::k_zfused<T, 0>);
+            for (int c = 0; c < gg::kClasses; ++c) {
+                const gg::ItemRefs ir = refs(ln_l, gg::KIND_ZF, c);
+                if (ir.n <= 0) continue;
+                const dim3 gr(grid_of(gg::xcd_grid(ir.n))), bl(gg::kBlock);
+                const size_t lds = sizeof(T) * t.lds[gg::KIND_ZF][c];
+                auto args = std::make_tuple(boxes_of(ln_l), ir, (const T *)d2, phi, tz, vol_part.as<double>(),
+                                            (const T *)taps_d.as<T>(), K, R, W, g);
+                auto go = [&](auto kern) {
+                    std::apply([&](auto... a) { hipLaunchKernelGGL(kern, gr, bl, lds, stream, a...); }, args);
+                };
+                if (R == 6) go(gg::k_zfused<T, 6>);
+                else if (R == 8) go(gg::k_zfused<T, 8>);
+                else go(gg::k_zfused<T, 0>);
+            }
             tend();
         }
         const int tb = 256, gb = (G + tb - 1) / tb;
         tbegin(GG_K_VOLUME, t.arena);
-        hipLaunchKernelGGL(gg::k_volumes, dim3(gb), dim3(tb), 0, stream, boxes_of(ln_l), ipref[ln_l][vk].as<long long>(),
+        hipLaunchKernelGGL(gg::k_volumes, dim3(gb), dim3(tb), 0, stream, boxes_of(ln_l), pref_of(ln_l, vk, 0),
                            vol_part.as<double>(), vol.as<double>(), G);
         tend();
         HIPCHECK(hipGetLastError());
