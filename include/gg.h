@@ -69,7 +69,9 @@ enum {
 
 typedef struct {
     int32_t dim;            /* 2 or 3                                               */
-    int32_t n[3];           /* periodic grid size; n[2] == 1 when dim == 2           */
+    int32_t n[3];           /* periodic grid size, each in [4P + 2, 4096] with       */
+                            /* P = ceil(band); n[2] == 1 when dim == 2; at most      */
+                            /* 2^31 - 1 voxels in all                                */
     double band;            /* narrow-band half width W in voxels (1 <= W <= 16);
                                the box pad is P = ceil(W) (Fig. 1a: >= 7 points)   */
     int32_t precision;      /* gg_precision                                         */

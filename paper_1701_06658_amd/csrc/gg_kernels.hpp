@@ -97,9 +97,10 @@ template <> __device__ __forceinline__ float tinf<float>() { return __builtin_in
 __host__ __device__ inline long long lds_need(int kind, int tx, int ty, int h, int h2, bool sx, bool sy) {
     if (kind == KIND_CXY)
         return (long long)((tx + 2 * h) | 1) * (ty + 2 * h) + kKB + (long long)tx * (ty + 2 * h + kKB);
-    if (kind == KIND_RXY) {
+    if (kind == KIND_RXY) {  // f tile, reference tile, and int offset tables (counted as one value each)
         const int hx = sx ? h : 0, hy = sy ? h : 0;
-        return (long long)((tx + 2 * hx + 2) | 1) * (ty + 2 * hy + 2) + (long long)((tx + 2 * hx) | 1) * (ty + 2 * hy);
+        return (long long)((tx + 2 * hx + 2) | 1) * (ty + 2 * hy + 2) + (long long)((tx + 2 * hx) | 1) * (ty + 2 * hy) +
+               (ty + 2 * hy + 2) + 2LL * (ty + 2 * hy) + (tx + 2 * hx + 2);
     }
     if (kind == KIND_ZF) {
         const int hz = sy ? h : 0;
@@ -849,6 +850,24 @@ template <typename T> struct Carry {
         const long long i = old_index(x, y, z);
         return i >= 0 ? src[i] : -W;
     }
+    // Offsets relative to the old box start, for per-tile tables: >= 0 inside
+    // both boxes, -1 inside the new box only, -2 outside the new box.
+    __device__ __forceinline__ int row_code(int y, int z) const {
+        const int ym = axis_map(y, nex[1], n[1]), zm = axis_map(z, nex[2], n[2]);
+        if (ym < 0 || zm < 0) return -2;
+        int oy = ym + d[1], oz = zm + d[2];
+        oy -= oy >= n[1] ? n[1] : 0;
+        oz -= oz >= n[2] ? n[2] : 0;
+        if (oy >= oex[1] || oz >= oex[2]) return -1;
+        return oex[0] * (oy + oex[1] * oz);
+    }
+    __device__ __forceinline__ int col_code(int x) const {
+        const int xm = axis_map(x, nex[0], n[0]);
+        if (xm < 0) return -2;
+        int ox = xm + d[0];
+        ox -= ox >= n[0] ? n[0] : 0;
+        return ox < oex[0] ? ox : -1;
+    }
     // Separable form of old_index: old_row(y, z) + old_col(x), each -1 outside.
     __device__ __forceinline__ long long old_row(int y, int z) const {
         const int ym = axis_map(y, nex[1], n[1]), zm = axis_map(z, nex[2], n[2]);
@@ -902,10 +921,38 @@ __global__ void __launch_bounds__(kBlock)
     const int RW = wx + 2 * hx, RP = RW | 1, RH = wy + 2 * hy;
     const int FW = RW + 2, FP = FW | 1, FH = RH + 2;
     T *f = sm, *ref = sm + FP * FH;
+    // offset tables (relative to the old box start): f rows, z-1 rows, z+1 rows, f columns
+    int *rtab = reinterpret_cast<int *>(ref + RP * RH), *rzm = rtab + FH, *rzp = rzm + RH, *ctab = rzp + RH;
+    const T *src = phic + cr.ooff;
     const T inf = tinf<T>();
-    stage_rows<T>(
-        f, FP, FW, FH, phic, [&](int rr) { return cr.old_row(y0 - hy - 1 + rr, z); },
-        [&](int cc) { return cr.old_col(x0 - hx - 1 + cc); }, -W);
+    for (int i = threadIdx.x; i < FH; i += kBlock) rtab[i] = cr.row_code(y0 - hy - 1 + i, z);
+    for (int i = threadIdx.x; i < RH; i += kBlock) {
+        rzm[i] = g.dim == 3 ? cr.row_code(y0 - hy + i, z - 1) : -2;
+        rzp[i] = g.dim == 3 ? cr.row_code(y0 - hy + i, z + 1) : -2;
+    }
+    for (int i = threadIdx.x; i < FW; i += kBlock) ctab[i] = cr.col_code(x0 - hx - 1 + i);
+    __syncthreads();
+    {
+        const int lane = threadIdx.x & 63, wave = wave_id();
+        for (int c0 = 0; c0 < FW; c0 += 64) {
+            const int cc = c0 + lane;
+            const int co = cc < FW ? ctab[cc] : -1;
+            for (int r0 = wave; r0 < FH; r0 += kWaves * kLoadBatch) {
+                T v[kLoadBatch];
+#pragma unroll
+                for (int j = 0; j < kLoadBatch; ++j) {
+                    const int rr = r0 + kWaves * j;
+                    const int ro = rr < FH ? rtab[rr] : -1;
+                    v[j] = (ro >= 0 && co >= 0) ? src[ro + co] : -W;
+                }
+#pragma unroll
+                for (int j = 0; j < kLoadBatch; ++j) {
+                    const int rr = r0 + kWaves * j;
+                    if (rr < FH && cc < FW) f[rr * FP + cc] = v[j];
+                }
+            }
+        }
+    }
     __syncthreads();
     // reference values: waves own rows, lanes own columns; the z neighbours of
     // kLoadBatch rows are gathered before any is used
@@ -914,28 +961,22 @@ __global__ void __launch_bounds__(kBlock)
         const int nn = g.dim == 3 ? 6 : 4;
         for (int c0 = 0; c0 < RW; c0 += 64) {
             const int cc = c0 + lane;
-            const int x = x0 - hx + cc;
-            const bool xin = cc < RW && axis_map(x, ex, g.n[0]) >= 0;
-            const int oc = xin ? cr.old_col(x) : -1;
+            const int co = cc < RW ? ctab[cc + 1] : -2;
             for (int r0 = wave; r0 < RH; r0 += kWaves * kLoadBatch) {
                 T zm[kLoadBatch], zp[kLoadBatch];
 #pragma unroll
                 for (int j = 0; j < kLoadBatch; ++j) {
                     const int rr = r0 + kWaves * j;
-                    zm[j] = zp[j] = -W;
-                    if (g.dim == 3 && rr < RH && oc >= 0) {
-                        const int y = y0 - hy + rr;
-                        const long long bm = cr.old_row(y, z - 1), bp = cr.old_row(y, z + 1);
-                        if (bm >= 0) zm[j] = phic[bm + oc];
-                        if (bp >= 0) zp[j] = phic[bp + oc];
-                    }
+                    const int om = rr < RH ? rzm[rr] : -1, op = rr < RH ? rzp[rr] : -1;
+                    zm[j] = (om >= 0 && co >= 0) ? src[om + co] : -W;
+                    zp[j] = (op >= 0 && co >= 0) ? src[op + co] : -W;
                 }
 #pragma unroll
                 for (int j = 0; j < kLoadBatch; ++j) {
                     const int rr = r0 + kWaves * j;
                     if (rr >= RH || cc >= RW) continue;
                     T r = inf;
-                    if (xin && axis_map(y0 - hy + rr, ey, g.n[1]) >= 0) {
+                    if (co != -2 && rtab[rr + 1] != -2) {
                         const T *fc_p = f + (rr + 1) * FP + cc + 1;
                         const T fc = fc_p[0];
                         const bool in = fc > T(0);
@@ -988,8 +1029,8 @@ __global__ void __launch_bounds__(kBlock)
             out[idx] = in ? d : -d;
         }
         if (iota_new) {
-            const long long oi = cr.old_index(x0 + c, y0 + r, z);
-            iota_new[idx] = oi >= 0 ? iota_old[oi] : -1;
+            const int ro = rtab[r + hy + 1], co = ctab[c + hx + 1];
+            iota_new[idx] = (ro >= 0 && co >= 0) ? iota_old[cr.ooff + ro + co] : -1;
         }
     }
     if (g.dim == 2) {

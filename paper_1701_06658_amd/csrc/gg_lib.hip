@@ -1022,6 +1022,8 @@ gg_status gg_create(const gg_config *cfg, const int32_t *labels, int32_t n_grain
         return fail(nullptr, GG_E_ARG, "bulk energy needs energy_density, voxel_m > 0 and gamma_max > 0");
     if (n_grains < 1) return fail(nullptr, GG_E_ARG, "n_grains must be >= 1");
     const long long nt3 = (long long)cfg->n[0] * cfg->n[1] * cfg->n[2];
+    // box offsets inside a grain's arena are 32-bit
+    if (nt3 > 2147483647LL) return fail(nullptr, GG_E_ARG, "grid must have fewer than 2^31 voxels");
     for (long long i = 0; i < nt3; ++i)
         if (labels[i] < 0 || labels[i] >= n_grains) return fail(nullptr, GG_E_ARG, "label out of [0, n_grains)");
     if (quat && (cfg->physics & GG_PHYS_MISORIENTATION))

@@ -66,6 +66,7 @@ def _create(lib, **kw):
     dict(G=0),
     dict(physics=1),                           # misorientation weights without quaternions
     dict(physics=2),                           # bulk energy without energy densities
+    dict(dim=3, n=(2048, 2048, 1024), labels=np.zeros(1, np.int32)),  # 2^32 voxels: rejected before labels are read
 ])
 def test_argument_errors_are_reported_before_any_device_use(lib, kw):
     st, msg = _create(lib, **kw)
