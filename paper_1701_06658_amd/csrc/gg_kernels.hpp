@@ -90,17 +90,20 @@ template <typename T> __device__ __forceinline__ T tinf();
 template <> __device__ __forceinline__ double tinf<double>() { return __builtin_inf(); }
 template <> __device__ __forceinline__ float tinf<float>() { return __builtin_inff(); }
 
-// LDS values needed by an output tile tx * ty.  h: stencil halo (R for the
-// predictor kinds, K for the re-initialization kinds), h2: R for the fused z
-// kind.  The re-initialization sweeps whole box lines, so its tiles need a halo
-// only along an axis that is split into several tiles (sx, sy).
-__host__ __device__ inline long long lds_need(int kind, int tx, int ty, int h, int h2, bool sx, bool sy) {
+// LDS values needed by an output tile tx * ty of nz planes.  h: stencil halo (R
+// for the predictor kinds, K for the re-initialization kinds), h2: R for the
+// fused z kind.  The re-initialization sweeps whole box lines, so its tiles need
+// a halo only along an axis that is split into several tiles (sx, sy).  Only the
+// re-initialization xy kind batches several planes into one work item: per
+// plane an f tile and a reference tile of (ty + 2hy + 2) rows of pitch
+// (tx + 2hx + 2) | 1, plus int offset tables (counted as one value each).
+__host__ __device__ inline long long lds_need(int kind, int tx, int ty, int h, int h2, bool sx, bool sy, int nz = 1) {
     if (kind == KIND_CXY)
         return (long long)((tx + 2 * h) | 1) * (ty + 2 * h) + kKB + (long long)tx * (ty + 2 * h + kKB);
-    if (kind == KIND_RXY) {  // f tile, reference tile, and int offset tables (counted as one value each)
+    if (kind == KIND_RXY) {
         const int hx = sx ? h : 0, hy = sy ? h : 0;
-        return (long long)((tx + 2 * hx + 2) | 1) * (ty + 2 * hy + 2) + (long long)((tx + 2 * hx) | 1) * (ty + 2 * hy) +
-               (ty + 2 * hy + 2) + 2LL * (ty + 2 * hy) + (tx + 2 * hx + 2);
+        const long long FW = tx + 2 * hx + 2, FH = ty + 2 * hy + 2;
+        return (long long)nz * (2 * (FW | 1) * FH + FH) + 2 * FH + FW;
     }
     if (kind == KIND_ZF) {
         const int hz = sy ? h : 0;
@@ -109,14 +112,18 @@ __host__ __device__ inline long long lds_need(int kind, int tx, int ty, int h, i
     return (long long)tx * (ty + 2 * h);  // prologue z pass
 }
 
+// nb: planes per work item (re-initialization xy kind only, else 1).
 struct Tiling {
-    int nxs, nys, tx, ty;
+    int nxs, nys, tx, ty, nb;
 };
 
 // Split a box cross-section ex * ey (second axis y for xy kernels, z for z
 // kernels) into the fewest near-equal tiles whose LDS need fits the budget.
-__host__ __device__ inline Tiling choose_tiling(int kind, int ex, int ey, int h, int h2, int budget) {
-    Tiling t = {0, 0, 0, 0};
+// The re-initialization xy kind then takes as many of the `planes` planes per
+// work item as fit `target` values of LDS, in near-equal chunks.
+__host__ __device__ inline Tiling choose_tiling(int kind, int ex, int ey, int planes, int h, int h2, int budget,
+                                                int target) {
+    Tiling t = {0, 0, 0, 0, 1};
     for (int nxs = (ex + 127) / 128; nxs <= ex; ++nxs) {
         const int tx = (ex + nxs - 1) / nxs;
         const bool sx = nxs > 1;
@@ -125,7 +132,7 @@ __host__ __device__ inline Tiling choose_tiling(int kind, int ex, int ey, int h,
             t.nys = 1;
             t.tx = tx;
             t.ty = ey;
-            return t;
+            break;
         }
         const int b = (int)lds_need(kind, tx, 0, h, h2, sx, true);  // the need is affine in ty
         const int a = (int)lds_need(kind, tx, 1, h, h2, sx, true) - b;
@@ -136,9 +143,18 @@ __host__ __device__ inline Tiling choose_tiling(int kind, int ex, int ey, int h,
         t.nys = nys;
         t.tx = tx;
         t.ty = (ey + nys - 1) / nys;
-        return t;
+        break;
     }
-    return t;  // infeasible: nxs == 0
+    if (kind == KIND_RXY && t.nxs > 0 && planes > 1) {
+        const bool sx = t.nxs > 1, sy = t.nys > 1;
+        const long long one = lds_need(kind, t.tx, t.ty, h, h2, sx, sy, 1);
+        const long long per = lds_need(kind, t.tx, t.ty, h, h2, sx, sy, 2) - one;
+        long long nb = (target - (one - per)) / per;
+        nb = nb < 1 ? 1 : (nb > planes ? planes : nb);
+        const int chunks = (int)((planes + nb - 1) / nb);
+        t.nb = (planes + chunks - 1) / chunks;
+    }
+    return t;
 }
 
 __host__ __device__ inline void kind_halos(int kind, int R, int K, int *h, int *h2) {
@@ -146,18 +162,27 @@ __host__ __device__ inline void kind_halos(int kind, int R, int K, int *h, int *
     *h2 = kind == KIND_ZF ? R : 0;
 }
 
-__host__ __device__ inline Tiling kind_tiling(int kind, const int *e, int R, int K, int budget) {
+__host__ __device__ inline int kind_planes(int kind, const int *e) {
+    return (kind == KIND_CXY || kind == KIND_RXY) ? e[2] : e[1];
+}
+
+__host__ __device__ inline Tiling kind_tiling(int kind, const int *e, int R, int K, int budget, int target) {
     int h, h2;
     kind_halos(kind, R, K, &h, &h2);
     const int ey = (kind == KIND_CXY || kind == KIND_RXY) ? e[1] : e[2];
-    return choose_tiling(kind, e[0], ey, h, h2, budget);
+    return choose_tiling(kind, e[0], ey, kind_planes(kind, e), h, h2, budget, target);
+}
+
+__host__ __device__ inline long long tiling_need(int kind, const Tiling &t, int R, int K) {
+    int h, h2;
+    kind_halos(kind, R, K, &h, &h2);
+    return lds_need(kind, t.tx, t.ty, h, h2, t.nxs > 1, t.nys > 1, t.nb);
 }
 
 // Number of work items of one kind for a box.
-__host__ __device__ inline long long kind_items(int kind, const int *e, int R, int K, int budget) {
-    const Tiling t = kind_tiling(kind, e, R, K, budget);
-    const int planes = (kind == KIND_CXY || kind == KIND_RXY) ? e[2] : e[1];
-    return (long long)planes * t.nxs * t.nys;
+__host__ __device__ inline long long tiling_items(int kind, const int *e, const Tiling &t) {
+    const int planes = kind_planes(kind, e);
+    return (long long)((planes + t.nb - 1) / t.nb) * t.nxs * t.nys;
 }
 
 // Work groups are dealt round-robin to the 8 XCDs of the chip (each with its
@@ -172,14 +197,14 @@ __device__ __forceinline__ long long xcd_item(long long n) {
     return (b % kXcds) * chunk + b / kXcds;
 }
 
-// Work item -> (grain, plane, tile origin, tile size).
+// Work item -> (grain, first plane, planes, tile origin, tile size).
 struct ItemTile {
     long long item;
-    int k, plane, x0, y0, wx, wy, nxs, nys;
+    int k, plane, np, x0, y0, wx, wy, nxs, nys;
 };
 
 // The tiling of every grain and kind is computed once per layout (k_item_counts)
-// and stored as int4 (nxs, nys, tx, ty).
+// and stored as two int4: (nxs, nys, tx, ty), (nb, 0, 0, 0).
 // Items of one class: owner[item] is the grain, pref the class prefix over
 // grains; pref_all (all items of the kind) gives the item's global index.
 struct ItemRefs {
@@ -197,13 +222,21 @@ __device__ __forceinline__ ItemTile decode_item(long long item, int kind, const 
     it.item = ir.pref_all[it.k] + sub;
     const int4 *tilings = ir.tilings;
     const int e[3] = {L.ext[3 * it.k], L.ext[3 * it.k + 1], L.ext[3 * it.k + 2]};
-    const int4 t4 = tilings[it.k];
-    const Tiling tl = {t4.x, t4.y, t4.z, t4.w};
+    const int4 t4 = tilings[2 * it.k];
+    const Tiling tl = {t4.x, t4.y, t4.z, t4.w, 1};
     it.nxs = tl.nxs;
     it.nys = tl.nys;
     const int per = tl.nxs * tl.nys;
-    it.plane = sub / per;
-    const int rem = sub - it.plane * per;
+    const int chunk = sub / per;
+    const int rem = sub - chunk * per;
+    if (kind == KIND_RXY) {
+        const int nb = tilings[2 * it.k + 1].x;
+        it.plane = chunk * nb;
+        it.np = min(nb, e[2] - it.plane);
+    } else {
+        it.plane = chunk;
+        it.np = 1;
+    }
     const int ys = rem / tl.nxs, xs = rem - ys * tl.nxs;
     it.x0 = xs * tl.tx;
     it.y0 = ys * tl.ty;
@@ -887,10 +920,42 @@ template <typename T> struct Carry {
     }
 };
 
+// Position (p, r, c) of element e of an array of planes of H rows of W values,
+// advanced by kBlock elements per step without division.
+struct Walk3 {
+    int p, r, c, W, H, dq, dm;
+    __device__ __forceinline__ Walk3(int e, int W_, int H_) : W(W_), H(H_) {
+        dq = kBlock / W;
+        dm = kBlock - dq * W;
+        const int rows = e / W;
+        c = e - rows * W;
+        p = rows / H;
+        r = rows - p * H;
+    }
+    __device__ __forceinline__ void step() {
+        c += dm;
+        r += dq;
+        if (c >= W) {
+            c -= W;
+            ++r;
+        }
+        while (r >= H) {
+            r -= H;
+            ++p;
+        }
+    }
+};
+
 // Reference values next to the sign change, then the x and y spreading sweeps,
-// on one tile of one z plane of the new box.  3D: writes the partial distance
-// with the inside flag as its sign bit; 2D: writes the final function and the
-// tile's volume.  Also carries the ID-field over to the new layout.
+// on one tile of nz consecutive z planes of the new box.  3D: writes the partial
+// distance with the inside flag as its sign bit; 2D: writes the final function
+// and the tile's volume.  Also carries the ID-field over to the new layout.
+//
+// LDS: nz f planes and nz reference planes, each FH rows of pitch FP (the tile
+// with one ring of stencil neighbours), then int tables of offsets relative to
+// the old box start: f rows of every plane, the rows of the planes just below
+// and above the batch (whose z neighbours are read from memory; the batch's
+// inner planes take theirs from LDS), and the f columns.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_reinit_xy(Boxes Lo, Boxes Ln, ItemRefs ir, const T *__restrict__ phic, T *__restrict__ out,
@@ -903,7 +968,7 @@ __global__ void __launch_bounds__(kBlock)
     if (cls_item >= ir.n) return;
     const ItemTile it = decode_item(cls_item, KIND_RXY, Ln, ir);
     const long long item = it.item;
-    const int k = it.k, z = it.plane, x0 = it.x0, y0 = it.y0, wx = it.wx, wy = it.wy;
+    const int k = it.k, z0 = it.plane, nz = it.np, x0 = it.x0, y0 = it.y0, wx = it.wx, wy = it.wy;
     Carry<T> cr;
     cr.src = phic;
     cr.W = W;
@@ -918,122 +983,145 @@ __global__ void __launch_bounds__(kBlock)
     }
     const int ex = cr.nex[0], ey = cr.nex[1];
     const int hx = it.nxs > 1 ? K : 0, hy = it.nys > 1 ? K : 0;
-    const int RW = wx + 2 * hx, RP = RW | 1, RH = wy + 2 * hy;
-    const int FW = RW + 2, FP = FW | 1, FH = RH + 2;
-    T *f = sm, *ref = sm + FP * FH;
-    // offset tables (relative to the old box start): f rows, z-1 rows, z+1 rows, f columns
-    int *rtab = reinterpret_cast<int *>(ref + RP * RH), *rzm = rtab + FH, *rzp = rzm + RH, *ctab = rzp + RH;
+    const int RW = wx + 2 * hx, RH = wy + 2 * hy;
+    const int FW = RW + 2, FP = FW | 1, FH = RH + 2, PS = FH * FP;
+    T *f = sm, *ref = sm + nz * PS;
+    int *rtab = reinterpret_cast<int *>(ref + nz * PS), *rzm = rtab + nz * FH, *rzp = rzm + FH, *ctab = rzp + FH;
     const T *src = phic + cr.ooff;
     const T inf = tinf<T>();
-    for (int i = threadIdx.x; i < FH; i += kBlock) rtab[i] = cr.row_code(y0 - hy - 1 + i, z);
-    for (int i = threadIdx.x; i < RH; i += kBlock) {
-        rzm[i] = g.dim == 3 ? cr.row_code(y0 - hy + i, z - 1) : -2;
-        rzp[i] = g.dim == 3 ? cr.row_code(y0 - hy + i, z + 1) : -2;
+    const bool d3 = g.dim == 3;
+    for (int i = threadIdx.x; i < nz * FH; i += kBlock) {
+        const int p = i / FH;
+        rtab[i] = cr.row_code(y0 - hy - 1 + i - p * FH, z0 + p);
     }
+    if (d3)
+        for (int i = threadIdx.x; i < FH; i += kBlock) {
+            rzm[i] = cr.row_code(y0 - hy - 1 + i, z0 - 1);
+            rzp[i] = cr.row_code(y0 - hy - 1 + i, z0 + nz);
+        }
     for (int i = threadIdx.x; i < FW; i += kBlock) ctab[i] = cr.col_code(x0 - hx - 1 + i);
     __syncthreads();
-    {
-        const int lane = threadIdx.x & 63, wave = wave_id();
-        for (int c0 = 0; c0 < FW; c0 += 64) {
-            const int cc = c0 + lane;
-            const int co = cc < FW ? ctab[cc] : -1;
-            for (int r0 = wave; r0 < FH; r0 += kWaves * kLoadBatch) {
-                T v[kLoadBatch];
+    // stage the f planes: kLoadBatch loads in flight per lane
+    for (Walk3 w(threadIdx.x, FW, FH); w.p < nz;) {
+        T v[kLoadBatch];
+        int at[kLoadBatch];
 #pragma unroll
-                for (int j = 0; j < kLoadBatch; ++j) {
-                    const int rr = r0 + kWaves * j;
-                    const int ro = rr < FH ? rtab[rr] : -1;
-                    v[j] = (ro >= 0 && co >= 0) ? src[ro + co] : -W;
-                }
-#pragma unroll
-                for (int j = 0; j < kLoadBatch; ++j) {
-                    const int rr = r0 + kWaves * j;
-                    if (rr < FH && cc < FW) f[rr * FP + cc] = v[j];
-                }
+        for (int j = 0; j < kLoadBatch; ++j) {
+            at[j] = -1;
+            v[j] = -W;
+            if (w.p < nz) {
+                const int ro = rtab[w.p * FH + w.r], co = ctab[w.c];
+                if (ro >= 0 && co >= 0) v[j] = src[ro + co];
+                at[j] = w.p * PS + w.r * FP + w.c;
             }
+            w.step();
         }
+#pragma unroll
+        for (int j = 0; j < kLoadBatch; ++j)
+            if (at[j] >= 0) f[at[j]] = v[j];
     }
     __syncthreads();
-    // reference values: waves own rows, lanes own columns; the z neighbours of
-    // kLoadBatch rows are gathered before any is used
-    {
-        const int lane = threadIdx.x & 63, wave = wave_id();
-        const int nn = g.dim == 3 ? 6 : 4;
-        for (int c0 = 0; c0 < RW; c0 += 64) {
-            const int cc = c0 + lane;
-            const int co = cc < RW ? ctab[cc + 1] : -2;
-            for (int r0 = wave; r0 < RH; r0 += kWaves * kLoadBatch) {
-                T zm[kLoadBatch], zp[kLoadBatch];
+    // reference values of the cells inside the ring; the z neighbours of
+    // kLoadBatch cells are gathered before any is used
+    for (Walk3 w(threadIdx.x, FW, FH); w.p < nz;) {
+        T zm[kLoadBatch], zp[kLoadBatch];
+        int at[kLoadBatch];
+        bool ib[kLoadBatch];
 #pragma unroll
-                for (int j = 0; j < kLoadBatch; ++j) {
-                    const int rr = r0 + kWaves * j;
-                    const int om = rr < RH ? rzm[rr] : -1, op = rr < RH ? rzp[rr] : -1;
-                    zm[j] = (om >= 0 && co >= 0) ? src[om + co] : -W;
-                    zp[j] = (op >= 0 && co >= 0) ? src[op + co] : -W;
-                }
-#pragma unroll
-                for (int j = 0; j < kLoadBatch; ++j) {
-                    const int rr = r0 + kWaves * j;
-                    if (rr >= RH || cc >= RW) continue;
-                    T r = inf;
-                    if (co != -2 && rtab[rr + 1] != -2) {
-                        const T *fc_p = f + (rr + 1) * FP + cc + 1;
-                        const T fc = fc_p[0];
-                        const bool in = fc > T(0);
-                        const T nb[6] = {fc_p[-1], fc_p[1], fc_p[-FP], fc_p[FP], zm[j], zp[j]};
-                        // theta = fc / (fc - fn) is monotone in fn (decreasing for an
-                        // inside voxel over fn <= 0, increasing for an outside voxel
-                        // over fn > 0), and so are the rounded operations: the
-                        // smallest theta is the one at the extreme opposite neighbour
-                        T ext = in ? inf : -inf;
-                        bool any = false;
-#pragma unroll
-                        for (int q = 0; q < 6; ++q) {
-                            if (q >= nn) break;
-                            const T fn = nb[q];
-                            if ((fn > T(0)) != in) {
-                                any = true;
-                                ext = in ? (fn < ext ? fn : ext) : (fn > ext ? fn : ext);
-                            }
-                        }
-                        if (any) r = fc / (fc - ext);
+        for (int j = 0; j < kLoadBatch; ++j) {
+            at[j] = -1;
+            ib[j] = false;
+            zm[j] = zp[j] = -W;
+            if (w.p < nz && w.r > 0 && w.r < FH - 1 && w.c > 0 && w.c < FW - 1) {
+                const int a = w.p * PS + w.r * FP + w.c;
+                const int co = ctab[w.c];
+                at[j] = a;
+                ib[j] = co != -2 && rtab[w.p * FH + w.r] != -2;
+                if (d3 && ib[j]) {
+                    if (w.p > 0) {
+                        zm[j] = f[a - PS];
+                    } else {
+                        const int ro = rzm[w.r];
+                        if (ro >= 0 && co >= 0) zm[j] = src[ro + co];
                     }
-                    ref[rr * RP + cc] = r;
+                    if (w.p < nz - 1) {
+                        zp[j] = f[a + PS];
+                    } else {
+                        const int ro = rzp[w.r];
+                        if (ro >= 0 && co >= 0) zp[j] = src[ro + co];
+                    }
                 }
             }
+            w.step();
+        }
+#pragma unroll
+        for (int j = 0; j < kLoadBatch; ++j) {
+            if (at[j] < 0) continue;
+            T r = inf;
+            if (ib[j]) {
+                const T *fc_p = f + at[j];
+                const T fc = fc_p[0];
+                const bool in = fc > T(0);
+                const T nb[6] = {fc_p[-1], fc_p[1], fc_p[-FP], fc_p[FP], zm[j], zp[j]};
+                // theta = fc / (fc - fn) is monotone in fn (decreasing for an
+                // inside voxel over fn <= 0, increasing for an outside voxel
+                // over fn > 0), and so are the rounded operations: the
+                // smallest theta is the one at the extreme opposite neighbour
+                T ext = in ? inf : -inf;
+                bool any = false;
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    if (q >= 4 && !d3) break;
+                    const T fn = nb[q];
+                    if ((fn > T(0)) != in) {
+                        any = true;
+                        ext = in ? (fn < ext ? fn : ext) : (fn > ext ? fn : ext);
+                    }
+                }
+                if (any) r = fc / (fc - ext);
+            }
+            ref[at[j]] = r;
         }
     }
     __syncthreads();
     // spreading: x along rows, then y along columns (one lane per line)
     const bool ringx = it.nxs == 1 && ex == g.n[0];
-    for (int rr = threadIdx.x; rr < RH; rr += kBlock) sweep_line<T>(ref + rr * RP, 1, RW, ringx);
+    for (int l = threadIdx.x; l < nz * RH; l += kBlock) {
+        const int p = l / RH;
+        sweep_line<T>(ref + p * PS + (l - p * RH + 1) * FP + 1, 1, RW, ringx);
+    }
     __syncthreads();
     const bool ringy = it.nys == 1 && ey == g.n[1];
-    for (int cc = threadIdx.x; cc < RW; cc += kBlock) sweep_line<T>(ref + cc, RP, RH, ringy);
+    for (int l = threadIdx.x; l < nz * RW; l += kBlock) {
+        const int p = l / RW;
+        sweep_line<T>(ref + p * PS + FP + l - p * RW + 1, FP, RH, ringy);
+    }
     __syncthreads();
-    const long long base = Ln.off[k] + (long long)z * ex * ey;
+    T *outk = out + Ln.off[k];
+    int *io_new = iota_new ? iota_new + Ln.off[k] : nullptr;
+    const int *io_old = iota_old ? iota_old + cr.ooff : nullptr;
     double vsum = 0.0;
-    for (int e = threadIdx.x; e < wx * wy; e += kBlock) {
-        const int r = e / wx, c = e - r * wx;
-        const T d = ref[(r + hy) * RP + c + hx];
-        const bool in = f[(r + hy + 1) * FP + c + hx + 1] > T(0);
-        const long long idx = base + (long long)(y0 + r) * ex + x0 + c;
-        if (g.dim == 2) {
+    for (Walk3 w(threadIdx.x, wx, wy); w.p < nz; w.step()) {
+        const int a = w.p * PS + (w.r + hy + 1) * FP + w.c + hx + 1;
+        const T d = ref[a];
+        const bool in = f[a] > T(0);
+        const int idx = ((z0 + w.p) * ey + y0 + w.r) * ex + x0 + w.c;
+        if (!d3) {
             const T dc = d < W ? d : W;
             const T p = in ? dc : -dc;
-            out[idx] = p;
+            outk[idx] = p;
             double cl = (double)p + 0.5;
             cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
             vsum += cl;
         } else {
-            out[idx] = in ? d : -d;
+            outk[idx] = in ? d : -d;
         }
-        if (iota_new) {
-            const int ro = rtab[r + hy + 1], co = ctab[c + hx + 1];
-            iota_new[idx] = (ro >= 0 && co >= 0) ? iota_old[cr.ooff + ro + co] : -1;
+        if (io_new) {
+            const int ro = rtab[w.p * FH + w.r + hy + 1], co = ctab[w.c + hx + 1];
+            io_new[idx] = (ro >= 0 && co >= 0) ? io_old[ro + co] : -1;
         }
     }
-    if (g.dim == 2) {
+    if (!d3) {
         const double s = block_sum(vsum, red);
         if (threadIdx.x == 0) vol_part[item] = s;
     }
@@ -1253,19 +1341,19 @@ __global__ void k_item_counts(Boxes L, long long *cnt, int4 *tilings, unsigned l
     for (int q = 0; q < kKinds; ++q) {
         long long *c = cnt + (long long)q * 3 * G;
         c[k] = c[G + k] = c[2LL * G + k] = 0;
-        tilings[(long long)q * G + k] = make_int4(0, 0, 0, 0);
+        int4 *rec = tilings + 2 * ((long long)q * G + k);
+        rec[0] = rec[1] = make_int4(0, 0, 0, 0);
         if (!L.alive[k]) continue;
         const int *e = L.ext + 3 * k;
-        const Tiling t = kind_tiling(q, e, R, K, budget);
-        tilings[(long long)q * G + k] = make_int4(t.nxs, t.nys, t.tx, t.ty);
+        const Tiling t = kind_tiling(q, e, R, K, budget, small);
+        rec[0] = make_int4(t.nxs, t.nys, t.tx, t.ty);
+        rec[1] = make_int4(t.nb, 0, 0, 0);
         if (t.nxs == 0) {
             atomicMax(&lds_max[q * kClasses + 1], 0xffffffffffffffffULL);  // infeasible tiling
             continue;
         }
-        const long long n = kind_items(q, e, R, K, budget);
-        int h, h2;
-        kind_halos(q, R, K, &h, &h2);
-        const long long need = lds_need(q, t.tx, t.ty, h, h2, t.nxs > 1, t.nys > 1);
+        const long long n = tiling_items(q, e, t);
+        const long long need = tiling_need(q, t, R, K);
         const int cls = need <= small ? 0 : 1;
         c[k] = n;
         c[(1LL + cls) * G + k] = n;

@@ -189,7 +189,7 @@ template <typename T> struct Sim final : SimBase {
     }
     gg_kernel_times kernel_times() const override { return ktimes; }
 
-    const int4 *tiles_of(int l, int kind) const { return itile[l].as<int4>() + (size_t)kind * G; }
+    const int4 *tiles_of(int l, int kind) const { return itile[l].as<int4>() + (size_t)kind * 2 * G; }
     Boxes boxes_of(int l) {
         return Boxes{lo[l].as<int>(), ext[l].as<int>(), alive[l].as<int>(), off[l].as<long long>()};
     }
@@ -251,7 +251,7 @@ template <typename T> struct Sim final : SimBase {
             alive[l].ensure(sizeof(int) * G);
             off[l].ensure(sizeof(long long) * (G + 1));
             ipref[l].ensure(sizeof(long long) * 3 * gg::kKinds * (size_t)(G + 1));
-            itile[l].ensure(sizeof(int4) * gg::kKinds * (size_t)G);
+            itile[l].ensure(sizeof(int4) * 2 * gg::kKinds * (size_t)G);
         }
         bmin.ensure(sizeof(int) * 3 * G);
         bmax.ensure(sizeof(int) * 3 * G);
