@@ -136,16 +136,16 @@ enum {
     GG_K_CONV_XY = 0,   /* predictor x and y passes (2D: whole predictor)          */
     GG_K_CONV_Z = 1,    /* predictor z pass (+ correction epilogue)                 */
     GG_K_COMPARE = 2,   /* corrector over global tiles                              */
-    GG_K_REINIT_XY = 3, /* reference values, x and y min-plus passes (2D: all)      */
-    GG_K_REINIT_Z = 4,  /* z min-plus pass, clamp, volume partial sums              */
+    GG_K_REINIT_XY = 3, /* reference values, x and y spreading sweeps (2D: all)     */
+    GG_K_REINIT_Z = 4,  /* z sweep, clamp, volume partial sums, next z convolution  */
     GG_K_PLAN = 5,      /* box plan, scans, work items, coverage lists              */
     GG_K_VOLUME = 6,    /* per-grain volume reduction                               */
     GG_K_CLASSES = 8
 };
 typedef struct {
     double ms[GG_K_CLASSES];          /* summed device time (HIP events)            */
-    int64_t launches[GG_K_CLASSES];   /* timed launches                             */
-    int64_t voxels[GG_K_CLASSES];     /* grain voxels those launches covered        */
+    int64_t launches[GG_K_CLASSES];   /* timed kernel dispatches                    */
+    int64_t voxels[GG_K_CLASSES];     /* grain voxels the timed spans covered       */
 } gg_kernel_times;
 
 /* Turn per-kernel timing on (resets the sums) or off.  While on, every launch

@@ -920,17 +920,15 @@ template <typename T> struct Carry {
     }
 };
 
-// Position (p, r, c) of element e of an array of planes of H rows of W values,
-// advanced by kBlock elements per step without division.
-struct Walk3 {
-    int p, r, c, W, H, dq, dm;
-    __device__ __forceinline__ Walk3(int e, int W_, int H_) : W(W_), H(H_) {
+// Position (r, c) of element e of an array of rows of W values, advanced by
+// kBlock elements per step without division.
+struct Walk2 {
+    int r, c, W, dq, dm;
+    __device__ __forceinline__ Walk2(int e, int W_) : W(W_) {
         dq = kBlock / W;
         dm = kBlock - dq * W;
-        const int rows = e / W;
-        c = e - rows * W;
-        p = rows / H;
-        r = rows - p * H;
+        r = e / W;
+        c = e - r * W;
     }
     __device__ __forceinline__ void step() {
         c += dm;
@@ -939,12 +937,17 @@ struct Walk3 {
             c -= W;
             ++r;
         }
-        while (r >= H) {
-            r -= H;
-            ++p;
-        }
     }
 };
+
+template <typename T> __device__ __forceinline__ T min3v(T a, T b, T c) {
+    const T m = a < b ? a : b;
+    return m < c ? m : c;
+}
+template <typename T> __device__ __forceinline__ T max3v(T a, T b, T c) {
+    const T m = a > b ? a : b;
+    return m > c ? m : c;
+}
 
 // Reference values next to the sign change, then the x and y spreading sweeps,
 // on one tile of nz consecutive z planes of the new box.  3D: writes the partial
@@ -1001,18 +1004,20 @@ __global__ void __launch_bounds__(kBlock)
         }
     for (int i = threadIdx.x; i < FW; i += kBlock) ctab[i] = cr.col_code(x0 - hx - 1 + i);
     __syncthreads();
-    // stage the f planes: kLoadBatch loads in flight per lane
-    for (Walk3 w(threadIdx.x, FW, FH); w.p < nz;) {
+    // stage the f planes (their rows are consecutive: row R = p * FH + r);
+    // kLoadBatch loads in flight per lane
+    const int NR = nz * FH;
+    for (Walk2 w(threadIdx.x, FW); w.r < NR;) {
         T v[kLoadBatch];
         int at[kLoadBatch];
 #pragma unroll
         for (int j = 0; j < kLoadBatch; ++j) {
             at[j] = -1;
             v[j] = -W;
-            if (w.p < nz) {
-                const int ro = rtab[w.p * FH + w.r], co = ctab[w.c];
+            if (w.r < NR) {
+                const int ro = rtab[w.r], co = ctab[w.c];
                 if (ro >= 0 && co >= 0) v[j] = src[ro + co];
-                at[j] = w.p * PS + w.r * FP + w.c;
+                at[j] = w.r * FP + w.c;
             }
             w.step();
         }
@@ -1021,66 +1026,63 @@ __global__ void __launch_bounds__(kBlock)
             if (at[j] >= 0) f[at[j]] = v[j];
     }
     __syncthreads();
-    // reference values of the cells inside the ring; the z neighbours of
-    // kLoadBatch cells are gathered before any is used
-    for (Walk3 w(threadIdx.x, FW, FH); w.p < nz;) {
-        T zm[kLoadBatch], zp[kLoadBatch];
-        int at[kLoadBatch];
-        bool ib[kLoadBatch];
-#pragma unroll
-        for (int j = 0; j < kLoadBatch; ++j) {
-            at[j] = -1;
-            ib[j] = false;
-            zm[j] = zp[j] = -W;
-            if (w.p < nz && w.r > 0 && w.r < FH - 1 && w.c > 0 && w.c < FW - 1) {
-                const int a = w.p * PS + w.r * FP + w.c;
-                const int co = ctab[w.c];
-                at[j] = a;
-                ib[j] = co != -2 && rtab[w.p * FH + w.r] != -2;
-                if (d3 && ib[j]) {
-                    if (w.p > 0) {
-                        zm[j] = f[a - PS];
-                    } else {
-                        const int ro = rzm[w.r];
-                        if (ro >= 0 && co >= 0) zm[j] = src[ro + co];
-                    }
-                    if (w.p < nz - 1) {
-                        zp[j] = f[a + PS];
-                    } else {
-                        const int ro = rzp[w.r];
-                        if (ro >= 0 && co >= 0) zp[j] = src[ro + co];
-                    }
-                }
+    // reference values: each lane takes cell positions of the tile and walks
+    // them through the nz planes, so that the z neighbours of a cell are the
+    // previous and next centre values (memory only below the first and above
+    // the last plane, fetched one position ahead).  Over all neighbours, the
+    // smallest value is <= 0 exactly when an inside cell has an outside
+    // neighbour, and then it is the extreme one; likewise the largest for an
+    // outside cell.  theta = fc / (fc - fn) is monotone in fn on that side, and
+    // so are the rounded operations, so the extreme neighbour gives the
+    // smallest theta.
+    {
+        Walk2 w(threadIdx.x, RW);
+        T zm_n = -W, zp_n = -W;
+        auto fetch = [&](int r, int c) {
+            zm_n = zp_n = -W;
+            if (d3 && r < RH) {
+                const int co = ctab[c + 1], rm = rzm[r + 1], rp = rzp[r + 1];
+                if (rm >= 0 && co >= 0) zm_n = src[rm + co];
+                if (rp >= 0 && co >= 0) zp_n = src[rp + co];
             }
+        };
+        fetch(w.r, w.c);
+        while (w.r < RH) {
+            const int r = w.r + 1, c = w.c + 1;
+            T zm = zm_n;
+            const T zlast = zp_n;
             w.step();
-        }
-#pragma unroll
-        for (int j = 0; j < kLoadBatch; ++j) {
-            if (at[j] < 0) continue;
-            T r = inf;
-            if (ib[j]) {
-                const T *fc_p = f + at[j];
-                const T fc = fc_p[0];
-                const bool in = fc > T(0);
-                const T nb[6] = {fc_p[-1], fc_p[1], fc_p[-FP], fc_p[FP], zm[j], zp[j]};
-                // theta = fc / (fc - fn) is monotone in fn (decreasing for an
-                // inside voxel over fn <= 0, increasing for an outside voxel
-                // over fn > 0), and so are the rounded operations: the
-                // smallest theta is the one at the extreme opposite neighbour
-                T ext = in ? inf : -inf;
-                bool any = false;
-#pragma unroll
-                for (int q = 0; q < 6; ++q) {
-                    if (q >= 4 && !d3) break;
-                    const T fn = nb[q];
-                    if ((fn > T(0)) != in) {
-                        any = true;
-                        ext = in ? (fn < ext ? fn : ext) : (fn > ext ? fn : ext);
+            fetch(w.r, w.c);
+            const bool colin = ctab[c] != -2;
+            int a = r * FP + c;
+            T cur = f[a];
+            for (int p = 0; p < nz; ++p, a += PS) {
+                const T nxt = p + 1 < nz ? f[a + PS] : zlast;
+                T rv = inf;
+                if (colin && rtab[p * FH + r] != -2) {
+                    const T n0 = f[a - 1], n1 = f[a + 1], n2 = f[a - FP], n3 = f[a + FP];
+                    T lo, hi;
+                    if (d3) {
+                        lo = min3v(n0, n1, n2);
+                        lo = min3v(lo, n3, zm);
+                        lo = lo < nxt ? lo : nxt;
+                        hi = max3v(n0, n1, n2);
+                        hi = max3v(hi, n3, zm);
+                        hi = hi > nxt ? hi : nxt;
+                    } else {
+                        lo = min3v(n0, n1, n2);
+                        lo = lo < n3 ? lo : n3;
+                        hi = max3v(n0, n1, n2);
+                        hi = hi > n3 ? hi : n3;
                     }
+                    const bool in = cur > T(0);
+                    const T ext = in ? lo : hi;
+                    if ((ext > T(0)) != in) rv = cur / (cur - ext);
                 }
-                if (any) r = fc / (fc - ext);
+                ref[a] = rv;
+                zm = cur;
+                cur = nxt;
             }
-            ref[at[j]] = r;
         }
     }
     __syncthreads();
@@ -1101,24 +1103,28 @@ __global__ void __launch_bounds__(kBlock)
     int *io_new = iota_new ? iota_new + Ln.off[k] : nullptr;
     const int *io_old = iota_old ? iota_old + cr.ooff : nullptr;
     double vsum = 0.0;
-    for (Walk3 w(threadIdx.x, wx, wy); w.p < nz; w.step()) {
-        const int a = w.p * PS + (w.r + hy + 1) * FP + w.c + hx + 1;
-        const T d = ref[a];
-        const bool in = f[a] > T(0);
-        const int idx = ((z0 + w.p) * ey + y0 + w.r) * ex + x0 + w.c;
-        if (!d3) {
-            const T dc = d < W ? d : W;
-            const T p = in ? dc : -dc;
-            outk[idx] = p;
-            double cl = (double)p + 0.5;
-            cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
-            vsum += cl;
-        } else {
-            outk[idx] = in ? d : -d;
-        }
-        if (io_new) {
-            const int ro = rtab[w.p * FH + w.r + hy + 1], co = ctab[w.c + hx + 1];
-            io_new[idx] = (ro >= 0 && co >= 0) ? io_old[ro + co] : -1;
+    const int plane_vals = ex * ey;
+    for (Walk2 w(threadIdx.x, wx); w.r < wy; w.step()) {
+        int a = (w.r + hy + 1) * FP + w.c + hx + 1;
+        int idx = (z0 * ey + y0 + w.r) * ex + x0 + w.c;
+        const int co = ctab[w.c + hx + 1];
+        for (int p = 0; p < nz; ++p, a += PS, idx += plane_vals) {
+            const T d = ref[a];
+            const bool in = f[a] > T(0);
+            if (!d3) {
+                const T dc = d < W ? d : W;
+                const T pv = in ? dc : -dc;
+                outk[idx] = pv;
+                double cl = (double)pv + 0.5;
+                cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
+                vsum += cl;
+            } else {
+                outk[idx] = in ? d : -d;
+            }
+            if (io_new) {
+                const int ro = rtab[p * FH + w.r + hy + 1];
+                io_new[idx] = (ro >= 0 && co >= 0) ? io_old[ro + co] : -1;
+            }
         }
     }
     if (!d3) {
@@ -1334,30 +1340,42 @@ __global__ void k_plan(Boxes Lo, Boxes Ln, int *bmin, int *bmax, unsigned *occ, 
 // Per-grain work item counts of the four stencil kinds, split into the two
 // launch classes, the stored tilings, and the largest LDS need per class.
 // cnt holds 3 arrays of G per kind: all items, class 0, class 1.
+// One thread per (grain, kind); grid (ceil(G / 256), kKinds).  The per-class
+// LDS maxima are reduced over the wave before one atomic per wave and class.
 __global__ void k_item_counts(Boxes L, long long *cnt, int4 *tilings, unsigned long long *lds_max, int R, int K, int G,
                               int budget, int small) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= G) return;
-    for (int q = 0; q < kKinds; ++q) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x, q = blockIdx.y;
+    unsigned long long need_c[kClasses] = {0, 0};
+    if (k < G) {
         long long *c = cnt + (long long)q * 3 * G;
         c[k] = c[G + k] = c[2LL * G + k] = 0;
         int4 *rec = tilings + 2 * ((long long)q * G + k);
         rec[0] = rec[1] = make_int4(0, 0, 0, 0);
-        if (!L.alive[k]) continue;
-        const int *e = L.ext + 3 * k;
-        const Tiling t = kind_tiling(q, e, R, K, budget, small);
-        rec[0] = make_int4(t.nxs, t.nys, t.tx, t.ty);
-        rec[1] = make_int4(t.nb, 0, 0, 0);
-        if (t.nxs == 0) {
-            atomicMax(&lds_max[q * kClasses + 1], 0xffffffffffffffffULL);  // infeasible tiling
-            continue;
+        if (L.alive[k]) {
+            const int *e = L.ext + 3 * k;
+            const Tiling t = kind_tiling(q, e, R, K, budget, small);
+            rec[0] = make_int4(t.nxs, t.nys, t.tx, t.ty);
+            rec[1] = make_int4(t.nb, 0, 0, 0);
+            if (t.nxs == 0) {
+                need_c[1] = 0xffffffffffffffffULL;  // infeasible tiling
+            } else {
+                const long long n = tiling_items(q, e, t);
+                const long long need = tiling_need(q, t, R, K);
+                const int cls = need <= small ? 0 : 1;
+                c[k] = n;
+                c[(1LL + cls) * G + k] = n;
+                need_c[cls] = (unsigned long long)need;
+            }
         }
-        const long long n = tiling_items(q, e, t);
-        const long long need = tiling_need(q, t, R, K);
-        const int cls = need <= small ? 0 : 1;
-        c[k] = n;
-        c[(1LL + cls) * G + k] = n;
-        atomicMax(&lds_max[q * kClasses + cls], (unsigned long long)need);
+    }
+#pragma unroll
+    for (int cl = 0; cl < kClasses; ++cl) {
+        unsigned long long v = need_c[cl];
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long u = __shfl_xor(v, o, 64);
+            v = u > v ? u : v;
+        }
+        if ((threadIdx.x & 63) == 0 && v) atomicMax(&lds_max[q * kClasses + cl], v);
     }
 }
 
@@ -1418,7 +1436,15 @@ __global__ void __launch_bounds__(1024) k_scan_int(const int *in, int *out, int 
     const int chunk = (n + 1023) / 1024;
     const int b = min(t * chunk, n), e = min(b + chunk, n);
     long long s = 0;
-    for (int i = b; i < e; ++i) s += in[i];
+    int i = b;
+    for (; i + 8 <= e; i += 8) {  // 8 loads in flight
+        int v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = in[i + j];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s += v[j];
+    }
+    for (; i < e; ++i) s += in[i];
     part[t] = s;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
@@ -1428,7 +1454,18 @@ __global__ void __launch_bounds__(1024) k_scan_int(const int *in, int *out, int 
         __syncthreads();
     }
     long long base = t ? part[t - 1] : 0;
-    for (int i = b; i < e; ++i) {
+    i = b;
+    for (; i + 8 <= e; i += 8) {
+        int v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = in[i + j];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            out[i + j] = (int)base;
+            base += v[j];
+        }
+    }
+    for (; i < e; ++i) {
         out[i] = (int)base;
         base += in[i];
     }
@@ -1483,13 +1520,16 @@ __global__ void k_coverage(Boxes L, int *cnt_or_cursor, int *list, TileArgs ta, 
 }
 
 // Per-grain volume from the per-item partial sums, in item order.
-__global__ void k_volumes(const Boxes L, const long long *pref, const double *vol_part, double *vol, int G) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per grain: lane-strided partial sums, then a butterfly (fixed order).
+__global__ void __launch_bounds__(64) k_volumes(const Boxes L, const long long *pref, const double *vol_part,
+                                                double *vol, int G) {
+    const int k = blockIdx.x;
     if (k >= G) return;
     double s = 0.0;
     if (L.alive[k])
-        for (long long i = pref[k]; i < pref[k + 1]; ++i) s += vol_part[i];
-    vol[k] = s;
+        for (long long i = pref[k] + threadIdx.x; i < pref[k + 1]; i += 64) s += vol_part[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (threadIdx.x == 0) vol[k] = s;
 }
 
 __global__ void k_totals(const long long *arena_pref, const long long *pref, const int *cov_off, int ntiles,

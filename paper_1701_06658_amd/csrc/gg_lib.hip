@@ -143,6 +143,7 @@ template <typename T> struct Sim final : SimBase {
         hipEvent_t a, b;
         int cls;
         long long vox;
+        int n;  // kernel dispatches in the span
     };
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -160,12 +161,13 @@ template <typename T> struct Sim final : SimBase {
     }
     void tbegin(int cls, long long vox) {
         if (!prof) return;
-        Span sp{next_event(), nullptr, cls, vox};
+        Span sp{next_event(), nullptr, cls, vox, 1};
         HIPCHECK(hipEventRecord(sp.a, stream));
         spans.push_back(sp);
     }
-    void tend() {
+    void tend(int dispatches = 1) {
         if (!prof) return;
+        spans.back().n = dispatches;
         spans.back().b = next_event();
         HIPCHECK(hipEventRecord(spans.back().b, stream));
     }
@@ -176,7 +178,7 @@ template <typename T> struct Sim final : SimBase {
             float ms = 0.f;
             HIPCHECK(hipEventElapsedTime(&ms, sp.a, sp.b));
             ktimes.ms[sp.cls] += ms;
-            ktimes.launches[sp.cls] += 1;
+            ktimes.launches[sp.cls] += sp.n;
             ktimes.voxels[sp.cls] += sp.vox;
         }
         spans.clear();
@@ -330,7 +332,7 @@ template <typename T> struct Sim final : SimBase {
         tbegin(GG_K_PLAN, 0);
         HIPCHECK(hipMemsetAsync(ldsmax.p, 0, sizeof(unsigned long long) * gg::kKinds * gg::kClasses, stream));
         const int tb = 256, gb = (G + tb - 1) / tb;
-        hipLaunchKernelGGL(gg::k_item_counts, dim3(gb), dim3(tb), 0, stream, L, cnt.as<long long>(), itile[l].as<int4>(),
+        hipLaunchKernelGGL(gg::k_item_counts, dim3(gb, gg::kKinds), dim3(tb), 0, stream, L, cnt.as<long long>(), itile[l].as<int4>(),
                            ldsmax.as<unsigned long long>(), R, K, G, gg::lds_budget<T>(),
                            gg::kSmallLdsBytes / (int)sizeof(T));
         hipLaunchKernelGGL(gg::k_scan_multi, dim3(3 * gg::kKinds), dim3(1024), 0, stream, cnt.as<long long>(),
@@ -436,9 +438,11 @@ template <typename T> struct Sim final : SimBase {
         const Totals &t = tot[l];
         if (t.items[gg::KIND_CXY][0] <= 0) return;
         tbegin(GG_K_CONV_XY, t.arena);
+        int nd = 0;
         for (int c = 0; c < gg::kClasses; ++c) {
             const gg::ItemRefs ir = refs(l, gg::KIND_CXY, c);
             if (ir.n <= 0) continue;
+            ++nd;
             const dim3 gr(grid_of(gg::xcd_grid(ir.n))), bl(gg::kBlock);
             const size_t lds = sizeof(T) * t.lds[gg::KIND_CXY][c];
             auto args = std::make_tuple(boxes_of(l), ir, src, dst, (const T *)taps_d.as<T>(), R, W, grid_args(), ph);
@@ -453,7 +457,7 @@ template <typename T> struct Sim final : SimBase {
             else if (R == 8) go(gg::k_conv_xy<T, 8, false>);
             else go(gg::k_conv_xy<T, 0, false>);
         }
-        tend();
+        tend(nd);
         HIPCHECK(hipGetLastError());
     }
 
@@ -462,14 +466,16 @@ template <typename T> struct Sim final : SimBase {
         const Totals &t = tot[l];
         if (t.items[gg::KIND_CZ][0] <= 0) return;
         tbegin(GG_K_CONV_Z, t.arena);
+        int nd = 0;
         for (int c = 0; c < gg::kClasses; ++c) {
             const gg::ItemRefs ir = refs(l, gg::KIND_CZ, c);
             if (ir.n <= 0) continue;
+            ++nd;
             hipLaunchKernelGGL(gg::k_conv_z<T>, dim3(grid_of(gg::xcd_grid(ir.n))), dim3(gg::kBlock),
                                sizeof(T) * t.lds[gg::KIND_CZ][c], stream, boxes_of(l), ir, src, dst, taps_d.as<T>(), R,
                                W, grid_args());
         }
-        tend();
+        tend(nd);
         HIPCHECK(hipGetLastError());
     }
 
@@ -483,21 +489,25 @@ template <typename T> struct Sim final : SimBase {
         vol_part.ensure(sizeof(double) * (size_t)std::max<long long>(t.items[vk][0], 1) * 5 / 4);
         if (t.items[gg::KIND_RXY][0] > 0) {
             tbegin(GG_K_REINIT_XY, t.arena);
+            int nd = 0;
             T *out = dim == 3 ? d2 : phi;
             for (int c = 0; c < gg::kClasses; ++c) {
                 const gg::ItemRefs ir = refs(ln_l, gg::KIND_RXY, c);
                 if (ir.n <= 0) continue;
+                ++nd;
                 hipLaunchKernelGGL(gg::k_reinit_xy<T>, dim3(grid_of(gg::xcd_grid(ir.n))), dim3(gg::kBlock),
                                    sizeof(T) * t.lds[gg::KIND_RXY][c], stream, boxes_of(lo_l), boxes_of(ln_l), ir,
                                    phic, out, iota_old, iota_new, vol_part.as<double>(), K, W, g);
             }
-            tend();
+            tend(nd);
         }
         if (dim == 3 && t.items[gg::KIND_ZF][0] > 0) {
             tbegin(GG_K_REINIT_Z, t.arena);
+            int nd = 0;
             for (int c = 0; c < gg::kClasses; ++c) {
                 const gg::ItemRefs ir = refs(ln_l, gg::KIND_ZF, c);
                 if (ir.n <= 0) continue;
+                ++nd;
                 const dim3 gr(grid_of(gg::xcd_grid(ir.n))), bl(gg::kBlock);
                 const size_t lds = sizeof(T) * t.lds[gg::KIND_ZF][c];
                 auto args = std::make_tuple(boxes_of(ln_l), ir, (const T *)d2, phi, tz, vol_part.as<double>(),
@@ -509,11 +519,11 @@ template <typename T> struct Sim final : SimBase {
                 else if (R == 8) go(gg::k_zfused<T, 8>);
                 else go(gg::k_zfused<T, 0>);
             }
-            tend();
+            tend(nd);
         }
         const int tb = 256, gb = (G + tb - 1) / tb;
         tbegin(GG_K_VOLUME, t.arena);
-        hipLaunchKernelGGL(gg::k_volumes, dim3(gb), dim3(tb), 0, stream, boxes_of(ln_l), pref_of(ln_l, vk, 0),
+        hipLaunchKernelGGL(gg::k_volumes, dim3(G), dim3(64), 0, stream, boxes_of(ln_l), pref_of(ln_l, vk, 0),
                            vol_part.as<double>(), vol.as<double>(), G);
         tend();
         HIPCHECK(hipGetLastError());
