@@ -93,10 +93,11 @@ template <> __device__ __forceinline__ float tinf<float>() { return __builtin_in
 // LDS values needed by an output tile tx * ty of nz planes.  h: stencil halo (R
 // for the predictor kinds, K for the re-initialization kinds), h2: R for the
 // fused z kind.  The re-initialization sweeps whole box lines, so its tiles need
-// a halo only along an axis that is split into several tiles (sx, sy).  Only the
-// re-initialization xy kind batches several planes into one work item: per
-// plane an f tile and a reference tile of (ty + 2hy + 2) rows of pitch
-// (tx + 2hx + 2) | 1, plus int offset tables (counted as one value each).
+// a halo only along an axis that is split into several tiles (sx, sy).  The two
+// re-initialization kinds batch several planes (xy kind: z planes, fused z
+// kind: y rows) into one work item.  xy kind: per plane an f tile and a
+// reference tile of (ty + 2hy + 2) rows of pitch (tx + 2hx + 2) | 1; both
+// kinds add int offset tables (counted as one value each).
 __host__ __device__ inline long long lds_need(int kind, int tx, int ty, int h, int h2, bool sx, bool sy, int nz = 1) {
     if (kind == KIND_CXY)
         return (long long)((tx + 2 * h) | 1) * (ty + 2 * h) + kKB + (long long)tx * (ty + 2 * h + kKB);
@@ -105,9 +106,10 @@ __host__ __device__ inline long long lds_need(int kind, int tx, int ty, int h, i
         const long long FW = tx + 2 * hx + 2, FH = ty + 2 * hy + 2;
         return (long long)nz * (2 * (FW | 1) * FH + FH) + 2 * FH + FW;
     }
-    if (kind == KIND_ZF) {
+    if (kind == KIND_ZF) {  // nz y rows of tx columns, (ty + 2 h2 + 2 hz + kKB) z rows; int offset tables
         const int hz = sy ? h : 0;
-        return (long long)tx * (ty + 2 * h2 + 2 * hz) + (long long)tx * (ty + 2 * h2 + kKB);
+        const long long D = ty + 2 * h2 + 2 * hz;
+        return (long long)nz * tx * (D + kKB + 1) + D;
     }
     return (long long)tx * (ty + 2 * h);  // prologue z pass
 }
@@ -145,7 +147,7 @@ __host__ __device__ inline Tiling choose_tiling(int kind, int ex, int ey, int pl
         t.ty = (ey + nys - 1) / nys;
         break;
     }
-    if (kind == KIND_RXY && t.nxs > 0 && planes > 1) {
+    if ((kind == KIND_RXY || kind == KIND_ZF) && t.nxs > 0 && planes > 1) {
         const bool sx = t.nxs > 1, sy = t.nys > 1;
         const long long one = lds_need(kind, t.tx, t.ty, h, h2, sx, sy, 1);
         const long long per = lds_need(kind, t.tx, t.ty, h, h2, sx, sy, 2) - one;
@@ -229,10 +231,10 @@ __device__ __forceinline__ ItemTile decode_item(long long item, int kind, const 
     const int per = tl.nxs * tl.nys;
     const int chunk = sub / per;
     const int rem = sub - chunk * per;
-    if (kind == KIND_RXY) {
+    if (kind == KIND_RXY || kind == KIND_ZF) {
         const int nb = tilings[2 * it.k + 1].x;
         it.plane = chunk * nb;
-        it.np = min(nb, e[2] - it.plane);
+        it.np = min(nb, kind_planes(kind, e) - it.plane);
     } else {
         it.plane = chunk;
         it.np = 1;
@@ -1133,9 +1135,13 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
-// Fused z sweep (3D) over one tile (x chunk * z range) of one y row of the new
-// box: z spreading, sign and band clamp -> phi (optionally stored) and the
-// tile's volume; then the next predictor's z pass of phi -> t.
+// Fused z sweep (3D) over one tile (x chunk * z range) of ny consecutive y rows
+// of the new box: z spreading, sign and band clamp -> phi (optionally stored)
+// and the tile's volume; then the next predictor's z pass of phi -> t.
+//
+// LDS: z rows of QW = ny * wx values (the y rows side by side, so that the
+// lanes of a sweep or of the z convolution read consecutive words), then int
+// tables: the box offset of every column (y row and x) and of every z row.
 template <typename T, int RS>
 __global__ void __launch_bounds__(kBlock)
     k_zfused(Boxes Ln, ItemRefs ir, const T *__restrict__ d2, T *__restrict__ phi_out,
@@ -1149,73 +1155,96 @@ __global__ void __launch_bounds__(kBlock)
     if (cls_item >= ir.n) return;
     const ItemTile it = decode_item(cls_item, KIND_ZF, Ln, ir);
     const long long item = it.item;
-    const int k = it.k, y = it.plane, x0 = it.x0, z0 = it.y0, wx = it.wx, wz = it.wy;
+    const int k = it.k, y0 = it.plane, ny = it.np, x0 = it.x0, z0 = it.y0, wx = it.wx, wz = it.wy;
     const int ex = Ln.ext[3 * k], ey = Ln.ext[3 * k + 1], ez = Ln.ext[3 * k + 2];
     const int hz = it.nys > 1 ? K : 0;
-    const int DH = wz + 2 * R + 2 * hz, PH = wz + 2 * R;
-    T *dc = sm, *pc = sm + wx * DH;
-    const long long plane = (long long)ex * ey;
-    const long long rowbase = Ln.off[k] + (long long)y * ex + x0;
+    const int DH = wz + 2 * R + 2 * hz, QW = ny * wx, plane = ex * ey;
+    T *dc = sm;  // DH + kKB rows
+    int *cq = reinterpret_cast<int *>(sm + (DH + kKB) * QW), *rz = cq + QW;
+    const T *src = d2 + Ln.off[k];
+    for (int q = threadIdx.x; q < QW; q += kBlock) {
+        const int j = q / wx;
+        cq[q] = (y0 + j) * ex + x0 + q - j * wx;
+    }
+    for (int r = threadIdx.x; r < DH; r += kBlock) {
+        const int zz = axis_map(z0 - R - hz + r, ez, g.n[2]);
+        rz[r] = zz >= 0 ? zz * plane : -1;
+    }
     T tp[RS > 0 ? 2 * RS + 1 : 1];
     if constexpr (RS > 0) {
 #pragma unroll
         for (int t = 0; t <= 2 * RS; ++t) tp[t] = taps[t];
     }
     const T inf = tinf<T>();
-    stage_rows<T>(
-        dc, wx, wx, DH, d2,
-        [&](int rr) -> long long {
-            const int zz = axis_map(z0 - R - hz + rr, ez, g.n[2]);
-            return zz >= 0 ? rowbase + (long long)zz * plane : -1;
-        },
-        [&](int c) { return c; }, inf);
+    __syncthreads();
+    for (Walk2 w(threadIdx.x, QW); w.r < DH;) {
+        T v[kLoadBatch];
+        int at[kLoadBatch];
+#pragma unroll
+        for (int j = 0; j < kLoadBatch; ++j) {
+            at[j] = -1;
+            v[j] = inf;
+            if (w.r < DH) {
+                const int ro = rz[w.r];
+                if (ro >= 0) v[j] = src[ro + cq[w.c]];
+                at[j] = w.r * QW + w.c;
+            }
+            w.step();
+        }
+#pragma unroll
+        for (int j = 0; j < kLoadBatch; ++j)
+            if (at[j] >= 0) dc[at[j]] = v[j];
+    }
     __syncthreads();
     // z spreading, one lane per column; a whole periodic z axis is a ring whose
     // copies in the halo rows are refreshed afterwards
     const bool ring = it.nys == 1 && ez == g.n[2];
-    for (int c = threadIdx.x; c < wx; c += kBlock) {
+    for (int q = threadIdx.x; q < QW; q += kBlock) {
         if (ring) {
-            sweep_line_signed<T>(dc + R * wx + c, wx, ez, true);
+            sweep_line_signed<T>(dc + R * QW + q, QW, ez, true);
             for (int j = 0; j < R; ++j) {
-                dc[j * wx + c] = dc[(ez + j) * wx + c];
-                dc[(R + ez + j) * wx + c] = dc[(R + j) * wx + c];
+                dc[j * QW + q] = dc[(ez + j) * QW + q];
+                dc[(R + ez + j) * QW + q] = dc[(R + j) * QW + q];
             }
         } else {
-            sweep_line_signed<T>(dc + c, wx, DH, false);
+            sweep_line_signed<T>(dc + q, QW, DH, false);
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < wx * PH; e += kBlock) {
-        const int r = e / wx, c = e - r * wx;
-        T p;
-        if (axis_map(z0 - R + r, ez, g.n[2]) < 0) {
-            p = -W;  // outside the box the predictor reads the fill value
+    // phi in place over the rows the z convolution reads (outside the box the
+    // predictor reads the fill value)
+    T *pc = dc + hz * QW;
+    const int PH = wz + 2 * R;
+    for (Walk2 w(threadIdx.x, QW); w.r < PH; w.step()) {
+        T *pv = pc + w.r * QW + w.c;
+        if (rz[w.r + hz] < 0) {
+            *pv = -W;
         } else {
-            const T v = dc[(r + hz) * wx + c];
-            const T a = fabs(v);
+            const T v = *pv, a = fabs(v);
             const T d = a < W ? a : W;
-            p = signbit(v) ? -d : d;
+            *pv = signbit(v) ? -d : d;
         }
-        pc[r * wx + c] = p;
     }
     __syncthreads();
+    T *phik = phi_out ? phi_out + Ln.off[k] : nullptr;
+    T *tk = t_out + Ln.off[k];
     double vsum = 0.0;
     const int ngz = (wz + kKB - 1) / kKB;
-    for (int e = threadIdx.x; e < ngz * wx; e += kBlock) {
-        const int c = e % wx, r0 = (e / wx) * kKB;
+    for (Walk2 w(threadIdx.x, QW); w.r < ngz; w.step()) {
+        const int r0 = w.r * kKB, q = w.c;
         T acc[kKB];
-        gauss_run<T, RS>(pc + r0 * wx + c, wx, tp, taps, R, acc);
+        gauss_run<T, RS>(pc + r0 * QW + q, QW, tp, taps, R, acc);
+        int idx = (z0 + r0) * plane + cq[q];
 #pragma unroll
-        for (int q = 0; q < kKB; ++q) {
-            const int r = r0 + q;
+        for (int u = 0; u < kKB; ++u, idx += plane) {
+            const int r = r0 + u;
             if (r >= wz) break;
-            const long long idx = rowbase + (long long)(z0 + r) * plane + c;
-            const T p = pc[(r + R) * wx + c];
-            if (phi_out) phi_out[idx] = p;
+            const T p = pc[(r + R) * QW + q];
+            if (phik) phik[idx] = p;
             double cl = (double)p + 0.5;
             cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
             vsum += cl;
-            t_out[idx] = acc[q];
+            tk[idx] = acc[u];
         }
     }
     const double s = block_sum(vsum, red);
