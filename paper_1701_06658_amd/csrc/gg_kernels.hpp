@@ -45,7 +45,10 @@ struct Boxes {
 
 // Work items of every kind come in two launch classes by their LDS need, so
 // that the many small boxes are not launched with the LDS of the largest one.
-constexpr int kSmallLdsBytes = 20480;
+#ifndef GG_SMALL_LDS_BYTES
+#define GG_SMALL_LDS_BYTES 20480
+#endif
+constexpr int kSmallLdsBytes = GG_SMALL_LDS_BYTES;
 constexpr int kClasses = 2;
 
 struct Totals {
@@ -535,6 +538,26 @@ __device__ inline T correct_prediction(const Physics<T> &ph, int k, long long id
 
 // --------------------------------------------------------- predictor kernels
 
+// Position (r, c) of element e of an array of rows of W values, advanced by
+// kBlock elements per step without division.
+struct Walk2 {
+    int r, c, W, dq, dm;
+    __device__ __forceinline__ Walk2(int e, int W_) : W(W_) {
+        dq = kBlock / W;
+        dm = kBlock - dq * W;
+        r = e / W;
+        c = e - r * W;
+    }
+    __device__ __forceinline__ void step() {
+        c += dm;
+        r += dq;
+        if (c >= W) {
+            c -= W;
+            ++r;
+        }
+    }
+};
+
 struct GridArgs {
     int n[3];
     int dim;
@@ -571,8 +594,9 @@ __global__ void __launch_bounds__(kBlock)
         [&](int cc) { return axis_map(x0 - R + cc, ex, g.n[0]); }, -W);
     __syncthreads();
     const int ngx = (wx + kKB - 1) / kKB;
-    for (int e = threadIdx.x; e < ngx * RH; e += kBlock) {
-        const int rr = e % RH, c0 = (e / RH) * kKB;
+    // x pass: consecutive lanes take consecutive rows (odd pitch: no bank conflicts)
+    for (Walk2 w(threadIdx.x, RH); w.r < ngx; w.step()) {
+        const int rr = w.c, c0 = w.r * kKB;
         T acc[kKB];
         if (axis_map(y0 - R + rr, ey, g.n[1]) < 0) {
 #pragma unroll
@@ -587,17 +611,18 @@ __global__ void __launch_bounds__(kBlock)
     __syncthreads();
     const int ngy = (wy + kKB - 1) / kKB;
     PairCache<T> pc;
-    for (int e = threadIdx.x; e < ngy * wx; e += kBlock) {
-        const int c = e % wx, r0 = (e / wx) * kKB;
+    T *outp = out + base;
+    for (Walk2 w(threadIdx.x, wx); w.r < ngy; w.step()) {
+        const int c = w.c, r0 = w.r * kKB;
         T acc[kKB];
         gauss_run<T, RS>(xp + r0 * wx + c, wx, tp, taps, R, acc);
+        int idx = (y0 + r0) * ex + x0 + c;  // within the plane
 #pragma unroll
-        for (int q = 0; q < kKB; ++q) {
+        for (int q = 0; q < kKB; ++q, idx += ex) {
             if (r0 + q >= wy) break;
-            const long long idx = base + (long long)(y0 + r0 + q) * ex + x0 + c;
             T v = acc[q];
-            if constexpr (PH) v = correct_prediction<T>(ph, k, idx, v, W, pc);
-            out[idx] = v;
+            if constexpr (PH) v = correct_prediction<T>(ph, k, base + idx, v, W, pc);
+            outp[idx] = v;
         }
     }
 }
@@ -664,6 +689,15 @@ template <typename T> struct Top2 {
     }
 };
 
+// Corrector register cache: grains per tile whose predicted values stay in
+// registers between the two passes (more cache, fewer waves per SIMD).
+#ifndef GG_CMP_CACHE_F32
+#define GG_CMP_CACHE_F32 24
+#endif
+#ifndef GG_CMP_CACHE_F64
+#define GG_CMP_CACHE_F64 12
+#endif
+
 constexpr int kTileVox = 512;
 constexpr int kVpt = kTileVox / kBlock;
 
@@ -715,7 +749,7 @@ __global__ void __launch_bounds__(kBlock)
     };
     // pass 1: top-2.  The first CR grains' values stay in registers for pass 2;
     // U grains' loads are issued together.
-    constexpr int CR = sizeof(T) == 4 ? 24 : 12;
+    constexpr int CR = sizeof(T) == 4 ? GG_CMP_CACHE_F32 : GG_CMP_CACHE_F64;
     constexpr int U = 4;
     T cache[CR][kVpt];
 #pragma unroll
@@ -830,7 +864,6 @@ __global__ void __launch_bounds__(kBlock)
         emit(j, val, hit, idx, l3);
     }
 }
-
 // Voxel labels: argmax over the covering grains (ties to the lowest id).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
@@ -919,26 +952,6 @@ template <typename T> struct Carry {
         int ox = xm + d[0];
         ox -= ox >= n[0] ? n[0] : 0;
         return ox < oex[0] ? ox : -1;
-    }
-};
-
-// Position (r, c) of element e of an array of rows of W values, advanced by
-// kBlock elements per step without division.
-struct Walk2 {
-    int r, c, W, dq, dm;
-    __device__ __forceinline__ Walk2(int e, int W_) : W(W_) {
-        dq = kBlock / W;
-        dm = kBlock - dq * W;
-        r = e / W;
-        c = e - r * W;
-    }
-    __device__ __forceinline__ void step() {
-        c += dm;
-        r += dq;
-        if (c >= W) {
-            c -= W;
-            ++r;
-        }
     }
 };
 
