@@ -93,6 +93,19 @@ template <typename T> __device__ __forceinline__ T tinf();
 template <> __device__ __forceinline__ double tinf<double>() { return __builtin_inf(); }
 template <> __device__ __forceinline__ float tinf<float>() { return __builtin_inff(); }
 
+// Hardware min / max.  No value on the path is NaN (device code is built
+// without NaN semantics); of +0 and -0 either may come back, which no result
+// depends on (a reference value fc / (fc - 0) is the same for both).
+__device__ __forceinline__ float vmin(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ double vmin(double a, double b) { return fmin(a, b); }
+__device__ __forceinline__ float vmax(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ double vmax(double a, double b) { return fmax(a, b); }
+
+// a / b: correctly rounded in FP64; in FP32 (the mixed path) the product with
+// the hardware reciprocal (about 1 ulp).
+__device__ __forceinline__ double ratio(double a, double b) { return a / b; }
+__device__ __forceinline__ float ratio(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
 // LDS values needed by an output tile tx * ty of nz planes.  h: stencil halo (R
 // for the predictor kinds, K for the re-initialization kinds), h2: R for the
 // fused z kind.  The re-initialization sweeps whole box lines, so its tiles need
@@ -334,7 +347,7 @@ __device__ __forceinline__ void minplus_run(const T *src, int stride, int K, T b
 // Spreading along one line of `len` values (stride `stride`): the distance
 // grows by one per voxel, forward then backward.  A ring (a line over a whole
 // periodic axis) is swept twice around in each direction, starting at index 0.
-// Same order of operations as the definition: w = previous + 1; keep w if w < v.
+// Same order of operations as the definition: w = previous + 1; keep the smaller of w and v.
 template <typename T> __device__ __forceinline__ void sweep_line(T *p, int stride, int len, bool ring) {
     if (len <= 1) return;
     T cur = p[0];
@@ -342,13 +355,13 @@ template <typename T> __device__ __forceinline__ void sweep_line(T *p, int strid
 #pragma unroll 4
         for (int i = 1; i < len; ++i) {
             const T v = p[i * stride], w = cur + T(1);
-            cur = w < v ? w : v;
+            cur = vmin(w, v);
             p[i * stride] = cur;
         }
 #pragma unroll 4
         for (int i = len - 2; i >= 0; --i) {
             const T v = p[i * stride], w = cur + T(1);
-            cur = w < v ? w : v;
+            cur = vmin(w, v);
             p[i * stride] = cur;
         }
         return;
@@ -357,7 +370,7 @@ template <typename T> __device__ __forceinline__ void sweep_line(T *p, int strid
     for (int t = 1; t < 2 * len; ++t) {
         i = i + 1 == len ? 0 : i + 1;
         const T v = p[i * stride], w = cur + T(1);
-        cur = w < v ? w : v;
+        cur = vmin(w, v);
         p[i * stride] = cur;
     }
     i = len - 1;
@@ -365,7 +378,7 @@ template <typename T> __device__ __forceinline__ void sweep_line(T *p, int strid
     for (int t = 1; t < 2 * len; ++t) {
         i = i == 0 ? len - 1 : i - 1;
         const T v = p[i * stride], w = cur + T(1);
-        cur = w < v ? w : v;
+        cur = vmin(w, v);
         p[i * stride] = cur;
     }
 }
@@ -379,13 +392,13 @@ template <typename T> __device__ __forceinline__ void sweep_line_signed(T *p, in
 #pragma unroll 4
         for (int i = 1; i < len; ++i) {
             const T v = p[i * stride], w = cur + T(1), a = fabs(v);
-            cur = w < a ? w : a;
+            cur = vmin(w, a);
             p[i * stride] = copysign(cur, v);
         }
 #pragma unroll 4
         for (int i = len - 2; i >= 0; --i) {
             const T v = p[i * stride], w = cur + T(1), a = fabs(v);
-            cur = w < a ? w : a;
+            cur = vmin(w, a);
             p[i * stride] = copysign(cur, v);
         }
         return;
@@ -394,7 +407,7 @@ template <typename T> __device__ __forceinline__ void sweep_line_signed(T *p, in
     for (int t = 1; t < 2 * len; ++t) {
         i = i + 1 == len ? 0 : i + 1;
         const T v = p[i * stride], w = cur + T(1), a = fabs(v);
-        cur = w < a ? w : a;
+        cur = vmin(w, a);
         p[i * stride] = copysign(cur, v);
     }
     i = len - 1;
@@ -402,7 +415,7 @@ template <typename T> __device__ __forceinline__ void sweep_line_signed(T *p, in
     for (int t = 1; t < 2 * len; ++t) {
         i = i == 0 ? len - 1 : i - 1;
         const T v = p[i * stride], w = cur + T(1), a = fabs(v);
-        cur = w < a ? w : a;
+        cur = vmin(w, a);
         p[i * stride] = copysign(cur, v);
     }
 }
@@ -955,14 +968,6 @@ template <typename T> struct Carry {
     }
 };
 
-template <typename T> __device__ __forceinline__ T min3v(T a, T b, T c) {
-    const T m = a < b ? a : b;
-    return m < c ? m : c;
-}
-template <typename T> __device__ __forceinline__ T max3v(T a, T b, T c) {
-    const T m = a > b ? a : b;
-    return m > c ? m : c;
-}
 
 // Reference values next to the sign change, then the x and y spreading sweeps,
 // on one tile of nz consecutive z planes of the new box.  3D: writes the partial
@@ -1076,23 +1081,14 @@ __global__ void __launch_bounds__(kBlock)
                 T rv = inf;
                 if (colin && rtab[p * FH + r] != -2) {
                     const T n0 = f[a - 1], n1 = f[a + 1], n2 = f[a - FP], n3 = f[a + FP];
-                    T lo, hi;
+                    T lo = vmin(vmin(n0, n1), vmin(n2, n3)), hi = vmax(vmax(n0, n1), vmax(n2, n3));
                     if (d3) {
-                        lo = min3v(n0, n1, n2);
-                        lo = min3v(lo, n3, zm);
-                        lo = lo < nxt ? lo : nxt;
-                        hi = max3v(n0, n1, n2);
-                        hi = max3v(hi, n3, zm);
-                        hi = hi > nxt ? hi : nxt;
-                    } else {
-                        lo = min3v(n0, n1, n2);
-                        lo = lo < n3 ? lo : n3;
-                        hi = max3v(n0, n1, n2);
-                        hi = hi > n3 ? hi : n3;
+                        lo = vmin(lo, vmin(zm, nxt));
+                        hi = vmax(hi, vmax(zm, nxt));
                     }
                     const bool in = cur > T(0);
                     const T ext = in ? lo : hi;
-                    if ((ext > T(0)) != in) rv = cur / (cur - ext);
+                    if ((ext > T(0)) != in) rv = ratio(cur, cur - ext);
                 }
                 ref[a] = rv;
                 zm = cur;
