@@ -276,14 +276,12 @@ __device__ inline double block_sum(double v, double *scratch) {
     return s;  // valid in thread 0
 }
 
-__device__ inline int wave_min(int v) {
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ inline int wave_max(int v) {
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
+// Wave-wide min / max (device library reductions over the active lanes, by
+// lane permutations within rows and across them); the result is uniform.
+extern "C" __device__ int __ockl_wfred_min_i32(int);
+extern "C" __device__ int __ockl_wfred_max_i32(int);
+__device__ __forceinline__ int wave_min(int v) { return __ockl_wfred_min_i32(v); }
+__device__ __forceinline__ int wave_max(int v) { return __ockl_wfred_max_i32(v); }
 
 // 1D Gaussian pass over KB consecutive outputs: acc[q] = sum_t g_t v[q + t],
 // summed in increasing t from 0.  Static radius: register window; RS == 0:
