@@ -28,6 +28,11 @@
 namespace gg {
 
 constexpr int kBlock = 256;       // threads per work group of the stencil/tile kernels
+constexpr int kWaves = kBlock / 64;
+// Predictor xy tiles: values per lane of one plane's tile held in registers.
+constexpr int kPF = 16;
+// Predictor xy work items: planes per item (pipelined through one LDS tile).
+constexpr int kCxyPlanes = 4;
 constexpr int kLdsBytes = 32768;  // dynamic LDS budget per work group
 constexpr int kKB = 4;            // outputs per thread along a stencil axis
 constexpr int kMaxRadius = 24;    // largest Gaussian radius R
@@ -115,8 +120,11 @@ __device__ __forceinline__ float ratio(float a, float b) { return a * __builtin_
 // reference tile of (ty + 2hy + 2) rows of pitch (tx + 2hx + 2) | 1; both
 // kinds add int offset tables (counted as one value each).
 __host__ __device__ inline long long lds_need(int kind, int tx, int ty, int h, int h2, bool sx, bool sy, int nz = 1) {
-    if (kind == KIND_CXY)
-        return (long long)((tx + 2 * h) | 1) * (ty + 2 * h) + kKB + (long long)tx * (ty + 2 * h + kKB);
+    if (kind == KIND_CXY) {  // one plane's raw tile and x-pass tile, row table; the raw tile
+                             // has at most 64 columns and kWaves * kPF rows (kPF values per lane)
+        if (tx + 2 * h > 64 || ty + 2 * h > kWaves * kPF) return 1LL << 40;
+        return (long long)((tx + 2 * h) | 1) * (ty + 2 * h) + kKB + (long long)tx * (ty + 2 * h + kKB) + ty + 2 * h;
+    }
     if (kind == KIND_RXY) {
         const int hx = sx ? h : 0, hy = sy ? h : 0;
         const long long FW = tx + 2 * hx + 2, FH = ty + 2 * hy + 2;
@@ -145,6 +153,7 @@ __host__ __device__ inline Tiling choose_tiling(int kind, int ex, int ey, int pl
     for (int nxs = (ex + 127) / 128; nxs <= ex; ++nxs) {
         const int tx = (ex + nxs - 1) / nxs;
         const bool sx = nxs > 1;
+        if (kind == KIND_CXY && tx + 2 * h > 64) continue;
         if (lds_need(kind, tx, ey, h, h2, sx, false) <= budget) {
             t.nxs = nxs;
             t.nys = 1;
@@ -152,16 +161,22 @@ __host__ __device__ inline Tiling choose_tiling(int kind, int ex, int ey, int pl
             t.ty = ey;
             break;
         }
-        const int b = (int)lds_need(kind, tx, 0, h, h2, sx, true);  // the need is affine in ty
-        const int a = (int)lds_need(kind, tx, 1, h, h2, sx, true) - b;
+        const long long b = lds_need(kind, tx, 0, h, h2, sx, true);  // the need is affine in ty
+        const long long a = lds_need(kind, tx, 1, h, h2, sx, true) - b;
         if (budget - b < a) continue;
-        const int tymax = (budget - b) / a;
+        int tymax = (int)((budget - b) / a);
+        if (kind == KIND_CXY) tymax = tymax < kWaves * kPF - 2 * h ? tymax : kWaves * kPF - 2 * h;
+        if (tymax < 1) continue;
         const int nys = (ey + tymax - 1) / tymax;
         t.nxs = nxs;
         t.nys = nys;
         t.tx = tx;
         t.ty = (ey + nys - 1) / nys;
         break;
+    }
+    if (kind == KIND_CXY && t.nxs > 0 && planes > 1) {
+        const int chunks = (planes + kCxyPlanes - 1) / kCxyPlanes;
+        t.nb = (planes + chunks - 1) / chunks;
     }
     if ((kind == KIND_RXY || kind == KIND_ZF) && t.nxs > 0 && planes > 1) {
         const bool sx = t.nxs > 1, sy = t.nys > 1;
@@ -247,7 +262,7 @@ __device__ __forceinline__ ItemTile decode_item(long long item, int kind, const 
     const int per = tl.nxs * tl.nys;
     const int chunk = sub / per;
     const int rem = sub - chunk * per;
-    if (kind == KIND_RXY || kind == KIND_ZF) {
+    if (kind == KIND_RXY || kind == KIND_ZF || kind == KIND_CXY) {
         const int nb = tilings[2 * it.k + 1].x;
         it.plane = chunk * nb;
         it.np = min(nb, kind_planes(kind, e) - it.plane);
@@ -425,7 +440,6 @@ template <typename T> __device__ __forceinline__ void sweep_line_signed(T *p, in
 // before it stores any of them, so that enough bytes are in flight to cover
 // HBM latency.
 constexpr int kLoadBatch = 8;
-constexpr int kWaves = kBlock / 64;
 
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
@@ -574,8 +588,12 @@ struct GridArgs {
     int dim;
 };
 
-// x and y passes of the Gaussian on one tile of one z plane, then the optional
-// correction epilogue; the output is the predicted function psi.
+// x and y passes of the Gaussian on one tile of nz consecutive z planes of a
+// box, then the optional correction epilogue; the output is the predicted
+// function psi.  The planes go through one LDS tile in turn.  Waves own tile
+// rows and lanes own columns; while a plane is convolved, its successor's tile
+// is already on its way into registers (kPF values per lane), so the loads'
+// latency overlaps the arithmetic.
 template <typename T, int RS, bool PH>
 __global__ void __launch_bounds__(kBlock)
     k_conv_xy(Boxes L, ItemRefs ir, const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ taps,
@@ -586,55 +604,83 @@ __global__ void __launch_bounds__(kBlock)
     const long long item = xcd_item(ir.n);
     if (item >= ir.n) return;
     const ItemTile it = decode_item(item, KIND_CXY, L, ir);
-    const int k = it.k, z = it.plane, x0 = it.x0, y0 = it.y0, wx = it.wx, wy = it.wy;
+    const int k = it.k, z0 = it.plane, nz = it.np, x0 = it.x0, y0 = it.y0, wx = it.wx, wy = it.wy;
     const int ex = L.ext[3 * k], ey = L.ext[3 * k + 1];
-    const int RW = wx + 2 * R, RP = RW | 1, RH = wy + 2 * R;
-    const long long base = L.off[k] + (long long)z * ex * ey;
+    const int RW = wx + 2 * R, RP = RW | 1, RH = wy + 2 * R;  // RW <= 64, RH <= kWaves * kPF
+    const int plane = ex * ey;
     T *raw = sm, *xp = sm + RH * RP + kKB;
+    int *rowo = reinterpret_cast<int *>(xp + wx * (RH + kKB));  // y offset in the plane, -1 outside the box
+    const long long base0 = L.off[k] + (long long)z0 * plane;
     T tp[RS > 0 ? 2 * RS + 1 : 1];
     if constexpr (RS > 0) {
 #pragma unroll
         for (int t = 0; t <= 2 * RS; ++t) tp[t] = taps[t];
     }
-    stage_rows<T>(
-        raw, RP, RW, RH, in,
-        [&](int rr) -> long long {
-            const int yy = axis_map(y0 - R + rr, ey, g.n[1]);
-            return yy >= 0 ? base + (long long)yy * ex : -1;
-        },
-        [&](int cc) { return axis_map(x0 - R + cc, ex, g.n[0]); }, -W);
-    __syncthreads();
-    const int ngx = (wx + kKB - 1) / kKB;
-    // x pass: consecutive lanes take consecutive rows (odd pitch: no bank conflicts)
-    for (Walk2 w(threadIdx.x, RH); w.r < ngx; w.step()) {
-        const int rr = w.c, c0 = w.r * kKB;
-        T acc[kKB];
-        if (axis_map(y0 - R + rr, ey, g.n[1]) < 0) {
-#pragma unroll
-            for (int q = 0; q < kKB; ++q) acc[q] = -W;  // rows outside the box read the fill value
-        } else {
-            gauss_run<T, RS>(raw + rr * RP + c0, 1, tp, taps, R, acc);
-        }
-#pragma unroll
-        for (int q = 0; q < kKB; ++q)
-            if (c0 + q < wx) xp[rr * wx + c0 + q] = acc[q];
+    for (int i = threadIdx.x; i < RH; i += kBlock) {
+        const int yy = axis_map(y0 - R + i, ey, g.n[1]);
+        rowo[i] = yy >= 0 ? yy * ex : -1;
     }
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    const int xx = lane < RW ? axis_map(x0 - R + lane, ex, g.n[0]) : -1;
     __syncthreads();
-    const int ngy = (wy + kKB - 1) / kKB;
-    PairCache<T> pc;
-    T *outp = out + base;
-    for (Walk2 w(threadIdx.x, wx); w.r < ngy; w.step()) {
-        const int c = w.c, r0 = w.r * kKB;
-        T acc[kKB];
-        gauss_run<T, RS>(xp + r0 * wx + c, wx, tp, taps, R, acc);
-        int idx = (y0 + r0) * ex + x0 + c;  // within the plane
+    // this lane's tile values of one plane: rows wave + kWaves * j, column lane
+    T v[kPF];
+    auto fetch = [&](const T *src) {
 #pragma unroll
-        for (int q = 0; q < kKB; ++q, idx += ex) {
-            if (r0 + q >= wy) break;
-            T v = acc[q];
-            if constexpr (PH) v = correct_prediction<T>(ph, k, base + idx, v, W, pc);
-            outp[idx] = v;
+        for (int j = 0; j < kPF; ++j) {
+            const int rr = wave + kWaves * j;
+            const int ro = rr < RH ? rowo[rr] : -1;
+            v[j] = (ro >= 0 && xx >= 0) ? src[ro + xx] : -W;
         }
+    };
+    fetch(in + base0);
+    const int ngx = (wx + kKB - 1) / kKB, ngy = (wy + kKB - 1) / kKB;
+    PairCache<T> pc;
+    for (int p = 0; p < nz; ++p) {
+        // the previous plane's x pass is done (barrier below): its tile is free
+        if (lane < RW) {
+#pragma unroll
+            for (int j = 0; j < kPF; ++j) {
+                const int rr = wave + kWaves * j;
+                if (rr < RH) raw[rr * RP + lane] = v[j];
+            }
+        }
+        __syncthreads();
+        const long long base = base0 + (long long)p * plane;
+        if (p + 1 < nz) fetch(in + base + plane);
+        // x pass: consecutive lanes take consecutive rows (odd pitch: no bank conflicts)
+        for (Walk2 w(threadIdx.x, RH); w.r < ngx; w.step()) {
+            const int rr = w.c, c0 = w.r * kKB;
+            T acc[kKB];
+            if (rowo[rr] < 0) {
+#pragma unroll
+                for (int q = 0; q < kKB; ++q) acc[q] = -W;  // rows outside the box read the fill value
+            } else {
+                gauss_run<T, RS>(raw + rr * RP + c0, 1, tp, taps, R, acc);
+            }
+#pragma unroll
+            for (int q = 0; q < kKB; ++q)
+                if (c0 + q < wx) xp[rr * wx + c0 + q] = acc[q];
+        }
+        __syncthreads();
+        T *outp = out + base;
+        for (Walk2 w(threadIdx.x, wx); w.r < ngy; w.step()) {
+            const int c = w.c, r0 = w.r * kKB;
+            T acc[kKB];
+            gauss_run<T, RS>(xp + r0 * wx + c, wx, tp, taps, R, acc);
+            int idx = (y0 + r0) * ex + x0 + c;  // within the plane
+#pragma unroll
+            for (int q = 0; q < kKB; ++q, idx += ex) {
+                if (r0 + q >= wy) break;
+                T val = acc[q];
+                if constexpr (PH) val = correct_prediction<T>(ph, k, base + idx, val, W, pc);
+                outp[idx] = val;
+            }
+        }
+        // the next plane's tile store (top of the loop) follows this plane's
+        // y pass only through the barrier after its x pass: xp and raw are
+        // disjoint, so the y pass may still read xp meanwhile; the next x pass
+        // writes xp only after the next barrier
     }
 }
 
