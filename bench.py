@@ -20,6 +20,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+SOURCES = [os.path.join(ROOT, "paper_1701_06658_amd", "csrc", f) for f in ("gg_kernels.hpp", "gg_lib.hip")]
+PROFILES = os.path.join(ROOT, "profiles")
 
 # Algorithmic bytes per grain voxel of one launch, by kernel class, in units of
 # the stored value size s (plus fixed extra bytes): every stencil kernel reads
@@ -40,7 +42,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_gpu(cfg, precision, steps, warmup):
+def run_gpu(cfg, precision, steps, warmup, copy_probe=False):
     import paper_1701_06658_amd as gg
     phys = {}
     if cfg.get("physics") == "anisotropic":
@@ -70,20 +72,47 @@ def run_gpu(cfg, precision, steps, warmup):
                superposition=st["superposition"], kernels=kt, physics=bool(phys))
     log(f"[bench] {precision}: {steps} steps in {dt:.3f} s, {out['value']:.3e} gv/s, "
         f"alive {st['alive']}")
+    if copy_probe:
+        # one state download after the timed steps: k_convert reads every stored
+        # value once (4 or 8 B) and writes it as a double; its byte counters
+        # calibrate the profiler
+        _, v = sim.values()
+        s = 4 if precision == "fp32" else 8
+        out["copy_probe"] = dict(kernel="k_convert", values=int(v.size), read_bytes=int(v.size) * s,
+                                 write_bytes=int(v.size) * 8)
     sim.close()
     return out
 
 
-def copy_probe(cfg, precision):
-    """One state download: k_convert reads every stored value once (4 or 8 B) and
-    writes it as a double; its byte counters calibrate the profiler."""
-    import paper_1701_06658_amd as gg
-    sim = gg.Simulation(cfg["labels"], cfg["W"], G=cfg["G"], precision=precision)
-    b, v = sim.values()
-    sim.close()
-    s = 4 if precision == "fp32" else 8
-    return dict(kernel="k_convert", values=int(v.size), read_bytes=int(v.size) * s,
-                write_bytes=int(v.size) * 8)
+def source_digest():
+    """SHA-256 of the kernel sources: a recorded counter figure applies only to them."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel, precision, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/traffic_<kernel>_<workload>_<precision>.md), or None when the
+    summary is missing or was taken from other kernel sources."""
+    path = os.path.join(PROFILES, f"traffic_{kernel}_{workload}_{precision}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("source_sha256") != source_digest():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def roofline(res, s_bytes):
@@ -97,13 +126,13 @@ def roofline(res, s_bytes):
         bytes_alg = (mult * s_bytes + extra) * k["voxels"]
         avg_ms = k["ms"] / k["launches"]
         gbs = bytes_alg / (k["ms"] * 1e-3) / 1e9
-        per[name] = dict(avg_ms=avg_ms, gbs=gbs, bytes_per_launch=bytes_alg / k["launches"])
+        per[name] = dict(avg_ms=avg_ms, gbs=gbs, bytes_per_launch=bytes_alg / k["launches"], launches=k["launches"])
         if best is None or k["ms"] > res["kernels"][best]["ms"]:
             best = name
     r = per[best]
     return dict(bound="hbm", kernel=best, achieved=r["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=r["gbs"] / HBM_PEAK_GBS, traffic=None,
-                avg_launch_ms=r["avg_ms"], alg_bytes_per_launch=r["bytes_per_launch"],
+                avg_launch_ms=r["avg_ms"], alg_bytes_per_launch=r["bytes_per_launch"], launches=r["launches"],
                 per_kernel={k: round(v["gbs"], 1) for k, v in per.items()})
 
 
@@ -139,8 +168,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="also run the library's state download once: a plain streaming kernel "
-                         "of known size (reference for profiler byte counters)")
+                    help="after the timed steps, run the library's state download once: a plain "
+                         "streaming kernel of known size (reference for profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -151,7 +180,7 @@ def main():
     cfg = make_config(args.config)
     log(f"[bench] inputs {cfg['name']}: {cfg['G']} grains in {time.perf_counter() - t0:.1f} s")
     precision = args.precision or cfg["precision"]
-    main_res = run_gpu(cfg, precision, args.steps, args.warmup)
+    main_res = run_gpu(cfg, precision, args.steps, args.warmup, copy_probe=args.copy_probe)
     s_bytes = 4 if precision == "fp32" else 8
     line = {
         "metric": "grain-voxel updates/s per step (mixed batched vs FP64 plain) + %HBM roofline",
@@ -172,12 +201,14 @@ def main():
                    "superposition": round(main_res["superposition"], 3)},
         "roofline": roofline(main_res, s_bytes),
     }
+    rl = line["roofline"]
+    rl["traffic"] = recorded_traffic(rl["kernel"], precision, "3d256_8000g" if args.config == 3 else f"config{args.config}")
     if not args.no_plain and precision != "fp64":
         plain = run_gpu(cfg, "fp64", args.steps, args.warmup)
         line["plain_fp64"] = dict(value=plain["value"], ms_per_step=plain["ms_per_step"],
                                   roofline=roofline(plain, 8), mixed_speedup=main_res["value"] / plain["value"])
     if args.copy_probe:
-        line["copy_probe"] = copy_probe(cfg, precision)
+        line["copy_probe"] = main_res["copy_probe"]
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.config)
     print(json.dumps(line), flush=True)
