@@ -1260,7 +1260,10 @@ __global__ void __launch_bounds__(kBlock)
                 dc[(R + ez + j) * QW + q] = dc[(R + j) * QW + q];
             }
         } else {
-            sweep_line_signed<T>(dc + q, QW, DH, false);
+            // rows outside the box hold the fill value and cannot lower a
+            // distance inside it: the box's rows are swept only
+            const int r_lo = max(0, R + hz - z0), r_hi = min(DH, ez - z0 + R + hz);
+            sweep_line_signed<T>(dc + r_lo * QW + q, QW, r_hi - r_lo, false);
         }
     }
     __syncthreads();
