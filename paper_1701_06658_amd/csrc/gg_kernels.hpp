@@ -33,7 +33,10 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kPF = 16;
 // Predictor xy work items: planes per item (pipelined through one LDS tile).
 constexpr int kCxyPlanes = 4;
-constexpr int kLdsBytes = 32768;  // dynamic LDS budget per work group
+#ifndef GG_LDS_BYTES
+#define GG_LDS_BYTES 32768
+#endif
+constexpr int kLdsBytes = GG_LDS_BYTES;  // dynamic LDS budget per work group (FP32)
 constexpr int kKB = 4;            // outputs per thread along a stencil axis
 constexpr int kMaxRadius = 24;    // largest Gaussian radius R
 constexpr int kMaxBand = 16;      // largest band half width W
@@ -84,7 +87,14 @@ __device__ __forceinline__ int wrap_diff(int a, int b, int N) {
     return d < 0 ? d + N : d;
 }
 
-template <typename T> constexpr int lds_budget() { return kLdsBytes / (int)sizeof(T); }
+// LDS budgets in values: the FP64 path gets twice the bytes (the same number of
+// values per tile as FP32), so that its boxes split no more often.
+#ifndef GG_F64_LDS_SCALE
+#define GG_F64_LDS_SCALE 2
+#endif
+template <typename T> constexpr int lds_scale() { return sizeof(T) == 8 ? GG_F64_LDS_SCALE : 1; }
+template <typename T> constexpr int lds_budget() { return kLdsBytes * lds_scale<T>() / (int)sizeof(T); }
+template <typename T> constexpr int small_budget() { return kSmallLdsBytes * lds_scale<T>() / (int)sizeof(T); }
 
 template <typename T> __device__ __forceinline__ T mac(T acc, T a, T b);
 template <> __device__ __forceinline__ double mac<double>(double acc, double a, double b) {

@@ -17,6 +17,13 @@
 #include "../../include/gg.h"
 #include "gg_kernels.hpp"
 
+// Corrector tile of the 3D grid (powers of two, 512 voxels).
+#ifndef GG_CMP_TILE_X
+#define GG_CMP_TILE_X 16
+#define GG_CMP_TILE_Y 8
+#define GG_CMP_TILE_Z 4
+#endif
+
 namespace {
 
 using gg::Boxes;
@@ -225,9 +232,9 @@ template <typename T> struct Sim final : SimBase {
         gamma_max = c.gamma_max;
         headroom = c.capacity_headroom > 1.0 ? c.capacity_headroom : 1.25;
         if (dim == 3) {
-            tdim[0] = pow2_divisor(n[0], 16);
-            tdim[1] = pow2_divisor(n[1], 8);
-            tdim[2] = pow2_divisor(n[2], 4);
+            tdim[0] = pow2_divisor(n[0], GG_CMP_TILE_X);
+            tdim[1] = pow2_divisor(n[1], GG_CMP_TILE_Y);
+            tdim[2] = pow2_divisor(n[2], GG_CMP_TILE_Z);
         } else {
             tdim[0] = pow2_divisor(n[0], 32);
             tdim[1] = pow2_divisor(n[1], 16);
@@ -334,7 +341,7 @@ template <typename T> struct Sim final : SimBase {
         const int tb = 256, gb = (G + tb - 1) / tb;
         hipLaunchKernelGGL(gg::k_item_counts, dim3(gb, gg::kKinds), dim3(tb), 0, stream, L, cnt.as<long long>(), itile[l].as<int4>(),
                            ldsmax.as<unsigned long long>(), R, K, G, gg::lds_budget<T>(),
-                           gg::kSmallLdsBytes / (int)sizeof(T));
+                           gg::small_budget<T>());
         hipLaunchKernelGGL(gg::k_scan_multi, dim3(3 * gg::kKinds), dim3(1024), 0, stream, cnt.as<long long>(),
                            ipref[l].as<long long>(), G);
         if (coverage) {
