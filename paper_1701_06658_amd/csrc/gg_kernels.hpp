@@ -34,7 +34,7 @@ constexpr int kPF = 16;
 // Predictor xy work items: planes per item (pipelined through one LDS tile).
 constexpr int kCxyPlanes = 4;
 #ifndef GG_LDS_BYTES
-#define GG_LDS_BYTES 32768
+#define GG_LDS_BYTES 40960
 #endif
 constexpr int kLdsBytes = GG_LDS_BYTES;  // dynamic LDS budget per work group (FP32)
 constexpr int kKB = 4;            // outputs per thread along a stencil axis
@@ -54,9 +54,13 @@ struct Boxes {
 // Work items of every kind come in two launch classes by their LDS need, so
 // that the many small boxes are not launched with the LDS of the largest one.
 #ifndef GG_SMALL_LDS_BYTES
-#define GG_SMALL_LDS_BYTES 20480
+#define GG_SMALL_LDS_BYTES 26624
 #endif
 constexpr int kSmallLdsBytes = GG_SMALL_LDS_BYTES;
+// LDS target of a fused z work item's row group, in percent of the small class.
+#ifndef GG_ZF_TARGET_PCT
+#define GG_ZF_TARGET_PCT 100
+#endif
 constexpr int kClasses = 2;
 
 struct Totals {
@@ -1448,7 +1452,7 @@ __global__ void k_item_counts(Boxes L, long long *cnt, int4 *tilings, unsigned l
         rec[0] = rec[1] = make_int4(0, 0, 0, 0);
         if (L.alive[k]) {
             const int *e = L.ext + 3 * k;
-            const Tiling t = kind_tiling(q, e, R, K, budget, small);
+            const Tiling t = kind_tiling(q, e, R, K, budget, q == KIND_ZF ? small / 100 * GG_ZF_TARGET_PCT : small);
             rec[0] = make_int4(t.nxs, t.nys, t.tx, t.ty);
             rec[1] = make_int4(t.nb, 0, 0, 0);
             if (t.nxs == 0) {
