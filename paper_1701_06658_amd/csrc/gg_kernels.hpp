@@ -57,9 +57,13 @@ struct Boxes {
 #define GG_SMALL_LDS_BYTES 26624
 #endif
 constexpr int kSmallLdsBytes = GG_SMALL_LDS_BYTES;
-// LDS target of a fused z work item's row group, in percent of the small class.
+// Small-class limit (and plane-group LDS target) of the re-initialization
+// kinds, in percent of the small class.
 #ifndef GG_ZF_TARGET_PCT
 #define GG_ZF_TARGET_PCT 100
+#endif
+#ifndef GG_RXY_SMALL_PCT
+#define GG_RXY_SMALL_PCT 100
 #endif
 constexpr int kClasses = 2;
 
@@ -196,7 +200,8 @@ __host__ __device__ inline Tiling choose_tiling(int kind, int ex, int ey, int pl
         const bool sx = t.nxs > 1, sy = t.nys > 1;
         const long long one = lds_need(kind, t.tx, t.ty, h, h2, sx, sy, 1);
         const long long per = lds_need(kind, t.tx, t.ty, h, h2, sx, sy, 2) - one;
-        long long nb = (target - (one - per)) / per;
+        const long long tg = target < budget ? target : budget;
+        long long nb = (tg - (one - per)) / per;
         nb = nb < 1 ? 1 : (nb > planes ? planes : nb);
         const int chunks = (int)((planes + nb - 1) / nb);
         t.nb = (planes + chunks - 1) / chunks;
@@ -1452,7 +1457,8 @@ __global__ void k_item_counts(Boxes L, long long *cnt, int4 *tilings, unsigned l
         rec[0] = rec[1] = make_int4(0, 0, 0, 0);
         if (L.alive[k]) {
             const int *e = L.ext + 3 * k;
-            const Tiling t = kind_tiling(q, e, R, K, budget, q == KIND_ZF ? small / 100 * GG_ZF_TARGET_PCT : small);
+            const int sq = q == KIND_ZF ? small / 100 * GG_ZF_TARGET_PCT : (q == KIND_RXY ? small / 100 * GG_RXY_SMALL_PCT : small);
+            const Tiling t = kind_tiling(q, e, R, K, budget, sq);
             rec[0] = make_int4(t.nxs, t.nys, t.tx, t.ty);
             rec[1] = make_int4(t.nb, 0, 0, 0);
             if (t.nxs == 0) {
@@ -1460,7 +1466,7 @@ __global__ void k_item_counts(Boxes L, long long *cnt, int4 *tilings, unsigned l
             } else {
                 const long long n = tiling_items(q, e, t);
                 const long long need = tiling_need(q, t, R, K);
-                const int cls = need <= small ? 0 : 1;
+                const int cls = need <= sq ? 0 : 1;
                 c[k] = n;
                 c[(1LL + cls) * G + k] = n;
                 need_c[cls] = (unsigned long long)need;
