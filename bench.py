@@ -30,10 +30,11 @@ ALG_BYTES = {
     "conv_xy": (2, 0), "conv_z": (2, 0), "compare": (2, 0),
     "reinit_xy": (2, 0), "reinit_z": (2, 0),
 }
-# with the predictor correction the z pass also reads phi and the ID-field, the
-# corrector writes the ID-field and the re-initialization carries it over
+# with the predictor correction the xy pass (its epilogue) also reads phi and the
+# ID-field, the corrector writes the ID-field and the re-initialization carries
+# it over
 ALG_BYTES_PHYS = {
-    "conv_xy": (2, 0), "conv_z": (3, 4), "compare": (2, 4),
+    "conv_xy": (3, 4), "conv_z": (2, 0), "compare": (2, 4),
     "reinit_xy": (2, 8), "reinit_z": (2, 0),
 }
 
