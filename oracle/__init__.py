@@ -4,5 +4,5 @@ Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` use this package.  It never imports the GPU library and the GPU
 library never imports it.
 """
-from .oracle import Oracle, build_oracle, load_library, convolve_box, redistance_box, \
+from .oracle import Oracle, build_oracle, load_library, convolve_box, redistance_box, euclid_sweeps, \
     misorientation_deg, pair_weight, num_threads  # noqa: F401

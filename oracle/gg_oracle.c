@@ -68,6 +68,8 @@ struct orc_sim {
     double *energy;
     double h_phys;
     double gamma_max;
+    /* re-initialization scheme of the steps: 0 taxicab spreading, 1 Euclidean */
+    int redist;
     /* intermediates of the last step */
     int keep;
     int *plo, *pext, *palive;
@@ -218,6 +220,115 @@ static void redistance_box(int dim, const int *n, double W, const int *e, const 
         out[v] = f[v] > 0.0 ? d : -d;
     }
     free(ref);
+}
+
+/* ---- Euclidean variant of the re-initialization (fast sweeping with
+ * Godunov's upwind update, the scheme the paper cites for its redistancing,
+ * taken with Euclidean instead of taxicab distances).
+ * Reference cells: cells with a face neighbour of the opposite sign.  Their
+ * value is |phi| / |grad phi| with the central-difference gradient (exact for
+ * a planar interface whatever the slope of phi), at most the smallest axis
+ * intercept phi / (phi - phi_n) (the taxicab reference value).
+ * Every other cell starts at +inf and takes K Jacobi sweeps of
+ * u <- min(u, g(a_1, .., a_D)), where a_a is the smaller magnitude of its two
+ * neighbours along axis a inside the box and g solves
+ * sum over the a_j below it of (g - a_j)^2 = 1.  A Godunov value exceeds its
+ * smallest neighbour by at least 1/sqrt(D), so a value at most W depends only
+ * on cells within sqrt(D) W steps: K = ceil(sqrt(D) W) + 1 sweeps (rounded up
+ * to an even count) reach the fixed point on the band. */
+static double godunov_update(double a1, double a2, double a3) {
+    double t;
+    if (a2 < a1) { t = a1; a1 = a2; a2 = t; }
+    if (a3 < a2) { t = a2; a2 = a3; a3 = t; }
+    if (a2 < a1) { t = a1; a1 = a2; a2 = t; }
+    double u = a1 + 1.0;
+    if (u > a2) {
+        const double d = a1 - a2;
+        u = (a1 + a2 + sqrt(2.0 - d * d)) * 0.5;
+        if (u > a3) {
+            const double s1 = a1 + a2 + a3, s2 = a1 * a1 + a2 * a2 + a3 * a3;
+            u = (s1 + sqrt(s1 * s1 - 3.0 * (s2 - 1.0))) / 3.0;
+        }
+    }
+    return u;
+}
+
+static int euclid_sweeps(int dim, double W) {
+    int K = (int)ceil(sqrt((double)dim) * W) + 1;
+    return K + (K & 1);
+}
+
+static void redistance_box_euclid(int dim, const int *n, double W, const int *e, const double *f,
+                                  double *out) {
+    long m = nvox(e);
+    double *u = (double *)malloc(sizeof(double) * m);
+    double *v = (double *)malloc(sizeof(double) * m);
+    unsigned char *fixed = (unsigned char *)malloc(m);
+    for (int z = 0; z < e[2]; z++)
+        for (int y = 0; y < e[1]; y++)
+            for (int x = 0; x < e[0]; x++) {
+                const long i = lidx(e, x, y, z);
+                const double fx = f[i];
+                const int in = fx > 0.0;
+                double th = INFINITY, gg = 0.0;
+                for (int a = 0; a < dim; a++) {
+                    long cm[3] = {x, y, z}, cp[3] = {x, y, z};
+                    cm[a] -= 1;
+                    cp[a] += 1;
+                    const double fm = sample(f, e, n, cm[0], cm[1], cm[2], -W);
+                    const double fp = sample(f, e, n, cp[0], cp[1], cp[2], -W);
+                    if ((fm > 0.0) != in) {
+                        const double t = fx / (fx - fm);
+                        if (t < th) th = t;
+                    }
+                    if ((fp > 0.0) != in) {
+                        const double t = fx / (fx - fp);
+                        if (t < th) th = t;
+                    }
+                    const double g = (fp - fm) * 0.5;
+                    gg = gg + g * g;
+                }
+                fixed[i] = th < INFINITY;
+                double r = INFINITY;
+                if (fixed[i]) {
+                    r = gg > 0.0 ? fabs(fx) / sqrt(gg) : INFINITY;
+                    if (th < r) r = th;
+                }
+                u[i] = r;
+            }
+    const int K = euclid_sweeps(dim, W);
+    for (int it = 0; it < K; it++) {
+        for (int z = 0; z < e[2]; z++)
+            for (int y = 0; y < e[1]; y++)
+                for (int x = 0; x < e[0]; x++) {
+                    const long i = lidx(e, x, y, z);
+                    if (fixed[i]) {
+                        v[i] = u[i];
+                        continue;
+                    }
+                    double a[3] = {INFINITY, INFINITY, INFINITY};
+                    for (int ax = 0; ax < dim; ax++) {
+                        long cm[3] = {x, y, z}, cp[3] = {x, y, z};
+                        cm[ax] -= 1;
+                        cp[ax] += 1;
+                        const double um = sample(u, e, n, cm[0], cm[1], cm[2], INFINITY);
+                        const double up = sample(u, e, n, cp[0], cp[1], cp[2], INFINITY);
+                        a[ax] = um < up ? um : up;
+                    }
+                    const double g = godunov_update(a[0], a[1], a[2]);
+                    v[i] = g < u[i] ? g : u[i];
+                }
+        double *t = u;
+        u = v;
+        v = t;
+    }
+    for (long i = 0; i < m; i++) {
+        const double d = fmin(u[i], W);
+        out[i] = f[i] > 0.0 ? d : -d;
+    }
+    free(u);
+    free(v);
+    free(fixed);
 }
 
 static double volume_box(const double *phi, long m) {
@@ -704,7 +815,10 @@ int orc_step(orc_sim *s, double dt) {
         free(s->phi[k]);
         free(s->iota[k]);
         s->phi[k] = (double *)malloc(sizeof(double) * m);
-        redistance_box(dim, n, W, ne, f, s->phi[k]);
+        if (s->redist == 1)
+            redistance_box_euclid(dim, n, W, ne, f, s->phi[k]);
+        else
+            redistance_box(dim, n, W, ne, f, s->phi[k]);
         s->iota[k] = io;
         memcpy(lo, nlo, sizeof(nlo));
         memcpy(e, ne, sizeof(ne));
@@ -854,6 +968,23 @@ int orc_convolve_box(int dim, const int32_t n[3], double band, double sigma,
     free(taps);
     return R;
 }
+
+int orc_set_redistance(orc_sim *s, int mode) {
+    if (!s || mode < 0 || mode > 1) return -1;
+    s->redist = mode;
+    return 0;
+}
+
+int orc_redistance_box_euclid(int dim, const int32_t n[3], double band, const int32_t lo[3],
+                              const int32_t ext[3], const double *f, double *out) {
+    (void)lo;
+    if (!valid_grid(dim, n) || !f || !out) return -1;
+    int e[3] = {ext[0], ext[1], ext[2]}, nn[3] = {n[0], n[1], n[2]};
+    redistance_box_euclid(dim, nn, band, e, f, out);
+    return 0;
+}
+
+int orc_euclid_sweeps(int dim, double band) { return euclid_sweeps(dim, band); }
 
 int orc_redistance_box(int dim, const int32_t n[3], double band,
                        const int32_t lo[3], const int32_t ext[3], const double *f, double *out) {

@@ -33,6 +33,12 @@ void orc_destroy(orc_sim *s);
 int orc_set_physics(orc_sim *s, int mode, const double *quat, double theta_c_deg,
                     const double *energy, double h_phys, double gamma_max);
 
+/* Re-initialization scheme of the following steps (creation always uses the
+ * taxicab one): 0 = the paper's fast scheme (exact reference values spread by
+ * one per voxel: taxicab distances), 1 = Euclidean fast sweeping (Godunov
+ * upwind update in Jacobi form from gradient-normalised reference values). */
+int orc_set_redistance(orc_sim *s, int mode);
+
 /* One timestep of normalised length dt (sigma = sqrt(2 dt) * n[0] voxels). */
 int orc_step(orc_sim *s, double dt);
 /* Keep the predictor output and the corrector output of the last step. */
@@ -61,6 +67,9 @@ int orc_convolve_box(int dim, const int32_t n[3], double band, double sigma,
                      const int32_t lo[3], const int32_t ext[3], const double *f, double *out);
 int orc_redistance_box(int dim, const int32_t n[3], double band,
                        const int32_t lo[3], const int32_t ext[3], const double *f, double *out);
+int orc_redistance_box_euclid(int dim, const int32_t n[3], double band,
+                              const int32_t lo[3], const int32_t ext[3], const double *f, double *out);
+int orc_euclid_sweeps(int dim, double band);   /* Jacobi sweeps of the Euclidean scheme */
 double orc_misorientation_deg(const double qa[4], const double qb[4]);
 double orc_pair_weight(double theta_deg, double theta_c_deg, double *mobility);
 int orc_num_threads(void);

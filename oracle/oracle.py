@@ -57,6 +57,9 @@ def load_library():
     lib.orc_convolve_box.argtypes = [C.c_int, _i32p, C.c_double, C.c_double, _i32p, _i32p,
                                      _f64p, _f64p]
     lib.orc_redistance_box.argtypes = [C.c_int, _i32p, C.c_double, _i32p, _i32p, _f64p, _f64p]
+    lib.orc_redistance_box_euclid.argtypes = [C.c_int, _i32p, C.c_double, _i32p, _i32p, _f64p, _f64p]
+    lib.orc_euclid_sweeps.argtypes = [C.c_int, C.c_double]
+    lib.orc_set_redistance.argtypes = [C.c_void_p, C.c_int]
     lib.orc_misorientation_deg.restype = C.c_double
     lib.orc_misorientation_deg.argtypes = [_f64p, _f64p]
     lib.orc_pair_weight.restype = C.c_double
@@ -115,6 +118,11 @@ class Oracle:
         if rc != 0:
             raise ValueError("oracle rejected the physics inputs")
         self._keep_q, self._keep_e = q, e
+
+    def set_redistance(self, mode):
+        """0: the paper's taxicab spreading; 1: Euclidean fast sweeping (steps after this call)."""
+        if self._lib.orc_set_redistance(self._p, int(mode)) != 0:
+            raise ValueError("unknown re-initialization scheme")
 
     def keep_intermediates(self, on=True):
         self._lib.orc_keep_intermediates(self._p, int(bool(on)))
@@ -216,8 +224,9 @@ def convolve_box(f, band, sigma, n, dim=None):
     return out
 
 
-def redistance_box(f, band, n, dim=None):
-    """Re-initialization of one box field f (shape (ez, ey, ex)) on grid n."""
+def redistance_box(f, band, n, dim=None, euclid=False):
+    """Re-initialization of one box field f (shape (ez, ey, ex)) on grid n
+    (euclid: the Euclidean fast-sweeping scheme instead of the taxicab one)."""
     lib = load_library()
     f = np.ascontiguousarray(f, dtype=np.float64)
     if f.ndim == 2:
@@ -226,8 +235,8 @@ def redistance_box(f, band, n, dim=None):
     dim = dim or (2 if nn[2] == 1 else 3)
     ext = np.array([f.shape[2], f.shape[1], f.shape[0]], np.int32)
     out = np.empty_like(f)
-    if lib.orc_redistance_box(dim, nn, float(band), np.zeros(3, np.int32), ext, f.ravel(),
-                              out.ravel()) != 0:
+    fn = lib.orc_redistance_box_euclid if euclid else lib.orc_redistance_box
+    if fn(dim, nn, float(band), np.zeros(3, np.int32), ext, f.ravel(), out.ravel()) != 0:
         raise ValueError("bad arguments")
     return out
 
@@ -247,3 +256,8 @@ def pair_weight(theta_deg, theta_c_deg=15.0):
 
 def num_threads():
     return load_library().orc_num_threads()
+
+
+def euclid_sweeps(dim, band):
+    """Jacobi sweeps the Euclidean scheme takes (even, >= ceil(sqrt(dim) band) + 1)."""
+    return int(load_library().orc_euclid_sweeps(int(dim), float(band)))
