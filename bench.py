@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -43,7 +44,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_gpu(cfg, precision, steps, warmup, copy_probe=False):
+def euclid_sweeps(dim, W):
+    """Jacobi sweep count of the Euclidean re-initialization variant (the
+    library's rule): ceil(sqrt(dim) W) + 1, rounded up to an even count."""
+    K = int(math.ceil(math.sqrt(dim) * W)) + 1
+    return K + (K & 1)
+
+
+def run_gpu(cfg, precision, steps, warmup, copy_probe=False, redistance="taxicab"):
     import paper_1701_06658_amd as gg
     phys = {}
     if cfg.get("physics") == "anisotropic":
@@ -52,7 +60,7 @@ def run_gpu(cfg, precision, steps, warmup, copy_probe=False):
         phys = dict(physics=gg.PHYS_BULK, energy=cfg["energy"], voxel_m=cfg["h_phys"],
                     gamma_max=cfg["gamma_max"])
     t0 = time.perf_counter()
-    sim = gg.Simulation(cfg["labels"], cfg["W"], G=cfg["G"], precision=precision, **phys)
+    sim = gg.Simulation(cfg["labels"], cfg["W"], G=cfg["G"], precision=precision, redistance=redistance, **phys)
     sim.sync()
     log(f"[bench] {precision}: created in {time.perf_counter() - t0:.2f} s")
     if warmup:
@@ -70,7 +78,8 @@ def run_gpu(cfg, precision, steps, warmup, copy_probe=False):
     sim.profile(False)
     gv = st["total_grain_voxels"] - gv0
     out = dict(value=gv / dt, ms_per_step=1e3 * dt / steps, grain_voxels=gv, alive=st["alive"],
-               superposition=st["superposition"], kernels=kt, physics=bool(phys))
+               superposition=st["superposition"], kernels=kt, physics=bool(phys),
+               sweeps=euclid_sweeps(cfg["dim"], cfg["W"]) if redistance == "euclid" else 0)
     log(f"[bench] {precision}: {steps} steps in {dt:.3f} s, {out['value']:.3e} gv/s, "
         f"alive {st['alive']}")
     if copy_probe:
@@ -117,7 +126,11 @@ def recorded_traffic(kernel, precision, workload):
 
 
 def roofline(res, s_bytes):
-    table = ALG_BYTES_PHYS if res["physics"] else ALG_BYTES
+    table = dict(ALG_BYTES_PHYS if res["physics"] else ALG_BYTES)
+    if res["sweeps"]:
+        # each Jacobi sweep of the Euclidean variant reads and writes every value
+        # once; one timed span holds all sweeps of a step
+        table["reinit_sweep"] = (2 * res["sweeps"], 0)
     best = None
     per = {}
     for name, (mult, extra) in table.items():
@@ -167,6 +180,8 @@ def main():
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--precision", default=None, help="fp32 (mixed) or fp64 (plain)")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--redistance", default="taxicab", choices=["taxicab", "euclid"],
+                    help="re-initialization scheme: the method's taxicab one or the Euclidean variant")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, run the library's state download once: a plain "
@@ -181,7 +196,8 @@ def main():
     cfg = make_config(args.config)
     log(f"[bench] inputs {cfg['name']}: {cfg['G']} grains in {time.perf_counter() - t0:.1f} s")
     precision = args.precision or cfg["precision"]
-    main_res = run_gpu(cfg, precision, args.steps, args.warmup, copy_probe=args.copy_probe)
+    main_res = run_gpu(cfg, precision, args.steps, args.warmup, copy_probe=args.copy_probe,
+                       redistance=args.redistance)
     s_bytes = 4 if precision == "fp32" else 8
     line = {
         "metric": "grain-voxel updates/s per step (mixed batched vs FP64 plain) + %HBM roofline",
@@ -198,14 +214,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["name"], "grid": list(cfg["n"]), "grains": cfg["G"],
                    "sigma_voxels": cfg["sigma"], "band_voxels": cfg["W"],
-                   "precision": precision, "alive_after": main_res["alive"],
+                   "precision": precision, "redistance": args.redistance, "alive_after": main_res["alive"],
                    "superposition": round(main_res["superposition"], 3)},
         "roofline": roofline(main_res, s_bytes),
     }
     rl = line["roofline"]
-    rl["traffic"] = recorded_traffic(rl["kernel"], precision, "3d256_8000g" if args.config == 3 else f"config{args.config}")
+    workload = ("3d256_8000g" if args.config == 3 else f"config{args.config}") + (
+        "_euclid" if args.redistance == "euclid" else "")
+    rl["traffic"] = recorded_traffic(rl["kernel"], precision, workload)
     if not args.no_plain and precision != "fp64":
-        plain = run_gpu(cfg, "fp64", args.steps, args.warmup)
+        plain = run_gpu(cfg, "fp64", args.steps, args.warmup, redistance=args.redistance)
         line["plain_fp64"] = dict(value=plain["value"], ms_per_step=plain["ms_per_step"],
                                   roofline=roofline(plain, 8), mixed_speedup=main_res["value"] / plain["value"])
     if args.copy_probe:

@@ -55,6 +55,21 @@ typedef enum {
     GG_FP32 = 1  /* mixed path: FP32 storage/arithmetic, FP64 volume reductions  */
 } gg_precision;
 
+/* Re-initialization scheme of gg_step (gg_create always uses the taxicab one
+ * for the initial function). */
+typedef enum {
+    GG_REDIST_TAXICAB = 0, /* the method's scheme (sec. 2.1.6): reference values
+                              next to the sign change spread as taxicab
+                              distances, exact min over reference cells        */
+    GG_REDIST_EUCLID = 1   /* variant: Euclidean fast sweeping with Godunov's
+                              upwind update (the redistancing scheme the paper
+                              cites), K = ceil(sqrt(dim) W) + 1 (rounded up to
+                              even) Jacobi sweeps from gradient-normalised
+                              reference values |phi| / |grad phi| (at most the
+                              taxicab reference value) on the cells next to the
+                              sign change; cells outside the box are absent    */
+} gg_redistance;
+
 /* Predictor-correction terms (sec. 2.1.4, Eq. eq:velocorrect). */
 enum {
     GG_PHYS_NONE = 0,
@@ -80,6 +95,7 @@ typedef struct {
     double voxel_m;         /* voxel edge h in metres (GG_PHYS_BULK)                 */
     double gamma_max;       /* maximal boundary energy, J/m^2 (GG_PHYS_BULK)         */
     double capacity_headroom; /* device arena slack factor (0: default 1.25)       */
+    int32_t redistance;     /* gg_redistance: re-initialization scheme of the steps  */
 } gg_config;
 
 typedef struct {
@@ -140,6 +156,7 @@ enum {
     GG_K_REINIT_Z = 4,  /* z sweep, clamp, volume partial sums, next z convolution  */
     GG_K_PLAN = 5,      /* box plan, scans, work items, coverage lists              */
     GG_K_VOLUME = 6,    /* per-grain volume reduction                               */
+    GG_K_REINIT_SWEEP = 7, /* Jacobi sweeps of GG_REDIST_EUCLID (2D: + clamp, volume) */
     GG_K_CLASSES = 8
 };
 typedef struct {

@@ -12,7 +12,9 @@
 //   k_zfused     d              -> t, phi  (z min-plus, band clamp, volume, predictor z pass)
 //   k_conv_xy    t              -> psi     (predictor x and y passes, correction epilogue)
 // The separable Gaussian is applied z, x, y so that its z pass can share the
-// z-line sweep of the re-initialization.
+// z-line sweep of the re-initialization.  The Euclidean re-initialization
+// variant replaces the min-plus sweeps: k_reinit_xy writes the reference
+// values, k_jacobi takes the Godunov sweeps, k_zfused only clamps.
 //
 // Stencil kernels stage one output tile plus its halo in LDS and read every HBM
 // value of their tile once; each thread produces KB consecutive outputs along
@@ -128,6 +130,11 @@ __device__ __forceinline__ double vmax(double a, double b) { return fmax(a, b); 
 // the hardware reciprocal (about 1 ulp).
 __device__ __forceinline__ double ratio(double a, double b) { return a / b; }
 __device__ __forceinline__ float ratio(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
+// a / sqrt(b), b > 0: correctly rounded steps in FP64; in FP32 the product with
+// the hardware reciprocal square root.
+__device__ __forceinline__ double grad_dist(double a, double b) { return a / sqrt(b); }
+__device__ __forceinline__ float grad_dist(float a, float b) { return a * __builtin_amdgcn_rsqf(b); }
 
 // LDS values needed by an output tile tx * ty of nz planes.  h: stencil halo (R
 // for the predictor kinds, K for the re-initialization kinds), h2: R for the
@@ -1046,7 +1053,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_reinit_xy(Boxes Lo, Boxes Ln, ItemRefs ir, const T *__restrict__ phic, T *__restrict__ out,
                 const int *__restrict__ iota_old, int *__restrict__ iota_new, double *__restrict__ vol_part, int K,
-                T W, GridArgs g) {
+                T W, int euclid, GridArgs g) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
     __shared__ double red[kBlock / 64];
@@ -1151,7 +1158,24 @@ __global__ void __launch_bounds__(kBlock)
                     }
                     const bool in = cur > T(0);
                     const T ext = in ? lo : hi;
-                    if ((ext > T(0)) != in) rv = ratio(cur, cur - ext);
+                    if ((ext > T(0)) != in) {
+                        rv = ratio(cur, cur - ext);
+                        if (euclid) {
+                            // |phi| / |grad phi|, central differences summed in
+                            // axis order, capped by the axis intercept above
+                            const T gx = (n1 - n0) * T(0.5), gy = (n3 - n2) * T(0.5);
+                            T gg = gx * gx;
+                            gg = gg + gy * gy;
+                            if (d3) {
+                                const T gz = (nxt - zm) * T(0.5);
+                                gg = gg + gz * gz;
+                            }
+                            if (gg > T(0)) {
+                                const T r = grad_dist(fabs(cur), gg);
+                                rv = rv < r ? rv : r;
+                            }
+                        }
+                    }
                 }
                 ref[a] = rv;
                 zm = cur;
@@ -1160,19 +1184,21 @@ __global__ void __launch_bounds__(kBlock)
         }
     }
     __syncthreads();
-    // spreading: x along rows, then y along columns (one lane per line)
-    const bool ringx = it.nxs == 1 && ex == g.n[0];
-    for (int l = threadIdx.x; l < nz * RH; l += kBlock) {
-        const int p = l / RH;
-        sweep_line<T>(ref + p * PS + (l - p * RH + 1) * FP + 1, 1, RW, ringx);
+    if (!euclid) {
+        // spreading: x along rows, then y along columns (one lane per line)
+        const bool ringx = it.nxs == 1 && ex == g.n[0];
+        for (int l = threadIdx.x; l < nz * RH; l += kBlock) {
+            const int p = l / RH;
+            sweep_line<T>(ref + p * PS + (l - p * RH + 1) * FP + 1, 1, RW, ringx);
+        }
+        __syncthreads();
+        const bool ringy = it.nys == 1 && ey == g.n[1];
+        for (int l = threadIdx.x; l < nz * RW; l += kBlock) {
+            const int p = l / RW;
+            sweep_line<T>(ref + p * PS + FP + l - p * RW + 1, FP, RH, ringy);
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    const bool ringy = it.nys == 1 && ey == g.n[1];
-    for (int l = threadIdx.x; l < nz * RW; l += kBlock) {
-        const int p = l / RW;
-        sweep_line<T>(ref + p * PS + FP + l - p * RW + 1, FP, RH, ringy);
-    }
-    __syncthreads();
     T *outk = out + Ln.off[k];
     int *io_new = iota_new ? iota_new + Ln.off[k] : nullptr;
     const int *io_old = iota_old ? iota_old + cr.ooff : nullptr;
@@ -1185,7 +1211,12 @@ __global__ void __launch_bounds__(kBlock)
         for (int p = 0; p < nz; ++p, a += PS, idx += plane_vals) {
             const T d = ref[a];
             const bool in = f[a] > T(0);
-            if (!d3) {
+            if (euclid) {
+                // reference value (+inf elsewhere) for the Jacobi sweeps, the
+                // inside flag in the sign bit (a zero value keeps it as well)
+                const T m = fabs(d);
+                outk[idx] = in ? m : -m;
+            } else if (!d3) {
                 const T dc = d < W ? d : W;
                 const T pv = in ? dc : -dc;
                 outk[idx] = pv;
@@ -1201,7 +1232,7 @@ __global__ void __launch_bounds__(kBlock)
             }
         }
     }
-    if (!d3) {
+    if (!d3 && !euclid) {
         const double s = block_sum(vsum, red);
         if (threadIdx.x == 0) vol_part[item] = s;
     }
@@ -1218,7 +1249,7 @@ template <typename T, int RS>
 __global__ void __launch_bounds__(kBlock)
     k_zfused(Boxes Ln, ItemRefs ir, const T *__restrict__ d2, T *__restrict__ phi_out,
              T *__restrict__ t_out, double *__restrict__ vol_part, const T *__restrict__ taps, int K, int R_, T W,
-             GridArgs g) {
+             int zsweep, GridArgs g) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
     __shared__ double red[kBlock / 64];
@@ -1271,7 +1302,7 @@ __global__ void __launch_bounds__(kBlock)
     // z spreading, one lane per column; a whole periodic z axis is a ring whose
     // copies in the halo rows are refreshed afterwards
     const bool ring = it.nys == 1 && ez == g.n[2];
-    for (int q = threadIdx.x; q < QW; q += kBlock) {
+    for (int q = threadIdx.x; zsweep && q < QW; q += kBlock) {
         if (ring) {
             sweep_line_signed<T>(dc + R * QW + q, QW, ez, true);
             for (int j = 0; j < R; ++j) {
@@ -1328,6 +1359,106 @@ __global__ void __launch_bounds__(kBlock)
 
 // Initial function before re-initialization: +1/2 on the grain's labelled
 // voxels, -1/2 elsewhere in its box.
+// Godunov's upwind update on a unit grid: the largest root u of
+// sum over the a_i below u of (u - a_i)^2 = 1, for neighbour values a1..a3
+// (+inf: no neighbour along that axis).  The three are sorted first; one
+// neighbour gives a + 1, two the quadratic's root, three the cubic's.
+template <typename T> __device__ __forceinline__ T godunov(T a1, T a2, T a3) {
+    T t;
+    if (a2 < a1) { t = a1; a1 = a2; a2 = t; }
+    if (a3 < a2) { t = a2; a2 = a3; a3 = t; }
+    if (a2 < a1) { t = a1; a1 = a2; a2 = t; }
+    T u = a1 + T(1);
+    if (u > a2) {
+        const T d = a1 - a2;
+        u = (a1 + a2 + sqrt(T(2) - d * d)) * T(0.5);
+        if (u > a3) {
+            const T s1 = a1 + a2 + a3, s2 = a1 * a1 + a2 * a2 + a3 * a3;
+            u = (s1 + sqrt(s1 * s1 - T(3) * (s2 - T(1)))) / T(3);
+        }
+    }
+    return u;
+}
+
+// One Jacobi sweep of the Euclidean re-initialization over a work item (tile of
+// nz planes) of the new box: src -> dst, distances with the inside flag in the
+// sign bit.  A cell with a face neighbour on the other side of the interface (a
+// cell outside the box counts as outside the grain) keeps its reference value;
+// every other cell takes min(u, godunov(a_x, a_y, a_z)), a_i the smaller
+// magnitude of its two neighbours along axis i that lie in the box.  `final2d`
+// (the last sweep in 2D) stores the band-clamped function and the tile's volume
+// instead.  Each lane walks one (x, y) position through the planes, keeping the
+// z neighbours in registers; in-plane neighbours come through the caches.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_jacobi(Boxes Ln, ItemRefs ir, const T *__restrict__ src, T *__restrict__ dst, double *__restrict__ vol_part,
+             T W, int final2d, GridArgs g) {
+    __shared__ double red[kBlock / 64];
+    const long long cls_item = xcd_item(ir.n);
+    if (cls_item >= ir.n) return;
+    const ItemTile it = decode_item(cls_item, KIND_RXY, Ln, ir);
+    const int k = it.k, z0 = it.plane, nz = it.np, x0 = it.x0, y0 = it.y0, wx = it.wx, wy = it.wy;
+    const int ex = Ln.ext[3 * k], ey = Ln.ext[3 * k + 1], ez = Ln.ext[3 * k + 2];
+    const T *u = src + Ln.off[k];
+    T *v = dst + Ln.off[k];
+    const T inf = tinf<T>();
+    const bool d3 = g.dim == 3;
+    const int plane = ex * ey;
+    double vsum = 0.0;
+    // an absent neighbour reads -inf: outside the grain, magnitude +inf
+    auto at = [&](int i) { return i >= 0 ? u[i] : -inf; };
+    for (Walk2 w(threadIdx.x, wx); w.r < wy; w.step()) {
+        const int x = x0 + w.c, y = y0 + w.r;
+        const int xm = axis_map(x - 1, ex, g.n[0]), xp = axis_map(x + 1, ex, g.n[0]);
+        const int ym = axis_map(y - 1, ey, g.n[1]), yp = axis_map(y + 1, ey, g.n[1]);
+        const int ixm = xm < 0 ? -1 : xm - x, ixp = xp < 0 ? -1 : xp - x;
+        const int iym = ym < 0 ? -1 : (ym - y) * ex, iyp = yp < 0 ? -1 : (yp - y) * ex;
+        int c = (z0 * ey + y) * ex + x;
+        T zlo = -inf;
+        if (d3) {
+            const int zz = axis_map(z0 - 1, ez, g.n[2]);
+            zlo = zz >= 0 ? u[(zz * ey + y) * ex + x] : -inf;
+        }
+        T cur = u[c];
+        for (int p = 0; p < nz; ++p, c += plane) {
+            T zhi = -inf;
+            if (d3) {
+                const int zz = axis_map(z0 + p + 1, ez, g.n[2]);
+                zhi = zz >= 0 ? u[(zz * ey + y) * ex + x] : -inf;
+            }
+            const T nxm = at(xm < 0 ? -1 : c + ixm), nxp = at(xp < 0 ? -1 : c + ixp);
+            const T nym = at(ym < 0 ? -1 : c + iym), nyp = at(yp < 0 ? -1 : c + iyp);
+            const bool sc = signbit(cur);
+            bool fixed = signbit(nxm) != sc || signbit(nxp) != sc || signbit(nym) != sc || signbit(nyp) != sc;
+            if (d3) fixed = fixed || signbit(zlo) != sc || signbit(zhi) != sc;
+            const T mc = fabs(cur);
+            T res = mc;
+            if (!fixed) {
+                const T ax = vmin(fabs(nxm), fabs(nxp)), ay = vmin(fabs(nym), fabs(nyp));
+                const T az = d3 ? vmin(fabs(zlo), fabs(zhi)) : inf;
+                const T gv = godunov(ax, ay, az);
+                res = gv < mc ? gv : mc;
+            }
+            if (final2d) {
+                const T dc = res < W ? res : W;
+                const T pv = sc ? -dc : dc;
+                v[c] = pv;
+                double cl = (double)pv + 0.5;
+                cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
+                vsum += cl;
+            } else {
+                v[c] = fixed ? cur : (sc ? -res : res);
+            }
+            zlo = cur;
+            cur = zhi;
+        }
+    }
+    if (final2d) {
+        const double s = block_sum(vsum, red);
+        if (threadIdx.x == 0) vol_part[it.item] = s;
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_init_indicator(Boxes L, const int *__restrict__ labels, T *__restrict__ out,
                                                            GridArgs g) {

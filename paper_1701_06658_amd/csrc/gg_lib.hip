@@ -104,6 +104,7 @@ struct SimBase {
 template <typename T> struct Sim final : SimBase {
     // configuration
     int dim, G, n[3], P, K;
+    int redist, K_euclid;  // re-initialization scheme of the steps; its Jacobi sweep count
     T W;
     int physics;
     double theta_c, voxel_m, gamma_max, headroom;
@@ -226,6 +227,11 @@ template <typename T> struct Sim final : SimBase {
         W = (T)c.band;
         P = (int)std::ceil(c.band);
         K = P;
+        redist = c.redistance;
+        // a Godunov value exceeds its smallest neighbour by >= 1/sqrt(dim): values
+        // up to W settle after ceil(sqrt(dim) W) + 1 sweeps, taken as an even count
+        K_euclid = (int)std::ceil(std::sqrt((double)dim) * c.band) + 1;
+        K_euclid += K_euclid & 1;
         physics = c.physics;
         theta_c = c.theta_c_deg;
         voxel_m = c.voxel_m;
@@ -489,7 +495,11 @@ template <typename T> struct Sim final : SimBase {
     // Re-initialization of phi^c (layout lo_l) into layout ln_l.  2D: the final
     // function goes to `phi`.  3D: partial distances to `d2`, then the fused z
     // sweep writes phi (when `phi` is not null) and the predictor z pass to `t`.
-    void launch_reinit(int lo_l, int ln_l, const T *phic, T *d2, T *phi, T *tz, const int *iota_old, int *iota_new) {
+    // Euclidean variant: reference values to `d2`, then K_euclid Jacobi sweeps
+    // between `d2` and `tz` (an even count: the result is back in `d2`; 2D: the
+    // last sweep writes `phi`), and in 3D the fused kernel without its z sweep.
+    void launch_reinit(int lo_l, int ln_l, const T *phic, T *d2, T *phi, T *tz, const int *iota_old, int *iota_new,
+                       bool euclid) {
         const Totals &t = tot[ln_l];
         const gg::GridArgs g = grid_args();
         const int vk = dim == 3 ? gg::KIND_ZF : gg::KIND_RXY;
@@ -497,16 +507,36 @@ template <typename T> struct Sim final : SimBase {
         if (t.items[gg::KIND_RXY][0] > 0) {
             tbegin(GG_K_REINIT_XY, t.arena);
             int nd = 0;
-            T *out = dim == 3 ? d2 : phi;
+            T *out = dim == 3 || euclid ? d2 : phi;
             for (int c = 0; c < gg::kClasses; ++c) {
                 const gg::ItemRefs ir = refs(ln_l, gg::KIND_RXY, c);
                 if (ir.n <= 0) continue;
                 ++nd;
                 hipLaunchKernelGGL(gg::k_reinit_xy<T>, dim3(grid_of(gg::xcd_grid(ir.n))), dim3(gg::kBlock),
                                    sizeof(T) * t.lds[gg::KIND_RXY][c], stream, boxes_of(lo_l), boxes_of(ln_l), ir,
-                                   phic, out, iota_old, iota_new, vol_part.as<double>(), K, W, g);
+                                   phic, out, iota_old, iota_new, vol_part.as<double>(), euclid ? 0 : K, W,
+                                   euclid ? 1 : 0, g);
             }
             tend(nd);
+            if (euclid) {
+                tbegin(GG_K_REINIT_SWEEP, t.arena);
+                nd = 0;
+                T *a = d2, *b = tz;
+                for (int s = 0; s < K_euclid; ++s) {
+                    const bool fin = dim == 2 && s == K_euclid - 1;
+                    T *dst = fin ? phi : b;
+                    for (int c = 0; c < gg::kClasses; ++c) {
+                        const gg::ItemRefs ir = refs(ln_l, gg::KIND_RXY, c);
+                        if (ir.n <= 0) continue;
+                        ++nd;
+                        hipLaunchKernelGGL(gg::k_jacobi<T>, dim3(grid_of(gg::xcd_grid(ir.n))), dim3(gg::kBlock), 0,
+                                           stream, boxes_of(ln_l), ir, (const T *)a, dst, vol_part.as<double>(), W,
+                                           fin ? 1 : 0, g);
+                    }
+                    std::swap(a, b);
+                }
+                tend(nd);
+            }
         }
         if (dim == 3 && t.items[gg::KIND_ZF][0] > 0) {
             tbegin(GG_K_REINIT_Z, t.arena);
@@ -518,7 +548,7 @@ template <typename T> struct Sim final : SimBase {
                 const dim3 gr(grid_of(gg::xcd_grid(ir.n))), bl(gg::kBlock);
                 const size_t lds = sizeof(T) * t.lds[gg::KIND_ZF][c];
                 auto args = std::make_tuple(boxes_of(ln_l), ir, (const T *)d2, phi, tz, vol_part.as<double>(),
-                                            (const T *)taps_d.as<T>(), K, R, W, g);
+                                            (const T *)taps_d.as<T>(), euclid ? 0 : K, R, W, euclid ? 0 : 1, g);
                 auto go = [&](auto kern) {
                     std::apply([&](auto... a) { hipLaunchKernelGGL(kern, gr, bl, lds, stream, a...); }, args);
                 };
@@ -528,7 +558,6 @@ template <typename T> struct Sim final : SimBase {
             }
             tend(nd);
         }
-        const int tb = 256, gb = (G + tb - 1) / tb;
         tbegin(GG_K_VOLUME, t.arena);
         hipLaunchKernelGGL(gg::k_volumes, dim3(G), dim3(64), 0, stream, boxes_of(ln_l), pref_of(ln_l, vk, 0),
                            vol_part.as<double>(), vol.as<double>(), G);
@@ -634,7 +663,7 @@ template <typename T> struct Sim final : SimBase {
                            lab.as<int>(), arena[0].as<T>(), grid_args());
         HIPCHECK(hipGetLastError());
         launch_reinit(0, 0, arena[0].as<T>(), arena[1].as<T>(), arena[2].as<T>(), arena[3].as<T>(), nullptr,
-                      nullptr);
+                      nullptr, false);
         a_state = 2;
         a_T = a_psi = -1;
         T_R = psi_R = -1;
@@ -759,13 +788,21 @@ template <typename T> struct Sim final : SimBase {
             const bool write_phi = last || physics;
             const int a_phi = write_phi ? pick(bit(a_phic) | bit(a_d2) | bit(a_t), need) : -1;
             launch_reinit(L, Ln, phic, arena[a_d2].as<T>(), write_phi ? arena[a_phi].as<T>() : nullptr,
-                          arena[a_t].as<T>(), io_old, io_new);
+                          arena[a_t].as<T>(), io_old, io_new, redist == GG_REDIST_EUCLID);
             a_T = a_t;
             T_R = R;
             a_state = a_phi;
         } else {
             const int a_phi = pick(bit(a_phic), need);
-            launch_reinit(L, Ln, phic, nullptr, arena[a_phi].as<T>(), nullptr, io_old, io_new);
+            if (redist == GG_REDIST_EUCLID) {
+                // the Jacobi sweeps alternate between two more arenas
+                const int a_u = pick(bit(a_phic) | bit(a_phi), need);
+                const int a_v = pick(bit(a_phic) | bit(a_phi) | bit(a_u), need);
+                launch_reinit(L, Ln, phic, arena[a_u].as<T>(), arena[a_phi].as<T>(), arena[a_v].as<T>(), io_old,
+                              io_new, true);
+            } else {
+                launch_reinit(L, Ln, phic, nullptr, arena[a_phi].as<T>(), nullptr, io_old, io_new, false);
+            }
             a_state = a_phi;
         }
         cur = Ln;
@@ -1033,6 +1070,8 @@ gg_status gg_create(const gg_config *cfg, const int32_t *labels, int32_t n_grain
     if (cfg->precision != GG_FP64 && cfg->precision != GG_FP32)
         return fail(nullptr, GG_E_UNSUPPORTED, "precision must be GG_FP64 or GG_FP32");
     if (cfg->physics < 0 || cfg->physics > 3) return fail(nullptr, GG_E_ARG, "unknown physics bits");
+    if (cfg->redistance != GG_REDIST_TAXICAB && cfg->redistance != GG_REDIST_EUCLID)
+        return fail(nullptr, GG_E_ARG, "redistance must be GG_REDIST_TAXICAB or GG_REDIST_EUCLID");
     if ((cfg->physics & GG_PHYS_MISORIENTATION) && (!quat || !(cfg->theta_c_deg > 0.0)))
         return fail(nullptr, GG_E_ARG, "misorientation weights need quat and theta_c_deg > 0");
     if ((cfg->physics & GG_PHYS_BULK) && (!energy_density || !(cfg->voxel_m > 0.0) || !(cfg->gamma_max > 0.0)))

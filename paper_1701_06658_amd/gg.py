@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libgg.so")
 
 GG_FP64, GG_FP32 = 0, 1
 PHYS_NONE, PHYS_MISORIENTATION, PHYS_BULK = 0, 1, 2
+GG_REDIST_TAXICAB, GG_REDIST_EUCLID = 0, 1
 
 STATUS = {0: "GG_OK", 1: "GG_E_ARG", 2: "GG_E_NOMEM", 3: "GG_E_HIP", 4: "GG_E_CAPACITY",
           5: "GG_E_SMALLBUF", 6: "GG_E_NUMERIC", 7: "GG_E_POISONED", 8: "GG_E_UNSUPPORTED",
@@ -26,7 +27,7 @@ EXPORTS = ["gg_create", "gg_step", "gg_sync", "gg_grain_count", "gg_grain_volume
            "gg_keep_intermediates", "gg_get_intermediate", "gg_status_str", "gg_last_error",
            "gg_destroy", "gg_version", "gg_profile", "gg_get_kernel_times"]
 
-KERNEL_CLASSES = ["conv_xy", "conv_z", "compare", "reinit_xy", "reinit_z", "plan", "volume", "unused"]
+KERNEL_CLASSES = ["conv_xy", "conv_z", "compare", "reinit_xy", "reinit_z", "plan", "volume", "reinit_sweep"]
 
 
 class GGError(RuntimeError):
@@ -39,7 +40,7 @@ class Config(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("band", C.c_double),
                 ("precision", C.c_int32), ("physics", C.c_int32), ("theta_c_deg", C.c_double),
                 ("voxel_m", C.c_double), ("gamma_max", C.c_double),
-                ("capacity_headroom", C.c_double)]
+                ("capacity_headroom", C.c_double), ("redistance", C.c_int32)]
 
 
 class KernelTimes(C.Structure):
@@ -108,7 +109,7 @@ class Simulation:
 
     def __init__(self, labels, band, G=None, precision="fp64", physics=0, quat=None,
                  theta_c_deg=15.0, energy=None, voxel_m=0.0, gamma_max=0.0, stream=None,
-                 headroom=0.0):
+                 headroom=0.0, redistance="taxicab"):
         lib = load_library()
         labels = np.ascontiguousarray(labels, dtype=np.int32)
         if labels.ndim == 2:
@@ -127,6 +128,7 @@ class Simulation:
         cfg.voxel_m = float(voxel_m)
         cfg.gamma_max = float(gamma_max)
         cfg.capacity_headroom = float(headroom)
+        cfg.redistance = {"taxicab": GG_REDIST_TAXICAB, "euclid": GG_REDIST_EUCLID}[redistance]
         q = None if quat is None else np.ascontiguousarray(quat, dtype=np.float64)
         e = None if energy is None else np.ascontiguousarray(energy, dtype=np.float64)
         h = C.c_void_p()

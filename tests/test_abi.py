@@ -33,6 +33,16 @@ def test_every_declared_symbol_is_exported(lib):
     assert sorted(gg.EXPORTS) == names
 
 
+def test_config_struct_matches_header():
+    # the ctypes mirror of gg_config lists the header's fields in order
+    from paper_1701_06658_amd import gg
+    text = open(HEADER).read()
+    body = re.search(r"typedef struct \{(.*?)\} gg_config;", text, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"\b(?:int32_t|double)\s+(\w+)", body)
+    assert names == [f[0] for f in gg.Config._fields_]
+
+
 def test_status_strings(lib):
     assert lib.gg_status_str(0) == b"ok"
     assert lib.gg_status_str(1) == b"invalid argument"
@@ -49,6 +59,7 @@ def _create(lib, **kw):
     cfg.precision = kw.get("precision", 0)
     cfg.physics = kw.get("physics", 0)
     cfg.theta_c_deg = 15.0
+    cfg.redistance = kw.get("redistance", 0)
     labels = kw.get("labels", np.zeros(int(np.prod(n)), np.int32))
     h = C.c_void_p()
     st = lib.gg_create(C.byref(cfg), labels.ctypes.data_as(C.c_void_p), kw.get("G", 1), None,
@@ -66,6 +77,7 @@ def _create(lib, **kw):
     dict(G=0),
     dict(physics=1),                           # misorientation weights without quaternions
     dict(physics=2),                           # bulk energy without energy densities
+    dict(redistance=2),                        # unknown re-initialization scheme
     dict(dim=3, n=(2048, 2048, 1024), labels=np.zeros(1, np.int32)),  # 2^32 voxels: rejected before labels are read
 ])
 def test_argument_errors_are_reported_before_any_device_use(lib, kw):
