@@ -35,6 +35,13 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kPF = 16;
 // Predictor xy work items: planes per item (pipelined through one LDS tile).
 constexpr int kCxyPlanes = 4;
+// Jacobi sweep work items: at most this many planes per item, marched through
+// a ring of three LDS planes; values per lane of the next plane held in registers.
+#ifndef GG_JAC_PLANES
+#define GG_JAC_PLANES 16
+#endif
+constexpr int kJacPlanes = GG_JAC_PLANES;
+constexpr int kJacQ = 16;
 #ifndef GG_LDS_BYTES
 #define GG_LDS_BYTES 40960
 #endif
@@ -42,8 +49,11 @@ constexpr int kLdsBytes = GG_LDS_BYTES;  // dynamic LDS budget per work group (F
 constexpr int kKB = 4;            // outputs per thread along a stencil axis
 constexpr int kMaxRadius = 24;    // largest Gaussian radius R
 constexpr int kMaxBand = 16;      // largest band half width W
-constexpr int kKinds = 4;         // item kinds: predictor xy, predictor z, reinit xy, fused z
-enum { KIND_CXY = 0, KIND_CZ = 1, KIND_RXY = 2, KIND_ZF = 3 };
+constexpr int kKinds = 5;         // item kinds: predictor xy, predictor z, reinit xy, fused z, Jacobi sweep
+enum { KIND_CXY = 0, KIND_CZ = 1, KIND_RXY = 2, KIND_ZF = 3, KIND_JAC = 4 };
+// kinds whose items are xy tiles of consecutive z planes (the others: x by z
+// tiles of y rows)
+__host__ __device__ inline bool kind_xy(int kind) { return kind == KIND_CXY || kind == KIND_RXY || kind == KIND_JAC; }
 
 // Box table of one layout.
 struct Boxes {
@@ -160,6 +170,10 @@ __host__ __device__ inline long long lds_need(int kind, int tx, int ty, int h, i
         const long long D = ty + 2 * h2 + 2 * hz;
         return (long long)nz * tx * (D + kKB + 1) + D;
     }
+    if (kind == KIND_JAC) {  // three planes of the tile with one ring of neighbours; row and column tables
+        const long long FW = tx + 2, FH = ty + 2;
+        return 3 * FW * FH + FW + FH;
+    }
     return (long long)tx * (ty + 2 * h);  // prologue z pass
 }
 
@@ -203,6 +217,10 @@ __host__ __device__ inline Tiling choose_tiling(int kind, int ex, int ey, int pl
         const int chunks = (planes + kCxyPlanes - 1) / kCxyPlanes;
         t.nb = (planes + chunks - 1) / chunks;
     }
+    if (kind == KIND_JAC && t.nxs > 0 && planes > 1) {
+        const int chunks = (planes + kJacPlanes - 1) / kJacPlanes;
+        t.nb = (planes + chunks - 1) / chunks;
+    }
     if ((kind == KIND_RXY || kind == KIND_ZF) && t.nxs > 0 && planes > 1) {
         const bool sx = t.nxs > 1, sy = t.nys > 1;
         const long long one = lds_need(kind, t.tx, t.ty, h, h2, sx, sy, 1);
@@ -217,18 +235,18 @@ __host__ __device__ inline Tiling choose_tiling(int kind, int ex, int ey, int pl
 }
 
 __host__ __device__ inline void kind_halos(int kind, int R, int K, int *h, int *h2) {
-    *h = (kind == KIND_CXY || kind == KIND_CZ) ? R : K;
+    *h = (kind == KIND_CXY || kind == KIND_CZ) ? R : (kind == KIND_JAC ? 1 : K);
     *h2 = kind == KIND_ZF ? R : 0;
 }
 
 __host__ __device__ inline int kind_planes(int kind, const int *e) {
-    return (kind == KIND_CXY || kind == KIND_RXY) ? e[2] : e[1];
+    return kind_xy(kind) ? e[2] : e[1];
 }
 
 __host__ __device__ inline Tiling kind_tiling(int kind, const int *e, int R, int K, int budget, int target) {
     int h, h2;
     kind_halos(kind, R, K, &h, &h2);
-    const int ey = (kind == KIND_CXY || kind == KIND_RXY) ? e[1] : e[2];
+    const int ey = kind_xy(kind) ? e[1] : e[2];
     return choose_tiling(kind, e[0], ey, kind_planes(kind, e), h, h2, budget, target);
 }
 
@@ -288,7 +306,7 @@ __device__ __forceinline__ ItemTile decode_item(long long item, int kind, const 
     const int per = tl.nxs * tl.nys;
     const int chunk = sub / per;
     const int rem = sub - chunk * per;
-    if (kind == KIND_RXY || kind == KIND_ZF || kind == KIND_CXY) {
+    if (kind != KIND_CZ) {
         const int nb = tilings[2 * it.k + 1].x;
         it.plane = chunk * nb;
         it.np = min(nb, kind_planes(kind, e) - it.plane);
@@ -299,7 +317,7 @@ __device__ __forceinline__ ItemTile decode_item(long long item, int kind, const 
     const int ys = rem / tl.nxs, xs = rem - ys * tl.nxs;
     it.x0 = xs * tl.tx;
     it.y0 = ys * tl.ty;
-    const int ey = (kind == KIND_CXY || kind == KIND_RXY) ? e[1] : e[2];
+    const int ey = kind_xy(kind) ? e[1] : e[2];
     it.wx = min(tl.tx, e[0] - it.x0);
     it.wy = min(tl.ty, ey - it.y0);
     return it;
@@ -1363,6 +1381,17 @@ __global__ void __launch_bounds__(kBlock)
 // sum over the a_i below u of (u - a_i)^2 = 1, for neighbour values a1..a3
 // (+inf: no neighbour along that axis).  The three are sorted first; one
 // neighbour gives a + 1, two the quadratic's root, three the cubic's.
+// Square root and division by 3 for the update: correctly rounded in FP64; in
+// FP32 (the mixed path) the hardware square root (1 ulp) and the product with
+// the rounded 1/3.
+__device__ __forceinline__ double upd_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float upd_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double upd_third(double x) { return x / 3.0; }
+__device__ __forceinline__ float upd_third(float x) { return x * (1.0f / 3.0f); }
+// A 32-bit word whose bit 31 is the sign bit of x.
+__device__ __forceinline__ int sign_word(float x) { return __float_as_int(x); }
+__device__ __forceinline__ int sign_word(double x) { return __double2hiint(x); }
+
 template <typename T> __device__ __forceinline__ T godunov(T a1, T a2, T a3) {
     T t;
     if (a2 < a1) { t = a1; a1 = a2; a2 = t; }
@@ -1371,32 +1400,39 @@ template <typename T> __device__ __forceinline__ T godunov(T a1, T a2, T a3) {
     T u = a1 + T(1);
     if (u > a2) {
         const T d = a1 - a2;
-        u = (a1 + a2 + sqrt(T(2) - d * d)) * T(0.5);
+        u = (a1 + a2 + upd_sqrt(T(2) - d * d)) * T(0.5);
         if (u > a3) {
             const T s1 = a1 + a2 + a3, s2 = a1 * a1 + a2 * a2 + a3 * a3;
-            u = (s1 + sqrt(s1 * s1 - T(3) * (s2 - T(1)))) / T(3);
+            u = upd_third(s1 + upd_sqrt(s1 * s1 - T(3) * (s2 - T(1))));
         }
     }
     return u;
 }
 
-// One Jacobi sweep of the Euclidean re-initialization over a work item (tile of
-// nz planes) of the new box: src -> dst, distances with the inside flag in the
-// sign bit.  A cell with a face neighbour on the other side of the interface (a
-// cell outside the box counts as outside the grain) keeps its reference value;
-// every other cell takes min(u, godunov(a_x, a_y, a_z)), a_i the smaller
-// magnitude of its two neighbours along axis i that lie in the box.  `final2d`
-// (the last sweep in 2D) stores the band-clamped function and the tile's volume
-// instead.  Each lane walks one (x, y) position through the planes, keeping the
-// z neighbours in registers; in-plane neighbours come through the caches.
+// One Jacobi sweep of the Euclidean re-initialization over a work item (an xy
+// tile of consecutive z planes) of the new box: src -> dst, distances with the
+// inside flag in the sign bit.  A cell with a face neighbour on the other side
+// of the interface (a cell outside the box counts as outside the grain) keeps
+// its reference value; every other cell takes min(u, godunov(a_x, a_y, a_z)),
+// a_i the smaller magnitude of its two neighbours along axis i that lie in the
+// box.  `final2d` (the last sweep in 2D) stores the band-clamped function and
+// the tile's volume instead.
+//
+// The item marches through its planes with a ring of three LDS planes, each the
+// tile and one ring of neighbours (FW x FH, -inf where the neighbour is not in
+// the box: outside the grain, magnitude +inf).  While one plane is updated from
+// LDS, the lanes' loads of the plane two ahead are in flight in registers.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_jacobi(Boxes Ln, ItemRefs ir, const T *__restrict__ src, T *__restrict__ dst, double *__restrict__ vol_part,
              T W, int final2d, GridArgs g) {
+    static_assert(lds_budget<T>() / 3 <= kJacQ * kBlock, "a Jacobi plane must fit the lanes' registers");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sm = reinterpret_cast<T *>(smem_raw);
     __shared__ double red[kBlock / 64];
     const long long cls_item = xcd_item(ir.n);
     if (cls_item >= ir.n) return;
-    const ItemTile it = decode_item(cls_item, KIND_RXY, Ln, ir);
+    const ItemTile it = decode_item(cls_item, KIND_JAC, Ln, ir);
     const int k = it.k, z0 = it.plane, nz = it.np, x0 = it.x0, y0 = it.y0, wx = it.wx, wy = it.wy;
     const int ex = Ln.ext[3 * k], ey = Ln.ext[3 * k + 1], ez = Ln.ext[3 * k + 2];
     const T *u = src + Ln.off[k];
@@ -1404,33 +1440,65 @@ __global__ void __launch_bounds__(kBlock)
     const T inf = tinf<T>();
     const bool d3 = g.dim == 3;
     const int plane = ex * ey;
-    double vsum = 0.0;
-    // an absent neighbour reads -inf: outside the grain, magnitude +inf
-    auto at = [&](int i) { return i >= 0 ? u[i] : -inf; };
-    for (Walk2 w(threadIdx.x, wx); w.r < wy; w.step()) {
-        const int x = x0 + w.c, y = y0 + w.r;
-        const int xm = axis_map(x - 1, ex, g.n[0]), xp = axis_map(x + 1, ex, g.n[0]);
-        const int ym = axis_map(y - 1, ey, g.n[1]), yp = axis_map(y + 1, ey, g.n[1]);
-        const int ixm = xm < 0 ? -1 : xm - x, ixp = xp < 0 ? -1 : xp - x;
-        const int iym = ym < 0 ? -1 : (ym - y) * ex, iyp = yp < 0 ? -1 : (yp - y) * ex;
-        int c = (z0 * ey + y) * ex + x;
-        T zlo = -inf;
-        if (d3) {
-            const int zz = axis_map(z0 - 1, ez, g.n[2]);
-            zlo = zz >= 0 ? u[(zz * ey + y) * ex + x] : -inf;
+    const int FW = wx + 2, FH = wy + 2, PS = FW * FH;
+    int *ctab = reinterpret_cast<int *>(sm + 3 * PS), *rtab = ctab + FW;
+    for (int i = threadIdx.x; i < FW; i += kBlock) ctab[i] = axis_map(x0 - 1 + i, ex, g.n[0]);
+    for (int i = threadIdx.x; i < FH; i += kBlock) {
+        const int yy = axis_map(y0 - 1 + i, ey, g.n[1]);
+        rtab[i] = yy < 0 ? -1 : yy * ex;
+    }
+    __syncthreads();
+    // in-plane offsets of this lane's ring positions (-1: not in the box)
+    int qo[kJacQ];
+#pragma unroll
+    for (int j = 0; j < kJacQ; ++j) {
+        const int q = j * kBlock + threadIdx.x;
+        qo[j] = -1;
+        if (q < PS) {
+            const int r = q / FW, c = q - r * FW;
+            const int ro = rtab[r], co = ctab[c];
+            if (ro >= 0 && co >= 0) qo[j] = ro + co;
         }
-        T cur = u[c];
-        for (int p = 0; p < nz; ++p, c += plane) {
-            T zhi = -inf;
-            if (d3) {
-                const int zz = axis_map(z0 + p + 1, ez, g.n[2]);
-                zhi = zz >= 0 ? u[(zz * ey + y) * ex + x] : -inf;
-            }
-            const T nxm = at(xm < 0 ? -1 : c + ixm), nxp = at(xp < 0 ? -1 : c + ixp);
-            const T nym = at(ym < 0 ? -1 : c + iym), nyp = at(yp < 0 ? -1 : c + iyp);
-            const bool sc = signbit(cur);
-            bool fixed = signbit(nxm) != sc || signbit(nxp) != sc || signbit(nym) != sc || signbit(nyp) != sc;
-            if (d3) fixed = fixed || signbit(zlo) != sc || signbit(zhi) != sc;
+    }
+    T nx[kJacQ];
+    auto fetch = [&](int z) {  // plane z (any integer) into registers
+        const int zz = d3 ? axis_map(z, ez, g.n[2]) : (z == 0 ? 0 : -1);
+        const T *pz = u + (zz < 0 ? 0 : zz) * plane;
+#pragma unroll
+        for (int j = 0; j < kJacQ; ++j) {
+            nx[j] = -inf;
+            if (zz >= 0 && qo[j] >= 0) nx[j] = pz[qo[j]];
+        }
+    };
+    auto stash = [&](int slot) {
+        T *d = sm + slot * PS;
+#pragma unroll
+        for (int j = 0; j < kJacQ; ++j) {
+            const int q = j * kBlock + threadIdx.x;
+            if (q < PS) d[q] = nx[j];
+        }
+    };
+    fetch(z0 - 1);
+    stash(0);
+    fetch(z0);
+    stash(1);
+    fetch(z0 + 1);
+    double vsum = 0.0;
+    for (int p = 0; p < nz; ++p) {
+        stash((p + 2) % 3);
+        __syncthreads();
+        if (p + 1 < nz) fetch(z0 + p + 2);
+        const T *lo = sm + (p % 3) * PS, *mid = sm + ((p + 1) % 3) * PS, *hi = sm + ((p + 2) % 3) * PS;
+        const int zoff = (z0 + p) * plane;
+        for (Walk2 w(threadIdx.x, wx); w.r < wy; w.step()) {
+            const int a = (w.r + 1) * FW + w.c + 1;
+            const T cur = mid[a], nxm = mid[a - 1], nxp = mid[a + 1], nym = mid[a - FW], nyp = mid[a + FW];
+            const T zlo = lo[a], zhi = hi[a];
+            // a neighbour on the other side: a sign bit that differs from the cell's
+            const int wc = sign_word(cur);
+            int diff = (sign_word(nxm) ^ wc) | (sign_word(nxp) ^ wc) | (sign_word(nym) ^ wc) | (sign_word(nyp) ^ wc);
+            if (d3) diff |= (sign_word(zlo) ^ wc) | (sign_word(zhi) ^ wc);
+            const bool sc = wc < 0, fixed = diff < 0;
             const T mc = fabs(cur);
             T res = mc;
             if (!fixed) {
@@ -1439,19 +1507,19 @@ __global__ void __launch_bounds__(kBlock)
                 const T gv = godunov(ax, ay, az);
                 res = gv < mc ? gv : mc;
             }
+            const int idx = zoff + (y0 + w.r) * ex + x0 + w.c;
             if (final2d) {
                 const T dc = res < W ? res : W;
                 const T pv = sc ? -dc : dc;
-                v[c] = pv;
+                v[idx] = pv;
                 double cl = (double)pv + 0.5;
                 cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
                 vsum += cl;
             } else {
-                v[c] = fixed ? cur : (sc ? -res : res);
+                v[idx] = fixed ? cur : (sc ? -res : res);
             }
-            zlo = cur;
-            cur = zhi;
         }
+        __syncthreads();
     }
     if (final2d) {
         const double s = block_sum(vsum, red);
@@ -1572,13 +1640,14 @@ __global__ void k_plan(Boxes Lo, Boxes Ln, int *bmin, int *bmax, unsigned *occ, 
     }
 }
 
-// Per-grain work item counts of the four stencil kinds, split into the two
-// launch classes, the stored tilings, and the largest LDS need per class.
+// Per-grain work item counts of the stencil kinds, split into the two launch
+// classes, the stored tilings, and the largest LDS need per class (Jacobi
+// sweep items only when `jac` is set).
 // cnt holds 3 arrays of G per kind: all items, class 0, class 1.
 // One thread per (grain, kind); grid (ceil(G / 256), kKinds).  The per-class
 // LDS maxima are reduced over the wave before one atomic per wave and class.
 __global__ void k_item_counts(Boxes L, long long *cnt, int4 *tilings, unsigned long long *lds_max, int R, int K, int G,
-                              int budget, int small) {
+                              int budget, int small, int jac) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x, q = blockIdx.y;
     unsigned long long need_c[kClasses] = {0, 0};
     if (k < G) {
@@ -1586,7 +1655,7 @@ __global__ void k_item_counts(Boxes L, long long *cnt, int4 *tilings, unsigned l
         c[k] = c[G + k] = c[2LL * G + k] = 0;
         int4 *rec = tilings + 2 * ((long long)q * G + k);
         rec[0] = rec[1] = make_int4(0, 0, 0, 0);
-        if (L.alive[k]) {
+        if (L.alive[k] && (q != KIND_JAC || jac)) {
             const int *e = L.ext + 3 * k;
             const int sq = q == KIND_ZF ? small / 100 * GG_ZF_TARGET_PCT : (q == KIND_RXY ? small / 100 * GG_RXY_SMALL_PCT : small);
             const Tiling t = kind_tiling(q, e, R, K, budget, sq);

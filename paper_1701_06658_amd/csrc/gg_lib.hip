@@ -347,7 +347,7 @@ template <typename T> struct Sim final : SimBase {
         const int tb = 256, gb = (G + tb - 1) / tb;
         hipLaunchKernelGGL(gg::k_item_counts, dim3(gb, gg::kKinds), dim3(tb), 0, stream, L, cnt.as<long long>(), itile[l].as<int4>(),
                            ldsmax.as<unsigned long long>(), R, K, G, gg::lds_budget<T>(),
-                           gg::small_budget<T>());
+                           gg::small_budget<T>(), redist == GG_REDIST_EUCLID ? 1 : 0);
         hipLaunchKernelGGL(gg::k_scan_multi, dim3(3 * gg::kKinds), dim3(1024), 0, stream, cnt.as<long long>(),
                            ipref[l].as<long long>(), G);
         if (coverage) {
@@ -502,7 +502,7 @@ template <typename T> struct Sim final : SimBase {
                        bool euclid) {
         const Totals &t = tot[ln_l];
         const gg::GridArgs g = grid_args();
-        const int vk = dim == 3 ? gg::KIND_ZF : gg::KIND_RXY;
+        const int vk = dim == 3 ? gg::KIND_ZF : (euclid ? gg::KIND_JAC : gg::KIND_RXY);
         vol_part.ensure(sizeof(double) * (size_t)std::max<long long>(t.items[vk][0], 1) * 5 / 4);
         if (t.items[gg::KIND_RXY][0] > 0) {
             tbegin(GG_K_REINIT_XY, t.arena);
@@ -526,12 +526,12 @@ template <typename T> struct Sim final : SimBase {
                     const bool fin = dim == 2 && s == K_euclid - 1;
                     T *dst = fin ? phi : b;
                     for (int c = 0; c < gg::kClasses; ++c) {
-                        const gg::ItemRefs ir = refs(ln_l, gg::KIND_RXY, c);
+                        const gg::ItemRefs ir = refs(ln_l, gg::KIND_JAC, c);
                         if (ir.n <= 0) continue;
                         ++nd;
-                        hipLaunchKernelGGL(gg::k_jacobi<T>, dim3(grid_of(gg::xcd_grid(ir.n))), dim3(gg::kBlock), 0,
-                                           stream, boxes_of(ln_l), ir, (const T *)a, dst, vol_part.as<double>(), W,
-                                           fin ? 1 : 0, g);
+                        hipLaunchKernelGGL(gg::k_jacobi<T>, dim3(grid_of(gg::xcd_grid(ir.n))), dim3(gg::kBlock),
+                                           sizeof(T) * t.lds[gg::KIND_JAC][c], stream, boxes_of(ln_l), ir,
+                                           (const T *)a, dst, vol_part.as<double>(), W, fin ? 1 : 0, g);
                     }
                     std::swap(a, b);
                 }
