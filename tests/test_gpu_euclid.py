@@ -88,3 +88,36 @@ def test_euclid_mixed_one_step_3d():
     o.set_redistance(1)
     o.step(c["dt"])
     _mixed_one_step(o, c["dt"], c["W"], c["G"], "euclid cfg2/64 from step 1", redistance="euclid")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_euclid_shrink_rate_on_gpu(precision):
+    # the arrival-time comparison of the two schemes on the GPU: a shrinking
+    # sphere's R^2 falls linearly, at kappa_s sigma^2 per step, with kappa_s
+    # closer to the curvature law (1) for the Euclidean variant; FP64 matches
+    # the oracle's kappa_s to rounding, FP32 within 0.5%
+    import paper_1701_06658_amd as gg
+    N, R0, sigma, W, steps = 64, 16.0, 2.0, 8.0, 12
+    dt = config_dt(sigma, N)
+    labels = ball_labels((N, N, N), R0)
+
+    def kappa(sim):
+        vals = []
+        for s in range(steps + 1):
+            if s:
+                sim.step(dt)
+            vals.append((3.0 * sim.volumes()[1] / (4.0 * np.pi)) ** (2.0 / 3.0))
+        slope = np.polyfit(np.arange(steps + 1, dtype=float), np.array(vals), 1)[0]
+        return -slope / (2.0 * sigma ** 2)
+
+    k = {}
+    for mode in ("taxicab", "euclid"):
+        k[mode] = kappa(gg.Simulation(labels, W, G=2, precision=precision, redistance=mode))
+    o = Oracle(labels, W, G=2)
+    o.set_redistance(1)
+    k_orc = kappa(o)
+    print(f"[{precision}] kappa_s taxicab {k['taxicab']:.4f} euclid {k['euclid']:.4f} (oracle euclid {k_orc:.4f})",
+          flush=True)
+    assert abs(k["euclid"] - k_orc) <= (1e-9 if precision == "fp64" else 5e-3 * k_orc)
+    assert 1.04 <= k["euclid"] <= 1.18
+    assert k["euclid"] < k["taxicab"] - 0.05
