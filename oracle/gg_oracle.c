@@ -969,6 +969,157 @@ int orc_convolve_box(int dim, const int32_t n[3], double band, double sigma,
     return R;
 }
 
+/* ------------------------------------------------------- grid coarsening
+ * (sec. 3, sequential optimizations): the grid spacing grows as grains vanish,
+ * so that a grain keeps about the same number of voxels, and each function is
+ * projected onto the coarser grid by trilinear interpolation.
+ *
+ * Reading: the periodic grid n becomes n' with the same ratio r = n / n' on
+ * every axis of the model (r >= 1, any rational value).  New node i' sits at
+ * old position i' r (node 0 on node 0), and the new voxel edge is r old edges.
+ * A grain's remapped function at i' is its old function, by the sampling rule
+ * (-W outside the old box), interpolated linearly along x, then y, then z
+ * between the two old nodes that enclose i' r, and divided by r (distances in
+ * new voxels).  The new box is the covered cyclic interval of the positive
+ * nodes on each axis, padded by P (the creation rule); a grain without a
+ * positive node vanishes.  The function is then re-initialised on the new box
+ * with the taxicab scheme (as at creation), which restores the band [-W, W].
+ * The voxel edge h used by the bulk term grows by r; the ID-field is rebuilt
+ * as at creation when the predictor correction is on. */
+
+/* Old node below new node i' and the interpolation weight of the node above:
+ * i' n / n' = i0 + rem / n' in exact integer arithmetic. */
+static void coarse_coord(int ip, int N, int Np, long *i0, double *t) {
+    const long num = (long)ip * N;
+    *i0 = num / Np;
+    *t = (double)(num - *i0 * Np) / (double)Np;
+}
+
+/* Remapped value (before re-initialization) of a grain's old function at new
+ * global node g' (n: old grid, np: new grid, r = n[0] / np[0]). */
+static double coarse_sample(const double *f, const int *lo, const int *e, const int *n, const int *np,
+                            int dim, double W, double r, const int gp[3]) {
+    long i0[3] = {0, 0, 0};
+    double t[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < dim; a++) coarse_coord(gp[a], n[a], np[a], &i0[a], &t[a]);
+    double c[2][2]; /* (y, z) corners after the x interpolation, then y */
+    const int nz = dim == 3 ? 2 : 1;
+    for (int dz = 0; dz < nz; dz++)
+        for (int dy = 0; dy < 2; dy++) {
+            const long y = i0[1] + dy - lo[1], z = i0[2] + dz - lo[2];
+            const double v0 = sample(f, e, n, i0[0] - lo[0], y, z, -W);
+            const double v1 = sample(f, e, n, i0[0] + 1 - lo[0], y, z, -W);
+            c[dz][dy] = (1.0 - t[0]) * v0 + t[0] * v1;
+        }
+    double v[2];
+    for (int dz = 0; dz < nz; dz++) v[dz] = (1.0 - t[1]) * c[dz][0] + t[1] * c[dz][1];
+    const double u = dim == 3 ? (1.0 - t[2]) * v[0] + t[2] * v[1] : v[0];
+    return u / r;
+}
+
+int orc_coarsen(orc_sim *s, const int32_t np_in[3]) {
+    if (!s || !np_in) return -1;
+    const int dim = s->dim;
+    int np[3] = {np_in[0], np_in[1], np_in[2]};
+    const int *n = s->n;
+    if (dim == 2 && np[2] != 1) return -1;
+    for (int a = 0; a < dim; a++) {
+        if (np[a] < 4 * s->P + 2 || np[a] > n[a]) return -1;
+        if ((long)np[a] * n[0] != (long)np[0] * n[a]) return -1; /* one ratio on every axis */
+    }
+    const double r = (double)n[0] / (double)np[0];
+    const double W = s->W;
+    const int G = s->G;
+    int *nlo = (int *)calloc(3L * G, sizeof(int)), *next = (int *)calloc(3L * G, sizeof(int));
+    int *nalive = (int *)calloc(G, sizeof(int));
+    double **nphi = (double **)calloc(G, sizeof(double *));
+#pragma omp parallel for schedule(dynamic)
+    for (int k = 0; k < G; k++) {
+        if (!s->alive[k]) continue;
+        const int *lo = &s->lo[3 * k], *e = &s->ext[3 * k];
+        /* positive nodes of the remapped function over the whole new grid */
+        unsigned char *occ[3];
+        for (int a = 0; a < 3; a++) occ[a] = (unsigned char *)calloc(np[a], 1);
+        int any = 0;
+        for (int z = 0; z < np[2]; z++)
+            for (int y = 0; y < np[1]; y++)
+                for (int x = 0; x < np[0]; x++) {
+                    const int gp[3] = {x, y, z};
+                    if (!(coarse_sample(s->phi[k], lo, e, n, np, dim, W, r, gp) > 0.0)) continue;
+                    any = 1;
+                    occ[0][x] = occ[1][y] = occ[2][z] = 1;
+                }
+        if (any) {
+            nalive[k] = 1;
+            for (int a = 0; a < 3; a++) {
+                int st, ln;
+                cyclic_cover(occ[a], np[a], &st, &ln);
+                pad_interval(st, ln, s->P, np[a], &nlo[3 * k + a], &next[3 * k + a]);
+            }
+            const int *ne = &next[3 * k], *nl = &nlo[3 * k];
+            const long m = nvox(ne);
+            double *f = (double *)malloc(sizeof(double) * m);
+            for (int z = 0; z < ne[2]; z++)
+                for (int y = 0; y < ne[1]; y++)
+                    for (int x = 0; x < ne[0]; x++) {
+                        const int gp[3] = {wrapi((long)nl[0] + x, np[0]), wrapi((long)nl[1] + y, np[1]),
+                                           wrapi((long)nl[2] + z, np[2])};
+                        f[lidx(ne, x, y, z)] = coarse_sample(s->phi[k], lo, e, n, np, dim, W, r, gp);
+                    }
+            nphi[k] = (double *)malloc(sizeof(double) * m);
+            redistance_box(dim, np, W, ne, f, nphi[k]);
+            free(f);
+        }
+        for (int a = 0; a < 3; a++) free(occ[a]);
+    }
+    for (int k = 0; k < G; k++) {
+        free(s->phi[k]);
+        free(s->iota[k]);
+        s->phi[k] = nphi[k];
+        s->iota[k] = NULL;
+        s->alive[k] = nalive[k];
+        s->vol[k] = 0.0;
+        for (int a = 0; a < 3; a++) {
+            s->lo[3 * k + a] = nlo[3 * k + a];
+            s->ext[3 * k + a] = next[3 * k + a];
+        }
+        if (nalive[k]) {
+            const long m = nvox(&next[3 * k]);
+            s->vol[k] = volume_box(nphi[k], m);
+            s->iota[k] = (int *)malloc(sizeof(int) * m);
+            for (long v = 0; v < m; v++) s->iota[k][v] = -1;
+        }
+    }
+    free(nlo);
+    free(next);
+    free(nalive);
+    free(nphi);
+    memcpy(s->n, np, sizeof(np));
+    s->h_phys = s->h_phys * r;
+    free_intermediates(s);
+    if (s->mode) initial_iota(s);
+    return 0;
+}
+
+/* Stand-alone remap of one box function (before re-initialization), for the
+ * pinning tests: values at the new nodes of box (nlo, next) on grid np. */
+int orc_coarse_sample_box(int dim, const int32_t n[3], const int32_t np[3], double band, const int32_t lo[3],
+                          const int32_t ext[3], const double *f, const int32_t nlo[3], const int32_t next[3],
+                          double *out) {
+    const int nn[3] = {n[0], n[1], n[2]}, npp[3] = {np[0], np[1], np[2]};
+    const int l[3] = {lo[0], lo[1], lo[2]}, e[3] = {ext[0], ext[1], ext[2]};
+    const int ne[3] = {next[0], next[1], next[2]};
+    const double r = (double)n[0] / (double)np[0];
+    for (int z = 0; z < ne[2]; z++)
+        for (int y = 0; y < ne[1]; y++)
+            for (int x = 0; x < ne[0]; x++) {
+                const int gp[3] = {wrapi((long)nlo[0] + x, npp[0]), wrapi((long)nlo[1] + y, npp[1]),
+                                   wrapi((long)nlo[2] + z, npp[2])};
+                out[lidx(ne, x, y, z)] = coarse_sample(f, l, e, nn, npp, dim, band, r, gp);
+            }
+    return 0;
+}
+
 int orc_set_redistance(orc_sim *s, int mode) {
     if (!s || mode < 0 || mode > 1) return -1;
     s->redist = mode;

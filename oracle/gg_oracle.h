@@ -39,6 +39,13 @@ int orc_set_physics(orc_sim *s, int mode, const double *quat, double theta_c_deg
  * upwind update in Jacobi form from gradient-normalised reference values). */
 int orc_set_redistance(orc_sim *s, int mode);
 
+/* Grid coarsening (sec. 3, sequential optimizations): project every grain onto
+ * the coarser periodic grid np (same ratio r = n / np >= 1 on every axis of the
+ * model, each axis >= 4P + 2) by trilinear interpolation at old position i' r,
+ * values divided by r; new boxes from the positive nodes; re-initialised with
+ * the taxicab scheme.  The voxel edge of the bulk term grows by r. */
+int orc_coarsen(orc_sim *s, const int32_t np[3]);
+
 /* One timestep of normalised length dt (sigma = sqrt(2 dt) * n[0] voxels). */
 int orc_step(orc_sim *s, double dt);
 /* Keep the predictor output and the corrector output of the last step. */
@@ -70,6 +77,10 @@ int orc_redistance_box(int dim, const int32_t n[3], double band,
 int orc_redistance_box_euclid(int dim, const int32_t n[3], double band,
                               const int32_t lo[3], const int32_t ext[3], const double *f, double *out);
 int orc_euclid_sweeps(int dim, double band);   /* Jacobi sweeps of the Euclidean scheme */
+/* The coarsening's remap of one box function before re-initialization. */
+int orc_coarse_sample_box(int dim, const int32_t n[3], const int32_t np[3], double band, const int32_t lo[3],
+                          const int32_t ext[3], const double *f, const int32_t nlo[3], const int32_t next[3],
+                          double *out);
 double orc_misorientation_deg(const double qa[4], const double qb[4]);
 double orc_pair_weight(double theta_deg, double theta_c_deg, double *mobility);
 int orc_num_threads(void);

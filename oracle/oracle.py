@@ -60,6 +60,9 @@ def load_library():
     lib.orc_redistance_box_euclid.argtypes = [C.c_int, _i32p, C.c_double, _i32p, _i32p, _f64p, _f64p]
     lib.orc_euclid_sweeps.argtypes = [C.c_int, C.c_double]
     lib.orc_set_redistance.argtypes = [C.c_void_p, C.c_int]
+    lib.orc_coarsen.argtypes = [C.c_void_p, _i32p]
+    lib.orc_coarse_sample_box.argtypes = [C.c_int, _i32p, _i32p, C.c_double, _i32p, _i32p, _f64p, _i32p, _i32p,
+                                          _f64p]
     lib.orc_misorientation_deg.restype = C.c_double
     lib.orc_misorientation_deg.argtypes = [_f64p, _f64p]
     lib.orc_pair_weight.restype = C.c_double
@@ -123,6 +126,13 @@ class Oracle:
         """0: the paper's taxicab spreading; 1: Euclidean fast sweeping (steps after this call)."""
         if self._lib.orc_set_redistance(self._p, int(mode)) != 0:
             raise ValueError("unknown re-initialization scheme")
+
+    def coarsen(self, n_new):
+        """Project every grain onto the coarser periodic grid n_new (same ratio on every axis)."""
+        nn = _grid(n_new)
+        if self._lib.orc_coarsen(self._p, nn) != 0:
+            raise ValueError("oracle rejected the coarser grid")
+        self.n = nn
 
     def keep_intermediates(self, on=True):
         self._lib.orc_keep_intermediates(self._p, int(bool(on)))
@@ -238,6 +248,24 @@ def redistance_box(f, band, n, dim=None, euclid=False):
     fn = lib.orc_redistance_box_euclid if euclid else lib.orc_redistance_box
     if fn(dim, nn, float(band), np.zeros(3, np.int32), ext, f.ravel(), out.ravel()) != 0:
         raise ValueError("bad arguments")
+    return out
+
+
+def coarse_sample_box(f, band, n, n_new, lo, new_lo, new_ext, dim=None):
+    """The coarsening's remap (before re-initialization) of one box field f
+    (shape (ez, ey, ex), box origin lo on grid n) at the nodes of the box
+    (new_lo, new_ext) of grid n_new."""
+    lib = load_library()
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    if f.ndim == 2:
+        f = f[None]
+    nn, npp = _grid(n), _grid(n_new)
+    dim = dim or (2 if nn[2] == 1 else 3)
+    ext = np.array([f.shape[2], f.shape[1], f.shape[0]], np.int32)
+    ne = np.ascontiguousarray(new_ext, np.int32)
+    out = np.empty(_shape(ne), np.float64)
+    lib.orc_coarse_sample_box(dim, nn, npp, float(band), np.ascontiguousarray(lo, np.int32), ext, f.ravel(),
+                              np.ascontiguousarray(new_lo, np.int32), ne, out.ravel())
     return out
 
 
