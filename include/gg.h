@@ -189,6 +189,24 @@ gg_status gg_get_iota(gg_sim *sim, int32_t *out, int64_t cap);
 gg_status gg_load_state(gg_sim *sim, const int32_t *lo, const int32_t *ext, const uint8_t *alive,
                         const double *values, const int32_t *iota);
 
+/* Grid coarsening (sec. 3, sequential optimizations: the grid spacing grows as
+ * grains vanish, keeping about the same voxels per grain; each function is
+ * projected by trilinear interpolation).  The periodic grid becomes n_new with
+ * one ratio r = n[a] / n_new[a] >= 1 on every axis of the model; new voxel i'
+ * sits at old position i' r (voxel 0 on voxel 0).  Each grain's function (-W
+ * outside its box) is interpolated linearly along x, y, z there and divided by
+ * r (lengths in new voxels); the new box is the covered cyclic interval of the
+ * positive voxels on each axis, padded by P (grains without one vanish); the
+ * function is re-initialised on it with the taxicab scheme, as in gg_create.
+ * voxel_m (the bulk term's h) grows by r; the ID-field is rebuilt as at
+ * creation.  Later steps take sigma = sqrt(2 dt) * n_new[0] voxels, so the
+ * same normalised dt is a shorter stencil.  Intermediates kept for
+ * gg_get_intermediate are dropped.
+ * Errors: GG_E_ARG (n_new outside [4P + 2, n] on an axis, ratios differ,
+ * n_new[2] != 1 in 2D; nothing changed), GG_E_CAPACITY / GG_E_NOMEM / GG_E_HIP
+ * (the state was replaced part way: the simulation is poisoned). */
+gg_status gg_coarsen(gg_sim *sim, const int32_t n_new[3]);
+
 /* Test hook: when on, each step keeps its predictor output (which = 0) and its
  * corrector output (which = 1) on the box layout the step started from; read
  * them with gg_get_intermediate (same packing as gg_get_values, with the boxes

@@ -1527,6 +1527,115 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
+// ------------------------------------------------------------ grid coarsening
+//
+// Projection onto a coarser periodic grid np (the ratio r = n / np on every
+// axis): new node i' sits at old position i' n / np = i0 + rem / np (exact
+// integer split).  A grain's value there is its old function (-W outside the
+// old box) interpolated linearly along x, then y, then z, divided by r.
+template <typename T> struct CoarsenArgs {
+    int n[3], np[3];
+    int dim;
+    T W, r;
+};
+
+template <typename T>
+__device__ T coarse_value(const T *__restrict__ f, const int *lo, const int *e, const CoarsenArgs<T> &ca, int gx,
+                          int gy, int gz) {
+    const int g[3] = {gx, gy, gz};
+    int i0[3] = {0, 0, 0};
+    T t[3] = {T(0), T(0), T(0)};
+    for (int a = 0; a < ca.dim; ++a) {
+        const long long num = (long long)g[a] * ca.n[a];
+        const long long q = num / ca.np[a];
+        i0[a] = (int)q;
+        t[a] = (T)(num - q * ca.np[a]) / (T)ca.np[a];
+    }
+    auto at = [&](int x, int y, int z) -> T {
+        const int lx = imod((long long)x - lo[0], ca.n[0]), ly = imod((long long)y - lo[1], ca.n[1]),
+                  lz = imod((long long)z - lo[2], ca.n[2]);
+        if (lx >= e[0] || ly >= e[1] || lz >= e[2]) return -ca.W;
+        return f[lx + (long long)e[0] * (ly + (long long)e[1] * lz)];
+    };
+    T c[2][2];
+    const int nzc = ca.dim == 3 ? 2 : 1;
+    for (int dz = 0; dz < nzc; ++dz)
+        for (int dy = 0; dy < 2; ++dy) {
+            const T v0 = at(i0[0], i0[1] + dy, i0[2] + dz), v1 = at(i0[0] + 1, i0[1] + dy, i0[2] + dz);
+            c[dz][dy] = (T(1) - t[0]) * v0 + t[0] * v1;
+        }
+    T v[2];
+    for (int dz = 0; dz < nzc; ++dz) v[dz] = (T(1) - t[1]) * c[dz][0] + t[1] * c[dz][1];
+    const T u = ca.dim == 3 ? (T(1) - t[2]) * v[0] + t[2] * v[1] : v[0];
+    return u / ca.r;
+}
+
+// New nodes whose value can be positive: along an axis the old box covers only
+// partly, those with old position in [lo - 1, lo + ext] (a superset); along a
+// whole axis, all.  Returns the first node (unwrapped) and the count.
+__device__ __forceinline__ void coarse_region(int lo, int ext, int N, int Np, int *first, int *count) {
+    if (ext == N) {
+        *first = 0;
+        *count = Np;
+        return;
+    }
+    const long long a = (long long)(lo - 1) * Np, b = (long long)(lo + ext) * Np;
+    const long long f0 = a >= 0 ? a / N : -((-a + N - 1) / N);  // floor
+    const long long l0 = b / N + 1;
+    long long c = l0 - f0 + 1;
+    *first = (int)f0;
+    *count = (int)(c < Np ? c : Np);
+}
+
+// Positive nodes of every grain's projection: occupancy bits per axis over the
+// new grid (the box plan's whole-axis rule then gives the new box) and a
+// positive flag in bmax.  Grid (G, y): the y blocks of a grain stride over its
+// region.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_coarsen_mark(Boxes L, const T *__restrict__ phi, CoarsenArgs<T> ca, int *bmax, unsigned *occ, int occ_words) {
+    const int k = blockIdx.x;
+    if (!L.alive[k]) return;
+    const int *lo = L.lo + 3 * k, *e = L.ext + 3 * k;
+    const T *f = phi + L.off[k];
+    int first[3], cnt[3];
+    for (int a = 0; a < 3; ++a) coarse_region(lo[a], e[a], ca.n[a], ca.np[a], &first[a], &cnt[a]);
+    // at most the new grid's voxel count (< 2^31)
+    const int total = cnt[0] * cnt[1] * cnt[2];
+    bool any = false;
+    for (int i = blockIdx.y * kBlock + threadIdx.x; i < total; i += gridDim.y * kBlock) {
+        const int yz = i / cnt[0], x = i - yz * cnt[0];
+        const int z = yz / cnt[1], y = yz - z * cnt[1];
+        const int gx = imod((long long)first[0] + x, ca.np[0]), gy = imod((long long)first[1] + y, ca.np[1]),
+                  gz = imod((long long)first[2] + z, ca.np[2]);
+        if (coarse_value(f, lo, e, ca, gx, gy, gz) > T(0)) {
+            any = true;
+            const int g[3] = {gx, gy, gz};
+            for (int a = 0; a < 3; ++a)
+                atomicOr(&occ[((long long)k * 3 + a) * occ_words + (g[a] >> 5)], 1u << (g[a] & 31));
+        }
+    }
+    if (any) atomicMax(&bmax[3 * k], 0);
+}
+
+// Projected values on the new boxes (layout Ln), before re-initialization.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_coarsen_values(Boxes Lo, const T *__restrict__ phi, Boxes Ln, T *__restrict__ out, CoarsenArgs<T> ca) {
+    const int k = blockIdx.x;
+    if (!Ln.alive[k]) return;
+    const int *lo = Lo.lo + 3 * k, *e = Lo.ext + 3 * k, *nlo = Ln.lo + 3 * k, *ne = Ln.ext + 3 * k;
+    const T *f = phi + Lo.off[k];
+    T *o = out + Ln.off[k];
+    const int total = ne[0] * ne[1] * ne[2];  // a box volume: < 2^31
+    for (int i = blockIdx.y * kBlock + threadIdx.x; i < total; i += gridDim.y * kBlock) {
+        const int yz = i / ne[0], x = i - yz * ne[0];
+        const int z = yz / ne[1], y = yz - z * ne[1];
+        o[i] = coarse_value(f, lo, e, ca, imod((long long)nlo[0] + x, ca.np[0]), imod((long long)nlo[1] + y, ca.np[1]),
+                            imod((long long)nlo[2] + z, ca.np[2]));
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_init_indicator(Boxes L, const int *__restrict__ labels, T *__restrict__ out,
                                                            GridArgs g) {

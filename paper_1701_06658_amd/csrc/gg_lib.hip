@@ -92,6 +92,7 @@ struct SimBase {
     virtual long long iota(int32_t *out, long long cap) = 0;
     virtual void load_state(const int32_t *lo, const int32_t *ext, const uint8_t *alive, const double *vals,
                             const int32_t *iota) = 0;
+    virtual void coarsen(const int32_t *np) = 0;
     virtual void sync() = 0;
     virtual int alive_count() const = 0;
     virtual gg_step_stats stats() const = 0;
@@ -237,20 +238,8 @@ template <typename T> struct Sim final : SimBase {
         voxel_m = c.voxel_m;
         gamma_max = c.gamma_max;
         headroom = c.capacity_headroom > 1.0 ? c.capacity_headroom : 1.25;
-        if (dim == 3) {
-            tdim[0] = pow2_divisor(n[0], GG_CMP_TILE_X);
-            tdim[1] = pow2_divisor(n[1], GG_CMP_TILE_Y);
-            tdim[2] = pow2_divisor(n[2], GG_CMP_TILE_Z);
-        } else {
-            tdim[0] = pow2_divisor(n[0], 32);
-            tdim[1] = pow2_divisor(n[1], 16);
-            tdim[2] = 1;
-        }
-        ntiles = 1;
-        for (int a = 0; a < 3; ++a) {
-            nt[a] = n[a] / tdim[a];
-            ntiles *= nt[a];
-        }
+        set_tiles();
+        // occupancy rows keep this width when the grid is coarsened
         occ_words = (std::max(n[0], std::max(n[1], n[2])) + 31) / 32;
         if (s) {
             stream = s;
@@ -285,6 +274,24 @@ template <typename T> struct Sim final : SimBase {
         taps_d.ensure(sizeof(T) * (2 * gg::kMaxRadius + 1));
         totals_d.ensure(sizeof(Totals));
         HIPCHECK(hipStreamSynchronize(stream));
+    }
+
+    // Global corrector / label tiles of the current grid.
+    void set_tiles() {
+        if (dim == 3) {
+            tdim[0] = pow2_divisor(n[0], GG_CMP_TILE_X);
+            tdim[1] = pow2_divisor(n[1], GG_CMP_TILE_Y);
+            tdim[2] = pow2_divisor(n[2], GG_CMP_TILE_Z);
+        } else {
+            tdim[0] = pow2_divisor(n[0], 32);
+            tdim[1] = pow2_divisor(n[1], 16);
+            tdim[2] = 1;
+        }
+        ntiles = 1;
+        for (int a = 0; a < 3; ++a) {
+            nt[a] = n[a] / tdim[a];
+            ntiles *= nt[a];
+        }
     }
 
     ~Sim() override {
@@ -811,6 +818,97 @@ template <typename T> struct Sim final : SimBase {
         if (!last) predict(Ln);
     }
 
+    // Grid coarsening onto np (validated by the caller): projection of the
+    // current phi, new boxes from its positive nodes (the box plan over a
+    // virtual layout that takes every axis whole), re-initialization as at
+    // creation, the ID-field rebuilt when the correction is on.
+    void coarsen(const int32_t *np_in) override {
+        int np[3] = {np_in[0], np_in[1], np_in[2]};
+        if (a_state < 0) throw ArgError{"no materialised state to coarsen"};
+        HIPCHECK(hipStreamSynchronize(stream));
+        const int L = cur, Ln = 1 - cur;
+        gg::CoarsenArgs<T> ca;
+        for (int a = 0; a < 3; ++a) {
+            ca.n[a] = n[a];
+            ca.np[a] = np[a];
+        }
+        ca.dim = dim;
+        ca.W = W;
+        const double r = (double)n[0] / (double)np[0];
+        ca.r = (T)r;
+        const int split = 8;  // blocks per grain
+        // virtual layout on the new grid: every axis whole, liveness of layout L
+        DBuf vlo, vext;
+        vlo.ensure(sizeof(int) * 3 * G);
+        vext.ensure(sizeof(int) * 3 * G);
+        std::vector<int> hz(3 * G, 0), he(3 * G);
+        for (int k = 0; k < G; ++k)
+            for (int a = 0; a < 3; ++a) he[3 * k + a] = np[a];
+        HIPCHECK(hipMemcpyAsync(vlo.p, hz.data(), sizeof(int) * 3 * G, hipMemcpyHostToDevice, stream));
+        HIPCHECK(hipMemcpyAsync(vext.p, he.data(), sizeof(int) * 3 * G, hipMemcpyHostToDevice, stream));
+        Boxes Lv{vlo.as<int>(), vext.as<int>(), alive[L].as<int>(), off[L].as<long long>()};
+        HIPCHECK(hipMemsetAsync(occ.p, 0, occ.cap, stream));
+        tbegin(GG_K_PLAN, 0);
+        hipLaunchKernelGGL(gg::k_coarsen_mark<T>, dim3(G, split), dim3(gg::kBlock), 0, stream, boxes_of(L),
+                           (const T *)arena[a_state].as<T>(), ca, bmax.as<int>(), occ.as<unsigned>(), occ_words);
+        gg::PlanArgs pa;
+        for (int a = 0; a < 3; ++a) pa.n[a] = np[a];
+        pa.P = P;
+        pa.occ_words = occ_words;
+        pa.G = G;
+        const int tb = 256, gb = (G + tb - 1) / tb;
+        hipLaunchKernelGGL(gg::k_plan, dim3(gb), dim3(tb), 0, stream, Lv, boxes_of(Ln), bmin.as<int>(),
+                           bmax.as<int>(), occ.as<unsigned>(), sizes.as<long long>(), pa);
+        hipLaunchKernelGGL(gg::k_scan, dim3(1), dim3(1024), 0, stream, sizes.as<long long>(), off[Ln].as<long long>(), G);
+        tend();
+        HIPCHECK(hipGetLastError());
+        // the new grid
+        for (int a = 0; a < 3; ++a) n[a] = np[a];
+        set_tiles();
+        cov_cnt.ensure(sizeof(int) * ntiles);
+        cov_off.ensure(sizeof(int) * (ntiles + 1));
+        cov_cur.ensure(sizeof(int) * (ntiles + 1));
+        voxel_m *= r;
+        items_R[0] = items_R[1] = -1;
+        have_keep = false;
+        set_identity_taps();
+        layout_meta_count(Ln, true);
+        const long long need = tot[Ln].arena;
+        const int a_f = pick(bit(a_state), need);
+        tbegin(GG_K_REINIT_XY, need);
+        hipLaunchKernelGGL(gg::k_coarsen_values<T>, dim3(G, split), dim3(gg::kBlock), 0, stream, boxes_of(L),
+                           (const T *)arena[a_state].as<T>(), boxes_of(Ln), arena[a_f].as<T>(), ca);
+        tend();
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipStreamSynchronize(stream));  // the old phi is dead only now
+        for (int a = 0; a < 4; ++a)
+            if (a != a_f) ensure_arena(a, need);
+        layout_meta_fill(Ln, true);
+        int others[3], m = 0;
+        for (int a = 0; a < 4; ++a)
+            if (a != a_f) others[m++] = a;
+        launch_reinit(Ln, Ln, arena[a_f].as<T>(), arena[others[0]].as<T>(), arena[others[1]].as<T>(),
+                      arena[others[2]].as<T>(), nullptr, nullptr, false);
+        cur = Ln;
+        a_state = others[1];
+        a_T = a_psi = -1;
+        T_R = psi_R = -1;
+        if (physics) {
+            ensure_iota(0, need);
+            ensure_iota(1, need);
+            iota_cur = 0;
+            hipLaunchKernelGGL(gg::k_compare<T>, dim3(grid_of(gg::xcd_grid(ntiles))), dim3(gg::kBlock), 0, stream,
+                               boxes_of(Ln), cov_off.as<int>(), cov_list.as<int>(), arena[a_state].as<T>(),
+                               (T *)nullptr, iota_a[0].as<int>(), bmin.as<int>(), bmax.as<int>(),
+                               occ.as<unsigned>(), tile_args(), W, 1);
+            HIPCHECK(hipGetLastError());
+        }
+        HIPCHECK(hipStreamSynchronize(stream));
+        resolve_spans();
+        vlo.release();
+        vext.release();
+    }
+
     void keep_copy(int L, const T *psi, const T *phic) {
         const long long m = tot[L].arena;
         keep_psi.ensure(sizeof(T) * std::max<long long>(m, 1));
@@ -993,6 +1091,7 @@ struct gg_sim {
     bool poisoned = false;
     int G = 0;
     int n[3] = {0, 0, 0};
+    int dim = 3, P = 1;
     int device = 0;
 };
 
@@ -1097,6 +1196,8 @@ gg_status gg_create(const gg_config *cfg, const int32_t *labels, int32_t n_grain
     if (!s) return fail(nullptr, GG_E_NOMEM, "host allocation failed");
     s->G = n_grains;
     for (int a = 0; a < 3; ++a) s->n[a] = cfg->n[a];
+    s->dim = cfg->dim;
+    s->P = (int)std::ceil(cfg->band);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
     s->device = dev;
@@ -1214,6 +1315,28 @@ gg_status gg_load_state(gg_sim *sim, const int32_t *lo, const int32_t *ext, cons
         sim->impl->load_state(lo, ext, alive, values, iota);
         return GG_OK;
     });
+}
+
+gg_status gg_coarsen(gg_sim *sim, const int32_t n_new[3]) {
+    if (!sim || !n_new) return fail(sim, GG_E_ARG, "NULL argument");
+    const int dim = sim->dim;
+    if (dim == 2 && n_new[2] != 1) return fail(sim, GG_E_ARG, "2D requires n_new[2] == 1");
+    for (int a = 0; a < dim; ++a) {
+        if (n_new[a] < 4 * sim->P + 2 || n_new[a] > sim->n[a])
+            return fail(sim, GG_E_ARG, "n_new must lie in [4P + 2, n] on every axis");
+        if ((long long)n_new[a] * sim->n[0] != (long long)n_new[0] * sim->n[a])
+            return fail(sim, GG_E_ARG, "n_new must keep the ratio n / n_new equal on every axis");
+    }
+    gg_status st = guarded(sim, [&]() {
+        sim->impl->coarsen(n_new);
+        return GG_OK;
+    });
+    if (st == GG_OK) {
+        for (int a = 0; a < 3; ++a) sim->n[a] = n_new[a];
+    } else if (st != GG_E_ARG && st != GG_E_POISONED) {
+        sim->poisoned = true;  // the state was replaced part way
+    }
+    return st;
 }
 
 gg_status gg_keep_intermediates(gg_sim *sim, int32_t on) {

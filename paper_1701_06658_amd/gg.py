@@ -25,7 +25,7 @@ STATUS = {0: "GG_OK", 1: "GG_E_ARG", 2: "GG_E_NOMEM", 3: "GG_E_HIP", 4: "GG_E_CA
 EXPORTS = ["gg_create", "gg_step", "gg_sync", "gg_grain_count", "gg_grain_volumes", "gg_labels",
            "gg_stats", "gg_get_boxes", "gg_get_values", "gg_get_iota", "gg_load_state",
            "gg_keep_intermediates", "gg_get_intermediate", "gg_status_str", "gg_last_error",
-           "gg_destroy", "gg_version", "gg_profile", "gg_get_kernel_times"]
+           "gg_destroy", "gg_version", "gg_profile", "gg_get_kernel_times", "gg_coarsen"]
 
 KERNEL_CLASSES = ["conv_xy", "conv_z", "compare", "reinit_xy", "reinit_z", "plan", "volume", "reinit_sweep"]
 
@@ -78,6 +78,7 @@ def load_library(path=LIB_PATH):
         "gg_get_values": (i32, [vp, vp, i64]),
         "gg_get_iota": (i32, [vp, vp, i64]),
         "gg_load_state": (i32, [vp, vp, vp, vp, vp, vp]),
+        "gg_coarsen": (i32, [vp, vp]),
         "gg_keep_intermediates": (i32, [vp, i32]),
         "gg_get_intermediate": (i32, [vp, i32, vp, i64, vp, vp, vp, vp, i64]),
         "gg_status_str": (C.c_char_p, [i32]),
@@ -157,6 +158,12 @@ class Simulation:
 
     def sync(self):
         self._check(self._lib.gg_sync(self._h))
+
+    def coarsen(self, n_new):
+        """Project the state onto the coarser periodic grid n_new = (nx, ny, nz) (nz = 1 in 2D)."""
+        nn = np.ascontiguousarray([int(v) for v in n_new] + [1] * (3 - len(n_new)), dtype=np.int32)
+        self._check(self._lib.gg_coarsen(self._h, _ptr(nn)))
+        self.n = (int(nn[0]), int(nn[1]), int(nn[2]))
 
     def alive_count(self):
         v = C.c_int32()

@@ -95,3 +95,9 @@ def test_null_handles(lib):
     assert lib.gg_step(None, 1e-3, 1) == 1
     assert lib.gg_sync(None) == 1
     lib.gg_destroy(None)
+
+
+def test_coarsen_rejects_null_simulation(lib):
+    n = np.array([32, 32, 1], np.int32)
+    lib.gg_coarsen.argtypes = [C.c_void_p, C.c_void_p]
+    assert lib.gg_coarsen(None, n.ctypes.data_as(C.c_void_p)) == 1
