@@ -68,6 +68,10 @@ int orc_set_grain(orc_sim *s, int k, int alive, const int32_t lo[3], const int32
 
 int orc_volumes(const orc_sim *s, double *out);      /* G values, 0 if extinct */
 int orc_labels(const orc_sim *s, int32_t *out);       /* prod(n) values */
+/* Interface area of every grain, sum of |grad clamp(phi + 1/2, 0, 1)| (central
+ * differences), and the same weighted by the Read-Shockley energy of the pair
+ * (k, iota) when the misorientation weights are on (weighted may be NULL). */
+int orc_grain_areas(const orc_sim *s, double *area, double *weighted);
 
 /* Stand-alone pieces used by the pinning tests. */
 int orc_convolve_box(int dim, const int32_t n[3], double band, double sigma,

@@ -61,6 +61,7 @@ def load_library():
     lib.orc_euclid_sweeps.argtypes = [C.c_int, C.c_double]
     lib.orc_set_redistance.argtypes = [C.c_void_p, C.c_int]
     lib.orc_coarsen.argtypes = [C.c_void_p, _i32p]
+    lib.orc_grain_areas.argtypes = [C.c_void_p, _f64p, _f64p]
     lib.orc_coarse_sample_box.argtypes = [C.c_int, _i32p, _i32p, C.c_double, _i32p, _i32p, _f64p, _i32p, _i32p,
                                           _f64p]
     lib.orc_misorientation_deg.restype = C.c_double
@@ -196,6 +197,13 @@ class Oracle:
         out = np.zeros(self.G, np.float64)
         self._lib.orc_volumes(self._p, out)
         return out
+
+    def areas(self):
+        """(area, weighted): per-grain interface areas and Read-Shockley-weighted areas."""
+        a = np.zeros(self.G, np.float64)
+        w = np.zeros(self.G, np.float64)
+        self._lib.orc_grain_areas(self._p, a, w)
+        return a, w
 
     def labels(self):
         out = np.empty(int(np.prod(self.n)), np.int32)
