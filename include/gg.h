@@ -138,6 +138,17 @@ gg_status gg_grain_count(gg_sim *sim, int32_t *alive);
  * by grain id (0 for extinct grains); out: host, cap >= n_grains. */
 gg_status gg_grain_volumes(gg_sim *sim, double *out, int64_t cap);
 
+/* Interface areas for the energy bookkeeping (energy functional, Eq.
+ * Energyfunctional): area[k] = sum over grain k's box of |grad H(phi_k)|, H =
+ * clamp(phi + 1/2, 0, 1) (the volume's smoothed Heaviside), central differences
+ * with -W outside the box, in FP64 and voxel^(D-1) units (by the coarea formula
+ * the interface area, whatever the slope of phi).  weighted (may be NULL): the
+ * same sum with each voxel weighted by the Read-Shockley energy of the pair
+ * (k, ID-field) under GG_PHYS_MISORIENTATION (1 otherwise).  The boundary
+ * energy is (1/2) sum_k weighted[k] gamma_max h^(D-1); the bulk energy is
+ * sum_k E_k V_k h^D.  Host arrays, cap >= n_grains (0 for extinct grains). */
+gg_status gg_grain_areas(gg_sim *sim, double *area, double *weighted, int64_t cap);
+
 /* Voxel labels: argmax over the grains whose box covers the voxel of their
  * function (ties to the lowest id); out: prod(n) int32, x fastest, host memory,
  * or device memory on the simulation's device when out_is_device != 0 (then

@@ -560,15 +560,17 @@ template <typename T> __device__ inline T misorientation_deg(const T *qa, const 
     return T(2) * dev_acos(best) * T(57.295779513082320877);
 }
 
+// Read-Shockley boundary energy, normalised to 1 at and above theta_c.
+template <typename T> __device__ inline T read_shockley(T theta, T theta_c) {
+    if (theta >= theta_c) return T(1);
+    if (theta <= T(0)) return T(0);
+    const T r = theta / theta_c;
+    return r * (T(1) - dev_log(r));
+}
+
 // Pair weight w = mobility * Read-Shockley energy (both normalised to (0, 1]).
 template <typename T> __device__ inline T pair_weight(T theta, T theta_c, T *mob) {
-    T g;
-    if (theta >= theta_c) g = T(1);
-    else if (theta <= T(0)) g = T(0);
-    else {
-        const T r = theta / theta_c;
-        g = r * (T(1) - dev_log(r));
-    }
+    const T g = read_shockley(theta, theta_c);
     const T u = theta / T(15);
     const T u3 = u * u * u;
     const T mu = T(1) - T(0.99) * dev_exp(T(-5) * (u3 * u3 * u3));
@@ -1634,6 +1636,85 @@ __global__ void __launch_bounds__(kBlock)
         o[i] = coarse_value(f, lo, e, ca, imod((long long)nlo[0] + x, ca.np[0]), imod((long long)nlo[1] + y, ca.np[1]),
                             imod((long long)nlo[2] + z, ca.np[2]));
     }
+}
+
+// ---------------------------------------------------------- interface areas
+//
+// Interface area of grain k: the sum over its box of |grad H(phi_k)|, H =
+// clamp(phi + 1/2, 0, 1) (the volume's smoothed Heaviside), central
+// differences with -W outside the box, squares summed over the axes in order,
+// all in FP64; `weighted` multiplies each voxel by the Read-Shockley energy of
+// the pair (k, iota) when the misorientation weights are on.  Grid (G, split):
+// block y of grain k writes its partial sums to part[k * split + y] (areas) and
+// part[(G + k) * split + y] (weighted).
+struct AreaArgs {
+    int mode;             // GG_PHYS_* bits
+    double theta_c_deg;
+    int split, G;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+    k_areas(Boxes L, const T *__restrict__ phi, const int *__restrict__ iota, const T *__restrict__ quat, AreaArgs aa,
+            double *__restrict__ part, T W, GridArgs g) {
+    __shared__ double red[kBlock / 64];
+    const int k = blockIdx.x;
+    double acc = 0.0, accw = 0.0;
+    if (L.alive[k]) {
+        const int ex = L.ext[3 * k], ey = L.ext[3 * k + 1], ez = L.ext[3 * k + 2];
+        const T *f = phi + L.off[k];
+        const int *io = iota ? iota + L.off[k] : nullptr;
+        const int total = ex * ey * ez;  // a box volume: < 2^31
+        const int e3[3] = {ex, ey, ez};
+        int jc = -2;
+        double gam_c = 1.0;
+        for (int i = blockIdx.y * kBlock + threadIdx.x; i < total; i += gridDim.y * kBlock) {
+            const int yz = i / ex, x = i - yz * ex;
+            const int z = yz / ey, y = yz - z * ey;
+            const int c[3] = {x, y, z};
+            double gg = 0.0;
+            for (int a = 0; a < g.dim; ++a) {
+                double h2[2];
+                for (int s = 0; s < 2; ++s) {
+                    int q[3] = {c[0], c[1], c[2]};
+                    q[a] = axis_map(c[a] + (s ? 1 : -1), e3[a], g.n[a]);
+                    const double v = q[a] < 0 ? -(double)W : (double)f[q[0] + ex * (q[1] + ey * q[2])];
+                    const double hv = v + 0.5;
+                    h2[s] = hv < 0.0 ? 0.0 : (hv > 1.0 ? 1.0 : hv);
+                }
+                const double gd = (h2[1] - h2[0]) * 0.5;
+                gg = gg + gd * gd;
+            }
+            const double m = sqrt(gg);
+            acc = acc + m;
+            double gam = 1.0;
+            if (io && (aa.mode & 1) && m > 0.0) {
+                const int j = io[i];
+                if (j >= 0) {
+                    if (j != jc) {
+                        jc = j;
+                        gam_c = (double)read_shockley<T>(misorientation_deg<T>(quat + 4LL * k, quat + 4LL * j),
+                                                         (T)aa.theta_c_deg);
+                    }
+                    gam = gam_c;
+                }
+            }
+            accw = accw + m * gam;
+        }
+    }
+    const double s0 = block_sum(acc, red);
+    if (threadIdx.x == 0) part[(long long)k * aa.split + blockIdx.y] = s0;
+    const double s1 = block_sum(accw, red);
+    if (threadIdx.x == 0) part[((long long)aa.G + k) * aa.split + blockIdx.y] = s1;
+}
+
+// out[i] = sum of the `split` partials of row i, in order (rows: 2G).
+__global__ void k_sum_rows(const double *__restrict__ part, double *__restrict__ out, int rows, int split) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    double s = 0.0;
+    for (int j = 0; j < split; ++j) s += part[(long long)i * split + j];
+    out[i] = s;
 }
 
 template <typename T>

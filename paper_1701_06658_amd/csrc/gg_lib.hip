@@ -93,6 +93,7 @@ struct SimBase {
     virtual void load_state(const int32_t *lo, const int32_t *ext, const uint8_t *alive, const double *vals,
                             const int32_t *iota) = 0;
     virtual void coarsen(const int32_t *np) = 0;
+    virtual void areas(double *area, double *weighted) = 0;
     virtual void sync() = 0;
     virtual int alive_count() const = 0;
     virtual gg_step_stats stats() const = 0;
@@ -909,6 +910,31 @@ template <typename T> struct Sim final : SimBase {
         vext.release();
     }
 
+    // Interface areas of the current phi (FP64 per-grain sums, fixed order).
+    void areas(double *area, double *weighted) override {
+        if (a_state < 0) throw ArgError{"no materialised state"};
+        const int split = 8;
+        DBuf part, sums;
+        part.ensure(sizeof(double) * 2 * (size_t)G * split);
+        sums.ensure(sizeof(double) * 2 * (size_t)G);
+        gg::AreaArgs aa;
+        aa.mode = physics;
+        aa.theta_c_deg = theta_c;
+        aa.split = split;
+        aa.G = G;
+        hipLaunchKernelGGL(gg::k_areas<T>, dim3(G, split), dim3(gg::kBlock), 0, stream, boxes_of(cur),
+                           (const T *)arena[a_state].as<T>(), iota_now(), (const T *)quat_d.as<T>(), aa,
+                           part.as<double>(), W, grid_args());
+        hipLaunchKernelGGL(gg::k_sum_rows, dim3((2 * G + 255) / 256), dim3(256), 0, stream, part.as<double>(),
+                           sums.as<double>(), 2 * G, split);
+        HIPCHECK(hipGetLastError());
+        std::vector<double> h(2 * (size_t)G);
+        HIPCHECK(hipMemcpyAsync(h.data(), sums.p, sizeof(double) * 2 * G, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+        std::memcpy(area, h.data(), sizeof(double) * G);
+        if (weighted) std::memcpy(weighted, h.data() + G, sizeof(double) * G);
+    }
+
     void keep_copy(int L, const T *psi, const T *phic) {
         const long long m = tot[L].arena;
         keep_psi.ensure(sizeof(T) * std::max<long long>(m, 1));
@@ -1313,6 +1339,15 @@ gg_status gg_load_state(gg_sim *sim, const int32_t *lo, const int32_t *ext, cons
     if (!sim || !lo || !ext || !alive || !values) return fail(sim, GG_E_ARG, "NULL argument");
     return guarded(sim, [&]() {
         sim->impl->load_state(lo, ext, alive, values, iota);
+        return GG_OK;
+    });
+}
+
+gg_status gg_grain_areas(gg_sim *sim, double *area, double *weighted, int64_t cap) {
+    if (!sim || !area) return fail(sim, GG_E_ARG, "NULL argument");
+    if (cap < sim->G) return fail(sim, GG_E_SMALLBUF, "cap < n_grains");
+    return guarded(sim, [&]() {
+        sim->impl->areas(area, weighted);
         return GG_OK;
     });
 }

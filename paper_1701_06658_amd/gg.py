@@ -25,7 +25,7 @@ STATUS = {0: "GG_OK", 1: "GG_E_ARG", 2: "GG_E_NOMEM", 3: "GG_E_HIP", 4: "GG_E_CA
 EXPORTS = ["gg_create", "gg_step", "gg_sync", "gg_grain_count", "gg_grain_volumes", "gg_labels",
            "gg_stats", "gg_get_boxes", "gg_get_values", "gg_get_iota", "gg_load_state",
            "gg_keep_intermediates", "gg_get_intermediate", "gg_status_str", "gg_last_error",
-           "gg_destroy", "gg_version", "gg_profile", "gg_get_kernel_times", "gg_coarsen"]
+           "gg_destroy", "gg_version", "gg_profile", "gg_get_kernel_times", "gg_coarsen", "gg_grain_areas"]
 
 KERNEL_CLASSES = ["conv_xy", "conv_z", "compare", "reinit_xy", "reinit_z", "plan", "volume", "reinit_sweep"]
 
@@ -79,6 +79,7 @@ def load_library(path=LIB_PATH):
         "gg_get_iota": (i32, [vp, vp, i64]),
         "gg_load_state": (i32, [vp, vp, vp, vp, vp, vp]),
         "gg_coarsen": (i32, [vp, vp]),
+        "gg_grain_areas": (i32, [vp, vp, vp, i64]),
         "gg_keep_intermediates": (i32, [vp, i32]),
         "gg_get_intermediate": (i32, [vp, i32, vp, i64, vp, vp, vp, vp, i64]),
         "gg_status_str": (C.c_char_p, [i32]),
@@ -158,6 +159,13 @@ class Simulation:
 
     def sync(self):
         self._check(self._lib.gg_sync(self._h))
+
+    def areas(self):
+        """(area, weighted): per-grain interface areas and Read-Shockley-weighted areas (FP64)."""
+        a = np.zeros(self.G, np.float64)
+        w = np.zeros(self.G, np.float64)
+        self._check(self._lib.gg_grain_areas(self._h, _ptr(a), _ptr(w), self.G))
+        return a, w
 
     def coarsen(self, n_new):
         """Project the state onto the coarser periodic grid n_new = (nx, ny, nz) (nz = 1 in 2D)."""
