@@ -94,6 +94,29 @@ def run_gpu(cfg, precision, steps, warmup, copy_probe=False, redistance="taxicab
     return out
 
 
+def run_coarsen(cfg, precision, warmup, n_new):
+    """One gg_coarsen of the workload after `warmup` steps: wall time with the
+    stream synchronised on both sides, and the grain voxels before and after."""
+    import paper_1701_06658_amd as gg
+    sim = gg.Simulation(cfg["labels"], cfg["W"], G=cfg["G"], precision=precision)
+    sim.step(cfg["dt"], max(warmup, 1))
+    sim.sync()
+    before = sim.stats()["grain_voxels"]
+    nn = (n_new, n_new, n_new) if cfg["dim"] == 3 else (n_new, n_new, 1)
+    t0 = time.perf_counter()
+    sim.coarsen(nn)
+    sim.sync()
+    ms = 1e3 * (time.perf_counter() - t0)
+    # one step on the new grid: its grain voxels are the coarsened layout's
+    sim.step(cfg["sigma"] ** 2 / (2.0 * n_new ** 2), 1)
+    after = sim.stats()["grain_voxels"]
+    alive = sim.alive_count()
+    sim.close()
+    log(f"[bench] coarsen {cfg['n'][0]} -> {n_new}: {ms:.2f} ms, {before} -> {after} grain voxels")
+    return dict(n_new=n_new, ms=ms, grain_voxels_before=before, grain_voxels_after=after, alive_after=alive,
+                gv_per_s=(before + after) / (ms * 1e-3))
+
+
 def source_digest():
     """SHA-256 of the kernel sources: a recorded counter figure applies only to them."""
     import hashlib
@@ -180,6 +203,8 @@ def main():
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--precision", default=None, help="fp32 (mixed) or fp64 (plain)")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--coarsen", type=int, default=0, metavar="N_NEW",
+                    help="also time one grid coarsening of the workload onto N_NEW voxels per axis")
     ap.add_argument("--redistance", default="taxicab", choices=["taxicab", "euclid"],
                     help="re-initialization scheme: the method's taxicab one or the Euclidean variant")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -228,6 +253,8 @@ def main():
                                   roofline=roofline(plain, 8), mixed_speedup=main_res["value"] / plain["value"])
     if args.copy_probe:
         line["copy_probe"] = main_res["copy_probe"]
+    if args.coarsen:
+        line["coarsen"] = run_coarsen(cfg, precision, args.warmup, args.coarsen)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.config)
     print(json.dumps(line), flush=True)
