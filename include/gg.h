@@ -29,6 +29,7 @@
 #ifndef GG_H
 #define GG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -51,8 +52,13 @@ typedef enum {
 } gg_status;
 
 typedef enum {
-    GG_FP64 = 0, /* plain path: FP64 storage and arithmetic                      */
-    GG_FP32 = 1  /* mixed path: FP32 storage/arithmetic, FP64 volume reductions  */
+    GG_FP64 = 0,       /* plain path: FP64 storage and arithmetic                */
+    GG_FP32 = 1,       /* mixed path: FP32 storage/arithmetic, FP64 reductions   */
+    GG_MIXED_BF16 = 2, /* BF16 convolution operands with FP32 accumulation: not
+                          built (GG_E_UNSUPPORTED); the FP32 path is bound by
+                          vector-ALU issue, not by bytes, so narrower storage of
+                          the predicted function would not shorten the step     */
+    GG_MIXED_FP16 = 3  /* FP16 likewise: GG_E_UNSUPPORTED                        */
 } gg_precision;
 
 /* Re-initialization scheme of gg_step (gg_create always uses the taxicab one
@@ -107,7 +113,21 @@ typedef struct {
     int64_t capacity;       /* device arena capacity in values                      */
     double superposition;   /* grain_voxels / prod(n)                               */
     double last_step_ms;    /* device time of the last gg_step call / its n_steps   */
+    int32_t n[3];           /* current periodic grid (changes with gg_coarsen)      */
+    int32_t dim;
 } gg_step_stats;
+
+/* Device memory of a simulation through the caller's allocator (e.g. a caching
+ * allocator): alloc(bytes, stream, user) returns device memory on the
+ * simulation's device, usable in stream order on `stream`, or NULL; free(p,
+ * stream, user) takes back a block alloc returned.  The library synchronises
+ * the device before it frees or replaces a buffer.  Used for every device
+ * buffer of the simulation, from gg_create to gg_destroy. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *user);
+    void (*free)(void *p, void *stream, void *user);
+    void *user;
+} gg_allocator;
 
 /* Create a simulation from a label field (host, prod(n) int32, x fastest, values
  * in [0, n_grains)); sec. 3.1: one grain object per cell of the input tessellation.
@@ -115,11 +135,15 @@ typedef struct {
  * axis, padded by P; its function is the re-initialised +-1/2 indicator.
  * quat: 4*n_grains doubles (w,x,y,z) or NULL; energy_density: n_grains doubles
  * in J/m^3 or NULL (required by the matching physics bits).
- * hip_stream: a hipStream_t or NULL.  On success *out owns the simulation.
- * Errors: GG_E_ARG (bad config/labels), GG_E_NODEVICE, GG_E_NOMEM, GG_E_HIP. */
+ * hip_stream: a hipStream_t or NULL (the library creates its own).  allocator:
+ * NULL (hipMalloc / hipFree) or the caller's allocator, copied; it needs a
+ * non-NULL hip_stream.  On success *out owns the simulation.
+ * Errors: GG_E_ARG (bad config/labels/allocator), GG_E_UNSUPPORTED (a
+ * precision this build does not implement), GG_E_NODEVICE, GG_E_NOMEM,
+ * GG_E_HIP. */
 gg_status gg_create(const gg_config *cfg, const int32_t *labels, int32_t n_grains,
                     const double *quat, const double *energy_density, void *hip_stream,
-                    gg_sim **out);
+                    const gg_allocator *allocator, gg_sim **out);
 
 /* Advance n_steps timesteps of normalised length dt (Algorithm 1): Gaussian
  * width sigma = sqrt(2 dt) * n[0] voxels (heat kernel of Eq. Heatequation),
@@ -217,6 +241,26 @@ gg_status gg_load_state(gg_sim *sim, const int32_t *lo, const int32_t *ext, cons
  * n_new[2] != 1 in 2D; nothing changed), GG_E_CAPACITY / GG_E_NOMEM / GG_E_HIP
  * (the state was replaced part way: the simulation is poisoned). */
 gg_status gg_coarsen(gg_sim *sim, const int32_t n_new[3]);
+
+/* One grain's box (lo, ext; all 0 for an extinct grain) and its values as
+ * doubles, x fastest (host memory).  With out == NULL (or cap too small) only
+ * the box is written: the call then returns GG_OK (out == NULL) or
+ * GG_E_SMALLBUF, and prod(ext) values are needed.  Errors: GG_E_ARG (id out of
+ * range). */
+gg_status gg_grain_sdf(gg_sim *sim, int32_t id, int32_t lo[3], int32_t ext[3], double *out, int64_t cap);
+
+/* Checkpoint / resume.  gg_save writes the state to a file: grid, boxes,
+ * liveness, values in the stored precision, the ID-field (with the predictor
+ * correction), volumes and step counters.  gg_load replaces the state of a
+ * simulation created with the same dim, n_grains, precision, band, physics
+ * and re-initialization scheme (the grid may differ: a coarsened run); per-grain
+ * physics inputs stay those given to gg_create.  The steps that follow a
+ * gg_load are identical to those that would have followed the gg_save.
+ * Errors: GG_E_ARG (cannot open or write the file, not a checkpoint of this
+ * library, a different configuration, a corrupt file; nothing changed),
+ * GG_E_NOMEM, GG_E_HIP. */
+gg_status gg_save(gg_sim *sim, const char *path);
+gg_status gg_load(gg_sim *sim, const char *path);
 
 /* Test hook: when on, each step keeps its predictor output (which = 0) and its
  * corrector output (which = 1) on the box layout the step started from; read

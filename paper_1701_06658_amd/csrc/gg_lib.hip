@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <type_traits>
 #include <memory>
 #include <tuple>
 #include <string>
@@ -50,28 +51,52 @@ struct MemError {
     std::string msg;
 };
 
-// A device buffer with a capacity in bytes.
+// The caller's allocator of the simulation being served on this thread (set
+// around every library call; NULL: hipMalloc / hipFree) and its stream.
+thread_local const gg_allocator *t_alloc = nullptr;
+thread_local void *t_alloc_stream = nullptr;
+
+// A device buffer with a capacity in bytes, owned (freed when it goes out of
+// scope) and freed through the allocator that allocated it.
 struct DBuf {
     void *p = nullptr;
     size_t cap = 0;
+    const gg_allocator *al = nullptr;
+    void *al_stream = nullptr;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf() { release(); }
     void ensure(size_t bytes) {
         if (bytes <= cap && p) return;
         if (p) (void)hipDeviceSynchronize();  // no pending work may still use the old buffer
         release();
         size_t b = std::max<size_t>(bytes, 256);
-        hipError_t e = hipMalloc(&p, b);
-        if (e != hipSuccess) {
-            p = nullptr;
-            cap = 0;
-            (void)hipGetLastError();
-            throw MemError{"device allocation of " + std::to_string(b) + " bytes failed"};
+        if (t_alloc) {
+            p = t_alloc->alloc(b, t_alloc_stream, t_alloc->user);
+            if (!p) throw MemError{"the caller's allocator returned NULL for " + std::to_string(b) + " bytes"};
+            al = t_alloc;
+            al_stream = t_alloc_stream;
+        } else {
+            hipError_t e = hipMalloc(&p, b);
+            if (e != hipSuccess) {
+                p = nullptr;
+                cap = 0;
+                (void)hipGetLastError();
+                throw MemError{"device allocation of " + std::to_string(b) + " bytes failed"};
+            }
+            al = nullptr;
         }
         cap = b;
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (al) al->free(p, al_stream, al->user);
+            else (void)hipFree(p);
+        }
         p = nullptr;
         cap = 0;
+        al = nullptr;
     }
     template <typename U> U *as() const { return reinterpret_cast<U *>(p); }
 };
@@ -94,6 +119,10 @@ struct SimBase {
                             const int32_t *iota) = 0;
     virtual void coarsen(const int32_t *np) = 0;
     virtual void areas(double *area, double *weighted) = 0;
+    virtual long long grain_sdf(int k, int32_t *lo, int32_t *ext, double *out, long long cap) = 0;
+    virtual void save(FILE *f) = 0;
+    virtual void load(FILE *f) = 0;
+    virtual void grid(int32_t *n) const = 0;
     virtual void sync() = 0;
     virtual int alive_count() const = 0;
     virtual gg_step_stats stats() const = 0;
@@ -108,6 +137,7 @@ template <typename T> struct Sim final : SimBase {
     int dim, G, n[3], P, K;
     int redist, K_euclid;  // re-initialization scheme of the steps; its Jacobi sweep count
     T W;
+    double band_d;  // W as given
     int physics;
     double theta_c, voxel_m, gamma_max, headroom;
     int tdim[3], nt[3], ntiles, occ_words;
@@ -227,6 +257,7 @@ template <typename T> struct Sim final : SimBase {
         G = G_;
         for (int a = 0; a < 3; ++a) n[a] = c.n[a];
         W = (T)c.band;
+        band_d = c.band;
         P = (int)std::ceil(c.band);
         K = P;
         redist = c.redistance;
@@ -293,6 +324,18 @@ template <typename T> struct Sim final : SimBase {
             nt[a] = n[a] / tdim[a];
             ntiles *= nt[a];
         }
+    }
+
+    // Switch to the periodic grid np (coarsening, checkpoint of a coarsened run).
+    void set_grid(const int *np) {
+        for (int a = 0; a < 3; ++a) n[a] = np[a];
+        set_tiles();
+        cov_cnt.ensure(sizeof(int) * ntiles);
+        cov_off.ensure(sizeof(int) * (ntiles + 1));
+        cov_cur.ensure(sizeof(int) * (ntiles + 1));
+    }
+    void grid(int32_t *out) const override {
+        for (int a = 0; a < 3; ++a) out[a] = n[a];
     }
 
     ~Sim() override {
@@ -864,11 +907,7 @@ template <typename T> struct Sim final : SimBase {
         tend();
         HIPCHECK(hipGetLastError());
         // the new grid
-        for (int a = 0; a < 3; ++a) n[a] = np[a];
-        set_tiles();
-        cov_cnt.ensure(sizeof(int) * ntiles);
-        cov_off.ensure(sizeof(int) * (ntiles + 1));
-        cov_cur.ensure(sizeof(int) * (ntiles + 1));
+        set_grid(np);
         voxel_m *= r;
         items_R[0] = items_R[1] = -1;
         have_keep = false;
@@ -933,6 +972,154 @@ template <typename T> struct Sim final : SimBase {
         HIPCHECK(hipStreamSynchronize(stream));
         std::memcpy(area, h.data(), sizeof(double) * G);
         if (weighted) std::memcpy(weighted, h.data() + G, sizeof(double) * G);
+    }
+
+    // One grain's box and values (as doubles); returns the value count, or
+    // -count when cap is too small (nothing written), 0 for an extinct grain.
+    long long grain_sdf(int k, int32_t *lo_o, int32_t *ext_o, double *out, long long cap) override {
+        int l[3], e[3], al = 0;
+        long long o = 0;
+        HIPCHECK(hipMemcpyAsync(l, lo[cur].as<int>() + 3 * k, sizeof(int) * 3, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipMemcpyAsync(e, ext[cur].as<int>() + 3 * k, sizeof(int) * 3, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipMemcpyAsync(&al, alive[cur].as<int>() + k, sizeof(int), hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipMemcpyAsync(&o, off[cur].as<long long>() + k, sizeof(long long), hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+        if (!al) {
+            for (int a = 0; a < 3; ++a) lo_o[a] = ext_o[a] = 0;
+            return 0;
+        }
+        for (int a = 0; a < 3; ++a) {
+            lo_o[a] = l[a];
+            ext_o[a] = e[a];
+        }
+        const long long m = (long long)e[0] * e[1] * e[2];
+        if (cap < m || !out) return -m;
+        if (a_state < 0) throw ArgError{"no materialised state"};
+        DBuf tmp;
+        tmp.ensure(sizeof(double) * m);
+        hipLaunchKernelGGL((gg::k_convert<T, double>), dim3(256), dim3(256), 0, stream, arena[a_state].as<T>() + o,
+                           tmp.as<double>(), m);
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipMemcpyAsync(out, tmp.p, sizeof(double) * m, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+        return m;
+    }
+
+    // ---------------------------------------------------------- checkpoint
+    struct CkptHeader {
+        char magic[8];
+        int32_t version, dim, n[3], G, precision, redistance, physics, has_iota, pad;
+        double band, theta_c, voxel_m, gamma_max;
+        int64_t steps, total_gv, values;
+    };
+    static constexpr char kMagic[8] = {'G', 'G', 'C', 'K', 'P', 'T', 0, 1};
+    int precision_code() const { return sizeof(T) == 8 ? GG_FP64 : GG_FP32; }
+
+    static void put(FILE *f, const void *p, size_t bytes) {
+        if (bytes && std::fwrite(p, 1, bytes, f) != bytes) throw ArgError{"checkpoint write failed"};
+    }
+    static void get(FILE *f, void *p, size_t bytes) {
+        if (bytes && std::fread(p, 1, bytes, f) != bytes) throw ArgError{"checkpoint is truncated"};
+    }
+
+    void save(FILE *f) override {
+        if (a_state < 0) throw ArgError{"no materialised state"};
+        HIPCHECK(hipStreamSynchronize(stream));
+        const long long m = tot[cur].arena;
+        CkptHeader h{};
+        std::memcpy(h.magic, kMagic, 8);
+        h.version = 1;
+        h.dim = dim;
+        for (int a = 0; a < 3; ++a) h.n[a] = n[a];
+        h.G = G;
+        h.precision = precision_code();
+        h.redistance = redist;
+        h.physics = physics;
+        h.has_iota = physics ? 1 : 0;
+        h.band = band_d;
+        h.theta_c = theta_c;
+        h.voxel_m = voxel_m;
+        h.gamma_max = gamma_max;
+        h.steps = steps_done;
+        h.total_gv = total_gv;
+        h.values = m;
+        std::vector<int> l(3 * G), e(3 * G), al(G), io;
+        std::vector<T> v(std::max<long long>(m, 1));
+        std::vector<double> vo(G);
+        HIPCHECK(hipMemcpyAsync(l.data(), lo[cur].p, sizeof(int) * 3 * G, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipMemcpyAsync(e.data(), ext[cur].p, sizeof(int) * 3 * G, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipMemcpyAsync(al.data(), alive[cur].p, sizeof(int) * G, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipMemcpyAsync(v.data(), arena[a_state].p, sizeof(T) * m, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipMemcpyAsync(vo.data(), vol.p, sizeof(double) * G, hipMemcpyDeviceToHost, stream));
+        if (h.has_iota) {
+            io.resize(std::max<long long>(m, 1));
+            HIPCHECK(hipMemcpyAsync(io.data(), iota_now(), sizeof(int) * m, hipMemcpyDeviceToHost, stream));
+        }
+        HIPCHECK(hipStreamSynchronize(stream));
+        put(f, &h, sizeof(h));
+        put(f, l.data(), sizeof(int) * 3 * G);
+        put(f, e.data(), sizeof(int) * 3 * G);
+        put(f, al.data(), sizeof(int) * G);
+        put(f, v.data(), sizeof(T) * m);
+        if (h.has_iota) put(f, io.data(), sizeof(int) * m);
+        put(f, vo.data(), sizeof(double) * G);
+    }
+
+    void load(FILE *f) override {
+        CkptHeader h;
+        get(f, &h, sizeof(h));
+        if (std::memcmp(h.magic, kMagic, 8) != 0 || h.version != 1) throw ArgError{"not a checkpoint of this library"};
+        if (h.dim != dim || h.G != G || h.precision != precision_code() || h.band != band_d ||
+            h.physics != physics || h.redistance != redist)
+            throw ArgError{"checkpoint of a different configuration (dim, grains, precision, band, physics, "
+                           "re-initialization)"};
+        long long nt = 1;
+        for (int a = 0; a < 3; ++a) {
+            const bool active = a < dim;
+            if (active ? (h.n[a] < 4 * P + 2 || h.n[a] > 4096) : h.n[a] != 1) throw ArgError{"checkpoint grid out of range"};
+            nt *= h.n[a];
+        }
+        if (nt > 2147483647LL || h.values < 0 || h.has_iota != (physics ? 1 : 0)) throw ArgError{"corrupt checkpoint"};
+        std::vector<int> l(3 * G), e(3 * G), al(G);
+        get(f, l.data(), sizeof(int) * 3 * G);
+        get(f, e.data(), sizeof(int) * 3 * G);
+        get(f, al.data(), sizeof(int) * G);
+        long long m = 0;
+        for (int k = 0; k < G; ++k)
+            if (al[k]) {
+                for (int a = 0; a < 3; ++a)
+                    if (e[3 * k + a] < 1 || e[3 * k + a] > h.n[a]) throw ArgError{"corrupt checkpoint box"};
+                m += (long long)e[3 * k] * e[3 * k + 1] * e[3 * k + 2];
+            }
+        if (m != h.values) throw ArgError{"corrupt checkpoint: box volumes and value count differ"};
+        std::vector<T> v(std::max<long long>(m, 1));
+        std::vector<int> io;
+        std::vector<double> vo(G);
+        get(f, v.data(), sizeof(T) * m);
+        if (h.has_iota) {
+            io.resize(std::max<long long>(m, 1));
+            get(f, io.data(), sizeof(int) * m);
+        }
+        get(f, vo.data(), sizeof(double) * G);
+        std::vector<uint8_t> a8(G);
+        for (int k = 0; k < G; ++k) a8[k] = al[k] ? 1 : 0;
+        // the grid of the checkpoint, then the state (validated by the box rule)
+        const int keep_n[3] = {n[0], n[1], n[2]};
+        const double keep_h = voxel_m;
+        set_grid(h.n);
+        voxel_m = h.voxel_m;
+        try {
+            load_state_core(l.data(), e.data(), a8.data(), v.data(), h.has_iota ? io.data() : nullptr);
+        } catch (const ArgError &) {
+            set_grid(keep_n);
+            voxel_m = keep_h;
+            throw;
+        }
+        HIPCHECK(hipMemcpyAsync(vol.p, vo.data(), sizeof(double) * G, hipMemcpyHostToDevice, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+        steps_done = h.steps;
+        total_gv = h.total_gv;
+        have_keep = false;
     }
 
     void keep_copy(int L, const T *psi, const T *phic) {
@@ -1031,6 +1218,14 @@ template <typename T> struct Sim final : SimBase {
 
     void load_state(const int32_t *hlo, const int32_t *hext, const uint8_t *hal, const double *vals,
                     const int32_t *hiota) override {
+        load_state_core(hlo, hext, hal, vals, hiota);
+    }
+
+    // State from host tables: values as doubles (any precision) or in the
+    // stored type T (a checkpoint of this precision, taken over unchanged).
+    template <typename V>
+    void load_state_core(const int32_t *hlo, const int32_t *hext, const uint8_t *hal, const V *vals,
+                         const int32_t *hiota) {
         std::vector<int> l(3 * G), e(3 * G), a(G);
         std::vector<long long> o(G + 1, 0);
         std::vector<double> vh(G, 0.0);
@@ -1051,12 +1246,12 @@ template <typename T> struct Sim final : SimBase {
         }
         const long long m = o[G];
         for (long long i = 0; i < m; ++i)
-            if (!std::isfinite(vals[i])) throw ArgError{"non-finite value in the state"};
+            if (!std::isfinite((double)vals[i])) throw ArgError{"non-finite value in the state"};
         for (int k = 0; k < G; ++k)
             if (a[k]) {
                 double s = 0.0;
                 for (long long i = o[k]; i < o[k + 1]; ++i) {
-                    double c = vals[i] + 0.5;
+                    double c = (double)vals[i] + 0.5;
                     c = c < 0.0 ? 0.0 : (c > 1.0 ? 1.0 : c);
                     s += c;
                 }
@@ -1066,12 +1261,19 @@ template <typename T> struct Sim final : SimBase {
         cur = 0;
         upload_table(0, l.data(), e.data(), a.data(), o.data());
         for (int q = 0; q < 4; ++q) ensure_arena(q, m);
-        std::vector<T> tv(std::max<long long>(m, 1));
-        for (long long i = 0; i < m; ++i) tv[i] = (T)vals[i];
         a_state = 0;
         a_T = a_psi = -1;
         T_R = psi_R = -1;
-        HIPCHECK(hipMemcpyAsync(arena[0].p, tv.data(), sizeof(T) * m, hipMemcpyHostToDevice, stream));
+        std::vector<T> tv;
+        const T *up;
+        if constexpr (std::is_same<V, T>::value) {
+            up = vals;
+        } else {
+            tv.resize(std::max<long long>(m, 1));
+            for (long long i = 0; i < m; ++i) tv[i] = (T)vals[i];
+            up = tv.data();
+        }
+        HIPCHECK(hipMemcpyAsync(arena[0].p, up, sizeof(T) * m, hipMemcpyHostToDevice, stream));
         HIPCHECK(hipMemcpyAsync(vol.p, vh.data(), sizeof(double) * G, hipMemcpyHostToDevice, stream));
         if (physics) {
             ensure_iota(0, m);
@@ -1105,6 +1307,8 @@ template <typename T> struct Sim final : SimBase {
         s.capacity = (int64_t)(arena[a_state >= 0 ? a_state : 0].cap / sizeof(T));
         s.superposition = (double)last_gv / ((double)n[0] * n[1] * n[2]);
         s.last_step_ms = last_ms;
+        for (int a = 0; a < 3; ++a) s.n[a] = n[a];
+        s.dim = dim;
         return s;
     }
 };
@@ -1112,6 +1316,9 @@ template <typename T> struct Sim final : SimBase {
 }  // namespace
 
 struct gg_sim {
+    bool has_alloc = false;
+    gg_allocator alloc{};  // the caller's allocator (has_alloc); declared before impl, so it outlives it
+    void *stream = nullptr;
     std::unique_ptr<SimBase> impl;
     std::string err;
     bool poisoned = false;
@@ -1135,9 +1342,25 @@ gg_status fail(gg_sim *s, gg_status st, const std::string &msg) {
     return st;
 }
 
+// Routes the thread's device allocations to the simulation's allocator for the
+// duration of a call.
+struct AllocScope {
+    const gg_allocator *pa;
+    void *ps;
+    explicit AllocScope(gg_sim *s) : pa(t_alloc), ps(t_alloc_stream) {
+        t_alloc = s && s->has_alloc ? &s->alloc : nullptr;
+        t_alloc_stream = s ? s->stream : nullptr;
+    }
+    ~AllocScope() {
+        t_alloc = pa;
+        t_alloc_stream = ps;
+    }
+};
+
 template <typename F> gg_status guarded(gg_sim *s, F &&f) {
     if (!s) return GG_E_ARG;
     if (s->poisoned) return fail(s, GG_E_POISONED, "simulation poisoned by an earlier HIP error: " + s->err);
+    AllocScope scope(s);
     try {
         HIPCHECK(hipSetDevice(s->device));
         return f();
@@ -1179,7 +1402,8 @@ const char *gg_status_str(gg_status st) {
 const char *gg_last_error(const gg_sim *sim) { return sim ? sim->err.c_str() : g_create_error.c_str(); }
 
 gg_status gg_create(const gg_config *cfg, const int32_t *labels, int32_t n_grains, const double *quat,
-                    const double *energy_density, void *hip_stream, gg_sim **out) {
+                    const double *energy_density, void *hip_stream, const gg_allocator *allocator,
+                    gg_sim **out) {
     g_create_error.clear();
     if (!out) return fail(nullptr, GG_E_ARG, "out is NULL");
     *out = nullptr;
@@ -1192,8 +1416,10 @@ gg_status gg_create(const gg_config *cfg, const int32_t *labels, int32_t n_grain
     const int P = (int)std::ceil(cfg->band);
     for (int a = 0; a < cfg->dim; ++a)
         if (cfg->n[a] < 4 * P + 2) return fail(nullptr, GG_E_ARG, "grid must have at least 4P + 2 voxels per axis");
+    if (cfg->precision == GG_MIXED_BF16 || cfg->precision == GG_MIXED_FP16)
+        return fail(nullptr, GG_E_UNSUPPORTED, "BF16 / FP16 convolution operands are not built: use GG_FP32");
     if (cfg->precision != GG_FP64 && cfg->precision != GG_FP32)
-        return fail(nullptr, GG_E_UNSUPPORTED, "precision must be GG_FP64 or GG_FP32");
+        return fail(nullptr, GG_E_ARG, "precision must be a gg_precision value");
     if (cfg->physics < 0 || cfg->physics > 3) return fail(nullptr, GG_E_ARG, "unknown physics bits");
     if (cfg->redistance != GG_REDIST_TAXICAB && cfg->redistance != GG_REDIST_EUCLID)
         return fail(nullptr, GG_E_ARG, "redistance must be GG_REDIST_TAXICAB or GG_REDIST_EUCLID");
@@ -1213,6 +1439,9 @@ gg_status gg_create(const gg_config *cfg, const int32_t *labels, int32_t n_grain
     if (energy_density && (cfg->physics & GG_PHYS_BULK))
         for (int k = 0; k < n_grains; ++k)
             if (!std::isfinite(energy_density[k])) return fail(nullptr, GG_E_ARG, "non-finite energy density");
+    if (allocator && (!allocator->alloc || !allocator->free))
+        return fail(nullptr, GG_E_ARG, "allocator needs both alloc and free");
+    if (allocator && !hip_stream) return fail(nullptr, GG_E_ARG, "an allocator needs the caller's stream");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
         (void)hipGetLastError();
@@ -1220,6 +1449,10 @@ gg_status gg_create(const gg_config *cfg, const int32_t *labels, int32_t n_grain
     }
     std::unique_ptr<gg_sim> s(new (std::nothrow) gg_sim());
     if (!s) return fail(nullptr, GG_E_NOMEM, "host allocation failed");
+    if (allocator) {
+        s->has_alloc = true;
+        s->alloc = *allocator;
+    }
     s->G = n_grains;
     for (int a = 0; a < 3; ++a) s->n[a] = cfg->n[a];
     s->dim = cfg->dim;
@@ -1231,6 +1464,8 @@ gg_status gg_create(const gg_config *cfg, const int32_t *labels, int32_t n_grain
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(nullptr, GG_E_NODEVICE, "device query failed");
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(nullptr, GG_E_NODEVICE, std::string("device is ") + prop.gcnArchName + ", not gfx950");
+    s->stream = hip_stream;
+    AllocScope scope(s.get());
     try {
         if (cfg->precision == GG_FP64) {
             auto *p = new Sim<double>(*cfg, n_grains, (hipStream_t)hip_stream);
@@ -1348,6 +1583,49 @@ gg_status gg_grain_areas(gg_sim *sim, double *area, double *weighted, int64_t ca
     if (cap < sim->G) return fail(sim, GG_E_SMALLBUF, "cap < n_grains");
     return guarded(sim, [&]() {
         sim->impl->areas(area, weighted);
+        return GG_OK;
+    });
+}
+
+gg_status gg_grain_sdf(gg_sim *sim, int32_t id, int32_t lo[3], int32_t ext[3], double *out, int64_t cap) {
+    if (!sim || !lo || !ext) return fail(sim, GG_E_ARG, "NULL argument");
+    if (id < 0 || id >= sim->G) return fail(sim, GG_E_ARG, "grain id out of range");
+    return guarded(sim, [&]() {
+        const long long m = sim->impl->grain_sdf(id, lo, ext, out, cap);
+        if (m < 0 && out) return fail(sim, GG_E_SMALLBUF, "cap too small (" + std::to_string(-m) + ")");
+        return GG_OK;
+    });
+}
+
+gg_status gg_save(gg_sim *sim, const char *path) {
+    if (!sim || !path) return fail(sim, GG_E_ARG, "NULL argument");
+    return guarded(sim, [&]() {
+        FILE *f = std::fopen(path, "wb");
+        if (!f) return fail(sim, GG_E_ARG, std::string("cannot open ") + path + " for writing");
+        try {
+            sim->impl->save(f);
+        } catch (...) {
+            std::fclose(f);
+            throw;
+        }
+        if (std::fclose(f) != 0) return fail(sim, GG_E_ARG, std::string("write to ") + path + " failed");
+        return GG_OK;
+    });
+}
+
+gg_status gg_load(gg_sim *sim, const char *path) {
+    if (!sim || !path) return fail(sim, GG_E_ARG, "NULL argument");
+    return guarded(sim, [&]() {
+        FILE *f = std::fopen(path, "rb");
+        if (!f) return fail(sim, GG_E_ARG, std::string("cannot open ") + path);
+        try {
+            sim->impl->load(f);
+        } catch (...) {
+            std::fclose(f);
+            throw;
+        }
+        std::fclose(f);
+        sim->impl->grid(sim->n);
         return GG_OK;
     });
 }

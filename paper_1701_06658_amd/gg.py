@@ -25,7 +25,8 @@ STATUS = {0: "GG_OK", 1: "GG_E_ARG", 2: "GG_E_NOMEM", 3: "GG_E_HIP", 4: "GG_E_CA
 EXPORTS = ["gg_create", "gg_step", "gg_sync", "gg_grain_count", "gg_grain_volumes", "gg_labels",
            "gg_stats", "gg_get_boxes", "gg_get_values", "gg_get_iota", "gg_load_state",
            "gg_keep_intermediates", "gg_get_intermediate", "gg_status_str", "gg_last_error",
-           "gg_destroy", "gg_version", "gg_profile", "gg_get_kernel_times", "gg_coarsen", "gg_grain_areas"]
+           "gg_destroy", "gg_version", "gg_profile", "gg_get_kernel_times", "gg_coarsen", "gg_grain_areas",
+           "gg_grain_sdf", "gg_save", "gg_load"]
 
 KERNEL_CLASSES = ["conv_xy", "conv_z", "compare", "reinit_xy", "reinit_z", "plan", "volume", "reinit_sweep"]
 
@@ -43,6 +44,33 @@ class Config(C.Structure):
                 ("capacity_headroom", C.c_double), ("redistance", C.c_int32)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", C.c_void_p)]
+
+
+def torch_allocator():
+    """A gg_allocator over PyTorch's caching allocator (the blocks show up in
+    torch.cuda.memory_allocated and are reused by torch after gg_destroy)."""
+    import torch
+
+    def _alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        except RuntimeError:
+            return None
+
+    def _free(ptr, stream, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a = Allocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
+    a._keep = (_alloc, _free)
+    return a
+
+
 class KernelTimes(C.Structure):
     _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8), ("voxels", C.c_int64 * 8)]
 
@@ -51,7 +79,8 @@ class StepStats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("total_grain_voxels", C.c_int64), ("alive", C.c_int32),
                 ("kernel_radius", C.c_int32),
                 ("grain_voxels", C.c_int64), ("capacity", C.c_int64),
-                ("superposition", C.c_double), ("last_step_ms", C.c_double)]
+                ("superposition", C.c_double), ("last_step_ms", C.c_double), ("n", C.c_int32 * 3),
+                ("dim", C.c_int32)]
 
 
 _lib = None
@@ -67,7 +96,7 @@ def load_library(path=LIB_PATH):
     lib = C.CDLL(path)
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     sig = {
-        "gg_create": (i32, [C.POINTER(Config), vp, i32, vp, vp, vp, C.POINTER(vp)]),
+        "gg_create": (i32, [C.POINTER(Config), vp, i32, vp, vp, vp, C.POINTER(Allocator), C.POINTER(vp)]),
         "gg_step": (i32, [vp, dbl, i32]),
         "gg_sync": (i32, [vp]),
         "gg_grain_count": (i32, [vp, C.POINTER(i32)]),
@@ -80,6 +109,9 @@ def load_library(path=LIB_PATH):
         "gg_load_state": (i32, [vp, vp, vp, vp, vp, vp]),
         "gg_coarsen": (i32, [vp, vp]),
         "gg_grain_areas": (i32, [vp, vp, vp, i64]),
+        "gg_grain_sdf": (i32, [vp, i32, vp, vp, vp, i64]),
+        "gg_save": (i32, [vp, C.c_char_p]),
+        "gg_load": (i32, [vp, C.c_char_p]),
         "gg_keep_intermediates": (i32, [vp, i32]),
         "gg_get_intermediate": (i32, [vp, i32, vp, i64, vp, vp, vp, vp, i64]),
         "gg_status_str": (C.c_char_p, [i32]),
@@ -107,11 +139,13 @@ class Simulation:
     labels: int array (nz, ny, nx) (nz == 1 in 2D), values in [0, G).
     precision: "fp64" (plain) or "fp32" (mixed).
     stream: optional hipStream_t handle (int), e.g. torch.cuda.current_stream().cuda_stream.
+    allocator: None (the library's hipMalloc), "torch" (PyTorch's caching
+    allocator, on `stream` or torch's current stream) or an Allocator.
     """
 
     def __init__(self, labels, band, G=None, precision="fp64", physics=0, quat=None,
                  theta_c_deg=15.0, energy=None, voxel_m=0.0, gamma_max=0.0, stream=None,
-                 headroom=0.0, redistance="taxicab"):
+                 headroom=0.0, redistance="taxicab", allocator=None):
         lib = load_library()
         labels = np.ascontiguousarray(labels, dtype=np.int32)
         if labels.ndim == 2:
@@ -133,9 +167,16 @@ class Simulation:
         cfg.redistance = {"taxicab": GG_REDIST_TAXICAB, "euclid": GG_REDIST_EUCLID}[redistance]
         q = None if quat is None else np.ascontiguousarray(quat, dtype=np.float64)
         e = None if energy is None else np.ascontiguousarray(energy, dtype=np.float64)
+        if allocator == "torch":
+            import torch
+            allocator = torch_allocator()
+            if not stream:
+                stream = torch.cuda.current_stream().cuda_stream
+        self._allocator = allocator  # the callbacks must outlive the simulation
         h = C.c_void_p()
         st = lib.gg_create(C.byref(cfg), _ptr(labels), self.G, _ptr(q), _ptr(e),
-                           C.c_void_p(int(stream)) if stream else None, C.byref(h))
+                           C.c_void_p(int(stream)) if stream else None,
+                           C.byref(allocator) if allocator is not None else None, C.byref(h))
         if st != 0:
             raise GGError(st, lib.gg_last_error(None).decode())
         self._lib = lib
@@ -159,6 +200,26 @@ class Simulation:
 
     def sync(self):
         self._check(self._lib.gg_sync(self._h))
+
+    def grain_sdf(self, k):
+        """(lo, ext, values (ez, ey, ex)) of grain k, or None if it is extinct."""
+        lo = np.zeros(3, np.int32)
+        ext = np.zeros(3, np.int32)
+        self._check(self._lib.gg_grain_sdf(self._h, int(k), _ptr(lo), _ptr(ext), None, 0))
+        if not ext.any():
+            return None
+        out = np.empty(int(np.prod(ext)), np.float64)
+        self._check(self._lib.gg_grain_sdf(self._h, int(k), _ptr(lo), _ptr(ext), _ptr(out), out.size))
+        return lo, ext, out.reshape(int(ext[2]), int(ext[1]), int(ext[0]))
+
+    def save(self, path):
+        """Write a checkpoint of the state to `path`."""
+        self._check(self._lib.gg_save(self._h, os.fsencode(path)))
+
+    def load(self, path):
+        """Replace the state by the checkpoint at `path` (same configuration)."""
+        self._check(self._lib.gg_load(self._h, os.fsencode(path)))
+        self.n = tuple(int(v) for v in self.stats()["n"])
 
     def areas(self):
         """(area, weighted): per-grain interface areas and Read-Shockley-weighted areas (FP64)."""
@@ -196,7 +257,9 @@ class Simulation:
     def stats(self):
         s = StepStats()
         self._check(self._lib.gg_stats(self._h, C.byref(s)))
-        return {f: getattr(s, f) for f, _ in StepStats._fields_}
+        out = {f: getattr(s, f) for f, _ in StepStats._fields_}
+        out["n"] = tuple(out["n"])
+        return out
 
     def profile(self, on=True):
         """Per-kernel HIP-event timing on the simulation's stream (resets the sums)."""

@@ -37,7 +37,7 @@ def test_config_struct_matches_header():
     # the ctypes mirror of gg_config lists the header's fields in order
     from paper_1701_06658_amd import gg
     text = open(HEADER).read()
-    body = re.search(r"typedef struct \{(.*?)\} gg_config;", text, re.S).group(1)
+    body = re.search(r"typedef struct \{([^{}]*)\} gg_config;", text).group(1)
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     names = re.findall(r"\b(?:int32_t|double)\s+(\w+)", body)
     assert names == [f[0] for f in gg.Config._fields_]
@@ -63,7 +63,7 @@ def _create(lib, **kw):
     labels = kw.get("labels", np.zeros(int(np.prod(n)), np.int32))
     h = C.c_void_p()
     st = lib.gg_create(C.byref(cfg), labels.ctypes.data_as(C.c_void_p), kw.get("G", 1), None,
-                       None, None, C.byref(h))
+                       None, None, kw.get("allocator"), C.byref(h))
     return st, lib.gg_last_error(None)
 
 
@@ -87,8 +87,21 @@ def test_argument_errors_are_reported_before_any_device_use(lib, kw):
 
 
 def test_unsupported_precision(lib):
+    for p in (2, 3):   # BF16 / FP16 operands: declared, not built
+        st, msg = _create(lib, precision=p)
+        assert st == 8 and b"FP32" in msg
     st, _ = _create(lib, precision=7)
-    assert st == 8
+    assert st == 1
+
+
+def test_allocator_arguments(lib):
+    from paper_1701_06658_amd import gg
+    half = gg.Allocator(gg.ALLOC_FN(lambda n, s, u: None), gg.FREE_FN(), None)
+    st, msg = _create(lib, allocator=C.byref(half))
+    assert st == 1 and b"alloc and free" in msg
+    full = gg.Allocator(gg.ALLOC_FN(lambda n, s, u: None), gg.FREE_FN(lambda p, s, u: None), None)
+    st, msg = _create(lib, allocator=C.byref(full))
+    assert st == 1 and b"stream" in msg
 
 
 def test_null_handles(lib):
@@ -101,3 +114,12 @@ def test_coarsen_rejects_null_simulation(lib):
     n = np.array([32, 32, 1], np.int32)
     lib.gg_coarsen.argtypes = [C.c_void_p, C.c_void_p]
     assert lib.gg_coarsen(None, n.ctypes.data_as(C.c_void_p)) == 1
+
+
+def test_step_stats_struct_matches_header():
+    from paper_1701_06658_amd import gg
+    text = open(HEADER).read()
+    body = re.search(r"typedef struct \{([^{}]*)\} gg_step_stats;", text).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"\b(?:int32_t|int64_t|double)\s+(\w+)", body)
+    assert names == [f[0] for f in gg.StepStats._fields_]
