@@ -51,7 +51,7 @@ def euclid_sweeps(dim, W):
     return K + (K & 1)
 
 
-def run_gpu(cfg, precision, steps, warmup, copy_probe=False, redistance="taxicab"):
+def run_gpu(cfg, precision, steps, warmup, copy_probe=False, redistance="taxicab", autotune=False):
     import paper_1701_06658_amd as gg
     phys = {}
     if cfg.get("physics") == "anisotropic":
@@ -63,6 +63,11 @@ def run_gpu(cfg, precision, steps, warmup, copy_probe=False, redistance="taxicab
     sim = gg.Simulation(cfg["labels"], cfg["W"], G=cfg["G"], precision=precision, redistance=redistance, **phys)
     sim.sync()
     log(f"[bench] {precision}: created in {time.perf_counter() - t0:.2f} s")
+    tuned = None
+    if autotune:
+        # the tuner's steps (one per candidate tiling) are warm-up steps
+        tuned = sim.autotune(cfg["dt"], 1)
+        log(f"[bench] {precision}: autotuned LDS budgets {tuned}")
     if warmup:
         sim.step(cfg["dt"], warmup)
     sim.sync()
@@ -79,7 +84,7 @@ def run_gpu(cfg, precision, steps, warmup, copy_probe=False, redistance="taxicab
     gv = st["total_grain_voxels"] - gv0
     out = dict(value=gv / dt, ms_per_step=1e3 * dt / steps, grain_voxels=gv, alive=st["alive"],
                superposition=st["superposition"], kernels=kt, physics=bool(phys),
-               sweeps=euclid_sweeps(cfg["dim"], cfg["W"]) if redistance == "euclid" else 0)
+               sweeps=euclid_sweeps(cfg["dim"], cfg["W"]) if redistance == "euclid" else 0, tuned=tuned)
     log(f"[bench] {precision}: {steps} steps in {dt:.3f} s, {out['value']:.3e} gv/s, "
         f"alive {st['alive']}")
     if copy_probe:
@@ -203,6 +208,8 @@ def main():
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--precision", default=None, help="fp32 (mixed) or fp64 (plain)")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose the tiling's LDS budgets with gg_autotune before the warm-up steps")
     ap.add_argument("--coarsen", type=int, default=0, metavar="N_NEW",
                     help="also time one grid coarsening of the workload onto N_NEW voxels per axis")
     ap.add_argument("--redistance", default="taxicab", choices=["taxicab", "euclid"],
@@ -222,7 +229,7 @@ def main():
     log(f"[bench] inputs {cfg['name']}: {cfg['G']} grains in {time.perf_counter() - t0:.1f} s")
     precision = args.precision or cfg["precision"]
     main_res = run_gpu(cfg, precision, args.steps, args.warmup, copy_probe=args.copy_probe,
-                       redistance=args.redistance)
+                       redistance=args.redistance, autotune=args.autotune)
     s_bytes = 4 if precision == "fp32" else 8
     line = {
         "metric": "grain-voxel updates/s per step (mixed batched vs FP64 plain) + %HBM roofline",
@@ -248,9 +255,11 @@ def main():
         "_euclid" if args.redistance == "euclid" else "")
     rl["traffic"] = recorded_traffic(rl["kernel"], precision, workload)
     if not args.no_plain and precision != "fp64":
-        plain = run_gpu(cfg, "fp64", args.steps, args.warmup, redistance=args.redistance)
+        plain = run_gpu(cfg, "fp64", args.steps, args.warmup, redistance=args.redistance, autotune=args.autotune)
         line["plain_fp64"] = dict(value=plain["value"], ms_per_step=plain["ms_per_step"],
                                   roofline=roofline(plain, 8), mixed_speedup=main_res["value"] / plain["value"])
+    if args.autotune:
+        line["tuning"] = {"lds_bytes": main_res["tuned"][0], "small_class_bytes": main_res["tuned"][1]}
     if args.copy_probe:
         line["copy_probe"] = main_res["copy_probe"]
     if args.coarsen:

@@ -249,6 +249,18 @@ gg_status gg_coarsen(gg_sim *sim, const int32_t n_new[3]);
  * range). */
 gg_status gg_grain_sdf(gg_sim *sim, int32_t id, int32_t lo[3], int32_t ext[3], double *out, int64_t cap);
 
+/* Autotuning of the tile shapes: work-item tilings follow two LDS budgets, the
+ * work group's (default 40 KB) and the small launch class's limit (default
+ * 26 KB; FP64 tiles get the same values, twice the bytes).  gg_autotune takes
+ * steps_per_candidate steps (normalised length dt) with each of a few
+ * candidate pairs (budgets up to 48 KB), keeps the pair with the least device
+ * time per grain voxel and returns it.  The simulation advances by those
+ * steps; the results do not depend on the tiling (FP64 bit-identical).
+ * Errors: GG_E_ARG (dt not finite/positive, steps_per_candidate < 1),
+ * GG_E_CAPACITY, GG_E_HIP. */
+gg_status gg_autotune(gg_sim *sim, double dt, int32_t steps_per_candidate, int32_t *lds_bytes,
+                      int32_t *small_bytes);
+
 /* Checkpoint / resume.  gg_save writes the state to a file: grid, boxes,
  * liveness, values in the stored precision, the ID-field (with the predictor
  * correction), volumes and step counters.  gg_load replaces the state of a

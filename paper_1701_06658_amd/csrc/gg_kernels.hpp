@@ -115,6 +115,10 @@ __device__ __forceinline__ int wrap_diff(int a, int b, int N) {
 template <typename T> constexpr int lds_scale() { return sizeof(T) == 8 ? GG_F64_LDS_SCALE : 1; }
 template <typename T> constexpr int lds_budget() { return kLdsBytes * lds_scale<T>() / (int)sizeof(T); }
 template <typename T> constexpr int small_budget() { return kSmallLdsBytes * lds_scale<T>() / (int)sizeof(T); }
+// The largest LDS budget a simulation may be tuned to (FP32 bytes; FP64 scaled
+// alike), and the budget in values for a byte figure.
+constexpr int kLdsBytesMax = 49152;
+template <typename T> constexpr int budget_values(int bytes) { return bytes * lds_scale<T>() / (int)sizeof(T); }
 
 template <typename T> __device__ __forceinline__ T mac(T acc, T a, T b);
 template <> __device__ __forceinline__ double mac<double>(double acc, double a, double b) {
@@ -1428,7 +1432,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_jacobi(Boxes Ln, ItemRefs ir, const T *__restrict__ src, T *__restrict__ dst, double *__restrict__ vol_part,
              T W, int final2d, GridArgs g) {
-    static_assert(lds_budget<T>() / 3 <= kJacQ * kBlock, "a Jacobi plane must fit the lanes' registers");
+    static_assert(budget_values<T>(kLdsBytesMax) / 3 <= kJacQ * kBlock, "a Jacobi plane must fit the lanes' registers");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
     __shared__ double red[kBlock / 64];

@@ -123,6 +123,7 @@ struct SimBase {
     virtual void save(FILE *f) = 0;
     virtual void load(FILE *f) = 0;
     virtual void grid(int32_t *n) const = 0;
+    virtual void autotune(double dt, int per, int32_t *best_lds, int32_t *best_small) = 0;
     virtual void sync() = 0;
     virtual int alive_count() const = 0;
     virtual gg_step_stats stats() const = 0;
@@ -138,6 +139,9 @@ template <typename T> struct Sim final : SimBase {
     int redist, K_euclid;  // re-initialization scheme of the steps; its Jacobi sweep count
     T W;
     double band_d;  // W as given
+    // LDS budget of a work group and limit of the small launch class (FP32
+    // bytes; FP64 tiles get the same values), tunable (gg_autotune)
+    int lds_bytes = gg::kLdsBytes, small_bytes = gg::kSmallLdsBytes;
     int physics;
     double theta_c, voxel_m, gamma_max, headroom;
     int tdim[3], nt[3], ntiles, occ_words;
@@ -397,8 +401,8 @@ template <typename T> struct Sim final : SimBase {
         HIPCHECK(hipMemsetAsync(ldsmax.p, 0, sizeof(unsigned long long) * gg::kKinds * gg::kClasses, stream));
         const int tb = 256, gb = (G + tb - 1) / tb;
         hipLaunchKernelGGL(gg::k_item_counts, dim3(gb, gg::kKinds), dim3(tb), 0, stream, L, cnt.as<long long>(), itile[l].as<int4>(),
-                           ldsmax.as<unsigned long long>(), R, K, G, gg::lds_budget<T>(),
-                           gg::small_budget<T>(), redist == GG_REDIST_EUCLID ? 1 : 0);
+                           ldsmax.as<unsigned long long>(), R, K, G, gg::budget_values<T>(lds_bytes),
+                           gg::budget_values<T>(small_bytes), redist == GG_REDIST_EUCLID ? 1 : 0);
         hipLaunchKernelGGL(gg::k_scan_multi, dim3(3 * gg::kKinds), dim3(1024), 0, stream, cnt.as<long long>(),
                            ipref[l].as<long long>(), G);
         if (coverage) {
@@ -420,7 +424,7 @@ template <typename T> struct Sim final : SimBase {
         if (!coverage) tot[l].cov = keep_cov;
         for (int q = 0; q < gg::kKinds; ++q)
             for (int c = 0; c < gg::kClasses; ++c)
-                if (tot[l].lds[q][c] < 0 || tot[l].lds[q][c] > gg::lds_budget<T>())
+                if (tot[l].lds[q][c] < 0 || tot[l].lds[q][c] > gg::budget_values<T>(lds_bytes))
                     throw CapError{"a box is too large for the stencil tiling"};
         items_R[l] = R;
     }
@@ -1122,6 +1126,34 @@ template <typename T> struct Sim final : SimBase {
         have_keep = false;
     }
 
+    // Try the candidate (budget, small-class limit) pairs for `per` steps each
+    // (the simulation advances), keep the one with the least device time per
+    // grain voxel.  Tile shapes follow the budgets; results do not.
+    void autotune(double dt, int per, int32_t *best_lds, int32_t *best_small) override {
+        static const int cand[][2] = {{40960, 26624}, {32768, 20480}, {40960, 20480}, {40960, 32768},
+                                      {49152, 26624}, {49152, 32768}, {32768, 26624}};
+        double best = 1e300;
+        int bl = lds_bytes, bs = small_bytes;
+        for (const auto &c : cand) {
+            lds_bytes = c[0];
+            small_bytes = c[1];
+            items_R[0] = items_R[1] = -1;  // re-tile the current layout (its predicted values stand)
+            const long long gv0 = total_gv;
+            step(dt, per);
+            const double per_gv = last_ms * per / (double)std::max<long long>(total_gv - gv0, 1);
+            if (per_gv < best) {
+                best = per_gv;
+                bl = c[0];
+                bs = c[1];
+            }
+        }
+        lds_bytes = bl;
+        small_bytes = bs;
+        items_R[0] = items_R[1] = -1;
+        *best_lds = bl;
+        *best_small = bs;
+    }
+
     void keep_copy(int L, const T *psi, const T *phic) {
         const long long m = tot[L].arena;
         keep_psi.ensure(sizeof(T) * std::max<long long>(m, 1));
@@ -1593,6 +1625,17 @@ gg_status gg_grain_sdf(gg_sim *sim, int32_t id, int32_t lo[3], int32_t ext[3], d
     return guarded(sim, [&]() {
         const long long m = sim->impl->grain_sdf(id, lo, ext, out, cap);
         if (m < 0 && out) return fail(sim, GG_E_SMALLBUF, "cap too small (" + std::to_string(-m) + ")");
+        return GG_OK;
+    });
+}
+
+gg_status gg_autotune(gg_sim *sim, double dt, int32_t steps_per_candidate, int32_t *lds_bytes,
+                      int32_t *small_bytes) {
+    if (!sim || !lds_bytes || !small_bytes) return fail(sim, GG_E_ARG, "NULL argument");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(sim, GG_E_ARG, "dt must be finite and positive");
+    if (steps_per_candidate < 1) return fail(sim, GG_E_ARG, "steps_per_candidate must be >= 1");
+    return guarded(sim, [&]() {
+        sim->impl->autotune(dt, steps_per_candidate, lds_bytes, small_bytes);
         return GG_OK;
     });
 }

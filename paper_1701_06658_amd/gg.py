@@ -26,7 +26,7 @@ EXPORTS = ["gg_create", "gg_step", "gg_sync", "gg_grain_count", "gg_grain_volume
            "gg_stats", "gg_get_boxes", "gg_get_values", "gg_get_iota", "gg_load_state",
            "gg_keep_intermediates", "gg_get_intermediate", "gg_status_str", "gg_last_error",
            "gg_destroy", "gg_version", "gg_profile", "gg_get_kernel_times", "gg_coarsen", "gg_grain_areas",
-           "gg_grain_sdf", "gg_save", "gg_load"]
+           "gg_grain_sdf", "gg_save", "gg_load", "gg_autotune"]
 
 KERNEL_CLASSES = ["conv_xy", "conv_z", "compare", "reinit_xy", "reinit_z", "plan", "volume", "reinit_sweep"]
 
@@ -110,6 +110,7 @@ def load_library(path=LIB_PATH):
         "gg_coarsen": (i32, [vp, vp]),
         "gg_grain_areas": (i32, [vp, vp, vp, i64]),
         "gg_grain_sdf": (i32, [vp, i32, vp, vp, vp, i64]),
+        "gg_autotune": (i32, [vp, dbl, i32, vp, vp]),
         "gg_save": (i32, [vp, C.c_char_p]),
         "gg_load": (i32, [vp, C.c_char_p]),
         "gg_keep_intermediates": (i32, [vp, i32]),
@@ -211,6 +212,14 @@ class Simulation:
         out = np.empty(int(np.prod(ext)), np.float64)
         self._check(self._lib.gg_grain_sdf(self._h, int(k), _ptr(lo), _ptr(ext), _ptr(out), out.size))
         return lo, ext, out.reshape(int(ext[2]), int(ext[1]), int(ext[0]))
+
+    def autotune(self, dt, steps_per_candidate=1):
+        """Pick the LDS budgets (work group, small class) with the fastest steps;
+        advances the simulation.  Returns (lds_bytes, small_bytes)."""
+        a = C.c_int32()
+        b = C.c_int32()
+        self._check(self._lib.gg_autotune(self._h, float(dt), int(steps_per_candidate), C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def save(self, path):
         """Write a checkpoint of the state to `path`."""
