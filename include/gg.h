@@ -5,8 +5,11 @@
  * Barrales-Mora (arXiv:1701.06658, sec. 2.1, Algorithm 1): every grain carries a
  * signed-distance function on its own padded bounding box; a step is the
  * Gaussian predictor (sec. 2.1.4), the comparison corrector (sec. 2.1.5), the
- * taxicab re-initialization in the narrow band (sec. 2.1.6) and the box /
- * neighbour update (sec. 3.1).
+ * taxicab re-initialization in the narrow band (sec. 2.1.6; a Euclidean
+ * fast-sweeping variant on request) and the box / neighbour update (sec. 3.1).
+ * Around the step: grid coarsening (sec. 3), interface areas for the energy
+ * bookkeeping (Eq. Energyfunctional), checkpoint / resume and a tiling
+ * autotuner.
  *
  * Conventions
  *  - Lengths are in voxels.  The grid is periodic with n[0] x n[1] x n[2] voxels

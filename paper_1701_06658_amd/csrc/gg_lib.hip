@@ -919,7 +919,7 @@ template <typename T> struct Sim final : SimBase {
         layout_meta_count(Ln, true);
         const long long need = tot[Ln].arena;
         const int a_f = pick(bit(a_state), need);
-        tbegin(GG_K_REINIT_XY, need);
+        tbegin(GG_K_PLAN, 0);
         hipLaunchKernelGGL(gg::k_coarsen_values<T>, dim3(G, split), dim3(gg::kBlock), 0, stream, boxes_of(L),
                            (const T *)arena[a_state].as<T>(), boxes_of(Ln), arena[a_f].as<T>(), ca);
         tend();
