@@ -178,24 +178,32 @@ def roofline(res, s_bytes):
                 per_kernel={k: round(v["gbs"], 1) for k, v in per.items()})
 
 
-def cpu_baseline(index):
-    """FP64 oracle on a bounded sample: one step of a density-matched 128^3 cut."""
-    from oracle import Oracle, num_threads
+def cpu_baseline(index, threads=None):
+    """FP64 oracle on a bounded sample: one step of a density-matched cut of the
+    workload (128^3 on all host threads; 64^3 on one thread)."""
+    from oracle import Oracle, num_threads, set_num_threads
     from synth import make_config
-    G = {1: None, 2: 1000, 3: 1000, 4: 781, 5: 781}[index]
-    N = None if index == 1 else 128
-    c = make_config(index, N=N, G=G)
-    o = Oracle(c["labels"], c["W"], G=c["G"])
-    gv = 0
-    for k in range(c["G"]):
-        alive, lo, ext = o.box(k)
-        if alive:
-            gv += int(ext[0]) * int(ext[1]) * int(ext[2])
-    t0 = time.perf_counter()
-    o.step(c["dt"])
-    dt = time.perf_counter() - t0
-    o.close()
-    return dict(value=gv / dt, unit="grain-voxel updates/s", cores=num_threads(), kind="oracle",
+    N = None if index == 1 else (64 if threads == 1 else 128)
+    G = None if index == 1 else int(round({2: 1000, 3: 1000, 4: 781, 5: 781}[index] * (N / 128) ** 3))
+    all_threads = num_threads()
+    if threads:
+        set_num_threads(threads)
+    try:
+        c = make_config(index, N=N, G=G)
+        o = Oracle(c["labels"], c["W"], G=c["G"])
+        gv = 0
+        for k in range(c["G"]):
+            alive, lo, ext = o.box(k)
+            if alive:
+                gv += int(ext[0]) * int(ext[1]) * int(ext[2])
+        used = num_threads()
+        t0 = time.perf_counter()
+        o.step(c["dt"])
+        dt = time.perf_counter() - t0
+        o.close()
+    finally:
+        set_num_threads(all_threads)
+    return dict(value=gv / dt, unit="grain-voxel updates/s", cores=used, kind="oracle",
                 sample=f"1 FP64 oracle step of a density-matched {c['N']}^{c['dim']} cut with "
                        f"{c['G']} grains of workload {index} ({gv} grain voxels, {dt:.2f} s)")
 
@@ -266,6 +274,7 @@ def main():
         line["coarsen"] = run_coarsen(cfg, precision, args.warmup, args.coarsen)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.config)
+        line["cpu_baseline_1thread"] = cpu_baseline(args.config, threads=1)
     print(json.dumps(line), flush=True)
 
 

@@ -6,4 +6,4 @@ library never imports it.
 """
 from .oracle import Oracle, build_oracle, load_library, convolve_box, redistance_box, euclid_sweeps, \
     coarse_sample_box, \
-    misorientation_deg, pair_weight, num_threads  # noqa: F401
+    misorientation_deg, pair_weight, num_threads, set_num_threads  # noqa: F401

@@ -449,6 +449,14 @@ int orc_num_threads(void) {
 #endif
 }
 
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 void orc_keep_intermediates(orc_sim *s, int on) {
     if (s) s->keep = on;
 }

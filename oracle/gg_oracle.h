@@ -88,6 +88,7 @@ int orc_coarse_sample_box(int dim, const int32_t n[3], const int32_t np[3], doub
 double orc_misorientation_deg(const double qa[4], const double qb[4]);
 double orc_pair_weight(double theta_deg, double theta_c_deg, double *mobility);
 int orc_num_threads(void);
+void orc_set_num_threads(int n);   /* threads of the following calls (n > 0) */
 
 #ifdef __cplusplus
 }

@@ -69,6 +69,7 @@ def load_library():
     lib.orc_pair_weight.restype = C.c_double
     lib.orc_pair_weight.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_double)]
     lib.orc_num_threads.restype = C.c_int
+    lib.orc_set_num_threads.argtypes = [C.c_int]
     del i32_3
     _lib = lib
     return lib
@@ -292,6 +293,11 @@ def pair_weight(theta_deg, theta_c_deg=15.0):
 
 def num_threads():
     return load_library().orc_num_threads()
+
+
+def set_num_threads(n):
+    """Threads of the oracle's following calls."""
+    load_library().orc_set_num_threads(int(n))
 
 
 def euclid_sweeps(dim, band):
