@@ -258,7 +258,8 @@ gg_status gg_grain_sdf(gg_sim *sim, int32_t id, int32_t lo[3], int32_t ext[3], d
  * steps_per_candidate steps (normalised length dt) with each of a few
  * candidate pairs (budgets up to 48 KB), keeps the pair with the least device
  * time per grain voxel and returns it.  The simulation advances by those
- * steps; the results do not depend on the tiling (FP64 bit-identical).
+ * steps; the functions do not depend on the tiling (bit-identical; volumes,
+ * sums of per-work-item partial sums, to rounding).
  * Errors: GG_E_ARG (dt not finite/positive, steps_per_candidate < 1),
  * GG_E_CAPACITY, GG_E_HIP. */
 gg_status gg_autotune(gg_sim *sim, double dt, int32_t steps_per_candidate, int32_t *lds_bytes,

@@ -1128,7 +1128,7 @@ template <typename T> struct Sim final : SimBase {
 
     // Try the candidate (budget, small-class limit) pairs for `per` steps each
     // (the simulation advances), keep the one with the least device time per
-    // grain voxel.  Tile shapes follow the budgets; results do not.
+    // grain voxel.  Tile shapes follow the budgets; the functions do not.
     void autotune(double dt, int per, int32_t *best_lds, int32_t *best_small) override {
         static const int cand[][2] = {{40960, 26624}, {32768, 20480}, {40960, 20480}, {40960, 32768},
                                       {49152, 26624}, {49152, 32768}, {32768, 26624}};

@@ -1,7 +1,8 @@
 """gg_autotune: the chosen LDS budgets come from the candidate set, and the
 steps it takes (each candidate tiling in turn) give exactly the states of
 untuned steps, in both precisions: the work-item tiling changes the schedule,
-never a value."""
+never a value of the functions (grain volumes, sums of per-work-item partial
+sums, agree to rounding)."""
 import numpy as np
 import pytest
 
@@ -29,4 +30,5 @@ def test_autotune_keeps_results(precision):
     a.step(c["dt"], 2)
     b.step(c["dt"], 2)
     _same(a.state(), b.state())
-    assert np.array_equal(a.volumes(), b.volumes())
+    # volumes are sums of per-work-item partial sums: equal to rounding
+    assert np.allclose(a.volumes(), b.volumes(), rtol=1e-12, atol=0)
