@@ -283,6 +283,19 @@ template <typename T> struct Sim final : SimBase {
             HIPCHECK(hipStreamCreate(&stream));
             own_stream = true;
         }
+        try {
+            allocate_tables();
+        } catch (...) {
+            // a throwing constructor runs no destructor: hand back what is not a member buffer
+            if (totals_h) (void)hipHostFree(totals_h);
+            totals_h = nullptr;
+            if (own_stream && stream) (void)hipStreamDestroy(stream);
+            stream = nullptr;
+            throw;
+        }
+    }
+
+    void allocate_tables() {
         HIPCHECK(hipHostMalloc((void **)&totals_h, sizeof(Totals), hipHostMallocDefault));
         std::memset(totals_h, 0, sizeof(Totals));
         for (int l = 0; l < 2; ++l) {

@@ -108,7 +108,7 @@ class _CountingAllocator:
     """A gg_allocator over hipMalloc / hipFree (through ctypes) that counts the
     bytes it has handed out and not yet taken back."""
 
-    def __init__(self):
+    def __init__(self, fail_after=None):
         import ctypes as C
         from paper_1701_06658_amd import gg
         hip = C.CDLL("libamdhip64.so")
@@ -117,6 +117,8 @@ class _CountingAllocator:
         self.live, self.calls, self.sizes = 0, 0, {}
 
         def _alloc(nbytes, stream, user):
+            if fail_after is not None and self.calls >= fail_after:
+                return None
             p = C.c_void_p()
             if hip.hipMalloc(C.byref(p), nbytes) != 0:
                 return None
@@ -149,3 +151,19 @@ def test_caller_allocator_runs_identically():
     assert al.calls > 10 and al.live > 10 * 2 ** 20      # the arenas came from the caller
     a.close()
     assert al.live == 0 and not al.sizes                   # and all went back
+
+
+def test_caller_allocator_failure_is_reported():
+    # an allocator that runs dry part way through gg_create: GG_E_NOMEM, and
+    # every block it did hand out comes back
+    import ctypes as C
+    import paper_1701_06658_amd as gg
+    hip = C.CDLL("libamdhip64.so")
+    hip.hipStreamCreate.argtypes = [C.POINTER(C.c_void_p)]
+    stream = C.c_void_p()
+    assert hip.hipStreamCreate(C.byref(stream)) == 0
+    c = make_config(1)
+    al = _CountingAllocator(fail_after=12)
+    with pytest.raises(gg.GGError, match="GG_E_NOMEM"):
+        _sim(c["labels"], c["W"], c["G"], "fp64", allocator=al.struct, stream=stream.value)
+    assert al.calls == 12 and al.live == 0
