@@ -228,8 +228,7 @@ def main():
                          "streaming kernel of known size (reference for profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     from synth import make_config
     t0 = time.perf_counter()
