@@ -6,7 +6,8 @@ on the GPU through the C ABI.
   the bulk term, with the Euclidean variant, and across a coarsened grid);
   mismatched configurations, corrupt and missing files are rejected and leave
   the simulation unchanged;
-* gg_grain_sdf returns a grain's box and values as in the whole-state download;
+* gg_grain_sdf returns a grain's box and values as in the whole-state download, and
+  gg_labels writes the same ids into device memory as into host memory;
 * a simulation on the caller's allocator runs bit-identically to one on the
   library's own hipMalloc, and every block goes back to the caller.
 """
@@ -167,3 +168,34 @@ def test_caller_allocator_failure_is_reported():
     with pytest.raises(gg.GGError, match="GG_E_NOMEM"):
         _sim(c["labels"], c["W"], c["G"], "fp64", allocator=al.struct, stream=stream.value)
     assert al.calls == 12 and al.live == 0
+
+
+def test_labels_into_device_memory():
+    # gg_labels with a device pointer: stream-ordered write, same ids as the host copy
+    import ctypes as C
+    hip = C.CDLL("libamdhip64.so")
+    hip.hipMalloc.argtypes = [C.POINTER(C.c_void_p), C.c_size_t]
+    hip.hipFree.argtypes = [C.c_void_p]
+    hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    c = make_config(2, N=64, G=125)
+    s = _sim(c["labels"], c["W"], c["G"], "fp32")
+    s.step(c["dt"], 2)
+    n = int(np.prod(s.n))
+    buf = C.c_void_p()
+    assert hip.hipMalloc(C.byref(buf), 4 * n) == 0
+
+    class _Dev:                      # the two methods the binding reads from a device tensor
+        def data_ptr(self):
+            return buf.value
+
+        def numel(self):
+            return n
+
+    try:
+        s.labels(device_out=_Dev())
+        s.sync()
+        host = np.empty(n, np.int32)
+        assert hip.hipMemcpy(host.ctypes.data, buf, 4 * n, 2) == 0   # device to host
+        assert np.array_equal(host.reshape(s.n[2], s.n[1], s.n[0]), s.labels())
+    finally:
+        hip.hipFree(buf)
