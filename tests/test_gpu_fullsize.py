@@ -7,7 +7,8 @@ oracle steps that neighbourhood, loaded with the GPU's own state before the
 step (identical inputs), and the sampled grain's new function is compared with
 the GPU's: FP64 to 1e-10 voxel, FP32 to 2e-3 voxel in the band with the same
 box and a volume within 0.5% (the taxicab scheme in both precisions, and the
-Euclidean variant in FP32).  Whole-state properties are checked at every
+Euclidean variant in FP32), on the first step and on a later one (step 41 of
+the 256^3 workload, step 26 of the 128^3 / 1000-grain one).  Whole-state properties are checked at every
 size, including the two 512^3 / 50000-grain workloads with the predictor
 correction: volumes sum to the grid volume within 0.5% and every voxel gets a
 label.
@@ -30,13 +31,19 @@ def _overlaps(lo, ext, k, n):
     return np.nonzero(np.all(hit, axis=1))[0]
 
 
-@pytest.mark.parametrize("precision,redistance", [("fp32", "taxicab"), ("fp64", "taxicab"), ("fp32", "euclid")])
-def test_sampled_grains_full_workload3(precision, redistance):
+@pytest.mark.parametrize("index,precision,redistance,before", [
+    (3, "fp32", "taxicab", 0), (3, "fp64", "taxicab", 0), (3, "fp32", "euclid", 0),
+    (3, "fp32", "taxicab", 40), (2, "fp64", "taxicab", 25)])
+def test_sampled_grains_full_workload(index, precision, redistance, before):
+    # `before` steps first: the sampled step then comes after boxes have moved,
+    # shrunk and grains have vanished
     import paper_1701_06658_amd as gg
-    c = make_config(3)
+    c = make_config(index)
     n = np.array(c["n"])
     W = c["W"]
     s = gg.Simulation(c["labels"], W, G=c["G"], precision=precision, redistance=redistance)
+    if before:
+        s.step(c["dt"], before)
     s0 = s.state()
     s.step(c["dt"])
     s1 = s.state()
@@ -63,7 +70,8 @@ def test_sampled_grains_full_workload3(precision, redistance):
         if not a["alive"][k]:
             continue
         r = compare_states(a, s1, n, W, band_only=precision != "fp64", grains=[int(k)])
-        print(f"[{precision} {redistance} grain {k}] |dphi| {r['max_abs']:.3e} box_mismatch {r['box_mismatch']} "
+        print(f"[workload {index} step {before + 1} {precision} {redistance} grain {k}] |dphi| {r['max_abs']:.3e} "
+              f"box_mismatch {r['box_mismatch']} "
               f"volume {vo[k]:.2f} vs {v1[k]:.2f} ({len(hood)} grains stepped)", flush=True)
         assert r["box_mismatch"] == 0 and r["max_abs"] <= tol
         assert abs(v1[k] - vo[k]) <= (1e-9 if precision == "fp64" else 5e-3 * max(vo[k], 50.0))
