@@ -48,7 +48,7 @@ typedef enum {
     GG_E_HIP = 3,         /* HIP runtime error; the simulation is now poisoned     */
     GG_E_CAPACITY = 4,    /* a size limit of the library was exceeded             */
     GG_E_SMALLBUF = 5,    /* caller's output buffer is too small                  */
-    GG_E_NUMERIC = 6,     /* non-finite value detected                            */
+    GG_E_NUMERIC = 6,     /* reserved: non-finite inputs are argument errors      */
     GG_E_POISONED = 7,    /* an earlier HIP error poisoned this simulation         */
     GG_E_UNSUPPORTED = 8, /* valid request this build does not implement          */
     GG_E_NODEVICE = 9     /* no usable gfx950 device                              */
@@ -123,8 +123,8 @@ typedef struct {
 /* Device memory of a simulation through the caller's allocator (e.g. a caching
  * allocator): alloc(bytes, stream, user) returns device memory on the
  * simulation's device, usable in stream order on `stream`, or NULL; free(p,
- * stream, user) takes back a block alloc returned.  The library synchronises
- * the device before it frees or replaces a buffer.  Used for every device
+ * stream, user) takes back a block alloc returned.  No work that uses a block
+ * is pending on the device when the library frees it.  Used for every device
  * buffer of the simulation, from gg_create to gg_destroy. */
 typedef struct {
     void *(*alloc)(size_t bytes, void *stream, void *user);
@@ -187,12 +187,12 @@ gg_status gg_stats(gg_sim *sim, gg_step_stats *out);
 
 /* Per-kernel device time, for roofline accounting.  Kernel classes: */
 enum {
-    GG_K_CONV_XY = 0,   /* predictor x and y passes (2D: whole predictor)          */
-    GG_K_CONV_Z = 1,    /* predictor z pass (+ correction epilogue)                 */
+    GG_K_CONV_XY = 0,   /* predictor x and y passes (+ correction epilogue)          */
+    GG_K_CONV_Z = 1,    /* predictor z pass on its own (first step, new dt)         */
     GG_K_COMPARE = 2,   /* corrector over global tiles                              */
     GG_K_REINIT_XY = 3, /* reference values, x and y spreading sweeps (2D: all)     */
     GG_K_REINIT_Z = 4,  /* z sweep, clamp, volume partial sums, next z convolution  */
-    GG_K_PLAN = 5,      /* box plan, scans, work items, coverage lists              */
+    GG_K_PLAN = 5,      /* box plan, scans, work items, coverage lists; coarsening  */
     GG_K_VOLUME = 6,    /* per-grain volume reduction                               */
     GG_K_REINIT_SWEEP = 7, /* Jacobi sweeps of GG_REDIST_EUCLID (2D: + clamp, volume) */
     GG_K_CLASSES = 8
