@@ -1,7 +1,8 @@
 """Edge cases of the GPU path against the oracle (FP64, |dphi| <= 1e-10):
 a single grain filling the periodic grid (no interface), non-cubic grids with
-axes that no tile size divides, a non-integer band half width, and the largest
-band half width W = 16."""
+axes that no tile size divides, a non-integer band half width, the largest
+band half width W = 16, and twin grains (identical functions) whose ties go
+to the lowest id."""
 import numpy as np
 import pytest
 
@@ -57,3 +58,38 @@ def test_largest_band():
         o.step(dt)
         s.step(dt)
         _check_fp64(o, s, W, f"W=16 step {step}")
+
+
+def test_twin_grains_tie_to_the_lowest_id():
+    # two grains with identical functions on the same box: labels and ID-fields
+    # take the lower id, and the corrector sees each twin's best other as the
+    # other twin: a zero corrected function inside, so both twins vanish in the
+    # first step and the matrix takes their voxels, on both sides alike
+    import paper_1701_06658_amd as gg
+    N, W, G = 48, 6.0, 3
+    y, x = np.mgrid[0:N, 0:N]
+    labels = ((x - 23.5) ** 2 + (y - 24.5) ** 2 < 10.3 ** 2).astype(np.int32)[None]
+    h = np.radians(20.0) / 2.0
+    quat = np.array([[1.0, 0.0, 0.0, 0.0], [np.cos(h), 0.0, 0.0, np.sin(h)],
+                     [np.cos(h), 0.0, 0.0, np.sin(h)]])
+    o = Oracle(labels, W, G=G)
+    alive, lo, ext = o.box(1)
+    o.set_grain(2, True, lo, ext, o.phi(1))
+    o.set_physics(1, quat=quat, theta_c_deg=15.0)
+    st = o.state()
+    s = gg.Simulation(labels, W, G=G, precision="fp64", physics=gg.PHYS_MISORIENTATION, quat=quat,
+                      theta_c_deg=15.0)
+    s.load_state(st["alive"], st["lo"], st["ext"], st["phi"],
+                 [o.iota(k) if st["alive"][k] else None for k in range(G)])
+    lab = s.labels()
+    assert np.array_equal(lab, o.labels()) and (lab == 1).any() and not (lab == 2).any()
+    for step in range(1, 3):
+        o.step(config_dt(1.5, N))
+        s.step(config_dt(1.5, N))
+        _check_fp64(o, s, W, f"twins step {step}")
+        assert np.array_equal(s.labels(), o.labels())
+        assert s.alive_count() == o.alive_count() == 1
+        _, io_gpu = s.iota()
+        io_orc = np.concatenate([o.iota(k).ravel() for k in range(G) if o.box(k)[0]])
+        assert np.array_equal(io_gpu, io_orc)
+    s.close()

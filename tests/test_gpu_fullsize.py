@@ -8,10 +8,12 @@ step (identical inputs), and the sampled grain's new function is compared with
 the GPU's: FP64 to 1e-10 voxel, FP32 to 2e-3 voxel in the band with the same
 box and a volume within 0.5% (the taxicab scheme in both precisions, and the
 Euclidean variant in FP32), on the first step and on a later one (step 41 of
-the 256^3 workload, step 26 of the 128^3 / 1000-grain one).  Whole-state properties are checked at every
-size, including the two 512^3 / 50000-grain workloads with the predictor
-correction: volumes sum to the grid volume within 0.5% and every voxel gets a
-label.
+the 256^3 workload, step 26 of the 128^3 / 1000-grain one).  The two 512^3 /
+50000-grain workloads with the predictor correction (misorientation weights;
+the magnetic bulk term) get the same sampled comparison on their second step,
+with the GPU's ID-fields loaded beside the functions.  Whole-state properties
+are checked at every size: volumes sum to the grid volume within 0.5% and every
+voxel gets a label.
 """
 import numpy as np
 import pytest
@@ -98,3 +100,63 @@ def test_full_workload_properties(index):
     lab = s.labels()
     assert lab.min() >= 0 and lab.max() < c["G"]
     s.close()
+
+
+def _physics(c, gg):
+    if c.get("physics") == "anisotropic":
+        return (dict(physics=gg.PHYS_MISORIENTATION, quat=c["quat"], theta_c_deg=c["theta_c_deg"]),
+                dict(mode=1, quat=c["quat"], theta_c_deg=c["theta_c_deg"]))
+    return (dict(physics=gg.PHYS_BULK, energy=c["energy"], voxel_m=c["h_phys"], gamma_max=c["gamma_max"]),
+            dict(mode=2, energy=c["energy"], h_phys=c["h_phys"], gamma_max=c["gamma_max"]))
+
+
+@pytest.mark.parametrize("index", [4, 5])
+def test_sampled_grains_physics_workloads(index):
+    # the 512^3 / 50000-grain workloads with the predictor correction: the
+    # neighbourhood's functions and ID-fields (written by the GPU's corrector
+    # in the step before) go to the oracle grain by grain, and the sampled
+    # grains' next step is compared as above
+    import paper_1701_06658_amd as gg
+    c = make_config(index)
+    n = np.array(c["n"])
+    W, G = c["W"], c["G"]
+    gphys, ophys = _physics(c, gg)
+    s = gg.Simulation(c["labels"], W, G=G, precision=c["precision"], **gphys)
+    s.step(c["dt"])
+    b0 = s.boxes()
+    _, io_flat = s.iota()
+    lo0, ext0 = b0["lo"], b0["ext"]
+    rng = np.random.default_rng(4)
+    sample = rng.choice(np.nonzero(b0["alive"])[0], size=12, replace=False)
+    hood = set()
+    for k in sample:
+        hood.update(int(j) for j in _overlaps(lo0, ext0, k, n) if b0["alive"][j])
+    o = Oracle(np.zeros((n[2], n[1], n[0]), np.int32), W, G=G)
+    o.set_grain(0, False)
+    o.set_physics(**ophys)
+    for j in sorted(hood):
+        lo, ext, phi = s.grain_sdf(j)
+        assert np.array_equal(lo, lo0[j]) and np.array_equal(ext, ext0[j])
+        off = int(b0["offset"][j])
+        o.set_grain(j, True, lo, ext, phi, io_flat[off:off + phi.size].reshape(phi.shape))
+    del io_flat
+    s.step(c["dt"])
+    o.step(c["dt"])
+    a = o.state()
+    b1 = s.boxes()
+    b = dict(alive=b1["alive"], lo=b1["lo"], ext=b1["ext"], phi=[None] * G)
+    for k in sample:
+        got = s.grain_sdf(int(k))
+        if got is not None:
+            b["phi"][k] = got[2]
+    v1, vo = s.volumes(), o.volumes()
+    s.close()
+    for k in sample:
+        assert a["alive"][k] == b["alive"][k]
+        if not a["alive"][k]:
+            continue
+        r = compare_states(a, b, n, W, band_only=True, grains=[int(k)])
+        print(f"[workload {index} step 2 grain {k}] |dphi| {r['max_abs']:.3e} box_mismatch {r['box_mismatch']} "
+              f"volume {vo[k]:.2f} vs {v1[k]:.2f} ({len(hood)} grains stepped)", flush=True)
+        assert r["box_mismatch"] == 0 and r["max_abs"] <= 2e-3
+        assert abs(v1[k] - vo[k]) <= 5e-3 * max(vo[k], 50.0)
