@@ -1119,21 +1119,26 @@ __global__ void __launch_bounds__(kBlock)
     for (int i = threadIdx.x; i < FW; i += kBlock) ctab[i] = cr.col_code(x0 - hx - 1 + i);
     __syncthreads();
     // stage the f planes (their rows are consecutive: row R = p * FH + r);
-    // kLoadBatch loads in flight per lane
+    // kLoadBatch loads in flight per lane: all table reads first, then the
+    // loads without branches (a position off the old box loads the box's
+    // first value and keeps -W), then the LDS stores
     const int NR = nz * FH;
     for (Walk2 w(threadIdx.x, FW); w.r < NR;) {
-        T v[kLoadBatch];
-        int at[kLoadBatch];
+        int ro[kLoadBatch], co[kLoadBatch], at[kLoadBatch];
 #pragma unroll
         for (int j = 0; j < kLoadBatch; ++j) {
-            at[j] = -1;
-            v[j] = -W;
-            if (w.r < NR) {
-                const int ro = rtab[w.r], co = ctab[w.c];
-                if (ro >= 0 && co >= 0) v[j] = src[ro + co];
-                at[j] = w.r * FP + w.c;
-            }
+            const bool ok = w.r < NR;
+            ro[j] = rtab[ok ? w.r : 0];
+            co[j] = ctab[ok ? w.c : 0];
+            at[j] = ok ? w.r * FP + w.c : -1;
             w.step();
+        }
+        T v[kLoadBatch];
+#pragma unroll
+        for (int j = 0; j < kLoadBatch; ++j) {
+            const bool hit = (ro[j] | co[j]) >= 0;
+            const T x = src[hit ? ro[j] + co[j] : 0];
+            v[j] = hit ? x : -W;
         }
 #pragma unroll
         for (int j = 0; j < kLoadBatch; ++j)
@@ -1304,19 +1309,24 @@ __global__ void __launch_bounds__(kBlock)
     }
     const T inf = tinf<T>();
     __syncthreads();
+    // table reads first, then the loads without branches (a row off the box
+    // loads the box's first value and keeps +inf), then the LDS stores
     for (Walk2 w(threadIdx.x, QW); w.r < DH;) {
-        T v[kLoadBatch];
-        int at[kLoadBatch];
+        int ro[kLoadBatch], co[kLoadBatch], at[kLoadBatch];
 #pragma unroll
         for (int j = 0; j < kLoadBatch; ++j) {
-            at[j] = -1;
-            v[j] = inf;
-            if (w.r < DH) {
-                const int ro = rz[w.r];
-                if (ro >= 0) v[j] = src[ro + cq[w.c]];
-                at[j] = w.r * QW + w.c;
-            }
+            const bool ok = w.r < DH;
+            ro[j] = rz[ok ? w.r : 0];
+            co[j] = cq[ok ? w.c : 0];
+            at[j] = ok ? w.r * QW + w.c : -1;
             w.step();
+        }
+        T v[kLoadBatch];
+#pragma unroll
+        for (int j = 0; j < kLoadBatch; ++j) {
+            const bool hit = ro[j] >= 0;
+            const T x = src[hit ? ro[j] + co[j] : 0];
+            v[j] = hit ? x : inf;
         }
 #pragma unroll
         for (int j = 0; j < kLoadBatch; ++j)
