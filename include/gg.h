@@ -58,9 +58,11 @@ typedef enum {
     GG_FP64 = 0,       /* plain path: FP64 storage and arithmetic                */
     GG_FP32 = 1,       /* mixed path: FP32 storage/arithmetic, FP64 reductions   */
     GG_MIXED_BF16 = 2, /* BF16 convolution operands with FP32 accumulation: not
-                          built (GG_E_UNSUPPORTED); the FP32 path is bound by
-                          vector-ALU issue, not by bytes, so narrower storage of
-                          the predicted function would not shorten the step     */
+                          built (GG_E_UNSUPPORTED); the FP32 path's kernels run
+                          at a fraction of the HBM bandwidth, bound by latency
+                          and instruction issue rather than by bytes, so
+                          narrower storage of the predicted function would not
+                          shorten the step                                      */
     GG_MIXED_FP16 = 3  /* FP16 likewise: GG_E_UNSUPPORTED                        */
 } gg_precision;
 
