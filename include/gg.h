@@ -21,7 +21,12 @@
  *  - Every call returns gg_status; nothing throws across the boundary.  After
  *    an error the text is available from gg_last_error.  A HIP runtime error
  *    poisons the simulation: later calls return GG_E_POISONED (gg_destroy
- *    still works).  Argument errors leave the simulation unchanged.
+ *    still works).  Argument errors leave the simulation unchanged.  The calls
+ *    that advance or replace the state (gg_step, gg_autotune, gg_coarsen,
+ *    gg_load_state, gg_load) check their arguments before they change
+ *    anything; when one fails later, for memory (GG_E_NOMEM) or a size limit
+ *    (GG_E_CAPACITY), its state may be part way replaced, and the simulation
+ *    is poisoned as by a HIP error.
  *  - Host pointers are read or written only during the call; the library
  *    copies inputs and owns all device memory it allocates.
  *  - Work is issued on the HIP stream given to gg_create (NULL: the library
@@ -153,8 +158,8 @@ gg_status gg_create(const gg_config *cfg, const int32_t *labels, int32_t n_grain
 /* Advance n_steps timesteps of normalised length dt (Algorithm 1): Gaussian
  * width sigma = sqrt(2 dt) * n[0] voxels (heat kernel of Eq. Heatequation),
  * kernel radius R = ceil(4 sigma).  Requires R <= 2*ceil(W) and R <= 24.
- * Errors: GG_E_ARG (dt not finite/positive, n_steps < 0, R too large),
- * GG_E_CAPACITY, GG_E_HIP, GG_E_POISONED. */
+ * Errors: GG_E_ARG (dt not finite/positive, n_steps < 0, R too large; nothing
+ * changed), GG_E_CAPACITY / GG_E_NOMEM / GG_E_HIP (poisoned), GG_E_POISONED. */
 gg_status gg_step(gg_sim *sim, double dt, int32_t n_steps);
 
 /* Wait for all issued work. */
@@ -225,7 +230,8 @@ gg_status gg_get_iota(gg_sim *sim, int32_t *out, int64_t cap);
  * values packed grain after grain in id order over the alive grains, and an
  * optional ID-field in the same order (NULL: all -1).  Boxes must satisfy the
  * library's box rule: 1 <= ext[a] <= n[a] - 2P or ext[a] == n[a], 0 <= lo < n.
- * Errors: GG_E_ARG, GG_E_NOMEM, GG_E_HIP. */
+ * Errors: GG_E_ARG (a box breaks the rule, a value is not finite; nothing
+ * changed), GG_E_NOMEM / GG_E_HIP (poisoned). */
 gg_status gg_load_state(gg_sim *sim, const int32_t *lo, const int32_t *ext, const uint8_t *alive,
                         const double *values, const int32_t *iota);
 
@@ -262,8 +268,8 @@ gg_status gg_grain_sdf(gg_sim *sim, int32_t id, int32_t lo[3], int32_t ext[3], d
  * time per grain voxel and returns it.  The simulation advances by those
  * steps; the functions do not depend on the tiling (bit-identical; volumes,
  * sums of per-work-item partial sums, to rounding).
- * Errors: GG_E_ARG (dt not finite/positive, steps_per_candidate < 1),
- * GG_E_CAPACITY, GG_E_HIP. */
+ * Errors: GG_E_ARG (dt not finite/positive, steps_per_candidate < 1; nothing
+ * changed), GG_E_CAPACITY / GG_E_NOMEM / GG_E_HIP (poisoned). */
 gg_status gg_autotune(gg_sim *sim, double dt, int32_t steps_per_candidate, int32_t *lds_bytes,
                       int32_t *small_bytes);
 
@@ -276,7 +282,7 @@ gg_status gg_autotune(gg_sim *sim, double dt, int32_t steps_per_candidate, int32
  * gg_load are identical to those that would have followed the gg_save.
  * Errors: GG_E_ARG (cannot open or write the file, not a checkpoint of this
  * library, a different configuration, a corrupt file; nothing changed),
- * GG_E_NOMEM, GG_E_HIP. */
+ * GG_E_NOMEM / GG_E_HIP (gg_load: poisoned). */
 gg_status gg_save(gg_sim *sim, const char *path);
 gg_status gg_load(gg_sim *sim, const char *path);
 

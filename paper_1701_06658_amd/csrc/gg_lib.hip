@@ -1536,14 +1536,22 @@ gg_status gg_create(const gg_config *cfg, const int32_t *labels, int32_t n_grain
     return GG_OK;
 }
 
+// The calls that advance or replace the state check their arguments before they
+// change anything (GG_E_ARG).  A later failure (memory, capacity) can leave the
+// state part way replaced: it poisons the simulation, as a HIP error does.
+static gg_status state_changed(gg_sim *sim, gg_status st) {
+    if (st == GG_E_NOMEM || st == GG_E_CAPACITY) sim->poisoned = true;
+    return st;
+}
+
 gg_status gg_step(gg_sim *sim, double dt, int32_t n_steps) {
     if (!sim) return GG_E_ARG;
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(sim, GG_E_ARG, "dt must be finite and positive");
     if (n_steps < 0) return fail(sim, GG_E_ARG, "n_steps must be >= 0");
-    return guarded(sim, [&]() {
-        sim->impl->step(dt, n_steps);
-        return GG_OK;
-    });
+    return state_changed(sim, guarded(sim, [&]() {
+                             sim->impl->step(dt, n_steps);
+                             return GG_OK;
+                         }));
 }
 
 gg_status gg_sync(gg_sim *sim) {
@@ -1617,10 +1625,10 @@ gg_status gg_get_iota(gg_sim *sim, int32_t *out, int64_t cap) {
 gg_status gg_load_state(gg_sim *sim, const int32_t *lo, const int32_t *ext, const uint8_t *alive,
                         const double *values, const int32_t *iota) {
     if (!sim || !lo || !ext || !alive || !values) return fail(sim, GG_E_ARG, "NULL argument");
-    return guarded(sim, [&]() {
-        sim->impl->load_state(lo, ext, alive, values, iota);
-        return GG_OK;
-    });
+    return state_changed(sim, guarded(sim, [&]() {
+                             sim->impl->load_state(lo, ext, alive, values, iota);
+                             return GG_OK;
+                         }));
 }
 
 gg_status gg_grain_areas(gg_sim *sim, double *area, double *weighted, int64_t cap) {
@@ -1647,10 +1655,10 @@ gg_status gg_autotune(gg_sim *sim, double dt, int32_t steps_per_candidate, int32
     if (!sim || !lds_bytes || !small_bytes) return fail(sim, GG_E_ARG, "NULL argument");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(sim, GG_E_ARG, "dt must be finite and positive");
     if (steps_per_candidate < 1) return fail(sim, GG_E_ARG, "steps_per_candidate must be >= 1");
-    return guarded(sim, [&]() {
-        sim->impl->autotune(dt, steps_per_candidate, lds_bytes, small_bytes);
-        return GG_OK;
-    });
+    return state_changed(sim, guarded(sim, [&]() {
+                             sim->impl->autotune(dt, steps_per_candidate, lds_bytes, small_bytes);
+                             return GG_OK;
+                         }));
 }
 
 gg_status gg_save(gg_sim *sim, const char *path) {
@@ -1671,19 +1679,19 @@ gg_status gg_save(gg_sim *sim, const char *path) {
 
 gg_status gg_load(gg_sim *sim, const char *path) {
     if (!sim || !path) return fail(sim, GG_E_ARG, "NULL argument");
-    return guarded(sim, [&]() {
-        FILE *f = std::fopen(path, "rb");
-        if (!f) return fail(sim, GG_E_ARG, std::string("cannot open ") + path);
-        try {
-            sim->impl->load(f);
-        } catch (...) {
-            std::fclose(f);
-            throw;
-        }
-        std::fclose(f);
-        sim->impl->grid(sim->n);
-        return GG_OK;
-    });
+    return state_changed(sim, guarded(sim, [&]() {
+                             FILE *f = std::fopen(path, "rb");
+                             if (!f) return fail(sim, GG_E_ARG, std::string("cannot open ") + path);
+                             try {
+                                 sim->impl->load(f);
+                             } catch (...) {
+                                 std::fclose(f);
+                                 throw;
+                             }
+                             std::fclose(f);
+                             sim->impl->grid(sim->n);
+                             return GG_OK;
+                         }));
 }
 
 gg_status gg_coarsen(gg_sim *sim, const int32_t n_new[3]) {
@@ -1700,12 +1708,9 @@ gg_status gg_coarsen(gg_sim *sim, const int32_t n_new[3]) {
         sim->impl->coarsen(n_new);
         return GG_OK;
     });
-    if (st == GG_OK) {
+    if (st == GG_OK)
         for (int a = 0; a < 3; ++a) sim->n[a] = n_new[a];
-    } else if (st != GG_E_ARG && st != GG_E_POISONED) {
-        sim->poisoned = true;  // the state was replaced part way
-    }
-    return st;
+    return state_changed(sim, st);
 }
 
 gg_status gg_keep_intermediates(gg_sim *sim, int32_t on) {

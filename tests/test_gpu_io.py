@@ -116,9 +116,10 @@ class _CountingAllocator:
         hip.hipMalloc.argtypes = [C.POINTER(C.c_void_p), C.c_size_t]
         hip.hipFree.argtypes = [C.c_void_p]
         self.live, self.calls, self.sizes = 0, 0, {}
+        self.dry = False                 # set to refuse every later request
 
         def _alloc(nbytes, stream, user):
-            if fail_after is not None and self.calls >= fail_after:
+            if self.dry or (fail_after is not None and self.calls >= fail_after):
                 return None
             p = C.c_void_p()
             if hip.hipMalloc(C.byref(p), nbytes) != 0:
@@ -168,6 +169,30 @@ def test_caller_allocator_failure_is_reported():
     with pytest.raises(gg.GGError, match="GG_E_NOMEM"):
         _sim(c["labels"], c["W"], c["G"], "fp64", allocator=al.struct, stream=stream.value)
     assert al.calls == 12 and al.live == 0
+
+
+def test_failure_part_way_poisons():
+    # a state-changing call whose allocation fails after its argument checks
+    # (here gg_coarsen) may leave the state part way replaced: GG_E_NOMEM, then
+    # GG_E_POISONED for every later call; gg_destroy still returns every block
+    import ctypes as C
+    import paper_1701_06658_amd as gg
+    hip = C.CDLL("libamdhip64.so")
+    hip.hipStreamCreate.argtypes = [C.POINTER(C.c_void_p)]
+    stream = C.c_void_p()
+    assert hip.hipStreamCreate(C.byref(stream)) == 0
+    c = make_config(1)
+    al = _CountingAllocator()
+    s = _sim(c["labels"], c["W"], c["G"], "fp64", allocator=al.struct, stream=stream.value)
+    s.step(c["dt"], 2)
+    al.dry = True
+    with pytest.raises(gg.GGError, match="GG_E_NOMEM"):
+        s.coarsen((32, 32, 1))
+    for call in (lambda: s.step(c["dt"]), lambda: s.volumes(), lambda: s.coarsen((32, 32, 1))):
+        with pytest.raises(gg.GGError, match="GG_E_POISONED"):
+            call()
+    s.close()
+    assert al.live == 0 and not al.sizes
 
 
 def test_labels_into_device_memory():
