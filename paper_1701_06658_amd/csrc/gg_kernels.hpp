@@ -8,12 +8,12 @@
 //
 // One step is four sweeps over the packed boxes:
 //   k_compare    psi            -> phi^c   (global tiles, top-2 of the covering grains)
-//   k_reinit_xy  phi^c (old box) -> d      (reference values, x and y min-plus, new box)
-//   k_zfused     d              -> t, phi  (z min-plus, band clamp, volume, predictor z pass)
+//   k_reinit_xy  phi^c (old box) -> d      (reference values, x and y spreading sweeps, new box)
+//   k_zfused     d              -> t, phi  (z spreading sweep, band clamp, volume, predictor z pass)
 //   k_conv_xy    t              -> psi     (predictor x and y passes, correction epilogue)
 // The separable Gaussian is applied z, x, y so that its z pass can share the
 // z-line sweep of the re-initialization.  The Euclidean re-initialization
-// variant replaces the min-plus sweeps: k_reinit_xy writes the reference
+// variant replaces the spreading sweeps: k_reinit_xy writes the reference
 // values, k_jacobi takes the Godunov sweeps, k_zfused only clamps.
 //
 // Stencil kernels stage one output tile plus its halo in LDS and read every HBM
@@ -69,14 +69,6 @@ struct Boxes {
 #define GG_SMALL_LDS_BYTES 26624
 #endif
 constexpr int kSmallLdsBytes = GG_SMALL_LDS_BYTES;
-// Small-class limit (and plane-group LDS target) of the re-initialization
-// kinds, in percent of the small class.
-#ifndef GG_ZF_TARGET_PCT
-#define GG_ZF_TARGET_PCT 100
-#endif
-#ifndef GG_RXY_SMALL_PCT
-#define GG_RXY_SMALL_PCT 100
-#endif
 constexpr int kClasses = 2;
 
 struct Totals {
@@ -368,39 +360,6 @@ __device__ __forceinline__ void gauss_run(const T *src, int stride, const T *tp,
             const T g = taps[t];
 #pragma unroll
             for (int q = 0; q < kKB; ++q) acc[q] = mac<T>(acc[q], g, src[(q + t) * stride]);
-        }
-    }
-}
-
-// 1D min-plus pass over KB consecutive outputs: best[q] = min_t |v[q + t]| + |t - K|.
-template <typename T, int KS>
-__device__ __forceinline__ void minplus_run(const T *src, int stride, int K, T best[kKB], bool magnitude) {
-#pragma unroll
-    for (int q = 0; q < kKB; ++q) best[q] = tinf<T>();
-    if constexpr (KS > 0) {
-#pragma unroll
-        for (int i = 0; i < 2 * KS + kKB; ++i) {
-            T v = src[i * stride];
-            if (magnitude) v = fabs(v);
-#pragma unroll
-            for (int q = 0; q < kKB; ++q) {
-                const int t = i - q;
-                if (t >= 0 && t <= 2 * KS) {
-                    const T c = v + T(t < KS ? KS - t : t - KS);
-                    if (c < best[q]) best[q] = c;
-                }
-            }
-        }
-    } else {
-        for (int t = 0; t <= 2 * K; ++t) {
-            const T d = T(t < K ? K - t : t - K);
-#pragma unroll
-            for (int q = 0; q < kKB; ++q) {
-                T v = src[(q + t) * stride];
-                if (magnitude) v = fabs(v);
-                const T c = v + d;
-                if (c < best[q]) best[q] = c;
-            }
         }
     }
 }
@@ -1861,8 +1820,7 @@ __global__ void k_item_counts(Boxes L, long long *cnt, int4 *tilings, unsigned l
         rec[0] = rec[1] = make_int4(0, 0, 0, 0);
         if (L.alive[k] && (q != KIND_JAC || jac)) {
             const int *e = L.ext + 3 * k;
-            const int sq = q == KIND_ZF ? small / 100 * GG_ZF_TARGET_PCT : (q == KIND_RXY ? small / 100 * GG_RXY_SMALL_PCT : small);
-            const Tiling t = kind_tiling(q, e, R, K, budget, sq);
+            const Tiling t = kind_tiling(q, e, R, K, budget, small);
             rec[0] = make_int4(t.nxs, t.nys, t.tx, t.ty);
             rec[1] = make_int4(t.nb, 0, 0, 0);
             if (t.nxs == 0) {
@@ -1870,7 +1828,7 @@ __global__ void k_item_counts(Boxes L, long long *cnt, int4 *tilings, unsigned l
             } else {
                 const long long n = tiling_items(q, e, t);
                 const long long need = tiling_need(q, t, R, K);
-                const int cls = need <= sq ? 0 : 1;
+                const int cls = need <= small ? 0 : 1;
                 c[k] = n;
                 c[(1LL + cls) * G + k] = n;
                 need_c[cls] = (unsigned long long)need;
