@@ -3,7 +3,10 @@
 * an exact +-SDF pair: with psi_1 = -psi_0 the corrector returns psi_0 itself,
   (psi - (-psi)) / 2 = psi, bit for bit (the convolution of -f is -conv(f));
 * ties go to the lowest id, in the labels and in the ID-field: two grains with
-  identical functions never give the larger id.
+  identical functions never give the larger id;
+* the sampling rule across the periodic boundary: a box that wraps around
+  the grid's edge meets the other grain at the right global voxels, checked
+  through an explicit global-index map (-W outside a box).
 """
 import numpy as np
 
@@ -53,3 +56,27 @@ def test_ties_go_to_the_lowest_id():
     # no tie for the twins themselves: each one's best other inside is the other twin
     assert np.all(o.iota(2)[inside] == 1) and np.all(o.iota(1)[inside] == 2)
     assert np.all(o.iota(2)[~inside] == 0) and np.all(o.iota(1)[~inside] == 0)
+
+
+def test_corrector_sampling_across_the_periodic_boundary():
+    # a partial box that wraps around x and y against a whole-grid grain: the
+    # corrector's other-grain maximum, checked voxel by voxel through an
+    # explicit global-index map (outside a box a grain reads -W)
+    N, W = 40, 5.0
+    rng = np.random.default_rng(17)
+    o = Oracle(np.zeros((1, N, N), np.int32), W, G=2)
+    f0 = rng.uniform(-W, W, size=(1, N, N))
+    lo1, ext1 = np.array([N - 6, N - 3, 0]), np.array([18, 16, 1])
+    f1 = rng.uniform(-W, W, size=(1, ext1[1], ext1[0]))
+    o.set_grain(0, True, [0, 0, 0], [N, N, 1], f0)
+    o.set_grain(1, True, lo1, ext1, f1)
+    o.keep_intermediates(True)
+    o.step(config_dt(1.5, N))
+    psi0, psi1 = o.psi(0)[0], o.psi(1)[0]
+    c0, c1 = o.phic(0)[0], o.phic(1)[0]
+    other = np.full((N, N), -W)                       # grain 1 seen on the global grid
+    ys = (np.arange(ext1[1]) + lo1[1]) % N
+    xs = (np.arange(ext1[0]) + lo1[0]) % N
+    other[np.ix_(ys, xs)] = psi1
+    assert np.array_equal(c0, 0.5 * (psi0 - other))
+    assert np.array_equal(c1, 0.5 * (psi1 - psi0[np.ix_(ys, xs)]))
