@@ -55,7 +55,7 @@ typedef enum {
     GG_E_SMALLBUF = 5,    /* caller's output buffer is too small                  */
     GG_E_NUMERIC = 6,     /* reserved: non-finite inputs are argument errors      */
     GG_E_POISONED = 7,    /* an earlier HIP error poisoned this simulation         */
-    GG_E_UNSUPPORTED = 8, /* valid request this build does not implement          */
+    GG_E_UNSUPPORTED = 8, /* valid request the library does not implement         */
     GG_E_NODEVICE = 9     /* no usable gfx950 device                              */
 } gg_status;
 
@@ -149,7 +149,7 @@ typedef struct {
  * NULL (hipMalloc / hipFree) or the caller's allocator, copied; it needs a
  * non-NULL hip_stream.  On success *out owns the simulation.
  * Errors: GG_E_ARG (bad config/labels/allocator), GG_E_UNSUPPORTED (a
- * precision this build does not implement), GG_E_NODEVICE, GG_E_NOMEM,
+ * precision the library does not implement), GG_E_NODEVICE, GG_E_NOMEM,
  * GG_E_HIP. */
 gg_status gg_create(const gg_config *cfg, const int32_t *labels, int32_t n_grains,
                     const double *quat, const double *energy_density, void *hip_stream,
