@@ -92,6 +92,22 @@ def test_fp64_config2_first_steps():
         _check_fp64(o, s, c["W"], f"cfg2 step {step}")
 
 
+def test_fp64_config2_full_trajectory():
+    # the whole 50-step run of the 128^3 / 1000-grain workload, state checked
+    # at steps 10, 25 and 50 and labels at the end
+    c = make_config(2)
+    o, s = _pair(c["labels"], c["W"], c["G"])
+    done = 0
+    for upto in (10, 25, c["steps"]):
+        o.step(c["dt"], upto - done)
+        s.step(c["dt"], upto - done)
+        done = upto
+        _check_fp64(o, s, c["W"], f"cfg2 step {done}")
+        print(f"[cfg2 step {done}] alive {s.alive_count()}", flush=True)
+    assert np.array_equal(o.labels(), s.labels())
+    s.close()
+
+
 @pytest.mark.parametrize("dim,N,R0", [(2, 96, 20.0), (3, 48, 12.0)])
 def test_fp64_ball_with_full_periodic_matrix(dim, N, R0):
     # grain 0 spans the whole periodic grid (its box wraps on every axis)
