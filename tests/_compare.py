@@ -57,7 +57,8 @@ def compare_states(a, b, n, W, band_only=False, grains=None):
 
 
 def top2_gap(state, n, W):
-    """Per voxel: gap between the largest and second largest grain value (global grid)."""
+    """Per voxel: gap between the largest and second largest grain value (global
+    grid); +inf where fewer than two grains cover the voxel (no tie possible)."""
     n = tuple(int(v) for v in n)
     shape = (n[2], n[1], n[0])
     m1 = np.full(shape, -np.inf)
@@ -73,4 +74,7 @@ def top2_gap(state, n, W):
         new2 = np.where(v > cur1, cur1, np.maximum(cur2, v))
         m1[gz, gy, gx] = new1
         m2[gz, gy, gx] = new2
-    return m1 - m2
+    gap = np.full(shape, np.inf)
+    two = np.isfinite(m2)
+    gap[two] = m1[two] - m2[two]
+    return gap

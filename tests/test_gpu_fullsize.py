@@ -8,7 +8,8 @@ step (identical inputs), and the sampled grain's new function is compared with
 the GPU's: FP64 to 1e-10 voxel, FP32 to 2e-3 voxel in the band with the same
 box and a volume within 0.5% (the taxicab scheme in both precisions, and the
 Euclidean variant in FP32), on the first step and on a later one (step 41 of
-the 256^3 workload, step 26 of the 128^3 / 1000-grain one).  The two 512^3 /
+the 256^3 workload, step 26 of the 128^3 / 1000-grain one), and so is the
+ownership inside the sampled grains' new boxes.  The two 512^3 /
 50000-grain workloads with the predictor correction (misorientation weights;
 the magnetic bulk term) get the same sampled comparison on their second step,
 with the GPU's ID-fields loaded beside the functions.  Whole-state properties
@@ -18,7 +19,7 @@ voxel gets a label.
 import numpy as np
 import pytest
 
-from _compare import compare_states
+from _compare import _sample as _sample_phi, compare_states, top2_gap
 from oracle import Oracle
 from synth import make_config
 
@@ -50,6 +51,7 @@ def test_sampled_grains_full_workload(index, precision, redistance, before):
     s.step(c["dt"])
     s1 = s.state()
     v1 = s.volumes()
+    lab_gpu = s.labels()
     s.close()
     alive0 = np.nonzero(s0["alive"])[0]
     lo0, ext0 = np.asarray(s0["lo"]), np.asarray(s0["ext"])
@@ -77,6 +79,34 @@ def test_sampled_grains_full_workload(index, precision, redistance, before):
               f"volume {vo[k]:.2f} vs {v1[k]:.2f} ({len(hood)} grains stepped)", flush=True)
         assert r["box_mismatch"] == 0 and r["max_abs"] <= tol
         assert abs(v1[k] - vo[k]) <= (1e-9 if precision == "fp64" else 5e-3 * max(vo[k], 50.0))
+    # ownership inside the sampled grains' boxes of the step's start, at the
+    # voxels some grain owns (a positive function): that grain's box of the
+    # step's start holds the voxel, so it was stepped.  Identical in FP64; in
+    # FP32 wherever the oracle's top two values are at least 4e-3 apart
+    lab_orc = o.labels()
+    gap = top2_gap(a, n, W) if precision != "fp64" else None
+    checked = 0
+    for k in sample:
+        lo, ext = lo0[k], ext0[k]
+        zs = (np.arange(ext[2]) + lo[2]) % n[2]
+        ys = (np.arange(ext[1]) + lo[1]) % n[1]
+        xs = (np.arange(ext[0]) + lo[0]) % n[0]
+        Z, Y, X = [v.ravel() for v in np.meshgrid(zs, ys, xs, indexing="ij")]
+        lab = lab_orc[Z, Y, X]
+        owned = np.zeros(lab.shape, bool)
+        for j in np.unique(lab):
+            if j < 0 or not a["alive"][j]:
+                continue
+            m = lab == j
+            owned[m] = _sample_phi(a, int(j), X[m], Y[m], Z[m], n, -W) > 0
+        same = lab == lab_gpu[Z, Y, X]
+        if gap is not None:
+            same |= gap[Z, Y, X] < 4e-3
+        same |= ~owned
+        checked += int(owned.sum())
+        assert same.all(), (int(k), int((~same).sum()))
+    print(f"[workload {index} step {before + 1} {precision} {redistance}] ownership equal on {checked} owned voxels",
+          flush=True)
 
 
 @pytest.mark.parametrize("index", [3, 4, 5])
