@@ -1,6 +1,7 @@
 """Argument errors on a live simulation (GPU, through the C ABI): each call is
 refused with GG_E_ARG (or GG_E_SMALLBUF) and leaves the state unchanged, so the
-simulation keeps stepping exactly as one that never saw the bad call."""
+simulation keeps stepping exactly as one that never saw the bad call.  Among
+them: a state with a non-finite value and one whose box breaks the box rule."""
 import ctypes as C
 
 import numpy as np
@@ -19,7 +20,15 @@ def test_refused_calls_change_nothing():
     b = gg.Simulation(c["labels"], c["W"], G=c["G"], precision="fp64")
     a.step(c["dt"], 2)
     b.step(c["dt"], 2)
+    st = a.state()
+    k0 = int(np.nonzero(st["alive"])[0][0])
+    phis_nan = [None if p is None else p.copy() for p in st["phi"]]
+    phis_nan[k0].flat[0] = np.nan                     # a non-finite value
+    ext_bad = st["ext"].copy()
+    ext_bad[k0, 0] = c["N"] - 1                       # longer than n - 2P, not the whole axis
     bad = [
+        lambda: a.load_state(st["alive"], st["lo"], st["ext"], phis_nan),
+        lambda: a.load_state(st["alive"], st["lo"], ext_bad, st["phi"]),
         lambda: a.step(config_dt(20.0, c["N"])),      # kernel radius beyond 2P
         lambda: a.step(-1.0),
         lambda: a.step(float("nan")),
