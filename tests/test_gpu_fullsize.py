@@ -14,7 +14,7 @@ ownership inside the sampled grains' new boxes.  The two 512^3 /
 the magnetic bulk term) get the same sampled comparison on their second step,
 with the GPU's ID-fields loaded beside the functions.  Whole-state properties
 are checked at every size: volumes sum to the grid volume within 0.5% and every
-voxel gets a label.
+voxel gets a label, also after the 256^3 workload is coarsened to 128^3.
 """
 import numpy as np
 import pytest
@@ -190,3 +190,24 @@ def test_sampled_grains_physics_workloads(index):
               f"volume {vo[k]:.2f} vs {v1[k]:.2f} ({len(hood)} grains stepped)", flush=True)
         assert r["box_mismatch"] == 0 and r["max_abs"] <= 2e-3
         assert abs(v1[k] - vo[k]) <= 5e-3 * max(vo[k], 50.0)
+
+
+def test_full_workload_coarsening():
+    # the 256^3 workload coarsened to 128^3 after 5 steps, then stepped on:
+    # volumes keep summing to the grid, every voxel gets a label
+    import paper_1701_06658_amd as gg
+    c = make_config(3)
+    s = gg.Simulation(c["labels"], c["W"], G=c["G"], precision=c["precision"])
+    s.step(c["dt"], 5)
+    alive = s.alive_count()
+    s.coarsen((128, 128, 128))
+    for step in range(3):
+        V = s.volumes()
+        print(f"[workload 3 coarsened, step {step}] sum V / 128^3 - 1 = {V.sum() / 128 ** 3 - 1:.2e}, "
+              f"alive {s.alive_count()} of {alive}", flush=True)
+        assert abs(V.sum() - 128 ** 3) <= 5e-3 * 128 ** 3 and np.all(V >= 0)
+        s.step(c["dt"] * 4.0)           # the same stencil on the coarser grid
+    lab = s.labels()
+    assert lab.shape == (128, 128, 128) and lab.min() >= 0 and lab.max() < c["G"]
+    assert s.alive_count() <= alive
+    s.close()
