@@ -123,3 +123,43 @@ def test_step_stats_struct_matches_header():
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     names = re.findall(r"\b(?:int32_t|int64_t|double)\s+(\w+)", body)
     assert names == [f[0] for f in gg.StepStats._fields_]
+
+
+def test_a_c_program_compiles_links_and_fails_loudly_without_a_device(lib, tmp_path):
+    # the header is plain C11 (no warnings), a C program links against the
+    # library, and without a gfx950 device gg_create refuses with a message
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc is not available")
+    from paper_1701_06658_amd import gg
+    src = tmp_path / "use.c"
+    src.write_text(r"""
+#include <stdio.h>
+#include <stdlib.h>
+#include "gg.h"
+int main(void) {
+    int32_t *labels = calloc(24 * 24 * 24, sizeof(int32_t));
+    gg_config cfg = {0};
+    cfg.dim = 3; cfg.n[0] = cfg.n[1] = cfg.n[2] = 24; cfg.band = 4.0; cfg.precision = GG_FP32;
+    gg_sim *sim = NULL;
+    gg_status st = gg_create(&cfg, labels, 1, NULL, NULL, NULL, NULL, &sim);
+    printf("%d %s|%s\n", (int)st, gg_status_str(st), gg_last_error(NULL));
+    if (st == GG_OK) gg_destroy(sim);
+    free(labels);
+    return st == GG_OK ? 0 : 3;
+}
+""")
+    exe = str(tmp_path / "use")
+    libdir = os.path.dirname(gg.LIB_PATH)
+    r = subprocess.run(["gcc", "-std=c11", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(ROOT, "include"),
+                        str(src), "-L", libdir, "-lgg", "-Wl,-rpath," + libdir, "-o", exe],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    if out.returncode == 0:
+        pytest.skip("a gfx950 device is present: the no-device path is not reachable")
+    assert out.returncode == 3
+    code, rest = out.stdout.split(" ", 1)
+    assert int(code) == 9                              # GG_E_NODEVICE
+    assert "device" in rest.split("|", 1)[1]           # the reason, from gg_last_error(NULL)
