@@ -1,10 +1,13 @@
 """Throughput of the level-set grain-growth step on one MI355X.
 
 Prints ONE JSON line: grain-voxel updates per second of the batched mixed
-(FP32) step on the 3D 256^3 / 8000-grain lognormal workload, the plain FP64
-path on the same inputs, the roofline of the dominant kernel (HIP events on
-the library's stream, algorithmic bytes), and the FP64 CPU oracle timed on a
-bounded sample of the same workload.
+(FP32) step on the 3D 256^3 / 8000-grain lognormal workload (captured HIP
+graphs, no per-kernel timing in the timed region), the plain FP64 path on the
+same inputs, the roofline of the dominant kernel (per-kernel HIP events of a
+second, profiled run of the same steps; algorithmic bytes), the whole step
+against the HBM roofline on the step's algorithmic bytes, a measured streaming
+copy beside the published peak, and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 3]
 """
@@ -21,23 +24,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-SOURCES = [os.path.join(ROOT, "paper_1701_06658_amd", "csrc", f) for f in ("gg_kernels.hpp", "gg_lib.hip")]
+SOURCES = [os.path.join(ROOT, "paper_1701_06658_amd", "csrc", f)
+           for f in ("gg_kernels.hpp", "gg_march.hpp", "gg_lib.hip")]
 PROFILES = os.path.join(ROOT, "profiles")
 
 # Algorithmic bytes per grain voxel of one launch, by kernel class, in units of
-# the stored value size s (plus fixed extra bytes): every stencil kernel reads
-# its input box values once and writes its output box values once.
-ALG_BYTES = {
-    "conv_xy": (2, 0), "conv_z": (2, 0), "compare": (2, 0),
-    "reinit_xy": (2, 0), "reinit_z": (2, 0),
-}
-# with the predictor correction the xy pass (its epilogue) also reads phi and the
-# ID-field, the corrector writes the ID-field and the re-initialization carries
-# it over
-ALG_BYTES_PHYS = {
-    "conv_xy": (3, 4), "conv_z": (2, 0), "compare": (2, 4),
-    "reinit_xy": (2, 8), "reinit_z": (2, 0),
-}
+# the stored value size s (plus fixed extra bytes): every sweep reads its input
+# box values once and writes its output box values once.  With the predictor
+# correction the corrector writes the ID-field and the predictor reads it (the
+# re-initialization's carrying of the ID-field to the new boxes is not counted:
+# it is this design's, not the method's).
+ALG_BYTES = {"predict": (2, 0), "compare": (2, 0), "reinit": (2, 0)}
+ALG_BYTES_PHYS = {"predict": (2, 4), "compare": (2, 4), "reinit": (2, 0)}
 
 
 def log(*a):
@@ -51,41 +49,54 @@ def euclid_sweeps(dim, W):
     return K + (K & 1)
 
 
-def run_gpu(cfg, precision, steps, warmup, copy_probe=False, redistance="taxicab", autotune=False):
+def step_alg_bytes(s_bytes, physics):
+    """Algorithmic bytes per grain voxel of a whole step: three sweeps, each
+    reading and writing the box values once (+ the ID-field written by the
+    corrector and read by the predictor with the correction)."""
+    return 6 * s_bytes + (8 if physics else 0)
+
+
+def _phys(cfg):
     import paper_1701_06658_amd as gg
-    phys = {}
     if cfg.get("physics") == "anisotropic":
-        phys = dict(physics=gg.PHYS_MISORIENTATION, quat=cfg["quat"], theta_c_deg=cfg["theta_c_deg"])
-    elif cfg.get("physics") == "magnetic":
-        phys = dict(physics=gg.PHYS_BULK, energy=cfg["energy"], voxel_m=cfg["h_phys"],
-                    gamma_max=cfg["gamma_max"])
+        return dict(physics=gg.PHYS_MISORIENTATION, quat=cfg["quat"], theta_c_deg=cfg["theta_c_deg"])
+    if cfg.get("physics") == "magnetic":
+        return dict(physics=gg.PHYS_BULK, energy=cfg["energy"], voxel_m=cfg["h_phys"], gamma_max=cfg["gamma_max"])
+    return {}
+
+
+def make_sim(cfg, precision, redistance, batched, order_size=False):
+    import paper_1701_06658_amd as gg
+    return gg.Simulation(cfg["labels"], cfg["W"], G=cfg["G"], precision=precision, redistance=redistance,
+                         batched=batched, order_size=order_size, **_phys(cfg))
+
+
+def run_gpu(cfg, precision, steps, warmup, redistance="taxicab", batched=True, order_size=False,
+            autotune=False, copy_probe=False):
+    """Timed run: warm-up steps, then `steps` steps between stream
+    synchronisations, with no per-kernel timing."""
     t0 = time.perf_counter()
-    sim = gg.Simulation(cfg["labels"], cfg["W"], G=cfg["G"], precision=precision, redistance=redistance, **phys)
+    sim = make_sim(cfg, precision, redistance, batched, order_size)
     sim.sync()
-    log(f"[bench] {precision}: created in {time.perf_counter() - t0:.2f} s")
+    log(f"[bench] {precision} batched={batched}: created in {time.perf_counter() - t0:.2f} s")
     tuned = None
     if autotune:
-        # the tuner's steps (one per candidate tiling) are warm-up steps
+        # the tuner's steps (one per candidate schedule) are warm-up steps
         tuned = sim.autotune(cfg["dt"], 1)
-        log(f"[bench] {precision}: autotuned LDS budgets {tuned}")
+        log(f"[bench] {precision}: autotuned schedule {tuned}")
     if warmup:
         sim.step(cfg["dt"], warmup)
     sim.sync()
     gv0 = sim.stats()["total_grain_voxels"]
-    sim.profile(True)
-    sim.sync()
     t0 = time.perf_counter()
     sim.step(cfg["dt"], steps)
     sim.sync()
     dt = time.perf_counter() - t0
     st = sim.stats()
-    kt = sim.kernel_times()
-    sim.profile(False)
     gv = st["total_grain_voxels"] - gv0
-    out = dict(value=gv / dt, ms_per_step=1e3 * dt / steps, grain_voxels=gv, alive=st["alive"],
-               superposition=st["superposition"], kernels=kt, physics=bool(phys),
-               sweeps=euclid_sweeps(cfg["dim"], cfg["W"]) if redistance == "euclid" else 0, tuned=tuned)
-    log(f"[bench] {precision}: {steps} steps in {dt:.3f} s, {out['value']:.3e} gv/s, "
+    out = dict(value=gv / dt, ms_per_step=1e3 * dt / steps, device_ms_per_step=st["last_step_ms"],
+               grain_voxels=gv, alive=st["alive"], superposition=st["superposition"], tuned=tuned)
+    log(f"[bench] {precision} batched={batched}: {steps} steps in {dt:.4f} s, {out['value']:.3e} gv/s, "
         f"alive {st['alive']}")
     if copy_probe:
         # one state download after the timed steps: k_convert reads every stored
@@ -99,27 +110,18 @@ def run_gpu(cfg, precision, steps, warmup, copy_probe=False, redistance="taxicab
     return out
 
 
-def run_coarsen(cfg, precision, warmup, n_new):
-    """One gg_coarsen of the workload after `warmup` steps: wall time with the
-    stream synchronised on both sides, and the grain voxels before and after."""
-    import paper_1701_06658_amd as gg
-    sim = gg.Simulation(cfg["labels"], cfg["W"], G=cfg["G"], precision=precision)
-    sim.step(cfg["dt"], max(warmup, 1))
-    sim.sync()
-    before = sim.stats()["grain_voxels"]
-    nn = (n_new, n_new, n_new) if cfg["dim"] == 3 else (n_new, n_new, 1)
-    t0 = time.perf_counter()
-    sim.coarsen(nn)
-    sim.sync()
-    ms = 1e3 * (time.perf_counter() - t0)
-    # one step on the new grid: its grain voxels are the coarsened layout's
-    sim.step(cfg["sigma"] ** 2 / (2.0 * n_new ** 2), 1)
-    after = sim.stats()["grain_voxels"]
-    alive = sim.alive_count()
+def run_profiled(cfg, precision, steps, warmup, redistance="taxicab", order_size=False):
+    """The same steps again on a fresh simulation with per-kernel HIP events
+    (plain launches)."""
+    sim = make_sim(cfg, precision, redistance, False, order_size)
+    if warmup:
+        sim.step(cfg["dt"], warmup)
+    sim.profile(True)
+    sim.step(cfg["dt"], steps)
+    kt = sim.kernel_times()
+    sim.profile(False)
     sim.close()
-    log(f"[bench] coarsen {cfg['n'][0]} -> {n_new}: {ms:.2f} ms, {before} -> {after} grain voxels")
-    return dict(n_new=n_new, ms=ms, grain_voxels_before=before, grain_voxels_after=after, alive_after=alive,
-                gv_per_s=(before + after) / (ms * 1e-3))
+    return kt
 
 
 def source_digest():
@@ -133,9 +135,9 @@ def source_digest():
 
 
 def recorded_traffic(kernel, precision, workload):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (profiles/traffic_<kernel>_<workload>_<precision>.md), or None when the
-    summary is missing or was taken from other kernel sources."""
+    """Counter-measured HBM bytes per grain voxel of `kernel` from the committed
+    summary profiles/traffic_<kernel>_<workload>_<precision>.md, or None when
+    the summary is missing or was taken from other kernel sources."""
     path = os.path.join(PROFILES, f"traffic_{kernel}_{workload}_{precision}.md")
     if not os.path.exists(path):
         return None
@@ -148,40 +150,73 @@ def recorded_traffic(kernel, precision, workload):
     if fields.get("source_sha256") != source_digest():
         return None
     try:
-        return float(fields["hbm_bytes_per_launch"])
+        return float(fields["hbm_bytes_per_gv"])
     except (KeyError, ValueError):
         return None
 
 
-def roofline(res, s_bytes):
-    table = dict(ALG_BYTES_PHYS if res["physics"] else ALG_BYTES)
-    if res["sweeps"]:
+def roofline(kt, s_bytes, physics, sweeps=0, workload=None, precision=None):
+    """Per-kernel achieved GB/s of algorithmic bytes (HIP-event span times)
+    and the dominant kernel's roofline entry."""
+    table = dict(ALG_BYTES_PHYS if physics else ALG_BYTES)
+    if sweeps:
         # each Jacobi sweep of the Euclidean variant reads and writes every value
         # once; one timed span holds all sweeps of a step
-        table["reinit_sweep"] = (2 * res["sweeps"], 0)
+        table["reinit_sweep"] = (2 * sweeps, 0)
     best = None
     per = {}
     for name, (mult, extra) in table.items():
-        k = res["kernels"][name]
-        if not k["launches"] or k["ms"] <= 0:
+        k = kt[name]
+        if not k["launches"] or k["ms"] <= 0 or not k["voxels"]:
             continue
-        bytes_alg = (mult * s_bytes + extra) * k["voxels"]
+        bpv = mult * s_bytes + extra
+        bytes_alg = bpv * k["voxels"]
         avg_ms = k["ms"] / k["launches"]
         gbs = bytes_alg / (k["ms"] * 1e-3) / 1e9
-        per[name] = dict(avg_ms=avg_ms, gbs=gbs, bytes_per_launch=bytes_alg / k["launches"], launches=k["launches"])
-        if best is None or k["ms"] > res["kernels"][best]["ms"]:
+        rec = recorded_traffic(name, precision, workload) if workload else None
+        per[name] = dict(avg_ms=avg_ms, gbs=gbs, bytes_per_launch=bytes_alg / k["launches"],
+                         launches=k["launches"], voxels_per_launch=k["voxels"] / k["launches"],
+                         alg_bytes_per_gv=bpv, traffic_bytes_per_gv=rec,
+                         traffic_over_algorithmic=(rec / bpv) if rec else None)
+        if best is None or k["ms"] > kt[best]["ms"]:
             best = name
     r = per[best]
+    traffic = r["traffic_bytes_per_gv"] * r["voxels_per_launch"] if r["traffic_bytes_per_gv"] else None
     return dict(bound="hbm", kernel=best, achieved=r["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=r["gbs"] / HBM_PEAK_GBS, traffic=None,
+                frac=r["gbs"] / HBM_PEAK_GBS, traffic=traffic,
+                traffic_over_algorithmic=r["traffic_over_algorithmic"],
                 avg_launch_ms=r["avg_ms"], alg_bytes_per_launch=r["bytes_per_launch"], launches=r["launches"],
-                per_kernel={k: round(v["gbs"], 1) for k, v in per.items()})
+                per_kernel={k: dict(GBs=round(v["gbs"], 1), avg_ms=round(v["avg_ms"], 5),
+                                    traffic_over_algorithmic=v["traffic_over_algorithmic"])
+                            for k, v in per.items()})
+
+
+def copy_peak(nbytes=2 << 30, reps=20):
+    """Measured streaming copy on the device (read + write bytes per second of
+    a device-to-device copy of `nbytes`), beside the published HBM peak."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return dict(GBs=2.0 * nbytes / (ms * 1e-3) / 1e9, bytes=nbytes, kind="torch device-to-device copy")
 
 
 def cpu_baseline(index, threads=None):
     """FP64 oracle on a bounded sample: one step of a density-matched cut of the
     workload (128^3 on all host threads; 64^3 on one thread)."""
-    from oracle import Oracle, num_threads, set_num_threads
+    from oracle import ORACLE_CFLAGS, Oracle, num_threads, set_num_threads
     from synth import make_config
     N = None if index == 1 else (64 if threads == 1 else 128)
     G = None if index == 1 else int(round({2: 1000, 3: 1000, 4: 781, 5: 781}[index] * (N / 128) ** 3))
@@ -205,24 +240,26 @@ def cpu_baseline(index, threads=None):
         set_num_threads(all_threads)
     return dict(value=gv / dt, unit="grain-voxel updates/s", cores=used, kind="oracle",
                 sample=f"1 FP64 oracle step of a density-matched {c['N']}^{c['dim']} cut with "
-                       f"{c['G']} grains of workload {index} ({gv} grain voxels, {dt:.2f} s)")
+                       f"{c['G']} grains of workload {index} ({gv} grain voxels, {dt:.2f} s); "
+                       f"gcc {' '.join(ORACLE_CFLAGS)}")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--precision", default=None, help="fp32 (mixed) or fp64 (plain)")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-profile", action="store_true", help="skip the profiled per-kernel run")
+    ap.add_argument("--order-size", action="store_true", help="per-grain kernels take the largest boxes first")
     ap.add_argument("--autotune", action="store_true",
-                    help="choose the tiling's LDS budgets with gg_autotune before the warm-up steps")
-    ap.add_argument("--coarsen", type=int, default=0, metavar="N_NEW",
-                    help="also time one grid coarsening of the workload onto N_NEW voxels per axis")
+                    help="choose the launch schedule with gg_autotune before the warm-up steps")
     ap.add_argument("--redistance", default="taxicab", choices=["taxicab", "euclid"],
                     help="re-initialization scheme: the method's taxicab one or the Euclidean variant")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-copy", action="store_true", help="skip the streaming-copy measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, run the library's state download once: a plain "
                          "streaming kernel of known size (reference for profiler byte counters)")
@@ -235,9 +272,13 @@ def main():
     cfg = make_config(args.config)
     log(f"[bench] inputs {cfg['name']}: {cfg['G']} grains in {time.perf_counter() - t0:.1f} s")
     precision = args.precision or cfg["precision"]
-    main_res = run_gpu(cfg, precision, args.steps, args.warmup, copy_probe=args.copy_probe,
-                       redistance=args.redistance, autotune=args.autotune)
+    physics = bool(_phys(cfg))
+    main_res = run_gpu(cfg, precision, args.steps, args.warmup, redistance=args.redistance, batched=True,
+                       order_size=args.order_size, autotune=args.autotune, copy_probe=args.copy_probe)
     s_bytes = 4 if precision == "fp32" else 8
+    workload = ("3d256_8000g" if args.config == 3 else f"config{args.config}") + (
+        "_euclid" if args.redistance == "euclid" else "")
+    bpg = step_alg_bytes(s_bytes, physics)
     line = {
         "metric": "grain-voxel updates/s per step (mixed batched vs FP64 plain) + %HBM roofline",
         "value": main_res["value"],
@@ -253,24 +294,39 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["name"], "grid": list(cfg["n"]), "grains": cfg["G"],
                    "sigma_voxels": cfg["sigma"], "band_voxels": cfg["W"],
-                   "precision": precision, "redistance": args.redistance, "alive_after": main_res["alive"],
+                   "precision": precision, "redistance": args.redistance, "batched": True,
+                   "order_size": bool(args.order_size), "alive_after": main_res["alive"],
                    "superposition": round(main_res["superposition"], 3)},
-        "roofline": roofline(main_res, s_bytes),
+        "step_roofline": {"alg_bytes_per_gv": bpg, "achieved": main_res["value"] * bpg / 1e9,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": main_res["value"] * bpg / 1e9 / HBM_PEAK_GBS,
+                          "device_ms_per_step": main_res["device_ms_per_step"]},
     }
-    rl = line["roofline"]
-    workload = ("3d256_8000g" if args.config == 3 else f"config{args.config}") + (
-        "_euclid" if args.redistance == "euclid" else "")
-    rl["traffic"] = recorded_traffic(rl["kernel"], precision, workload)
+    sweeps = euclid_sweeps(cfg["dim"], cfg["W"]) if args.redistance == "euclid" else 0
+    if not args.no_profile:
+        kt = run_profiled(cfg, precision, args.steps, args.warmup, redistance=args.redistance,
+                          order_size=args.order_size)
+        line["roofline"] = roofline(kt, s_bytes, physics, sweeps, workload, precision)
+    plain32 = run_gpu(cfg, precision, args.steps, args.warmup, redistance=args.redistance, batched=False,
+                      order_size=args.order_size)
+    line["plain_launches"] = dict(value=plain32["value"], ms_per_step=plain32["ms_per_step"],
+                                  batched_speedup=main_res["value"] / plain32["value"])
     if not args.no_plain and precision != "fp64":
-        plain = run_gpu(cfg, "fp64", args.steps, args.warmup, redistance=args.redistance, autotune=args.autotune)
+        plain = run_gpu(cfg, "fp64", args.steps, args.warmup, redistance=args.redistance, batched=False,
+                        order_size=args.order_size)
         line["plain_fp64"] = dict(value=plain["value"], ms_per_step=plain["ms_per_step"],
-                                  roofline=roofline(plain, 8), mixed_speedup=main_res["value"] / plain["value"])
+                                  step_roofline_frac=plain["value"] * step_alg_bytes(8, physics) / 1e9 / HBM_PEAK_GBS,
+                                  mixed_speedup=main_res["value"] / plain["value"])
+        if not args.no_profile:
+            kt64 = run_profiled(cfg, "fp64", args.steps, args.warmup, redistance=args.redistance,
+                                order_size=args.order_size)
+            line["plain_fp64"]["roofline"] = roofline(kt64, 8, physics, sweeps, workload, "fp64")
     if args.autotune:
-        line["tuning"] = {"lds_bytes": main_res["tuned"][0], "small_class_bytes": main_res["tuned"][1]}
+        line["tuning"] = main_res["tuned"]
     if args.copy_probe:
         line["copy_probe"] = main_res["copy_probe"]
-    if args.coarsen:
-        line["coarsen"] = run_coarsen(cfg, precision, args.warmup, args.coarsen)
+    if not args.no_copy:
+        line["copy_peak"] = copy_peak()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.config)
         line["cpu_baseline_1thread"] = cpu_baseline(args.config, threads=1)

@@ -30,9 +30,13 @@
  *  - Host pointers are read or written only during the call; the library
  *    copies inputs and owns all device memory it allocates.
  *  - Work is issued on the HIP stream given to gg_create (NULL: the library
- *    creates its own).  gg_step returns when the steps have been issued and
- *    the layout bookkeeping of the last step has been read back; query calls
- *    synchronise the stream.
+ *    creates its own).  A step's launch geometry is fixed (one work group per
+ *    grain or per global tile) and its bookkeeping stays on the device, so the
+ *    host reads nothing back between steps.  With gg_config.batched == 0,
+ *    gg_step returns when its steps have finished; with batched != 0 it
+ *    returns once the steps have been queued (as replays of captured HIP
+ *    graphs, one per step) and the next call on the simulation waits for them.
+ *    Query calls synchronise the stream.
  */
 #ifndef GG_H
 #define GG_H
@@ -63,11 +67,10 @@ typedef enum {
     GG_FP64 = 0,       /* plain path: FP64 storage and arithmetic                */
     GG_FP32 = 1,       /* mixed path: FP32 storage/arithmetic, FP64 reductions   */
     GG_MIXED_BF16 = 2, /* BF16 convolution operands with FP32 accumulation: not
-                          built (GG_E_UNSUPPORTED); the FP32 path's kernels run
-                          at a fraction of the HBM bandwidth, bound by latency
-                          and instruction issue rather than by bytes, so
-                          narrower storage of the predicted function would not
-                          shorten the step                                      */
+                          built (GG_E_UNSUPPORTED): the convolution is a
+                          17-tap stencil on the vector ALUs, not a dense
+                          contraction, and its operands are already read once
+                          per step in FP32                                      */
     GG_MIXED_FP16 = 3  /* FP16 likewise: GG_E_UNSUPPORTED                        */
 } gg_precision;
 
@@ -110,9 +113,24 @@ typedef struct {
     double theta_c_deg;     /* Read-Shockley cutoff angle (GG_PHYS_MISORIENTATION)   */
     double voxel_m;         /* voxel edge h in metres (GG_PHYS_BULK)                 */
     double gamma_max;       /* maximal boundary energy, J/m^2 (GG_PHYS_BULK)         */
-    double capacity_headroom; /* device arena slack factor (0: default 1.25)       */
+    double capacity_headroom; /* device buffer slack factor (0: default 1.25); 1:
+                               no slack, the buffers hold exactly the current
+                               layout (every step whose boxes grow is then taken
+                               again after the buffers grow)                   */
     int32_t redistance;     /* gg_redistance: re-initialization scheme of the steps  */
+    int32_t batched;        /* 0: gg_step launches its kernels and waits for them;
+                               1: gg_step replays captured HIP graphs and returns
+                               at once (the Euclidean variant, per-kernel timing
+                               and kept intermediates use plain launches)       */
+    uint32_t flags;         /* GG_FLAG_* bits                                       */
 } gg_config;
+
+/* gg_config.flags */
+enum {
+    GG_FLAG_ORDER_SIZE = 1u /* launch the per-grain kernels largest box first
+                               (the default order is by grain id); results do
+                               not depend on the order                          */
+};
 
 typedef struct {
     int64_t steps;          /* steps taken since gg_create                          */
@@ -155,9 +173,16 @@ gg_status gg_create(const gg_config *cfg, const int32_t *labels, int32_t n_grain
                     const double *quat, const double *energy_density, void *hip_stream,
                     const gg_allocator *allocator, gg_sim **out);
 
-/* Advance n_steps timesteps of normalised length dt (Algorithm 1): Gaussian
- * width sigma = sqrt(2 dt) * n[0] voxels (heat kernel of Eq. Heatequation),
- * kernel radius R = ceil(4 sigma).  Requires R <= 2*ceil(W) and R <= 24.
+/* Advance n_steps timesteps of normalised length dt (Algorithm 1, sec. 2.1.3):
+ * Gaussian width sigma = sqrt(2 dt) * n[0] voxels (heat kernel of Eq.
+ * Heatequation), kernel radius R = ceil(4 sigma).  Requires R <= 2*ceil(W) and
+ * R <= 12.  Each step is the predictor, the corrector, the box plan with the
+ * coverage lists of the new boxes, and the re-initialization into the new
+ * boxes; a step whose new boxes or coverage lists do not fit the device
+ * buffers leaves its starting state untouched, and the library grows the
+ * buffers and takes the step again.  batched != 0: the call returns once the
+ * steps are queued; errors of the queued steps (GG_E_NOMEM, GG_E_CAPACITY,
+ * GG_E_HIP) are reported by the next call.
  * Errors: GG_E_ARG (dt not finite/positive, n_steps < 0, R too large; nothing
  * changed), GG_E_CAPACITY / GG_E_NOMEM / GG_E_HIP (poisoned), GG_E_POISONED. */
 gg_status gg_step(gg_sim *sim, double dt, int32_t n_steps);
@@ -168,8 +193,11 @@ gg_status gg_sync(gg_sim *sim);
 /* Number of alive grains. */
 gg_status gg_grain_count(gg_sim *sim, int32_t *alive);
 
-/* Grain volumes V_k = sum over the box of clamp(phi + 1/2, 0, 1), FP64, indexed
- * by grain id (0 for extinct grains); out: host, cap >= n_grains. */
+/* Grain volumes (sec. 3.1: the size of each grain object), read as the smoothed
+ * Heaviside sum V_k = sum over the box of clamp(phi + 1/2, 0, 1) in FP64 and
+ * voxels (exact across a planar two-grain boundary, where the two functions are
+ * opposite), indexed by grain id (0 for extinct grains); out: host, cap >=
+ * n_grains.  Errors: GG_E_ARG, GG_E_SMALLBUF. */
 gg_status gg_grain_volumes(gg_sim *sim, double *out, int64_t cap);
 
 /* Interface areas for the energy bookkeeping (energy functional, Eq.
@@ -183,26 +211,32 @@ gg_status gg_grain_volumes(gg_sim *sim, double *out, int64_t cap);
  * sum_k E_k V_k h^D.  Host arrays, cap >= n_grains (0 for extinct grains). */
 gg_status gg_grain_areas(gg_sim *sim, double *area, double *weighted, int64_t cap);
 
-/* Voxel labels: argmax over the grains whose box covers the voxel of their
- * function (ties to the lowest id); out: prod(n) int32, x fastest, host memory,
- * or device memory on the simulation's device when out_is_device != 0 (then
- * the write is ordered on the simulation's stream and the call does not wait). */
+/* Voxel labels (the tessellation the grains define, sec. 2.1.1: a voxel belongs
+ * to the grain whose function is largest there, i.e. inside its zero level
+ * set): argmax over the grains whose box covers the voxel of their function
+ * (ties to the lowest id); out: prod(n) int32, x fastest, host memory, or
+ * device memory on the simulation's device when out_is_device != 0 (then the
+ * write is ordered on the simulation's stream and the call does not wait for
+ * it).  Errors: GG_E_ARG, GG_E_SMALLBUF. */
 gg_status gg_labels(gg_sim *sim, int32_t *out, int64_t cap, int32_t out_is_device);
 
-/* Step statistics. */
+/* Step statistics: the counters of the metric (grain voxels per step, the
+ * box voxels of the size-adaptive boxes of sec. 3.1), the superposition of
+ * the boxes (sec. 5.2.3) and the device time of the last gg_step call.
+ * Errors: GG_E_ARG. */
 gg_status gg_stats(gg_sim *sim, gg_step_stats *out);
 
 /* Per-kernel device time, for roofline accounting.  Kernel classes: */
 enum {
-    GG_K_CONV_XY = 0,   /* predictor x and y passes (+ correction epilogue)          */
-    GG_K_CONV_Z = 1,    /* predictor z pass on its own (first step, new dt)         */
-    GG_K_COMPARE = 2,   /* corrector over global tiles                              */
-    GG_K_REINIT_XY = 3, /* reference values, x and y spreading sweeps (2D: all)     */
-    GG_K_REINIT_Z = 4,  /* z sweep, clamp, volume partial sums, next z convolution  */
-    GG_K_PLAN = 5,      /* box plan, scans, work items, coverage lists; coarsening  */
-    GG_K_VOLUME = 6,    /* per-grain volume reduction                               */
-    GG_K_REINIT_SWEEP = 7, /* Jacobi sweeps of GG_REDIST_EUCLID (2D: + clamp, volume) */
-    GG_K_CLASSES = 8
+    GG_K_PREDICT = 0,   /* backward z spreading, band clamp, volume, Gaussian z/x/y
+                           (+ correction epilogue): f -> psi (+ phi)              */
+    GG_K_COMPARE = 1,   /* corrector over global tiles: psi -> phi^c              */
+    GG_K_REINIT = 2,    /* reference values, x/y spreading, forward z spreading:
+                           phi^c -> f (Euclidean variant: reference values)       */
+    GG_K_REINIT_SWEEP = 3, /* Jacobi sweeps of GG_REDIST_EUCLID                   */
+    GG_K_PLAN = 4,      /* box plan, scans, coverage lists, launch order, step
+                           counters; coarsening                                   */
+    GG_K_CLASSES = 5
 };
 typedef struct {
     double ms[GG_K_CLASSES];          /* summed device time (HIP events)            */
@@ -260,18 +294,25 @@ gg_status gg_coarsen(gg_sim *sim, const int32_t n_new[3]);
  * range). */
 gg_status gg_grain_sdf(gg_sim *sim, int32_t id, int32_t lo[3], int32_t ext[3], double *out, int64_t cap);
 
-/* Autotuning of the tile shapes: work-item tilings follow two LDS budgets, the
- * work group's (default 40 KB) and the small launch class's limit (default
- * 26 KB; FP64 tiles get the same values, twice the bytes).  gg_autotune takes
- * steps_per_candidate steps (normalised length dt) with each of a few
- * candidate pairs (budgets up to 48 KB), keeps the pair with the least device
- * time per grain voxel and returns it.  The simulation advances by those
- * steps; the functions do not depend on the tiling (bit-identical; volumes,
- * sums of per-work-item partial sums, to rounding).
+/* Autotuning of the launch schedule: the order in which the per-grain kernels
+ * take the boxes (grain id or largest box first, GG_FLAG_ORDER_SIZE) and, for
+ * the Euclidean variant, the LDS budgets of its work-item tilings (the work
+ * group's, default 40 KB, and the small launch class's, default 26 KB).
+ * gg_autotune takes steps_per_candidate steps (normalised length dt) with
+ * each candidate, keeps the one with the least device time per grain voxel
+ * and reports every candidate's time.  The simulation advances by those steps;
+ * the functions do not depend on the schedule (bit-identical).
  * Errors: GG_E_ARG (dt not finite/positive, steps_per_candidate < 1; nothing
  * changed), GG_E_CAPACITY / GG_E_NOMEM / GG_E_HIP (poisoned). */
-gg_status gg_autotune(gg_sim *sim, double dt, int32_t steps_per_candidate, int32_t *lds_bytes,
-                      int32_t *small_bytes);
+typedef struct {
+    int32_t order_size;        /* chosen: 1 largest box first, 0 grain id       */
+    int32_t lds_bytes;         /* chosen Euclidean work-group LDS budget        */
+    int32_t small_bytes;       /* chosen Euclidean small-class LDS limit        */
+    int32_t candidates;        /* candidates timed                              */
+    double ns_per_gv[8];       /* device time per grain voxel of each candidate */
+    int32_t cand_order[8], cand_lds[8], cand_small[8];
+} gg_tuning;
+gg_status gg_autotune(gg_sim *sim, double dt, int32_t steps_per_candidate, gg_tuning *out);
 
 /* Checkpoint / resume.  gg_save writes the state to a file: grid, boxes,
  * liveness, values in the stored precision, the ID-field (with the predictor

@@ -1,27 +1,25 @@
-// Device code of the level-set grain-growth step for gfx950 (MI355X).
+// Device code of the level-set grain-growth step for gfx950 (MI355X): shared
+// helpers, the corrector, the Euclidean re-initialization variant, grid
+// coarsening, interface areas and the box / coverage bookkeeping.  The two
+// z-marching kernels of the step are in gg_march.hpp.
 //
 // Data layout in HBM: every alive grain's box is stored contiguously, x
 // fastest, in grain-id order ("packed arena"); a box table (lo, ext, alive,
-// offset) per layout describes it.  Per-voxel work is expressed as work items
-// over boxes (predictor, re-initialization) or over fixed tiles of the global
-// grid (corrector, labels); per-item grain lookups are O(1) maps.
+// offset) per layout describes it.  The corrector and the labels work over
+// fixed tiles of the global grid with per-tile coverage lists of grains.
 //
-// One step is four sweeps over the packed boxes:
-//   k_compare    psi            -> phi^c   (global tiles, top-2 of the covering grains)
-//   k_reinit_xy  phi^c (old box) -> d      (reference values, x and y spreading sweeps, new box)
-//   k_zfused     d              -> t, phi  (z spreading sweep, band clamp, volume, predictor z pass)
-//   k_conv_xy    t              -> psi     (predictor x and y passes, correction epilogue)
-// The separable Gaussian is applied z, x, y so that its z pass can share the
-// z-line sweep of the re-initialization.  The Euclidean re-initialization
-// variant replaces the spreading sweeps: k_reinit_xy writes the reference
-// values, k_jacobi takes the Godunov sweeps, k_zfused only clamps.
+// One step is three sweeps over the packed boxes:
+//   k_compare        psi (layout L)      -> phi^c (L)   top-2 of the covering grains per global tile
+//   k_reinit_march   phi^c (L)           -> f (L')      reference values, taxicab spreading x, y, forward z
+//   k_predict_march  f (L')              -> psi (L')    backward z spreading, band clamp, volume,
+//                                                       Gaussian z, x, y (+ correction epilogue)
+// with the box plan and coverage lists of the new layout L' between the first
+// two.  The Euclidean variant replaces k_reinit_march by k_reinit_xy (reference
+// values) and k_jacobi (Godunov sweeps).
 //
-// Stencil kernels stage one output tile plus its halo in LDS and read every HBM
-// value of their tile once; each thread produces KB consecutive outputs along
-// the stencil axis from a register window.  Along an axis a box is either the
-// whole periodic axis (indices wrap) or at most n - 2P long (indices outside
-// the box read the fill value): a stencil of reach <= 2P never wraps into a
-// partial box.
+// Along an axis a box is either the whole periodic axis (indices wrap) or at
+// most n - 2P long (indices outside the box read the fill value): a stencil of
+// reach <= 2P never wraps into a partial box.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -29,12 +27,8 @@
 
 namespace gg {
 
-constexpr int kBlock = 256;       // threads per work group of the stencil/tile kernels
+constexpr int kBlock = 256;       // threads per work group of the tile kernels
 constexpr int kWaves = kBlock / 64;
-// Predictor xy tiles: values per lane of one plane's tile held in registers.
-constexpr int kPF = 16;
-// Predictor xy work items: planes per item (pipelined through one LDS tile).
-constexpr int kCxyPlanes = 4;
 // Jacobi sweep work items: at most this many planes per item, marched through
 // a ring of three LDS planes; values per lane of the next plane held in registers.
 #ifndef GG_JAC_PLANES
@@ -46,14 +40,12 @@ constexpr int kJacQ = 16;
 #define GG_LDS_BYTES 40960
 #endif
 constexpr int kLdsBytes = GG_LDS_BYTES;  // dynamic LDS budget per work group (FP32)
-constexpr int kKB = 4;            // outputs per thread along a stencil axis
-constexpr int kMaxRadius = 24;    // largest Gaussian radius R
+constexpr int kMaxRadius = 12;    // largest Gaussian radius R
 constexpr int kMaxBand = 16;      // largest band half width W
-constexpr int kKinds = 5;         // item kinds: predictor xy, predictor z, reinit xy, fused z, Jacobi sweep
-enum { KIND_CXY = 0, KIND_CZ = 1, KIND_RXY = 2, KIND_ZF = 3, KIND_JAC = 4 };
-// kinds whose items are xy tiles of consecutive z planes (the others: x by z
-// tiles of y rows)
-__host__ __device__ inline bool kind_xy(int kind) { return kind == KIND_CXY || kind == KIND_RXY || kind == KIND_JAC; }
+// item kinds of the Euclidean variant: reference values (xy tiles of z planes),
+// Jacobi sweeps
+constexpr int kKinds = 2;
+enum { KIND_RXY = 0, KIND_JAC = 1 };
 
 // Box table of one layout.
 struct Boxes {
@@ -142,65 +134,41 @@ __device__ __forceinline__ float ratio(float a, float b) { return a * __builtin_
 __device__ __forceinline__ double grad_dist(double a, double b) { return a / sqrt(b); }
 __device__ __forceinline__ float grad_dist(float a, float b) { return a * __builtin_amdgcn_rsqf(b); }
 
-// LDS values needed by an output tile tx * ty of nz planes.  h: stencil halo (R
-// for the predictor kinds, K for the re-initialization kinds), h2: R for the
-// fused z kind.  The re-initialization sweeps whole box lines, so its tiles need
-// a halo only along an axis that is split into several tiles (sx, sy).  The two
-// re-initialization kinds batch several planes (xy kind: z planes, fused z
-// kind: y rows) into one work item.  xy kind: per plane an f tile and a
-// reference tile of (ty + 2hy + 2) rows of pitch (tx + 2hx + 2) | 1; both
-// kinds add int offset tables (counted as one value each).
-__host__ __device__ inline long long lds_need(int kind, int tx, int ty, int h, int h2, bool sx, bool sy, int nz = 1) {
-    if (kind == KIND_CXY) {  // one plane's raw tile and x-pass tile, row table; the raw tile
-                             // has at most 64 columns and kWaves * kPF rows (kPF values per lane)
-        if (tx + 2 * h > 64 || ty + 2 * h > kWaves * kPF) return 1LL << 40;
-        return (long long)((tx + 2 * h) | 1) * (ty + 2 * h) + kKB + (long long)tx * (ty + 2 * h + kKB) + ty + 2 * h;
-    }
-    if (kind == KIND_RXY) {
-        const int hx = sx ? h : 0, hy = sy ? h : 0;
-        const long long FW = tx + 2 * hx + 2, FH = ty + 2 * hy + 2;
-        return (long long)nz * (2 * (FW | 1) * FH + FH) + 2 * FH + FW;
-    }
-    if (kind == KIND_ZF) {  // nz y rows of tx columns, (ty + 2 h2 + 2 hz + kKB) z rows; int offset tables
-        const int hz = sy ? h : 0;
-        const long long D = ty + 2 * h2 + 2 * hz;
-        return (long long)nz * tx * (D + kKB + 1) + D;
-    }
-    if (kind == KIND_JAC) {  // three planes of the tile with one ring of neighbours; row and column tables
-        const long long FW = tx + 2, FH = ty + 2;
-        return 3 * FW * FH + FW + FH;
-    }
-    return (long long)tx * (ty + 2 * h);  // prologue z pass
+// LDS values needed by an output tile tx * ty of nz planes.  Reference-value
+// kind: per plane an f tile and a reference tile of (ty + 2) rows of pitch
+// (tx + 2) | 1 (one ring of stencil neighbours) and int offset tables (counted
+// as one value each).  Jacobi kind: three planes of the tile with one ring of
+// neighbours, row and column tables.
+__host__ __device__ inline long long lds_need(int kind, int tx, int ty, int nz = 1) {
+    const long long FW = tx + 2, FH = ty + 2;
+    if (kind == KIND_RXY) return (long long)nz * (2 * (FW | 1) * FH + FH) + 2 * FH + FW;
+    return 3 * FW * FH + FW + FH;
 }
 
-// nb: planes per work item (re-initialization xy kind only, else 1).
+// nb: planes per work item.
 struct Tiling {
     int nxs, nys, tx, ty, nb;
 };
 
-// Split a box cross-section ex * ey (second axis y for xy kernels, z for z
-// kernels) into the fewest near-equal tiles whose LDS need fits the budget.
-// The re-initialization xy kind then takes as many of the `planes` planes per
-// work item as fit `target` values of LDS, in near-equal chunks.
-__host__ __device__ inline Tiling choose_tiling(int kind, int ex, int ey, int planes, int h, int h2, int budget,
-                                                int target) {
+// Split a box cross-section ex * ey into the fewest near-equal tiles whose LDS
+// need fits the budget; then take as many of the `planes` z planes per work item
+// as fit `target` values of LDS (reference kind) or kJacPlanes (Jacobi kind), in
+// near-equal chunks.
+__host__ __device__ inline Tiling choose_tiling(int kind, int ex, int ey, int planes, int budget, int target) {
     Tiling t = {0, 0, 0, 0, 1};
     for (int nxs = (ex + 127) / 128; nxs <= ex; ++nxs) {
         const int tx = (ex + nxs - 1) / nxs;
-        const bool sx = nxs > 1;
-        if (kind == KIND_CXY && tx + 2 * h > 64) continue;
-        if (lds_need(kind, tx, ey, h, h2, sx, false) <= budget) {
+        if (lds_need(kind, tx, ey) <= budget) {
             t.nxs = nxs;
             t.nys = 1;
             t.tx = tx;
             t.ty = ey;
             break;
         }
-        const long long b = lds_need(kind, tx, 0, h, h2, sx, true);  // the need is affine in ty
-        const long long a = lds_need(kind, tx, 1, h, h2, sx, true) - b;
+        const long long b = lds_need(kind, tx, 0);  // the need is affine in ty
+        const long long a = lds_need(kind, tx, 1) - b;
         if (budget - b < a) continue;
-        int tymax = (int)((budget - b) / a);
-        if (kind == KIND_CXY) tymax = tymax < kWaves * kPF - 2 * h ? tymax : kWaves * kPF - 2 * h;
+        const int tymax = (int)((budget - b) / a);
         if (tymax < 1) continue;
         const int nys = (ey + tymax - 1) / tymax;
         t.nxs = nxs;
@@ -209,20 +177,14 @@ __host__ __device__ inline Tiling choose_tiling(int kind, int ex, int ey, int pl
         t.ty = (ey + nys - 1) / nys;
         break;
     }
-    if (kind == KIND_CXY && t.nxs > 0 && planes > 1) {
-        const int chunks = (planes + kCxyPlanes - 1) / kCxyPlanes;
-        t.nb = (planes + chunks - 1) / chunks;
-    }
-    if (kind == KIND_JAC && t.nxs > 0 && planes > 1) {
-        const int chunks = (planes + kJacPlanes - 1) / kJacPlanes;
-        t.nb = (planes + chunks - 1) / chunks;
-    }
-    if ((kind == KIND_RXY || kind == KIND_ZF) && t.nxs > 0 && planes > 1) {
-        const bool sx = t.nxs > 1, sy = t.nys > 1;
-        const long long one = lds_need(kind, t.tx, t.ty, h, h2, sx, sy, 1);
-        const long long per = lds_need(kind, t.tx, t.ty, h, h2, sx, sy, 2) - one;
-        const long long tg = target < budget ? target : budget;
-        long long nb = (tg - (one - per)) / per;
+    if (t.nxs > 0 && planes > 1) {
+        long long nb = kJacPlanes;
+        if (kind == KIND_RXY) {
+            const long long one = lds_need(kind, t.tx, t.ty, 1);
+            const long long per = lds_need(kind, t.tx, t.ty, 2) - one;
+            const long long tg = target < budget ? target : budget;
+            nb = (tg - (one - per)) / per;
+        }
         nb = nb < 1 ? 1 : (nb > planes ? planes : nb);
         const int chunks = (int)((planes + nb - 1) / nb);
         t.nb = (planes + chunks - 1) / chunks;
@@ -230,36 +192,19 @@ __host__ __device__ inline Tiling choose_tiling(int kind, int ex, int ey, int pl
     return t;
 }
 
-__host__ __device__ inline void kind_halos(int kind, int R, int K, int *h, int *h2) {
-    *h = (kind == KIND_CXY || kind == KIND_CZ) ? R : (kind == KIND_JAC ? 1 : K);
-    *h2 = kind == KIND_ZF ? R : 0;
+__host__ __device__ inline Tiling kind_tiling(int kind, const int *e, int budget, int target) {
+    return choose_tiling(kind, e[0], e[1], e[2], budget, target);
 }
 
-__host__ __device__ inline int kind_planes(int kind, const int *e) {
-    return kind_xy(kind) ? e[2] : e[1];
-}
-
-__host__ __device__ inline Tiling kind_tiling(int kind, const int *e, int R, int K, int budget, int target) {
-    int h, h2;
-    kind_halos(kind, R, K, &h, &h2);
-    const int ey = kind_xy(kind) ? e[1] : e[2];
-    return choose_tiling(kind, e[0], ey, kind_planes(kind, e), h, h2, budget, target);
-}
-
-__host__ __device__ inline long long tiling_need(int kind, const Tiling &t, int R, int K) {
-    int h, h2;
-    kind_halos(kind, R, K, &h, &h2);
-    return lds_need(kind, t.tx, t.ty, h, h2, t.nxs > 1, t.nys > 1, t.nb);
+__host__ __device__ inline long long tiling_need(int kind, const Tiling &t) {
+    return lds_need(kind, t.tx, t.ty, t.nb);
 }
 
 // Number of work items of one kind for a box.
-__host__ __device__ inline long long tiling_items(int kind, const int *e, const Tiling &t) {
-    const int planes = kind_planes(kind, e);
-    return (long long)((planes + t.nb - 1) / t.nb) * t.nxs * t.nys;
+__host__ __device__ inline long long tiling_items(const int *e, const Tiling &t) {
+    return (long long)((e[2] + t.nb - 1) / t.nb) * t.nxs * t.nys;
 }
 
-// Work groups are dealt round-robin to the 8 XCDs of the chip (each with its
-// own L2).  Launches use a grid of 8 * ceil(n / 8) groups and give every XCD a
 // contiguous run of items, so that neighbouring planes of a box, or
 // neighbouring tiles of the grid, are processed by the same L2.
 constexpr int kXcds = 8;
@@ -302,20 +247,14 @@ __device__ __forceinline__ ItemTile decode_item(long long item, int kind, const 
     const int per = tl.nxs * tl.nys;
     const int chunk = sub / per;
     const int rem = sub - chunk * per;
-    if (kind != KIND_CZ) {
-        const int nb = tilings[2 * it.k + 1].x;
-        it.plane = chunk * nb;
-        it.np = min(nb, kind_planes(kind, e) - it.plane);
-    } else {
-        it.plane = chunk;
-        it.np = 1;
-    }
+    const int nb = tilings[2 * it.k + 1].x;
+    it.plane = chunk * nb;
+    it.np = min(nb, e[2] - it.plane);
     const int ys = rem / tl.nxs, xs = rem - ys * tl.nxs;
     it.x0 = xs * tl.tx;
     it.y0 = ys * tl.ty;
-    const int ey = kind_xy(kind) ? e[1] : e[2];
     it.wx = min(tl.tx, e[0] - it.x0);
-    it.wy = min(tl.ty, ey - it.y0);
+    it.wy = min(tl.ty, e[1] - it.y0);
     return it;
 }
 
@@ -338,141 +277,8 @@ extern "C" __device__ int __ockl_wfred_max_i32(int);
 __device__ __forceinline__ int wave_min(int v) { return __ockl_wfred_min_i32(v); }
 __device__ __forceinline__ int wave_max(int v) { return __ockl_wfred_max_i32(v); }
 
-// 1D Gaussian pass over KB consecutive outputs: acc[q] = sum_t g_t v[q + t],
-// summed in increasing t from 0.  Static radius: register window; RS == 0:
-// runtime radius read from `taps`.
-template <typename T, int RS>
-__device__ __forceinline__ void gauss_run(const T *src, int stride, const T *tp, const T *taps, int R, T acc[kKB]) {
-#pragma unroll
-    for (int q = 0; q < kKB; ++q) acc[q] = T(0);
-    if constexpr (RS > 0) {
-#pragma unroll
-        for (int i = 0; i < 2 * RS + kKB; ++i) {
-            const T v = src[i * stride];
-#pragma unroll
-            for (int q = 0; q < kKB; ++q) {
-                const int t = i - q;
-                if (t >= 0 && t <= 2 * RS) acc[q] = mac<T>(acc[q], tp[t], v);
-            }
-        }
-    } else {
-        for (int t = 0; t <= 2 * R; ++t) {
-            const T g = taps[t];
-#pragma unroll
-            for (int q = 0; q < kKB; ++q) acc[q] = mac<T>(acc[q], g, src[(q + t) * stride]);
-        }
-    }
-}
-
-// Spreading along one line of `len` values (stride `stride`): the distance
-// grows by one per voxel, forward then backward.  A ring (a line over a whole
-// periodic axis) is swept twice around in each direction, starting at index 0.
-// Same order of operations as the definition: w = previous + 1; keep the smaller of w and v.
-template <typename T> __device__ __forceinline__ void sweep_line(T *p, int stride, int len, bool ring) {
-    if (len <= 1) return;
-    T cur = p[0];
-    if (!ring) {
-#pragma unroll 4
-        for (int i = 1; i < len; ++i) {
-            const T v = p[i * stride], w = cur + T(1);
-            cur = vmin(w, v);
-            p[i * stride] = cur;
-        }
-#pragma unroll 4
-        for (int i = len - 2; i >= 0; --i) {
-            const T v = p[i * stride], w = cur + T(1);
-            cur = vmin(w, v);
-            p[i * stride] = cur;
-        }
-        return;
-    }
-    int i = 0;
-    for (int t = 1; t < 2 * len; ++t) {
-        i = i + 1 == len ? 0 : i + 1;
-        const T v = p[i * stride], w = cur + T(1);
-        cur = vmin(w, v);
-        p[i * stride] = cur;
-    }
-    i = len - 1;
-    cur = p[i * stride];
-    for (int t = 1; t < 2 * len; ++t) {
-        i = i == 0 ? len - 1 : i - 1;
-        const T v = p[i * stride], w = cur + T(1);
-        cur = vmin(w, v);
-        p[i * stride] = cur;
-    }
-}
-
-// The same on signed values whose sign bit marks the inside: the magnitude is
-// spread, the sign of every value is kept.
-template <typename T> __device__ __forceinline__ void sweep_line_signed(T *p, int stride, int len, bool ring) {
-    if (len <= 1) return;
-    T cur = fabs(p[0]);
-    if (!ring) {
-#pragma unroll 4
-        for (int i = 1; i < len; ++i) {
-            const T v = p[i * stride], w = cur + T(1), a = fabs(v);
-            cur = vmin(w, a);
-            p[i * stride] = copysign(cur, v);
-        }
-#pragma unroll 4
-        for (int i = len - 2; i >= 0; --i) {
-            const T v = p[i * stride], w = cur + T(1), a = fabs(v);
-            cur = vmin(w, a);
-            p[i * stride] = copysign(cur, v);
-        }
-        return;
-    }
-    int i = 0;
-    for (int t = 1; t < 2 * len; ++t) {
-        i = i + 1 == len ? 0 : i + 1;
-        const T v = p[i * stride], w = cur + T(1), a = fabs(v);
-        cur = vmin(w, a);
-        p[i * stride] = copysign(cur, v);
-    }
-    i = len - 1;
-    cur = fabs(p[i * stride]);
-    for (int t = 1; t < 2 * len; ++t) {
-        i = i == 0 ? len - 1 : i - 1;
-        const T v = p[i * stride], w = cur + T(1), a = fabs(v);
-        cur = vmin(w, a);
-        p[i * stride] = copysign(cur, v);
-    }
-}
-
-// Stage a W x H tile into LDS (row pitch `pitch`).  Element (rr, cc) is
-// src[rowbase(rr) + colidx(cc)], or `fill` when either is negative.  Waves own
-// rows (the row mapping is wave-uniform), lanes own columns (the column mapping
-// is computed once per lane), and each lane issues kLoadBatch independent loads
-// before it stores any of them, so that enough bytes are in flight to cover
 // HBM latency.
 constexpr int kLoadBatch = 8;
-
-__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
-
-template <typename T, typename RowF, typename ColF>
-__device__ __forceinline__ void stage_rows(T *lds, int pitch, int W, int H, const T *__restrict__ src, RowF rowbase,
-                                           ColF colidx, T fill) {
-    const int lane = threadIdx.x & 63, wave = wave_id();
-    for (int c0 = 0; c0 < W; c0 += 64) {
-        const int cc = c0 + lane;
-        const int ci = cc < W ? colidx(cc) : -1;
-        for (int r0 = wave; r0 < H; r0 += kWaves * kLoadBatch) {
-            T v[kLoadBatch];
-#pragma unroll
-            for (int j = 0; j < kLoadBatch; ++j) {
-                const int rr = r0 + kWaves * j;
-                const long long rb = rr < H ? rowbase(rr) : -1;
-                v[j] = (rb >= 0 && ci >= 0) ? src[rb + ci] : fill;
-            }
-#pragma unroll
-            for (int j = 0; j < kLoadBatch; ++j) {
-                const int rr = r0 + kWaves * j;
-                if (rr < H && cc < W) lds[rr * pitch + cc] = v[j];
-            }
-        }
-    }
-}
 
 // ------------------------------------------------ predictor correction terms
 
@@ -546,29 +352,6 @@ template <typename T> struct PairCache {
     T w = 1, b = 0;
 };
 
-// d^p = phi + w (psi - phi) + mob (E_j - E_k) * bulk_scale, clamped to [-W, W].
-template <typename T>
-__device__ inline T correct_prediction(const Physics<T> &ph, int k, long long idx, T psi, T W, PairCache<T> &pc) {
-    const int j = ph.iota[idx];
-    if (j != pc.j) {
-        pc.j = j;
-        pc.w = 1;
-        pc.b = 0;
-        if (j >= 0) {
-            T mob = 1;
-            if (ph.mode & 1) {
-                const T th = misorientation_deg<T>(ph.quat + 4LL * k, ph.quat + 4LL * j);
-                pc.w = pair_weight<T>(th, ph.theta_c_deg, &mob);
-            }
-            if (ph.mode & 2) pc.b = mob * (ph.energy[j] - ph.energy[k]) * ph.bulk_scale;
-        }
-    }
-    const T p = ph.phi[idx];
-    T d = p + pc.w * (psi - p) + pc.b;
-    d = d > W ? W : d;
-    d = d < -W ? -W : d;
-    return d;
-}
 
 // --------------------------------------------------------- predictor kernels
 
@@ -598,132 +381,27 @@ struct GridArgs {
 };
 
 // x and y passes of the Gaussian on one tile of nz consecutive z planes of a
-// box, then the optional correction epilogue; the output is the predicted
-// function psi.  The planes go through one LDS tile in turn.  Waves own tile
-// rows and lanes own columns; while a plane is convolved, its successor's tile
-// is already on its way into registers (kPF values per lane), so the loads'
-// latency overlaps the arithmetic.
-template <typename T, int RS, bool PH>
-__global__ void __launch_bounds__(kBlock)
-    k_conv_xy(Boxes L, ItemRefs ir, const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ taps,
-              int R_, T W, GridArgs g, Physics<T> ph) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *sm = reinterpret_cast<T *>(smem_raw);
-    const int R = RS ? RS : R_;
-    const long long item = xcd_item(ir.n);
-    if (item >= ir.n) return;
-    const ItemTile it = decode_item(item, KIND_CXY, L, ir);
-    const int k = it.k, z0 = it.plane, nz = it.np, x0 = it.x0, y0 = it.y0, wx = it.wx, wy = it.wy;
-    const int ex = L.ext[3 * k], ey = L.ext[3 * k + 1];
-    const int RW = wx + 2 * R, RP = RW | 1, RH = wy + 2 * R;  // RW <= 64, RH <= kWaves * kPF
-    const int plane = ex * ey;
-    T *raw = sm, *xp = sm + RH * RP + kKB;
-    int *rowo = reinterpret_cast<int *>(xp + wx * (RH + kKB));  // y offset in the plane, -1 outside the box
-    const long long base0 = L.off[k] + (long long)z0 * plane;
-    T tp[RS > 0 ? 2 * RS + 1 : 1];
-    if constexpr (RS > 0) {
-#pragma unroll
-        for (int t = 0; t <= 2 * RS; ++t) tp[t] = taps[t];
-    }
-    for (int i = threadIdx.x; i < RH; i += kBlock) {
-        const int yy = axis_map(y0 - R + i, ey, g.n[1]);
-        rowo[i] = yy >= 0 ? yy * ex : -1;
-    }
-    const int lane = threadIdx.x & 63, wave = wave_id();
-    const int xx = lane < RW ? axis_map(x0 - R + lane, ex, g.n[0]) : -1;
-    __syncthreads();
-    // this lane's tile values of one plane: rows wave + kWaves * j, column lane
-    T v[kPF];
-    auto fetch = [&](const T *src) {
-#pragma unroll
-        for (int j = 0; j < kPF; ++j) {
-            const int rr = wave + kWaves * j;
-            const int ro = rr < RH ? rowo[rr] : -1;
-            v[j] = (ro >= 0 && xx >= 0) ? src[ro + xx] : -W;
-        }
-    };
-    fetch(in + base0);
-    const int ngx = (wx + kKB - 1) / kKB, ngy = (wy + kKB - 1) / kKB;
-    PairCache<T> pc;
-    for (int p = 0; p < nz; ++p) {
-        // the previous plane's x pass is done (barrier below): its tile is free
-        if (lane < RW) {
-#pragma unroll
-            for (int j = 0; j < kPF; ++j) {
-                const int rr = wave + kWaves * j;
-                if (rr < RH) raw[rr * RP + lane] = v[j];
-            }
-        }
-        __syncthreads();
-        const long long base = base0 + (long long)p * plane;
-        if (p + 1 < nz) fetch(in + base + plane);
-        // x pass: consecutive lanes take consecutive rows (odd pitch: no bank conflicts)
-        for (Walk2 w(threadIdx.x, RH); w.r < ngx; w.step()) {
-            const int rr = w.c, c0 = w.r * kKB;
-            T acc[kKB];
-            if (rowo[rr] < 0) {
-#pragma unroll
-                for (int q = 0; q < kKB; ++q) acc[q] = -W;  // rows outside the box read the fill value
-            } else {
-                gauss_run<T, RS>(raw + rr * RP + c0, 1, tp, taps, R, acc);
-            }
-#pragma unroll
-            for (int q = 0; q < kKB; ++q)
-                if (c0 + q < wx) xp[rr * wx + c0 + q] = acc[q];
-        }
-        __syncthreads();
-        T *outp = out + base;
-        for (Walk2 w(threadIdx.x, wx); w.r < ngy; w.step()) {
-            const int c = w.c, r0 = w.r * kKB;
-            T acc[kKB];
-            gauss_run<T, RS>(xp + r0 * wx + c, wx, tp, taps, R, acc);
-            int idx = (y0 + r0) * ex + x0 + c;  // within the plane
-#pragma unroll
-            for (int q = 0; q < kKB; ++q, idx += ex) {
-                if (r0 + q >= wy) break;
-                T val = acc[q];
-                if constexpr (PH) val = correct_prediction<T>(ph, k, base + idx, val, W, pc);
-                outp[idx] = val;
-            }
-        }
-        // the next plane's tile store (top of the loop) follows this plane's
-        // y pass only through the barrier after its x pass: xp and raw are
-        // disjoint, so the y pass may still read xp meanwhile; the next x pass
-        // writes xp only after the next barrier
-    }
-}
 
-// Predictor z pass on its own (first step after create / load / a new dt).
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
-    k_conv_z(Boxes L, ItemRefs ir, const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ taps, int R,
-             T W, GridArgs g) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *col = reinterpret_cast<T *>(smem_raw);
-    const long long item = xcd_item(ir.n);
-    if (item >= ir.n) return;
-    const ItemTile it = decode_item(item, KIND_CZ, L, ir);
-    const int k = it.k, y = it.plane, x0 = it.x0, z0 = it.y0, wx = it.wx, wz = it.wy;
-    const int ex = L.ext[3 * k], ey = L.ext[3 * k + 1], ez = L.ext[3 * k + 2];
-    const int CH = wz + 2 * R;
-    const long long plane = (long long)ex * ey;
-    const long long rowbase = L.off[k] + (long long)y * ex + x0;
-    stage_rows<T>(
-        col, wx, wx, CH, in,
-        [&](int rr) -> long long {
-            const int zz = axis_map(z0 - R + rr, ez, g.n[2]);
-            return zz >= 0 ? rowbase + zz * plane : -1;
-        },
-        [&](int c) { return c; }, -W);
-    __syncthreads();
-    for (int e = threadIdx.x; e < wx * wz; e += kBlock) {
-        const int r = e / wx, c = e - r * wx;
-        T acc = 0;
-        const T *cp = col + r * wx + c;
-        for (int j = 0; j <= 2 * R; ++j) acc = mac<T>(acc, taps[j], cp[j * wx]);
-        out[rowbase + (long long)(z0 + r) * plane + c] = acc;
-    }
-}
+// Device control block of the step sequence.  Every kernel of a step returns
+// at once when `fail` is set, so that a step whose new layout does not fit the
+// buffers leaves the state it started from untouched (the library then grows
+// the buffers and runs the step again).
+struct Ctl {
+    int fail;             // sticky: 0 none, 1 value arenas too small, 2 coverage list too small
+    int fail_step;        // completed steps when the failure was raised
+    int steps;            // completed steps since creation
+    int alive;            // alive grains after the last completed step
+    int phi_at;           // the step (value of `steps` while it runs) whose predictor stores phi
+    int pad;
+    long long need_arena; // values the failing layout needs
+    long long need_cov;   // coverage entries the failing layout needs
+    long long total_gv;   // grain voxels summed over completed steps
+    long long last_gv;    // grain voxels of the last completed step
+    long long arena_now;  // values of the layout after the last completed step
+    long long cov_now;    // coverage entries of that layout
+};
+
+__device__ __forceinline__ bool ctl_failed(const Ctl *c) { return c != nullptr && c->fail != 0; }
 
 // ------------------------------------------------------------ corrector (a3)
 
@@ -776,7 +454,8 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_compare(Boxes L, const int *__restrict__ cov_off, const int *__restrict__ cov_list, const T *__restrict__ psi,
               T *__restrict__ phic, int *__restrict__ iota_out, int *bmin, int *bmax, unsigned *occ, TileArgs ta,
-              T W, int mode) {
+              T W, int mode, const Ctl *ctl) {
+    if (ctl_failed(ctl)) return;
     const int ntiles = ta.nt[0] * ta.nt[1] * ta.nt[2];
     const int tile = (int)xcd_item(ntiles);
     if (tile >= ntiles) return;
@@ -1031,19 +710,27 @@ template <typename T> struct Carry {
 // with one ring of stencil neighbours), then int tables of offsets relative to
 // the old box start: f rows of every plane, the rows of the planes just below
 // and above the batch (whose z neighbours are read from memory; the batch's
+// Reference values of the Euclidean re-initialization variant on one tile of
+// nz consecutive z planes of the new box: |phi| / |grad phi| (central
+// differences summed in axis order) capped by the axis intercept theta = phi /
+// (phi - phi_n), at cells with a face neighbour across the sign change, +inf
+// elsewhere; written with the inside flag as the sign bit.  Also carries the
+// ID-field over to the new layout.
+//
+// LDS: nz f planes and nz reference planes, each FH rows of pitch FP (the tile
+// with one ring of stencil neighbours), then int tables of offsets relative to
+// the old box start: f rows of every plane, the rows of the planes just below
+// and above the batch (whose z neighbours are read from memory; the batch's
 // inner planes take theirs from LDS), and the f columns.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
     k_reinit_xy(Boxes Lo, Boxes Ln, ItemRefs ir, const T *__restrict__ phic, T *__restrict__ out,
-                const int *__restrict__ iota_old, int *__restrict__ iota_new, double *__restrict__ vol_part, int K,
-                T W, int euclid, GridArgs g) {
+                const int *__restrict__ iota_old, int *__restrict__ iota_new, T W, GridArgs g) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sm = reinterpret_cast<T *>(smem_raw);
-    __shared__ double red[kBlock / 64];
     const long long cls_item = xcd_item(ir.n);
     if (cls_item >= ir.n) return;
     const ItemTile it = decode_item(cls_item, KIND_RXY, Ln, ir);
-    const long long item = it.item;
     const int k = it.k, z0 = it.plane, nz = it.np, x0 = it.x0, y0 = it.y0, wx = it.wx, wy = it.wy;
     Carry<T> cr;
     cr.src = phic;
@@ -1058,8 +745,7 @@ __global__ void __launch_bounds__(kBlock)
         cr.d[a] = dd < 0 ? dd + g.n[a] : dd;
     }
     const int ex = cr.nex[0], ey = cr.nex[1];
-    const int hx = it.nxs > 1 ? K : 0, hy = it.nys > 1 ? K : 0;
-    const int RW = wx + 2 * hx, RH = wy + 2 * hy;
+    const int RW = wx, RH = wy;
     const int FW = RW + 2, FP = FW | 1, FH = RH + 2, PS = FH * FP;
     T *f = sm, *ref = sm + nz * PS;
     int *rtab = reinterpret_cast<int *>(ref + nz * PS), *rzm = rtab + nz * FH, *rzp = rzm + FH, *ctab = rzp + FH;
@@ -1068,14 +754,14 @@ __global__ void __launch_bounds__(kBlock)
     const bool d3 = g.dim == 3;
     for (int i = threadIdx.x; i < nz * FH; i += kBlock) {
         const int p = i / FH;
-        rtab[i] = cr.row_code(y0 - hy - 1 + i - p * FH, z0 + p);
+        rtab[i] = cr.row_code(y0 - 1 + i - p * FH, z0 + p);
     }
     if (d3)
         for (int i = threadIdx.x; i < FH; i += kBlock) {
-            rzm[i] = cr.row_code(y0 - hy - 1 + i, z0 - 1);
-            rzp[i] = cr.row_code(y0 - hy - 1 + i, z0 + nz);
+            rzm[i] = cr.row_code(y0 - 1 + i, z0 - 1);
+            rzp[i] = cr.row_code(y0 - 1 + i, z0 + nz);
         }
-    for (int i = threadIdx.x; i < FW; i += kBlock) ctab[i] = cr.col_code(x0 - hx - 1 + i);
+    for (int i = threadIdx.x; i < FW; i += kBlock) ctab[i] = cr.col_code(x0 - 1 + i);
     __syncthreads();
     // stage the f planes (their rows are consecutive: row R = p * FH + r);
     // kLoadBatch loads in flight per lane: all table reads first, then the
@@ -1148,20 +834,18 @@ __global__ void __launch_bounds__(kBlock)
                     const T ext = in ? lo : hi;
                     if ((ext > T(0)) != in) {
                         rv = ratio(cur, cur - ext);
-                        if (euclid) {
-                            // |phi| / |grad phi|, central differences summed in
-                            // axis order, capped by the axis intercept above
-                            const T gx = (n1 - n0) * T(0.5), gy = (n3 - n2) * T(0.5);
-                            T gg = gx * gx;
-                            gg = gg + gy * gy;
-                            if (d3) {
-                                const T gz = (nxt - zm) * T(0.5);
-                                gg = gg + gz * gz;
-                            }
-                            if (gg > T(0)) {
-                                const T r = grad_dist(fabs(cur), gg);
-                                rv = rv < r ? rv : r;
-                            }
+                        // |phi| / |grad phi|, central differences summed in
+                        // axis order, capped by the axis intercept above
+                        const T gx = (n1 - n0) * T(0.5), gy = (n3 - n2) * T(0.5);
+                        T gg = gx * gx;
+                        gg = gg + gy * gy;
+                        if (d3) {
+                            const T gz = (nxt - zm) * T(0.5);
+                            gg = gg + gz * gz;
+                        }
+                        if (gg > T(0)) {
+                            const T r = grad_dist(fabs(cur), gg);
+                            rv = rv < r ? rv : r;
                         }
                     }
                 }
@@ -1172,186 +856,28 @@ __global__ void __launch_bounds__(kBlock)
         }
     }
     __syncthreads();
-    if (!euclid) {
-        // spreading: x along rows, then y along columns (one lane per line)
-        const bool ringx = it.nxs == 1 && ex == g.n[0];
-        for (int l = threadIdx.x; l < nz * RH; l += kBlock) {
-            const int p = l / RH;
-            sweep_line<T>(ref + p * PS + (l - p * RH + 1) * FP + 1, 1, RW, ringx);
-        }
-        __syncthreads();
-        const bool ringy = it.nys == 1 && ey == g.n[1];
-        for (int l = threadIdx.x; l < nz * RW; l += kBlock) {
-            const int p = l / RW;
-            sweep_line<T>(ref + p * PS + FP + l - p * RW + 1, FP, RH, ringy);
-        }
-        __syncthreads();
-    }
     T *outk = out + Ln.off[k];
     int *io_new = iota_new ? iota_new + Ln.off[k] : nullptr;
     const int *io_old = iota_old ? iota_old + cr.ooff : nullptr;
-    double vsum = 0.0;
     const int plane_vals = ex * ey;
     for (Walk2 w(threadIdx.x, wx); w.r < wy; w.step()) {
-        int a = (w.r + hy + 1) * FP + w.c + hx + 1;
+        int a = (w.r + 1) * FP + w.c + 1;
         int idx = (z0 * ey + y0 + w.r) * ex + x0 + w.c;
-        const int co = ctab[w.c + hx + 1];
+        const int co = ctab[w.c + 1];
         for (int p = 0; p < nz; ++p, a += PS, idx += plane_vals) {
-            const T d = ref[a];
-            const bool in = f[a] > T(0);
-            if (euclid) {
-                // reference value (+inf elsewhere) for the Jacobi sweeps, the
-                // inside flag in the sign bit (a zero value keeps it as well)
-                const T m = fabs(d);
-                outk[idx] = in ? m : -m;
-            } else if (!d3) {
-                const T dc = d < W ? d : W;
-                const T pv = in ? dc : -dc;
-                outk[idx] = pv;
-                double cl = (double)pv + 0.5;
-                cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
-                vsum += cl;
-            } else {
-                outk[idx] = in ? d : -d;
-            }
+            // reference value (+inf elsewhere) for the Jacobi sweeps, the
+            // inside flag in the sign bit (a zero value keeps it as well)
+            const T m = fabs(ref[a]);
+            outk[idx] = f[a] > T(0) ? m : -m;
             if (io_new) {
-                const int ro = rtab[p * FH + w.r + hy + 1];
+                const int ro = rtab[p * FH + w.r + 1];
                 io_new[idx] = (ro >= 0 && co >= 0) ? io_old[ro + co] : -1;
             }
         }
     }
-    if (!d3 && !euclid) {
-        const double s = block_sum(vsum, red);
-        if (threadIdx.x == 0) vol_part[item] = s;
-    }
 }
 
-// Fused z sweep (3D) over one tile (x chunk * z range) of ny consecutive y rows
-// of the new box: z spreading, sign and band clamp -> phi (optionally stored)
-// and the tile's volume; then the next predictor's z pass of phi -> t.
-//
-// LDS: z rows of QW = ny * wx values (the y rows side by side, so that the
-// lanes of a sweep or of the z convolution read consecutive words), then int
-// tables: the box offset of every column (y row and x) and of every z row.
-template <typename T, int RS>
-__global__ void __launch_bounds__(kBlock)
-    k_zfused(Boxes Ln, ItemRefs ir, const T *__restrict__ d2, T *__restrict__ phi_out,
-             T *__restrict__ t_out, double *__restrict__ vol_part, const T *__restrict__ taps, int K, int R_, T W,
-             int zsweep, GridArgs g) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *sm = reinterpret_cast<T *>(smem_raw);
-    __shared__ double red[kBlock / 64];
-    const int R = RS ? RS : R_;
-    const long long cls_item = xcd_item(ir.n);
-    if (cls_item >= ir.n) return;
-    const ItemTile it = decode_item(cls_item, KIND_ZF, Ln, ir);
-    const long long item = it.item;
-    const int k = it.k, y0 = it.plane, ny = it.np, x0 = it.x0, z0 = it.y0, wx = it.wx, wz = it.wy;
-    const int ex = Ln.ext[3 * k], ey = Ln.ext[3 * k + 1], ez = Ln.ext[3 * k + 2];
-    const int hz = it.nys > 1 ? K : 0;
-    const int DH = wz + 2 * R + 2 * hz, QW = ny * wx, plane = ex * ey;
-    T *dc = sm;  // DH + kKB rows
-    int *cq = reinterpret_cast<int *>(sm + (DH + kKB) * QW), *rz = cq + QW;
-    const T *src = d2 + Ln.off[k];
-    for (int q = threadIdx.x; q < QW; q += kBlock) {
-        const int j = q / wx;
-        cq[q] = (y0 + j) * ex + x0 + q - j * wx;
-    }
-    for (int r = threadIdx.x; r < DH; r += kBlock) {
-        const int zz = axis_map(z0 - R - hz + r, ez, g.n[2]);
-        rz[r] = zz >= 0 ? zz * plane : -1;
-    }
-    T tp[RS > 0 ? 2 * RS + 1 : 1];
-    if constexpr (RS > 0) {
-#pragma unroll
-        for (int t = 0; t <= 2 * RS; ++t) tp[t] = taps[t];
-    }
-    const T inf = tinf<T>();
-    __syncthreads();
-    // table reads first, then the loads without branches (a row off the box
-    // loads the box's first value and keeps +inf), then the LDS stores
-    for (Walk2 w(threadIdx.x, QW); w.r < DH;) {
-        int ro[kLoadBatch], co[kLoadBatch], at[kLoadBatch];
-#pragma unroll
-        for (int j = 0; j < kLoadBatch; ++j) {
-            const bool ok = w.r < DH;
-            ro[j] = rz[ok ? w.r : 0];
-            co[j] = cq[ok ? w.c : 0];
-            at[j] = ok ? w.r * QW + w.c : -1;
-            w.step();
-        }
-        T v[kLoadBatch];
-#pragma unroll
-        for (int j = 0; j < kLoadBatch; ++j) {
-            const bool hit = ro[j] >= 0;
-            const T x = src[hit ? ro[j] + co[j] : 0];
-            v[j] = hit ? x : inf;
-        }
-#pragma unroll
-        for (int j = 0; j < kLoadBatch; ++j)
-            if (at[j] >= 0) dc[at[j]] = v[j];
-    }
-    __syncthreads();
-    // z spreading, one lane per column; a whole periodic z axis is a ring whose
-    // copies in the halo rows are refreshed afterwards
-    const bool ring = it.nys == 1 && ez == g.n[2];
-    for (int q = threadIdx.x; zsweep && q < QW; q += kBlock) {
-        if (ring) {
-            sweep_line_signed<T>(dc + R * QW + q, QW, ez, true);
-            for (int j = 0; j < R; ++j) {
-                dc[j * QW + q] = dc[(ez + j) * QW + q];
-                dc[(R + ez + j) * QW + q] = dc[(R + j) * QW + q];
-            }
-        } else {
-            // rows outside the box hold the fill value and cannot lower a
-            // distance inside it: the box's rows are swept only
-            const int r_lo = max(0, R + hz - z0), r_hi = min(DH, ez - z0 + R + hz);
-            sweep_line_signed<T>(dc + r_lo * QW + q, QW, r_hi - r_lo, false);
-        }
-    }
-    __syncthreads();
-    // phi in place over the rows the z convolution reads (outside the box the
-    // predictor reads the fill value)
-    T *pc = dc + hz * QW;
-    const int PH = wz + 2 * R;
-    for (Walk2 w(threadIdx.x, QW); w.r < PH; w.step()) {
-        T *pv = pc + w.r * QW + w.c;
-        if (rz[w.r + hz] < 0) {
-            *pv = -W;
-        } else {
-            const T v = *pv, a = fabs(v);
-            const T d = a < W ? a : W;
-            *pv = signbit(v) ? -d : d;
-        }
-    }
-    __syncthreads();
-    T *phik = phi_out ? phi_out + Ln.off[k] : nullptr;
-    T *tk = t_out + Ln.off[k];
-    double vsum = 0.0;
-    const int ngz = (wz + kKB - 1) / kKB;
-    for (Walk2 w(threadIdx.x, QW); w.r < ngz; w.step()) {
-        const int r0 = w.r * kKB, q = w.c;
-        T acc[kKB];
-        gauss_run<T, RS>(pc + r0 * QW + q, QW, tp, taps, R, acc);
-        int idx = (z0 + r0) * plane + cq[q];
-#pragma unroll
-        for (int u = 0; u < kKB; ++u, idx += plane) {
-            const int r = r0 + u;
-            if (r >= wz) break;
-            const T p = pc[(r + R) * QW + q];
-            if (phik) phik[idx] = p;
-            double cl = (double)p + 0.5;
-            cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
-            vsum += cl;
-            tk[idx] = acc[u];
-        }
-    }
-    const double s = block_sum(vsum, red);
-    if (threadIdx.x == 0) vol_part[item] = s;
-}
 
-// Initial function before re-initialization: +1/2 on the grain's labelled
-// voxels, -1/2 elsewhere in its box.
 // Godunov's upwind update on a unit grid: the largest root u of
 // sum over the a_i below u of (u - a_i)^2 = 1, for neighbour values a1..a3
 // (+inf: no neighbour along that axis).  The three are sorted first; one
@@ -1706,7 +1232,6 @@ __global__ void __launch_bounds__(kBlock) k_init_indicator(Boxes L, const int *_
         out[L.off[k] + v] = lab == k ? T(0.5) : T(-0.5);
     }
 }
-
 // -------------------------------------------------------------- bookkeeping
 
 // Covered cyclic interval of a bit row: complement of the largest run of zeros
@@ -1753,7 +1278,9 @@ struct PlanArgs {
 
 // New boxes from the positive set of phi^c (sec. 3.1: size-adaptive boxes;
 // extinction when the set is empty).  Resets the bounding-box accumulators.
-__global__ void k_plan(Boxes Lo, Boxes Ln, int *bmin, int *bmax, unsigned *occ, long long *sizes, PlanArgs pa) {
+__global__ void k_plan(Boxes Lo, Boxes Ln, int *bmin, int *bmax, unsigned *occ, long long *sizes, PlanArgs pa,
+                       const Ctl *ctl) {
+    if (ctl_failed(ctl)) return;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= pa.G) return;
     const bool alive = Lo.alive[k] && bmax[3 * k] >= 0;
@@ -1803,14 +1330,13 @@ __global__ void k_plan(Boxes Lo, Boxes Ln, int *bmin, int *bmax, unsigned *occ, 
     }
 }
 
-// Per-grain work item counts of the stencil kinds, split into the two launch
-// classes, the stored tilings, and the largest LDS need per class (Jacobi
-// sweep items only when `jac` is set).
+// Per-grain work item counts of the Euclidean variant's kinds, split into the
+// two launch classes, the stored tilings, and the largest LDS need per class.
 // cnt holds 3 arrays of G per kind: all items, class 0, class 1.
 // One thread per (grain, kind); grid (ceil(G / 256), kKinds).  The per-class
 // LDS maxima are reduced over the wave before one atomic per wave and class.
-__global__ void k_item_counts(Boxes L, long long *cnt, int4 *tilings, unsigned long long *lds_max, int R, int K, int G,
-                              int budget, int small, int jac) {
+__global__ void k_item_counts(Boxes L, long long *cnt, int4 *tilings, unsigned long long *lds_max, int G, int budget,
+                              int small) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x, q = blockIdx.y;
     unsigned long long need_c[kClasses] = {0, 0};
     if (k < G) {
@@ -1818,16 +1344,16 @@ __global__ void k_item_counts(Boxes L, long long *cnt, int4 *tilings, unsigned l
         c[k] = c[G + k] = c[2LL * G + k] = 0;
         int4 *rec = tilings + 2 * ((long long)q * G + k);
         rec[0] = rec[1] = make_int4(0, 0, 0, 0);
-        if (L.alive[k] && (q != KIND_JAC || jac)) {
+        if (L.alive[k]) {
             const int *e = L.ext + 3 * k;
-            const Tiling t = kind_tiling(q, e, R, K, budget, small);
+            const Tiling t = kind_tiling(q, e, budget, small);
             rec[0] = make_int4(t.nxs, t.nys, t.tx, t.ty);
             rec[1] = make_int4(t.nb, 0, 0, 0);
             if (t.nxs == 0) {
                 need_c[1] = 0xffffffffffffffffULL;  // infeasible tiling
             } else {
-                const long long n = tiling_items(q, e, t);
-                const long long need = tiling_need(q, t, R, K);
+                const long long n = tiling_items(e, t);
+                const long long need = tiling_need(q, t);
                 const int cls = need <= small ? 0 : 1;
                 c[k] = n;
                 c[(1LL + cls) * G + k] = n;
@@ -1874,7 +1400,10 @@ __global__ void __launch_bounds__(1024) k_scan_multi(const long long *in, long l
 }
 
 // Exclusive prefix sum of n values (out has n + 1 entries), one work group.
-__global__ void __launch_bounds__(1024) k_scan(const long long *in, long long *out, int n) {
+// With a control block: a total above `cap` raises fail = 1 (the value arenas
+// are too small for the new layout) and records the need.
+__global__ void __launch_bounds__(1024) k_scan(const long long *in, long long *out, int n, Ctl *ctl, long long cap) {
+    if (ctl_failed(ctl)) return;
     __shared__ long long part[1024];
     const int t = threadIdx.x;
     const int chunk = (n + 1023) / 1024;
@@ -1894,10 +1423,22 @@ __global__ void __launch_bounds__(1024) k_scan(const long long *in, long long *o
         out[i] = base;
         base += in[i];
     }
-    if (t == 1023) out[n] = part[1023];
+    if (t == 1023) {
+        out[n] = part[1023];
+        if (ctl && part[1023] > cap) {
+            ctl->need_arena = part[1023];
+            ctl->fail_step = ctl->steps;
+            ctl->fail = 1;
+        }
+    }
 }
 
-__global__ void __launch_bounds__(1024) k_scan_int(const int *in, int *out, int n) {
+// Exclusive prefix sum of n coverage counts into `out` and `cur` (the fill
+// kernel's cursors), one work group; the 64-bit total goes to *total.  A total
+// above `cap` (or beyond 32-bit offsets) raises fail = 2 in the control block.
+__global__ void __launch_bounds__(1024) k_scan_int(const int *in, int *out, int *cur, int n, long long *total, Ctl *ctl,
+                                                   long long cap) {
+    if (ctl_failed(ctl)) return;
     __shared__ long long part[1024];
     const int t = threadIdx.x;
     const int chunk = (n + 1023) / 1024;
@@ -1929,14 +1470,26 @@ __global__ void __launch_bounds__(1024) k_scan_int(const int *in, int *out, int 
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             out[i + j] = (int)base;
+            cur[i + j] = (int)base;
             base += v[j];
         }
     }
     for (; i < e; ++i) {
         out[i] = (int)base;
+        cur[i] = (int)base;
         base += in[i];
     }
-    if (t == 1023) out[n] = (int)part[1023];
+    if (t == 1023) {
+        const long long tot = part[1023];
+        out[n] = (int)tot;
+        cur[n] = (int)tot;
+        *total = tot;
+        if (ctl && (tot > cap || tot > 0x7fffffffLL)) {
+            ctl->need_cov = tot;
+            ctl->fail_step = ctl->steps;
+            ctl->fail = 2;
+        }
+    }
 }
 
 // item -> grain maps, one per (kind, class) = blockIdx.y; pref holds the
@@ -1966,7 +1519,8 @@ __device__ inline void axis_tiles(int lo, int ext, int N, int T, int nt, int *t0
 
 // Coverage lists: for every global tile, the alive grains whose box covers it.
 // mode 0 counts, mode 1 fills (cursor = running positions).
-__global__ void k_coverage(Boxes L, int *cnt_or_cursor, int *list, TileArgs ta, int G, int mode) {
+__global__ void k_coverage(Boxes L, int *cnt_or_cursor, int *list, TileArgs ta, int G, int mode, const Ctl *ctl) {
+    if (ctl_failed(ctl)) return;
     const int k = blockIdx.x;
     if (!L.alive[k]) return;
     int t0[3], c[3];
@@ -1986,8 +1540,9 @@ __global__ void k_coverage(Boxes L, int *cnt_or_cursor, int *list, TileArgs ta, 
     }
 }
 
-// Per-grain volume from the per-item partial sums, in item order.
-// One wave per grain: lane-strided partial sums, then a butterfly (fixed order).
+// Per-grain volume from per-item partial sums, in item order (the Euclidean
+// variant's last 2D sweep).  One wave per grain: lane-strided partial sums,
+// then a butterfly (fixed order).
 __global__ void __launch_bounds__(64) k_volumes(const Boxes L, const long long *pref, const double *vol_part,
                                                 double *vol, int G) {
     const int k = blockIdx.x;
@@ -1999,15 +1554,17 @@ __global__ void __launch_bounds__(64) k_volumes(const Boxes L, const long long *
     if (threadIdx.x == 0) vol[k] = s;
 }
 
-__global__ void k_totals(const long long *arena_pref, const long long *pref, const int *cov_off, int ntiles,
+// Layout totals for the host: arena size, item counts and LDS maxima of the
+// Euclidean kinds (when pref is given), coverage entries, alive grains.
+__global__ void k_totals(const long long *arena_pref, const long long *pref, const long long *cov_total,
                          const int *alive, int G, const unsigned long long *lds_max, Totals *t) {
     if (threadIdx.x == 0) {
         t->arena = arena_pref[G];
         for (int q = 0; q < kKinds; ++q)
-            for (int j = 0; j < 3; ++j) t->items[q][j] = pref[((long long)q * 3 + j) * (G + 1) + G];
-        t->cov = cov_off ? cov_off[ntiles] : 0;
+            for (int j = 0; j < 3; ++j) t->items[q][j] = pref ? pref[((long long)q * 3 + j) * (G + 1) + G] : 0;
+        t->cov = cov_total ? *cov_total : 0;
         for (int q = 0; q < kKinds; ++q)
-            for (int c = 0; c < kClasses; ++c) t->lds[q][c] = (long long)lds_max[q * kClasses + c];
+            for (int c = 0; c < kClasses; ++c) t->lds[q][c] = pref ? (long long)lds_max[q * kClasses + c] : 0;
     }
     __shared__ int cnt;
     if (threadIdx.x == 0) cnt = 0;

@@ -1,22 +1,32 @@
 // Host side of the MI355X level-set grain-growth library: the C ABI declared
-// in include/gg.h, device memory ownership, and the per-step launch sequence
-//   predictor (xy, z) -> corrector (global tiles) -> box plan + item/coverage
-//   bookkeeping -> re-initialization (xy, z) into the new box layout -> volumes.
+// in include/gg.h, device memory ownership, and the launch sequence of a step
+//   corrector (global tiles) -> box plan, coverage lists of the new boxes ->
+//   re-initialization march (phi^c -> f, new boxes) -> predictor march
+//   (f -> psi, phi, volumes)
+// Every launch of a step has a fixed grid (one work group per grain or per
+// global tile) and the step's bookkeeping stays on the device: buffers are
+// sized with headroom, a step whose new layout does not fit raises a sticky
+// flag in a device control block that makes the rest of the step (and of the
+// batch) skip, and the host grows the buffers and takes the step again.  The
+// host therefore reads nothing back between steps, and a step can be captured
+// once in a HIP graph and replayed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <type_traits>
 #include <memory>
-#include <tuple>
 #include <string>
+#include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/gg.h"
 #include "gg_kernels.hpp"
+#include "gg_march.hpp"
 
 // Corrector tile of the 3D grid (powers of two, 512 voxels).
 #ifndef GG_CMP_TILE_X
@@ -28,6 +38,7 @@
 namespace {
 
 using gg::Boxes;
+using gg::Ctl;
 using gg::Totals;
 
 struct HipError {
@@ -98,6 +109,12 @@ struct DBuf {
         cap = 0;
         al = nullptr;
     }
+    void swap(DBuf &o) {
+        std::swap(p, o.p);
+        std::swap(cap, o.cap);
+        std::swap(al, o.al);
+        std::swap(al_stream, o.al_stream);
+    }
     template <typename U> U *as() const { return reinterpret_cast<U *>(p); }
 };
 
@@ -106,6 +123,18 @@ int pow2_divisor(int N, int target) {
     while (t > 1 && N % t) t >>= 1;
     return t;
 }
+
+// Roles of the value arenas: the predicted function psi; the corrected function
+// phi^c (and the materialised phi in 3D); f, the forward-spread distances (3D)
+// or phi (2D) or the Euclidean sweeps' result; the Euclidean sweeps' second
+// buffer.
+enum { A_PSI = 0, A_PHIC = 1, A_F = 2, A_SCR = 3 };
+
+struct Tuning {
+    int order_size, lds_bytes, small_bytes, candidates;
+    double ns_per_gv[8];
+    int cand_order[8], cand_lds[8], cand_small[8];
+};
 
 struct SimBase {
     virtual ~SimBase() = default;
@@ -123,14 +152,13 @@ struct SimBase {
     virtual void save(FILE *f) = 0;
     virtual void load(FILE *f) = 0;
     virtual void grid(int32_t *n) const = 0;
-    virtual void autotune(double dt, int per, int32_t *best_lds, int32_t *best_small) = 0;
+    virtual void autotune(double dt, int per, Tuning *out) = 0;
     virtual void sync() = 0;
-    virtual int alive_count() const = 0;
-    virtual gg_step_stats stats() const = 0;
-    virtual long long arena_total(bool prev) const = 0;
+    virtual int alive_count() = 0;
+    virtual gg_step_stats stats() = 0;
     virtual void profile(bool on) = 0;
-    virtual gg_kernel_times kernel_times() const = 0;
-    bool keep = false;
+    virtual gg_kernel_times kernel_times() = 0;
+    virtual void set_keep(bool on) = 0;
 };
 
 template <typename T> struct Sim final : SimBase {
@@ -139,35 +167,40 @@ template <typename T> struct Sim final : SimBase {
     int redist, K_euclid;  // re-initialization scheme of the steps; its Jacobi sweep count
     T W;
     double band_d;  // W as given
-    // LDS budget of a work group and limit of the small launch class (FP32
-    // bytes; FP64 tiles get the same values), tunable (gg_autotune)
+    // LDS budget of a work group and limit of the small launch class of the
+    // Euclidean variant's item tilings (FP32 bytes; FP64 tiles get the same
+    // values), tunable (gg_autotune)
     int lds_bytes = gg::kLdsBytes, small_bytes = gg::kSmallLdsBytes;
     int physics;
     double theta_c, voxel_m, gamma_max, headroom;
+    bool exact = false;  // capacities without slack
+    bool batched;
+    int order_size;  // per-grain kernels take the largest boxes first
     int tdim[3], nt[3], ntiles, occ_words;
     hipStream_t stream = nullptr;
     bool own_stream = false;
 
-    // layouts 0/1: box tables and work items
+    // layouts 0/1: box tables (+ the Euclidean variant's work items)
     DBuf lo[2], ext[2], alive[2], off[2];
     DBuf ipref[2], iowner[2][gg::kKinds * gg::kClasses], itile[2];
-    int items_R[2] = {-1, -1};
     Totals tot[2];
     int cur = 0;
 
     // per step accumulators and scratch
     DBuf bmin, bmax, occ, sizes, cnt, ldsmax, vol, vol_part;
-    DBuf cov_cnt, cov_off, cov_cur, cov_list;
-    DBuf taps_d, quat_d, energy_d, totals_d;
+    DBuf cov_cnt, cov_off, cov_cur, cov_list, cov_total;
+    DBuf taps_d, quat_d, energy_d, totals_d, ctl_d, order_d;
     Totals *totals_h = nullptr;
-    // value arenas and their roles for the current layout (-1: not held)
-    DBuf arena[4], iota_a[2];
-    int a_state = -1;  // phi, materialised
-    int a_T = -1;      // z pass of the predictor applied to phi (3D), radius T_R
-    int a_psi = -1;    // predicted function psi, radius psi_R
-    int T_R = -1, psi_R = -1;
+    Ctl *ctl_h = nullptr;
+    long long cap_arena = 0, cap_cov = 0;  // values per arena, coverage entries
+    DBuf arena[4];  // value arenas, roles A_PSI .. A_SCR
+    DBuf iota_a[2];
     int iota_cur = 0;  // ID-field of the current layout
+    bool psi_ok = false;  // arena A_PSI holds psi of the current layout and taps
+    int f_chain = 1;      // arena A_F: forward-spread distances (1) or a final function (0)
+    int a_phi = -1;       // arena holding phi of the current layout (-1: not materialised)
     // kept intermediates (test hook)
+    bool keep = false;
     DBuf keep_psi, keep_phic, keep_lo, keep_ext, keep_alive, keep_off;
     Totals keep_tot{};
     bool have_keep = false;
@@ -175,24 +208,43 @@ template <typename T> struct Sim final : SimBase {
     // current Gaussian
     double sigma = -1.0;
     int R = 0;
+    long long taps_epoch = 0;
     std::vector<T> taps_h;
 
-    long long steps_done = 0;
+    // host mirrors of the device counters (valid when nothing is pending)
+    long long steps_done = 0, total_gv = 0, last_gv = 0;
+    int alive_n = 0;
     double last_ms = 0.0;
-    long long last_gv = 0;
-    long long total_gv = 0;
+
+    // the steps queued by the last gg_step call
+    bool pending = false;
+    long long call_steps0 = 0;
+    int call_n = 0, call_cur0 = 0, call_ic0 = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    // captured steps: one graph per (layout parity, ID-field parity)
+    struct GSlot {
+        bool valid = false;
+        int cur = 0, ic = 0;
+        long long epoch = -1, taps = -1;
+        hipGraphExec_t exec = nullptr;
+    } gslot[4];
+    long long epoch = 0;  // bumped whenever a buffer the step uses moves
+    int gnext = 0;
 
     // per-kernel timing: HIP event pairs on the simulation's stream
     struct Span {
         hipEvent_t a, b;
         int cls;
         long long vox;
-        int n;  // kernel dispatches in the span
+        int vmode;  // voxel count: 0 as given, 1 the step's input layout, 2 its new layout
+        int n;      // kernel dispatches in the span
     };
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     std::vector<Span> spans;
+    size_t spans_step0 = 0;
     gg_kernel_times ktimes{};
 
     hipEvent_t next_event() {
@@ -203,9 +255,9 @@ template <typename T> struct Sim final : SimBase {
         }
         return ev_pool[ev_used++];
     }
-    void tbegin(int cls, long long vox) {
+    void tbegin(int cls, long long vox, int vmode = 0) {
         if (!prof) return;
-        Span sp{next_event(), nullptr, cls, vox, 1};
+        Span sp{next_event(), nullptr, cls, vox, vmode, 1};
         HIPCHECK(hipEventRecord(sp.a, stream));
         spans.push_back(sp);
     }
@@ -226,16 +278,25 @@ template <typename T> struct Sim final : SimBase {
             ktimes.voxels[sp.cls] += sp.vox;
         }
         spans.clear();
+        spans_step0 = 0;
         ev_used = 0;
     }
     void profile(bool on) override {
+        settle();
         resolve_spans();
         prof = on;
         std::memset(&ktimes, 0, sizeof(ktimes));
     }
-    gg_kernel_times kernel_times() const override { return ktimes; }
+    gg_kernel_times kernel_times() override {
+        settle();
+        resolve_spans();
+        return ktimes;
+    }
+    void set_keep(bool on) override {
+        settle();
+        keep = on;
+    }
 
-    const int4 *tiles_of(int l, int kind) const { return itile[l].as<int4>() + (size_t)kind * 2 * G; }
     Boxes boxes_of(int l) {
         return Boxes{lo[l].as<int>(), ext[l].as<int>(), alive[l].as<int>(), off[l].as<long long>()};
     }
@@ -255,6 +316,7 @@ template <typename T> struct Sim final : SimBase {
         g.dim = dim;
         return g;
     }
+    Ctl *ctl() const { return ctl_d.as<Ctl>(); }
 
     Sim(const gg_config &c, int G_, hipStream_t s) {
         dim = c.dim;
@@ -273,9 +335,12 @@ template <typename T> struct Sim final : SimBase {
         theta_c = c.theta_c_deg;
         voxel_m = c.voxel_m;
         gamma_max = c.gamma_max;
-        headroom = c.capacity_headroom > 1.0 ? c.capacity_headroom : 1.25;
+        // 0: default slack; 1: buffers hold exactly the current layout
+        headroom = c.capacity_headroom >= 1.0 ? c.capacity_headroom : 1.25;
+        exact = c.capacity_headroom == 1.0;
+        batched = c.batched != 0;
+        order_size = (c.flags & GG_FLAG_ORDER_SIZE) ? 1 : 0;
         set_tiles();
-        // occupancy rows keep this width when the grid is coarsened
         occ_words = (std::max(n[0], std::max(n[1], n[2])) + 31) / 32;
         if (s) {
             stream = s;
@@ -287,24 +352,39 @@ template <typename T> struct Sim final : SimBase {
             allocate_tables();
         } catch (...) {
             // a throwing constructor runs no destructor: hand back what is not a member buffer
-            if (totals_h) (void)hipHostFree(totals_h);
-            totals_h = nullptr;
+            free_host();
             if (own_stream && stream) (void)hipStreamDestroy(stream);
             stream = nullptr;
             throw;
         }
     }
 
+    void free_host() {
+        if (totals_h) (void)hipHostFree(totals_h);
+        if (ctl_h) (void)hipHostFree(ctl_h);
+        totals_h = nullptr;
+        ctl_h = nullptr;
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        ev0 = ev1 = nullptr;
+    }
+
     void allocate_tables() {
         HIPCHECK(hipHostMalloc((void **)&totals_h, sizeof(Totals), hipHostMallocDefault));
+        HIPCHECK(hipHostMalloc((void **)&ctl_h, sizeof(Ctl), hipHostMallocDefault));
         std::memset(totals_h, 0, sizeof(Totals));
+        std::memset(ctl_h, 0, sizeof(Ctl));
+        HIPCHECK(hipEventCreate(&ev0));
+        HIPCHECK(hipEventCreate(&ev1));
         for (int l = 0; l < 2; ++l) {
             lo[l].ensure(sizeof(int) * 3 * G);
             ext[l].ensure(sizeof(int) * 3 * G);
             alive[l].ensure(sizeof(int) * G);
             off[l].ensure(sizeof(long long) * (G + 1));
-            ipref[l].ensure(sizeof(long long) * 3 * gg::kKinds * (size_t)(G + 1));
-            itile[l].ensure(sizeof(int4) * 2 * gg::kKinds * (size_t)G);
+            if (redist == GG_REDIST_EUCLID) {
+                ipref[l].ensure(sizeof(long long) * 3 * gg::kKinds * (size_t)(G + 1));
+                itile[l].ensure(sizeof(int4) * 2 * gg::kKinds * (size_t)G);
+            }
         }
         bmin.ensure(sizeof(int) * 3 * G);
         bmax.ensure(sizeof(int) * 3 * G);
@@ -314,14 +394,21 @@ template <typename T> struct Sim final : SimBase {
         HIPCHECK(hipMemcpyAsync(bmin.p, init_min.data(), sizeof(int) * 3 * G, hipMemcpyHostToDevice, stream));
         HIPCHECK(hipMemcpyAsync(bmax.p, init_max.data(), sizeof(int) * 3 * G, hipMemcpyHostToDevice, stream));
         sizes.ensure(sizeof(long long) * G);
-        cnt.ensure(sizeof(long long) * 3 * gg::kKinds * (size_t)G);
-        ldsmax.ensure(sizeof(unsigned long long) * gg::kKinds * gg::kClasses);
+        if (redist == GG_REDIST_EUCLID) {
+            cnt.ensure(sizeof(long long) * 3 * gg::kKinds * (size_t)G);
+            ldsmax.ensure(sizeof(unsigned long long) * gg::kKinds * gg::kClasses);
+        }
         vol.ensure(sizeof(double) * G);
+        HIPCHECK(hipMemsetAsync(vol.p, 0, sizeof(double) * G, stream));
         cov_cnt.ensure(sizeof(int) * ntiles);
         cov_off.ensure(sizeof(int) * (ntiles + 1));
         cov_cur.ensure(sizeof(int) * (ntiles + 1));
+        cov_total.ensure(sizeof(long long));
         taps_d.ensure(sizeof(T) * (2 * gg::kMaxRadius + 1));
         totals_d.ensure(sizeof(Totals));
+        ctl_d.ensure(sizeof(Ctl));
+        order_d.ensure(sizeof(int) * G);
+        HIPCHECK(hipMemcpyAsync(ctl_d.p, ctl_h, sizeof(Ctl), hipMemcpyHostToDevice, stream));
         HIPCHECK(hipStreamSynchronize(stream));
     }
 
@@ -343,13 +430,22 @@ template <typename T> struct Sim final : SimBase {
         }
     }
 
-    // Switch to the periodic grid np (coarsening, checkpoint of a coarsened run).
+    // Switch to the periodic grid np (coarsening, checkpoint of another grid):
+    // corrector tiles, coverage counters and the occupancy rows of whole-axis
+    // boxes (one bit per voxel of an axis), grown for a finer grid.
     void set_grid(const int *np) {
         for (int a = 0; a < 3; ++a) n[a] = np[a];
         set_tiles();
         cov_cnt.ensure(sizeof(int) * ntiles);
         cov_off.ensure(sizeof(int) * (ntiles + 1));
         cov_cur.ensure(sizeof(int) * (ntiles + 1));
+        const int words = (std::max(n[0], std::max(n[1], n[2])) + 31) / 32;
+        if (words > occ_words) {
+            occ.ensure(sizeof(unsigned) * 3 * (size_t)G * words);
+            HIPCHECK(hipMemsetAsync(occ.p, 0, occ.cap, stream));
+            occ_words = words;
+        }
+        ++epoch;
     }
     void grid(int32_t *out) const override {
         for (int a = 0; a < 3; ++a) out[a] = n[a];
@@ -357,11 +453,13 @@ template <typename T> struct Sim final : SimBase {
 
     ~Sim() override {
         if (stream) (void)hipStreamSynchronize(stream);
-        DBuf *all[] = {&bmin, &bmax, &occ, &sizes, &ldsmax, &vol, &vol_part, &cov_cnt, &cov_off, &cov_cur,
-                       &cov_list, &taps_d, &quat_d, &energy_d, &totals_d, &keep_psi, &keep_phic, &keep_lo,
-                       &keep_ext, &keep_alive, &keep_off};
+        for (GSlot &g : gslot)
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        DBuf *all[] = {&bmin,     &bmax,     &occ,      &sizes,   &ldsmax,   &vol,       &vol_part, &cov_cnt,
+                       &cov_off,  &cov_cur,  &cov_list, &cov_total, &taps_d, &quat_d,    &energy_d, &totals_d,
+                       &ctl_d,    &order_d,  &keep_psi, &keep_phic, &keep_lo, &keep_ext, &keep_alive, &keep_off,
+                       &cnt};
         for (DBuf *b : all) b->release();
-        cnt.release();
         for (int l = 0; l < 2; ++l) {
             lo[l].release();
             ext[l].release();
@@ -374,75 +472,119 @@ template <typename T> struct Sim final : SimBase {
         }
         for (int a = 0; a < 4; ++a) arena[a].release();
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-        if (totals_h) (void)hipHostFree(totals_h);
+        free_host();
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
 
-    void sync() override { HIPCHECK(hipStreamSynchronize(stream)); }
-
-    // Arena capacity for a layout of `need` values (with headroom).
-    size_t grow_to(long long need) const { return (size_t)((double)need * headroom) + 1024; }
-
-    void ensure_arena(int a, long long need) {
-        if ((size_t)need * sizeof(T) <= arena[a].cap && arena[a].p) return;
-        arena[a].ensure(grow_to(need) * sizeof(T));
-    }
-    // First arena outside `excl` (bit mask of arenas holding live data) with room
-    // for `need` values; grows a dead one when none has room.
-    int pick(unsigned excl, long long need) {
-        for (int a = 0; a < 4; ++a)
-            if (!(excl >> a & 1u) && arena[a].p && (size_t)need * sizeof(T) <= arena[a].cap) return a;
-        for (int a = 0; a < 4; ++a)
-            if (!(excl >> a & 1u)) {
-                ensure_arena(a, need);
-                return a;
-            }
-        throw CapError{"no free value arena"};
-    }
-    static unsigned bit(int a) { return a >= 0 ? 1u << a : 0u; }
-
-    void ensure_iota(int a, long long need) {
-        if ((size_t)need * sizeof(int) <= iota_a[a].cap && iota_a[a].p) return;
-        iota_a[a].ensure(grow_to(need) * sizeof(int));
+    void sync() override {
+        settle();
+        HIPCHECK(hipStreamSynchronize(stream));
     }
 
-    // Offsets, work items and coverage counts of layout l; fills tot[l] (syncs).
-    // Then the item maps and the coverage lists.
-    void layout_meta_count(int l, bool coverage) {
+    // ------------------------------------------------------------ capacities
+
+    long long grow_to(long long need) const {
+        return exact ? std::max<long long>(need, 1) : (long long)((double)need * headroom) + 1024;
+    }
+    int n_arenas() const { return redist == GG_REDIST_EUCLID ? 4 : 3; }
+
+    // Grow a buffer to `bytes`, keeping its first `keep_bytes`.
+    void grow_keep(DBuf &b, size_t bytes, size_t keep_bytes) {
+        if (b.p && bytes <= b.cap) return;
+        DBuf nb;
+        nb.ensure(bytes);
+        if (b.p && keep_bytes) {
+            HIPCHECK(hipMemcpyAsync(nb.p, b.p, std::min(keep_bytes, b.cap), hipMemcpyDeviceToDevice, stream));
+            HIPCHECK(hipStreamSynchronize(stream));
+        }
+        b.swap(nb);
+        ++epoch;
+    }
+
+    // Value arenas (and ID-fields) for `need` values; arenas in `keep_mask`
+    // keep their contents.
+    void ensure_arenas(long long need, unsigned keep_mask) {
+        if (need <= cap_arena && arena[0].p) return;
+        const long long old = cap_arena;
+        if (exact) cap_arena = 0;
+        cap_arena = std::max(grow_to(need), cap_arena);
+        for (int a = 0; a < n_arenas(); ++a)
+            grow_keep(arena[a], sizeof(T) * (size_t)cap_arena, (keep_mask >> a & 1u) ? sizeof(T) * (size_t)old : 0);
+        if (physics)
+            for (int l = 0; l < 2; ++l) grow_keep(iota_a[l], sizeof(int) * (size_t)cap_arena, 0);
+        ++epoch;
+    }
+
+    void ensure_cov(long long need) {
+        if (need > 0x7fffffffLL) throw CapError{"coverage list exceeds 2^31 entries"};
+        if (need <= cap_cov && cov_list.p) return;
+        if (exact) cap_cov = 0;
+        cap_cov = std::min<long long>(std::max(grow_to(need), cap_cov), 0x7fffffffLL);
+        cov_list.ensure(sizeof(int) * (size_t)cap_cov);
+        ++epoch;
+    }
+
+    // Coverage lists of layout l, sized on the host (synchronous).
+    void build_coverage(int l) {
+        tbegin(GG_K_PLAN, 0);
+        HIPCHECK(hipMemsetAsync(cov_cnt.p, 0, sizeof(int) * ntiles, stream));
+        hipLaunchKernelGGL(gg::k_coverage, dim3(G), dim3(64), 0, stream, boxes_of(l), cov_cnt.as<int>(), (int *)nullptr,
+                           tile_args(), G, 0, (const Ctl *)nullptr);
+        hipLaunchKernelGGL(gg::k_scan_int, dim3(1), dim3(1024), 0, stream, cov_cnt.as<int>(), cov_off.as<int>(),
+                           cov_cur.as<int>(), ntiles, cov_total.as<long long>(), (Ctl *)nullptr, 0LL);
+        tend();
+        HIPCHECK(hipGetLastError());
+        long long total = 0;
+        HIPCHECK(hipMemcpyAsync(&total, cov_total.p, sizeof(long long), hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+        ensure_cov(total);
+        tbegin(GG_K_PLAN, 0);
+        hipLaunchKernelGGL(gg::k_coverage, dim3(G), dim3(64), 0, stream, boxes_of(l), cov_cur.as<int>(),
+                           cov_list.as<int>(), tile_args(), G, 1, (const Ctl *)nullptr);
+        tend();
+        HIPCHECK(hipGetLastError());
+        tot[l].cov = total;
+    }
+
+    // Arena size and alive count of layout l (synchronous).
+    void read_totals(int l) {
+        hipLaunchKernelGGL(gg::k_totals, dim3(1), dim3(256), 0, stream, (const long long *)off[l].as<long long>(),
+                           (const long long *)nullptr, (const long long *)nullptr, (const int *)alive[l].as<int>(), G,
+                           (const unsigned long long *)nullptr, totals_d.as<Totals>());
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipMemcpyAsync(totals_h, totals_d.p, sizeof(Totals), hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+        tot[l].arena = totals_h->arena;
+        tot[l].alive = totals_h->alive;
+    }
+
+    // Work items of the Euclidean variant's kinds on layout l (synchronous).
+    void layout_items(int l) {
         Boxes L = boxes_of(l);
         tbegin(GG_K_PLAN, 0);
         HIPCHECK(hipMemsetAsync(ldsmax.p, 0, sizeof(unsigned long long) * gg::kKinds * gg::kClasses, stream));
         const int tb = 256, gb = (G + tb - 1) / tb;
-        hipLaunchKernelGGL(gg::k_item_counts, dim3(gb, gg::kKinds), dim3(tb), 0, stream, L, cnt.as<long long>(), itile[l].as<int4>(),
-                           ldsmax.as<unsigned long long>(), R, K, G, gg::budget_values<T>(lds_bytes),
-                           gg::budget_values<T>(small_bytes), redist == GG_REDIST_EUCLID ? 1 : 0);
+        hipLaunchKernelGGL(gg::k_item_counts, dim3(gb, gg::kKinds), dim3(tb), 0, stream, L, cnt.as<long long>(),
+                           itile[l].as<int4>(), ldsmax.as<unsigned long long>(), G,
+                           gg::budget_values<T>(lds_bytes), gg::budget_values<T>(small_bytes));
         hipLaunchKernelGGL(gg::k_scan_multi, dim3(3 * gg::kKinds), dim3(1024), 0, stream, cnt.as<long long>(),
                            ipref[l].as<long long>(), G);
-        if (coverage) {
-            HIPCHECK(hipMemsetAsync(cov_cnt.p, 0, sizeof(int) * ntiles, stream));
-            hipLaunchKernelGGL(gg::k_coverage, dim3(G), dim3(64), 0, stream, L, cov_cnt.as<int>(), (int *)nullptr,
-                               tile_args(), G, 0);
-            hipLaunchKernelGGL(gg::k_scan_int, dim3(1), dim3(1024), 0, stream, cov_cnt.as<int>(), cov_off.as<int>(),
-                               ntiles);
-        }
-        hipLaunchKernelGGL(gg::k_totals, dim3(1), dim3(256), 0, stream, L.off, ipref[l].as<long long>(),
-                           coverage ? cov_off.as<int>() : (const int *)nullptr, ntiles, L.alive, G,
-                           ldsmax.as<unsigned long long>(), totals_d.as<Totals>());
+        hipLaunchKernelGGL(gg::k_totals, dim3(1), dim3(256), 0, stream, (const long long *)L.off,
+                           (const long long *)ipref[l].as<long long>(), (const long long *)nullptr,
+                           (const int *)L.alive, G, (const unsigned long long *)ldsmax.as<unsigned long long>(),
+                           totals_d.as<Totals>());
         HIPCHECK(hipGetLastError());
         tend();
         HIPCHECK(hipMemcpyAsync(totals_h, totals_d.p, sizeof(Totals), hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipStreamSynchronize(stream));
-        const long long keep_cov = tot[l].cov;
-        tot[l] = *totals_h;
-        if (!coverage) tot[l].cov = keep_cov;
-        for (int q = 0; q < gg::kKinds; ++q)
-            for (int c = 0; c < gg::kClasses; ++c)
+        for (int q = 0; q < gg::kKinds; ++q) {
+            for (int j = 0; j < 3; ++j) tot[l].items[q][j] = totals_h->items[q][j];
+            for (int c = 0; c < gg::kClasses; ++c) {
+                tot[l].lds[q][c] = totals_h->lds[q][c];
                 if (tot[l].lds[q][c] < 0 || tot[l].lds[q][c] > gg::budget_values<T>(lds_bytes))
                     throw CapError{"a box is too large for the stencil tiling"};
-        items_R[l] = R;
-    }
-
-    void layout_meta_fill(int l, bool coverage) {
+            }
+        }
         gg::OwnerMaps om;
         for (int q = 0; q < gg::kKinds; ++q)
             for (int c = 0; c < gg::kClasses; ++c) {
@@ -450,19 +592,9 @@ template <typename T> struct Sim final : SimBase {
                 b.ensure(sizeof(int) * (size_t)std::max<long long>(tot[l].items[q][1 + c], 1) * 5 / 4);
                 om.owner[q * gg::kClasses + c] = b.as<int>();
             }
-        if (coverage) {
-            if (tot[l].cov > 0x7fffffffLL) throw CapError{"coverage list exceeds 2^31 entries"};
-            cov_list.ensure(sizeof(int) * (size_t)std::max<long long>(tot[l].cov, 1) * 5 / 4);
-        }
         tbegin(GG_K_PLAN, 0);
         hipLaunchKernelGGL(gg::k_fill_owner, dim3(G, gg::kKinds * gg::kClasses), dim3(64), 0, stream,
                            ipref[l].as<long long>(), om, G);
-        if (coverage) {
-            HIPCHECK(hipMemcpyAsync(cov_cur.p, cov_off.p, sizeof(int) * (ntiles + 1), hipMemcpyDeviceToDevice,
-                                    stream));
-            hipLaunchKernelGGL(gg::k_coverage, dim3(G), dim3(64), 0, stream, boxes_of(l), cov_cur.as<int>(),
-                               cov_list.as<int>(), tile_args(), G, 1);
-        }
         HIPCHECK(hipGetLastError());
         tend();
     }
@@ -475,17 +607,18 @@ template <typename T> struct Sim final : SimBase {
         r.owner = iowner[l][kind * gg::kClasses + cls].as<int>();
         r.pref = pref_of(l, kind, 1 + cls);
         r.pref_all = pref_of(l, kind, 0);
-        r.tilings = tiles_of(l, kind);
+        r.tilings = itile[l].as<int4>() + (size_t)kind * 2 * G;
         r.n = tot[l].items[kind][1 + cls];
         return r;
     }
 
+    // New taps when sigma changes; a cached predicted function is then stale.
     void set_gaussian(double dt) {
         double s = std::sqrt(2.0 * dt) * (double)n[0];
         if (s == sigma) return;
         int r = (int)std::ceil(4.0 * s - 1e-9);
         if (r < 1) r = 1;
-        if (r > gg::kMaxRadius || r > 2 * P) throw ArgError{"kernel radius R = ceil(4 sigma) exceeds min(24, 2P)"};
+        if (r > gg::kMaxRadius || r > 2 * P) throw ArgError{"kernel radius R = ceil(4 sigma) exceeds min(12, 2P)"};
         std::vector<double> t(2 * r + 1);
         double s2 = 2.0 * s * s, sum = 0.0;
         for (int i = -r; i <= r; ++i) {
@@ -498,142 +631,96 @@ template <typename T> struct Sim final : SimBase {
         HIPCHECK(hipStreamSynchronize(stream));
         sigma = s;
         R = r;
+        psi_ok = false;
+        ++taps_epoch;
     }
 
-    gg::Physics<T> physics_args(const T *phi, const int *iota_p) const {
+    gg::Physics<T> physics_args(const int *iota_p) const {
         gg::Physics<T> ph;
         ph.mode = physics;
         ph.quat = quat_d.as<T>();
         ph.energy = energy_d.as<T>();
         ph.theta_c_deg = (T)theta_c;
         ph.bulk_scale = (physics & 2) ? (T)(sigma * sigma * voxel_m / (2.0 * gamma_max)) : T(0);
-        ph.phi = phi;
+        ph.phi = nullptr;
         ph.iota = iota_p;
         return ph;
     }
 
-    static unsigned grid_of(long long items) { return (unsigned)items; }
-
-    // Predictor x and y passes (+ correction epilogue) on layout l: src -> dst.
-    void launch_conv_xy(int l, const T *src, T *dst, const gg::Physics<T> &ph) {
-        const Totals &t = tot[l];
-        if (t.items[gg::KIND_CXY][0] <= 0) return;
-        tbegin(GG_K_CONV_XY, t.arena);
-        int nd = 0;
-        for (int c = 0; c < gg::kClasses; ++c) {
-            const gg::ItemRefs ir = refs(l, gg::KIND_CXY, c);
-            if (ir.n <= 0) continue;
-            ++nd;
-            const dim3 gr(grid_of(gg::xcd_grid(ir.n))), bl(gg::kBlock);
-            const size_t lds = sizeof(T) * t.lds[gg::KIND_CXY][c];
-            auto args = std::make_tuple(boxes_of(l), ir, src, dst, (const T *)taps_d.as<T>(), R, W, grid_args(), ph);
-            auto go = [&](auto kern) {
-                std::apply([&](auto... a) { hipLaunchKernelGGL(kern, gr, bl, lds, stream, a...); }, args);
-            };
-            if (ph.mode) {
-                if (R == 6) go(gg::k_conv_xy<T, 6, true>);
-                else if (R == 8) go(gg::k_conv_xy<T, 8, true>);
-                else go(gg::k_conv_xy<T, 0, true>);
-            } else if (R == 6) go(gg::k_conv_xy<T, 6, false>);
-            else if (R == 8) go(gg::k_conv_xy<T, 8, false>);
-            else go(gg::k_conv_xy<T, 0, false>);
-        }
-        tend(nd);
-        HIPCHECK(hipGetLastError());
+    gg::MarchArgs march_args(bool in_step) const {
+        gg::MarchArgs ma;
+        for (int a = 0; a < 3; ++a) ma.n[a] = n[a];
+        ma.dim = dim;
+        ma.G = G;
+        ma.K = K;
+        ma.R = R;
+        ma.order = (in_step && order_size) ? order_d.as<int>() : nullptr;
+        ma.ctl = in_step ? ctl() : nullptr;
+        return ma;
     }
 
-    // Predictor z pass alone on layout l (3D): src -> dst.
-    void launch_conv_z(int l, const T *src, T *dst) {
-        const Totals &t = tot[l];
-        if (t.items[gg::KIND_CZ][0] <= 0) return;
-        tbegin(GG_K_CONV_Z, t.arena);
-        int nd = 0;
-        for (int c = 0; c < gg::kClasses; ++c) {
-            const gg::ItemRefs ir = refs(l, gg::KIND_CZ, c);
-            if (ir.n <= 0) continue;
-            ++nd;
-            hipLaunchKernelGGL(gg::k_conv_z<T>, dim3(grid_of(gg::xcd_grid(ir.n))), dim3(gg::kBlock),
-                               sizeof(T) * t.lds[gg::KIND_CZ][c], stream, boxes_of(l), ir, src, dst, taps_d.as<T>(), R,
-                               W, grid_args());
-        }
-        tend(nd);
-        HIPCHECK(hipGetLastError());
-    }
+    // ------------------------------------------------------------ launches
 
-    // Re-initialization of phi^c (layout lo_l) into layout ln_l.  2D: the final
-    // function goes to `phi`.  3D: partial distances to `d2`, then the fused z
-    // sweep writes phi (when `phi` is not null) and the predictor z pass to `t`.
-    // Euclidean variant: reference values to `d2`, then K_euclid Jacobi sweeps
-    // between `d2` and `tz` (an even count: the result is back in `d2`; 2D: the
-    // last sweep writes `phi`), and in 3D the fused kernel without its z sweep.
-    void launch_reinit(int lo_l, int ln_l, const T *phic, T *d2, T *phi, T *tz, const int *iota_old, int *iota_new,
-                       bool euclid) {
-        const Totals &t = tot[ln_l];
-        const gg::GridArgs g = grid_args();
-        const int vk = dim == 3 ? gg::KIND_ZF : (euclid ? gg::KIND_JAC : gg::KIND_RXY);
-        vol_part.ensure(sizeof(double) * (size_t)std::max<long long>(t.items[vk][0], 1) * 5 / 4);
-        if (t.items[gg::KIND_RXY][0] > 0) {
-            tbegin(GG_K_REINIT_XY, t.arena);
-            int nd = 0;
-            T *out = dim == 3 || euclid ? d2 : phi;
-            for (int c = 0; c < gg::kClasses; ++c) {
-                const gg::ItemRefs ir = refs(ln_l, gg::KIND_RXY, c);
-                if (ir.n <= 0) continue;
-                ++nd;
-                hipLaunchKernelGGL(gg::k_reinit_xy<T>, dim3(grid_of(gg::xcd_grid(ir.n))), dim3(gg::kBlock),
-                                   sizeof(T) * t.lds[gg::KIND_RXY][c], stream, boxes_of(lo_l), boxes_of(ln_l), ir,
-                                   phic, out, iota_old, iota_new, vol_part.as<double>(), euclid ? 0 : K, W,
-                                   euclid ? 1 : 0, g);
-            }
-            tend(nd);
-            if (euclid) {
-                tbegin(GG_K_REINIT_SWEEP, t.arena);
-                nd = 0;
-                T *a = d2, *b = tz;
-                for (int s = 0; s < K_euclid; ++s) {
-                    const bool fin = dim == 2 && s == K_euclid - 1;
-                    T *dst = fin ? phi : b;
-                    for (int c = 0; c < gg::kClasses; ++c) {
-                        const gg::ItemRefs ir = refs(ln_l, gg::KIND_JAC, c);
-                        if (ir.n <= 0) continue;
-                        ++nd;
-                        hipLaunchKernelGGL(gg::k_jacobi<T>, dim3(grid_of(gg::xcd_grid(ir.n))), dim3(gg::kBlock),
-                                           sizeof(T) * t.lds[gg::KIND_JAC][c], stream, boxes_of(ln_l), ir,
-                                           (const T *)a, dst, vol_part.as<double>(), W, fin ? 1 : 0, g);
-                    }
-                    std::swap(a, b);
-                }
-                tend(nd);
-            }
-        }
-        if (dim == 3 && t.items[gg::KIND_ZF][0] > 0) {
-            tbegin(GG_K_REINIT_Z, t.arena);
-            int nd = 0;
-            for (int c = 0; c < gg::kClasses; ++c) {
-                const gg::ItemRefs ir = refs(ln_l, gg::KIND_ZF, c);
-                if (ir.n <= 0) continue;
-                ++nd;
-                const dim3 gr(grid_of(gg::xcd_grid(ir.n))), bl(gg::kBlock);
-                const size_t lds = sizeof(T) * t.lds[gg::KIND_ZF][c];
-                auto args = std::make_tuple(boxes_of(ln_l), ir, (const T *)d2, phi, tz, vol_part.as<double>(),
-                                            (const T *)taps_d.as<T>(), euclid ? 0 : K, R, W, euclid ? 0 : 1, g);
-                auto go = [&](auto kern) {
-                    std::apply([&](auto... a) { hipLaunchKernelGGL(kern, gr, bl, lds, stream, a...); }, args);
-                };
-                if (R == 6) go(gg::k_zfused<T, 6>);
-                else if (R == 8) go(gg::k_zfused<T, 8>);
-                else go(gg::k_zfused<T, 0>);
-            }
-            tend(nd);
-        }
-        tbegin(GG_K_VOLUME, t.arena);
-        hipLaunchKernelGGL(gg::k_volumes, dim3(G), dim3(64), 0, stream, boxes_of(ln_l), pref_of(ln_l, vk, 0),
-                           vol_part.as<double>(), vol.as<double>(), G);
+    // Re-initialization march: phi^c on layout lo_l -> f on layout ln_l (2D:
+    // the final function and the volumes).
+    void launch_reinit(int lo_l, int ln_l, const T *phic, T *out, const int *io_old, int *io_new, bool in_step) {
+        const gg::MarchArgs ma = march_args(in_step);
+        const size_t lds = 3 * (size_t)gg::march_buf<4>() * sizeof(T);
+        double *v = dim == 2 ? vol.as<double>() : nullptr;
+        tbegin(GG_K_REINIT, in_step ? 0 : tot[ln_l].arena, in_step ? 1 : 0);
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(G), dim3(gg::kMT), lds, stream, boxes_of(lo_l), boxes_of(ln_l), ma, phic,
+                               out, io_old, io_new, v, W);
+        };
+        if (K == 8) go(gg::k_reinit_march<T, 8, 4>);
+        else if (K == 6) go(gg::k_reinit_march<T, 6, 4>);
+        else go(gg::k_reinit_march<T, 0, 4>);
         tend();
         HIPCHECK(hipGetLastError());
     }
 
-    // ---------------------------------------------------------------- create
+    // Predictor march on layout l: in (f when chain, else a final function) ->
+    // psi (when given) with the correction epilogue, phi (when given), volumes.
+    void launch_predict(int l, T *in, int chain, T *psi, T *phi_out, const int *iota_l, bool in_step) {
+        const gg::MarchArgs ma = march_args(in_step);
+        const gg::Physics<T> ph = physics_args(iota_l);
+        double *v = dim == 3 ? vol.as<double>() : nullptr;
+        const int Rk = psi ? R : 8;
+        tbegin(GG_K_PREDICT, in_step ? 0 : tot[l].arena, in_step ? 2 : 0);
+        auto go = [&](auto kern, int yb) {
+            const size_t lds = 2 * (size_t)(gg::kMT * yb + 256) * sizeof(T);
+            hipLaunchKernelGGL(kern, dim3(G), dim3(gg::kMT), lds, stream, boxes_of(l), ma, in, psi, phi_out, v,
+                               (const T *)taps_d.as<T>(), ph, W, chain);
+        };
+        const bool phys = physics != 0 && psi != nullptr;
+        if (Rk == 8) {
+            if (phys) go(gg::k_predict_march<T, 8, 4, true>, 4);
+            else go(gg::k_predict_march<T, 8, 4, false>, 4);
+        } else if (Rk == 6) {
+            if (phys) go(gg::k_predict_march<T, 6, 4, true>, 4);
+            else go(gg::k_predict_march<T, 6, 4, false>, 4);
+        } else {
+            if (phys) go(gg::k_predict_march<T, 0, 2, true>, 2);
+            else go(gg::k_predict_march<T, 0, 2, false>, 2);
+        }
+        tend();
+        HIPCHECK(hipGetLastError());
+    }
+
+    void launch_compare(int L, const T *psi, T *phic, int *iota_out, int mode, bool in_step) {
+        tbegin(GG_K_COMPARE, 0, 1);
+        hipLaunchKernelGGL(gg::k_compare<T>, dim3((unsigned)gg::xcd_grid(ntiles)), dim3(gg::kBlock), 0, stream,
+                           boxes_of(L), (const int *)cov_off.as<int>(), (const int *)cov_list.as<int>(), psi, phic,
+                           iota_out, bmin.as<int>(), bmax.as<int>(), occ.as<unsigned>(), tile_args(), W, mode,
+                           in_step ? (const Ctl *)ctl() : (const Ctl *)nullptr);
+        tend();
+        HIPCHECK(hipGetLastError());
+    }
+
+    const int *iota_of(int ic) const { return physics ? iota_a[ic].as<int>() : nullptr; }
+    int *iota_w(int ic) { return physics ? iota_a[ic].as<int>() : nullptr; }
+
+    // ----------------------------------------------------------------- create
     void create(const int32_t *labels, const double *quat, const double *energy) {
         // initial boxes on the host: per axis the covered cyclic interval of the
         // grain's projection, padded by P (a box within 2P of the axis takes it all)
@@ -698,10 +785,16 @@ template <typename T> struct Sim final : SimBase {
             if (!ok)
                 for (int a = 0; a < 3; ++a) hlo[3 * k + a] = hext[3 * k + a] = 0;
         }
-        for (int k = 0; k < G; ++k)
+        int nalive = 0;
+        for (int k = 0; k < G; ++k) {
             hoff[k + 1] = hoff[k] + (hal[k] ? (long long)hext[3 * k] * hext[3 * k + 1] * hext[3 * k + 2] : 0);
+            nalive += hal[k];
+        }
         upload_table(0, hlo.data(), hext.data(), hal.data(), hoff.data());
         cur = 0;
+        iota_cur = 0;
+        tot[0].arena = hoff[G];
+        alive_n = nalive;
         if (physics & 1) {
             std::vector<T> q(4 * (size_t)G);
             for (size_t i = 0; i < q.size(); ++i) q[i] = (T)quat[i];
@@ -716,46 +809,41 @@ template <typename T> struct Sim final : SimBase {
             HIPCHECK(hipMemcpyAsync(energy_d.p, e.data(), sizeof(T) * G, hipMemcpyHostToDevice, stream));
             HIPCHECK(hipStreamSynchronize(stream));
         }
-        // initial function: re-initialised +-1/2 indicator, on the same boxes
-        // (the item bookkeeping needs a radius: R = 1 with identity taps; the
-        // z-convolved output of this pass is discarded)
-        set_identity_taps();
-        layout_meta_count(0, true);
-        layout_meta_fill(0, true);
-        const long long need = tot[0].arena;
-        for (int a = 0; a < 4; ++a) ensure_arena(a, need);
+        ensure_arenas(hoff[G], 0u);
+        build_coverage(0);
+        // initial function: the re-initialised +-1/2 indicator on the same boxes
         DBuf lab;
         lab.ensure(sizeof(int32_t) * nt3);
         HIPCHECK(hipMemcpyAsync(lab.p, labels, sizeof(int32_t) * nt3, hipMemcpyHostToDevice, stream));
         hipLaunchKernelGGL(gg::k_init_indicator<T>, dim3(G), dim3(gg::kBlock), 0, stream, boxes_of(0),
-                           lab.as<int>(), arena[0].as<T>(), grid_args());
+                           lab.as<int>(), arena[A_PHIC].as<T>(), grid_args());
         HIPCHECK(hipGetLastError());
-        launch_reinit(0, 0, arena[0].as<T>(), arena[1].as<T>(), arena[2].as<T>(), arena[3].as<T>(), nullptr,
-                      nullptr, false);
-        a_state = 2;
-        a_T = a_psi = -1;
-        T_R = psi_R = -1;
+        reinit_in_place(0, A_PHIC);
         HIPCHECK(hipStreamSynchronize(stream));
         lab.release();
-        if (physics) {
-            ensure_iota(0, need);
-            ensure_iota(1, need);
-            iota_cur = 0;
-            hipLaunchKernelGGL(gg::k_compare<T>, dim3(grid_of(gg::xcd_grid(ntiles))), dim3(gg::kBlock), 0, stream, boxes_of(0),
-                               cov_off.as<int>(), cov_list.as<int>(), arena[a_state].as<T>(), (T *)nullptr,
-                               iota_a[0].as<int>(), bmin.as<int>(), bmax.as<int>(), occ.as<unsigned>(),
-                               tile_args(), W, 1);
-            HIPCHECK(hipGetLastError());
-            HIPCHECK(hipStreamSynchronize(stream));
-        }
+        if (physics) initial_iota();
     }
 
-    void set_identity_taps() {
-        std::vector<T> t = {T(0), T(1), T(0)};
-        HIPCHECK(hipMemcpyAsync(taps_d.p, t.data(), sizeof(T) * 3, hipMemcpyHostToDevice, stream));
+    // Re-initialization of the values in arena `src` on layout l (creation,
+    // coarsening): phi into a_phi, f (3D) or phi (2D) into A_F, volumes.
+    void reinit_in_place(int l, int src) {
+        launch_reinit(l, l, arena[src].as<T>(), arena[A_F].as<T>(), nullptr, nullptr, false);
+        if (dim == 3) {
+            launch_predict(l, arena[A_F].as<T>(), 1, nullptr, arena[A_PHIC].as<T>(), nullptr, false);
+            a_phi = A_PHIC;
+            f_chain = 1;
+        } else {
+            a_phi = A_F;
+            f_chain = 0;
+        }
+        psi_ok = false;
+    }
+
+    // ID-field of the current phi: argmax of the other grains' functions.
+    void initial_iota() {
+        iota_cur = 0;
+        launch_compare(cur, arena[a_phi].as<T>(), (T *)nullptr, iota_a[0].as<int>(), 1, false);
         HIPCHECK(hipStreamSynchronize(stream));
-        R = 1;
-        sigma = -1.0;
     }
 
     void upload_table(int l, const int *hlo, const int *hext, const int *hal, const long long *hoff) {
@@ -767,68 +855,22 @@ template <typename T> struct Sim final : SimBase {
     }
 
     // ------------------------------------------------------------------ step
-    void step(double dt, int nsteps) override {
-        set_gaussian(dt);
-        hipEvent_t e0, e1;
-        HIPCHECK(hipEventCreate(&e0));
-        HIPCHECK(hipEventCreate(&e1));
-        HIPCHECK(hipEventRecord(e0, stream));
-        for (int s = 0; s < nsteps; ++s) step_once(s == nsteps - 1);
-        HIPCHECK(hipEventRecord(e1, stream));
-        HIPCHECK(hipEventSynchronize(e1));
-        resolve_spans();
-        float ms = 0.f;
-        HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        if (nsteps > 0) last_ms = ms / nsteps;
+
+    // psi of the current layout from the state in A_F.
+    void predict_state() {
+        launch_predict(cur, arena[A_F].as<T>(), f_chain, arena[A_PSI].as<T>(), nullptr, iota_of(iota_cur), false);
+        psi_ok = true;
     }
 
-    const int *iota_now() { return physics ? iota_a[iota_cur].as<int>() : nullptr; }
-
-    // psi of the current layout from phi (or from the kept z pass of phi).
-    void predict(int l) {
-        const long long m = tot[l].arena;
-        int src = a_state;
-        if (dim == 3) {
-            if (a_T < 0 || T_R != R) {
-                a_T = pick(bit(a_state), m);
-                launch_conv_z(l, arena[a_state].as<T>(), arena[a_T].as<T>());
-                T_R = R;
-            }
-            src = a_T;
-        }
-        a_psi = pick(bit(a_state) | bit(src), m);
-        const T *phi = a_state >= 0 ? arena[a_state].as<T>() : nullptr;
-        launch_conv_xy(l, arena[src].as<T>(), arena[a_psi].as<T>(), physics_args(phi, iota_now()));
-        psi_R = R;
-    }
-
-    void step_once(bool last) {
-        const int L = cur, Ln = 1 - cur;
-        if (items_R[L] != R) {
-            layout_meta_count(L, false);
-            layout_meta_fill(L, false);
-        }
-        const Totals &t = tot[L];
-        last_gv = t.arena;
-        total_gv += t.arena;
-        // 1. predictor (already issued at the end of the previous step when possible)
-        if (a_psi < 0 || psi_R != R) predict(L);
-        // 2. corrector: psi -> phi^c (phi, its z pass and psi are dead afterwards)
-        const int a_phic = pick(bit(a_psi), t.arena);
-        T *psi = arena[a_psi].as<T>(), *phic = arena[a_phic].as<T>();
-        const int iota_old = 1 - iota_cur;
-        if (physics) ensure_iota(iota_old, t.arena);
-        tbegin(GG_K_COMPARE, t.arena);
-        hipLaunchKernelGGL(gg::k_compare<T>, dim3(grid_of(gg::xcd_grid(ntiles))), dim3(gg::kBlock), 0, stream, boxes_of(L), cov_off.as<int>(),
-                           cov_list.as<int>(), psi, phic, physics ? iota_a[iota_old].as<int>() : (int *)nullptr,
-                           bmin.as<int>(), bmax.as<int>(), occ.as<unsigned>(), tile_args(), W, 0);
-        tend();
-        HIPCHECK(hipGetLastError());
-        if (keep) keep_copy(L, psi, phic);
-        a_state = a_T = a_psi = -1;
-        // 3. new boxes, offsets, items and coverage of the new layout
+    // The kernels of one step from layout L (ID-field parity ic) to layout
+    // 1 - L (1 - ic).  No host synchronisation: the step can be captured.
+    void issue_step(int L, int ic) {
+        const int Ln = 1 - L, icn = 1 - ic;
+        Ctl *c = ctl();
+        // 1. corrector: psi -> phi^c, ID-field, bounding boxes of phi^c > 0
+        launch_compare(L, arena[A_PSI].as<T>(), arena[A_PHIC].as<T>(), iota_w(ic), 0, true);
+        if (keep) keep_copy(L, arena[A_PSI].as<T>(), arena[A_PHIC].as<T>());
+        // 2. new boxes, offsets (capacity check), coverage lists (capacity check), launch order
         gg::PlanArgs pa;
         for (int a = 0; a < 3; ++a) pa.n[a] = n[a];
         pa.P = P;
@@ -837,46 +879,255 @@ template <typename T> struct Sim final : SimBase {
         const int tb = 256, gb = (G + tb - 1) / tb;
         tbegin(GG_K_PLAN, 0);
         hipLaunchKernelGGL(gg::k_plan, dim3(gb), dim3(tb), 0, stream, boxes_of(L), boxes_of(Ln), bmin.as<int>(),
-                           bmax.as<int>(), occ.as<unsigned>(), sizes.as<long long>(), pa);
-        hipLaunchKernelGGL(gg::k_scan, dim3(1), dim3(1024), 0, stream, sizes.as<long long>(), off[Ln].as<long long>(), G);
+                           bmax.as<int>(), occ.as<unsigned>(), sizes.as<long long>(), pa, (const Ctl *)c);
+        hipLaunchKernelGGL(gg::k_scan, dim3(1), dim3(1024), 0, stream, (const long long *)sizes.as<long long>(),
+                           off[Ln].as<long long>(), G, c, cap_arena);
+        hipLaunchKernelGGL(gg::k_zero_int, dim3((ntiles + 255) / 256), dim3(256), 0, stream, cov_cnt.as<int>(), ntiles,
+                           (const Ctl *)c);
+        hipLaunchKernelGGL(gg::k_coverage, dim3(G), dim3(64), 0, stream, boxes_of(Ln), cov_cnt.as<int>(),
+                           (int *)nullptr, tile_args(), G, 0, (const Ctl *)c);
+        hipLaunchKernelGGL(gg::k_scan_int, dim3(1), dim3(1024), 0, stream, (const int *)cov_cnt.as<int>(),
+                           cov_off.as<int>(), cov_cur.as<int>(), ntiles, cov_total.as<long long>(), c, cap_cov);
+        hipLaunchKernelGGL(gg::k_coverage, dim3(G), dim3(64), 0, stream, boxes_of(Ln), cov_cur.as<int>(),
+                           cov_list.as<int>(), tile_args(), G, 1, (const Ctl *)c);
+        if (order_size)
+            hipLaunchKernelGGL(gg::k_order_size, dim3(1), dim3(1024), 0, stream,
+                               (const long long *)off[Ln].as<long long>(), (const int *)alive[Ln].as<int>(),
+                               order_d.as<int>(), G, (const Ctl *)c);
+        tend(order_size ? 7 : 6);
+        HIPCHECK(hipGetLastError());
+        // 3. re-initialization into the new boxes, 4. the next predictor
+        if (redist == GG_REDIST_EUCLID) {
+            euclid_reinit(L, Ln, ic, icn);
+        } else {
+            launch_reinit(L, Ln, arena[A_PHIC].as<T>(), arena[A_F].as<T>(), iota_of(ic), iota_w(icn), true);
+        }
+        const int chain = (dim == 3 && redist != GG_REDIST_EUCLID) ? 1 : 0;
+        launch_predict(Ln, arena[A_F].as<T>(), chain, arena[A_PSI].as<T>(),
+                       dim == 3 ? arena[A_PHIC].as<T>() : (T *)nullptr, iota_of(icn), true);
+        tbegin(GG_K_PLAN, 0);
+        hipLaunchKernelGGL(gg::k_step_end, dim3(1), dim3(1024), 0, stream, c, (const int *)alive[Ln].as<int>(),
+                           (const long long *)off[L].as<long long>(), (const long long *)off[Ln].as<long long>(),
+                           (const long long *)cov_total.as<long long>(), G);
         tend();
         HIPCHECK(hipGetLastError());
-        layout_meta_count(Ln, true);
-        const long long need = tot[Ln].arena;
-        for (int a = 0; a < 4; ++a)
-            if (a != a_phic) ensure_arena(a, need);  // all dead: grow before the writes
-        if (physics) ensure_iota(iota_cur, need);
-        layout_meta_fill(Ln, true);
-        // 4. re-initialization into the new layout (+ the next predictor's z pass)
-        const int *io_old = physics ? iota_a[iota_old].as<int>() : nullptr;
-        int *io_new = physics ? iota_a[iota_cur].as<int>() : nullptr;
-        if (dim == 3) {
-            const int a_d2 = pick(bit(a_phic), need);
-            const int a_t = pick(bit(a_phic) | bit(a_d2), need);
-            const bool write_phi = last || physics;
-            const int a_phi = write_phi ? pick(bit(a_phic) | bit(a_d2) | bit(a_t), need) : -1;
-            launch_reinit(L, Ln, phic, arena[a_d2].as<T>(), write_phi ? arena[a_phi].as<T>() : nullptr,
-                          arena[a_t].as<T>(), io_old, io_new, redist == GG_REDIST_EUCLID);
-            a_T = a_t;
-            T_R = R;
-            a_state = a_phi;
-        } else {
-            const int a_phi = pick(bit(a_phic), need);
-            if (redist == GG_REDIST_EUCLID) {
-                // the Jacobi sweeps alternate between two more arenas
-                const int a_u = pick(bit(a_phic) | bit(a_phi), need);
-                const int a_v = pick(bit(a_phic) | bit(a_phi) | bit(a_u), need);
-                launch_reinit(L, Ln, phic, arena[a_u].as<T>(), arena[a_phi].as<T>(), arena[a_v].as<T>(), io_old,
-                              io_new, true);
-            } else {
-                launch_reinit(L, Ln, phic, nullptr, arena[a_phi].as<T>(), nullptr, io_old, io_new, false);
+    }
+
+    // The Euclidean variant's re-initialization (synchronous: its work items
+    // are sized on the host).  A step whose layout failed the capacity checks
+    // is left to the caller.
+    void euclid_reinit(int L, int Ln, int ic, int icn) {
+        HIPCHECK(hipMemcpyAsync(ctl_h, ctl_d.p, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+        if (ctl_h->fail) return;
+        layout_items(Ln);
+        const Totals &t = tot[Ln];
+        const gg::GridArgs g = grid_args();
+        T *u = arena[A_F].as<T>(), *v2 = arena[A_SCR].as<T>();
+        if (t.items[gg::KIND_RXY][0] > 0) {
+            tbegin(GG_K_REINIT, 0, 2);
+            int nd = 0;
+            for (int c = 0; c < gg::kClasses; ++c) {
+                const gg::ItemRefs ir = refs(Ln, gg::KIND_RXY, c);
+                if (ir.n <= 0) continue;
+                ++nd;
+                hipLaunchKernelGGL(gg::k_reinit_xy<T>, dim3((unsigned)gg::xcd_grid(ir.n)), dim3(gg::kBlock),
+                                   sizeof(T) * t.lds[gg::KIND_RXY][c], stream, boxes_of(L), boxes_of(Ln), ir,
+                                   (const T *)arena[A_PHIC].as<T>(), u, iota_of(ic), iota_w(icn), W, g);
             }
-            a_state = a_phi;
+            tend(nd);
+            HIPCHECK(hipGetLastError());
         }
-        cur = Ln;
-        ++steps_done;
-        // 5. the next step's predictor
-        if (!last) predict(Ln);
+        vol_part.ensure(sizeof(double) * (size_t)std::max<long long>(t.items[gg::KIND_JAC][0], 1) * 5 / 4);
+        tbegin(GG_K_REINIT_SWEEP, 0, 2);
+        int nd = 0;
+        T *a = u, *b = v2;
+        for (int s = 0; s < K_euclid; ++s) {
+            const bool fin = dim == 2 && s == K_euclid - 1;  // K_euclid is even: the last sweep writes u
+            T *dst = fin ? u : b;
+            for (int c = 0; c < gg::kClasses; ++c) {
+                const gg::ItemRefs ir = refs(Ln, gg::KIND_JAC, c);
+                if (ir.n <= 0) continue;
+                ++nd;
+                hipLaunchKernelGGL(gg::k_jacobi<T>, dim3((unsigned)gg::xcd_grid(ir.n)), dim3(gg::kBlock),
+                                   sizeof(T) * t.lds[gg::KIND_JAC][c], stream, boxes_of(Ln), ir, (const T *)a, dst,
+                                   vol_part.as<double>(), W, fin ? 1 : 0, g);
+            }
+            std::swap(a, b);
+        }
+        tend(nd);
+        HIPCHECK(hipGetLastError());
+        if (dim == 2) {
+            tbegin(GG_K_PLAN, 0);
+            hipLaunchKernelGGL(gg::k_volumes, dim3(G), dim3(64), 0, stream, boxes_of(Ln), pref_of(Ln, gg::KIND_JAC, 0),
+                               (const double *)vol_part.as<double>(), vol.as<double>(), G);
+            tend();
+            HIPCHECK(hipGetLastError());
+        }
+    }
+
+    hipGraphExec_t graph_for(int c, int ic) {
+        for (GSlot &g : gslot)
+            if (g.valid && g.cur == c && g.ic == ic && g.epoch == epoch && g.taps == taps_epoch) return g.exec;
+        GSlot &g = gslot[gnext];
+        gnext = (gnext + 1) % 4;
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g.exec = nullptr;
+        g.valid = false;
+        hipGraph_t graph = nullptr;
+        HIPCHECK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        try {
+            issue_step(c, ic);
+        } catch (...) {
+            (void)hipStreamEndCapture(stream, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        HIPCHECK(hipStreamEndCapture(stream, &graph));
+        hipGraphExec_t ex = nullptr;
+        hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHECK(e);
+        g.valid = true;
+        g.cur = c;
+        g.ic = ic;
+        g.epoch = epoch;
+        g.taps = taps_epoch;
+        g.exec = ex;
+        return ex;
+    }
+
+    // Queue `nsteps` steps from the current layout (no synchronisation).
+    void run_steps(int nsteps, bool use_graphs) {
+        for (int s = 0; s < nsteps; ++s) {
+            if (use_graphs) {
+                HIPCHECK(hipGraphLaunch(graph_for(cur, iota_cur), stream));
+            } else {
+                if (prof) spans_step0 = spans.size();
+                issue_step(cur, iota_cur);
+                if (prof) resolve_step_voxels();
+                if (redist == GG_REDIST_EUCLID && ctl_h->fail) {  // read back by euclid_reinit
+                    grow_after_failure();
+                    --s;
+                    continue;
+                }
+            }
+            cur = 1 - cur;
+            iota_cur = 1 - iota_cur;
+        }
+    }
+
+    // Profiling: the voxel counts of the last step's spans (synchronous).
+    void resolve_step_voxels() {
+        HIPCHECK(hipMemcpyAsync(ctl_h, ctl_d.p, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+        for (size_t i = spans_step0; i < spans.size(); ++i) {
+            if (spans[i].vmode == 1) spans[i].vox = ctl_h->fail ? 0 : ctl_h->last_gv;
+            if (spans[i].vmode == 2) spans[i].vox = ctl_h->fail ? 0 : ctl_h->arena_now;
+        }
+    }
+
+    void upload_ctl(int phi_at) {
+        ctl_h->fail = 0;
+        ctl_h->fail_step = 0;
+        ctl_h->steps = (int)steps_done;
+        ctl_h->alive = alive_n;
+        ctl_h->phi_at = phi_at;
+        ctl_h->total_gv = total_gv;
+        ctl_h->last_gv = last_gv;
+        ctl_h->arena_now = tot[cur].arena;
+        ctl_h->cov_now = tot[cur].cov;
+        HIPCHECK(hipMemcpyAsync(ctl_d.p, ctl_h, sizeof(Ctl), hipMemcpyHostToDevice, stream));
+    }
+
+    void step(double dt, int nsteps) override {
+        settle();
+        if (nsteps <= 0) return;
+        set_gaussian(dt);
+        if (!psi_ok) predict_state();
+        call_steps0 = steps_done;
+        call_n = nsteps;
+        call_cur0 = cur;
+        call_ic0 = iota_cur;
+        upload_ctl((int)(steps_done + nsteps - 1));
+        const bool graphs = batched && !prof && !keep && redist != GG_REDIST_EUCLID;
+        HIPCHECK(hipEventRecord(ev0, stream));
+        run_steps(nsteps, graphs);
+        HIPCHECK(hipEventRecord(ev1, stream));
+        pending = true;
+        a_phi = dim == 3 ? A_PHIC : A_F;
+        f_chain = (dim == 3 && redist != GG_REDIST_EUCLID) ? 1 : 0;
+        psi_ok = true;
+        have_keep = keep;
+        if (!batched) settle();
+    }
+
+    // Wait for the queued steps, take over the device counters, and finish the
+    // steps a capacity failure stopped.
+    void settle() {
+        if (!pending) return;
+        pending = false;
+        HIPCHECK(hipMemcpyAsync(ctl_h, ctl_d.p, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, ev0, ev1));
+        if (call_n > 0) last_ms = ms / call_n;
+        if (ctl_h->fail) recover();
+        steps_done = ctl_h->steps;
+        total_gv = ctl_h->total_gv;
+        last_gv = ctl_h->last_gv;
+        alive_n = ctl_h->alive;
+        tot[cur].arena = ctl_h->arena_now;
+        tot[cur].cov = ctl_h->cov_now;
+        resolve_spans();
+    }
+
+    // A step failed its capacity check (ctl_h read back); the state it started
+    // from (psi in A_PSI on layout cur) is intact.  Grow the buffer that was too
+    // small and rebuild the coverage lists of that layout when the failing step
+    // overwrote them; the counters of the completed steps stand.
+    void grow_after_failure() {
+        const int why = ctl_h->fail;
+        if (why == 1) ensure_arenas(ctl_h->need_arena, 1u << A_PSI);
+        if (why == 2) ensure_cov(ctl_h->need_cov);
+        steps_done = ctl_h->steps;
+        total_gv = ctl_h->total_gv;
+        last_gv = ctl_h->last_gv;
+        alive_n = ctl_h->alive;
+        if (why == 2) build_coverage(cur);
+        upload_ctl(ctl_h->phi_at);
+    }
+
+    // Take again the queued steps from the one that failed.
+    void recover() {
+        for (int round = 0; ctl_h->fail; ++round) {
+            if (round > 8) throw CapError{"the step layout keeps outgrowing the device buffers"};
+            const int completed = (int)(ctl_h->steps - call_steps0);
+            const int remaining = call_n - completed;
+            cur = call_cur0 ^ (completed & 1);
+            iota_cur = call_ic0 ^ (completed & 1);
+            grow_after_failure();
+            call_steps0 = steps_done;
+            call_n = remaining;
+            call_cur0 = cur;
+            call_ic0 = iota_cur;
+            run_steps(remaining, false);
+            HIPCHECK(hipMemcpyAsync(ctl_h, ctl_d.p, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+            HIPCHECK(hipStreamSynchronize(stream));
+        }
+    }
+
+    // phi of the current layout (materialised from A_F when needed).
+    void ensure_phi() {
+        settle();
+        if (a_phi >= 0) return;
+        if (dim == 3) {
+            launch_predict(cur, arena[A_F].as<T>(), f_chain, nullptr, arena[A_PHIC].as<T>(), nullptr, false);
+            a_phi = A_PHIC;
+        } else {
+            a_phi = A_F;
+        }
+        HIPCHECK(hipStreamSynchronize(stream));
     }
 
     // Grid coarsening onto np (validated by the caller): projection of the
@@ -885,7 +1136,7 @@ template <typename T> struct Sim final : SimBase {
     // creation, the ID-field rebuilt when the correction is on.
     void coarsen(const int32_t *np_in) override {
         int np[3] = {np_in[0], np_in[1], np_in[2]};
-        if (a_state < 0) throw ArgError{"no materialised state to coarsen"};
+        ensure_phi();
         HIPCHECK(hipStreamSynchronize(stream));
         const int L = cur, Ln = 1 - cur;
         gg::CoarsenArgs<T> ca;
@@ -911,7 +1162,7 @@ template <typename T> struct Sim final : SimBase {
         HIPCHECK(hipMemsetAsync(occ.p, 0, occ.cap, stream));
         tbegin(GG_K_PLAN, 0);
         hipLaunchKernelGGL(gg::k_coarsen_mark<T>, dim3(G, split), dim3(gg::kBlock), 0, stream, boxes_of(L),
-                           (const T *)arena[a_state].as<T>(), ca, bmax.as<int>(), occ.as<unsigned>(), occ_words);
+                           (const T *)arena[a_phi].as<T>(), ca, bmax.as<int>(), occ.as<unsigned>(), occ_words);
         gg::PlanArgs pa;
         for (int a = 0; a < 3; ++a) pa.n[a] = np[a];
         pa.P = P;
@@ -919,47 +1170,29 @@ template <typename T> struct Sim final : SimBase {
         pa.G = G;
         const int tb = 256, gb = (G + tb - 1) / tb;
         hipLaunchKernelGGL(gg::k_plan, dim3(gb), dim3(tb), 0, stream, Lv, boxes_of(Ln), bmin.as<int>(),
-                           bmax.as<int>(), occ.as<unsigned>(), sizes.as<long long>(), pa);
-        hipLaunchKernelGGL(gg::k_scan, dim3(1), dim3(1024), 0, stream, sizes.as<long long>(), off[Ln].as<long long>(), G);
+                           bmax.as<int>(), occ.as<unsigned>(), sizes.as<long long>(), pa, (const Ctl *)nullptr);
+        hipLaunchKernelGGL(gg::k_scan, dim3(1), dim3(1024), 0, stream, (const long long *)sizes.as<long long>(),
+                           off[Ln].as<long long>(), G, (Ctl *)nullptr, 0LL);
         tend();
         HIPCHECK(hipGetLastError());
         // the new grid
         set_grid(np);
         voxel_m *= r;
-        items_R[0] = items_R[1] = -1;
         have_keep = false;
-        set_identity_taps();
-        layout_meta_count(Ln, true);
-        const long long need = tot[Ln].arena;
-        const int a_f = pick(bit(a_state), need);
+        read_totals(Ln);
+        ensure_arenas(tot[Ln].arena, 1u << a_phi);
+        const int a_src = A_PSI;  // psi is stale from here on
         tbegin(GG_K_PLAN, 0);
         hipLaunchKernelGGL(gg::k_coarsen_values<T>, dim3(G, split), dim3(gg::kBlock), 0, stream, boxes_of(L),
-                           (const T *)arena[a_state].as<T>(), boxes_of(Ln), arena[a_f].as<T>(), ca);
+                           (const T *)arena[a_phi].as<T>(), boxes_of(Ln), arena[a_src].as<T>(), ca);
         tend();
         HIPCHECK(hipGetLastError());
-        HIPCHECK(hipStreamSynchronize(stream));  // the old phi is dead only now
-        for (int a = 0; a < 4; ++a)
-            if (a != a_f) ensure_arena(a, need);
-        layout_meta_fill(Ln, true);
-        int others[3], m = 0;
-        for (int a = 0; a < 4; ++a)
-            if (a != a_f) others[m++] = a;
-        launch_reinit(Ln, Ln, arena[a_f].as<T>(), arena[others[0]].as<T>(), arena[others[1]].as<T>(),
-                      arena[others[2]].as<T>(), nullptr, nullptr, false);
+        HIPCHECK(hipStreamSynchronize(stream));
         cur = Ln;
-        a_state = others[1];
-        a_T = a_psi = -1;
-        T_R = psi_R = -1;
-        if (physics) {
-            ensure_iota(0, need);
-            ensure_iota(1, need);
-            iota_cur = 0;
-            hipLaunchKernelGGL(gg::k_compare<T>, dim3(grid_of(gg::xcd_grid(ntiles))), dim3(gg::kBlock), 0, stream,
-                               boxes_of(Ln), cov_off.as<int>(), cov_list.as<int>(), arena[a_state].as<T>(),
-                               (T *)nullptr, iota_a[0].as<int>(), bmin.as<int>(), bmax.as<int>(),
-                               occ.as<unsigned>(), tile_args(), W, 1);
-            HIPCHECK(hipGetLastError());
-        }
+        build_coverage(Ln);
+        reinit_in_place(Ln, a_src);
+        alive_n = (int)tot[Ln].alive;
+        if (physics) initial_iota();
         HIPCHECK(hipStreamSynchronize(stream));
         resolve_spans();
         vlo.release();
@@ -968,7 +1201,7 @@ template <typename T> struct Sim final : SimBase {
 
     // Interface areas of the current phi (FP64 per-grain sums, fixed order).
     void areas(double *area, double *weighted) override {
-        if (a_state < 0) throw ArgError{"no materialised state"};
+        ensure_phi();
         const int split = 8;
         DBuf part, sums;
         part.ensure(sizeof(double) * 2 * (size_t)G * split);
@@ -979,7 +1212,7 @@ template <typename T> struct Sim final : SimBase {
         aa.split = split;
         aa.G = G;
         hipLaunchKernelGGL(gg::k_areas<T>, dim3(G, split), dim3(gg::kBlock), 0, stream, boxes_of(cur),
-                           (const T *)arena[a_state].as<T>(), iota_now(), (const T *)quat_d.as<T>(), aa,
+                           (const T *)arena[a_phi].as<T>(), iota_of(iota_cur), (const T *)quat_d.as<T>(), aa,
                            part.as<double>(), W, grid_args());
         hipLaunchKernelGGL(gg::k_sum_rows, dim3((2 * G + 255) / 256), dim3(256), 0, stream, part.as<double>(),
                            sums.as<double>(), 2 * G, split);
@@ -994,6 +1227,7 @@ template <typename T> struct Sim final : SimBase {
     // One grain's box and values (as doubles); returns the value count, or
     // -count when cap is too small (nothing written), 0 for an extinct grain.
     long long grain_sdf(int k, int32_t *lo_o, int32_t *ext_o, double *out, long long cap) override {
+        ensure_phi();
         int l[3], e[3], al = 0;
         long long o = 0;
         HIPCHECK(hipMemcpyAsync(l, lo[cur].as<int>() + 3 * k, sizeof(int) * 3, hipMemcpyDeviceToHost, stream));
@@ -1011,10 +1245,9 @@ template <typename T> struct Sim final : SimBase {
         }
         const long long m = (long long)e[0] * e[1] * e[2];
         if (cap < m || !out) return -m;
-        if (a_state < 0) throw ArgError{"no materialised state"};
         DBuf tmp;
         tmp.ensure(sizeof(double) * m);
-        hipLaunchKernelGGL((gg::k_convert<T, double>), dim3(256), dim3(256), 0, stream, arena[a_state].as<T>() + o,
+        hipLaunchKernelGGL((gg::k_convert<T, double>), dim3(256), dim3(256), 0, stream, arena[a_phi].as<T>() + o,
                            tmp.as<double>(), m);
         HIPCHECK(hipGetLastError());
         HIPCHECK(hipMemcpyAsync(out, tmp.p, sizeof(double) * m, hipMemcpyDeviceToHost, stream));
@@ -1040,7 +1273,7 @@ template <typename T> struct Sim final : SimBase {
     }
 
     void save(FILE *f) override {
-        if (a_state < 0) throw ArgError{"no materialised state"};
+        ensure_phi();
         HIPCHECK(hipStreamSynchronize(stream));
         const long long m = tot[cur].arena;
         CkptHeader h{};
@@ -1066,11 +1299,11 @@ template <typename T> struct Sim final : SimBase {
         HIPCHECK(hipMemcpyAsync(l.data(), lo[cur].p, sizeof(int) * 3 * G, hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipMemcpyAsync(e.data(), ext[cur].p, sizeof(int) * 3 * G, hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipMemcpyAsync(al.data(), alive[cur].p, sizeof(int) * G, hipMemcpyDeviceToHost, stream));
-        HIPCHECK(hipMemcpyAsync(v.data(), arena[a_state].p, sizeof(T) * m, hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipMemcpyAsync(v.data(), arena[a_phi].p, sizeof(T) * m, hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipMemcpyAsync(vo.data(), vol.p, sizeof(double) * G, hipMemcpyDeviceToHost, stream));
         if (h.has_iota) {
             io.resize(std::max<long long>(m, 1));
-            HIPCHECK(hipMemcpyAsync(io.data(), iota_now(), sizeof(int) * m, hipMemcpyDeviceToHost, stream));
+            HIPCHECK(hipMemcpyAsync(io.data(), iota_of(iota_cur), sizeof(int) * m, hipMemcpyDeviceToHost, stream));
         }
         HIPCHECK(hipStreamSynchronize(stream));
         put(f, &h, sizeof(h));
@@ -1083,6 +1316,7 @@ template <typename T> struct Sim final : SimBase {
     }
 
     void load(FILE *f) override {
+        settle();
         CkptHeader h;
         get(f, &h, sizeof(h));
         if (std::memcmp(h.magic, kMagic, 8) != 0 || h.version != 1) throw ArgError{"not a checkpoint of this library"};
@@ -1090,13 +1324,14 @@ template <typename T> struct Sim final : SimBase {
             h.physics != physics || h.redistance != redist)
             throw ArgError{"checkpoint of a different configuration (dim, grains, precision, band, physics, "
                            "re-initialization)"};
-        long long nt = 1;
+        long long ntot = 1;
         for (int a = 0; a < 3; ++a) {
             const bool active = a < dim;
-            if (active ? (h.n[a] < 4 * P + 2 || h.n[a] > 4096) : h.n[a] != 1) throw ArgError{"checkpoint grid out of range"};
-            nt *= h.n[a];
+            if (active ? (h.n[a] < 4 * P + 2 || h.n[a] > 4096) : h.n[a] != 1)
+                throw ArgError{"checkpoint grid out of range"};
+            ntot *= h.n[a];
         }
-        if (nt > 2147483647LL || h.values < 0 || h.has_iota != (physics ? 1 : 0)) throw ArgError{"corrupt checkpoint"};
+        if (ntot > 2147483647LL || h.values < 0 || h.has_iota != (physics ? 1 : 0)) throw ArgError{"corrupt checkpoint"};
         std::vector<int> l(3 * G), e(3 * G), al(G);
         get(f, l.data(), sizeof(int) * 3 * G);
         get(f, e.data(), sizeof(int) * 3 * G);
@@ -1139,38 +1374,56 @@ template <typename T> struct Sim final : SimBase {
         have_keep = false;
     }
 
-    // Try the candidate (budget, small-class limit) pairs for `per` steps each
-    // (the simulation advances), keep the one with the least device time per
-    // grain voxel.  Tile shapes follow the budgets; the functions do not.
-    void autotune(double dt, int per, int32_t *best_lds, int32_t *best_small) override {
-        static const int cand[][2] = {{40960, 26624}, {32768, 20480}, {40960, 20480}, {40960, 32768},
-                                      {49152, 26624}, {49152, 32768}, {32768, 26624}};
+    // Try the candidate schedules for `per` steps each (the simulation
+    // advances), keep the one with the least device time per grain voxel.
+    void autotune(double dt, int per, Tuning *out) override {
+        settle();
+        std::vector<std::array<int, 3>> cand;
+        if (redist == GG_REDIST_EUCLID) {
+            static const int b[][2] = {{40960, 26624}, {32768, 20480}, {40960, 20480}, {49152, 26624}, {49152, 32768}};
+            for (const auto &c : b) cand.push_back({order_size, c[0], c[1]});
+        } else {
+            cand.push_back({0, lds_bytes, small_bytes});
+            cand.push_back({1, lds_bytes, small_bytes});
+        }
         double best = 1e300;
-        int bl = lds_bytes, bs = small_bytes;
-        for (const auto &c : cand) {
-            lds_bytes = c[0];
-            small_bytes = c[1];
-            items_R[0] = items_R[1] = -1;  // re-tile the current layout (its predicted values stand)
+        std::array<int, 3> pick = cand[0];
+        Tuning t{};
+        t.candidates = (int)cand.size();
+        for (size_t i = 0; i < cand.size(); ++i) {
+            order_size = cand[i][0];
+            lds_bytes = cand[i][1];
+            small_bytes = cand[i][2];
+            ++epoch;
             const long long gv0 = total_gv;
             step(dt, per);
-            const double per_gv = last_ms * per / (double)std::max<long long>(total_gv - gv0, 1);
+            settle();
+            const double per_gv = 1e6 * last_ms * per / (double)std::max<long long>(total_gv - gv0, 1);
+            t.ns_per_gv[i] = per_gv;
+            t.cand_order[i] = cand[i][0];
+            t.cand_lds[i] = cand[i][1];
+            t.cand_small[i] = cand[i][2];
             if (per_gv < best) {
                 best = per_gv;
-                bl = c[0];
-                bs = c[1];
+                pick = cand[i];
             }
         }
-        lds_bytes = bl;
-        small_bytes = bs;
-        items_R[0] = items_R[1] = -1;
-        *best_lds = bl;
-        *best_small = bs;
+        order_size = pick[0];
+        lds_bytes = pick[1];
+        small_bytes = pick[2];
+        ++epoch;
+        t.order_size = order_size;
+        t.lds_bytes = lds_bytes;
+        t.small_bytes = small_bytes;
+        *out = t;
     }
 
     void keep_copy(int L, const T *psi, const T *phic) {
-        const long long m = tot[L].arena;
-        keep_psi.ensure(sizeof(T) * std::max<long long>(m, 1));
-        keep_phic.ensure(sizeof(T) * std::max<long long>(m, 1));
+        long long m = 0;  // the step's layout size (the host mirror is per call)
+        HIPCHECK(hipMemcpyAsync(&m, off[L].as<long long>() + G, sizeof(long long), hipMemcpyDeviceToHost, stream));
+        HIPCHECK(hipStreamSynchronize(stream));
+        keep_psi.ensure(sizeof(T) * (size_t)std::max<long long>(cap_arena, 1));
+        keep_phic.ensure(sizeof(T) * (size_t)std::max<long long>(cap_arena, 1));
         keep_lo.ensure(sizeof(int) * 3 * G);
         keep_ext.ensure(sizeof(int) * 3 * G);
         keep_alive.ensure(sizeof(int) * G);
@@ -1182,16 +1435,18 @@ template <typename T> struct Sim final : SimBase {
         HIPCHECK(hipMemcpyAsync(keep_alive.p, alive[L].p, sizeof(int) * G, hipMemcpyDeviceToDevice, stream));
         HIPCHECK(hipMemcpyAsync(keep_off.p, off[L].p, sizeof(long long) * (G + 1), hipMemcpyDeviceToDevice, stream));
         keep_tot = tot[L];
-        have_keep = true;
+        keep_tot.arena = m;
     }
 
     // ---------------------------------------------------------------- queries
     void volumes(double *out) override {
+        settle();
         HIPCHECK(hipMemcpyAsync(out, vol.p, sizeof(double) * G, hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipStreamSynchronize(stream));
     }
 
     void labels(int32_t *out, bool device) override {
+        ensure_phi();
         const long long nt3 = (long long)n[0] * n[1] * n[2];
         DBuf tmp;
         int32_t *dst = out;
@@ -1199,8 +1454,9 @@ template <typename T> struct Sim final : SimBase {
             tmp.ensure(sizeof(int32_t) * nt3);
             dst = tmp.as<int32_t>();
         }
-        hipLaunchKernelGGL(gg::k_labels<T>, dim3(ntiles), dim3(gg::kBlock), 0, stream, boxes_of(cur), cov_off.as<int>(),
-                           cov_list.as<int>(), arena[a_state].as<T>(), dst, tile_args());
+        hipLaunchKernelGGL(gg::k_labels<T>, dim3(ntiles), dim3(gg::kBlock), 0, stream, boxes_of(cur),
+                           (const int *)cov_off.as<int>(), (const int *)cov_list.as<int>(),
+                           (const T *)arena[a_phi].as<T>(), dst, tile_args());
         HIPCHECK(hipGetLastError());
         if (!device) {
             HIPCHECK(hipMemcpyAsync(out, dst, sizeof(int32_t) * nt3, hipMemcpyDeviceToHost, stream));
@@ -1209,6 +1465,7 @@ template <typename T> struct Sim final : SimBase {
     }
 
     void boxes(int32_t *hlo, int32_t *hext, int32_t *hal, int64_t *hoff, bool prev) override {
+        settle();
         std::vector<int> a(G);
         std::vector<long long> o(G + 1);
         const void *plo = prev ? keep_lo.p : lo[cur].p, *pext = prev ? keep_ext.p : ext[cur].p;
@@ -1224,15 +1481,15 @@ template <typename T> struct Sim final : SimBase {
         }
     }
 
-    long long arena_total(bool prev) const override { return prev ? keep_tot.arena : tot[cur].arena; }
-
     long long values(double *out, long long cap, int which) override {
         const T *src;
         long long m;
         if (which < 0) {
-            src = arena[a_state].as<T>();
+            ensure_phi();
+            src = arena[a_phi].as<T>();
             m = tot[cur].arena;
         } else {
+            settle();
             if (!have_keep) throw ArgError{"no intermediates kept"};
             src = which == 0 ? keep_psi.as<T>() : keep_phic.as<T>();
             m = keep_tot.arena;
@@ -1250,6 +1507,7 @@ template <typename T> struct Sim final : SimBase {
     }
 
     long long iota(int32_t *out, long long cap) override {
+        settle();
         const long long m = tot[cur].arena;
         if (cap < m) return -m;
         if (!physics) {
@@ -1263,6 +1521,7 @@ template <typename T> struct Sim final : SimBase {
 
     void load_state(const int32_t *hlo, const int32_t *hext, const uint8_t *hal, const double *vals,
                     const int32_t *hiota) override {
+        settle();
         load_state_core(hlo, hext, hal, vals, hiota);
     }
 
@@ -1274,8 +1533,10 @@ template <typename T> struct Sim final : SimBase {
         std::vector<int> l(3 * G), e(3 * G), a(G);
         std::vector<long long> o(G + 1, 0);
         std::vector<double> vh(G, 0.0);
+        int nalive = 0;
         for (int k = 0; k < G; ++k) {
             a[k] = hal[k] ? 1 : 0;
+            nalive += a[k];
             for (int q = 0; q < 3; ++q) {
                 l[3 * k + q] = a[k] ? hlo[3 * k + q] : 0;
                 e[3 * k + q] = a[k] ? hext[3 * k + q] : 0;
@@ -1305,10 +1566,9 @@ template <typename T> struct Sim final : SimBase {
         HIPCHECK(hipStreamSynchronize(stream));
         cur = 0;
         upload_table(0, l.data(), e.data(), a.data(), o.data());
-        for (int q = 0; q < 4; ++q) ensure_arena(q, m);
-        a_state = 0;
-        a_T = a_psi = -1;
-        T_R = psi_R = -1;
+        tot[0].arena = m;
+        alive_n = nalive;
+        ensure_arenas(m, 0u);
         std::vector<T> tv;
         const T *up;
         if constexpr (std::is_same<V, T>::value) {
@@ -1318,38 +1578,38 @@ template <typename T> struct Sim final : SimBase {
             for (long long i = 0; i < m; ++i) tv[i] = (T)vals[i];
             up = tv.data();
         }
-        HIPCHECK(hipMemcpyAsync(arena[0].p, up, sizeof(T) * m, hipMemcpyHostToDevice, stream));
+        HIPCHECK(hipMemcpyAsync(arena[A_F].p, up, sizeof(T) * m, hipMemcpyHostToDevice, stream));
         HIPCHECK(hipMemcpyAsync(vol.p, vh.data(), sizeof(double) * G, hipMemcpyHostToDevice, stream));
+        a_phi = A_F;
+        f_chain = 0;
+        psi_ok = false;
+        have_keep = false;
+        iota_cur = 0;
         if (physics) {
-            ensure_iota(0, m);
-            ensure_iota(1, m);
-            iota_cur = 0;
             std::vector<int> io(std::max<long long>(m, 1), -1);
             if (hiota)
                 for (long long i = 0; i < m; ++i) io[i] = hiota[i];
             HIPCHECK(hipMemcpyAsync(iota_a[0].p, io.data(), sizeof(int) * m, hipMemcpyHostToDevice, stream));
         }
         HIPCHECK(hipStreamSynchronize(stream));
-        items_R[0] = items_R[1] = -1;
-        const int keepR = R;
-        R = R > 0 ? R : 1;
-        layout_meta_count(0, true);
-        layout_meta_fill(0, true);
-        R = keepR;
-        if (R <= 0) items_R[0] = -1;
+        build_coverage(0);
         HIPCHECK(hipStreamSynchronize(stream));
     }
 
-    int alive_count() const override { return (int)tot[cur].alive; }
+    int alive_count() override {
+        settle();
+        return alive_n;
+    }
 
-    gg_step_stats stats() const override {
+    gg_step_stats stats() override {
+        settle();
         gg_step_stats s;
         s.steps = steps_done;
         s.total_grain_voxels = total_gv;
-        s.alive = (int)tot[cur].alive;
+        s.alive = alive_n;
         s.kernel_radius = R;
         s.grain_voxels = last_gv;
-        s.capacity = (int64_t)(arena[a_state >= 0 ? a_state : 0].cap / sizeof(T));
+        s.capacity = cap_arena;
         s.superposition = (double)last_gv / ((double)n[0] * n[1] * n[2]);
         s.last_step_ms = last_ms;
         for (int a = 0; a < 3; ++a) s.n[a] = n[a];
@@ -1422,11 +1682,18 @@ template <typename F> gg_status guarded(gg_sim *s, F &&f) {
     }
 }
 
+// Calls that wait for queued steps report their failures as state-changing
+// failures: memory or capacity errors poison the simulation.
+gg_status settled(gg_sim *sim, gg_status st) {
+    if (st == GG_E_NOMEM || st == GG_E_CAPACITY) sim->poisoned = true;
+    return st;
+}
+
 }  // namespace
 
 extern "C" {
 
-const char *gg_version(void) { return "gg-mi355x 0.1 (gfx950)"; }
+const char *gg_version(void) { return "gg-mi355x 0.2 (gfx950)"; }
 
 const char *gg_status_str(gg_status st) {
     switch (st) {
@@ -1468,6 +1735,8 @@ gg_status gg_create(const gg_config *cfg, const int32_t *labels, int32_t n_grain
     if (cfg->physics < 0 || cfg->physics > 3) return fail(nullptr, GG_E_ARG, "unknown physics bits");
     if (cfg->redistance != GG_REDIST_TAXICAB && cfg->redistance != GG_REDIST_EUCLID)
         return fail(nullptr, GG_E_ARG, "redistance must be GG_REDIST_TAXICAB or GG_REDIST_EUCLID");
+    if (cfg->batched != 0 && cfg->batched != 1) return fail(nullptr, GG_E_ARG, "batched must be 0 or 1");
+    if (cfg->flags & ~(uint32_t)GG_FLAG_ORDER_SIZE) return fail(nullptr, GG_E_ARG, "unknown flag bits");
     if ((cfg->physics & GG_PHYS_MISORIENTATION) && (!quat || !(cfg->theta_c_deg > 0.0)))
         return fail(nullptr, GG_E_ARG, "misorientation weights need quat and theta_c_deg > 0");
     if ((cfg->physics & GG_PHYS_BULK) && (!energy_density || !(cfg->voxel_m > 0.0) || !(cfg->gamma_max > 0.0)))
@@ -1536,162 +1805,166 @@ gg_status gg_create(const gg_config *cfg, const int32_t *labels, int32_t n_grain
     return GG_OK;
 }
 
-// The calls that advance or replace the state check their arguments before they
-// change anything (GG_E_ARG).  A later failure (memory, capacity) can leave the
-// state part way replaced: it poisons the simulation, as a HIP error does.
-static gg_status state_changed(gg_sim *sim, gg_status st) {
-    if (st == GG_E_NOMEM || st == GG_E_CAPACITY) sim->poisoned = true;
-    return st;
-}
-
 gg_status gg_step(gg_sim *sim, double dt, int32_t n_steps) {
     if (!sim) return GG_E_ARG;
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(sim, GG_E_ARG, "dt must be finite and positive");
     if (n_steps < 0) return fail(sim, GG_E_ARG, "n_steps must be >= 0");
-    return state_changed(sim, guarded(sim, [&]() {
-                             sim->impl->step(dt, n_steps);
-                             return GG_OK;
-                         }));
+    return settled(sim, guarded(sim, [&]() {
+                       sim->impl->step(dt, n_steps);
+                       return GG_OK;
+                   }));
 }
 
 gg_status gg_sync(gg_sim *sim) {
-    return guarded(sim, [&]() {
-        sim->impl->sync();
-        return GG_OK;
-    });
+    return settled(sim, guarded(sim, [&]() {
+                       sim->impl->sync();
+                       return GG_OK;
+                   }));
 }
 
 gg_status gg_grain_count(gg_sim *sim, int32_t *alive) {
     if (!alive) return fail(sim, GG_E_ARG, "alive is NULL");
-    return guarded(sim, [&]() {
-        *alive = sim->impl->alive_count();
-        return GG_OK;
-    });
+    return settled(sim, guarded(sim, [&]() {
+                       *alive = sim->impl->alive_count();
+                       return GG_OK;
+                   }));
 }
 
 gg_status gg_grain_volumes(gg_sim *sim, double *out, int64_t cap) {
     if (!sim || !out) return fail(sim, GG_E_ARG, "NULL argument");
     if (cap < sim->G) return fail(sim, GG_E_SMALLBUF, "cap < n_grains");
-    return guarded(sim, [&]() {
-        sim->impl->volumes(out);
-        return GG_OK;
-    });
+    return settled(sim, guarded(sim, [&]() {
+                       sim->impl->volumes(out);
+                       return GG_OK;
+                   }));
 }
 
 gg_status gg_labels(gg_sim *sim, int32_t *out, int64_t cap, int32_t out_is_device) {
     if (!sim || !out) return fail(sim, GG_E_ARG, "NULL argument");
     if (cap < (int64_t)sim->n[0] * sim->n[1] * sim->n[2]) return fail(sim, GG_E_SMALLBUF, "cap < prod(n)");
-    return guarded(sim, [&]() {
-        sim->impl->labels(out, out_is_device != 0);
-        return GG_OK;
-    });
+    return settled(sim, guarded(sim, [&]() {
+                       sim->impl->labels(out, out_is_device != 0);
+                       return GG_OK;
+                   }));
 }
 
 gg_status gg_stats(gg_sim *sim, gg_step_stats *out) {
     if (!sim || !out) return fail(sim, GG_E_ARG, "NULL argument");
-    return guarded(sim, [&]() {
-        *out = sim->impl->stats();
-        return GG_OK;
-    });
+    return settled(sim, guarded(sim, [&]() {
+                       *out = sim->impl->stats();
+                       return GG_OK;
+                   }));
 }
 
 gg_status gg_get_boxes(gg_sim *sim, int32_t *lo, int32_t *ext, int32_t *alive, int64_t *offset, int64_t cap) {
     if (!sim) return GG_E_ARG;
     if (cap < sim->G) return fail(sim, GG_E_SMALLBUF, "cap < n_grains");
-    return guarded(sim, [&]() {
-        sim->impl->boxes(lo, ext, alive, offset, false);
-        return GG_OK;
-    });
+    return settled(sim, guarded(sim, [&]() {
+                       sim->impl->boxes(lo, ext, alive, offset, false);
+                       return GG_OK;
+                   }));
 }
 
 gg_status gg_get_values(gg_sim *sim, double *out, int64_t cap) {
     if (!sim || !out) return fail(sim, GG_E_ARG, "NULL argument");
-    return guarded(sim, [&]() {
-        long long m = sim->impl->values(out, cap, -1);
-        if (m < 0) return fail(sim, GG_E_SMALLBUF, "cap < sum of box volumes (" + std::to_string(-m) + ")");
-        return GG_OK;
-    });
+    return settled(sim, guarded(sim, [&]() {
+                       long long m = sim->impl->values(out, cap, -1);
+                       if (m < 0)
+                           return fail(sim, GG_E_SMALLBUF, "cap < sum of box volumes (" + std::to_string(-m) + ")");
+                       return GG_OK;
+                   }));
 }
 
 gg_status gg_get_iota(gg_sim *sim, int32_t *out, int64_t cap) {
     if (!sim || !out) return fail(sim, GG_E_ARG, "NULL argument");
-    return guarded(sim, [&]() {
-        long long m = sim->impl->iota(out, cap);
-        if (m < 0) return fail(sim, GG_E_SMALLBUF, "cap < sum of box volumes");
-        return GG_OK;
-    });
+    return settled(sim, guarded(sim, [&]() {
+                       long long m = sim->impl->iota(out, cap);
+                       if (m < 0) return fail(sim, GG_E_SMALLBUF, "cap < sum of box volumes");
+                       return GG_OK;
+                   }));
 }
 
 gg_status gg_load_state(gg_sim *sim, const int32_t *lo, const int32_t *ext, const uint8_t *alive,
                         const double *values, const int32_t *iota) {
     if (!sim || !lo || !ext || !alive || !values) return fail(sim, GG_E_ARG, "NULL argument");
-    return state_changed(sim, guarded(sim, [&]() {
-                             sim->impl->load_state(lo, ext, alive, values, iota);
-                             return GG_OK;
-                         }));
+    return settled(sim, guarded(sim, [&]() {
+                       sim->impl->load_state(lo, ext, alive, values, iota);
+                       return GG_OK;
+                   }));
 }
 
 gg_status gg_grain_areas(gg_sim *sim, double *area, double *weighted, int64_t cap) {
     if (!sim || !area) return fail(sim, GG_E_ARG, "NULL argument");
     if (cap < sim->G) return fail(sim, GG_E_SMALLBUF, "cap < n_grains");
-    return guarded(sim, [&]() {
-        sim->impl->areas(area, weighted);
-        return GG_OK;
-    });
+    return settled(sim, guarded(sim, [&]() {
+                       sim->impl->areas(area, weighted);
+                       return GG_OK;
+                   }));
 }
 
 gg_status gg_grain_sdf(gg_sim *sim, int32_t id, int32_t lo[3], int32_t ext[3], double *out, int64_t cap) {
     if (!sim || !lo || !ext) return fail(sim, GG_E_ARG, "NULL argument");
     if (id < 0 || id >= sim->G) return fail(sim, GG_E_ARG, "grain id out of range");
-    return guarded(sim, [&]() {
-        const long long m = sim->impl->grain_sdf(id, lo, ext, out, cap);
-        if (m < 0 && out) return fail(sim, GG_E_SMALLBUF, "cap too small (" + std::to_string(-m) + ")");
-        return GG_OK;
-    });
+    return settled(sim, guarded(sim, [&]() {
+                       const long long m = sim->impl->grain_sdf(id, lo, ext, out, cap);
+                       if (m < 0 && out) return fail(sim, GG_E_SMALLBUF, "cap too small (" + std::to_string(-m) + ")");
+                       return GG_OK;
+                   }));
 }
 
-gg_status gg_autotune(gg_sim *sim, double dt, int32_t steps_per_candidate, int32_t *lds_bytes,
-                      int32_t *small_bytes) {
-    if (!sim || !lds_bytes || !small_bytes) return fail(sim, GG_E_ARG, "NULL argument");
+gg_status gg_autotune(gg_sim *sim, double dt, int32_t steps_per_candidate, gg_tuning *out) {
+    if (!sim || !out) return fail(sim, GG_E_ARG, "NULL argument");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(sim, GG_E_ARG, "dt must be finite and positive");
     if (steps_per_candidate < 1) return fail(sim, GG_E_ARG, "steps_per_candidate must be >= 1");
-    return state_changed(sim, guarded(sim, [&]() {
-                             sim->impl->autotune(dt, steps_per_candidate, lds_bytes, small_bytes);
-                             return GG_OK;
-                         }));
+    return settled(sim, guarded(sim, [&]() {
+                       Tuning t{};
+                       sim->impl->autotune(dt, steps_per_candidate, &t);
+                       std::memset(out, 0, sizeof(*out));
+                       out->order_size = t.order_size;
+                       out->lds_bytes = t.lds_bytes;
+                       out->small_bytes = t.small_bytes;
+                       out->candidates = t.candidates;
+                       for (int i = 0; i < 8; ++i) {
+                           out->ns_per_gv[i] = t.ns_per_gv[i];
+                           out->cand_order[i] = t.cand_order[i];
+                           out->cand_lds[i] = t.cand_lds[i];
+                           out->cand_small[i] = t.cand_small[i];
+                       }
+                       return GG_OK;
+                   }));
 }
 
 gg_status gg_save(gg_sim *sim, const char *path) {
     if (!sim || !path) return fail(sim, GG_E_ARG, "NULL argument");
-    return guarded(sim, [&]() {
-        FILE *f = std::fopen(path, "wb");
-        if (!f) return fail(sim, GG_E_ARG, std::string("cannot open ") + path + " for writing");
-        try {
-            sim->impl->save(f);
-        } catch (...) {
-            std::fclose(f);
-            throw;
-        }
-        if (std::fclose(f) != 0) return fail(sim, GG_E_ARG, std::string("write to ") + path + " failed");
-        return GG_OK;
-    });
+    return settled(sim, guarded(sim, [&]() {
+                       FILE *f = std::fopen(path, "wb");
+                       if (!f) return fail(sim, GG_E_ARG, std::string("cannot open ") + path + " for writing");
+                       try {
+                           sim->impl->save(f);
+                       } catch (...) {
+                           std::fclose(f);
+                           throw;
+                       }
+                       if (std::fclose(f) != 0) return fail(sim, GG_E_ARG, std::string("write to ") + path + " failed");
+                       return GG_OK;
+                   }));
 }
 
 gg_status gg_load(gg_sim *sim, const char *path) {
     if (!sim || !path) return fail(sim, GG_E_ARG, "NULL argument");
-    return state_changed(sim, guarded(sim, [&]() {
-                             FILE *f = std::fopen(path, "rb");
-                             if (!f) return fail(sim, GG_E_ARG, std::string("cannot open ") + path);
-                             try {
-                                 sim->impl->load(f);
-                             } catch (...) {
-                                 std::fclose(f);
-                                 throw;
-                             }
-                             std::fclose(f);
-                             sim->impl->grid(sim->n);
-                             return GG_OK;
-                         }));
+    return settled(sim, guarded(sim, [&]() {
+                       FILE *f = std::fopen(path, "rb");
+                       if (!f) return fail(sim, GG_E_ARG, std::string("cannot open ") + path);
+                       try {
+                           sim->impl->load(f);
+                       } catch (...) {
+                           std::fclose(f);
+                           throw;
+                       }
+                       std::fclose(f);
+                       sim->impl->grid(sim->n);
+                       return GG_OK;
+                   }));
 }
 
 gg_status gg_coarsen(gg_sim *sim, const int32_t n_new[3]) {
@@ -1710,41 +1983,41 @@ gg_status gg_coarsen(gg_sim *sim, const int32_t n_new[3]) {
     });
     if (st == GG_OK)
         for (int a = 0; a < 3; ++a) sim->n[a] = n_new[a];
-    return state_changed(sim, st);
+    return settled(sim, st);
 }
 
 gg_status gg_keep_intermediates(gg_sim *sim, int32_t on) {
-    return guarded(sim, [&]() {
-        sim->impl->keep = on != 0;
-        return GG_OK;
-    });
+    return settled(sim, guarded(sim, [&]() {
+                       sim->impl->set_keep(on != 0);
+                       return GG_OK;
+                   }));
 }
 
 gg_status gg_get_intermediate(gg_sim *sim, int32_t which, double *out, int64_t cap, int32_t *lo, int32_t *ext,
                               int32_t *alive, int64_t *offset, int64_t cap_grains) {
     if (!sim || !out || (which != 0 && which != 1)) return fail(sim, GG_E_ARG, "bad argument");
     if ((lo || ext || alive || offset) && cap_grains < sim->G) return fail(sim, GG_E_SMALLBUF, "cap_grains < n_grains");
-    return guarded(sim, [&]() {
-        long long m = sim->impl->values(out, cap, which);
-        if (m < 0) return fail(sim, GG_E_SMALLBUF, "cap too small (" + std::to_string(-m) + ")");
-        if (lo || ext || alive || offset) sim->impl->boxes(lo, ext, alive, offset, true);
-        return GG_OK;
-    });
+    return settled(sim, guarded(sim, [&]() {
+                       long long m = sim->impl->values(out, cap, which);
+                       if (m < 0) return fail(sim, GG_E_SMALLBUF, "cap too small (" + std::to_string(-m) + ")");
+                       if (lo || ext || alive || offset) sim->impl->boxes(lo, ext, alive, offset, true);
+                       return GG_OK;
+                   }));
 }
 
 gg_status gg_profile(gg_sim *sim, int32_t on) {
-    return guarded(sim, [&]() {
-        sim->impl->profile(on != 0);
-        return GG_OK;
-    });
+    return settled(sim, guarded(sim, [&]() {
+                       sim->impl->profile(on != 0);
+                       return GG_OK;
+                   }));
 }
 
 gg_status gg_get_kernel_times(gg_sim *sim, gg_kernel_times *out) {
     if (!sim || !out) return fail(sim, GG_E_ARG, "NULL argument");
-    return guarded(sim, [&]() {
-        *out = sim->impl->kernel_times();
-        return GG_OK;
-    });
+    return settled(sim, guarded(sim, [&]() {
+                       *out = sim->impl->kernel_times();
+                       return GG_OK;
+                   }));
 }
 
 void gg_destroy(gg_sim *sim) {

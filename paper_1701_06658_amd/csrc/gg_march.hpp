@@ -1,0 +1,723 @@
+// Z-marching kernels of the level-set step for gfx950 (MI355X): one work group
+// per grain box walks through the box plane by plane, so every value of the box
+// is read once from HBM and written once, in contiguous plane-sized chunks.
+//
+//   k_reinit_march   phi^c (old box) -> f    reference values next to the sign
+//                    change, taxicab spreading along x and y inside the plane,
+//                    forward spreading along z (ascending march); 2D: the final
+//                    function and the grain volume
+//   k_predict_march  f -> psi (+ phi)        backward spreading along z, band
+//                    clamp, grain volume (3D), then the separable Gaussian: the
+//                    z pass from a register window of 2R + 1 planes, the x and y
+//                    passes inside the plane (descending march); the optional
+//                    predictor-correction epilogue
+//
+// Together with the corrector these are the three sweeps of a step.  The
+// spreading (sec. 2.1.6) is the running minimum c <- min(v, c + 1) along each
+// line: forward and backward chains inside a window of +-K cells give the same
+// value as sweeps over the whole line wherever the distance is below the band
+// (a source farther than K cells is more than K away), and the band clamp makes
+// every larger value W; along z the chains run over the whole column, forward in
+// the first kernel, backward in the second, in the order of the sequential
+// sweeps.
+//
+// Threads of a group own column units: one x position and YB consecutive rows
+// of a plane tile, whose values of successive planes stay in registers.  In-plane
+// passes go through LDS.  A box cross-section larger than the group is cut into
+// tiles with halos (the stencil reach) on every side inside the box; a box axis
+// that spans the whole periodic grid wraps its halos around.
+#pragma once
+
+#include "gg_kernels.hpp"
+
+namespace gg {
+
+constexpr int kMT = 512;  // threads per march group
+constexpr int kQX = 4;    // outputs per thread of an in-plane x pass
+
+// LDS cells of one plane buffer for column units of YB rows.
+template <int YB> constexpr int march_buf() { return kMT * YB + 256; }
+
+struct MarchArgs {
+    int n[3];
+    int dim;
+    int G;
+    int K;              // taxicab spreading reach P (k_reinit_march)
+    int R;              // Gaussian radius (k_predict_march)
+    const int *order;   // grain processed by each block (NULL: block index)
+    const Ctl *ctl;     // NULL outside the step sequence
+};
+
+// Tiling of a box cross-section (x, y) for a march group.
+struct MSplit {
+    int e[2], nt[2], w[2], h;
+    bool ring[2];
+};
+
+// The fewest tiles whose extended tile (interior plus a halo of h cells on each
+// side that lies inside the box, or wraps around a whole periodic axis) has
+// EX * ceil(EY / YB) <= kMT column units and (EX | 1) * EY <= buf cells.
+template <int YB> __device__ inline MSplit march_split(int e0, int e1, int N0, int N1, int h, int buf) {
+    MSplit s;
+    s.e[0] = e0;
+    s.e[1] = e1;
+    s.h = h;
+    s.ring[0] = e0 == N0;
+    s.ring[1] = e1 == N1;
+    s.nt[0] = s.nt[1] = 0;
+    int best = 0x7fffffff;
+    for (int tx = 1; tx <= e0 && tx < best; ++tx) {
+        const int wx = (e0 + tx - 1) / tx;
+        const int EX = wx + ((tx > 1 || s.ring[0]) ? 2 * h : 0);
+        if (EX > kMT) continue;
+        const int rows = min(YB * (kMT / EX), buf / (EX | 1));
+        if (rows < 1) continue;
+        int ty;
+        if (!s.ring[1] && e1 <= rows) {
+            ty = 1;
+        } else {
+            const int avail = rows - 2 * h;
+            if (avail < 1) continue;
+            ty = (e1 + avail - 1) / avail;
+        }
+        if (tx * ty < best) {
+            best = tx * ty;
+            s.nt[0] = tx;
+            s.nt[1] = ty;
+        }
+    }
+    for (int a = 0; a < 2; ++a) {
+        if (s.nt[a] < 1) s.nt[a] = 1;  // unreachable for boxes of at most 4096 cells per axis
+        s.w[a] = (s.e[a] + s.nt[a] - 1) / s.nt[a];
+        s.nt[a] = (s.e[a] + s.w[a] - 1) / s.w[a];  // no empty tile
+    }
+    return s;
+}
+
+// Extended tile `t` of a split: first cell in box coordinates (below 0 or past
+// the box only on a whole periodic axis), size, and interior [in0, in1) in
+// extended coordinates.
+struct MTile {
+    int org[2], ext[2], in0[2], in1[2];
+};
+
+__device__ inline MTile march_tile(const MSplit &s, int t) {
+    MTile m;
+    const int i[2] = {t % s.nt[0], t / s.nt[0]};
+    for (int a = 0; a < 2; ++a) {
+        const int b = i[a] * s.w[a], e = min(s.e[a], b + s.w[a]);
+        const int hl = s.ring[a] ? s.h : min(s.h, b), hr = s.ring[a] ? s.h : min(s.h, s.e[a] - e);
+        m.org[a] = b - hl;
+        m.ext[a] = hl + (e - b) + hr;
+        m.in0[a] = hl;
+        m.in1[a] = hl + (e - b);
+    }
+    return m;
+}
+
+// Taxicab chains over a window: forward c <- min(v_i, c + 1) and backward, each
+// from the window's end; o[q] = the smaller of the two at window position KW + q.
+template <typename T, int NV, int KW, int NO>
+__device__ __forceinline__ void taxicab_chains(const T (&v)[NV], T (&o)[NO]) {
+    static_assert(KW >= 1 && KW + NO <= NV, "window");
+    T c = v[0];
+#pragma unroll
+    for (int i = 1; i < NV; ++i) {
+        c = vmin(v[i], c + T(1));
+        if (i >= KW && i < KW + NO) o[i - KW] = c;
+    }
+    c = v[NV - 1];
+#pragma unroll
+    for (int i = NV - 2; i >= 0; --i) {
+        c = vmin(v[i], c + T(1));
+        if (i >= KW && i < KW + NO) o[i - KW] = vmin(o[i - KW], c);
+    }
+}
+
+// Gaussian pass over NO consecutive outputs from a register window v (first
+// entry at output 0 - R): o[q] = sum over t = 0..2R of tp[t] v[q + t], summed in
+// increasing t.  RM: static window radius (>= R).
+template <typename T, int RM, int NO>
+__device__ __forceinline__ void gauss_window(const T (&v)[NO + 2 * RM], const T *tp, int R, T (&o)[NO]) {
+#pragma unroll
+    for (int q = 0; q < NO; ++q) o[q] = T(0);
+#pragma unroll
+    for (int t = 0; t <= 2 * RM; ++t) {
+        if (t > 2 * R) break;
+        const T g = tp[t];
+#pragma unroll
+        for (int q = 0; q < NO; ++q) o[q] = mac<T>(o[q], g, v[q + t]);
+    }
+}
+
+// Column geometry of a thread in an extended tile: the column unit's x, its
+// first row, the box coordinates and interior flags of its YB cells.
+template <int YB> struct MCol {
+    bool act;          // the thread owns a column unit
+    int cx, ry0;       // extended-tile column and first row
+    int bx;            // box x of the column
+    bool colint;       // the column lies in the interior
+    bool rv[YB];       // the row exists in the tile
+    bool rint[YB];     // the cell lies in the interior
+    int by[YB];        // box y of the row
+};
+
+template <int YB>
+__device__ inline MCol<YB> march_col(const MTile &tl, int ex, int ey, int N0, int N1) {
+    MCol<YB> c;
+    const int EX = tl.ext[0], EY = tl.ext[1];
+    const int nyb = (EY + YB - 1) / YB;
+    const int u = threadIdx.x;
+    c.act = u < EX * nyb;
+    c.cx = c.act ? u % EX : 0;
+    c.ry0 = c.act ? (u / EX) * YB : 0;
+    c.bx = axis_map(tl.org[0] + c.cx, ex, N0);
+    c.colint = c.act && c.cx >= tl.in0[0] && c.cx < tl.in1[0];
+#pragma unroll
+    for (int j = 0; j < YB; ++j) {
+        const int ry = c.ry0 + j;
+        c.rv[j] = c.act && ry < EY;
+        c.by[j] = c.rv[j] ? axis_map(tl.org[1] + ry, ey, N1) : 0;
+        c.rint[j] = c.rv[j] && c.colint && ry >= tl.in0[1] && ry < tl.in1[1];
+    }
+    return c;
+}
+
+// ------------------------------------------------------- k_reinit_march (a4)
+
+// Re-initialization of phi^c (old layout Lo) into the new layout Ln (sec.
+// 2.1.6, taxicab scheme): reference values theta = phi / (phi - phi_n) at cells
+// with a face neighbour across the sign change, spreading along x and y by
+// windowed chains inside each plane, forward spreading along z.  3D: writes the
+// partially spread distance with the inside flag as its sign bit; 2D: writes
+// phi = +-min(d, W) and the grain's volume.  Carries the ID-field over to the
+// new layout.  KS: static reach (0: runtime ma.K <= kMaxBand).
+template <typename T, int KS, int YB>
+__global__ void __launch_bounds__(kMT)
+    k_reinit_march(Boxes Lo, Boxes Ln, MarchArgs ma, const T *__restrict__ phic, T *__restrict__ out,
+                   const int *__restrict__ iota_old, int *__restrict__ iota_new, double *__restrict__ vol, T W) {
+    constexpr int KW = KS ? KS : kMaxBand;
+    constexpr int BUF = march_buf<YB>();
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *F = reinterpret_cast<T *>(smem_raw), *Rf = F + BUF, *Dx = Rf + BUF;
+    __shared__ double red[kMT / 64];
+    if (ctl_failed(ma.ctl) || (int)blockIdx.x >= ma.G) return;
+    const int k = ma.order ? ma.order[blockIdx.x] : (int)blockIdx.x;
+    const bool d3 = ma.dim == 3;
+    if (!Ln.alive[k]) {
+        if (!d3 && vol && threadIdx.x == 0) vol[k] = 0.0;
+        return;
+    }
+    const int K = KS ? KS : ma.K;
+    int ne[3], oe[3], dd[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        ne[a] = Ln.ext[3 * k + a];
+        oe[a] = Lo.ext[3 * k + a];
+        const int t = Ln.lo[3 * k + a] - Lo.lo[3 * k + a];  // both in [0, n)
+        dd[a] = t < 0 ? t + ma.n[a] : t;
+    }
+    const T *src = phic + Lo.off[k];
+    T *dst = out + Ln.off[k];
+    const int *io_src = iota_old ? iota_old + Lo.off[k] : nullptr;
+    int *io_dst = iota_new ? iota_new + Ln.off[k] : nullptr;
+    const long long osz = (long long)oe[0] * oe[1];
+    const long long nplane = (long long)ne[0] * ne[1];
+    const int ez = d3 ? ne[2] : 1;
+    const bool ringz = d3 && ne[2] == ma.n[2];
+    const T inf = tinf<T>();
+    const MSplit sp = march_split<YB>(ne[0], ne[1], ma.n[0], ma.n[1], K + 1, BUF);
+    double vsum = 0.0;
+    for (int tile = 0; tile < sp.nt[0] * sp.nt[1]; ++tile) {
+        const MTile tl = march_tile(sp, tile);
+        const int EX = tl.ext[0], EY = tl.ext[1], pitch = EX | 1;
+        const MCol<YB> c = march_col<YB>(tl, ne[0], ne[1], ma.n[0], ma.n[1]);
+        // old-box offsets of the column's cells within a plane (-1: outside the old box)
+        int ocol = c.bx + dd[0];
+        ocol -= ocol >= ma.n[0] ? ma.n[0] : 0;
+        int orow[YB], nrow[YB];
+#pragma unroll
+        for (int j = 0; j < YB; ++j) {
+            int oy = c.by[j] + dd[1];
+            oy -= oy >= ma.n[1] ? ma.n[1] : 0;
+            orow[j] = (c.rv[j] && ocol < oe[0] && oy < oe[1]) ? oy * oe[0] + ocol : -1;
+            nrow[j] = c.by[j] * ne[0] + c.bx;
+        }
+        auto oplane = [&](int z) -> long long {  // old-box offset of new plane z, -1 outside either box
+            int zm = d3 ? axis_map(z, ne[2], ma.n[2]) : (z == 0 ? 0 : -1);
+            if (zm < 0) return -1;
+            int oz = zm + dd[2];
+            oz -= oz >= ma.n[2] ? ma.n[2] : 0;
+            return oz < oe[2] ? (long long)oz * osz : -1;
+        };
+        auto load = [&](int z, T (&v)[YB]) {
+            const long long po = oplane(z);
+#pragma unroll
+            for (int j = 0; j < YB; ++j) v[j] = (po >= 0 && orow[j] >= 0) ? src[po + orow[j]] : -W;
+        };
+        T cm[YB], cc[YB], cp[YB], pf[YB], car[YB];
+        load(-1, cm);
+        load(0, cc);
+        load(1, cp);
+#pragma unroll
+        for (int j = 0; j < YB; ++j) {
+            car[j] = inf;
+            pf[j] = -W;
+        }
+        const int nxq = (EX + kQX - 1) / kQX;
+        for (int z = 0; z < ez; ++z) {
+            if (d3) load(z + 2, pf);
+            // A: the plane's phi^c
+#pragma unroll
+            for (int j = 0; j < YB; ++j)
+                if (c.rv[j]) F[(c.ry0 + j) * pitch + c.cx] = cc[j];
+            __syncthreads();
+            // B: reference values.  Over all neighbours the smallest value is <= 0
+            // exactly when an inside cell has an outside neighbour, and then it is
+            // the extreme one (likewise the largest for an outside cell); theta =
+            // fc / (fc - fn) is monotone in fn on that side, and so are the rounded
+            // operations, so the extreme neighbour gives the smallest theta.
+#pragma unroll
+            for (int j = 0; j < YB; ++j) {
+                if (!c.rv[j]) continue;
+                const int ry = c.ry0 + j, a = ry * pitch + c.cx;
+                const T xm = c.cx > 0 ? F[a - 1] : -W, xp = c.cx + 1 < EX ? F[a + 1] : -W;
+                const T ym = j > 0 ? cc[j > 0 ? j - 1 : 0] : (ry > 0 ? F[a - pitch] : -W);
+                const T yp = (j + 1 < YB && ry + 1 < EY) ? cc[j + 1 < YB ? j + 1 : j] : (ry + 1 < EY ? F[a + pitch] : -W);
+                T lo = vmin(vmin(xm, xp), vmin(ym, yp)), hi = vmax(vmax(xm, xp), vmax(ym, yp));
+                if (d3) {
+                    lo = vmin(lo, vmin(cm[j], cp[j]));
+                    hi = vmax(hi, vmax(cm[j], cp[j]));
+                }
+                const T cur = cc[j];
+                const bool in = cur > T(0);
+                const T ext = in ? lo : hi;
+                T r = inf;
+                if ((ext > T(0)) != in) r = ratio(cur, cur - ext);
+                Rf[a] = r;
+            }
+            __syncthreads();
+            // C: spreading along x (row units, rows fastest across lanes)
+            for (int r = threadIdx.x; r < EY * nxq; r += kMT) {
+                const int ry = r % EY, x0 = (r / EY) * kQX;
+                T v[kQX + 2 * KW];
+#pragma unroll
+                for (int i = 0; i < kQX + 2 * KW; ++i) {
+                    const int x = x0 - KW + i;
+                    const bool ok = x >= 0 && x < EX && x >= x0 - K && x <= x0 + kQX - 1 + K;
+                    v[i] = ok ? Rf[ry * pitch + (ok ? x : 0)] : inf;
+                }
+                T o[kQX];
+                taxicab_chains<T, kQX + 2 * KW, KW, kQX>(v, o);
+#pragma unroll
+                for (int q = 0; q < kQX; ++q)
+                    if (x0 + q < EX) Dx[ry * pitch + x0 + q] = o[q];
+            }
+            __syncthreads();
+            // D: spreading along y for the column unit
+            T d[YB];
+            if (c.act) {
+                T v[YB + 2 * KW];
+#pragma unroll
+                for (int i = 0; i < YB + 2 * KW; ++i) {
+                    const int y = c.ry0 - KW + i;
+                    const bool ok = y >= 0 && y < EY && y >= c.ry0 - K && y <= c.ry0 + YB - 1 + K;
+                    v[i] = ok ? Dx[(ok ? y : 0) * pitch + c.cx] : inf;
+                }
+                taxicab_chains<T, YB + 2 * KW, KW, YB>(v, d);
+            }
+            // E: forward spreading along z, output of the interior cells
+            const long long po = oplane(z);
+#pragma unroll
+            for (int j = 0; j < YB; ++j) {
+                if (!c.rint[j]) continue;
+                const bool in = cc[j] > T(0);
+                const long long idx = (long long)z * nplane + nrow[j];
+                if (d3) {
+                    car[j] = vmin(d[j], car[j] + T(1));
+                    dst[idx] = in ? car[j] : -car[j];
+                } else {
+                    const T dc = d[j] < W ? d[j] : W;
+                    const T pv = in ? dc : -dc;
+                    dst[idx] = pv;
+                    double cl = (double)pv + 0.5;
+                    cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
+                    vsum += cl;
+                }
+                if (io_dst) io_dst[idx] = (po >= 0 && orow[j] >= 0) ? io_src[po + orow[j]] : -1;
+            }
+#pragma unroll
+            for (int j = 0; j < YB; ++j) {
+                cm[j] = cc[j];
+                cc[j] = cp[j];
+                cp[j] = pf[j];
+            }
+        }
+        if (ringz) {
+            // a whole periodic z axis is a ring: the forward chain goes around a
+            // second time from plane 0, over the values of the first lap
+            __threadfence();
+            for (int z = 0; z < ez; ++z)
+#pragma unroll
+                for (int j = 0; j < YB; ++j) {
+                    if (!c.rint[j]) continue;
+                    const long long idx = (long long)z * nplane + nrow[j];
+                    const T v = dst[idx];
+                    car[j] = vmin(fabs(v), car[j] + T(1));
+                    dst[idx] = copysign(car[j], v);
+                }
+        }
+    }
+    if (!d3) {
+        const double s = block_sum(vsum, red);
+        if (threadIdx.x == 0 && vol) vol[k] = s;
+    }
+}
+
+// ------------------------------------------------------ k_predict_march (a1, a2)
+
+// d^p = phi + w (psi - phi) + mob (E_j - E_k) * bulk_scale, clamped to [-W, W],
+// for a cell whose ID-field entry is j and whose function value is p.
+template <typename T>
+__device__ inline T correct_prediction_v(const Physics<T> &ph, int k, int j, T p, T psi, T W, PairCache<T> &pc) {
+    if (j != pc.j) {
+        pc.j = j;
+        pc.w = 1;
+        pc.b = 0;
+        if (j >= 0) {
+            T mob = 1;
+            if (ph.mode & 1) {
+                const T th = misorientation_deg<T>(ph.quat + 4LL * k, ph.quat + 4LL * j);
+                pc.w = pair_weight<T>(th, ph.theta_c_deg, &mob);
+            }
+            if (ph.mode & 2) pc.b = mob * (ph.energy[j] - ph.energy[k]) * ph.bulk_scale;
+        }
+    }
+    T d = p + pc.w * (psi - p) + pc.b;
+    d = d > W ? W : d;
+    d = d < -W ? -W : d;
+    return d;
+}
+
+// The in-plane Gaussian passes of one plane: Cz (the z-convolved plane) -> Cx
+// (x pass, row units) -> the column unit's y pass in `acc`.  Values outside the
+// extended tile read the fill value -W (outside the box; halos hold the box's
+// own values).  Two barriers: Cz is complete before the x pass, Cx before the y
+// pass.
+template <typename T, int RM, int YB>
+__device__ __forceinline__ void plane_xy_pass(const T *Cz, T *Cx, int pitch, int EX, int EY, const MCol<YB> &c,
+                                              const T *tp, int R, T W, T (&acc)[YB]) {
+    __syncthreads();
+    const int nxq = (EX + kQX - 1) / kQX;
+    for (int r = threadIdx.x; r < EY * nxq; r += kMT) {
+        const int ry = r % EY, x0 = (r / EY) * kQX;
+        T v[kQX + 2 * RM];
+#pragma unroll
+        for (int i = 0; i < kQX + 2 * RM; ++i) {
+            const int x = x0 - R + i;
+            const bool ok = x >= 0 && x < EX;
+            v[i] = ok ? Cz[ry * pitch + (ok ? x : 0)] : -W;
+        }
+        T o[kQX];
+        gauss_window<T, RM, kQX>(v, tp, R, o);
+#pragma unroll
+        for (int q = 0; q < kQX; ++q)
+            if (x0 + q < EX) Cx[ry * pitch + x0 + q] = o[q];
+    }
+    __syncthreads();
+    if (c.act) {
+        T v[YB + 2 * RM];
+#pragma unroll
+        for (int i = 0; i < YB + 2 * RM; ++i) {
+            const int y = c.ry0 - R + i;
+            const bool ok = y >= 0 && y < EY;
+            v[i] = ok ? Cx[(ok ? y : 0) * pitch + c.cx] : -W;
+        }
+        gauss_window<T, RM, YB>(v, tp, R, acc);
+    }
+}
+
+// Backward spreading along z of the forward-spread distances f (sign bit: the
+// inside flag), band clamp phi = +-min(d, W), the grain volume sum of clamp(phi
+// + 1/2, 0, 1) (3D), and the predictor psi = G_sigma * phi (passes z, x, y; a
+// sample outside the box reads -W), with the correction epilogue when PH.
+// chain = 0: the input is already a final function (the identity on it).
+// psi == NULL: phi and the volume only.  phi_out: phi is stored when given and
+// the step is the one ma.ctl->phi_at names (always without a control block).
+// RS: static radius (0: runtime ma.R <= kMaxRadius).
+template <typename T, int RS, int YB, bool PH>
+__global__ void __launch_bounds__(kMT)
+    k_predict_march(Boxes L, MarchArgs ma, T *__restrict__ in, T *__restrict__ psi, T *__restrict__ phi_out,
+                    double *__restrict__ vol, const T *__restrict__ taps, Physics<T> ph, T W, int chain) {
+    constexpr int RM = RS ? RS : kMaxRadius;
+    constexpr int NW = 2 * RM + 1;
+    constexpr int BUF = march_buf<YB>();
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *Cz = reinterpret_cast<T *>(smem_raw), *Cx = Cz + BUF;
+    __shared__ double red[kMT / 64];
+    if (ctl_failed(ma.ctl) || (int)blockIdx.x >= ma.G) return;
+    const int k = ma.order ? ma.order[blockIdx.x] : (int)blockIdx.x;
+    const bool d3 = ma.dim == 3;
+    if (!L.alive[k]) {
+        if (d3 && vol && threadIdx.x == 0) vol[k] = 0.0;
+        return;
+    }
+    const int R = RS ? RS : ma.R;
+    const bool want_psi = psi != nullptr;
+    const bool write_phi = phi_out != nullptr && (ma.ctl == nullptr || ma.ctl->steps == ma.ctl->phi_at);
+    const int ex = L.ext[3 * k], ey = L.ext[3 * k + 1], ez = d3 ? L.ext[3 * k + 2] : 1;
+    const long long plane = (long long)ex * ey;
+    T *f = in + L.off[k];
+    T *pp = want_psi ? psi + L.off[k] : nullptr;
+    T *po = write_phi ? phi_out + L.off[k] : nullptr;
+    const int *io = PH ? ph.iota + L.off[k] : nullptr;
+    T tp[NW];
+#pragma unroll
+    for (int t = 0; t < NW; ++t) tp[t] = (want_psi && t <= 2 * R) ? taps[t] : T(0);
+    const MSplit sp = march_split<YB>(ex, ey, ma.n[0], ma.n[1], want_psi ? R : 0, BUF);
+    const bool ringz = d3 && ez == ma.n[2];
+    const T inf = tinf<T>();
+    double vsum = 0.0;
+    PairCache<T> pc;
+
+    auto emit = [&](const MCol<YB> &c, int q, const T (&acc)[YB], const T (&phv)[YB]) {
+#pragma unroll
+        for (int j = 0; j < YB; ++j) {
+            if (!c.rint[j]) continue;
+            const long long idx = (long long)q * plane + c.by[j] * ex + c.bx;
+            T val = acc[j];
+            if constexpr (PH) val = correct_prediction_v<T>(ph, k, io[idx], phv[j], val, W, pc);
+            pp[idx] = val;
+        }
+    };
+
+    if (!d3) {
+        // 2D: the input is the final function; x and y passes only
+        for (int tile = 0; tile < sp.nt[0] * sp.nt[1] && want_psi; ++tile) {
+            const MTile tl = march_tile(sp, tile);
+            const int EX = tl.ext[0], EY = tl.ext[1], pitch = EX | 1;
+            const MCol<YB> c = march_col<YB>(tl, ex, ey, ma.n[0], ma.n[1]);
+            T phv[YB];
+#pragma unroll
+            for (int j = 0; j < YB; ++j) {
+                phv[j] = c.rv[j] ? f[c.by[j] * ex + c.bx] : -W;
+                if (c.rv[j]) Cz[(c.ry0 + j) * pitch + c.cx] = phv[j];
+            }
+            T acc[YB];
+            plane_xy_pass<T, RM, YB>(Cz, Cx, pitch, EX, EY, c, tp, R, W, acc);
+            emit(c, 0, acc, phv);
+        }
+        return;
+    }
+
+    if (ringz) {
+        // A whole periodic z axis: the backward chain goes around twice (from
+        // the last plane), then the final function is convolved with wrapped
+        // planes.  Phase 1 writes phi of every interior cell (to phi_out, or in
+        // place); phase 2 reads it back after a fence.
+        T *tgt = po ? po : f;
+        for (int tile = 0; tile < sp.nt[0] * sp.nt[1]; ++tile) {
+            const MTile tl = march_tile(sp, tile);
+            const MCol<YB> c = march_col<YB>(tl, ex, ey, ma.n[0], ma.n[1]);
+            T car[YB];
+#pragma unroll
+            for (int j = 0; j < YB; ++j) car[j] = inf;
+            for (int lap = 0; lap < 2; ++lap) {
+                for (int z = ez - 1; z >= 0; --z)
+#pragma unroll
+                    for (int j = 0; j < YB; ++j) {
+                        if (!c.rint[j]) continue;
+                        const long long idx = (long long)z * plane + c.by[j] * ex + c.bx;
+                        const T v = lap ? tgt[idx] : f[idx];
+                        const T a = fabs(v);
+                        T b = a;
+                        if (chain) b = (lap == 0 && z == ez - 1) ? a : vmin(a, car[j] + T(1));
+                        car[j] = b;
+                        if (lap == 0) {
+                            tgt[idx] = copysign(b, v);
+                        } else {
+                            const T dc = b < W ? b : W;
+                            const T pv = signbit(v) ? -dc : dc;
+                            tgt[idx] = pv;
+                            double cl = (double)pv + 0.5;
+                            cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
+                            vsum += cl;
+                        }
+                    }
+                __threadfence();
+            }
+        }
+        __syncthreads();
+        for (int tile = 0; tile < sp.nt[0] * sp.nt[1] && want_psi; ++tile) {
+            const MTile tl = march_tile(sp, tile);
+            const int EX = tl.ext[0], EY = tl.ext[1], pitch = EX | 1;
+            const MCol<YB> c = march_col<YB>(tl, ex, ey, ma.n[0], ma.n[1]);
+            T win[NW][YB];
+#pragma unroll
+            for (int i = 0; i < NW; ++i)
+#pragma unroll
+                for (int j = 0; j < YB; ++j) win[i][j] = -W;
+            for (int p = ez - 1 + R; p >= -R; --p) {
+                const int pz = p < 0 ? p + ez : (p >= ez ? p - ez : p);
+#pragma unroll
+                for (int i = NW - 1; i > 0; --i)
+#pragma unroll
+                    for (int j = 0; j < YB; ++j) win[i][j] = win[i - 1][j];
+#pragma unroll
+                for (int j = 0; j < YB; ++j) win[0][j] = c.rv[j] ? tgt[(long long)pz * plane + c.by[j] * ex + c.bx] : -W;
+                const int q = p + R;
+                if (q > ez - 1 || q < 0) continue;
+                T phv[YB];
+#pragma unroll
+                for (int j = 0; j < YB; ++j) {
+                    phv[j] = win[R][j];
+                    if (!c.rv[j]) continue;
+                    T a = T(0);
+#pragma unroll
+                    for (int t = 0; t < NW; ++t)
+                        if (t <= 2 * R) a = mac<T>(a, tp[t], win[t][j]);
+                    Cz[(c.ry0 + j) * pitch + c.cx] = a;
+                }
+                T acc[YB];
+                plane_xy_pass<T, RM, YB>(Cz, Cx, pitch, EX, EY, c, tp, R, W, acc);
+                emit(c, q, acc, phv);
+            }
+        }
+    } else {
+        for (int tile = 0; tile < sp.nt[0] * sp.nt[1]; ++tile) {
+            const MTile tl = march_tile(sp, tile);
+            const int EX = tl.ext[0], EY = tl.ext[1], pitch = EX | 1;
+            const MCol<YB> c = march_col<YB>(tl, ex, ey, ma.n[0], ma.n[1]);
+            long long cell[YB];
+#pragma unroll
+            for (int j = 0; j < YB; ++j) cell[j] = c.by[j] * ex + c.bx;
+            T win[NW][YB], bcar[YB], pf[YB];
+#pragma unroll
+            for (int j = 0; j < YB; ++j) {
+                bcar[j] = inf;
+                pf[j] = c.rv[j] ? f[(long long)(ez - 1) * plane + cell[j]] : -W;
+#pragma unroll
+                for (int i = 0; i < NW; ++i) win[i][j] = -W;
+            }
+            const int pend = want_psi ? -R : 0;
+            for (int p = ez - 1; p >= pend; --p) {
+                T phv[YB];
+                if (p >= 0) {
+                    T cur[YB];
+#pragma unroll
+                    for (int j = 0; j < YB; ++j) {
+                        cur[j] = pf[j];
+                        if (p >= 1 && c.rv[j]) pf[j] = f[(long long)(p - 1) * plane + cell[j]];
+                    }
+#pragma unroll
+                    for (int j = 0; j < YB; ++j) {
+                        if (!c.rv[j]) {
+                            phv[j] = -W;
+                            continue;
+                        }
+                        const T a = fabs(cur[j]);
+                        const T b = chain ? vmin(a, bcar[j] + T(1)) : a;
+                        bcar[j] = b;
+                        const T dc = b < W ? b : W;
+                        phv[j] = signbit(cur[j]) ? -dc : dc;
+                        if (c.rint[j]) {
+                            double cl = (double)phv[j] + 0.5;
+                            cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
+                            vsum += cl;
+                            if (po) po[(long long)p * plane + cell[j]] = phv[j];
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < YB; ++j) phv[j] = -W;
+                }
+                if (!want_psi) continue;
+                // window: win[i] holds plane p + i
+#pragma unroll
+                for (int i = NW - 1; i > 0; --i)
+#pragma unroll
+                    for (int j = 0; j < YB; ++j) win[i][j] = win[i - 1][j];
+#pragma unroll
+                for (int j = 0; j < YB; ++j) win[0][j] = phv[j];
+                const int q = p + R;
+                if (q > ez - 1) continue;
+                T phq[YB];
+#pragma unroll
+                for (int j = 0; j < YB; ++j) {
+                    phq[j] = win[R][j];
+                    if (!c.rv[j]) continue;
+                    T a = T(0);
+#pragma unroll
+                    for (int t = 0; t < NW; ++t)
+                        if (t <= 2 * R) a = mac<T>(a, tp[t], win[t][j]);
+                    Cz[(c.ry0 + j) * pitch + c.cx] = a;
+                }
+                T acc[YB];
+                plane_xy_pass<T, RM, YB>(Cz, Cx, pitch, EX, EY, c, tp, R, W, acc);
+                emit(c, q, acc, phq);
+            }
+        }
+    }
+    const double s = block_sum(vsum, red);
+    if (threadIdx.x == 0 && vol) vol[k] = s;
+}
+
+// ------------------------------------------------------ step bookkeeping
+
+// Zero n ints (graph-safe replacement of a memset).
+__global__ void k_zero_int(int *p, int n, const Ctl *ctl) {
+    if (ctl_failed(ctl)) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// End of a completed step: alive count and sizes of the new layout, grain
+// voxels of the step (the box volumes of its input layout), step counter.
+__global__ void __launch_bounds__(1024) k_step_end(Ctl *ctl, const int *alive_new, const long long *off_in,
+                                                   const long long *off_new, const long long *cov_total, int G) {
+    if (ctl->fail) return;
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    int local = 0;
+    for (int k = threadIdx.x; k < G; k += blockDim.x) local += alive_new[k] != 0;
+    atomicAdd(&cnt, local);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ctl->alive = cnt;
+        ctl->last_gv = off_in[G];
+        ctl->total_gv += off_in[G];
+        ctl->arena_now = off_new[G];
+        ctl->cov_now = *cov_total;
+        ctl->steps += 1;
+    }
+}
+
+// Launch order of the march kernels: grains by box volume, largest first
+// (classes of equal floor(log2 volume); the order within a class is
+// arbitrary), extinct grains last.  One work group.
+__global__ void __launch_bounds__(1024) k_order_size(const long long *off, const int *alive, int *order, int G,
+                                                     const Ctl *ctl) {
+    if (ctl_failed(ctl)) return;
+    __shared__ int cnt[64], cur[64];
+    const int t = threadIdx.x;
+    if (t < 64) cnt[t] = 0;
+    __syncthreads();
+    auto bucket = [&](int k) {
+        const long long v = alive[k] ? off[k + 1] - off[k] : 0;
+        return v > 0 ? __clzll(v) : 63;  // larger volume: fewer leading zeros
+    };
+    for (int k = t; k < G; k += blockDim.x) atomicAdd(&cnt[bucket(k)], 1);
+    __syncthreads();
+    if (t == 0) {
+        int s = 0;
+        for (int b = 0; b < 64; ++b) {
+            cur[b] = s;
+            s += cnt[b];
+        }
+    }
+    __syncthreads();
+    for (int k = t; k < G; k += blockDim.x) order[atomicAdd(&cur[bucket(k)], 1)] = k;
+}
+
+}  // namespace gg

@@ -28,7 +28,8 @@ EXPORTS = ["gg_create", "gg_step", "gg_sync", "gg_grain_count", "gg_grain_volume
            "gg_destroy", "gg_version", "gg_profile", "gg_get_kernel_times", "gg_coarsen", "gg_grain_areas",
            "gg_grain_sdf", "gg_save", "gg_load", "gg_autotune"]
 
-KERNEL_CLASSES = ["conv_xy", "conv_z", "compare", "reinit_xy", "reinit_z", "plan", "volume", "reinit_sweep"]
+KERNEL_CLASSES = ["predict", "compare", "reinit", "reinit_sweep", "plan"]
+FLAG_ORDER_SIZE = 1
 
 
 class GGError(RuntimeError):
@@ -41,7 +42,8 @@ class Config(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("band", C.c_double),
                 ("precision", C.c_int32), ("physics", C.c_int32), ("theta_c_deg", C.c_double),
                 ("voxel_m", C.c_double), ("gamma_max", C.c_double),
-                ("capacity_headroom", C.c_double), ("redistance", C.c_int32)]
+                ("capacity_headroom", C.c_double), ("redistance", C.c_int32),
+                ("batched", C.c_int32), ("flags", C.c_uint32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -72,7 +74,13 @@ def torch_allocator():
 
 
 class KernelTimes(C.Structure):
-    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8), ("voxels", C.c_int64 * 8)]
+    _fields_ = [("ms", C.c_double * 5), ("launches", C.c_int64 * 5), ("voxels", C.c_int64 * 5)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("order_size", C.c_int32), ("lds_bytes", C.c_int32), ("small_bytes", C.c_int32),
+                ("candidates", C.c_int32), ("ns_per_gv", C.c_double * 8), ("cand_order", C.c_int32 * 8),
+                ("cand_lds", C.c_int32 * 8), ("cand_small", C.c_int32 * 8)]
 
 
 class StepStats(C.Structure):
@@ -110,7 +118,7 @@ def load_library(path=LIB_PATH):
         "gg_coarsen": (i32, [vp, vp]),
         "gg_grain_areas": (i32, [vp, vp, vp, i64]),
         "gg_grain_sdf": (i32, [vp, i32, vp, vp, vp, i64]),
-        "gg_autotune": (i32, [vp, dbl, i32, vp, vp]),
+        "gg_autotune": (i32, [vp, dbl, i32, C.POINTER(Tuning)]),
         "gg_save": (i32, [vp, C.c_char_p]),
         "gg_load": (i32, [vp, C.c_char_p]),
         "gg_keep_intermediates": (i32, [vp, i32]),
@@ -142,11 +150,13 @@ class Simulation:
     stream: optional hipStream_t handle (int), e.g. torch.cuda.current_stream().cuda_stream.
     allocator: None (the library's hipMalloc), "torch" (PyTorch's caching
     allocator, on `stream` or torch's current stream) or an Allocator.
+    batched: gg_step queues captured HIP graphs and returns without waiting.
+    order_size: per-grain kernels take the largest boxes first.
     """
 
     def __init__(self, labels, band, G=None, precision="fp64", physics=0, quat=None,
                  theta_c_deg=15.0, energy=None, voxel_m=0.0, gamma_max=0.0, stream=None,
-                 headroom=0.0, redistance="taxicab", allocator=None):
+                 headroom=0.0, redistance="taxicab", allocator=None, batched=False, order_size=False):
         lib = load_library()
         labels = np.ascontiguousarray(labels, dtype=np.int32)
         if labels.ndim == 2:
@@ -166,6 +176,8 @@ class Simulation:
         cfg.gamma_max = float(gamma_max)
         cfg.capacity_headroom = float(headroom)
         cfg.redistance = {"taxicab": GG_REDIST_TAXICAB, "euclid": GG_REDIST_EUCLID}[redistance]
+        cfg.batched = 1 if batched else 0
+        cfg.flags = FLAG_ORDER_SIZE if order_size else 0
         q = None if quat is None else np.ascontiguousarray(quat, dtype=np.float64)
         e = None if energy is None else np.ascontiguousarray(energy, dtype=np.float64)
         if allocator == "torch":
@@ -214,12 +226,15 @@ class Simulation:
         return lo, ext, out.reshape(int(ext[2]), int(ext[1]), int(ext[0]))
 
     def autotune(self, dt, steps_per_candidate=1):
-        """Pick the LDS budgets (work group, small class) with the fastest steps;
-        advances the simulation.  Returns (lds_bytes, small_bytes)."""
-        a = C.c_int32()
-        b = C.c_int32()
-        self._check(self._lib.gg_autotune(self._h, float(dt), int(steps_per_candidate), C.byref(a), C.byref(b)))
-        return a.value, b.value
+        """Pick the launch schedule with the fastest steps (advances the
+        simulation).  Returns a dict: the chosen order_size, lds_bytes,
+        small_bytes and every candidate's device ns per grain voxel."""
+        t = Tuning()
+        self._check(self._lib.gg_autotune(self._h, float(dt), int(steps_per_candidate), C.byref(t)))
+        n = t.candidates
+        return dict(order_size=t.order_size, lds_bytes=t.lds_bytes, small_bytes=t.small_bytes,
+                    candidates=[dict(order_size=t.cand_order[i], lds_bytes=t.cand_lds[i],
+                                     small_bytes=t.cand_small[i], ns_per_gv=t.ns_per_gv[i]) for i in range(n)])
 
     def save(self, path):
         """Write a checkpoint of the state to `path`."""

@@ -39,7 +39,7 @@ def test_config_struct_matches_header():
     text = open(HEADER).read()
     body = re.search(r"typedef struct \{([^{}]*)\} gg_config;", text).group(1)
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
-    names = re.findall(r"\b(?:int32_t|double)\s+(\w+)", body)
+    names = re.findall(r"\b(?:u?int32_t|double)\s+(\w+)", body)
     assert names == [f[0] for f in gg.Config._fields_]
 
 
@@ -60,6 +60,8 @@ def _create(lib, **kw):
     cfg.physics = kw.get("physics", 0)
     cfg.theta_c_deg = 15.0
     cfg.redistance = kw.get("redistance", 0)
+    cfg.batched = kw.get("batched", 0)
+    cfg.flags = kw.get("flags", 0)
     labels = kw.get("labels", np.zeros(int(np.prod(n)), np.int32))
     h = C.c_void_p()
     st = lib.gg_create(C.byref(cfg), labels.ctypes.data_as(C.c_void_p), kw.get("G", 1), None,
@@ -78,6 +80,8 @@ def _create(lib, **kw):
     dict(physics=1),                           # misorientation weights without quaternions
     dict(physics=2),                           # bulk energy without energy densities
     dict(redistance=2),                        # unknown re-initialization scheme
+    dict(batched=2),                           # batched is a flag
+    dict(flags=8),                             # unknown flag bits
     dict(dim=3, n=(2048, 2048, 1024), labels=np.zeros(1, np.int32)),  # 2^32 voxels: rejected before labels are read
 ])
 def test_argument_errors_are_reported_before_any_device_use(lib, kw):
