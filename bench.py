@@ -65,13 +65,13 @@ def _phys(cfg):
     return {}
 
 
-def make_sim(cfg, precision, redistance, batched, order_size=False):
+def make_sim(cfg, precision, redistance, batched, order_size=True):
     import paper_1701_06658_amd as gg
     return gg.Simulation(cfg["labels"], cfg["W"], G=cfg["G"], precision=precision, redistance=redistance,
                          batched=batched, order_size=order_size, **_phys(cfg))
 
 
-def run_gpu(cfg, precision, steps, warmup, redistance="taxicab", batched=True, order_size=False,
+def run_gpu(cfg, precision, steps, warmup, redistance="taxicab", batched=True, order_size=True,
             autotune=False, copy_probe=False):
     """Timed run: warm-up steps, then `steps` steps between stream
     synchronisations, with no per-kernel timing."""
@@ -110,7 +110,7 @@ def run_gpu(cfg, precision, steps, warmup, redistance="taxicab", batched=True, o
     return out
 
 
-def run_profiled(cfg, precision, steps, warmup, redistance="taxicab", order_size=False):
+def run_profiled(cfg, precision, steps, warmup, redistance="taxicab", order_size=True):
     """The same steps again on a fresh simulation with per-kernel HIP events
     (plain launches)."""
     sim = make_sim(cfg, precision, redistance, False, order_size)
@@ -193,24 +193,31 @@ def roofline(kt, s_bytes, physics, sweeps=0, workload=None, precision=None):
 
 def copy_peak(nbytes=2 << 30, reps=20):
     """Measured streaming copy on the device (read + write bytes per second of
-    a device-to-device copy of `nbytes`), beside the published HBM peak."""
-    import torch
-    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    a.fill_(1.0)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    del a, b
-    torch.cuda.empty_cache()
-    return dict(GBs=2.0 * nbytes / (ms * 1e-3) / 1e9, bytes=nbytes, kind="torch device-to-device copy")
+    a device-to-device copy of `nbytes` by PyTorch), beside the published HBM
+    peak.  Runs in a process of its own: PyTorch brings its own HIP runtime."""
+    import subprocess
+    code = f"""
+import json, torch
+a = torch.empty({nbytes} // 4, dtype=torch.float32, device="cuda")
+b = torch.empty_like(a)
+a.fill_(1.0)
+for _ in range(3):
+    b.copy_(a)
+torch.cuda.synchronize()
+e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+e0.record()
+for _ in range({reps}):
+    b.copy_(a)
+e1.record()
+torch.cuda.synchronize()
+print(json.dumps(e0.elapsed_time(e1) / {reps}))
+"""
+    try:
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240)
+        ms = float(r.stdout.strip().splitlines()[-1])
+    except (subprocess.SubprocessError, ValueError, IndexError):
+        return None
+    return dict(GBs=2.0 * nbytes / (ms * 1e-3) / 1e9, bytes=nbytes, kind="PyTorch device-to-device copy")
 
 
 def cpu_baseline(index, threads=None):
@@ -253,7 +260,8 @@ def main():
     ap.add_argument("--precision", default=None, help="fp32 (mixed) or fp64 (plain)")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-profile", action="store_true", help="skip the profiled per-kernel run")
-    ap.add_argument("--order-size", action="store_true", help="per-grain kernels take the largest boxes first")
+    ap.add_argument("--order-id", action="store_true",
+                    help="per-grain kernels in grain-id order (default: largest box first)")
     ap.add_argument("--autotune", action="store_true",
                     help="choose the launch schedule with gg_autotune before the warm-up steps")
     ap.add_argument("--redistance", default="taxicab", choices=["taxicab", "euclid"],
@@ -274,7 +282,7 @@ def main():
     precision = args.precision or cfg["precision"]
     physics = bool(_phys(cfg))
     main_res = run_gpu(cfg, precision, args.steps, args.warmup, redistance=args.redistance, batched=True,
-                       order_size=args.order_size, autotune=args.autotune, copy_probe=args.copy_probe)
+                       order_size=not args.order_id, autotune=args.autotune, copy_probe=args.copy_probe)
     s_bytes = 4 if precision == "fp32" else 8
     workload = ("3d256_8000g" if args.config == 3 else f"config{args.config}") + (
         "_euclid" if args.redistance == "euclid" else "")
@@ -295,7 +303,7 @@ def main():
         "config": {"workload": cfg["name"], "grid": list(cfg["n"]), "grains": cfg["G"],
                    "sigma_voxels": cfg["sigma"], "band_voxels": cfg["W"],
                    "precision": precision, "redistance": args.redistance, "batched": True,
-                   "order_size": bool(args.order_size), "alive_after": main_res["alive"],
+                   "order_size": not args.order_id, "alive_after": main_res["alive"],
                    "superposition": round(main_res["superposition"], 3)},
         "step_roofline": {"alg_bytes_per_gv": bpg, "achieved": main_res["value"] * bpg / 1e9,
                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -305,21 +313,23 @@ def main():
     sweeps = euclid_sweeps(cfg["dim"], cfg["W"]) if args.redistance == "euclid" else 0
     if not args.no_profile:
         kt = run_profiled(cfg, precision, args.steps, args.warmup, redistance=args.redistance,
-                          order_size=args.order_size)
+                          order_size=not args.order_id)
         line["roofline"] = roofline(kt, s_bytes, physics, sweeps, workload, precision)
+        log(f"[bench] {precision} per kernel: " + json.dumps({k: dict(ms=round(v["ms"], 3), launches=v["launches"])
+                                                              for k, v in kt.items()}))
     plain32 = run_gpu(cfg, precision, args.steps, args.warmup, redistance=args.redistance, batched=False,
-                      order_size=args.order_size)
+                      order_size=not args.order_id)
     line["plain_launches"] = dict(value=plain32["value"], ms_per_step=plain32["ms_per_step"],
                                   batched_speedup=main_res["value"] / plain32["value"])
     if not args.no_plain and precision != "fp64":
         plain = run_gpu(cfg, "fp64", args.steps, args.warmup, redistance=args.redistance, batched=False,
-                        order_size=args.order_size)
+                        order_size=not args.order_id)
         line["plain_fp64"] = dict(value=plain["value"], ms_per_step=plain["ms_per_step"],
                                   step_roofline_frac=plain["value"] * step_alg_bytes(8, physics) / 1e9 / HBM_PEAK_GBS,
                                   mixed_speedup=main_res["value"] / plain["value"])
         if not args.no_profile:
             kt64 = run_profiled(cfg, "fp64", args.steps, args.warmup, redistance=args.redistance,
-                                order_size=args.order_size)
+                                order_size=not args.order_id)
             line["plain_fp64"]["roofline"] = roofline(kt64, 8, physics, sweeps, workload, "fp64")
     if args.autotune:
         line["tuning"] = main_res["tuned"]

@@ -127,9 +127,10 @@ typedef struct {
 
 /* gg_config.flags */
 enum {
-    GG_FLAG_ORDER_SIZE = 1u /* launch the per-grain kernels largest box first
-                               (the default order is by grain id); results do
-                               not depend on the order                          */
+    GG_FLAG_ORDER_ID = 1u   /* launch the per-grain kernels in grain-id order
+                               (the default is largest box first, which keeps
+                               the longest boxes off the end of each launch);
+                               results do not depend on the order               */
 };
 
 typedef struct {
@@ -295,7 +296,7 @@ gg_status gg_coarsen(gg_sim *sim, const int32_t n_new[3]);
 gg_status gg_grain_sdf(gg_sim *sim, int32_t id, int32_t lo[3], int32_t ext[3], double *out, int64_t cap);
 
 /* Autotuning of the launch schedule: the order in which the per-grain kernels
- * take the boxes (grain id or largest box first, GG_FLAG_ORDER_SIZE) and, for
+ * take the boxes (largest box first, or grain id: GG_FLAG_ORDER_ID) and, for
  * the Euclidean variant, the LDS budgets of its work-item tilings (the work
  * group's, default 40 KB, and the small launch class's, default 26 KB).
  * gg_autotune takes steps_per_candidate steps (normalised length dt) with

@@ -339,7 +339,7 @@ template <typename T> struct Sim final : SimBase {
         headroom = c.capacity_headroom >= 1.0 ? c.capacity_headroom : 1.25;
         exact = c.capacity_headroom == 1.0;
         batched = c.batched != 0;
-        order_size = (c.flags & GG_FLAG_ORDER_SIZE) ? 1 : 0;
+        order_size = (c.flags & GG_FLAG_ORDER_ID) ? 0 : 1;
         set_tiles();
         occ_words = (std::max(n[0], std::max(n[1], n[2])) + 31) / 32;
         if (s) {
@@ -665,7 +665,7 @@ template <typename T> struct Sim final : SimBase {
     // the final function and the volumes).
     void launch_reinit(int lo_l, int ln_l, const T *phic, T *out, const int *io_old, int *io_new, bool in_step) {
         const gg::MarchArgs ma = march_args(in_step);
-        const size_t lds = 3 * (size_t)gg::march_buf<4>() * sizeof(T);
+        const size_t lds = (size_t)gg::reinit_cells<T>() * sizeof(T);
         double *v = dim == 2 ? vol.as<double>() : nullptr;
         tbegin(GG_K_REINIT, in_step ? 0 : tot[ln_l].arena, in_step ? 1 : 0);
         auto go = [&](auto kern) {
@@ -688,7 +688,8 @@ template <typename T> struct Sim final : SimBase {
         const int Rk = psi ? R : 8;
         tbegin(GG_K_PREDICT, in_step ? 0 : tot[l].arena, in_step ? 2 : 0);
         auto go = [&](auto kern, int yb) {
-            const size_t lds = 2 * (size_t)(gg::kMT * yb + 256) * sizeof(T);
+            const size_t lds = (size_t)gg::predict_cells<T>() * sizeof(T);
+            (void)yb;
             hipLaunchKernelGGL(kern, dim3(G), dim3(gg::kMT), lds, stream, boxes_of(l), ma, in, psi, phi_out, v,
                                (const T *)taps_d.as<T>(), ph, W, chain);
         };
@@ -1736,7 +1737,7 @@ gg_status gg_create(const gg_config *cfg, const int32_t *labels, int32_t n_grain
     if (cfg->redistance != GG_REDIST_TAXICAB && cfg->redistance != GG_REDIST_EUCLID)
         return fail(nullptr, GG_E_ARG, "redistance must be GG_REDIST_TAXICAB or GG_REDIST_EUCLID");
     if (cfg->batched != 0 && cfg->batched != 1) return fail(nullptr, GG_E_ARG, "batched must be 0 or 1");
-    if (cfg->flags & ~(uint32_t)GG_FLAG_ORDER_SIZE) return fail(nullptr, GG_E_ARG, "unknown flag bits");
+    if (cfg->flags & ~(uint32_t)GG_FLAG_ORDER_ID) return fail(nullptr, GG_E_ARG, "unknown flag bits");
     if ((cfg->physics & GG_PHYS_MISORIENTATION) && (!quat || !(cfg->theta_c_deg > 0.0)))
         return fail(nullptr, GG_E_ARG, "misorientation weights need quat and theta_c_deg > 0");
     if ((cfg->physics & GG_PHYS_BULK) && (!energy_density || !(cfg->voxel_m > 0.0) || !(cfg->gamma_max > 0.0)))

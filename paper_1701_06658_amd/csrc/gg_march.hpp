@@ -32,11 +32,57 @@
 
 namespace gg {
 
-constexpr int kMT = 512;  // threads per march group
+#ifndef GG_MT
+#define GG_MT 512
+#endif
+constexpr int kMT = GG_MT;  // threads per march group
 constexpr int kQX = 4;    // outputs per thread of an in-plane x pass
 
-// LDS cells of one plane buffer for column units of YB rows.
-template <int YB> constexpr int march_buf() { return kMT * YB + 256; }
+// LDS layouts of the march kernels for an extended tile of EX x EY cells.
+// Every in-plane window pass reads from a buffer whose frame (wide enough for
+// the window) holds the fill value, so window reads need no bounds checks; the
+// frames are written once per tile and never overwritten by plane data.
+//
+// Both kernels are software-pipelined over the planes of a box: each stage
+// reads the buffer its predecessor wrote in the previous iteration, so every
+// buffer comes twice (for planes of even and odd index) and one barrier per
+// plane separates the stages.
+//
+// Re-initialization: F, phi^c with a one-cell frame of -W; Rf, reference values
+// with x frames of KW cells of +inf (and kQX more on the right); Dx, the x-spread
+// values with y frames of KW rows of +inf (and YB more below).
+template <int KW, int YB> struct ReinitLds {
+    int pf, pr, pd, sF, sR, sD, oR, oD, total;
+    __host__ __device__ ReinitLds(int EX, int EY) {
+        pf = (EX + 2) | 1;
+        pr = (EX + 2 * KW + kQX) | 1;
+        pd = EX | 1;
+        sF = pf * (EY + 2);
+        sR = pr * EY;
+        sD = pd * (EY + 2 * KW + YB);
+        oR = 2 * sF;
+        oD = oR + 2 * sR;
+        total = oD + 2 * sD;
+    }
+};
+// Predictor: Cz, the z-convolved plane with x frames of RM cells of -W (and kQX
+// more on the right); Cx, the x-convolved plane with y frames of RM rows of -W
+// (and YB more below).
+template <int RM, int YB> struct PredictLds {
+    int pz, px, sZ, sX, oX, total;
+    __host__ __device__ PredictLds(int EX, int EY) {
+        pz = (EX + 2 * RM + kQX) | 1;
+        px = EX | 1;
+        sZ = pz * EY;
+        sX = px * (EY + 2 * RM + YB);
+        oX = 2 * sZ;
+        total = oX + 2 * sX;
+    }
+};
+
+// LDS cells a march kernel may use (its dynamic allocation).
+template <typename T> constexpr int reinit_cells() { return sizeof(T) == 8 ? 12288 : 16384; }
+template <typename T> constexpr int predict_cells() { return sizeof(T) == 8 ? 8192 : 12288; }
 
 struct MarchArgs {
     int n[3];
@@ -56,8 +102,10 @@ struct MSplit {
 
 // The fewest tiles whose extended tile (interior plus a halo of h cells on each
 // side that lies inside the box, or wraps around a whole periodic axis) has
-// EX * ceil(EY / YB) <= kMT column units and (EX | 1) * EY <= buf cells.
-template <int YB> __device__ inline MSplit march_split(int e0, int e1, int N0, int N1, int h, int buf) {
+// EX * ceil(EY / YB) <= kMT column units and a layout Lay(EX, EY) of at most
+// `cells` LDS cells (the layout's size is affine in EY).
+template <int YB, typename Lay>
+__device__ inline MSplit march_split(int e0, int e1, int N0, int N1, int h, int cells) {
     MSplit s;
     s.e[0] = e0;
     s.e[1] = e1;
@@ -70,7 +118,8 @@ template <int YB> __device__ inline MSplit march_split(int e0, int e1, int N0, i
         const int wx = (e0 + tx - 1) / tx;
         const int EX = wx + ((tx > 1 || s.ring[0]) ? 2 * h : 0);
         if (EX > kMT) continue;
-        const int rows = min(YB * (kMT / EX), buf / (EX | 1));
+        const int b = Lay(EX, 0).total, a = Lay(EX, 1).total - b;
+        const int rows = min(YB * (kMT / EX), cells >= b ? (cells - b) / a : 0);
         if (rows < 1) continue;
         int ty;
         if (!s.ring[1] && e1 <= rows) {
@@ -92,6 +141,11 @@ template <int YB> __device__ inline MSplit march_split(int e0, int e1, int N0, i
         s.nt[a] = (s.e[a] + s.w[a] - 1) / s.w[a];  // no empty tile
     }
     return s;
+}
+
+// Fill n LDS cells with v (all threads of the group).
+template <typename T> __device__ __forceinline__ void lds_fill(T *p, int n, T v) {
+    for (int i = threadIdx.x; i < n; i += kMT) p[i] = v;
 }
 
 // Extended tile `t` of a split: first cell in box coordinates (below 0 or past
@@ -197,9 +251,9 @@ __global__ void __launch_bounds__(kMT)
     k_reinit_march(Boxes Lo, Boxes Ln, MarchArgs ma, const T *__restrict__ phic, T *__restrict__ out,
                    const int *__restrict__ iota_old, int *__restrict__ iota_new, double *__restrict__ vol, T W) {
     constexpr int KW = KS ? KS : kMaxBand;
-    constexpr int BUF = march_buf<YB>();
+    using Lay = ReinitLds<KW, YB>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *F = reinterpret_cast<T *>(smem_raw), *Rf = F + BUF, *Dx = Rf + BUF;
+    T *sm = reinterpret_cast<T *>(smem_raw);
     __shared__ double red[kMT / 64];
     if (ctl_failed(ma.ctl) || (int)blockIdx.x >= ma.G) return;
     const int k = ma.order ? ma.order[blockIdx.x] : (int)blockIdx.x;
@@ -221,16 +275,21 @@ __global__ void __launch_bounds__(kMT)
     T *dst = out + Ln.off[k];
     const int *io_src = iota_old ? iota_old + Lo.off[k] : nullptr;
     int *io_dst = iota_new ? iota_new + Ln.off[k] : nullptr;
-    const long long osz = (long long)oe[0] * oe[1];
-    const long long nplane = (long long)ne[0] * ne[1];
+    const int osz = oe[0] * oe[1];  // box volumes are below 2^31
+    const int nplane = ne[0] * ne[1];
     const int ez = d3 ? ne[2] : 1;
     const bool ringz = d3 && ne[2] == ma.n[2];
     const T inf = tinf<T>();
-    const MSplit sp = march_split<YB>(ne[0], ne[1], ma.n[0], ma.n[1], K + 1, BUF);
+    const MSplit sp = march_split<YB, Lay>(ne[0], ne[1], ma.n[0], ma.n[1], K + 1, reinit_cells<T>());
     double vsum = 0.0;
     for (int tile = 0; tile < sp.nt[0] * sp.nt[1]; ++tile) {
         const MTile tl = march_tile(sp, tile);
-        const int EX = tl.ext[0], EY = tl.ext[1], pitch = EX | 1;
+        const int EX = tl.ext[0], EY = tl.ext[1];
+        const Lay ly(EX, EY);
+        // frames: -W around phi^c, +inf around the spreading inputs
+        lds_fill(sm, ly.oR, -W);
+        lds_fill(sm + ly.oR, ly.total - ly.oR, inf);
+        __syncthreads();
         const MCol<YB> c = march_col<YB>(tl, ne[0], ne[1], ma.n[0], ma.n[1]);
         // old-box offsets of the column's cells within a plane (-1: outside the old box)
         int ocol = c.bx + dd[0];
@@ -243,115 +302,131 @@ __global__ void __launch_bounds__(kMT)
             orow[j] = (c.rv[j] && ocol < oe[0] && oy < oe[1]) ? oy * oe[0] + ocol : -1;
             nrow[j] = c.by[j] * ne[0] + c.bx;
         }
-        auto oplane = [&](int z) -> long long {  // old-box offset of new plane z, -1 outside either box
+        auto oplane = [&](int z) -> int {  // old-box offset of new plane z, -1 outside either box
             int zm = d3 ? axis_map(z, ne[2], ma.n[2]) : (z == 0 ? 0 : -1);
             if (zm < 0) return -1;
             int oz = zm + dd[2];
             oz -= oz >= ma.n[2] ? ma.n[2] : 0;
-            return oz < oe[2] ? (long long)oz * osz : -1;
+            return oz < oe[2] ? oz * osz : -1;
         };
         auto load = [&](int z, T (&v)[YB]) {
-            const long long po = oplane(z);
+            const int po = oplane(z);
 #pragma unroll
             for (int j = 0; j < YB; ++j) v[j] = (po >= 0 && orow[j] >= 0) ? src[po + orow[j]] : -W;
         };
-        T cm[YB], cc[YB], cp[YB], pf[YB], car[YB];
-        load(-1, cm);
-        load(0, cc);
-        load(1, cp);
+        // at the start of iteration z: planes z - 2, z - 1, z in q0, q1, q2;
+        // z + 1 and z + 2 on their way in n1, n2
+        T q0[YB], q1[YB], q2[YB], n1[YB], n2[YB], car[YB];
+        load(-2, q0);
+        load(-1, q1);
+        load(0, q2);
+        load(1, n1);
+        load(2, n2);
 #pragma unroll
-        for (int j = 0; j < YB; ++j) {
-            car[j] = inf;
-            pf[j] = -W;
-        }
+        for (int j = 0; j < YB; ++j) car[j] = inf;
+        unsigned ins = 0;  // inside flags: bit 4 j + (plane & 3)
         const int nxq = (EX + kQX - 1) / kQX;
-        for (int z = 0; z < ez; ++z) {
-            if (d3) load(z + 2, pf);
-            // A: the plane's phi^c
+        const int fc = (c.ry0 + 1) * ly.pf + c.cx + 1;  // the unit's first cell in F
+        // stages of iteration z: A plane z (phi^c into F), B plane z - 1
+        // (reference values into Rf), C plane z - 2 (x spreading into Dx), D and
+        // E plane z - 3 (y spreading, forward z spreading, output)
+        for (int z = 0; z < ez + 3; ++z) {
+            if (z < ez && c.act) {
+                T *Fb = sm + (z & 1) * ly.sF;
 #pragma unroll
-            for (int j = 0; j < YB; ++j)
-                if (c.rv[j]) F[(c.ry0 + j) * pitch + c.cx] = cc[j];
-            __syncthreads();
-            // B: reference values.  Over all neighbours the smallest value is <= 0
-            // exactly when an inside cell has an outside neighbour, and then it is
-            // the extreme one (likewise the largest for an outside cell); theta =
-            // fc / (fc - fn) is monotone in fn on that side, and so are the rounded
-            // operations, so the extreme neighbour gives the smallest theta.
-#pragma unroll
-            for (int j = 0; j < YB; ++j) {
-                if (!c.rv[j]) continue;
-                const int ry = c.ry0 + j, a = ry * pitch + c.cx;
-                const T xm = c.cx > 0 ? F[a - 1] : -W, xp = c.cx + 1 < EX ? F[a + 1] : -W;
-                const T ym = j > 0 ? cc[j > 0 ? j - 1 : 0] : (ry > 0 ? F[a - pitch] : -W);
-                const T yp = (j + 1 < YB && ry + 1 < EY) ? cc[j + 1 < YB ? j + 1 : j] : (ry + 1 < EY ? F[a + pitch] : -W);
-                T lo = vmin(vmin(xm, xp), vmin(ym, yp)), hi = vmax(vmax(xm, xp), vmax(ym, yp));
-                if (d3) {
-                    lo = vmin(lo, vmin(cm[j], cp[j]));
-                    hi = vmax(hi, vmax(cm[j], cp[j]));
+                for (int j = 0; j < YB; ++j) {
+                    if (!c.rv[j]) continue;
+                    Fb[fc + j * ly.pf] = q2[j];
+                    const unsigned bit = 1u << (4 * j + (z & 3));
+                    ins = q2[j] > T(0) ? (ins | bit) : (ins & ~bit);
                 }
-                const T cur = cc[j];
-                const bool in = cur > T(0);
-                const T ext = in ? lo : hi;
-                T r = inf;
-                if ((ext > T(0)) != in) r = ratio(cur, cur - ext);
-                Rf[a] = r;
             }
-            __syncthreads();
-            // C: spreading along x (row units, rows fastest across lanes)
-            for (int r = threadIdx.x; r < EY * nxq; r += kMT) {
-                const int ry = r % EY, x0 = (r / EY) * kQX;
-                T v[kQX + 2 * KW];
+            if (z >= 1 && z - 1 < ez && c.act) {
+                // reference values.  Over all neighbours the smallest value is <= 0
+                // exactly when an inside cell has an outside neighbour, and then it
+                // is the extreme one (likewise the largest for an outside cell);
+                // theta = fc / (fc - fn) is monotone in fn on that side, and so are
+                // the rounded operations, so the extreme neighbour gives the
+                // smallest theta.
+                const T *Fb = sm + ((z - 1) & 1) * ly.sF;
+                T *Rb = sm + ly.oR + ((z - 1) & 1) * ly.sR;
 #pragma unroll
-                for (int i = 0; i < kQX + 2 * KW; ++i) {
-                    const int x = x0 - KW + i;
-                    const bool ok = x >= 0 && x < EX && x >= x0 - K && x <= x0 + kQX - 1 + K;
-                    v[i] = ok ? Rf[ry * pitch + (ok ? x : 0)] : inf;
+                for (int j = 0; j < YB; ++j) {
+                    if (!c.rv[j]) continue;
+                    const int a = fc + j * ly.pf;
+                    const T xm = Fb[a - 1], xp = Fb[a + 1];
+                    const T ym = j > 0 ? q1[j > 0 ? j - 1 : 0] : Fb[a - ly.pf];
+                    const T yp = (j + 1 < YB && c.rv[j + 1 < YB ? j + 1 : j]) ? q1[j + 1 < YB ? j + 1 : j] : Fb[a + ly.pf];
+                    T lo = vmin(vmin(xm, xp), vmin(ym, yp)), hi = vmax(vmax(xm, xp), vmax(ym, yp));
+                    if (d3) {
+                        lo = vmin(lo, vmin(q0[j], q2[j]));
+                        hi = vmax(hi, vmax(q0[j], q2[j]));
+                    }
+                    const T cur = q1[j];
+                    const bool in = cur > T(0);
+                    const T ext = in ? lo : hi;
+                    T r = inf;
+                    if ((ext > T(0)) != in) r = ratio(cur, cur - ext);
+                    Rb[(c.ry0 + j) * ly.pr + c.cx + KW] = r;
                 }
-                T o[kQX];
-                taxicab_chains<T, kQX + 2 * KW, KW, kQX>(v, o);
-#pragma unroll
-                for (int q = 0; q < kQX; ++q)
-                    if (x0 + q < EX) Dx[ry * pitch + x0 + q] = o[q];
             }
-            __syncthreads();
-            // D: spreading along y for the column unit
-            T d[YB];
-            if (c.act) {
-                T v[YB + 2 * KW];
+            if (z >= 2 && z - 2 < ez) {
+                // spreading along x (row units, rows fastest across lanes); the
+                // window [x0 - KW, x0 + kQX + KW) reads the +inf frame beyond the tile
+                const T *Rb = sm + ly.oR + ((z - 2) & 1) * ly.sR;
+                T *Db = sm + ly.oD + ((z - 2) & 1) * ly.sD;
+                for (int r = threadIdx.x; r < EY * nxq; r += kMT) {
+                    const int ry = r % EY, x0 = (r / EY) * kQX;
+                    const T *row = Rb + ry * ly.pr + x0;
+                    T v[kQX + 2 * KW];
 #pragma unroll
-                for (int i = 0; i < YB + 2 * KW; ++i) {
-                    const int y = c.ry0 - KW + i;
-                    const bool ok = y >= 0 && y < EY && y >= c.ry0 - K && y <= c.ry0 + YB - 1 + K;
-                    v[i] = ok ? Dx[(ok ? y : 0) * pitch + c.cx] : inf;
+                    for (int i = 0; i < kQX + 2 * KW; ++i) v[i] = row[i];
+                    T o[kQX];
+                    taxicab_chains<T, kQX + 2 * KW, KW, kQX>(v, o);
+                    T *drow = Db + (ry + KW) * ly.pd + x0;
+#pragma unroll
+                    for (int q = 0; q < kQX; ++q)
+                        if (x0 + q < EX) drow[q] = o[q];
                 }
+            }
+            if (z >= 3 && c.act) {
+                // spreading along y for the column unit (rows [ry0 - KW, ry0 + YB + KW)),
+                // forward spreading along z, output of the interior cells
+                const int zz = z - 3;
+                const T *col = sm + ly.oD + (zz & 1) * ly.sD + c.ry0 * ly.pd + c.cx;
+                T v[YB + 2 * KW], d[YB];
+#pragma unroll
+                for (int i = 0; i < YB + 2 * KW; ++i) v[i] = col[i * ly.pd];
                 taxicab_chains<T, YB + 2 * KW, KW, YB>(v, d);
-            }
-            // E: forward spreading along z, output of the interior cells
-            const long long po = oplane(z);
+                const int po = oplane(zz);
 #pragma unroll
-            for (int j = 0; j < YB; ++j) {
-                if (!c.rint[j]) continue;
-                const bool in = cc[j] > T(0);
-                const long long idx = (long long)z * nplane + nrow[j];
-                if (d3) {
-                    car[j] = vmin(d[j], car[j] + T(1));
-                    dst[idx] = in ? car[j] : -car[j];
-                } else {
-                    const T dc = d[j] < W ? d[j] : W;
-                    const T pv = in ? dc : -dc;
-                    dst[idx] = pv;
-                    double cl = (double)pv + 0.5;
-                    cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
-                    vsum += cl;
+                for (int j = 0; j < YB; ++j) {
+                    if (!c.rint[j]) continue;
+                    const bool in = (ins >> (4 * j + (zz & 3))) & 1u;
+                    const int idx = zz * nplane + nrow[j];
+                    if (d3) {
+                        car[j] = vmin(d[j], car[j] + T(1));
+                        dst[idx] = in ? car[j] : -car[j];
+                    } else {
+                        const T dc = d[j] < W ? d[j] : W;
+                        const T pv = in ? dc : -dc;
+                        dst[idx] = pv;
+                        double cl = (double)pv + 0.5;
+                        cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
+                        vsum += cl;
+                    }
+                    if (io_dst) io_dst[idx] = (po >= 0 && orow[j] >= 0) ? io_src[po + orow[j]] : -1;
                 }
-                if (io_dst) io_dst[idx] = (po >= 0 && orow[j] >= 0) ? io_src[po + orow[j]] : -1;
             }
 #pragma unroll
             for (int j = 0; j < YB; ++j) {
-                cm[j] = cc[j];
-                cc[j] = cp[j];
-                cp[j] = pf[j];
+                q0[j] = q1[j];
+                q1[j] = q2[j];
+                q2[j] = n1[j];
+                n1[j] = n2[j];
             }
+            if (d3) load(z + 3, n2);
+            __syncthreads();
         }
         if (ringz) {
             // a whole periodic z axis is a ring: the forward chain goes around a
@@ -361,12 +436,13 @@ __global__ void __launch_bounds__(kMT)
 #pragma unroll
                 for (int j = 0; j < YB; ++j) {
                     if (!c.rint[j]) continue;
-                    const long long idx = (long long)z * nplane + nrow[j];
+                    const int idx = z * nplane + nrow[j];
                     const T v = dst[idx];
                     car[j] = vmin(fabs(v), car[j] + T(1));
                     dst[idx] = copysign(car[j], v);
                 }
         }
+        __syncthreads();  // the next tile refills the frames
     }
     if (!d3) {
         const double s = block_sum(vsum, red);
@@ -399,40 +475,34 @@ __device__ inline T correct_prediction_v(const Physics<T> &ph, int k, int j, T p
     return d;
 }
 
-// The in-plane Gaussian passes of one plane: Cz (the z-convolved plane) -> Cx
-// (x pass, row units) -> the column unit's y pass in `acc`.  Values outside the
-// extended tile read the fill value -W (outside the box; halos hold the box's
-// own values).  Two barriers: Cz is complete before the x pass, Cx before the y
-// pass.
+// The in-plane Gaussian passes of one plane: Cz (the z-convolved plane, x
+// frames of RM cells of -W) -> Cx (x pass, row units; y frames of RM rows of
+// -W) -> the column unit's y pass in `acc`.  Two barriers: Cz is complete
+// before the x pass, Cx before the y pass.
 template <typename T, int RM, int YB>
-__device__ __forceinline__ void plane_xy_pass(const T *Cz, T *Cx, int pitch, int EX, int EY, const MCol<YB> &c,
-                                              const T *tp, int R, T W, T (&acc)[YB]) {
+__device__ __forceinline__ void plane_xy_pass(const T *Cz, T *Cx, const PredictLds<RM, YB> &ly, int EX, int EY,
+                                              const MCol<YB> &c, const T *tp, int R, T (&acc)[YB]) {
     __syncthreads();
     const int nxq = (EX + kQX - 1) / kQX;
     for (int r = threadIdx.x; r < EY * nxq; r += kMT) {
         const int ry = r % EY, x0 = (r / EY) * kQX;
+        const T *row = Cz + ry * ly.pz + x0 + (RM - R);
         T v[kQX + 2 * RM];
 #pragma unroll
-        for (int i = 0; i < kQX + 2 * RM; ++i) {
-            const int x = x0 - R + i;
-            const bool ok = x >= 0 && x < EX;
-            v[i] = ok ? Cz[ry * pitch + (ok ? x : 0)] : -W;
-        }
+        for (int i = 0; i < kQX + 2 * RM; ++i) v[i] = (i < kQX + 2 * R) ? row[i] : T(0);
         T o[kQX];
         gauss_window<T, RM, kQX>(v, tp, R, o);
+        T *xrow = Cx + (ry + RM) * ly.px + x0;
 #pragma unroll
         for (int q = 0; q < kQX; ++q)
-            if (x0 + q < EX) Cx[ry * pitch + x0 + q] = o[q];
+            if (x0 + q < EX) xrow[q] = o[q];
     }
     __syncthreads();
     if (c.act) {
+        const T *col = Cx + (c.ry0 + RM - R) * ly.px + c.cx;
         T v[YB + 2 * RM];
 #pragma unroll
-        for (int i = 0; i < YB + 2 * RM; ++i) {
-            const int y = c.ry0 - R + i;
-            const bool ok = y >= 0 && y < EY;
-            v[i] = ok ? Cx[(ok ? y : 0) * pitch + c.cx] : -W;
-        }
+        for (int i = 0; i < YB + 2 * RM; ++i) v[i] = (i < YB + 2 * R) ? col[i * ly.px] : T(0);
         gauss_window<T, RM, YB>(v, tp, R, acc);
     }
 }
@@ -451,9 +521,9 @@ __global__ void __launch_bounds__(kMT)
                     double *__restrict__ vol, const T *__restrict__ taps, Physics<T> ph, T W, int chain) {
     constexpr int RM = RS ? RS : kMaxRadius;
     constexpr int NW = 2 * RM + 1;
-    constexpr int BUF = march_buf<YB>();
+    using Lay = PredictLds<RM, YB>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *Cz = reinterpret_cast<T *>(smem_raw), *Cx = Cz + BUF;
+    T *sm = reinterpret_cast<T *>(smem_raw);
     __shared__ double red[kMT / 64];
     if (ctl_failed(ma.ctl) || (int)blockIdx.x >= ma.G) return;
     const int k = ma.order ? ma.order[blockIdx.x] : (int)blockIdx.x;
@@ -466,7 +536,7 @@ __global__ void __launch_bounds__(kMT)
     const bool want_psi = psi != nullptr;
     const bool write_phi = phi_out != nullptr && (ma.ctl == nullptr || ma.ctl->steps == ma.ctl->phi_at);
     const int ex = L.ext[3 * k], ey = L.ext[3 * k + 1], ez = d3 ? L.ext[3 * k + 2] : 1;
-    const long long plane = (long long)ex * ey;
+    const int plane = ex * ey;  // box volumes are below 2^31
     T *f = in + L.off[k];
     T *pp = want_psi ? psi + L.off[k] : nullptr;
     T *po = write_phi ? phi_out + L.off[k] : nullptr;
@@ -474,7 +544,7 @@ __global__ void __launch_bounds__(kMT)
     T tp[NW];
 #pragma unroll
     for (int t = 0; t < NW; ++t) tp[t] = (want_psi && t <= 2 * R) ? taps[t] : T(0);
-    const MSplit sp = march_split<YB>(ex, ey, ma.n[0], ma.n[1], want_psi ? R : 0, BUF);
+    const MSplit sp = march_split<YB, Lay>(ex, ey, ma.n[0], ma.n[1], want_psi ? R : 0, predict_cells<T>());
     const bool ringz = d3 && ez == ma.n[2];
     const T inf = tinf<T>();
     double vsum = 0.0;
@@ -484,27 +554,36 @@ __global__ void __launch_bounds__(kMT)
 #pragma unroll
         for (int j = 0; j < YB; ++j) {
             if (!c.rint[j]) continue;
-            const long long idx = (long long)q * plane + c.by[j] * ex + c.bx;
+            const int idx = q * plane + c.by[j] * ex + c.bx;
             T val = acc[j];
             if constexpr (PH) val = correct_prediction_v<T>(ph, k, io[idx], phv[j], val, W, pc);
             pp[idx] = val;
         }
+    };
+    // frames of -W around both buffers (the next tile refills after a barrier)
+    auto frames = [&](const Lay &ly) {
+        __syncthreads();
+        lds_fill(sm, ly.total, -W);
+        __syncthreads();
     };
 
     if (!d3) {
         // 2D: the input is the final function; x and y passes only
         for (int tile = 0; tile < sp.nt[0] * sp.nt[1] && want_psi; ++tile) {
             const MTile tl = march_tile(sp, tile);
-            const int EX = tl.ext[0], EY = tl.ext[1], pitch = EX | 1;
+            const int EX = tl.ext[0], EY = tl.ext[1];
+            const Lay ly(EX, EY);
+            frames(ly);
+            T *Cz = sm, *Cx = sm + ly.oX;
             const MCol<YB> c = march_col<YB>(tl, ex, ey, ma.n[0], ma.n[1]);
             T phv[YB];
 #pragma unroll
             for (int j = 0; j < YB; ++j) {
                 phv[j] = c.rv[j] ? f[c.by[j] * ex + c.bx] : -W;
-                if (c.rv[j]) Cz[(c.ry0 + j) * pitch + c.cx] = phv[j];
+                if (c.rv[j]) Cz[(c.ry0 + j) * ly.pz + c.cx + RM] = phv[j];
             }
             T acc[YB];
-            plane_xy_pass<T, RM, YB>(Cz, Cx, pitch, EX, EY, c, tp, R, W, acc);
+            plane_xy_pass<T, RM, YB>(Cz, Cx, ly, EX, EY, c, tp, R, acc);
             emit(c, 0, acc, phv);
         }
         return;
@@ -527,7 +606,7 @@ __global__ void __launch_bounds__(kMT)
 #pragma unroll
                     for (int j = 0; j < YB; ++j) {
                         if (!c.rint[j]) continue;
-                        const long long idx = (long long)z * plane + c.by[j] * ex + c.bx;
+                        const int idx = z * plane + c.by[j] * ex + c.bx;
                         const T v = lap ? tgt[idx] : f[idx];
                         const T a = fabs(v);
                         T b = a;
@@ -550,7 +629,10 @@ __global__ void __launch_bounds__(kMT)
         __syncthreads();
         for (int tile = 0; tile < sp.nt[0] * sp.nt[1] && want_psi; ++tile) {
             const MTile tl = march_tile(sp, tile);
-            const int EX = tl.ext[0], EY = tl.ext[1], pitch = EX | 1;
+            const int EX = tl.ext[0], EY = tl.ext[1];
+            const Lay ly(EX, EY);
+            frames(ly);
+            T *Cz = sm, *Cx = sm + ly.oX;
             const MCol<YB> c = march_col<YB>(tl, ex, ey, ma.n[0], ma.n[1]);
             T win[NW][YB];
 #pragma unroll
@@ -564,7 +646,7 @@ __global__ void __launch_bounds__(kMT)
 #pragma unroll
                     for (int j = 0; j < YB; ++j) win[i][j] = win[i - 1][j];
 #pragma unroll
-                for (int j = 0; j < YB; ++j) win[0][j] = c.rv[j] ? tgt[(long long)pz * plane + c.by[j] * ex + c.bx] : -W;
+                for (int j = 0; j < YB; ++j) win[0][j] = c.rv[j] ? tgt[pz * plane + c.by[j] * ex + c.bx] : -W;
                 const int q = p + R;
                 if (q > ez - 1 || q < 0) continue;
                 T phv[YB];
@@ -576,38 +658,50 @@ __global__ void __launch_bounds__(kMT)
 #pragma unroll
                     for (int t = 0; t < NW; ++t)
                         if (t <= 2 * R) a = mac<T>(a, tp[t], win[t][j]);
-                    Cz[(c.ry0 + j) * pitch + c.cx] = a;
+                    Cz[(c.ry0 + j) * ly.pz + c.cx + RM] = a;
                 }
                 T acc[YB];
-                plane_xy_pass<T, RM, YB>(Cz, Cx, pitch, EX, EY, c, tp, R, W, acc);
+                plane_xy_pass<T, RM, YB>(Cz, Cx + 0, ly, EX, EY, c, tp, R, acc);
                 emit(c, q, acc, phv);
             }
         }
     } else {
         for (int tile = 0; tile < sp.nt[0] * sp.nt[1]; ++tile) {
             const MTile tl = march_tile(sp, tile);
-            const int EX = tl.ext[0], EY = tl.ext[1], pitch = EX | 1;
+            const int EX = tl.ext[0], EY = tl.ext[1];
+            const Lay ly(EX, EY);
+            if (want_psi) frames(ly);
             const MCol<YB> c = march_col<YB>(tl, ex, ey, ma.n[0], ma.n[1]);
-            long long cell[YB];
+            int cell[YB];
 #pragma unroll
             for (int j = 0; j < YB; ++j) cell[j] = c.by[j] * ex + c.bx;
-            T win[NW][YB], bcar[YB], pf[YB];
+            // planes p, p - 1, p - 2 on their way while plane p + 1 is used
+            constexpr int PD = 3;
+            T win[NW][YB], bcar[YB], pf[PD][YB];
 #pragma unroll
             for (int j = 0; j < YB; ++j) {
                 bcar[j] = inf;
-                pf[j] = c.rv[j] ? f[(long long)(ez - 1) * plane + cell[j]] : -W;
+#pragma unroll
+                for (int d = 0; d < PD; ++d)
+                    pf[d][j] = (c.rv[j] && ez - 1 - d >= 0) ? f[(ez - 1 - d) * plane + cell[j]] : -W;
 #pragma unroll
                 for (int i = 0; i < NW; ++i) win[i][j] = -W;
             }
-            const int pend = want_psi ? -R : 0;
+            const int nxq = (EX + kQX - 1) / kQX;
+            // stages of the iteration for input plane p (descending): the z pass
+            // of plane p + R into Cz, the x pass of plane p + R + 1 (Cz -> Cx), the
+            // y pass and output of plane p + R + 2 (from Cx)
+            const int pend = want_psi ? -R - 2 : 0;
             for (int p = ez - 1; p >= pend; --p) {
                 T phv[YB];
                 if (p >= 0) {
                     T cur[YB];
 #pragma unroll
                     for (int j = 0; j < YB; ++j) {
-                        cur[j] = pf[j];
-                        if (p >= 1 && c.rv[j]) pf[j] = f[(long long)(p - 1) * plane + cell[j]];
+                        cur[j] = pf[0][j];
+#pragma unroll
+                        for (int d = 0; d + 1 < PD; ++d) pf[d][j] = pf[d + 1][j];
+                        if (p - PD >= 0 && c.rv[j]) pf[PD - 1][j] = f[(p - PD) * plane + cell[j]];
                     }
 #pragma unroll
                     for (int j = 0; j < YB; ++j) {
@@ -624,7 +718,7 @@ __global__ void __launch_bounds__(kMT)
                             double cl = (double)phv[j] + 0.5;
                             cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
                             vsum += cl;
-                            if (po) po[(long long)p * plane + cell[j]] = phv[j];
+                            if (po) po[p * plane + cell[j]] = phv[j];
                         }
                     }
                 } else {
@@ -639,22 +733,50 @@ __global__ void __launch_bounds__(kMT)
                     for (int j = 0; j < YB; ++j) win[i][j] = win[i - 1][j];
 #pragma unroll
                 for (int j = 0; j < YB; ++j) win[0][j] = phv[j];
-                const int q = p + R;
-                if (q > ez - 1) continue;
-                T phq[YB];
+                const int qz = p + R, qx = qz + 1, qy = qz + 2;
+                if (qy <= ez - 1 && c.act) {
+                    // y pass and output of plane qy (its phi: window entry R + 2)
+                    const T *col = sm + ly.oX + (qy & 1) * ly.sX + (c.ry0 + RM - R) * ly.px + c.cx;
+                    T v[YB + 2 * RM], acc[YB], phy[YB];
 #pragma unroll
-                for (int j = 0; j < YB; ++j) {
-                    phq[j] = win[R][j];
-                    if (!c.rv[j]) continue;
-                    T a = T(0);
+                    for (int i = 0; i < YB + 2 * RM; ++i) v[i] = (i < YB + 2 * R) ? col[i * ly.px] : T(0);
+                    gauss_window<T, RM, YB>(v, tp, R, acc);
 #pragma unroll
-                    for (int t = 0; t < NW; ++t)
-                        if (t <= 2 * R) a = mac<T>(a, tp[t], win[t][j]);
-                    Cz[(c.ry0 + j) * pitch + c.cx] = a;
+                    for (int j = 0; j < YB; ++j) phy[j] = win[R + 2][j];
+                    emit(c, qy, acc, phy);
                 }
-                T acc[YB];
-                plane_xy_pass<T, RM, YB>(Cz, Cx, pitch, EX, EY, c, tp, R, W, acc);
-                emit(c, q, acc, phq);
+                if (qx >= 0 && qx <= ez - 1) {
+                    // x pass of plane qx (row units, rows fastest across lanes)
+                    const T *Zb = sm + (qx & 1) * ly.sZ;
+                    T *Xb = sm + ly.oX + (qx & 1) * ly.sX;
+                    for (int r = threadIdx.x; r < EY * nxq; r += kMT) {
+                        const int ry = r % EY, x0 = (r / EY) * kQX;
+                        const T *row = Zb + ry * ly.pz + x0 + (RM - R);
+                        T v[kQX + 2 * RM];
+#pragma unroll
+                        for (int i = 0; i < kQX + 2 * RM; ++i) v[i] = (i < kQX + 2 * R) ? row[i] : T(0);
+                        T o[kQX];
+                        gauss_window<T, RM, kQX>(v, tp, R, o);
+                        T *xrow = Xb + (ry + RM) * ly.px + x0;
+#pragma unroll
+                        for (int q = 0; q < kQX; ++q)
+                            if (x0 + q < EX) xrow[q] = o[q];
+                    }
+                }
+                if (qz >= 0 && qz <= ez - 1 && c.act) {
+                    // z pass of plane qz from the window (ascending taps)
+                    T *Zb = sm + (qz & 1) * ly.sZ;
+#pragma unroll
+                    for (int j = 0; j < YB; ++j) {
+                        if (!c.rv[j]) continue;
+                        T a = T(0);
+#pragma unroll
+                        for (int t = 0; t < NW; ++t)
+                            if (t <= 2 * R) a = mac<T>(a, tp[t], win[t][j]);
+                        Zb[(c.ry0 + j) * ly.pz + c.cx + RM] = a;
+                    }
+                }
+                if (qx <= ez - 1) __syncthreads();
             }
         }
     }

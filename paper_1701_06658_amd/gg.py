@@ -29,7 +29,7 @@ EXPORTS = ["gg_create", "gg_step", "gg_sync", "gg_grain_count", "gg_grain_volume
            "gg_grain_sdf", "gg_save", "gg_load", "gg_autotune"]
 
 KERNEL_CLASSES = ["predict", "compare", "reinit", "reinit_sweep", "plan"]
-FLAG_ORDER_SIZE = 1
+FLAG_ORDER_ID = 1
 
 
 class GGError(RuntimeError):
@@ -151,12 +151,12 @@ class Simulation:
     allocator: None (the library's hipMalloc), "torch" (PyTorch's caching
     allocator, on `stream` or torch's current stream) or an Allocator.
     batched: gg_step queues captured HIP graphs and returns without waiting.
-    order_size: per-grain kernels take the largest boxes first.
+    order_size: per-grain kernels take the largest boxes first (False: grain-id order).
     """
 
     def __init__(self, labels, band, G=None, precision="fp64", physics=0, quat=None,
                  theta_c_deg=15.0, energy=None, voxel_m=0.0, gamma_max=0.0, stream=None,
-                 headroom=0.0, redistance="taxicab", allocator=None, batched=False, order_size=False):
+                 headroom=0.0, redistance="taxicab", allocator=None, batched=False, order_size=True):
         lib = load_library()
         labels = np.ascontiguousarray(labels, dtype=np.int32)
         if labels.ndim == 2:
@@ -177,7 +177,7 @@ class Simulation:
         cfg.capacity_headroom = float(headroom)
         cfg.redistance = {"taxicab": GG_REDIST_TAXICAB, "euclid": GG_REDIST_EUCLID}[redistance]
         cfg.batched = 1 if batched else 0
-        cfg.flags = FLAG_ORDER_SIZE if order_size else 0
+        cfg.flags = 0 if order_size else FLAG_ORDER_ID
         q = None if quat is None else np.ascontiguousarray(quat, dtype=np.float64)
         e = None if energy is None else np.ascontiguousarray(energy, dtype=np.float64)
         if allocator == "torch":

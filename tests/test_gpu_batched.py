@@ -93,7 +93,7 @@ def test_growing_grain_forces_retakes():
 def test_order_size_changes_no_value():
     c = make_config(2, N=64, G=125)
     a = _sim(c, "fp32", batched=True, order_size=True)
-    b = _sim(c, "fp32", batched=True)
+    b = _sim(c, "fp32", batched=True, order_size=False)
     a.step(c["dt"], 6)
     b.step(c["dt"], 6)
     _same(a.state(), b.state())
