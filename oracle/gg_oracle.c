@@ -70,6 +70,10 @@ struct orc_sim {
     double gamma_max;
     /* re-initialization scheme of the steps: 0 taxicab spreading, 1 Euclidean */
     int redist;
+    /* misorientation weight from the closest boundary point inside the tube
+     * |phi| < cp_tube (sec. 3.2); otherwise from the ID-field */
+    int closest;
+    double cp_tube;
     /* intermediates of the last step */
     int keep;
     int *plo, *pext, *palive;
@@ -439,6 +443,370 @@ double orc_pair_weight(double theta_deg, double theta_c_deg, double *mobility) {
     return mu * g;
 }
 
+/* ---------------------------------------- closest grain-boundary point (a2) */
+/*
+ * Sec. 2.1.4 lets every grid point of grain k adopt the boundary properties of
+ * the closest point of the boundary; sec. 3.2 finds that point on an explicit
+ * linear representation of the zero level set (marching squares / cubes), with
+ * the pieces clustered by the number of neighbouring grains (ID-field) and the
+ * search restricted to a narrow tube.  Reading taken here:
+ *  - cells: the 2^D nodes c + {0,1}^D of the box (on an axis the box takes
+ *    whole, cells wrap around the periodic grid); each cell is cut along its
+ *    main diagonal into simplices -- triangles (0,1,3), (0,2,3) in 2D, the six
+ *    tetrahedra (0, e_a, e_a + e_b, 7) in 3D, corner bit 0 = x, 1 = y, 2 = z --
+ *    and the zero set of the linear interpolant of phi on a simplex is a
+ *    segment (2D) or one or two triangles (3D);
+ *  - a crossing vertex on the simplex edge from node u to node v (u <= v
+ *    componentwise) lies at u + t (v - u), t = phi_u / (phi_u - phi_v), in
+ *    coordinates relative to the voxel x (exact integers plus t);
+ *  - the piece's character: the distinct ID-field entries j >= 0 at the cell's
+ *    nodes (one: the boundary with grain j; more: a triple or higher junction);
+ *    its weight is the mean of w(k, j) over them, 1 with none;
+ *  - every voxel with |phi(x)| < tube takes the weight of the piece of smallest
+ *    squared Euclidean distance, ties to the lowest cell (linear index of its
+ *    lower node) and then the lowest piece; other voxels keep the ID-field.
+ * The distances follow one fixed sequence of operations (segment: endpoints in
+ * the order of their node keys, clamped projection; triangle: projection when
+ * it falls inside, else the nearest edge), so that a voxel equally far from
+ * two pieces that share a vertex or an edge sees the same value from both.
+ */
+static int valid_grid(int dim, const int32_t n[3]);
+
+typedef struct {
+    int u[3];  /* node u relative to the voxel */
+    int d[3];  /* v - u, 0 or 1 per axis */
+    double t;
+} cp_vtx;
+
+static void cp_pos(const cp_vtx *a, double p[3]) {
+    for (int i = 0; i < 3; i++) p[i] = (double)a->u[i] + a->t * (double)a->d[i];
+}
+
+/* node key order: (u_z, u_y, u_x, v_z, v_y, v_x) */
+static int cp_less(const cp_vtx *a, const cp_vtx *b) {
+    int ka[6] = {a->u[2], a->u[1], a->u[0], a->u[2] + a->d[2], a->u[1] + a->d[1], a->u[0] + a->d[0]};
+    int kb[6] = {b->u[2], b->u[1], b->u[0], b->u[2] + b->d[2], b->u[1] + b->d[1], b->u[0] + b->d[0]};
+    for (int i = 0; i < 6; i++)
+        if (ka[i] != kb[i]) return ka[i] < kb[i];
+    return 0;
+}
+
+static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+static void cross3(const double a[3], const double b[3], double o[3]) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* squared distance from the voxel (the origin) to the segment PQ */
+static double cp_seg2(const cp_vtx *P, const cp_vtx *Q) {
+    if (cp_less(Q, P)) {
+        const cp_vtx *t = P;
+        P = Q;
+        Q = t;
+    }
+    double p[3], q[3], d[3], c[3];
+    cp_pos(P, p);
+    cp_pos(Q, q);
+    for (int i = 0; i < 3; i++) d[i] = q[i] - p[i];
+    double dd = dot3(d, d), s = 0.0;
+    if (dd > 0.0) {
+        s = -dot3(p, d) / dd;
+        if (s < 0.0) s = 0.0;
+        if (s > 1.0) s = 1.0;
+    }
+    for (int i = 0; i < 3; i++) c[i] = p[i] + s * d[i];
+    return dot3(c, c);
+}
+
+/* squared distance from the origin to the triangle ABC */
+static double cp_tri2(const cp_vtx *A, const cp_vtx *B, const cp_vtx *C) {
+    double a[3], b[3], c[3], ab[3], ac[3], bc[3], ca[3], n[3];
+    cp_pos(A, a);
+    cp_pos(B, b);
+    cp_pos(C, c);
+    for (int i = 0; i < 3; i++) {
+        ab[i] = b[i] - a[i];
+        ac[i] = c[i] - a[i];
+        bc[i] = c[i] - b[i];
+        ca[i] = a[i] - c[i];
+    }
+    cross3(ab, ac, n);
+    double nn = dot3(n, n);
+    if (nn > 0.0) {
+        double ma[3] = {-a[0], -a[1], -a[2]}, mb[3] = {-b[0], -b[1], -b[2]}, mc[3] = {-c[0], -c[1], -c[2]};
+        double e0[3], e1[3], e2[3];
+        cross3(ab, ma, e0);
+        cross3(bc, mb, e1);
+        cross3(ca, mc, e2);
+        if (dot3(n, e0) >= 0.0 && dot3(n, e1) >= 0.0 && dot3(n, e2) >= 0.0) {
+            double h = dot3(n, ma);
+            return h * h / nn;
+        }
+    }
+    double m = cp_seg2(A, B), m1 = cp_seg2(B, C), m2 = cp_seg2(C, A);
+    if (m1 < m) m = m1;
+    if (m2 < m) m = m2;
+    return m;
+}
+
+static const int cp_tets[6][4] = {{0, 1, 3, 7}, {0, 1, 5, 7}, {0, 2, 3, 7}, {0, 2, 6, 7}, {0, 4, 5, 7}, {0, 4, 6, 7}};
+static const int cp_tris[2][3] = {{0, 1, 3}, {0, 2, 3}};
+
+/* crossing vertex on the edge between simplex corners bu <= bv (corner bits) */
+static void cp_edge(const int o[3], int bu, int bv, const double *f, cp_vtx *out) {
+    for (int a = 0; a < 3; a++) {
+        out->u[a] = o[a] + ((bu >> a) & 1);
+        out->d[a] = ((bv >> a) & 1) - ((bu >> a) & 1);
+    }
+    out->t = f[bu] / (f[bu] - f[bv]);
+}
+
+/* Every piece of one cell (lower node at offset o from the voxel, node values
+ * f by corner bits): squared distances into d2[piece], -1 where the piece does
+ * not exist.  Pieces: 2D triangle i -> piece i; 3D tetrahedron i -> pieces
+ * 2i (and 2i + 1 when the zero set is a quadrilateral). */
+static void cp_cell(int dim, const int o[3], const double *f, double d2[12]) {
+    for (int i = 0; i < 12; i++) d2[i] = -1.0;
+    if (dim == 2) {
+        for (int ti = 0; ti < 2; ti++) {
+            const int *tv = cp_tris[ti];
+            int nin = 0, in[3];
+            for (int i = 0; i < 3; i++) {
+                in[i] = f[tv[i]] > 0.0;
+                nin += in[i];
+            }
+            if (nin == 0 || nin == 3) continue;
+            int lone = -1;
+            for (int i = 0; i < 3; i++)
+                if (in[i] == (nin == 1)) lone = i;
+            cp_vtx v[2];
+            int m = 0;
+            for (int i = 0; i < 3; i++) {
+                if (i == lone) continue;
+                int lo = lone < i ? lone : i, hi = lone < i ? i : lone;
+                cp_edge(o, tv[lo], tv[hi], f, &v[m++]);
+            }
+            d2[ti] = cp_seg2(&v[0], &v[1]);
+        }
+        return;
+    }
+    for (int ti = 0; ti < 6; ti++) {
+        const int *tv = cp_tets[ti];
+        int nin = 0, in[4];
+        for (int i = 0; i < 4; i++) {
+            in[i] = f[tv[i]] > 0.0;
+            nin += in[i];
+        }
+        if (nin == 0 || nin == 4) continue;
+        if (nin == 1 || nin == 3) {
+            int lone = -1;
+            for (int i = 0; i < 4; i++)
+                if (in[i] == (nin == 1)) lone = i;
+            cp_vtx v[3];
+            int m = 0;
+            for (int i = 0; i < 4; i++) {
+                if (i == lone) continue;
+                int lo = lone < i ? lone : i, hi = lone < i ? i : lone;
+                cp_edge(o, tv[lo], tv[hi], f, &v[m++]);
+            }
+            d2[2 * ti] = cp_tri2(&v[0], &v[1], &v[2]);
+        } else {
+            int I[2], O[2], ni = 0, no = 0;
+            for (int i = 0; i < 4; i++) {
+                if (in[i]) I[ni++] = i;
+                else O[no++] = i;
+            }
+            /* edge (i, j) with i < j in simplex order */
+#define CP_E(i, j, out) cp_edge(o, tv[(i) < (j) ? (i) : (j)], tv[(i) < (j) ? (j) : (i)], f, out)
+            cp_vtx vac, vad, vbd, vbc;
+            CP_E(I[0], O[0], &vac);
+            CP_E(I[0], O[1], &vad);
+            CP_E(I[1], O[1], &vbd);
+            CP_E(I[1], O[0], &vbc);
+#undef CP_E
+            d2[2 * ti] = cp_tri2(&vac, &vad, &vbd);
+            d2[2 * ti + 1] = cp_tri2(&vac, &vbd, &vbc);
+        }
+    }
+}
+
+/* offset of cell coordinate c from voxel coordinate x on an axis of extent e
+ * (whole periodic axis when ring: the image in [-floor(e/2), ceil(e/2) - 1]) */
+static int cp_offset(int c, int x, int e, int ring) {
+    int o = c - x;
+    if (ring) {
+        if (o < -(e / 2)) o += e;
+        else if (o >= e - e / 2) o -= e;
+    }
+    return o;
+}
+
+/* The closest piece of every box voxel with |phi| < tube, by brute force over
+ * all cells of the box: d2 (-1 outside the tube or when the box has no
+ * piece), cell (linear index of the lower node), piece. */
+static void closest_pieces(int dim, const int *n, const int *e, const double *phi, double tube, double *d2o,
+                           long *cello, int *pieceo) {
+    int ring[3] = {0, 0, 0}, ce[3] = {1, 1, 1};
+    for (int a = 0; a < dim; a++) {
+        ring[a] = e[a] == n[a];
+        ce[a] = ring[a] ? e[a] : e[a] - 1;  /* cells per axis */
+    }
+    const int nc = 1 << dim;
+    long m = nvox(e);
+    for (long v = 0; v < m; v++) {
+        d2o[v] = -1.0;
+        cello[v] = -1;
+        pieceo[v] = -1;
+    }
+    if (ce[0] < 1 || ce[1] < 1 || ce[2] < 1) return;
+    /* the cells the zero set crosses, in increasing linear index, with their node values */
+    long ncell = (long)ce[0] * ce[1] * ce[2], nx = 0;
+    int *xc = (int *)malloc(sizeof(int) * 3 * ncell);
+    double *xf = (double *)malloc(sizeof(double) * 8 * ncell);
+    for (int cz = 0; cz < ce[2]; cz++)
+        for (int cy = 0; cy < ce[1]; cy++)
+            for (int cx = 0; cx < ce[0]; cx++) {
+                int c[3] = {cx, cy, cz}, pos = 0, neg = 0;
+                double *f = xf + 8 * nx;
+                for (int b = 0; b < nc; b++) {
+                    int g[3];
+                    for (int a = 0; a < 3; a++) {
+                        g[a] = c[a] + ((b >> a) & 1);
+                        if (g[a] >= e[a]) g[a] -= e[a]; /* ring axes only */
+                    }
+                    f[b] = phi[lidx(e, g[0], g[1], g[2])];
+                    if (f[b] > 0.0) pos++;
+                    else neg++;
+                }
+                if (!pos || !neg) continue;
+                for (int a = 0; a < 3; a++) xc[3 * nx + a] = c[a];
+                nx++;
+            }
+#pragma omp parallel for schedule(dynamic)
+    for (int z = 0; z < e[2]; z++)
+        for (int y = 0; y < e[1]; y++)
+            for (int x = 0; x < e[0]; x++) {
+                long v = lidx(e, x, y, z);
+                if (!(fabs(phi[v]) < tube)) continue;
+                int xv[3] = {x, y, z};
+                double best = -1.0;
+                long bc = -1;
+                int bp = -1;
+                for (long i = 0; i < nx; i++) { /* cells and pieces in increasing order: the first wins ties */
+                    const int *c = xc + 3 * i;
+                    int o[3] = {0, 0, 0};
+                    for (int a = 0; a < dim; a++) o[a] = cp_offset(c[a], xv[a], e[a], ring[a]);
+                    double d2[12];
+                    cp_cell(dim, o, xf + 8 * i, d2);
+                    for (int pc = 0; pc < 12; pc++) {
+                        if (d2[pc] < 0.0) continue;
+                        if (best < 0.0 || d2[pc] < best) {
+                            best = d2[pc];
+                            bc = lidx(e, c[0], c[1], c[2]);
+                            bp = pc;
+                        }
+                    }
+                }
+                d2o[v] = best;
+                cello[v] = bc;
+                pieceo[v] = bp;
+            }
+    free(xc);
+    free(xf);
+}
+
+/* weight of a piece of grain k in the cell with lower node `cell` (linear
+ * box index): mean of w(k, j) over the distinct ID-field entries j >= 0 at
+ * the cell's nodes, in increasing j; 1 with none */
+static double cell_weight(const orc_sim *s, int k, const int *e, long cell) {
+    int dim = s->dim, nc = 1 << dim;
+    int c[3] = {(int)(cell % e[0]), (int)((cell / e[0]) % e[1]), (int)(cell / ((long)e[0] * e[1]))};
+    int js[8], nj = 0;
+    for (int b = 0; b < nc; b++) {
+        int g[3];
+        for (int a = 0; a < 3; a++) {
+            g[a] = c[a] + ((b >> a) & 1);
+            if (g[a] >= e[a]) g[a] -= e[a];
+        }
+        int j = s->iota[k][lidx(e, g[0], g[1], g[2])];
+        if (j < 0) continue;
+        int seen = 0;
+        for (int i = 0; i < nj; i++) seen |= js[i] == j;
+        if (!seen) js[nj++] = j;
+    }
+    if (!nj) return 1.0;
+    for (int i = 1; i < nj; i++) /* increasing j */
+        for (int q = i; q > 0 && js[q - 1] > js[q]; q--) {
+            int t = js[q];
+            js[q] = js[q - 1];
+            js[q - 1] = t;
+        }
+    double sum = 0.0;
+    for (int i = 0; i < nj; i++)
+        sum += orc_pair_weight(orc_misorientation_deg(&s->quat[4 * k], &s->quat[4 * js[i]]), s->theta_c, NULL);
+    return sum / (double)nj;
+}
+
+/* The correction weight of every voxel of grain k's box for the next step:
+ * the closest piece's weight inside the tube, the pair (k, iota) outside
+ * (1 where iota < 0); out[v] also on extinct-free boxes only. */
+static void closest_weight_map(const orc_sim *s, int k, double *w) {
+    const int *e = &s->ext[3 * k];
+    long m = nvox(e);
+    double *d2 = (double *)malloc(sizeof(double) * m);
+    long *cell = (long *)malloc(sizeof(long) * m);
+    int *piece = (int *)malloc(sizeof(int) * m);
+    closest_pieces(s->dim, s->n, e, s->phi[k], s->cp_tube, d2, cell, piece);
+    for (long v = 0; v < m; v++) {
+        if (d2[v] >= 0.0) {
+            w[v] = cell_weight(s, k, e, cell[v]);
+        } else {
+            int j = s->iota[k][v];
+            w[v] = j >= 0 ? orc_pair_weight(orc_misorientation_deg(&s->quat[4 * k], &s->quat[4 * j]), s->theta_c, NULL)
+                          : 1.0;
+        }
+    }
+    free(d2);
+    free(cell);
+    free(piece);
+}
+
+int orc_set_closest_point(orc_sim *s, int on, double tube) {
+    if (!s || (on && !(tube > 0.0))) return -1;
+    s->closest = on != 0;
+    s->cp_tube = tube;
+    return 0;
+}
+
+int orc_closest_weights(const orc_sim *s, int k, double *out, int64_t cap) {
+    if (!s || k < 0 || k >= s->G || !out || !(s->mode & 1)) return -1;
+    if (!s->alive[k]) return 0;
+    if (nvox(&s->ext[3 * k]) > cap) return -1;
+    closest_weight_map(s, k, out);
+    return 1;
+}
+
+int orc_closest_box(int dim, const int32_t n[3], const int32_t ext[3], const double *phi, double tube,
+                    double *d2, int64_t *cell, int32_t *piece) {
+    if (!valid_grid(dim, n) || !phi || !d2 || !cell || !piece) return -1;
+    int nn[3] = {n[0], n[1], n[2]}, e[3] = {ext[0], ext[1], ext[2]};
+    for (int a = 0; a < 3; a++)
+        if (e[a] < 1 || e[a] > nn[a]) return -1;
+    long m = nvox(e);
+    long *c = (long *)malloc(sizeof(long) * m);
+    int *p = (int *)malloc(sizeof(int) * m);
+    closest_pieces(dim, nn, e, phi, tube, d2, c, p);
+    for (long v = 0; v < m; v++) {
+        cell[v] = c[v];
+        piece[v] = p[v];
+    }
+    free(c);
+    free(p);
+    return 0;
+}
+
 /* --------------------------------------------------------------- lifecycle */
 
 int orc_num_threads(void) {
@@ -547,7 +915,7 @@ orc_sim *orc_create(int dim, const int32_t n[3], double band, const int32_t *lab
         unsigned char *o = occ + (size_t)k * ntot_axis;
         int ok = 1, off = 0;
         for (int a = 0; a < 3; a++) {
-            int st, ln;
+            int st = 0, ln = 0;
             if (!cyclic_cover(o + off, n[a], &st, &ln)) {
                 ok = 0;
                 break;
@@ -706,6 +1074,11 @@ int orc_step(orc_sim *s, double dt) {
         psi[k] = (double *)malloc(sizeof(double) * m);
         predictor_box(dim, n, W, e, s->phi[k], psi[k], taps, R);
         if (s->mode) {
+            double *wcp = NULL;
+            if (s->closest && (s->mode & 1)) {
+                wcp = (double *)malloc(sizeof(double) * m);
+                closest_weight_map(s, k, wcp);
+            }
             for (long v = 0; v < m; v++) {
                 int j = s->iota[k][v];
                 double w = 1.0, mob = 1.0, b = 0.0;
@@ -716,12 +1089,14 @@ int orc_step(orc_sim *s, double dt) {
                     }
                     if (s->mode & 2) b = mob * (s->energy[j] - s->energy[k]) * bulk_scale;
                 }
+                if (wcp) w = wcp[v]; /* closest boundary point: the weight only */
                 double p = s->phi[k][v];
                 double d = p + w * (psi[k][v] - p) + b;
                 if (d > W) d = W;
                 if (d < -W) d = -W;
                 psi[k][v] = d;
             }
+            free(wcp);
         }
     }
 
@@ -792,7 +1167,7 @@ int orc_step(orc_sim *s, double dt) {
         }
         int nlo[3], ne[3];
         for (int a = 0; a < 3; a++) {
-            int st, ln;
+            int st = 0, ln = 0;
             if (occ[a]) {
                 cyclic_cover(occ[a], n[a], &st, &ln);
                 st = wrapi((long)olo[a] + st, n[a]);
@@ -1111,7 +1486,7 @@ int orc_coarsen(orc_sim *s, const int32_t np_in[3]) {
         if (any) {
             nalive[k] = 1;
             for (int a = 0; a < 3; a++) {
-                int st, ln;
+                int st = 0, ln = 0;
                 cyclic_cover(occ[a], np[a], &st, &ln);
                 pad_interval(st, ln, s->P, np[a], &nlo[3 * k + a], &next[3 * k + a]);
             }

@@ -39,6 +39,17 @@ int orc_set_physics(orc_sim *s, int mode, const double *quat, double theta_c_deg
  * upwind update in Jacobi form from gradient-normalised reference values). */
 int orc_set_redistance(orc_sim *s, int mode);
 
+/* Closest grain-boundary point (sec. 3.2, with the correction of sec. 2.1.4):
+ * with on != 0 and the misorientation weights on, every voxel with |phi| <
+ * tube takes its correction weight from the closest piece of the linearised
+ * zero level set of its grain (simplices cut along each cell's main diagonal;
+ * the piece's weight is the mean pair weight over the distinct ID-field
+ * entries at its cell's nodes); other voxels keep the ID-field pair. */
+int orc_set_closest_point(orc_sim *s, int on, double tube);
+/* The weight map the next step's correction uses for grain k (needs mode bit
+ * 1); returns 1, 0 if extinct, -1 on error. */
+int orc_closest_weights(const orc_sim *s, int k, double *out, int64_t cap);
+
 /* Grid coarsening (sec. 3, sequential optimizations): project every grain onto
  * the coarser periodic grid np (same ratio r = n / np >= 1 on every axis of the
  * model, each axis >= 4P + 2) by trilinear interpolation at old position i' r,
@@ -85,6 +96,11 @@ int orc_euclid_sweeps(int dim, double band);   /* Jacobi sweeps of the Euclidean
 int orc_coarse_sample_box(int dim, const int32_t n[3], const int32_t np[3], double band, const int32_t lo[3],
                           const int32_t ext[3], const double *f, const int32_t nlo[3], const int32_t next[3],
                           double *out);
+/* Closest piece of every voxel of a stand-alone box with |phi| < tube (the
+ * box may take a whole periodic axis): squared distance (-1 outside the tube),
+ * cell (linear box index of its lower node) and piece index. */
+int orc_closest_box(int dim, const int32_t n[3], const int32_t ext[3], const double *phi, double tube,
+                    double *d2, int64_t *cell, int32_t *piece);
 double orc_misorientation_deg(const double qa[4], const double qb[4]);
 double orc_pair_weight(double theta_deg, double theta_c_deg, double *mobility);
 int orc_num_threads(void);

@@ -73,6 +73,10 @@ def load_library():
     lib.orc_misorientation_deg.argtypes = [_f64p, _f64p]
     lib.orc_pair_weight.restype = C.c_double
     lib.orc_pair_weight.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_double)]
+    lib.orc_set_closest_point.argtypes = [C.c_void_p, C.c_int, C.c_double]
+    lib.orc_closest_weights.argtypes = [C.c_void_p, C.c_int, _f64p, C.c_int64]
+    lib.orc_closest_box.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_double, _f64p,
+                                    np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS"), _i32p]
     lib.orc_num_threads.restype = C.c_int
     lib.orc_set_num_threads.argtypes = [C.c_int]
     del i32_3
@@ -128,6 +132,22 @@ class Oracle:
         if rc != 0:
             raise ValueError("oracle rejected the physics inputs")
         self._keep_q, self._keep_e = q, e
+
+    def set_closest_point(self, on=True, tube=2.0):
+        """Correction weights from the closest grain-boundary point inside the
+        tube |phi| < tube (sec. 3.2); needs the misorientation weights."""
+        if self._lib.orc_set_closest_point(self._p, int(bool(on)), float(tube)) != 0:
+            raise ValueError("bad closest-point arguments")
+
+    def closest_weights(self, k):
+        """The correction weight map of grain k for the next step (box shape)."""
+        alive, lo, ext = self.box(k)
+        if not alive:
+            return None
+        out = np.empty(int(np.prod(ext)), np.float64)
+        if self._lib.orc_closest_weights(self._p, int(k), out, out.size) != 1:
+            raise ValueError("closest weights need the misorientation weights")
+        return out.reshape(_shape(ext))
 
     def set_redistance(self, mode):
         """0: the paper's taxicab spreading; 1: Euclidean fast sweeping (steps after this call)."""
@@ -263,6 +283,25 @@ def redistance_box(f, band, n, dim=None, euclid=False):
     if fn(dim, nn, float(band), np.zeros(3, np.int32), ext, f.ravel(), out.ravel()) != 0:
         raise ValueError("bad arguments")
     return out
+
+
+def closest_box(f, n, tube, dim=None):
+    """Closest piece of the linearised zero level set of one box field f (shape
+    (ez, ey, ex)) for every voxel with |f| < tube: (d2, cell, piece), d2 = -1
+    elsewhere.  A box axis equal to the grid's wraps around."""
+    lib = load_library()
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    if f.ndim == 2:
+        f = f[None]
+    nn = _grid(n)
+    dim = dim or (2 if nn[2] == 1 else 3)
+    ext = np.array([f.shape[2], f.shape[1], f.shape[0]], np.int32)
+    d2 = np.empty(f.shape, np.float64)
+    cell = np.empty(f.shape, np.int64)
+    piece = np.empty(f.shape, np.int32)
+    if lib.orc_closest_box(dim, nn, ext, f.ravel(), float(tube), d2.ravel(), cell.ravel(), piece.ravel()) != 0:
+        raise ValueError("bad arguments")
+    return d2, cell, piece
 
 
 def coarse_sample_box(f, band, n, n_new, lo, new_lo, new_ext, dim=None):
