@@ -105,7 +105,8 @@ def run_gpu(cfg, precision, steps, warmup, redistance="taxicab", batched=True, o
         _, v = sim.values()
         s = 4 if precision == "fp32" else 8
         out["copy_probe"] = dict(kernel="k_convert", values=int(v.size), read_bytes=int(v.size) * s,
-                                 write_bytes=int(v.size) * 8)
+                                 write_bytes=int(v.size) * 8, steps_all=warmup + steps,
+                                 grain_voxels_all=int(st["total_grain_voxels"]))
     sim.close()
     return out
 
@@ -258,7 +259,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--precision", default=None, help="fp32 (mixed) or fp64 (plain)")
-    ap.add_argument("--no-plain", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain-launch runs (FP32 and the FP64 comparison)")
     ap.add_argument("--no-profile", action="store_true", help="skip the profiled per-kernel run")
     ap.add_argument("--order-id", action="store_true",
                     help="per-grain kernels in grain-id order (default: largest box first)")
@@ -317,10 +319,11 @@ def main():
         line["roofline"] = roofline(kt, s_bytes, physics, sweeps, workload, precision)
         log(f"[bench] {precision} per kernel: " + json.dumps({k: dict(ms=round(v["ms"], 3), launches=v["launches"])
                                                               for k, v in kt.items()}))
-    plain32 = run_gpu(cfg, precision, args.steps, args.warmup, redistance=args.redistance, batched=False,
-                      order_size=not args.order_id)
-    line["plain_launches"] = dict(value=plain32["value"], ms_per_step=plain32["ms_per_step"],
-                                  batched_speedup=main_res["value"] / plain32["value"])
+    if not args.no_plain:
+        plain32 = run_gpu(cfg, precision, args.steps, args.warmup, redistance=args.redistance, batched=False,
+                          order_size=not args.order_id)
+        line["plain_launches"] = dict(value=plain32["value"], ms_per_step=plain32["ms_per_step"],
+                                      batched_speedup=main_res["value"] / plain32["value"])
     if not args.no_plain and precision != "fp64":
         plain = run_gpu(cfg, "fp64", args.steps, args.warmup, redistance=args.redistance, batched=False,
                         order_size=not args.order_id)
