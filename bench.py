@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 SOURCES = [os.path.join(ROOT, "paper_1701_06658_amd", "csrc", f)
-           for f in ("gg_kernels.hpp", "gg_march.hpp", "gg_lib.hip")]
+           for f in ("gg_kernels.hpp", "gg_march.hpp", "gg_closest.hpp", "gg_lib.hip")]
 PROFILES = os.path.join(ROOT, "profiles")
 
 # Algorithmic bytes per grain voxel of one launch, by kernel class, in units of

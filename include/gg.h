@@ -127,10 +127,23 @@ typedef struct {
 
 /* gg_config.flags */
 enum {
-    GG_FLAG_ORDER_ID = 1u   /* launch the per-grain kernels in grain-id order
+    GG_FLAG_ORDER_ID = 1u,  /* launch the per-grain kernels in grain-id order
                                (the default is largest box first, which keeps
                                the longest boxes off the end of each launch);
                                results do not depend on the order               */
+    GG_FLAG_CLOSEST_POINT = 2u /* correction weight from the closest point of
+                               the grain boundary (sec. 3.2, with the
+                               correction of sec. 2.1.4; needs
+                               GG_PHYS_MISORIENTATION): every voxel with
+                               |phi| < 2 takes the weight of the closest piece
+                               of its grain's linearised zero level set (cells
+                               cut along the main diagonal into triangles /
+                               tetrahedra; a piece's weight is the mean pair
+                               weight over the distinct ID-field entries at
+                               its cell's nodes: boundary or junction; ties to
+                               the lowest cell, then piece); other voxels keep
+                               the ID-field pair.  Adds a pass that finishes
+                               phi (3D) and the search to every step      */
 };
 
 typedef struct {
@@ -237,7 +250,8 @@ enum {
     GG_K_REINIT_SWEEP = 3, /* Jacobi sweeps of GG_REDIST_EUCLID                   */
     GG_K_PLAN = 4,      /* box plan, scans, coverage lists, launch order, step
                            counters; coarsening                                   */
-    GG_K_CLASSES = 5
+    GG_K_CLOSEST = 5,   /* closest-boundary-point weights (GG_FLAG_CLOSEST_POINT) */
+    GG_K_CLASSES = 6
 };
 typedef struct {
     double ms[GG_K_CLASSES];          /* summed device time (HIP events)            */
@@ -331,7 +345,9 @@ gg_status gg_load(gg_sim *sim, const char *path);
 /* Test hook: when on, each step keeps its predictor output (which = 0) and its
  * corrector output (which = 1) on the box layout the step started from; read
  * them with gg_get_intermediate (same packing as gg_get_values, with the boxes
- * of that layout written to lo/ext/alive/offset when not NULL). */
+ * of that layout written to lo/ext/alive/offset when not NULL).  which = 2
+ * (GG_FLAG_CLOSEST_POINT, no keeping needed): the correction weights of the
+ * current state's next predictor, on the current boxes. */
 gg_status gg_keep_intermediates(gg_sim *sim, int32_t on);
 gg_status gg_get_intermediate(gg_sim *sim, int32_t which, double *out, int64_t cap, int32_t *lo,
                               int32_t *ext, int32_t *alive, int64_t *offset, int64_t cap_grains);

@@ -10,6 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "gg_lib.hip")
 DEPS = [SRC, os.path.join(HERE, "csrc", "gg_kernels.hpp"), os.path.join(HERE, "csrc", "gg_march.hpp"),
+        os.path.join(HERE, "csrc", "gg_closest.hpp"),
         os.path.join(ROOT, "include", "gg.h")]
 LIB = os.path.join(HERE, "libgg.so")
 

@@ -290,6 +290,7 @@ template <typename T> struct Physics {
     T bulk_scale;       // sigma^2 h / (2 gamma_max): voxels per (J/m^3) and step
     const T *phi;       // the step's input function (same layout as psi)
     const int *iota;    // ID-field of the previous corrector (same layout)
+    const T *wcp;       // per-voxel correction weights (same layout), or NULL: the pair (k, iota)
 };
 
 template <typename T> __device__ inline T dev_acos(T c);

@@ -27,6 +27,7 @@
 #include "../../include/gg.h"
 #include "gg_kernels.hpp"
 #include "gg_march.hpp"
+#include "gg_closest.hpp"
 
 // Corrector tile of the 3D grid (powers of two, 512 voxels).
 #ifndef GG_CMP_TILE_X
@@ -176,6 +177,7 @@ template <typename T> struct Sim final : SimBase {
     bool exact = false;  // capacities without slack
     bool batched;
     int order_size;  // per-grain kernels take the largest boxes first
+    bool closest = false;  // correction weights from the closest boundary point (A_SCR)
     int tdim[3], nt[3], ntiles, occ_words;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -340,6 +342,7 @@ template <typename T> struct Sim final : SimBase {
         exact = c.capacity_headroom == 1.0;
         batched = c.batched != 0;
         order_size = (c.flags & GG_FLAG_ORDER_ID) ? 0 : 1;
+        closest = (c.flags & GG_FLAG_CLOSEST_POINT) != 0;
         set_tiles();
         occ_words = (std::max(n[0], std::max(n[1], n[2])) + 31) / 32;
         if (s) {
@@ -486,7 +489,7 @@ template <typename T> struct Sim final : SimBase {
     long long grow_to(long long need) const {
         return exact ? std::max<long long>(need, 1) : (long long)((double)need * headroom) + 1024;
     }
-    int n_arenas() const { return redist == GG_REDIST_EUCLID ? 4 : 3; }
+    int n_arenas() const { return (redist == GG_REDIST_EUCLID || closest) ? 4 : 3; }
 
     // Grow a buffer to `bytes`, keeping its first `keep_bytes`.
     void grow_keep(DBuf &b, size_t bytes, size_t keep_bytes) {
@@ -644,6 +647,7 @@ template <typename T> struct Sim final : SimBase {
         ph.bulk_scale = (physics & 2) ? (T)(sigma * sigma * voxel_m / (2.0 * gamma_max)) : T(0);
         ph.phi = nullptr;
         ph.iota = iota_p;
+        ph.wcp = nullptr;
         return ph;
     }
 
@@ -655,6 +659,7 @@ template <typename T> struct Sim final : SimBase {
         ma.K = K;
         ma.R = R;
         ma.order = (in_step && order_size) ? order_d.as<int>() : nullptr;
+        ma.phi_always = 0;
         ma.ctl = in_step ? ctl() : nullptr;
         return ma;
     }
@@ -681,9 +686,12 @@ template <typename T> struct Sim final : SimBase {
 
     // Predictor march on layout l: in (f when chain, else a final function) ->
     // psi (when given) with the correction epilogue, phi (when given), volumes.
-    void launch_predict(int l, T *in, int chain, T *psi, T *phi_out, const int *iota_l, bool in_step) {
-        const gg::MarchArgs ma = march_args(in_step);
-        const gg::Physics<T> ph = physics_args(iota_l);
+    void launch_predict(int l, T *in, int chain, T *psi, T *phi_out, const int *iota_l, bool in_step,
+                        const T *wcp = nullptr, bool phi_always = false) {
+        gg::MarchArgs ma = march_args(in_step);
+        ma.phi_always = phi_always ? 1 : 0;
+        gg::Physics<T> ph = physics_args(iota_l);
+        ph.wcp = wcp;
         double *v = dim == 3 ? vol.as<double>() : nullptr;
         const int Rk = psi ? R : 8;
         tbegin(GG_K_PREDICT, in_step ? 0 : tot[l].arena, in_step ? 2 : 0);
@@ -859,8 +867,30 @@ template <typename T> struct Sim final : SimBase {
 
     // psi of the current layout from the state in A_F.
     void predict_state() {
-        launch_predict(cur, arena[A_F].as<T>(), f_chain, arena[A_PSI].as<T>(), nullptr, iota_of(iota_cur), false);
+        const T *wcp = closest_weights(cur, f_chain, iota_of(iota_cur), false);
+        launch_predict(cur, arena[A_F].as<T>(), f_chain, arena[A_PSI].as<T>(), nullptr, iota_of(iota_cur), false, wcp);
         psi_ok = true;
+    }
+
+    // Correction weights from the closest boundary point (sec. 3.2) of layout l
+    // into A_SCR, from the layout's function (A_F; with a pending z chain,
+    // finished into A_PHIC first) and ID-field; NULL when the mode is off.
+    const T *closest_weights(int l, int chain, const int *iota_l, bool in_step) {
+        if (!closest) return nullptr;
+        const T *phi_src = arena[A_F].as<T>();
+        if (chain) {
+            launch_predict(l, arena[A_F].as<T>(), chain, nullptr, arena[A_PHIC].as<T>(), nullptr, in_step, nullptr,
+                           true);
+            phi_src = arena[A_PHIC].as<T>();
+        }
+        tbegin(GG_K_CLOSEST, in_step ? 0 : tot[l].arena, in_step ? 2 : 0);
+        hipLaunchKernelGGL(gg::k_closest_weight<T>, dim3(G), dim3(gg::kBlock), 0, stream, boxes_of(l), phi_src,
+                           iota_l, physics_args(iota_l), arena[A_SCR].as<T>(), grid_args(),
+                           (const int *)((in_step && order_size) ? order_d.as<int>() : nullptr),
+                           in_step ? (const Ctl *)ctl() : (const Ctl *)nullptr);
+        tend();
+        HIPCHECK(hipGetLastError());
+        return arena[A_SCR].as<T>();
     }
 
     // The kernels of one step from layout L (ID-field parity ic) to layout
@@ -904,8 +934,9 @@ template <typename T> struct Sim final : SimBase {
             launch_reinit(L, Ln, arena[A_PHIC].as<T>(), arena[A_F].as<T>(), iota_of(ic), iota_w(icn), true);
         }
         const int chain = (dim == 3 && redist != GG_REDIST_EUCLID) ? 1 : 0;
+        const T *wcp = closest_weights(Ln, chain, iota_of(icn), true);
         launch_predict(Ln, arena[A_F].as<T>(), chain, arena[A_PSI].as<T>(),
-                       dim == 3 ? arena[A_PHIC].as<T>() : (T *)nullptr, iota_of(icn), true);
+                       dim == 3 ? arena[A_PHIC].as<T>() : (T *)nullptr, iota_of(icn), true, wcp);
         tbegin(GG_K_PLAN, 0);
         hipLaunchKernelGGL(gg::k_step_end, dim3(1), dim3(1024), 0, stream, c, (const int *)alive[Ln].as<int>(),
                            (const long long *)off[L].as<long long>(), (const long long *)off[Ln].as<long long>(),
@@ -1489,6 +1520,12 @@ template <typename T> struct Sim final : SimBase {
             ensure_phi();
             src = arena[a_phi].as<T>();
             m = tot[cur].arena;
+        } else if (which == 2) {
+            settle();
+            if (!closest) throw ArgError{"closest-point weights need GG_FLAG_CLOSEST_POINT"};
+            if (!psi_ok) predict_state();  // the weights of the state's next correction
+            src = arena[A_SCR].as<T>();
+            m = tot[cur].arena;
         } else {
             settle();
             if (!have_keep) throw ArgError{"no intermediates kept"};
@@ -1737,7 +1774,10 @@ gg_status gg_create(const gg_config *cfg, const int32_t *labels, int32_t n_grain
     if (cfg->redistance != GG_REDIST_TAXICAB && cfg->redistance != GG_REDIST_EUCLID)
         return fail(nullptr, GG_E_ARG, "redistance must be GG_REDIST_TAXICAB or GG_REDIST_EUCLID");
     if (cfg->batched != 0 && cfg->batched != 1) return fail(nullptr, GG_E_ARG, "batched must be 0 or 1");
-    if (cfg->flags & ~(uint32_t)GG_FLAG_ORDER_ID) return fail(nullptr, GG_E_ARG, "unknown flag bits");
+    if (cfg->flags & ~(uint32_t)(GG_FLAG_ORDER_ID | GG_FLAG_CLOSEST_POINT))
+        return fail(nullptr, GG_E_ARG, "unknown flag bits");
+    if ((cfg->flags & GG_FLAG_CLOSEST_POINT) && !(cfg->physics & GG_PHYS_MISORIENTATION))
+        return fail(nullptr, GG_E_ARG, "GG_FLAG_CLOSEST_POINT needs GG_PHYS_MISORIENTATION");
     if ((cfg->physics & GG_PHYS_MISORIENTATION) && (!quat || !(cfg->theta_c_deg > 0.0)))
         return fail(nullptr, GG_E_ARG, "misorientation weights need quat and theta_c_deg > 0");
     if ((cfg->physics & GG_PHYS_BULK) && (!energy_density || !(cfg->voxel_m > 0.0) || !(cfg->gamma_max > 0.0)))
@@ -1996,12 +2036,12 @@ gg_status gg_keep_intermediates(gg_sim *sim, int32_t on) {
 
 gg_status gg_get_intermediate(gg_sim *sim, int32_t which, double *out, int64_t cap, int32_t *lo, int32_t *ext,
                               int32_t *alive, int64_t *offset, int64_t cap_grains) {
-    if (!sim || !out || (which != 0 && which != 1)) return fail(sim, GG_E_ARG, "bad argument");
+    if (!sim || !out || which < 0 || which > 2) return fail(sim, GG_E_ARG, "bad argument");
     if ((lo || ext || alive || offset) && cap_grains < sim->G) return fail(sim, GG_E_SMALLBUF, "cap_grains < n_grains");
     return settled(sim, guarded(sim, [&]() {
                        long long m = sim->impl->values(out, cap, which);
                        if (m < 0) return fail(sim, GG_E_SMALLBUF, "cap too small (" + std::to_string(-m) + ")");
-                       if (lo || ext || alive || offset) sim->impl->boxes(lo, ext, alive, offset, true);
+                       if (lo || ext || alive || offset) sim->impl->boxes(lo, ext, alive, offset, which != 2);
                        return GG_OK;
                    }));
 }

@@ -53,36 +53,37 @@ constexpr int kQX = 4;    // outputs per thread of an in-plane x pass
 // values with y frames of KW rows of +inf (and YB more below).
 template <int KW, int YB> struct ReinitLds {
     int pf, pr, pd, sF, sR, sD, oR, oD, total;
-    __host__ __device__ ReinitLds(int EX, int EY) {
-        pf = (EX + 2) | 1;
-        pr = (EX + 2 * KW + kQX) | 1;
-        pd = EX | 1;
-        sF = pf * (EY + 2);
-        sR = pr * EY;
-        sD = pd * (EY + 2 * KW + YB);
-        oR = 2 * sF;
-        oD = oR + 2 * sR;
-        total = oD + 2 * sD;
-    }
+    __host__ __device__ constexpr ReinitLds(int EX, int EY)
+        : pf((EX + 2) | 1), pr((EX + 2 * KW + kQX) | 1), pd(EX | 1), sF(pf * (EY + 2)), sR(pr * EY),
+          sD(pd * (EY + 2 * KW + YB)), oR(2 * sF), oD(oR + 2 * sR), total(oD + 2 * sD) {}
 };
 // Predictor: Cz, the z-convolved plane with x frames of RM cells of -W (and kQX
 // more on the right); Cx, the x-convolved plane with y frames of RM rows of -W
 // (and YB more below).
 template <int RM, int YB> struct PredictLds {
     int pz, px, sZ, sX, oX, total;
-    __host__ __device__ PredictLds(int EX, int EY) {
-        pz = (EX + 2 * RM + kQX) | 1;
-        px = EX | 1;
-        sZ = pz * EY;
-        sX = px * (EY + 2 * RM + YB);
-        oX = 2 * sZ;
-        total = oX + 2 * sX;
-    }
+    __host__ __device__ constexpr PredictLds(int EX, int EY)
+        : pz((EX + 2 * RM + kQX) | 1), px(EX | 1), sZ(pz * EY), sX(px * (EY + 2 * RM + YB)), oX(2 * sZ),
+          total(oX + 2 * sX) {}
 };
 
 // LDS cells a march kernel may use (its dynamic allocation).
-template <typename T> constexpr int reinit_cells() { return sizeof(T) == 8 ? 12288 : 16384; }
+template <typename T> constexpr int reinit_cells() { return sizeof(T) == 8 ? 13312 : 16384; }
 template <typename T> constexpr int predict_cells() { return sizeof(T) == 8 ? 8192 : 12288; }
+
+// Every box has a tiling: the smallest extended tile (one interior cell and
+// halos of the largest reach on both sides of both axes) fits the group's
+// column units and each kernel's LDS.
+constexpr int kReinitMinTile = 2 * (kMaxBand + 1) + 1;
+constexpr int kPredictMinTile = 2 * kMaxRadius + 1;
+static_assert(ReinitLds<kMaxBand, 4>(kReinitMinTile, kReinitMinTile).total <= reinit_cells<double>() &&
+                  ReinitLds<kMaxBand, 4>(kReinitMinTile, kReinitMinTile).total <= reinit_cells<float>(),
+              "re-initialization LDS too small for the largest band");
+static_assert(PredictLds<kMaxRadius, 2>(kPredictMinTile, kPredictMinTile).total <= predict_cells<double>() &&
+                  PredictLds<kMaxRadius, 2>(kPredictMinTile, kPredictMinTile).total <= predict_cells<float>(),
+              "predictor LDS too small for the largest radius");
+static_assert(4 * (kMT / kReinitMinTile) >= kReinitMinTile && 2 * (kMT / kPredictMinTile) >= kPredictMinTile,
+              "too few threads per group for the smallest tiles");
 
 struct MarchArgs {
     int n[3];
@@ -92,6 +93,7 @@ struct MarchArgs {
     int R;              // Gaussian radius (k_predict_march)
     const int *order;   // grain processed by each block (NULL: block index)
     const Ctl *ctl;     // NULL outside the step sequence
+    int phi_always;     // k_predict_march: write phi at every step of a batch
 };
 
 // Tiling of a box cross-section (x, y) for a march group.
@@ -453,9 +455,11 @@ __global__ void __launch_bounds__(kMT)
 // ------------------------------------------------------ k_predict_march (a1, a2)
 
 // d^p = phi + w (psi - phi) + mob (E_j - E_k) * bulk_scale, clamped to [-W, W],
-// for a cell whose ID-field entry is j and whose function value is p.
+// for a cell whose ID-field entry is j and whose function value is p; w from
+// the pair (k, j), or wc when wc >= 0 (closest-boundary-point weights).
 template <typename T>
-__device__ inline T correct_prediction_v(const Physics<T> &ph, int k, int j, T p, T psi, T W, PairCache<T> &pc) {
+__device__ inline T correct_prediction_v(const Physics<T> &ph, int k, int j, T p, T psi, T W, PairCache<T> &pc,
+                                         T wc) {
     if (j != pc.j) {
         pc.j = j;
         pc.w = 1;
@@ -469,7 +473,7 @@ __device__ inline T correct_prediction_v(const Physics<T> &ph, int k, int j, T p
             if (ph.mode & 2) pc.b = mob * (ph.energy[j] - ph.energy[k]) * ph.bulk_scale;
         }
     }
-    T d = p + pc.w * (psi - p) + pc.b;
+    T d = p + (wc >= T(0) ? wc : pc.w) * (psi - p) + pc.b;
     d = d > W ? W : d;
     d = d < -W ? -W : d;
     return d;
@@ -534,13 +538,15 @@ __global__ void __launch_bounds__(kMT)
     }
     const int R = RS ? RS : ma.R;
     const bool want_psi = psi != nullptr;
-    const bool write_phi = phi_out != nullptr && (ma.ctl == nullptr || ma.ctl->steps == ma.ctl->phi_at);
+    const bool write_phi =
+        phi_out != nullptr && (ma.ctl == nullptr || ma.phi_always || ma.ctl->steps == ma.ctl->phi_at);
     const int ex = L.ext[3 * k], ey = L.ext[3 * k + 1], ez = d3 ? L.ext[3 * k + 2] : 1;
     const int plane = ex * ey;  // box volumes are below 2^31
     T *f = in + L.off[k];
     T *pp = want_psi ? psi + L.off[k] : nullptr;
     T *po = write_phi ? phi_out + L.off[k] : nullptr;
     const int *io = PH ? ph.iota + L.off[k] : nullptr;
+    const T *wcb = (PH && ph.wcp) ? ph.wcp + L.off[k] : nullptr;
     T tp[NW];
 #pragma unroll
     for (int t = 0; t < NW; ++t) tp[t] = (want_psi && t <= 2 * R) ? taps[t] : T(0);
@@ -556,7 +562,7 @@ __global__ void __launch_bounds__(kMT)
             if (!c.rint[j]) continue;
             const int idx = q * plane + c.by[j] * ex + c.bx;
             T val = acc[j];
-            if constexpr (PH) val = correct_prediction_v<T>(ph, k, io[idx], phv[j], val, W, pc);
+            if constexpr (PH) val = correct_prediction_v<T>(ph, k, io[idx], phv[j], val, W, pc, wcb ? wcb[idx] : T(-1));
             pp[idx] = val;
         }
     };

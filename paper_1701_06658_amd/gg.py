@@ -28,8 +28,9 @@ EXPORTS = ["gg_create", "gg_step", "gg_sync", "gg_grain_count", "gg_grain_volume
            "gg_destroy", "gg_version", "gg_profile", "gg_get_kernel_times", "gg_coarsen", "gg_grain_areas",
            "gg_grain_sdf", "gg_save", "gg_load", "gg_autotune"]
 
-KERNEL_CLASSES = ["predict", "compare", "reinit", "reinit_sweep", "plan"]
+KERNEL_CLASSES = ["predict", "compare", "reinit", "reinit_sweep", "plan", "closest"]
 FLAG_ORDER_ID = 1
+FLAG_CLOSEST_POINT = 2
 
 
 class GGError(RuntimeError):
@@ -74,7 +75,7 @@ def torch_allocator():
 
 
 class KernelTimes(C.Structure):
-    _fields_ = [("ms", C.c_double * 5), ("launches", C.c_int64 * 5), ("voxels", C.c_int64 * 5)]
+    _fields_ = [("ms", C.c_double * 6), ("launches", C.c_int64 * 6), ("voxels", C.c_int64 * 6)]
 
 
 class Tuning(C.Structure):
@@ -152,11 +153,14 @@ class Simulation:
     allocator, on `stream` or torch's current stream) or an Allocator.
     batched: gg_step queues captured HIP graphs and returns without waiting.
     order_size: per-grain kernels take the largest boxes first (False: grain-id order).
+    closest_point: correction weights from the closest grain-boundary point in
+    the tube |phi| < 2 (needs physics with the misorientation weights).
     """
 
     def __init__(self, labels, band, G=None, precision="fp64", physics=0, quat=None,
                  theta_c_deg=15.0, energy=None, voxel_m=0.0, gamma_max=0.0, stream=None,
-                 headroom=0.0, redistance="taxicab", allocator=None, batched=False, order_size=True):
+                 headroom=0.0, redistance="taxicab", allocator=None, batched=False, order_size=True,
+                 closest_point=False):
         lib = load_library()
         labels = np.ascontiguousarray(labels, dtype=np.int32)
         if labels.ndim == 2:
@@ -177,7 +181,7 @@ class Simulation:
         cfg.capacity_headroom = float(headroom)
         cfg.redistance = {"taxicab": GG_REDIST_TAXICAB, "euclid": GG_REDIST_EUCLID}[redistance]
         cfg.batched = 1 if batched else 0
-        cfg.flags = 0 if order_size else FLAG_ORDER_ID
+        cfg.flags = (0 if order_size else FLAG_ORDER_ID) | (FLAG_CLOSEST_POINT if closest_point else 0)
         q = None if quat is None else np.ascontiguousarray(quat, dtype=np.float64)
         e = None if energy is None else np.ascontiguousarray(energy, dtype=np.float64)
         if allocator == "torch":
@@ -318,6 +322,11 @@ class Simulation:
         self._check(self._lib.gg_get_iota(self._h, _ptr(out), out.size))
         return b, out[:m]
 
+    def closest_weights(self):
+        """Correction weights of the next predictor (closest_point mode): per-grain
+        dict like state(), the weights in place of phi."""
+        return self.intermediate(2)
+
     def state(self):
         """Per-grain dict like the oracle's: alive, lo, ext, phi (list of (ez, ey, ex) arrays)."""
         b, v = self.values()
@@ -341,7 +350,9 @@ class Simulation:
         self._check(self._lib.gg_keep_intermediates(self._h, int(bool(on))))
 
     def intermediate(self, which):
-        """which 0: predictor output, 1: corrector output, on the step's starting boxes."""
+        """which 0: predictor output, 1: corrector output, on the step's starting
+        boxes; 2: the closest-point correction weights of the next predictor, on
+        the current boxes."""
         lo = np.zeros((self.G, 3), np.int32)
         ext = np.zeros((self.G, 3), np.int32)
         alive = np.zeros(self.G, np.int32)

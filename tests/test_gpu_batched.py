@@ -90,6 +90,51 @@ def test_growing_grain_forces_retakes():
     _check(o, s, W, "bulk growth, exact buffers")
 
 
+def growing_disk(dim=2, N=64, r0=10.45, push=1.0, sigma=1.5):
+    """A disk (ball) grain 1 in a matrix grain 0 whose bulk energy density is
+    higher: the bulk term moves the boundary outward by about `push` voxels a
+    step, so grain 1's box grows within a few steps while the matrix keeps its
+    whole-axis box: the layout's total volume grows.  Returns labels, the GPU
+    and oracle physics arguments and dt."""
+    n = (N,) * dim
+    c = (N - 1) / 2.0
+    g = np.meshgrid(*[np.arange(N)] * dim, indexing="ij")
+    r2 = sum((x - c) ** 2 for x in g)
+    labels = (r2 < r0 ** 2).astype(np.int32)
+    if dim == 2:
+        labels = labels[None]
+    h, gam = 2.0e-5, 0.3
+    scale = sigma ** 2 * h / (2 * gam)            # voxels per (J/m^3) and step
+    energy = np.array([push / scale, 0.0])
+    gpu = dict(physics=2, energy=energy, voxel_m=h, gamma_max=gam)
+    orc = dict(mode=2, energy=energy, h_phys=h, gamma_max=gam)
+    return labels, gpu, orc, config_dt(sigma, N)
+
+
+@pytest.mark.parametrize("dim,batched", [(2, False), (2, True), (3, True)])
+def test_growing_disk_forces_retakes(dim, batched):
+    # exact buffers: the steps whose layout outgrows them fail their capacity
+    # check and are taken again after the buffers grow; the results equal the
+    # plain run with headroom and the oracle
+    import paper_1701_06658_amd as gg
+    labels, gphys, ophys, dt = growing_disk(dim, N=64 if dim == 2 else 40, r0=10.45 if dim == 2 else 7.45)
+    W = 6.0
+    a = gg.Simulation(labels, W, G=2, precision="fp64", headroom=1.0, batched=batched, **gphys)
+    b = gg.Simulation(labels, W, G=2, precision="fp64", **gphys)
+    o = Oracle(labels, W, G=2)
+    o.set_physics(**ophys)
+    cap0 = a.stats()["capacity"]
+    a.step(dt, 6)
+    b.step(dt, 6)
+    o.step(dt, 6)
+    cap1 = a.stats()["capacity"]
+    print(f"[growing disk {dim}D batched={batched}] capacity {cap0} -> {cap1}", flush=True)
+    assert cap1 > cap0                               # the retake path ran
+    assert a.stats()["steps"] == 6
+    _same(a.state(), b.state())
+    _check(o, a, W, f"growing disk {dim}D")
+
+
 def test_order_size_changes_no_value():
     c = make_config(2, N=64, G=125)
     a = _sim(c, "fp32", batched=True, order_size=True)
