@@ -225,6 +225,24 @@ gg_status gg_grain_volumes(gg_sim *sim, double *out, int64_t cap);
  * sum_k E_k V_k h^D.  Host arrays, cap >= n_grains (0 for extinct grains). */
 gg_status gg_grain_areas(gg_sim *sim, double *area, double *weighted, int64_t cap);
 
+/* gg_grain_areas for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and summation order, so the same values, written into device memory
+ * of the simulation's device (area_dev, weighted_dev: cap >= n_grains doubles
+ * each; weighted_dev may be NULL), ordered on the simulation's stream; the call
+ * does not wait for the write.  It allocates nothing: the per-block partial
+ * sums go to a static device array of the library (partials of at most 65536
+ * grains, 8 MiB on every device the library runs on, held until the process
+ * ends).  Every call on one device shares that array: calls whose streams
+ * overlap on one device (different simulations, different streams) race on
+ * it.  Queued batched steps are taken over only if none of them failed its
+ * capacity check; otherwise the call returns GG_E_CAPACITY, writes nothing and
+ * leaves the steps queued (gg_sync, which may allocate, takes them again).
+ * Errors: GG_E_ARG (NULL area_dev), GG_E_SMALLBUF, GG_E_CAPACITY (n_grains >
+ * 65536, or a queued step that needs larger buffers), GG_E_UNSUPPORTED
+ * (device index above 63). */
+gg_status gg_grain_areas_noalloc(gg_sim *sim, double *area_dev, double *weighted_dev, int64_t cap);
+
 /* Voxel labels (the tessellation the grains define, sec. 2.1.1: a voxel belongs
  * to the grain whose function is largest there, i.e. inside its zero level
  * set): argmax over the grains whose box covers the voxel of their function

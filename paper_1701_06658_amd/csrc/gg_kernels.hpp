@@ -1208,13 +1208,16 @@ __global__ void __launch_bounds__(kBlock)
     if (threadIdx.x == 0) part[((long long)aa.G + k) * aa.split + blockIdx.y] = s1;
 }
 
-// out[i] = sum of the `split` partials of row i, in order (rows: 2G).
-__global__ void k_sum_rows(const double *__restrict__ part, double *__restrict__ out, int rows, int split) {
+// Sum of the `split` partials of row i, in order, for the 2G rows of k_areas:
+// rows [0, G) into out0, rows [G, 2G) into out1 (skipped when out1 is NULL).
+__global__ void k_sum_rows(const double *__restrict__ part, double *__restrict__ out0, double *__restrict__ out1,
+                           int G, int split) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= rows) return;
+    if (i >= 2 * G || (i >= G && !out1)) return;
     double s = 0.0;
     for (int j = 0; j < split; ++j) s += part[(long long)i * split + j];
-    out[i] = s;
+    if (i < G) out0[i] = s;
+    else out1[i - G] = s;
 }
 
 template <typename T>

@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <type_traits>
@@ -35,6 +36,17 @@
 #define GG_CMP_TILE_Y 8
 #define GG_CMP_TILE_Z 4
 #endif
+
+// Partial sums per grain of the interface areas (blocks per grain box).
+constexpr int kAreaSplit = 8;
+
+// Device scratch of gg_grain_areas_noalloc: the per-block partial sums of the
+// interface areas for up to kNoAllocMaxGrains grains (8 MiB on every device the
+// library runs on, held until the process ends).  Host code reaches it only
+// through the device address taken once per device at set-up (g_scratch).
+constexpr int kNoAllocMaxGrains = 65536;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) double scratch[2 * kAreaSplit * kNoAllocMaxGrains];
 
 namespace {
 
@@ -149,6 +161,7 @@ struct SimBase {
                             const int32_t *iota) = 0;
     virtual void coarsen(const int32_t *np) = 0;
     virtual void areas(double *area, double *weighted) = 0;
+    virtual bool areas_noalloc(double *part, double *area, double *weighted) = 0;
     virtual long long grain_sdf(int k, int32_t *lo, int32_t *ext, double *out, long long cap) = 0;
     virtual void save(FILE *f) = 0;
     virtual void load(FILE *f) = 0;
@@ -1232,28 +1245,52 @@ template <typename T> struct Sim final : SimBase {
     }
 
     // Interface areas of the current phi (FP64 per-grain sums, fixed order).
-    void areas(double *area, double *weighted) override {
-        ensure_phi();
-        const int split = 8;
-        DBuf part, sums;
-        part.ensure(sizeof(double) * 2 * (size_t)G * split);
-        sums.ensure(sizeof(double) * 2 * (size_t)G);
+    // k_areas into `part` (2 G kAreaSplit doubles), then the per-grain sums into
+    // area_out and weighted_out (NULL: not written), ordered on the stream.
+    void areas_launch(double *part, double *area_out, double *weighted_out) {
         gg::AreaArgs aa;
         aa.mode = physics;
         aa.theta_c_deg = theta_c;
-        aa.split = split;
+        aa.split = kAreaSplit;
         aa.G = G;
-        hipLaunchKernelGGL(gg::k_areas<T>, dim3(G, split), dim3(gg::kBlock), 0, stream, boxes_of(cur),
-                           (const T *)arena[a_phi].as<T>(), iota_of(iota_cur), (const T *)quat_d.as<T>(), aa,
-                           part.as<double>(), W, grid_args());
-        hipLaunchKernelGGL(gg::k_sum_rows, dim3((2 * G + 255) / 256), dim3(256), 0, stream, part.as<double>(),
-                           sums.as<double>(), 2 * G, split);
+        hipLaunchKernelGGL(gg::k_areas<T>, dim3(G, kAreaSplit), dim3(gg::kBlock), 0, stream, boxes_of(cur),
+                           (const T *)arena[a_phi].as<T>(), iota_of(iota_cur), (const T *)quat_d.as<T>(), aa, part,
+                           W, grid_args());
+        hipLaunchKernelGGL(gg::k_sum_rows, dim3((2 * G + 255) / 256), dim3(256), 0, stream, (const double *)part,
+                           area_out, weighted_out, G, kAreaSplit);
         HIPCHECK(hipGetLastError());
+    }
+    void areas(double *area, double *weighted) override {
+        ensure_phi();
+        DBuf part, sums;
+        part.ensure(sizeof(double) * 2 * (size_t)G * kAreaSplit);
+        sums.ensure(sizeof(double) * 2 * (size_t)G);
+        areas_launch(part.as<double>(), sums.as<double>(), sums.as<double>() + G);
         std::vector<double> h(2 * (size_t)G);
         HIPCHECK(hipMemcpyAsync(h.data(), sums.p, sizeof(double) * 2 * G, hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipStreamSynchronize(stream));
         std::memcpy(area, h.data(), sizeof(double) * G);
         if (weighted) std::memcpy(weighted, h.data() + G, sizeof(double) * G);
+    }
+    // The same launches with the caller's partial-sum memory and device outputs,
+    // allocating nothing: queued steps are taken over only when none of them
+    // failed its capacity check (false: one did; it stays queued, and the next
+    // other call grows the buffers and takes it again), and no timing spans are
+    // recorded (they take events).
+    bool areas_noalloc(double *part, double *area, double *weighted) override {
+        if (pending) {
+            HIPCHECK(hipMemcpyAsync(ctl_h, ctl_d.p, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+            HIPCHECK(hipStreamSynchronize(stream));
+            if (ctl_h->fail) return false;
+        }
+        struct ProfOff {
+            bool &p, was;
+            explicit ProfOff(bool &q) : p(q), was(q) { p = false; }
+            ~ProfOff() { p = was; }
+        } off(prof);
+        ensure_phi();
+        areas_launch(part, area, weighted);
+        return true;
     }
 
     // One grain's box and values (as doubles); returns the value count, or
@@ -1675,6 +1712,28 @@ namespace {
 
 thread_local std::string g_create_error;
 
+// Device address of `scratch` on each device, taken once per device at set-up.
+std::mutex g_scratch_mu;
+double *g_scratch[kScratchDevices] = {};
+
+// With `dev` current: take the device address of the scratch array (once).
+hipError_t scratch_setup(int dev) {
+    if (dev < 0 || dev >= kScratchDevices) return hipSuccess;  // no no-alloc calls there
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[dev]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = static_cast<double *>(p);
+    return hipSuccess;
+}
+
+double *scratch_of(int dev) {
+    if (dev < 0 || dev >= kScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch[dev];
+}
+
 gg_status fail(gg_sim *s, gg_status st, const std::string &msg) {
     if (s) {
         s->err = msg;
@@ -1819,6 +1878,13 @@ gg_status gg_create(const gg_config *cfg, const int32_t *labels, int32_t n_grain
     if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(nullptr, GG_E_NODEVICE, "device query failed");
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(nullptr, GG_E_NODEVICE, std::string("device is ") + prop.gcnArchName + ", not gfx950");
+    {
+        const hipError_t e = scratch_setup(dev);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(nullptr, GG_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+    }
     s->stream = hip_stream;
     AllocScope scope(s.get());
     try {
@@ -1941,6 +2007,21 @@ gg_status gg_grain_areas(gg_sim *sim, double *area, double *weighted, int64_t ca
                        sim->impl->areas(area, weighted);
                        return GG_OK;
                    }));
+}
+
+gg_status gg_grain_areas_noalloc(gg_sim *sim, double *area_dev, double *weighted_dev, int64_t cap) {
+    if (!sim || !area_dev) return fail(sim, GG_E_ARG, "NULL argument");
+    if (cap < sim->G) return fail(sim, GG_E_SMALLBUF, "cap < n_grains");
+    if (sim->G > kNoAllocMaxGrains)
+        return fail(sim, GG_E_CAPACITY, "n_grains exceeds the 65536 grains of the no-alloc scratch");
+    double *part = scratch_of(sim->device);
+    if (!part) return fail(sim, GG_E_UNSUPPORTED, "no no-alloc scratch on this device (index >= 64)");
+    return guarded(sim, [&]() {
+        if (!sim->impl->areas_noalloc(part, area_dev, weighted_dev))
+            return fail(sim, GG_E_CAPACITY,
+                        "a queued step awaits a retake with larger buffers: call gg_sync first");
+        return GG_OK;
+    });
 }
 
 gg_status gg_grain_sdf(gg_sim *sim, int32_t id, int32_t lo[3], int32_t ext[3], double *out, int64_t cap) {

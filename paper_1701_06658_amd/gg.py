@@ -26,7 +26,7 @@ EXPORTS = ["gg_create", "gg_step", "gg_sync", "gg_grain_count", "gg_grain_volume
            "gg_stats", "gg_get_boxes", "gg_get_values", "gg_get_iota", "gg_load_state",
            "gg_keep_intermediates", "gg_get_intermediate", "gg_status_str", "gg_last_error",
            "gg_destroy", "gg_version", "gg_profile", "gg_get_kernel_times", "gg_coarsen", "gg_grain_areas",
-           "gg_grain_sdf", "gg_save", "gg_load", "gg_autotune"]
+           "gg_grain_sdf", "gg_save", "gg_load", "gg_autotune", "gg_grain_areas_noalloc"]
 
 KERNEL_CLASSES = ["predict", "compare", "reinit", "reinit_sweep", "plan", "closest"]
 FLAG_ORDER_ID = 1
@@ -118,6 +118,7 @@ def load_library(path=LIB_PATH):
         "gg_load_state": (i32, [vp, vp, vp, vp, vp, vp]),
         "gg_coarsen": (i32, [vp, vp]),
         "gg_grain_areas": (i32, [vp, vp, vp, i64]),
+        "gg_grain_areas_noalloc": (i32, [vp, vp, vp, i64]),
         "gg_grain_sdf": (i32, [vp, i32, vp, vp, vp, i64]),
         "gg_autotune": (i32, [vp, dbl, i32, C.POINTER(Tuning)]),
         "gg_save": (i32, [vp, C.c_char_p]),
@@ -255,6 +256,15 @@ class Simulation:
         w = np.zeros(self.G, np.float64)
         self._check(self._lib.gg_grain_areas(self._h, _ptr(a), _ptr(w), self.G))
         return a, w
+
+    def areas_noalloc(self, area_dev, weighted_dev=None):
+        """gg_grain_areas_noalloc: the areas written into device buffers (objects
+        with data_ptr() and numel(), e.g. torch tensors of float64 on the
+        simulation's device); stream-ordered, the call does not wait."""
+        cap = area_dev.numel() if weighted_dev is None else min(area_dev.numel(), weighted_dev.numel())
+        self._check(self._lib.gg_grain_areas_noalloc(
+            self._h, C.c_void_p(area_dev.data_ptr()),
+            C.c_void_p(weighted_dev.data_ptr()) if weighted_dev is not None else None, cap))
 
     def coarsen(self, n_new):
         """Project the state onto the coarser periodic grid n_new = (nx, ny, nz) (nz = 1 in 2D)."""
