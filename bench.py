@@ -36,6 +36,8 @@ PROFILES = os.path.join(ROOT, "profiles")
 # it is this design's, not the method's).
 ALG_BYTES = {"predict": (2, 0), "compare": (2, 0), "reinit": (2, 0)}
 ALG_BYTES_PHYS = {"predict": (2, 4), "compare": (2, 4), "reinit": (2, 0)}
+# closest-point weights: read phi and the ID-field, write the weight
+ALG_BYTES_CLOSEST = (2, 4)
 
 
 def log(*a):
@@ -65,10 +67,13 @@ def _phys(cfg):
     return {}
 
 
+CLOSEST = False  # --closest-point: correction weights from the closest boundary point
+
+
 def make_sim(cfg, precision, redistance, batched, order_size=True):
     import paper_1701_06658_amd as gg
     return gg.Simulation(cfg["labels"], cfg["W"], G=cfg["G"], precision=precision, redistance=redistance,
-                         batched=batched, order_size=order_size, **_phys(cfg))
+                         batched=batched, order_size=order_size, closest_point=CLOSEST, **_phys(cfg))
 
 
 def run_gpu(cfg, precision, steps, warmup, redistance="taxicab", batched=True, order_size=True,
@@ -156,10 +161,35 @@ def recorded_traffic(kernel, precision, workload):
         return None
 
 
+def recorded_error_vs_oracle(precision="fp32"):
+    """The mixed path's error against the FP64 oracle over trajectories, per
+    result (first divergence step, largest band |dphi|, ownership mismatch
+    share, worst volume error, alive-count difference), from the committed
+    summary profiles/error_vs_oracle_<precision>.md of the GPU test
+    tests/test_gpu_mixed_trajectory.py; source_match tells whether it was
+    taken from the current kernel sources.  None when there is no summary."""
+    path = os.path.join(PROFILES, f"error_vs_oracle_{precision}.md")
+    if not os.path.exists(path):
+        return None
+    work, digest = {}, None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- source_sha256:"):
+                digest = line.split(":", 1)[1].strip().strip("`")
+            elif line.startswith("- {"):
+                rec = json.loads(line[2:])
+                rec.pop("per_step", None)
+                work[rec.pop("workload")] = rec
+    return dict(workloads=work, source_match=digest == source_digest(),
+                test="tests/test_gpu_mixed_trajectory.py")
+
+
 def roofline(kt, s_bytes, physics, sweeps=0, workload=None, precision=None):
     """Per-kernel achieved GB/s of algorithmic bytes (HIP-event span times)
     and the dominant kernel's roofline entry."""
     table = dict(ALG_BYTES_PHYS if physics else ALG_BYTES)
+    if CLOSEST:
+        table["closest"] = ALG_BYTES_CLOSEST
     if sweeps:
         # each Jacobi sweep of the Euclidean variant reads and writes every value
         # once; one timed span holds all sweeps of a step
@@ -221,33 +251,36 @@ print(json.dumps(e0.elapsed_time(e1) / {reps}))
     return dict(GBs=2.0 * nbytes / (ms * 1e-3) / 1e9, bytes=nbytes, kind="PyTorch device-to-device copy")
 
 
-def cpu_baseline(index, threads=None):
-    """FP64 oracle on a bounded sample: one step of a density-matched cut of the
-    workload (128^3 on all host threads; 64^3 on one thread)."""
+def cpu_baseline(index, threads=None, steps=None):
+    """FP64 oracle on a bounded sample: `steps` steps (4 on all host threads, 3
+    on one) of a density-matched cut of the workload (128^3 on all host
+    threads; 64^3 on one thread), about 10 s of host time on the GPU machine."""
     from oracle import ORACLE_CFLAGS, Oracle, num_threads, set_num_threads
     from synth import make_config
     N = None if index == 1 else (64 if threads == 1 else 128)
     G = None if index == 1 else int(round({2: 1000, 3: 1000, 4: 781, 5: 781}[index] * (N / 128) ** 3))
+    steps = steps or (3 if threads == 1 else 4)
     all_threads = num_threads()
     if threads:
         set_num_threads(threads)
     try:
         c = make_config(index, N=N, G=G)
         o = Oracle(c["labels"], c["W"], G=c["G"])
-        gv = 0
-        for k in range(c["G"]):
-            alive, lo, ext = o.box(k)
-            if alive:
-                gv += int(ext[0]) * int(ext[1]) * int(ext[2])
         used = num_threads()
-        t0 = time.perf_counter()
-        o.step(c["dt"])
-        dt = time.perf_counter() - t0
+        gv, dt = 0, 0.0
+        for _ in range(steps):
+            for k in range(c["G"]):
+                alive, lo, ext = o.box(k)
+                if alive:
+                    gv += int(ext[0]) * int(ext[1]) * int(ext[2])
+            t0 = time.perf_counter()
+            o.step(c["dt"])
+            dt += time.perf_counter() - t0
         o.close()
     finally:
         set_num_threads(all_threads)
     return dict(value=gv / dt, unit="grain-voxel updates/s", cores=used, kind="oracle",
-                sample=f"1 FP64 oracle step of a density-matched {c['N']}^{c['dim']} cut with "
+                sample=f"{steps} FP64 oracle steps of a density-matched {c['N']}^{c['dim']} cut with "
                        f"{c['G']} grains of workload {index} ({gv} grain voxels, {dt:.2f} s); "
                        f"gcc {' '.join(ORACLE_CFLAGS)}")
 
@@ -268,6 +301,9 @@ def main():
                     help="choose the launch schedule with gg_autotune before the warm-up steps")
     ap.add_argument("--redistance", default="taxicab", choices=["taxicab", "euclid"],
                     help="re-initialization scheme: the method's taxicab one or the Euclidean variant")
+    ap.add_argument("--closest-point", action="store_true",
+                    help="correction weights from the closest grain-boundary point (workloads with the "
+                         "misorientation weights: --config 4)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-copy", action="store_true", help="skip the streaming-copy measurement")
     ap.add_argument("--copy-probe", action="store_true",
@@ -278,6 +314,8 @@ def main():
         print("bench.py runs on one GPU only: the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     from synth import make_config
+    global CLOSEST
+    CLOSEST = args.closest_point
     t0 = time.perf_counter()
     cfg = make_config(args.config)
     log(f"[bench] inputs {cfg['name']}: {cfg['G']} grains in {time.perf_counter() - t0:.1f} s")
@@ -287,7 +325,7 @@ def main():
                        order_size=not args.order_id, autotune=args.autotune, copy_probe=args.copy_probe)
     s_bytes = 4 if precision == "fp32" else 8
     workload = ("3d256_8000g" if args.config == 3 else f"config{args.config}") + (
-        "_euclid" if args.redistance == "euclid" else "")
+        "_euclid" if args.redistance == "euclid" else "") + ("_closest" if CLOSEST else "")
     bpg = step_alg_bytes(s_bytes, physics)
     line = {
         "metric": "grain-voxel updates/s per step (mixed batched vs FP64 plain) + %HBM roofline",
@@ -305,7 +343,7 @@ def main():
         "config": {"workload": cfg["name"], "grid": list(cfg["n"]), "grains": cfg["G"],
                    "sigma_voxels": cfg["sigma"], "band_voxels": cfg["W"],
                    "precision": precision, "redistance": args.redistance, "batched": True,
-                   "order_size": not args.order_id, "alive_after": main_res["alive"],
+                   "order_size": not args.order_id, "closest_point": CLOSEST, "alive_after": main_res["alive"],
                    "superposition": round(main_res["superposition"], 3)},
         "step_roofline": {"alg_bytes_per_gv": bpg, "achieved": main_res["value"] * bpg / 1e9,
                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -336,6 +374,8 @@ def main():
             line["plain_fp64"]["roofline"] = roofline(kt64, 8, physics, sweeps, workload, "fp64")
     if args.autotune:
         line["tuning"] = main_res["tuned"]
+    if precision == "fp32":
+        line["error_vs_oracle"] = recorded_error_vs_oracle("fp32")
     if args.copy_probe:
         line["copy_probe"] = main_res["copy_probe"]
     if not args.no_copy:

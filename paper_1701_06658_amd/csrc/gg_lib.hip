@@ -30,7 +30,15 @@
 #include "gg_march.hpp"
 #include "gg_closest.hpp"
 
-// Corrector tile of the 3D grid (powers of two, 512 voxels).
+// Rows per column unit of the FP64 predictor march.
+#ifndef GG_PREDICT_YB64
+#define GG_PREDICT_YB64 2
+#endif
+
+// Corrector tile of the 3D grid (powers of two, 512 voxels).  Rows of 16 FP32
+// values write half cache lines of each box row; 8-wide rows (a cube, the
+// fewest covering boxes per voxel) were 2% faster but wrote 2.1x the bytes,
+// 32- and 64-wide rows cover more boxes per voxel and were 23-80% slower.
 #ifndef GG_CMP_TILE_X
 #define GG_CMP_TILE_X 16
 #define GG_CMP_TILE_Y 8
@@ -690,9 +698,21 @@ template <typename T> struct Sim final : SimBase {
             hipLaunchKernelGGL(kern, dim3(G), dim3(gg::kMT), lds, stream, boxes_of(lo_l), boxes_of(ln_l), ma, phic,
                                out, io_old, io_new, v, W);
         };
-        if (K == 8) go(gg::k_reinit_march<T, 8, 4>);
-        else if (K == 6) go(gg::k_reinit_march<T, 6, 4>);
-        else go(gg::k_reinit_march<T, 0, 4>);
+        constexpr int YB = gg::kReinitYB;
+        auto pick = [&](auto ks) {
+            constexpr int KS = decltype(ks)::value;
+            const bool io = io_new != nullptr && io_old != nullptr;
+            if (dim == 3) {
+                if (io) go(gg::k_reinit_march<T, KS, YB, true, true>);
+                else go(gg::k_reinit_march<T, KS, YB, true, false>);
+            } else {
+                if (io) go(gg::k_reinit_march<T, KS, YB, false, true>);
+                else go(gg::k_reinit_march<T, KS, YB, false, false>);
+            }
+        };
+        if (K == 8) pick(std::integral_constant<int, 8>{});
+        else if (K == 6) pick(std::integral_constant<int, 6>{});
+        else pick(std::integral_constant<int, 0>{});
         tend();
         HIPCHECK(hipGetLastError());
     }
@@ -715,12 +735,15 @@ template <typename T> struct Sim final : SimBase {
                                (const T *)taps_d.as<T>(), ph, W, chain);
         };
         const bool phys = physics != 0 && psi != nullptr;
+        // rows per column unit: FP64 keeps its register window (2R + 1 planes of
+        // YB rows) small enough not to spill
+        constexpr int YB = sizeof(T) == 8 ? GG_PREDICT_YB64 : 4;
         if (Rk == 8) {
-            if (phys) go(gg::k_predict_march<T, 8, 4, true>, 4);
-            else go(gg::k_predict_march<T, 8, 4, false>, 4);
+            if (phys) go(gg::k_predict_march<T, 8, YB, true>, YB);
+            else go(gg::k_predict_march<T, 8, YB, false>, YB);
         } else if (Rk == 6) {
-            if (phys) go(gg::k_predict_march<T, 6, 4, true>, 4);
-            else go(gg::k_predict_march<T, 6, 4, false>, 4);
+            if (phys) go(gg::k_predict_march<T, 6, YB, true>, YB);
+            else go(gg::k_predict_march<T, 6, YB, false>, YB);
         } else {
             if (phys) go(gg::k_predict_march<T, 0, 2, true>, 2);
             else go(gg::k_predict_march<T, 0, 2, false>, 2);

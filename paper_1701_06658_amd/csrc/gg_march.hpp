@@ -36,7 +36,39 @@ namespace gg {
 #define GG_MT 512
 #endif
 constexpr int kMT = GG_MT;  // threads per march group
-constexpr int kQX = 4;    // outputs per thread of an in-plane x pass
+#ifndef GG_REINIT_QX
+#define GG_REINIT_QX 8
+#endif
+#ifndef GG_PREDICT_QX
+#define GG_PREDICT_QX 4
+#endif
+#ifndef GG_REINIT_YB
+#define GG_REINIT_YB 4
+#endif
+constexpr int kQXR = GG_REINIT_QX;   // outputs per thread of the re-initialization's x spreading
+constexpr int kQXP = GG_PREDICT_QX;  // outputs per thread of the predictor's x pass
+constexpr int kReinitYB = GG_REINIT_YB;  // rows per column unit of the re-initialization
+
+// The row units (kQ consecutive cells of one row) a thread takes in a tile of
+// EY rows: unit r = threadIdx.x + i kMT has row r % EY and x block r / EY,
+// stepped without division.
+struct RowWalk {
+    int ry, xq, dq, dr;
+    __device__ explicit RowWalk(int EY) {
+        ry = (int)threadIdx.x % EY;
+        xq = (int)threadIdx.x / EY;
+        dq = kMT / EY;
+        dr = kMT - dq * EY;
+    }
+    __device__ void next(int EY) {
+        ry += dr;
+        xq += dq;
+        if (ry >= EY) {
+            ry -= EY;
+            ++xq;
+        }
+    }
+};
 
 // LDS layouts of the march kernels for an extended tile of EX x EY cells.
 // Every in-plane window pass reads from a buffer whose frame (wide enough for
@@ -49,21 +81,21 @@ constexpr int kQX = 4;    // outputs per thread of an in-plane x pass
 // plane separates the stages.
 //
 // Re-initialization: F, phi^c with a one-cell frame of -W; Rf, reference values
-// with x frames of KW cells of +inf (and kQX more on the right); Dx, the x-spread
+// with x frames of KW cells of +inf (and kQXR more on the right); Dx, the x-spread
 // values with y frames of KW rows of +inf (and YB more below).
 template <int KW, int YB> struct ReinitLds {
     int pf, pr, pd, sF, sR, sD, oR, oD, total;
     __host__ __device__ constexpr ReinitLds(int EX, int EY)
-        : pf((EX + 2) | 1), pr((EX + 2 * KW + kQX) | 1), pd(EX | 1), sF(pf * (EY + 2)), sR(pr * EY),
+        : pf((EX + 2) | 1), pr((EX + 2 * KW + kQXR) | 1), pd(EX | 1), sF(pf * (EY + 2)), sR(pr * EY),
           sD(pd * (EY + 2 * KW + YB)), oR(2 * sF), oD(oR + 2 * sR), total(oD + 2 * sD) {}
 };
-// Predictor: Cz, the z-convolved plane with x frames of RM cells of -W (and kQX
+// Predictor: Cz, the z-convolved plane with x frames of RM cells of -W (and kQXP
 // more on the right); Cx, the x-convolved plane with y frames of RM rows of -W
 // (and YB more below).
 template <int RM, int YB> struct PredictLds {
     int pz, px, sZ, sX, oX, total;
     __host__ __device__ constexpr PredictLds(int EX, int EY)
-        : pz((EX + 2 * RM + kQX) | 1), px(EX | 1), sZ(pz * EY), sX(px * (EY + 2 * RM + YB)), oX(2 * sZ),
+        : pz((EX + 2 * RM + kQXP) | 1), px(EX | 1), sZ(pz * EY), sX(px * (EY + 2 * RM + YB)), oX(2 * sZ),
           total(oX + 2 * sX) {}
 };
 
@@ -76,13 +108,13 @@ template <typename T> constexpr int predict_cells() { return sizeof(T) == 8 ? 81
 // column units and each kernel's LDS.
 constexpr int kReinitMinTile = 2 * (kMaxBand + 1) + 1;
 constexpr int kPredictMinTile = 2 * kMaxRadius + 1;
-static_assert(ReinitLds<kMaxBand, 4>(kReinitMinTile, kReinitMinTile).total <= reinit_cells<double>() &&
-                  ReinitLds<kMaxBand, 4>(kReinitMinTile, kReinitMinTile).total <= reinit_cells<float>(),
+static_assert(ReinitLds<kMaxBand, kReinitYB>(kReinitMinTile, kReinitMinTile).total <= reinit_cells<double>() &&
+                  ReinitLds<kMaxBand, kReinitYB>(kReinitMinTile, kReinitMinTile).total <= reinit_cells<float>(),
               "re-initialization LDS too small for the largest band");
 static_assert(PredictLds<kMaxRadius, 2>(kPredictMinTile, kPredictMinTile).total <= predict_cells<double>() &&
                   PredictLds<kMaxRadius, 2>(kPredictMinTile, kPredictMinTile).total <= predict_cells<float>(),
               "predictor LDS too small for the largest radius");
-static_assert(4 * (kMT / kReinitMinTile) >= kReinitMinTile && 2 * (kMT / kPredictMinTile) >= kPredictMinTile,
+static_assert(kReinitYB * (kMT / kReinitMinTile) >= kReinitMinTile && 2 * (kMT / kPredictMinTile) >= kPredictMinTile,
               "too few threads per group for the smallest tiles");
 
 struct MarchArgs {
@@ -247,8 +279,9 @@ __device__ inline MCol<YB> march_col(const MTile &tl, int ex, int ey, int N0, in
 // windowed chains inside each plane, forward spreading along z.  3D: writes the
 // partially spread distance with the inside flag as its sign bit; 2D: writes
 // phi = +-min(d, W) and the grain's volume.  Carries the ID-field over to the
-// new layout.  KS: static reach (0: runtime ma.K <= kMaxBand).
-template <typename T, int KS, int YB>
+// new layout.  KS: static reach (0: runtime ma.K <= kMaxBand); D3: a 3D grid;
+// IO: the ID-field is carried (iota_old and iota_new given).
+template <typename T, int KS, int YB, bool D3, bool IO>
 __global__ void __launch_bounds__(kMT)
     k_reinit_march(Boxes Lo, Boxes Ln, MarchArgs ma, const T *__restrict__ phic, T *__restrict__ out,
                    const int *__restrict__ iota_old, int *__restrict__ iota_new, double *__restrict__ vol, T W) {
@@ -259,7 +292,7 @@ __global__ void __launch_bounds__(kMT)
     __shared__ double red[kMT / 64];
     if (ctl_failed(ma.ctl) || (int)blockIdx.x >= ma.G) return;
     const int k = ma.order ? ma.order[blockIdx.x] : (int)blockIdx.x;
-    const bool d3 = ma.dim == 3;
+    constexpr bool d3 = D3;
     if (!Ln.alive[k]) {
         if (!d3 && vol && threadIdx.x == 0) vol[k] = 0.0;
         return;
@@ -275,8 +308,8 @@ __global__ void __launch_bounds__(kMT)
     }
     const T *src = phic + Lo.off[k];
     T *dst = out + Ln.off[k];
-    const int *io_src = iota_old ? iota_old + Lo.off[k] : nullptr;
-    int *io_dst = iota_new ? iota_new + Ln.off[k] : nullptr;
+    const int *io_src = IO ? iota_old + Lo.off[k] : nullptr;
+    int *io_dst = IO ? iota_new + Ln.off[k] : nullptr;
     const int osz = oe[0] * oe[1];  // box volumes are below 2^31
     const int nplane = ne[0] * ne[1];
     const int ez = d3 ? ne[2] : 1;
@@ -327,7 +360,8 @@ __global__ void __launch_bounds__(kMT)
 #pragma unroll
         for (int j = 0; j < YB; ++j) car[j] = inf;
         unsigned ins = 0;  // inside flags: bit 4 j + (plane & 3)
-        const int nxq = (EX + kQX - 1) / kQX;
+        const int nxq = (EX + kQXR - 1) / kQXR;
+        const RowWalk rw0(EY);
         const int fc = (c.ry0 + 1) * ly.pf + c.cx + 1;  // the unit's first cell in F
         // stages of iteration z: A plane z (phi^c into F), B plane z - 1
         // (reference values into Rf), C plane z - 2 (x spreading into Dx), D and
@@ -374,20 +408,20 @@ __global__ void __launch_bounds__(kMT)
             }
             if (z >= 2 && z - 2 < ez) {
                 // spreading along x (row units, rows fastest across lanes); the
-                // window [x0 - KW, x0 + kQX + KW) reads the +inf frame beyond the tile
+                // window [x0 - KW, x0 + kQXR + KW) reads the +inf frame beyond the tile
                 const T *Rb = sm + ly.oR + ((z - 2) & 1) * ly.sR;
                 T *Db = sm + ly.oD + ((z - 2) & 1) * ly.sD;
-                for (int r = threadIdx.x; r < EY * nxq; r += kMT) {
-                    const int ry = r % EY, x0 = (r / EY) * kQX;
+                for (RowWalk rw = rw0; rw.xq < nxq; rw.next(EY)) {
+                    const int ry = rw.ry, x0 = rw.xq * kQXR;
                     const T *row = Rb + ry * ly.pr + x0;
-                    T v[kQX + 2 * KW];
+                    T v[kQXR + 2 * KW];
 #pragma unroll
-                    for (int i = 0; i < kQX + 2 * KW; ++i) v[i] = row[i];
-                    T o[kQX];
-                    taxicab_chains<T, kQX + 2 * KW, KW, kQX>(v, o);
+                    for (int i = 0; i < kQXR + 2 * KW; ++i) v[i] = row[i];
+                    T o[kQXR];
+                    taxicab_chains<T, kQXR + 2 * KW, KW, kQXR>(v, o);
                     T *drow = Db + (ry + KW) * ly.pd + x0;
 #pragma unroll
-                    for (int q = 0; q < kQX; ++q)
+                    for (int q = 0; q < kQXR; ++q)
                         if (x0 + q < EX) drow[q] = o[q];
                 }
             }
@@ -417,7 +451,7 @@ __global__ void __launch_bounds__(kMT)
                         cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
                         vsum += cl;
                     }
-                    if (io_dst) io_dst[idx] = (po >= 0 && orow[j] >= 0) ? io_src[po + orow[j]] : -1;
+                    if constexpr (IO) io_dst[idx] = (po >= 0 && orow[j] >= 0) ? io_src[po + orow[j]] : -1;
                 }
             }
 #pragma unroll
@@ -487,18 +521,18 @@ template <typename T, int RM, int YB>
 __device__ __forceinline__ void plane_xy_pass(const T *Cz, T *Cx, const PredictLds<RM, YB> &ly, int EX, int EY,
                                               const MCol<YB> &c, const T *tp, int R, T (&acc)[YB]) {
     __syncthreads();
-    const int nxq = (EX + kQX - 1) / kQX;
+    const int nxq = (EX + kQXP - 1) / kQXP;
     for (int r = threadIdx.x; r < EY * nxq; r += kMT) {
-        const int ry = r % EY, x0 = (r / EY) * kQX;
+        const int ry = r % EY, x0 = (r / EY) * kQXP;
         const T *row = Cz + ry * ly.pz + x0 + (RM - R);
-        T v[kQX + 2 * RM];
+        T v[kQXP + 2 * RM];
 #pragma unroll
-        for (int i = 0; i < kQX + 2 * RM; ++i) v[i] = (i < kQX + 2 * R) ? row[i] : T(0);
-        T o[kQX];
-        gauss_window<T, RM, kQX>(v, tp, R, o);
+        for (int i = 0; i < kQXP + 2 * RM; ++i) v[i] = (i < kQXP + 2 * R) ? row[i] : T(0);
+        T o[kQXP];
+        gauss_window<T, RM, kQXP>(v, tp, R, o);
         T *xrow = Cx + (ry + RM) * ly.px + x0;
 #pragma unroll
-        for (int q = 0; q < kQX; ++q)
+        for (int q = 0; q < kQXP; ++q)
             if (x0 + q < EX) xrow[q] = o[q];
     }
     __syncthreads();
@@ -693,7 +727,7 @@ __global__ void __launch_bounds__(kMT)
 #pragma unroll
                 for (int i = 0; i < NW; ++i) win[i][j] = -W;
             }
-            const int nxq = (EX + kQX - 1) / kQX;
+            const int nxq = (EX + kQXP - 1) / kQXP;
             // stages of the iteration for input plane p (descending): the z pass
             // of plane p + R into Cz, the x pass of plane p + R + 1 (Cz -> Cx), the
             // y pass and output of plane p + R + 2 (from Cx)
@@ -756,16 +790,16 @@ __global__ void __launch_bounds__(kMT)
                     const T *Zb = sm + (qx & 1) * ly.sZ;
                     T *Xb = sm + ly.oX + (qx & 1) * ly.sX;
                     for (int r = threadIdx.x; r < EY * nxq; r += kMT) {
-                        const int ry = r % EY, x0 = (r / EY) * kQX;
+                        const int ry = r % EY, x0 = (r / EY) * kQXP;
                         const T *row = Zb + ry * ly.pz + x0 + (RM - R);
-                        T v[kQX + 2 * RM];
+                        T v[kQXP + 2 * RM];
 #pragma unroll
-                        for (int i = 0; i < kQX + 2 * RM; ++i) v[i] = (i < kQX + 2 * R) ? row[i] : T(0);
-                        T o[kQX];
-                        gauss_window<T, RM, kQX>(v, tp, R, o);
+                        for (int i = 0; i < kQXP + 2 * RM; ++i) v[i] = (i < kQXP + 2 * R) ? row[i] : T(0);
+                        T o[kQXP];
+                        gauss_window<T, RM, kQXP>(v, tp, R, o);
                         T *xrow = Xb + (ry + RM) * ly.px + x0;
 #pragma unroll
-                        for (int q = 0; q < kQX; ++q)
+                        for (int q = 0; q < kQXP; ++q)
                             if (x0 + q < EX) xrow[q] = o[q];
                     }
                 }
@@ -782,7 +816,10 @@ __global__ void __launch_bounds__(kMT)
                         Zb[(c.ry0 + j) * ly.pz + c.cx + RM] = a;
                     }
                 }
-                if (qx <= ez - 1) __syncthreads();
+                // the stages of the next iteration read what this one wrote (the z
+                // stage writes from qz = ez - 1 on, one iteration before the first
+                // x stage reads it), and write what this one read
+                if (qz <= ez - 1) __syncthreads();
             }
         }
     }

@@ -78,3 +78,22 @@ def top2_gap(state, n, W):
     two = np.isfinite(m2)
     gap[two] = m1[two] - m2[two]
     return gap
+
+
+def interface_voxels(state):
+    """Per grain: the voxels whose volume term clamp(phi + 1/2, 0, 1) lies
+    strictly between 0 and 1 (|phi| < 1/2), the only ones where a change of
+    phi changes the grain volume."""
+    out = np.zeros(len(state["alive"]), np.int64)
+    for k in range(len(state["alive"])):
+        if state["alive"][k]:
+            out[k] = int((np.abs(state["phi"][k]) < 0.5).sum())
+    return out
+
+
+def volume_bound(vol, iface, tol_phi):
+    """Allowed |V_a - V_b| per grain between two states whose band values
+    differ by at most tol_phi: each interface voxel moves its volume term by at
+    most tol_phi, so the error is at most tol_phi * iface; grains above 0.5%
+    of their volume per that bound keep the 0.5% relative bar."""
+    return np.maximum(5e-3 * vol, tol_phi * iface)

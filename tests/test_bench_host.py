@@ -1,6 +1,7 @@
 """Host logic of bench.py (no GPU): the one-GPU guard, the roofline arithmetic
 of the dominant kernel, the committed counter figures and their source digest,
 and the Jacobi sweep count of the Euclidean variant."""
+import json
 import math
 import os
 import subprocess
@@ -72,6 +73,19 @@ def test_recorded_traffic_follows_the_sources(monkeypatch, tmp_path):
     assert bench.recorded_traffic("compare", "fp32", "no_such_workload") is None
     monkeypatch.setattr(bench, "source_digest", lambda: "0" * 64)
     assert bench.recorded_traffic("compare", "fp32", "w") is None
+
+
+def test_recorded_error_vs_oracle(monkeypatch, tmp_path):
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
+    assert bench.recorded_error_vs_oracle("fp32") is None
+    rec = dict(workload="config 1", steps=20, first_divergence_step=None, band_max_abs=1e-4, per_step=[{}])
+    (tmp_path / "error_vs_oracle_fp32.md").write_text(
+        f"# summary\n- source_sha256: `{bench.source_digest()}`\n- {json.dumps(rec)}\n")
+    r = bench.recorded_error_vs_oracle("fp32")
+    assert r["source_match"] and r["workloads"]["config 1"] == dict(steps=20, first_divergence_step=None,
+                                                                    band_max_abs=1e-4)
+    monkeypatch.setattr(bench, "source_digest", lambda: "0" * 64)
+    assert not bench.recorded_error_vs_oracle("fp32")["source_match"]
 
 
 def test_committed_traffic_summaries_name_their_figures():

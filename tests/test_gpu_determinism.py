@@ -47,3 +47,27 @@ def test_two_runs_are_bit_identical(precision, redistance, physics):
           flush=True)
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_predictor_output_is_bit_identical(precision):
+    # the predictor's output of every step, box values far from any interface
+    # included (where a wrong value changes no function but may name another
+    # neighbour in the ID-field): equal between two runs, step by step
+    import paper_1701_06658_amd as gg
+    c = make_config(3, N=96, G=400)
+    a = gg.Simulation(c["labels"], c["W"], G=c["G"], precision=precision)
+    b = gg.Simulation(c["labels"], c["W"], G=c["G"], precision=precision)
+    a.keep_intermediates(True)
+    b.keep_intermediates(True)
+    for step in range(1, 5):
+        a.step(c["dt"])
+        b.step(c["dt"])
+        pa, pb = a.intermediate(0), b.intermediate(0)
+        for k in range(c["G"]):
+            assert pa["alive"][k] == pb["alive"][k]
+            if pa["alive"][k]:
+                assert np.array_equal(pa["phi"][k], pb["phi"][k]), (precision, step, k)
+                assert np.all(np.abs(pa["phi"][k]) <= c["W"] * (1 + 1e-6)), (precision, step, k)  # sums of taps round
+    a.close()
+    b.close()

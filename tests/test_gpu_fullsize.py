@@ -78,7 +78,10 @@ def test_sampled_grains_full_workload(index, precision, redistance, before):
               f"box_mismatch {r['box_mismatch']} "
               f"volume {vo[k]:.2f} vs {v1[k]:.2f} ({len(hood)} grains stepped)", flush=True)
         assert r["box_mismatch"] == 0 and r["max_abs"] <= tol
-        assert abs(v1[k] - vo[k]) <= (1e-9 if precision == "fp64" else 5e-3 * max(vo[k], 50.0))
+        # FP32: 0.5%, or what band values within 2e-3 can move (each interface
+        # voxel's volume term by at most that much)
+        iface = int((np.abs(a["phi"][k]) < 0.5).sum())
+        assert abs(v1[k] - vo[k]) <= (1e-9 if precision == "fp64" else max(5e-3 * vo[k], 2e-3 * iface))
     # ownership inside the sampled grains' boxes of the step's start, at the
     # voxels some grain owns (a positive function): that grain's box of the
     # step's start holds the voxel, so it was stepped.  Identical in FP64; in
@@ -189,7 +192,8 @@ def test_sampled_grains_physics_workloads(index):
         print(f"[workload {index} step 2 grain {k}] |dphi| {r['max_abs']:.3e} box_mismatch {r['box_mismatch']} "
               f"volume {vo[k]:.2f} vs {v1[k]:.2f} ({len(hood)} grains stepped)", flush=True)
         assert r["box_mismatch"] == 0 and r["max_abs"] <= 2e-3
-        assert abs(v1[k] - vo[k]) <= 5e-3 * max(vo[k], 50.0)
+        iface = int((np.abs(a["phi"][k]) < 0.5).sum())
+        assert abs(v1[k] - vo[k]) <= max(5e-3 * vo[k], 2e-3 * iface)
 
 
 def test_full_workload_coarsening():
