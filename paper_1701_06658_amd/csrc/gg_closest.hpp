@@ -26,9 +26,12 @@
 //
 // Search per tube voxel: rings of cells around it ([-r-1, r] per axis, r = 0,
 // 1, ...) until a piece is found, then every cell within the found distance
-// (cells whose integer box distance exceeds it are skipped).  On a whole
-// periodic axis a cell is taken at the image whose offset lies in
-// [-floor(e/2), ceil(e/2) - 1], and the search never leaves that range.
+// (cells whose integer box distance exceeds it are skipped, and cells the
+// rings took are not taken again).  On a whole periodic axis a cell is taken at
+// the image whose offset lies in [-floor(e/2), ceil(e/2) - 1], and the search
+// never leaves that range.  A group queues the tube voxels of its box in LDS
+// and searches them a group's width at a time; a cell's node values sit in
+// the thread's LDS column while its simplices are taken in a rolled loop.
 #pragma once
 
 #include "gg_kernels.hpp"
@@ -120,19 +123,6 @@ __device__ inline double cv_tri2(const CVtx &A, const CVtx &B, const CVtx &C) {
     return m;
 }
 
-// crossing vertex on the edge between cell corners bu <= bv (corner bits); o:
-// the cell's lower node relative to the voxel
-__device__ inline CVtx cv_edge(const int o[3], int bu, int bv, const double *f) {
-    CVtx r;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        r.u[a] = o[a] + ((bu >> a) & 1);
-        r.d[a] = ((bv >> a) & 1) - ((bu >> a) & 1);
-    }
-    r.t = f[bu] / (f[bu] - f[bv]);
-    return r;
-}
-
 // The best piece so far: smallest d2, then cell, then piece.
 struct CBest {
     double d2;
@@ -146,70 +136,103 @@ struct CBest {
     }
 };
 
-// Every piece of one cell (lower node at offset o, node values f by corner
-// bits) against the best so far.  Pieces: 2D triangle i -> piece i; 3D
-// tetrahedron i -> piece 2i (and 2i + 1 for a quadrilateral zero set).
+// crossing vertex on the edge between cell corners bu <= bv, node values read
+// from the thread's LDS column f (stride kBlock per corner)
+__device__ inline CVtx cv_edge_l(const int o[3], int bu, int bv, const double *f) {
+    CVtx r;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r.u[a] = o[a] + ((bu >> a) & 1);
+        r.d[a] = ((bv >> a) & 1) - ((bu >> a) & 1);
+    }
+    const double fu = f[bu * kBlock], fv = f[bv * kBlock];
+    r.t = fu / (fu - fv);
+    return r;
+}
+
+__device__ inline CVtx cv_pick(bool s, const CVtx &a, const CVtx &b) {
+    CVtx r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        r.u[i] = s ? a.u[i] : b.u[i];
+        r.d[i] = s ? a.d[i] : b.d[i];
+    }
+    r.t = s ? a.t : b.t;
+    return r;
+}
+
+// Every piece of one cell (lower node at offset o, node values in the
+// thread's LDS column f, by corner bits) against the best so far.  Pieces: 2D
+// triangle i -> piece i; 3D tetrahedron i -> piece 2i (and 2i + 1 for a
+// quadrilateral zero set, cut along the diagonal from its first vertex).  The
+// simplices are taken in a rolled loop: tetrahedron i = (0, e_a, e_a + e_b, 7)
+// with a = i / 2 and b the smaller (i even) or larger (i odd) other axis.
 __device__ inline void cell_pieces(int dim, const int o[3], const double *f, int cell, CBest &best) {
     if (dim == 2) {
-        constexpr int tris[2][3] = {{0, 1, 3}, {0, 2, 3}};
+#pragma unroll 1
         for (int ti = 0; ti < 2; ++ti) {
-            const int *tv = tris[ti];
-            const bool i0 = f[tv[0]] > 0.0, i1 = f[tv[1]] > 0.0, i2 = f[tv[2]] > 0.0;
-            const int nin = (int)i0 + (int)i1 + (int)i2;
+            const int tv[3] = {0, ti ? 2 : 1, 3};
+            bool in[3];
+            int nin = 0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                in[i] = f[tv[i] * kBlock] > 0.0;
+                nin += in[i];
+            }
             if (nin == 0 || nin == 3) continue;
             // the lone vertex: inside when one is inside, outside when two are
             const bool want = nin == 1;
-            const int lone = i0 == want ? 0 : (i1 == want ? 1 : 2);
+            const int lone = in[0] == want ? 0 : (in[1] == want ? 1 : 2);
             const int a = lone == 0 ? 1 : 0, b = lone == 2 ? 1 : 2;  // the other two, increasing
-            const CVtx va = cv_edge(o, tv[min(lone, a)], tv[max(lone, a)], f);
-            const CVtx vb = cv_edge(o, tv[min(lone, b)], tv[max(lone, b)], f);
+            const CVtx va = cv_edge_l(o, tv[min(lone, a)], tv[max(lone, a)], f);
+            const CVtx vb = cv_edge_l(o, tv[min(lone, b)], tv[max(lone, b)], f);
             best.take(cv_seg2(va, vb), cell, ti);
         }
         return;
     }
-    constexpr int tets[6][4] = {{0, 1, 3, 7}, {0, 1, 5, 7}, {0, 2, 3, 7}, {0, 2, 6, 7}, {0, 4, 5, 7}, {0, 4, 6, 7}};
+#pragma unroll 1
     for (int ti = 0; ti < 6; ++ti) {
-        const int *tv = tets[ti];
+        const int a1 = ti >> 1;
+        const int lo = a1 == 0 ? 1 : 0, hi = a1 == 2 ? 1 : 2;
+        const int v1 = 1 << a1, v2 = v1 | (1 << ((ti & 1) ? hi : lo));
+        const int tv[4] = {0, v1, v2, 7};
         bool in[4];
         int nin = 0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            in[i] = f[tv[i]] > 0.0;
+            in[i] = f[tv[i] * kBlock] > 0.0;
             nin += in[i];
         }
         if (nin == 0 || nin == 4) continue;
+        CVtx V0, V1, V2, V3;
+        int ntri;
         if (nin != 2) {
+            // one triangle: the edges from the lone vertex to the others, in order
             const bool want = nin == 1;
-            int lone = 0;
-#pragma unroll
-            for (int i = 3; i >= 0; --i)
-                if (in[i] == want) lone = i;
-            CVtx v[3];
-            int m = 0;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                if (i == lone) continue;
-                v[m++] = cv_edge(o, tv[min(lone, i)], tv[max(lone, i)], f);
-            }
-            best.take(cv_tri2(v[0], v[1], v[2]), cell, 2 * ti);
+            const int l = in[0] == want ? 0 : (in[1] == want ? 1 : (in[2] == want ? 2 : 3));
+            const int p0 = l == 0 ? 1 : 0, p1 = l <= 1 ? 2 : 1, p2 = l <= 2 ? 3 : 2;
+            V0 = cv_edge_l(o, tv[min(l, p0)], tv[max(l, p0)], f);
+            V1 = cv_edge_l(o, tv[min(l, p1)], tv[max(l, p1)], f);
+            V2 = cv_edge_l(o, tv[min(l, p2)], tv[max(l, p2)], f);
+            V3 = V2;
+            ntri = 1;
         } else {
-            int I0 = -1, I1 = -1, O0 = -1, O1 = -1;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                if (in[i]) {
-                    if (I0 < 0) I0 = i;
-                    else I1 = i;
-                } else {
-                    if (O0 < 0) O0 = i;
-                    else O1 = i;
-                }
-            }
-            const CVtx vac = cv_edge(o, tv[min(I0, O0)], tv[max(I0, O0)], f);
-            const CVtx vad = cv_edge(o, tv[min(I0, O1)], tv[max(I0, O1)], f);
-            const CVtx vbd = cv_edge(o, tv[min(I1, O1)], tv[max(I1, O1)], f);
-            const CVtx vbc = cv_edge(o, tv[min(I1, O0)], tv[max(I1, O0)], f);
-            best.take(cv_tri2(vac, vad, vbd), cell, 2 * ti);
-            best.take(cv_tri2(vac, vbd, vbc), cell, 2 * ti + 1);
+            // a quadrilateral: inside corners I0 < I1, outside O0 < O1
+            const int I0 = in[0] ? 0 : (in[1] ? 1 : 2);
+            const int I1 = in[3] ? 3 : (in[2] ? 2 : 1);
+            const int O0 = !in[0] ? 0 : (!in[1] ? 1 : 2);
+            const int O1 = !in[3] ? 3 : (!in[2] ? 2 : 1);
+            V0 = cv_edge_l(o, tv[min(I0, O0)], tv[max(I0, O0)], f);  // ac
+            V1 = cv_edge_l(o, tv[min(I0, O1)], tv[max(I0, O1)], f);  // ad
+            V2 = cv_edge_l(o, tv[min(I1, O1)], tv[max(I1, O1)], f);  // bd
+            V3 = cv_edge_l(o, tv[min(I1, O0)], tv[max(I1, O0)], f);  // bc
+            ntri = 2;
+        }
+#pragma unroll 1
+        for (int t = 0; t < ntri; ++t) {
+            // triangles (V0, V1, V2) and (V0, V2, V3)
+            const CVtx B = cv_pick(t != 0, V2, V1), C = cv_pick(t != 0, V3, V2);
+            best.take(cv_tri2(V0, B, C), cell, 2 * ti + t);
         }
     }
 }
@@ -246,115 +269,155 @@ __global__ void __launch_bounds__(kBlock)
     T *w = wout + L.off[k];
     const int plane = e[0] * e[1];
     const int total = plane * e[2];  // a box volume: below 2^31
+    // the node values of the cell being searched, one LDS column per thread
+    __shared__ double corners[8 * kBlock];
+    double *corner = corners + threadIdx.x;
     int cj = -2;
     double cw = 1.0;
-    for (int i = threadIdx.x; i < total; i += kBlock) {
+    // ID-field weight of voxel i (outside the tube)
+    auto id_weight = [&](int i) -> double {
+        const int j = io[i];
+        if (j != cj) {
+            cj = j;
+            cw = j >= 0 ? pair_w<T>(ph, k, j) : 1.0;
+        }
+        return cw;
+    };
+    // The closest piece's weight of tube voxel i (the ID-field weight when
+    // the box holds no piece).
+    auto tube_weight = [&](int i) -> double {
         const int z = i / plane, r = i - z * plane, y = r / e[0], x = r - y * e[0];
         const int xv[3] = {x, y, z};
-        const double p = (double)f[i];
-        int cell = -1;
-        if (fabs(p) < kClosestTube) {
-            CBest best{__builtin_inf(), 0x7fffffff, 0x7fffffff};
-            // cells with offsets in [-r-1, r] on each axis (clamped to the box,
-            // or to the canonical image range on a whole periodic axis);
-            // prune: skip cells farther than the best piece
-            auto scan = [&](int rr, bool prune) -> bool {
-                int ol[3], oh[3];
-                bool full = true;
-                for (int a = 0; a < 3; ++a) {
-                    if (a >= dim) {
-                        ol[a] = oh[a] = 0;
-                        continue;
-                    }
-                    const int L0 = ring[a] ? lo_lim[a] : -xv[a];
-                    const int H0 = ring[a] ? hi_ring[a] : e[a] - 2 - xv[a];
-                    ol[a] = max(-rr - 1, L0);
-                    oh[a] = min(rr, H0);
-                    full = full && ol[a] == L0 && oh[a] == H0;
+        CBest best{__builtin_inf(), 0x7fffffff, 0x7fffffff};
+        // one region per round: offsets [-rr-1, rr] per axis (clamped to the
+        // box, or to the canonical image range on a whole periodic axis)
+        // without [-sk-1, sk] (scanned before); with prune, cells farther
+        // than the best piece are skipped.  Rings rr = 0, 1, ... until a piece
+        // is found, then one round out to the found distance.
+        int rr = 0, sk = -1;
+        bool prune = false;
+        for (;;) {
+            int ol[3], oh[3];
+            bool full = true;
+            for (int a = 0; a < 3; ++a) {
+                if (a >= dim) {
+                    ol[a] = oh[a] = 0;
+                    continue;
                 }
-                for (int oz = ol[2]; oz <= oh[2]; ++oz)
-                    for (int oy = ol[1]; oy <= oh[1]; ++oy)
-                        for (int ox = ol[0]; ox <= oh[0]; ++ox) {
-                            const int o[3] = {ox, oy, oz};
-                            if (prune) {
-                                int s = 0;
-#pragma unroll
-                                for (int a = 0; a < 3; ++a) {
-                                    const int d = o[a] > 0 ? o[a] : (o[a] < -1 ? -(o[a] + 1) : 0);
-                                    s += d * d;
-                                }
-                                if ((double)s > best.d2) continue;
-                            }
-                            int c[3];
+                const int L0 = ring[a] ? lo_lim[a] : -xv[a];
+                const int H0 = ring[a] ? hi_ring[a] : e[a] - 2 - xv[a];
+                ol[a] = max(-rr - 1, L0);
+                oh[a] = min(rr, H0);
+                full = full && ol[a] == L0 && oh[a] == H0;
+            }
+            for (int oz = ol[2]; oz <= oh[2]; ++oz)
+                for (int oy = ol[1]; oy <= oh[1]; ++oy)
+                    for (int ox = ol[0]; ox <= oh[0]; ++ox) {
+                        if (sk >= 0 && ox >= -sk - 1 && ox <= sk && oy >= -sk - 1 && oy <= sk && oz >= -sk - 1 &&
+                            oz <= sk)
+                            continue;
+                        const int o[3] = {ox, oy, oz};
+                        if (prune) {
+                            int sq = 0;
 #pragma unroll
                             for (int a = 0; a < 3; ++a) {
-                                int v = xv[a] + o[a];
-                                if (ring[a]) v = v < 0 ? v + e[a] : (v >= e[a] ? v - e[a] : v);
-                                c[a] = v;
+                                const int d = o[a] > 0 ? o[a] : (o[a] < -1 ? -(o[a] + 1) : 0);
+                                sq += d * d;
                             }
-                            double fv[8];
-                            int pos = 0;
-                            for (int b = 0; b < nc; ++b) {
-                                int q[3];
-#pragma unroll
-                                for (int a = 0; a < 3; ++a) {
-                                    q[a] = c[a] + ((b >> a) & 1);
-                                    if (q[a] >= e[a]) q[a] -= e[a];  // whole periodic axes only
-                                }
-                                fv[b] = (double)f[q[0] + e[0] * (q[1] + e[1] * q[2])];
-                                pos += fv[b] > 0.0;
-                            }
-                            if (pos == 0 || pos == nc) continue;
-                            cell_pieces(dim, o, fv, c[0] + e[0] * (c[1] + e[1] * c[2]), best);
+                            if ((double)sq > best.d2) continue;
                         }
-                return full;
-            };
-            int rr = 0;
-            for (;; ++rr)
-                if (scan(rr, false) || best.cell != 0x7fffffff) break;
-            if (best.cell != 0x7fffffff) {
-                const int r2 = (int)floor(sqrt(best.d2)) + 1;
-                if (r2 > rr) scan(r2, true);
-                cell = best.cell;
-            }
-        }
-        double wv;
-        if (cell >= 0) {
-            // the cell's character: distinct ID-field entries at its nodes
-            const int c[3] = {cell % e[0], (cell / e[0]) % e[1], cell / plane};
-            int js[8], nj = 0;
-            for (int b = 0; b < nc; ++b) {
-                int q[3];
+                        int c[3];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    q[a] = c[a] + ((b >> a) & 1);
-                    if (q[a] >= e[a]) q[a] -= e[a];
-                }
-                const int j = io[q[0] + e[0] * (q[1] + e[1] * q[2])];
-                if (j < 0) continue;
-                bool seen = false;
-                for (int t = 0; t < nj; ++t) seen = seen || js[t] == j;
-                if (!seen) {
-                    int t = nj++;  // insertion in increasing j
-                    while (t > 0 && js[t - 1] > j) {
-                        js[t] = js[t - 1];
-                        --t;
+                        for (int a = 0; a < 3; ++a) {
+                            int v = xv[a] + o[a];
+                            if (ring[a]) v = v < 0 ? v + e[a] : (v >= e[a] ? v - e[a] : v);
+                            c[a] = v;
+                        }
+                        const int ci = c[0] + e[0] * (c[1] + e[1] * c[2]);
+                        int pos = 0;
+#pragma unroll
+                        for (int bb = 0; bb < 8; ++bb) {
+                            if (bb >= nc) continue;
+                            int q[3];
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                q[a] = c[a] + ((bb >> a) & 1);
+                                if (q[a] >= e[a]) q[a] -= e[a];  // whole periodic axes only
+                            }
+                            const double v = (double)f[q[0] + e[0] * (q[1] + e[1] * q[2])];
+                            corner[bb * kBlock] = v;
+                            pos += v > 0.0;
+                        }
+                        if (pos == 0 || pos == nc) continue;
+                        cell_pieces(dim, o, corner, ci, best);
                     }
-                    js[t] = j;
-                }
+            if (!prune && best.cell != 0x7fffffff) {
+                const int r2 = (int)floor(sqrt(best.d2)) + 1;
+                if (r2 <= rr || full) break;
+                prune = true;
+                sk = rr;
+                rr = r2;
+                continue;
             }
-            double s = 0.0;
-            for (int t = 0; t < nj; ++t) s += pair_w<T>(ph, k, js[t]);
-            wv = nj ? s / (double)nj : 1.0;
-        } else {
-            const int j = io[i];
-            if (j != cj) {
-                cj = j;
-                cw = j >= 0 ? pair_w<T>(ph, k, j) : 1.0;
-            }
-            wv = cw;
+            if (prune || full) break;
+            sk = rr;
+            ++rr;
         }
-        w[i] = (T)wv;
+        if (best.cell == 0x7fffffff) return id_weight(i);
+        // the cell's character: distinct ID-field entries at its nodes
+        const int cell = best.cell;
+        const int c[3] = {cell % e[0], (cell / e[0]) % e[1], cell / plane};
+        int js[8], nj = 0;
+        for (int bb = 0; bb < nc; ++bb) {
+            int q[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                q[a] = c[a] + ((bb >> a) & 1);
+                if (q[a] >= e[a]) q[a] -= e[a];
+            }
+            const int j = io[q[0] + e[0] * (q[1] + e[1] * q[2])];
+            if (j < 0) continue;
+            bool seen = false;
+            for (int t = 0; t < nj; ++t) seen = seen || js[t] == j;
+            if (!seen) {
+                int t = nj++;  // insertion in increasing j
+                while (t > 0 && js[t - 1] > j) {
+                    js[t] = js[t - 1];
+                    --t;
+                }
+                js[t] = j;
+            }
+        }
+        double sum = 0.0;
+        for (int t = 0; t < nj; ++t) sum += pair_w<T>(ph, k, js[t]);
+        return nj ? sum / (double)nj : 1.0;
+    };
+    // Tube voxels are gathered into a queue and searched a group's width at a
+    // time, so that no lane idles on a voxel outside the tube.
+    __shared__ int queue[2 * kBlock];
+    __shared__ int qn;
+    if (threadIdx.x == 0) qn = 0;
+    __syncthreads();
+    for (int base = 0; base < total; base += kBlock) {
+        const int i = base + (int)threadIdx.x;
+        if (i < total) {
+            if (fabs((double)f[i]) < kClosestTube) queue[atomicAdd(&qn, 1)] = i;
+            else w[i] = (T)id_weight(i);
+        }
+        __syncthreads();
+        const bool last = base + kBlock >= total;
+        int n = qn;
+        while (n >= kBlock || (last && n > 0)) {
+            const int take = min(n, kBlock);
+            if ((int)threadIdx.x < take) {
+                const int v = queue[n - take + threadIdx.x];
+                w[v] = (T)tube_weight(v);
+            }
+            n -= take;
+            __syncthreads();
+            if (threadIdx.x == 0) qn = n;
+            __syncthreads();
+        }
     }
 }
 
