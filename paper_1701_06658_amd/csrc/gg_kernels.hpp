@@ -421,153 +421,270 @@ template <typename T> struct Top2 {
         m1 = m2 = -tinf<T>();
         i1 = i2 = -1;
     }
-    __device__ void push(T v, int j) {
-        if (v > m1 || (v == m1 && j < i1)) {
-            m2 = m1;
-            i2 = i1;
-            m1 = v;
-            i1 = j;
-        } else if (v > m2 || (v == m2 && (i2 < 0 || j < i2))) {
-            m2 = v;
-            i2 = j;
+    // v (from grain j) joins when `in` holds, branch-free.  IDS: equal values
+    // are ordered by id, lowest first, so that the argmax over the others is
+    // unique; otherwise the first pushed stays first, which changes no value
+    // the corrector takes from the pair.
+    template <bool IDS> __device__ void push(T v, int j, bool in) {
+        bool a1, a2;
+        if constexpr (IDS) {
+            a1 = in && (v > m1 || (v == m1 && j < i1));
+            a2 = in && (v > m2 || (v == m2 && (i2 < 0 || j < i2)));
+        } else {
+            a1 = in && v > m1;
+            a2 = in && v > m2;
         }
+        m2 = a1 ? m1 : (a2 ? v : m2);
+        i2 = a1 ? i1 : (a2 ? j : i2);
+        m1 = a1 ? v : m1;
+        i1 = a1 ? j : i1;
     }
 };
 
-// Corrector register cache: grains per tile whose predicted values stay in
-// registers between the two passes (more cache, fewer waves per SIMD).
-#ifndef GG_CMP_CACHE_F32
-#define GG_CMP_CACHE_F32 24
-#endif
-#ifndef GG_CMP_CACHE_F64
-#define GG_CMP_CACHE_F64 12
+// Values a corrector group keeps in LDS between its two passes: one slot per
+// covering grain (in coverage-list order) and voxel of the tile; the values of
+// grains past the last slot are read again in the second pass.
+#ifndef GG_CMP_LDS_BYTES
+#define GG_CMP_LDS_BYTES 16384
 #endif
 
 constexpr int kTileVox = 512;
 constexpr int kVpt = kTileVox / kBlock;
+template <typename T> constexpr int cmp_slots() { return GG_CMP_LDS_BYTES / (kTileVox * (int)sizeof(T)); }
+
+// Where a global tile meets box j.  Per axis s = (tile origin - box start) mod
+// n.  The box coordinate of the tile voxel at offset v is linear, d + v, when
+// no voxel of the tile reaches the box a second time around the axis: when
+// ext + t <= n (then d = s, or s - n if s >= ext, the box starting inside the
+// tile), or when s + t <= n (d = s).  The voxel lies in the box exactly when
+// 0 <= d + v < ext, and its value is then at base + v_x + ext_x (v_y + ext_y
+// v_z).  Otherwise ("wrapped") the coordinate is (s + v) mod n per voxel.
+struct TileBox {
+    long long off, base;
+    int j, s[3], d[3], e[3];
+    int lin;
+};
+
+// The TileBox of coverage entry c (c < end), computed by one lane.
+__device__ __forceinline__ TileBox tile_box(const Boxes &L, const int *cov_list, int c, int end, const int (&t0)[3],
+                                            const TileArgs &ta) {
+    TileBox b;
+    const int j = c < end ? cov_list[c] : 0;
+    b.j = j;
+    b.off = L.off[j];
+    b.lin = 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int lo = L.lo[3 * j + a], ex = L.ext[3 * j + a], n = ta.n[a];
+        int s = t0[a] - lo;
+        s += s < 0 ? n : 0;
+        b.s[a] = s;
+        b.e[a] = ex;
+        const int once = ex + ta.t[a] <= n;
+        b.lin &= once | (s + ta.t[a] <= n);
+        b.d[a] = (once && s >= ex) ? s - n : s;
+    }
+    b.base = b.off + b.d[0] + (long long)b.e[0] * (b.d[1] + (long long)b.e[1] * b.d[2]);
+    return b;
+}
+
+// Uniform copies of lane `lane`'s TileBox (the fields of the linear case, or
+// all of them).
+__device__ __forceinline__ long long readlane64(long long v, int lane) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+template <bool ALL> __device__ __forceinline__ TileBox box_of_lane(const TileBox &w, int lane) {
+    TileBox b;
+    b.j = __builtin_amdgcn_readlane(w.j, lane);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        b.e[a] = __builtin_amdgcn_readlane(w.e[a], lane);
+        if constexpr (ALL) b.s[a] = __builtin_amdgcn_readlane(w.s[a], lane);
+        else b.d[a] = __builtin_amdgcn_readlane(w.d[a], lane);
+    }
+    if constexpr (ALL) b.off = readlane64(w.off, lane);
+    else b.base = readlane64(w.base, lane);
+    return b;
+}
+
+// An element of an array at a byte offset from a base pointer.
+template <typename U, typename O> __device__ __forceinline__ U &at_bytes(U *base, O bo) {
+    return *reinterpret_cast<U *>(reinterpret_cast<char *>(base) + bo);
+}
+template <typename U, typename O> __device__ __forceinline__ const U &at_bytes(const U *base, O bo) {
+    return *reinterpret_cast<const U *>(reinterpret_cast<const char *>(base) + bo);
+}
+
+#ifndef GG_CMP_U
+#define GG_CMP_U 4
+#endif
 
 // One global tile: the top-2 of the predicted functions of every grain whose
 // box covers the tile, then for each of those grains
 //   phi^c = (psi - max over the other grains) / 2   (-W if no other grain),
-// its ID-field (argmax of the others), and the bounding box of phi^c > 0.
-// mode 0: corrector; mode 1: ID-field only (argmax of the others' values).
-template <typename T>
+// its ID-field (argmax of the others; IDS: iota_out given), and the bounding
+// box of phi^c > 0.  mode 0: corrector; mode 1: ID-field only.
+template <typename T, bool IDS>
 __global__ void __launch_bounds__(kBlock)
     k_compare(Boxes L, const int *__restrict__ cov_off, const int *__restrict__ cov_list, const T *__restrict__ psi,
               T *__restrict__ phic, int *__restrict__ iota_out, int *bmin, int *bmax, unsigned *occ, TileArgs ta,
               T W, int mode, const Ctl *ctl) {
+    constexpr int NS = cmp_slots<T>();
+    __shared__ T cache[NS > 0 ? NS : 1][kTileVox];
     if (ctl_failed(ctl)) return;
     const int ntiles = ta.nt[0] * ta.nt[1] * ta.nt[2];
     const int tile = (int)xcd_item(ntiles);
     if (tile >= ntiles) return;
-    const int tx = tile % ta.nt[0], ty = (tile / ta.nt[0]) % ta.nt[1], tz = tile / (ta.nt[0] * ta.nt[1]);
+    const int t0[3] = {(tile % ta.nt[0]) * ta.t[0], ((tile / ta.nt[0]) % ta.nt[1]) * ta.t[1],
+                       (tile / (ta.nt[0] * ta.nt[1])) * ta.t[2]};
     const int tvol = ta.t[0] * ta.t[1] * ta.t[2];
-    int gx[kVpt], gy[kVpt], gz[kVpt];
+    // the thread's voxels: offsets in the tile, and the x offset in bytes
+    int vc[kVpt][3];
+    unsigned bx[kVpt];
     bool valid[kVpt];
 #pragma unroll
     for (int i = 0; i < kVpt; ++i) {
         const int v = threadIdx.x + i * kBlock;
         valid[i] = v < tvol;
-        const int vx = v % ta.t[0], vy = (v / ta.t[0]) % ta.t[1], vz = v / (ta.t[0] * ta.t[1]);
-        gx[i] = tx * ta.t[0] + vx;
-        gy[i] = ty * ta.t[1] + vy;
-        gz[i] = tz * ta.t[2] + vz;
+        vc[i][0] = v % ta.t[0];
+        vc[i][1] = (v / ta.t[0]) % ta.t[1];
+        vc[i][2] = v / (ta.t[0] * ta.t[1]);
+        bx[i] = (unsigned)vc[i][0] * (unsigned)sizeof(T);
     }
     const int b = cov_off[tile], e = cov_off[tile + 1];
+    // Linear case: membership, box coordinates, and the byte offset of the
+    // value from base (below 2^32: ext <= 4096, tile offsets below 32).
+    auto probe_lin = [&](const TileBox &tb, bool (&hit)[kVpt], int (&l)[kVpt][3], unsigned (&bo)[kVpt]) {
+#pragma unroll
+        for (int i = 0; i < kVpt; ++i) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) l[i][a] = tb.d[a] + vc[i][a];
+            hit[i] = valid[i] && (unsigned)l[i][0] < (unsigned)tb.e[0] && (unsigned)l[i][1] < (unsigned)tb.e[1] &&
+                     (unsigned)l[i][2] < (unsigned)tb.e[2];
+            const unsigned r = (unsigned)vc[i][1] + (unsigned)__umul24(tb.e[1], vc[i][2]);
+            bo[i] = bx[i] + (unsigned)__umul24(tb.e[0] * (int)sizeof(T), r);
+        }
+    };
+    // Wrapped case: the same with the element index of the value.
+    auto probe_wrap = [&](const TileBox &tb, bool (&hit)[kVpt], int (&l)[kVpt][3], long long (&ix)[kVpt]) {
+#pragma unroll
+        for (int i = 0; i < kVpt; ++i) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int q = tb.s[a] + vc[i][a];
+                l[i][a] = q >= ta.n[a] ? q - ta.n[a] : q;
+            }
+            hit[i] = valid[i] && l[i][0] < tb.e[0] && l[i][1] < tb.e[1] && l[i][2] < tb.e[2];
+            ix[i] = tb.off + l[i][0] + (long long)tb.e[0] * (l[i][1] + (long long)tb.e[1] * l[i][2]);
+        }
+    };
     Top2<T> top[kVpt];
 #pragma unroll
     for (int i = 0; i < kVpt; ++i) top[i].init();
-    // Local coordinates of the thread's voxels in box j; hit = inside the box.
-    auto locate = [&](int j, long long idx[kVpt], bool hit[kVpt], int l3[kVpt][3]) {
-        const int lx0 = L.lo[3 * j], ly0 = L.lo[3 * j + 1], lz0 = L.lo[3 * j + 2];
-        const int ex = L.ext[3 * j], ey = L.ext[3 * j + 1], ez = L.ext[3 * j + 2];
-        const long long off = L.off[j];
-#pragma unroll
-        for (int i = 0; i < kVpt; ++i) {
-            const int lx = wrap_diff(gx[i], lx0, ta.n[0]), ly = wrap_diff(gy[i], ly0, ta.n[1]),
-                      lz = wrap_diff(gz[i], lz0, ta.n[2]);
-            hit[i] = valid[i] && lx < ex && ly < ey && lz < ez;
-            idx[i] = off + lx + (long long)ex * (ly + (long long)ey * lz);
-            l3[i][0] = lx;
-            l3[i][1] = ly;
-            l3[i][2] = lz;
-        }
+    auto keep = [&](int slot, int i, T v) {
+        if (slot < NS) cache[slot < NS ? slot : 0][threadIdx.x + i * kBlock] = v;
     };
-    // pass 1: top-2.  The first CR grains' values stay in registers for pass 2;
-    // U grains' loads are issued together.
-    constexpr int CR = sizeof(T) == 4 ? GG_CMP_CACHE_F32 : GG_CMP_CACHE_F64;
-    constexpr int U = 4;
-    T cache[CR][kVpt];
+    // Each wave holds the TileBoxes of 64 coverage entries, one per lane.
+    const int lane_id = (int)(threadIdx.x & 63);
+    TileBox wb;
+    int held = -1;
+    auto hold = [&](int cb) {
+        if (held != cb) wb = tile_box(L, cov_list, cb + lane_id, e, t0, ta);
+        held = cb;
+    };
+    // pass 1: top-2 over the covering grains, U linear boxes' loads issued together
+    constexpr int U = GG_CMP_U;
+    for (int cb = b; cb < e; cb += 64) {
+        hold(cb);
+        const int ce = min(e, cb + 64);
+        const unsigned long long wrapped = __ballot(cb + lane_id < e && !wb.lin);
+        for (int c0 = cb; c0 < ce; c0 += U) {
+            T v[U][kVpt];
+            bool hit[U][kVpt];
+            int jj[U];
 #pragma unroll
-    for (int c0 = 0; c0 < CR; c0 += U) {
-        int jj[U];
-        bool hit[U][kVpt];
+            for (int u = 0; u < U; ++u) {
+                const int c = c0 + u;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int c = b + c0 + u;
-            jj[u] = c < e ? cov_list[c] : -1;
-            long long idx[kVpt];
-            int l3[kVpt][3];
+                for (int i = 0; i < kVpt; ++i) hit[u][i] = false;
+                jj[u] = -1;
+                if (c >= ce || ((wrapped >> (c - cb)) & 1ull)) continue;
+                const TileBox tb = box_of_lane<false>(wb, c - cb);
+                jj[u] = tb.j;
+                int l[kVpt][3];
+                unsigned bo[kVpt];
+                probe_lin(tb, hit[u], l, bo);
+                const T *pb = psi + tb.base;
 #pragma unroll
-            for (int i = 0; i < kVpt; ++i) hit[u][i] = false;
-            if (jj[u] < 0) continue;
-            locate(jj[u], idx, hit[u], l3);
+                for (int i = 0; i < kVpt; ++i)
+                    if (hit[u][i]) v[u][i] = at_bytes(pb, bo[i]);
+            }
 #pragma unroll
-            for (int i = 0; i < kVpt; ++i)
-                if (hit[u][i]) cache[c0 + u][i] = psi[idx[i]];
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int i = 0; i < kVpt; ++i) {
+                    top[i].template push<IDS>(v[u][i], jj[u], hit[u][i]);
+                    if (hit[u][i]) keep(c0 + u - b, i, v[u][i]);
+                }
         }
+        for (unsigned long long m = wrapped; m; m &= m - 1) {
+            const int lane = __builtin_ctzll(m);
+            const TileBox tb = box_of_lane<true>(wb, lane);
+            bool hit[kVpt];
+            int l[kVpt][3];
+            long long ix[kVpt];
+            probe_wrap(tb, hit, l, ix);
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int i = 0; i < kVpt; ++i)
-                if (hit[u][i]) top[i].push(cache[c0 + u][i], jj[u]);
-    }
-    for (int c0 = b + CR; c0 < e; c0 += U) {
-        T v[U][kVpt];
-        int jj[U];
-        bool hit[U][kVpt];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int c = c0 + u;
-            jj[u] = c < e ? cov_list[c] : -1;
-            long long idx[kVpt];
-            int l3[kVpt][3];
-#pragma unroll
-            for (int i = 0; i < kVpt; ++i) hit[u][i] = false;
-            if (jj[u] < 0) continue;
-            locate(jj[u], idx, hit[u], l3);
-#pragma unroll
-            for (int i = 0; i < kVpt; ++i)
-                if (hit[u][i]) v[u][i] = psi[idx[i]];
+            for (int i = 0; i < kVpt; ++i) {
+                const T v = hit[i] ? psi[ix[i]] : T(0);
+                top[i].template push<IDS>(v, tb.j, hit[i]);
+                if (hit[i]) keep(cb + lane - b, i, v);
+            }
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int i = 0; i < kVpt; ++i)
-                if (hit[u][i]) top[i].push(v[u][i], jj[u]);
     }
     // pass 2: the corrected function of every covering grain
-    auto emit = [&](int j, const T val[kVpt], const bool hit[kVpt], const long long idx[kVpt],
-                    const int l3[kVpt][3]) {
-        const int e3[3] = {L.ext[3 * j], L.ext[3 * j + 1], L.ext[3 * j + 2]};
+    auto emit = [&](auto lin, auto cached, int slot, const TileBox &tb) {
+        constexpr bool LIN = decltype(lin)::value, CACHED = decltype(cached)::value;
+        const int j = tb.j;
+        bool hit[kVpt];
+        int l[kVpt][3];
+        unsigned bo[kVpt];
+        long long ix[kVpt];
+        if constexpr (LIN) probe_lin(tb, hit, l, bo);
+        else probe_wrap(tb, hit, l, ix);
+        T val[kVpt];
+#pragma unroll
+        for (int i = 0; i < kVpt; ++i) {
+            if constexpr (CACHED) val[i] = cache[slot < NS ? slot : 0][threadIdx.x + i * kBlock];
+            else if (hit[i]) {
+                if constexpr (LIN) val[i] = at_bytes(psi + tb.base, bo[i]);
+                else val[i] = psi[ix[i]];
+            }
+        }
         int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-1, -1, -1};
 #pragma unroll
         for (int i = 0; i < kVpt; ++i) {
             if (!hit[i]) continue;
             const bool first = top[i].i1 == j;
-            const int other = first ? top[i].i2 : top[i].i1;
-            if (iota_out) iota_out[idx[i]] = other;
+            if constexpr (IDS) {
+                const int other = first ? top[i].i2 : top[i].i1;
+                if constexpr (LIN) at_bytes(iota_out + tb.base, bo[i] / (unsigned)(sizeof(T) / sizeof(int))) = other;
+                else iota_out[ix[i]] = other;
+            }
             if (mode != 0) continue;
             const T m = first ? (top[i].i2 < 0 ? -W : top[i].m2) : top[i].m1;
             const T pc = T(0.5) * (val[i] - m);
-            phic[idx[i]] = pc;
+            if constexpr (LIN) at_bytes(phic + tb.base, bo[i]) = pc;
+            else phic[ix[i]] = pc;
             if (pc > T(0)) {
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    mn[a] = min(mn[a], l3[i][a]);
-                    mx[a] = max(mx[a], l3[i][a]);
-                    if (e3[a] == ta.n[a])
-                        atomicOr(&occ[((long long)j * 3 + a) * ta.occ_words + (l3[i][a] >> 5)], 1u << (l3[i][a] & 31));
+                    mn[a] = min(mn[a], l[i][a]);
+                    mx[a] = max(mx[a], l[i][a]);
+                    if (tb.e[a] == ta.n[a])
+                        atomicOr(&occ[((long long)j * 3 + a) * ta.occ_words + (l[i][a] >> 5)], 1u << (l[i][a] & 31));
                 }
             }
         }
@@ -586,28 +703,22 @@ __global__ void __launch_bounds__(kBlock)
             }
         }
     };
-#pragma unroll
-    for (int cc = 0; cc < CR; ++cc) {
-        const int c = b + cc;
-        if (c >= e) break;
-        const int j = cov_list[c];
-        long long idx[kVpt];
-        bool hit[kVpt];
-        int l3[kVpt][3];
-        locate(j, idx, hit, l3);
-        emit(j, cache[cc], hit, idx, l3);
-    }
-    for (int c = b + CR; c < e; ++c) {
-        const int j = cov_list[c];
-        long long idx[kVpt];
-        bool hit[kVpt];
-        int l3[kVpt][3];
-        locate(j, idx, hit, l3);
-        T val[kVpt];
-#pragma unroll
-        for (int i = 0; i < kVpt; ++i)
-            if (hit[i]) val[i] = psi[idx[i]];
-        emit(j, val, hit, idx, l3);
+    using Lin = std::integral_constant<bool, true>;
+    using Wrap = std::integral_constant<bool, false>;
+    using Yes = std::integral_constant<bool, true>;
+    using No = std::integral_constant<bool, false>;
+    for (int cb = b; cb < e; cb += 64) {
+        hold(cb);
+        const int ce = min(e, cb + 64);
+        for (int c = cb; c < ce; ++c) {
+            const int slot = c - b;
+            if (__builtin_amdgcn_readlane(wb.lin, c - cb)) {
+                if (slot < NS) emit(Lin{}, Yes{}, slot, box_of_lane<false>(wb, c - cb));
+                else emit(Lin{}, No{}, slot, box_of_lane<false>(wb, c - cb));
+            } else {
+                emit(Wrap{}, No{}, slot, box_of_lane<true>(wb, c - cb));
+            }
+        }
     }
 }
 // Voxel labels: argmax over the covering grains (ties to the lowest id).

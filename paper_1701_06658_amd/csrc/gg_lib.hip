@@ -754,8 +754,8 @@ template <typename T> struct Sim final : SimBase {
 
     void launch_compare(int L, const T *psi, T *phic, int *iota_out, int mode, bool in_step) {
         tbegin(GG_K_COMPARE, 0, 1);
-        hipLaunchKernelGGL(gg::k_compare<T>, dim3((unsigned)gg::xcd_grid(ntiles)), dim3(gg::kBlock), 0, stream,
-                           boxes_of(L), (const int *)cov_off.as<int>(), (const int *)cov_list.as<int>(), psi, phic,
+        auto kern = iota_out ? gg::k_compare<T, true> : gg::k_compare<T, false>;
+        hipLaunchKernelGGL(kern, dim3((unsigned)gg::xcd_grid(ntiles)), dim3(gg::kBlock), 0, stream, boxes_of(L), (const int *)cov_off.as<int>(), (const int *)cov_list.as<int>(), psi, phic,
                            iota_out, bmin.as<int>(), bmax.as<int>(), occ.as<unsigned>(), tile_args(), W, mode,
                            in_step ? (const Ctl *)ctl() : (const Ctl *)nullptr);
         tend();

@@ -48,15 +48,25 @@ constexpr int kMT = GG_MT;  // threads per march group
 constexpr int kQXR = GG_REINIT_QX;   // outputs per thread of the re-initialization's x spreading
 constexpr int kQXP = GG_PREDICT_QX;  // outputs per thread of the predictor's x pass
 constexpr int kReinitYB = GG_REINIT_YB;  // rows per column unit of the re-initialization
+#ifndef GG_ROW_REVERSE
+#define GG_ROW_REVERSE 1
+#endif
+#ifndef GG_ROW_REVERSE_P
+#define GG_ROW_REVERSE_P 1
+#endif
+// First row unit of the thread: row units are dealt from the last thread down,
+// column units from the first thread up, so that in a tile smaller than the
+// group the two kinds of work fall on different waves.
+template <bool REV> __device__ __forceinline__ int row_unit0() { return REV ? kMT - 1 - (int)threadIdx.x : (int)threadIdx.x; }
 
 // The row units (kQ consecutive cells of one row) a thread takes in a tile of
 // EY rows: unit r = threadIdx.x + i kMT has row r % EY and x block r / EY,
 // stepped without division.
 struct RowWalk {
     int ry, xq, dq, dr;
-    __device__ explicit RowWalk(int EY) {
-        ry = (int)threadIdx.x % EY;
-        xq = (int)threadIdx.x / EY;
+    __device__ RowWalk(int EY, int t) {
+        ry = t % EY;
+        xq = t / EY;
         dq = kMT / EY;
         dr = kMT - dq * EY;
     }
@@ -100,7 +110,13 @@ template <int RM, int YB> struct PredictLds {
 };
 
 // LDS cells a march kernel may use (its dynamic allocation).
-template <typename T> constexpr int reinit_cells() { return sizeof(T) == 8 ? 13312 : 16384; }
+#ifndef GG_REINIT_CELLS_F32
+#define GG_REINIT_CELLS_F32 16384
+#endif
+#ifndef GG_REINIT_WAVES
+#define GG_REINIT_WAVES 1
+#endif
+template <typename T> constexpr int reinit_cells() { return sizeof(T) == 8 ? 13312 : GG_REINIT_CELLS_F32; }
 template <typename T> constexpr int predict_cells() { return sizeof(T) == 8 ? 8192 : 12288; }
 
 // Every box has a tiling: the smallest extended tile (one interior cell and
@@ -282,7 +298,7 @@ __device__ inline MCol<YB> march_col(const MTile &tl, int ex, int ey, int N0, in
 // new layout.  KS: static reach (0: runtime ma.K <= kMaxBand); D3: a 3D grid;
 // IO: the ID-field is carried (iota_old and iota_new given).
 template <typename T, int KS, int YB, bool D3, bool IO>
-__global__ void __launch_bounds__(kMT)
+__global__ void __launch_bounds__(kMT, sizeof(T) == 4 ? GG_REINIT_WAVES : 1)
     k_reinit_march(Boxes Lo, Boxes Ln, MarchArgs ma, const T *__restrict__ phic, T *__restrict__ out,
                    const int *__restrict__ iota_old, int *__restrict__ iota_new, double *__restrict__ vol, T W) {
     constexpr int KW = KS ? KS : kMaxBand;
@@ -361,7 +377,7 @@ __global__ void __launch_bounds__(kMT)
         for (int j = 0; j < YB; ++j) car[j] = inf;
         unsigned ins = 0;  // inside flags: bit 4 j + (plane & 3)
         const int nxq = (EX + kQXR - 1) / kQXR;
-        const RowWalk rw0(EY);
+        const RowWalk rw0(EY, row_unit0<GG_ROW_REVERSE>());
         const int fc = (c.ry0 + 1) * ly.pf + c.cx + 1;  // the unit's first cell in F
         // stages of iteration z: A plane z (phi^c into F), B plane z - 1
         // (reference values into Rf), C plane z - 2 (x spreading into Dx), D and
@@ -522,7 +538,7 @@ __device__ __forceinline__ void plane_xy_pass(const T *Cz, T *Cx, const PredictL
                                               const MCol<YB> &c, const T *tp, int R, T (&acc)[YB]) {
     __syncthreads();
     const int nxq = (EX + kQXP - 1) / kQXP;
-    for (int r = threadIdx.x; r < EY * nxq; r += kMT) {
+    for (int r = row_unit0<GG_ROW_REVERSE_P>(); r < EY * nxq; r += kMT) {
         const int ry = r % EY, x0 = (r / EY) * kQXP;
         const T *row = Cz + ry * ly.pz + x0 + (RM - R);
         T v[kQXP + 2 * RM];
@@ -553,8 +569,11 @@ __device__ __forceinline__ void plane_xy_pass(const T *Cz, T *Cx, const PredictL
 // psi == NULL: phi and the volume only.  phi_out: phi is stored when given and
 // the step is the one ma.ctl->phi_at names (always without a control block).
 // RS: static radius (0: runtime ma.R <= kMaxRadius).
+#ifndef GG_PREDICT_WAVES
+#define GG_PREDICT_WAVES 4
+#endif
 template <typename T, int RS, int YB, bool PH>
-__global__ void __launch_bounds__(kMT)
+__global__ void __launch_bounds__(kMT, sizeof(T) == 4 && !PH ? GG_PREDICT_WAVES : 1)
     k_predict_march(Boxes L, MarchArgs ma, T *__restrict__ in, T *__restrict__ psi, T *__restrict__ phi_out,
                     double *__restrict__ vol, const T *__restrict__ taps, Physics<T> ph, T W, int chain) {
     constexpr int RM = RS ? RS : kMaxRadius;
@@ -789,7 +808,7 @@ __global__ void __launch_bounds__(kMT)
                     // x pass of plane qx (row units, rows fastest across lanes)
                     const T *Zb = sm + (qx & 1) * ly.sZ;
                     T *Xb = sm + ly.oX + (qx & 1) * ly.sX;
-                    for (int r = threadIdx.x; r < EY * nxq; r += kMT) {
+                    for (int r = row_unit0<GG_ROW_REVERSE_P>(); r < EY * nxq; r += kMT) {
                         const int ry = r % EY, x0 = (r / EY) * kQXP;
                         const T *row = Zb + ry * ly.pz + x0 + (RM - R);
                         T v[kQXP + 2 * RM];
