@@ -360,19 +360,36 @@ __global__ void __launch_bounds__(kMT, sizeof(T) == 4 ? GG_REINIT_WAVES : 1)
             oz -= oz >= ma.n[2] ? ma.n[2] : 0;
             return oz < oe[2] ? oz * osz : -1;
         };
-        auto load = [&](int z, T (&v)[YB]) {
+        // Loads are issued for every row (outside the old box from its first
+        // value), and which of them stand for -W is kept in `okp` (bit YB slot + j)
+        // until the plane is settled where it is first used, so that the number
+        // of loads in flight is the same on every path.
+        static_assert(5 * YB <= 32, "validity bits of the plane ring");
+        unsigned okp = 0;
+        auto load = [&](int z, int slot, T (&v)[YB]) {
             const int po = oplane(z);
 #pragma unroll
-            for (int j = 0; j < YB; ++j) v[j] = (po >= 0 && orow[j] >= 0) ? src[po + orow[j]] : -W;
+            for (int j = 0; j < YB; ++j) {
+                const bool ok = po >= 0 && orow[j] >= 0;
+                v[j] = src[ok ? po + orow[j] : 0];
+                const unsigned bit = 1u << (YB * slot + j);
+                okp = ok ? (okp | bit) : (okp & ~bit);
+            }
         };
-        // at the start of iteration z: planes z - 2, z - 1, z in q0, q1, q2;
-        // z + 1 and z + 2 on their way in n1, n2
-        T q0[YB], q1[YB], q2[YB], n1[YB], n2[YB], car[YB];
-        load(-2, q0);
-        load(-1, q1);
-        load(0, q2);
-        load(1, n1);
-        load(2, n2);
+        auto settle = [&](int slot, T (&v)[YB]) {
+#pragma unroll
+            for (int j = 0; j < YB; ++j) v[j] = ((okp >> (YB * slot + j)) & 1u) ? v[j] : -W;
+        };
+        // planes in a ring of five buffers, plane p in P[(p + 2) % 5]: at
+        // iteration z the planes z - 2, z - 1, z are used and z + 1, z + 2 are on
+        // their way.  The plane loop is unrolled by five so that every buffer has
+        // a fixed register home (a loaded plane is never moved, and its load is
+        // waited for only where it is used, three iterations later).
+        T P[5][YB], car[YB];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) load(i - 2, i, P[i]);
+        settle(0, P[0]);
+        settle(1, P[1]);
 #pragma unroll
         for (int j = 0; j < YB; ++j) car[j] = inf;
         unsigned ins = 0;  // inside flags: bit 4 j + (plane & 3)
@@ -382,7 +399,15 @@ __global__ void __launch_bounds__(kMT, sizeof(T) == 4 ? GG_REINIT_WAVES : 1)
         // stages of iteration z: A plane z (phi^c into F), B plane z - 1
         // (reference values into Rf), C plane z - 2 (x spreading into Dx), D and
         // E plane z - 3 (y spreading, forward z spreading, output)
-        for (int z = 0; z < ez + 3; ++z) {
+        // (the last group of five may run past plane ez + 2: its stages are off)
+        for (int zb = 0; zb < ez + 3; zb += 5)
+#pragma unroll
+        for (int r = 0; r < 5; ++r) {
+            const int z = zb + r;
+            T(&q0)[YB] = P[r];
+            T(&q1)[YB] = P[(r + 1) % 5];
+            T(&q2)[YB] = P[(r + 2) % 5];
+            settle((r + 2) % 5, q2);
             if (z < ez && c.act) {
                 T *Fb = sm + (z & 1) * ly.sF;
 #pragma unroll
@@ -441,7 +466,7 @@ __global__ void __launch_bounds__(kMT, sizeof(T) == 4 ? GG_REINIT_WAVES : 1)
                         if (x0 + q < EX) drow[q] = o[q];
                 }
             }
-            if (z >= 3 && c.act) {
+            if (z >= 3 && z - 3 < ez && c.act) {
                 // spreading along y for the column unit (rows [ry0 - KW, ry0 + YB + KW)),
                 // forward spreading along z, output of the interior cells
                 const int zz = z - 3;
@@ -470,14 +495,7 @@ __global__ void __launch_bounds__(kMT, sizeof(T) == 4 ? GG_REINIT_WAVES : 1)
                     if constexpr (IO) io_dst[idx] = (po >= 0 && orow[j] >= 0) ? io_src[po + orow[j]] : -1;
                 }
             }
-#pragma unroll
-            for (int j = 0; j < YB; ++j) {
-                q0[j] = q1[j];
-                q1[j] = q2[j];
-                q2[j] = n1[j];
-                n1[j] = n2[j];
-            }
-            if (d3) load(z + 3, n2);
+            if (d3) load(z + 3, r, q0);  // plane z + 3 takes the place of plane z - 2
             __syncthreads();
         }
         if (ringz) {
@@ -734,34 +752,41 @@ __global__ void __launch_bounds__(kMT, sizeof(T) == 4 && !PH ? GG_PREDICT_WAVES 
             int cell[YB];
 #pragma unroll
             for (int j = 0; j < YB; ++j) cell[j] = c.by[j] * ex + c.bx;
-            // planes p, p - 1, p - 2 on their way while plane p + 1 is used
-            constexpr int PD = 3;
-            T win[NW][YB], bcar[YB], pf[PD][YB];
+            // Input planes in a ring of PR buffers: iteration i (plane p = ez - 1
+            // - i) uses PF[i % PR] and loads the plane of iteration i + PR - 1 into
+            // the buffer of iteration i - 1.  The plane loop is unrolled by PR so
+            // that every buffer has a fixed register home (a loaded plane is never
+            // moved).  Every load is issued (rows and planes outside the box read
+            // plane 0 and are not used), so that the number in flight is the same
+            // on every path.
+            constexpr int PR = 3;
+            T win[NW][YB], bcar[YB], PF[PR][YB];
+            auto load = [&](int pz, T(&v)[YB]) {
+#pragma unroll
+                for (int j = 0; j < YB; ++j) v[j] = f[(pz > 0 ? pz : 0) * plane + cell[j]];
+            };
 #pragma unroll
             for (int j = 0; j < YB; ++j) {
                 bcar[j] = inf;
 #pragma unroll
-                for (int d = 0; d < PD; ++d)
-                    pf[d][j] = (c.rv[j] && ez - 1 - d >= 0) ? f[(ez - 1 - d) * plane + cell[j]] : -W;
-#pragma unroll
                 for (int i = 0; i < NW; ++i) win[i][j] = -W;
             }
+#pragma unroll
+            for (int d = 0; d + 1 < PR; ++d) load(ez - 1 - d, PF[d]);
             const int nxq = (EX + kQXP - 1) / kQXP;
             // stages of the iteration for input plane p (descending): the z pass
             // of plane p + R into Cz, the x pass of plane p + R + 1 (Cz -> Cx), the
-            // y pass and output of plane p + R + 2 (from Cx)
+            // y pass and output of plane p + R + 2 (from Cx); the last group of PR
+            // may run past plane pend, with every stage off
             const int pend = want_psi ? -R - 2 : 0;
-            for (int p = ez - 1; p >= pend; --p) {
+            for (int pb = ez - 1; pb >= pend; pb -= PR)
+#pragma unroll
+            for (int u = 0; u < PR; ++u) {
+                const int p = pb - u;
+                load(p - (PR - 1), PF[(u + PR - 1) % PR]);
                 T phv[YB];
                 if (p >= 0) {
-                    T cur[YB];
-#pragma unroll
-                    for (int j = 0; j < YB; ++j) {
-                        cur[j] = pf[0][j];
-#pragma unroll
-                        for (int d = 0; d + 1 < PD; ++d) pf[d][j] = pf[d + 1][j];
-                        if (p - PD >= 0 && c.rv[j]) pf[PD - 1][j] = f[(p - PD) * plane + cell[j]];
-                    }
+                    T(&cur)[YB] = PF[u];
 #pragma unroll
                     for (int j = 0; j < YB; ++j) {
                         if (!c.rv[j]) {
@@ -793,7 +818,7 @@ __global__ void __launch_bounds__(kMT, sizeof(T) == 4 && !PH ? GG_PREDICT_WAVES 
 #pragma unroll
                 for (int j = 0; j < YB; ++j) win[0][j] = phv[j];
                 const int qz = p + R, qx = qz + 1, qy = qz + 2;
-                if (qy <= ez - 1 && c.act) {
+                if (qy >= 0 && qy <= ez - 1 && c.act) {
                     // y pass and output of plane qy (its phi: window entry R + 2)
                     const T *col = sm + ly.oX + (qy & 1) * ly.sX + (c.ry0 + RM - R) * ly.px + c.cx;
                     T v[YB + 2 * RM], acc[YB], phy[YB];
