@@ -441,14 +441,17 @@ template <typename T> struct Top2 {
     }
 };
 
-// Values a corrector group keeps in LDS between its two passes: one slot per
-// covering grain (in coverage-list order) and voxel of the tile; the values of
-// grains past the last slot are read again in the second pass.
+// Values a corrector group keeps in LDS between its two passes: per voxel its
+// first NS values from boxes met linearly, in coverage-list order (the k-th in
+// slot k); the others are read again in the second pass.
 #ifndef GG_CMP_LDS_BYTES
 #define GG_CMP_LDS_BYTES 16384
 #endif
 
-constexpr int kTileVox = 512;
+#ifndef GG_CMP_TILE_VOX
+#define GG_CMP_TILE_VOX 512
+#endif
+constexpr int kTileVox = GG_CMP_TILE_VOX;  // voxels of a corrector tile (at most)
 constexpr int kVpt = kTileVox / kBlock;
 template <typename T> constexpr int cmp_slots() { return GG_CMP_LDS_BYTES / (kTileVox * (int)sizeof(T)); }
 
@@ -532,7 +535,8 @@ __global__ void __launch_bounds__(kBlock)
               T *__restrict__ phic, int *__restrict__ iota_out, int *bmin, int *bmax, unsigned *occ, TileArgs ta,
               T W, int mode, const Ctl *ctl) {
     constexpr int NS = cmp_slots<T>();
-    __shared__ T cache[NS > 0 ? NS : 1][kTileVox];
+    static_assert(NS >= 1, "corrector LDS holds at least one value per voxel");
+    __shared__ T cache[NS][kTileVox];
     if (ctl_failed(ctl)) return;
     const int ntiles = ta.nt[0] * ta.nt[1] * ta.nt[2];
     const int tile = (int)xcd_item(ntiles);
@@ -583,8 +587,13 @@ __global__ void __launch_bounds__(kBlock)
     Top2<T> top[kVpt];
 #pragma unroll
     for (int i = 0; i < kVpt; ++i) top[i].init();
-    auto keep = [&](int slot, int i, T v) {
-        if (slot < NS) cache[slot < NS ? slot : 0][threadIdx.x + i * kBlock] = v;
+    // values kept per voxel (pass 1), then values taken back (pass 2)
+    int kept[kVpt];
+#pragma unroll
+    for (int i = 0; i < kVpt; ++i) kept[i] = 0;
+    auto keep = [&](int i, T v) {
+        if (kept[i] < NS) cache[kept[i] < NS ? kept[i] : 0][threadIdx.x + i * kBlock] = v;
+        ++kept[i];
     };
     // Each wave holds the TileBoxes of 64 coverage entries, one per lane.
     const int lane_id = (int)(threadIdx.x & 63);
@@ -626,7 +635,7 @@ __global__ void __launch_bounds__(kBlock)
 #pragma unroll
                 for (int i = 0; i < kVpt; ++i) {
                     top[i].template push<IDS>(v[u][i], jj[u], hit[u][i]);
-                    if (hit[u][i]) keep(c0 + u - b, i, v[u][i]);
+                    if (hit[u][i]) keep(i, v[u][i]);
                 }
         }
         for (unsigned long long m = wrapped; m; m &= m - 1) {
@@ -640,13 +649,15 @@ __global__ void __launch_bounds__(kBlock)
             for (int i = 0; i < kVpt; ++i) {
                 const T v = hit[i] ? psi[ix[i]] : T(0);
                 top[i].template push<IDS>(v, tb.j, hit[i]);
-                if (hit[i]) keep(cb + lane - b, i, v);
+
             }
         }
     }
     // pass 2: the corrected function of every covering grain
-    auto emit = [&](auto lin, auto cached, int slot, const TileBox &tb) {
-        constexpr bool LIN = decltype(lin)::value, CACHED = decltype(cached)::value;
+#pragma unroll
+    for (int i = 0; i < kVpt; ++i) kept[i] = 0;
+    auto emit = [&](auto lin, const TileBox &tb) {
+        constexpr bool LIN = decltype(lin)::value;
         const int j = tb.j;
         bool hit[kVpt];
         int l[kVpt][3];
@@ -657,10 +668,15 @@ __global__ void __launch_bounds__(kBlock)
         T val[kVpt];
 #pragma unroll
         for (int i = 0; i < kVpt; ++i) {
-            if constexpr (CACHED) val[i] = cache[slot < NS ? slot : 0][threadIdx.x + i * kBlock];
-            else if (hit[i]) {
-                if constexpr (LIN) val[i] = at_bytes(psi + tb.base, bo[i]);
-                else val[i] = psi[ix[i]];
+            if constexpr (LIN) {
+                // the LDS slot is read for every lane (clamped), HBM only for
+                // the values that were not kept
+                const int k = kept[i];
+                val[i] = cache[k < NS ? k : NS - 1][threadIdx.x + i * kBlock];
+                if (hit[i] && k >= NS) val[i] = at_bytes(psi + tb.base, bo[i]);
+                kept[i] += hit[i] ? 1 : 0;
+            } else if (hit[i]) {
+                val[i] = psi[ix[i]];
             }
         }
         int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-1, -1, -1};
@@ -705,18 +721,14 @@ __global__ void __launch_bounds__(kBlock)
     };
     using Lin = std::integral_constant<bool, true>;
     using Wrap = std::integral_constant<bool, false>;
-    using Yes = std::integral_constant<bool, true>;
-    using No = std::integral_constant<bool, false>;
     for (int cb = b; cb < e; cb += 64) {
         hold(cb);
         const int ce = min(e, cb + 64);
         for (int c = cb; c < ce; ++c) {
-            const int slot = c - b;
             if (__builtin_amdgcn_readlane(wb.lin, c - cb)) {
-                if (slot < NS) emit(Lin{}, Yes{}, slot, box_of_lane<false>(wb, c - cb));
-                else emit(Lin{}, No{}, slot, box_of_lane<false>(wb, c - cb));
+                emit(Lin{}, box_of_lane<false>(wb, c - cb));
             } else {
-                emit(Wrap{}, No{}, slot, box_of_lane<true>(wb, c - cb));
+                emit(Wrap{}, box_of_lane<true>(wb, c - cb));
             }
         }
     }

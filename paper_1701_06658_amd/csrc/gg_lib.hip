@@ -444,7 +444,7 @@ template <typename T> struct Sim final : SimBase {
             tdim[2] = pow2_divisor(n[2], GG_CMP_TILE_Z);
         } else {
             tdim[0] = pow2_divisor(n[0], 32);
-            tdim[1] = pow2_divisor(n[1], 16);
+            tdim[1] = pow2_divisor(n[1], gg::kTileVox / 32);
             tdim[2] = 1;
         }
         ntiles = 1;

@@ -353,6 +353,14 @@ __global__ void __launch_bounds__(kMT, sizeof(T) == 4 ? GG_REINIT_WAVES : 1)
             orow[j] = (c.rv[j] && ocol < oe[0] && oy < oe[1]) ? oy * oe[0] + ocol : -1;
             nrow[j] = c.by[j] * ne[0] + c.bx;
         }
+        // the same as byte offsets inside a plane (below 2^32: a plane has at
+        // most 4096^2 cells), for addressing from a uniform plane base
+        unsigned orb[YB], nrb[YB];
+#pragma unroll
+        for (int j = 0; j < YB; ++j) {
+            orb[j] = orow[j] >= 0 ? (unsigned)orow[j] * (unsigned)sizeof(T) : 0u;
+            nrb[j] = (unsigned)nrow[j] * (unsigned)sizeof(T);
+        }
         auto oplane = [&](int z) -> int {  // old-box offset of new plane z, -1 outside either box
             int zm = d3 ? axis_map(z, ne[2], ma.n[2]) : (z == 0 ? 0 : -1);
             if (zm < 0) return -1;
@@ -368,10 +376,11 @@ __global__ void __launch_bounds__(kMT, sizeof(T) == 4 ? GG_REINIT_WAVES : 1)
         unsigned okp = 0;
         auto load = [&](int z, int slot, T (&v)[YB]) {
             const int po = oplane(z);
+            const T *sp = src + (po >= 0 ? po : 0);
 #pragma unroll
             for (int j = 0; j < YB; ++j) {
                 const bool ok = po >= 0 && orow[j] >= 0;
-                v[j] = src[ok ? po + orow[j] : 0];
+                v[j] = at_bytes(sp, ok ? orb[j] : 0u);
                 const unsigned bit = 1u << (YB * slot + j);
                 okp = ok ? (okp | bit) : (okp & ~bit);
             }
@@ -476,6 +485,7 @@ __global__ void __launch_bounds__(kMT, sizeof(T) == 4 ? GG_REINIT_WAVES : 1)
                 for (int i = 0; i < YB + 2 * KW; ++i) v[i] = col[i * ly.pd];
                 taxicab_chains<T, YB + 2 * KW, KW, YB>(v, d);
                 const int po = oplane(zz);
+                T *dp = dst + (long long)zz * nplane;
 #pragma unroll
                 for (int j = 0; j < YB; ++j) {
                     if (!c.rint[j]) continue;
@@ -483,11 +493,11 @@ __global__ void __launch_bounds__(kMT, sizeof(T) == 4 ? GG_REINIT_WAVES : 1)
                     const int idx = zz * nplane + nrow[j];
                     if (d3) {
                         car[j] = vmin(d[j], car[j] + T(1));
-                        dst[idx] = in ? car[j] : -car[j];
+                        at_bytes(dp, nrb[j]) = in ? car[j] : -car[j];
                     } else {
                         const T dc = d[j] < W ? d[j] : W;
                         const T pv = in ? dc : -dc;
-                        dst[idx] = pv;
+                        at_bytes(dp, nrb[j]) = pv;
                         double cl = (double)pv + 0.5;
                         cl = cl < 0.0 ? 0.0 : (cl > 1.0 ? 1.0 : cl);
                         vsum += cl;
