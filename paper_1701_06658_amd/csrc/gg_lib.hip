@@ -30,9 +30,15 @@
 #include "gg_march.hpp"
 #include "gg_closest.hpp"
 
-// Rows per column unit of the FP64 predictor march.
+// Rows per column unit of the FP64 predictor march: 3 (boxes up to 39 cells
+// wide in one tile; with 2 rows those from 33 on split into tiles, whose halo
+// work made the march 40% slower); 2 with the correction epilogue, whose
+// registers spill at 3.
 #ifndef GG_PREDICT_YB64
-#define GG_PREDICT_YB64 2
+#define GG_PREDICT_YB64 3
+#endif
+#ifndef GG_PREDICT_YB64_PH
+#define GG_PREDICT_YB64_PH 2
 #endif
 
 // Corrector tile of the 3D grid (powers of two, 512 voxels).  Rows of 16 FP32
@@ -738,11 +744,12 @@ template <typename T> struct Sim final : SimBase {
         // rows per column unit: FP64 keeps its register window (2R + 1 planes of
         // YB rows) small enough not to spill
         constexpr int YB = sizeof(T) == 8 ? GG_PREDICT_YB64 : 4;
+        constexpr int YBP = sizeof(T) == 8 ? GG_PREDICT_YB64_PH : 4;
         if (Rk == 8) {
-            if (phys) go(gg::k_predict_march<T, 8, YB, true>, YB);
+            if (phys) go(gg::k_predict_march<T, 8, YBP, true>, YBP);
             else go(gg::k_predict_march<T, 8, YB, false>, YB);
         } else if (Rk == 6) {
-            if (phys) go(gg::k_predict_march<T, 6, YB, true>, YB);
+            if (phys) go(gg::k_predict_march<T, 6, YBP, true>, YBP);
             else go(gg::k_predict_march<T, 6, YB, false>, YB);
         } else {
             if (phys) go(gg::k_predict_march<T, 0, 2, true>, 2);

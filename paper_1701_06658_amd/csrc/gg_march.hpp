@@ -116,8 +116,13 @@ template <int RM, int YB> struct PredictLds {
 #ifndef GG_REINIT_WAVES
 #define GG_REINIT_WAVES 1
 #endif
-template <typename T> constexpr int reinit_cells() { return sizeof(T) == 8 ? 13312 : GG_REINIT_CELLS_F32; }
-template <typename T> constexpr int predict_cells() { return sizeof(T) == 8 ? 8192 : 12288; }
+#ifndef GG_MARCH_CELLS_F64
+#define GG_MARCH_CELLS_F64 19968
+#endif
+// FP64 marches run one group per CU (their registers allow no more), so they
+// take nearly the whole 160 KB of the CU's LDS: larger tiles, fewer halos.
+template <typename T> constexpr int reinit_cells() { return sizeof(T) == 8 ? GG_MARCH_CELLS_F64 : GG_REINIT_CELLS_F32; }
+template <typename T> constexpr int predict_cells() { return sizeof(T) == 8 ? GG_MARCH_CELLS_F64 : 12288; }
 
 // Every box has a tiling: the smallest extended tile (one interior cell and
 // halos of the largest reach on both sides of both axes) fits the group's
