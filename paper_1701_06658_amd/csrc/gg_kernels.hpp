@@ -447,13 +447,18 @@ template <typename T> struct Top2 {
 #ifndef GG_CMP_LDS_BYTES
 #define GG_CMP_LDS_BYTES 16384
 #endif
+#ifndef GG_CMP_LDS_BYTES_F64
+#define GG_CMP_LDS_BYTES_F64 16384
+#endif
 
 #ifndef GG_CMP_TILE_VOX
 #define GG_CMP_TILE_VOX 512
 #endif
 constexpr int kTileVox = GG_CMP_TILE_VOX;  // voxels of a corrector tile (at most)
 constexpr int kVpt = kTileVox / kBlock;
-template <typename T> constexpr int cmp_slots() { return GG_CMP_LDS_BYTES / (kTileVox * (int)sizeof(T)); }
+template <typename T> constexpr int cmp_slots() {
+    return (sizeof(T) == 8 ? GG_CMP_LDS_BYTES_F64 : GG_CMP_LDS_BYTES) / (kTileVox * (int)sizeof(T));
+}
 
 // Where a global tile meets box j.  Per axis s = (tile origin - box start) mod
 // n.  The box coordinate of the tile voxel at offset v is linear, d + v, when
