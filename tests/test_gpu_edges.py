@@ -93,3 +93,35 @@ def test_twin_grains_tie_to_the_lowest_id():
         io_orc = np.concatenate([o.iota(k).ravel() for k in range(G) if o.box(k)[0]])
         assert np.array_equal(io_gpu, io_orc)
     s.close()
+
+
+def _max_tile_coverage(st, shape_xyz, tile_xyz):
+    """Most boxes that cover one corrector tile (host count from the box table)."""
+    nt = [n // t for n, t in zip(shape_xyz, tile_xyz)]
+    cover = np.zeros(nt[::-1], np.int32)  # (z, y, x)
+    for k in np.nonzero(st["alive"])[0]:
+        sets = []
+        for a in range(3):
+            cells = (st["lo"][k][a] + np.arange(st["ext"][k][a])) % shape_xyz[a]
+            sets.append(np.unique(cells // tile_xyz[a]))
+        cover[np.ix_(sets[2], sets[1], sets[0])] += 1
+    return int(cover.max())
+
+
+def test_tiles_covered_by_more_than_64_boxes():
+    # 300 grains in 32^3 with W = 4: about 100 boxes meet each 16x8x4 corrector
+    # tile, so the corrector walks its coverage list in several chunks of 64
+    shape = (32, 32, 32)
+    rng = np.random.default_rng(37)
+    labels = power_labels(shape, uniform_voronoi(shape, 300, rng))
+    W = 4.0
+    o, s = _pair(labels, W, 300)
+    cov = _max_tile_coverage(s.state(), (32, 32, 32), (16, 8, 4))
+    print(f"[coverage] most boxes on one tile: {cov}", flush=True)
+    assert cov > 64
+    dt = config_dt(1.5, 32)
+    for step in range(1, 4):
+        o.step(dt)
+        s.step(dt)
+        _check_fp64(o, s, W, f"coverage > 64, step {step}")
+        assert np.array_equal(o.labels(), s.labels())
