@@ -526,7 +526,7 @@ template <typename U, typename O> __device__ __forceinline__ const U &at_bytes(c
 }
 
 #ifndef GG_CMP_U
-#define GG_CMP_U 4
+#define GG_CMP_U 8
 #endif
 
 // One global tile: the top-2 of the predicted functions of every grain whose
@@ -608,33 +608,51 @@ __global__ void __launch_bounds__(kBlock)
         if (held != cb) wb = tile_box(L, cov_list, cb + lane_id, e, t0, ta);
         held = cb;
     };
-    // pass 1: top-2 over the covering grains, U linear boxes' loads issued together
+    // pass 1: top-2 over the covering grains, U linear boxes' loads issued
+    // together.  The values of the first U boxes stay in registers (v0) for
+    // pass 2, those of later ones in the LDS cache.
     constexpr int U = GG_CMP_U;
+    auto load_group = [&](int c0, int cb, int ce, unsigned long long wrapped, T (&v)[U][kVpt], bool (&hit)[U][kVpt],
+                          int (&jj)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int c = c0 + u;
+#pragma unroll
+            for (int i = 0; i < kVpt; ++i) hit[u][i] = false;
+            jj[u] = -1;
+            if (c >= ce || ((wrapped >> (c - cb)) & 1ull)) continue;
+            const TileBox tb = box_of_lane<false>(wb, c - cb);
+            jj[u] = tb.j;
+            int l[kVpt][3];
+            unsigned bo[kVpt];
+            probe_lin(tb, hit[u], l, bo);
+            const T *pb = psi + tb.base;
+#pragma unroll
+            for (int i = 0; i < kVpt; ++i)
+                if (hit[u][i]) v[u][i] = at_bytes(pb, bo[i]);
+        }
+    };
+    T v0[U][kVpt];
     for (int cb = b; cb < e; cb += 64) {
         hold(cb);
         const int ce = min(e, cb + 64);
         const unsigned long long wrapped = __ballot(cb + lane_id < e && !wb.lin);
-        for (int c0 = cb; c0 < ce; c0 += U) {
+        int c0 = cb;
+        if (cb == b) {
+            bool hit[U][kVpt];
+            int jj[U];
+            load_group(b, cb, ce, wrapped, v0, hit, jj);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int i = 0; i < kVpt; ++i) top[i].template push<IDS>(v0[u][i], jj[u], hit[u][i]);
+            c0 += U;
+        }
+        for (; c0 < ce; c0 += U) {
             T v[U][kVpt];
             bool hit[U][kVpt];
             int jj[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int c = c0 + u;
-#pragma unroll
-                for (int i = 0; i < kVpt; ++i) hit[u][i] = false;
-                jj[u] = -1;
-                if (c >= ce || ((wrapped >> (c - cb)) & 1ull)) continue;
-                const TileBox tb = box_of_lane<false>(wb, c - cb);
-                jj[u] = tb.j;
-                int l[kVpt][3];
-                unsigned bo[kVpt];
-                probe_lin(tb, hit[u], l, bo);
-                const T *pb = psi + tb.base;
-#pragma unroll
-                for (int i = 0; i < kVpt; ++i)
-                    if (hit[u][i]) v[u][i] = at_bytes(pb, bo[i]);
-            }
+            load_group(c0, cb, ce, wrapped, v, hit, jj);
 #pragma unroll
             for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -654,15 +672,15 @@ __global__ void __launch_bounds__(kBlock)
             for (int i = 0; i < kVpt; ++i) {
                 const T v = hit[i] ? psi[ix[i]] : T(0);
                 top[i].template push<IDS>(v, tb.j, hit[i]);
-
             }
         }
     }
     // pass 2: the corrected function of every covering grain
 #pragma unroll
     for (int i = 0; i < kVpt; ++i) kept[i] = 0;
-    auto emit = [&](auto lin, const TileBox &tb) {
-        constexpr bool LIN = decltype(lin)::value;
+    // REG: the values come from rv (a linear box among the first U)
+    auto emit = [&](auto lin, auto reg, const TileBox &tb, const T (&rv)[kVpt]) {
+        constexpr bool LIN = decltype(lin)::value, REG = decltype(reg)::value;
         const int j = tb.j;
         bool hit[kVpt];
         int l[kVpt][3];
@@ -673,7 +691,9 @@ __global__ void __launch_bounds__(kBlock)
         T val[kVpt];
 #pragma unroll
         for (int i = 0; i < kVpt; ++i) {
-            if constexpr (LIN) {
+            if constexpr (REG) {
+                val[i] = rv[i];
+            } else if constexpr (LIN) {
                 // the LDS slot is read for every lane (clamped), HBM only for
                 // the values that were not kept
                 const int k = kept[i];
@@ -726,15 +746,24 @@ __global__ void __launch_bounds__(kBlock)
     };
     using Lin = std::integral_constant<bool, true>;
     using Wrap = std::integral_constant<bool, false>;
+    using Reg = std::integral_constant<bool, true>;
+    using Mem = std::integral_constant<bool, false>;
     for (int cb = b; cb < e; cb += 64) {
         hold(cb);
         const int ce = min(e, cb + 64);
-        for (int c = cb; c < ce; ++c) {
-            if (__builtin_amdgcn_readlane(wb.lin, c - cb)) {
-                emit(Lin{}, box_of_lane<false>(wb, c - cb));
-            } else {
-                emit(Wrap{}, box_of_lane<true>(wb, c - cb));
+        int c = cb;
+        if (cb == b) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (b + u >= ce) continue;
+                if (__builtin_amdgcn_readlane(wb.lin, u)) emit(Lin{}, Reg{}, box_of_lane<false>(wb, u), v0[u]);
+                else emit(Wrap{}, Mem{}, box_of_lane<true>(wb, u), v0[u]);
             }
+            c += U;
+        }
+        for (; c < ce; ++c) {
+            if (__builtin_amdgcn_readlane(wb.lin, c - cb)) emit(Lin{}, Mem{}, box_of_lane<false>(wb, c - cb), v0[0]);
+            else emit(Wrap{}, Mem{}, box_of_lane<true>(wb, c - cb), v0[0]);
         }
     }
 }
