@@ -29,9 +29,10 @@
 // (cells whose integer box distance exceeds it are skipped, and cells the
 // rings took are not taken again).  On a whole periodic axis a cell is taken at
 // the image whose offset lies in [-floor(e/2), ceil(e/2) - 1], and the search
-// never leaves that range.  A group queues the tube voxels of its box in LDS
-// and searches them a group's width at a time; a cell's node values sit in
-// the thread's LDS column while its simplices are taken in a rolled loop.
+// never leaves that range.  A group queues the tube voxels of its box in LDS,
+// in bands of |phi|, and searches them a group's width at a time; a cell's
+// node values sit in the thread's LDS column while its simplices are taken in
+// a rolled loop.
 #pragma once
 
 #include "gg_kernels.hpp"
@@ -291,9 +292,10 @@ __global__ void __launch_bounds__(kBlock)
         CBest best{__builtin_inf(), 0x7fffffff, 0x7fffffff};
         // one region per round: offsets [-rr-1, rr] per axis (clamped to the
         // box, or to the canonical image range on a whole periodic axis)
-        // without [-sk-1, sk] (scanned before); with prune, cells farther
-        // than the best piece are skipped.  Rings rr = 0, 1, ... until a piece
-        // is found, then one round out to the found distance.
+        // without [-sk-1, sk] (scanned before); once a piece is found, cells
+        // farther than the best piece are skipped (their pieces are at least
+        // their box distance away).  Rings rr = 0, 1, ... until a piece is
+        // found, then one round out to the found distance.
         int rr = 0, sk = -1;
         bool prune = false;
         for (;;) {
@@ -317,7 +319,7 @@ __global__ void __launch_bounds__(kBlock)
                             oz <= sk)
                             continue;
                         const int o[3] = {ox, oy, oz};
-                        if (prune) {
+                        if (best.cell != 0x7fffffff) {
                             int sq = 0;
 #pragma unroll
                             for (int a = 0; a < 3; ++a) {
@@ -392,31 +394,44 @@ __global__ void __launch_bounds__(kBlock)
         for (int t = 0; t < nj; ++t) sum += pair_w<T>(ph, k, js[t]);
         return nj ? sum / (double)nj : 1.0;
     };
-    // Tube voxels are gathered into a queue and searched a group's width at a
-    // time, so that no lane idles on a voxel outside the tube.
-    __shared__ int queue[2 * kBlock];
-    __shared__ int qn;
-    if (threadIdx.x == 0) qn = 0;
+    // Tube voxels are gathered into queues by |phi| (kQueues bands of the
+    // tube) and searched a group's width at a time, so that no lane idles on a
+    // voxel outside the tube and the lanes of a wave need searches of about the
+    // same extent (the search grows with the distance to the boundary).
+#ifndef GG_CLOSEST_QUEUES
+#define GG_CLOSEST_QUEUES 4
+#endif
+    constexpr int kQueues = GG_CLOSEST_QUEUES;
+    __shared__ int queue[kQueues][2 * kBlock];
+    __shared__ int qn[kQueues];
+    if (threadIdx.x < kQueues) qn[threadIdx.x] = 0;
     __syncthreads();
     for (int base = 0; base < total; base += kBlock) {
         const int i = base + (int)threadIdx.x;
         if (i < total) {
-            if (fabs((double)f[i]) < kClosestTube) queue[atomicAdd(&qn, 1)] = i;
-            else w[i] = (T)id_weight(i);
+            const double a = fabs((double)f[i]);
+            if (a < kClosestTube) {
+                const int qb = min(kQueues - 1, (int)(a * (kQueues / kClosestTube)));
+                queue[qb][atomicAdd(&qn[qb], 1)] = i;
+            } else {
+                w[i] = (T)id_weight(i);
+            }
         }
         __syncthreads();
         const bool last = base + kBlock >= total;
-        int n = qn;
-        while (n >= kBlock || (last && n > 0)) {
-            const int take = min(n, kBlock);
-            if ((int)threadIdx.x < take) {
-                const int v = queue[n - take + threadIdx.x];
-                w[v] = (T)tube_weight(v);
+        for (int qb = 0; qb < kQueues; ++qb) {
+            int n = qn[qb];
+            while (n >= kBlock || (last && n > 0)) {
+                const int take = min(n, kBlock);
+                if ((int)threadIdx.x < take) {
+                    const int v = queue[qb][n - take + threadIdx.x];
+                    w[v] = (T)tube_weight(v);
+                }
+                n -= take;
+                __syncthreads();
+                if (threadIdx.x == 0) qn[qb] = n;
+                __syncthreads();
             }
-            n -= take;
-            __syncthreads();
-            if (threadIdx.x == 0) qn = n;
-            __syncthreads();
         }
     }
 }
