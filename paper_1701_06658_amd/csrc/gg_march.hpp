@@ -109,6 +109,13 @@ template <int RM, int YB> struct PredictLds {
           total(oX + 2 * sX) {}
 };
 
+// Tiles at most kPitchW wide may run with the LDS pitches of that width fixed
+// at compile time (the |1 of the pitches makes 44 and 45 alike).
+#ifndef GG_PITCH_W
+#define GG_PITCH_W 45
+#endif
+constexpr int kPitchW = GG_PITCH_W;
+
 // LDS cells a march kernel may use (its dynamic allocation).
 #ifndef GG_REINIT_CELLS_F32
 #define GG_REINIT_CELLS_F32 16384
@@ -341,7 +348,13 @@ __global__ void __launch_bounds__(kMT, sizeof(T) == 4 ? GG_REINIT_WAVES : 1)
     for (int tile = 0; tile < sp.nt[0] * sp.nt[1]; ++tile) {
         const MTile tl = march_tile(sp, tile);
         const int EX = tl.ext[0], EY = tl.ext[1];
-        const Lay ly(EX, EY);
+        // The tile body comes twice: with the LDS pitches of a tile kPitchW
+        // wide, fixed at compile time (window reads then take immediate
+        // offsets), when the tile is at most that wide and that layout fits;
+        // else with the tile's own pitches.
+        auto body = [&](auto wc) {
+        constexpr int WC = decltype(wc)::value;
+        const Lay ly(WC ? WC : EX, EY);
         // frames: -W around phi^c, +inf around the spreading inputs
         lds_fill(sm, ly.oR, -W);
         lds_fill(sm + ly.oR, ly.total - ly.oR, inf);
@@ -523,11 +536,14 @@ __global__ void __launch_bounds__(kMT, sizeof(T) == 4 ? GG_REINIT_WAVES : 1)
                     if (!c.rint[j]) continue;
                     const int idx = z * nplane + nrow[j];
                     const T v = dst[idx];
-                    car[j] = vmin(fabs(v), car[j] + T(1));
+                    car[j] = vmin(T(fabs(v)), car[j] + T(1));
                     dst[idx] = copysign(car[j], v);
                 }
         }
         __syncthreads();  // the next tile refills the frames
+        };
+        if (EX <= kPitchW && Lay(kPitchW, EY).total <= reinit_cells<T>()) body(std::integral_constant<int, kPitchW>{});
+        else body(std::integral_constant<int, 0>{});
     }
     if (!d3) {
         const double s = block_sum(vsum, red);
@@ -761,7 +777,11 @@ __global__ void __launch_bounds__(kMT, sizeof(T) == 4 && !PH ? GG_PREDICT_WAVES 
         for (int tile = 0; tile < sp.nt[0] * sp.nt[1]; ++tile) {
             const MTile tl = march_tile(sp, tile);
             const int EX = tl.ext[0], EY = tl.ext[1];
-            const Lay ly(EX, EY);
+            // as in the re-initialization: compile-time LDS pitches for tiles at
+            // most kPitchW wide whose layout at that width fits
+            auto body = [&](auto wc) {
+            constexpr int WC = decltype(wc)::value;
+            const Lay ly(WC ? WC : EX, EY);
             if (want_psi) frames(ly);
             const MCol<YB> c = march_col<YB>(tl, ex, ey, ma.n[0], ma.n[1]);
             int cell[YB];
@@ -880,6 +900,9 @@ __global__ void __launch_bounds__(kMT, sizeof(T) == 4 && !PH ? GG_PREDICT_WAVES 
                 // x stage reads it), and write what this one read
                 if (qz <= ez - 1) __syncthreads();
             }
+            };
+            if (EX <= kPitchW && Lay(kPitchW, EY).total <= predict_cells<T>()) body(std::integral_constant<int, kPitchW>{});
+            else body(std::integral_constant<int, 0>{});
         }
     }
     const double s = block_sum(vsum, red);
