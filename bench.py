@@ -254,7 +254,7 @@ print(json.dumps(e0.elapsed_time(e1) / {reps}))
 def cpu_baseline(index, threads=None, steps=None):
     """FP64 oracle on a bounded sample: `steps` steps (4 on all host threads, 3
     on one) of a density-matched cut of the workload (128^3 on all host
-    threads; 64^3 on one thread), about 10 s of host time on the GPU machine."""
+    threads; 64^3 on one thread), about 10 s of host time on an MI355X node."""
     from oracle import ORACLE_CFLAGS, Oracle, num_threads, set_num_threads
     from synth import make_config
     N = None if index == 1 else (64 if threads == 1 else 128)

@@ -16,7 +16,7 @@ _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 _f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 
 
-# -O3 for x86-64-v3 (AVX2; every host of the GPU machines has it); products and
+# -O3 for x86-64-v3 (AVX2, which the hosts of MI355X nodes have); products and
 # sums are still rounded separately (no contraction), so results do not depend
 # on the flags.
 ORACLE_CFLAGS = ["-O3", "-march=x86-64-v3", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math"]
